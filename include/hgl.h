@@ -1,0 +1,182 @@
+/*
+ * hgl -- hypergraph ranking solves on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library.  It computes, for a hypergraph with binary incidence
+ * H (N vertices x E hyperedges) and hyperedge weights w, the normalised
+ * adjacency A = Dv^-1/2 H W De^-1 H' Dv^-1/2 (paper, section 2, eq. 1),
+ * Zhou's Laplacian L = I - A, and solves
+ *
+ *        M F = Y,   M = I + L / lambda,
+ *
+ * for many columns of Y.  With theta = lambda this is the paper's ranking
+ * system X f = theta/(1+theta) y (eq. 6), X = I - A/(1+theta), and F equals
+ * f* of eq. (3) column by column.
+ *
+ * Conventions (all entry points):
+ *  - every array argument is a DEVICE pointer owned by the caller unless its
+ *    name ends in _host (host memory, owned by the caller);
+ *  - dense matrices are row-major, n_rows x k, with a leading dimension
+ *    ld >= k counted in elements; row r starts at ptr + r*ld;
+ *  - integer index arrays are int32;
+ *  - every call is ordered on the given HIP stream; calls that fill _host
+ *    outputs synchronise that stream before returning, the others return
+ *    as soon as the work is enqueued;
+ *  - the return value is a status: 0 = HGL_OK, positive = informational,
+ *    negative = error; hgl_last_error() gives a message for the last failing
+ *    call on the calling thread; no C++ exception crosses this boundary;
+ *  - a handle owns its device buffers (allocated with hipMalloc) and frees
+ *    them in hgl_destroy; a handle must not be used from two threads at once.
+ */
+#ifndef HGL_H
+#define HGL_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hgl_handle hgl_handle;
+
+enum hgl_status {
+  HGL_OK = 0,
+  HGL_NOT_CONVERGED = 1,  /* iteration limit hit; outputs hold the last iterate */
+  HGL_EINVAL = -1,        /* invalid argument or hypergraph structure */
+  HGL_ENOMEM = -2,        /* device allocation failed */
+  HGL_EDEVICE = -3,       /* HIP runtime error (message carries its text) */
+  HGL_EBREAKDOWN = -4,    /* CG breakdown: p'Mp <= 0 or not finite */
+  HGL_ECHOLQR = -5,       /* Cholesky of a Gram matrix failed in CholQR */
+  HGL_EUNSUPPORTED = -6   /* valid request this build does not handle */
+};
+
+enum hgl_dtype { HGL_F64 = 0, HGL_F32 = 1 };
+
+enum hgl_cg_mode {
+  /* every vector, product and inner product in FP64 */
+  HGL_CG_PLAIN_F64 = 0,
+  /* vectors and operator products in FP32; inner products accumulated in
+     FP64; the residual is recomputed as Y - M F with FP64 accumulation every
+     rr_period iterations and whenever a column's recursive residual claims
+     convergence (residual replacement); a column stops only on that
+     recomputed FP64 residual */
+  HGL_CG_F32_F64DOT_RR = 1
+};
+
+typedef struct hgl_cg_opts {
+  int32_t mode;       /* enum hgl_cg_mode */
+  double tol;         /* per-column target ||y_j - M f_j|| / ||y_j|| */
+  int32_t max_iter;   /* iteration limit (>= 1) */
+  int32_t x0_given;   /* 1: F holds the starting guess on entry; 0: start from 0 */
+  int32_t rr_period;  /* residual replacement period (F32 mode); 0 = only on claims */
+  int32_t chunk;      /* iterations enqueued between host convergence checks; 0 = automatic */
+} hgl_cg_opts;
+
+/* Library version, e.g. 100 for 0.1.0. */
+int hgl_version(void);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* hgl_last_error(void);
+
+/*
+ * Build the operator for one hypergraph (paper, section 2).
+ *  edge_ptr [E+1], edge_vtx [nnz]: edge-major CSR of H.  Hyperedge e is the
+ *    vertex set edge_vtx[edge_ptr[e] .. edge_ptr[e+1]-1]; its ids must be
+ *    strictly increasing (H is binary, so a repeated vertex is invalid), lie
+ *    in [0, N), and every hyperedge must be nonempty.
+ *  w [E]: hyperedge weights, finite and >= 0 (L does not change when w is
+ *    scaled, so w need not sum to one).
+ * Computes delta(v) = sum_e w(e) H(v,e), delta(e) = |e|, the scales
+ * s_v = delta(v)^-1/2 (0 when delta(v) = 0, i.e. the pseudo-inverse) and
+ * c_e = w_e / delta(e), and the vertex-major transpose of H.  The inputs are
+ * copied; the caller may free them afterwards.  Invalid structure or weights
+ * -> HGL_EINVAL (validation runs on the device; this call synchronises).
+ */
+int hgl_build_laplacian(int32_t N, int32_t E, int64_t nnz, const int32_t* edge_ptr,
+                        const int32_t* edge_vtx, const double* w, hgl_handle** out,
+                        hipStream_t stream);
+
+/*
+ * Build one operator for G independent hypergraphs stored as their disjoint
+ * union (vertex ids global).  vtx_offsets_host[G+1] and edge_offsets_host[G+1]
+ * give each graph's vertex and hyperedge ranges; every hyperedge of graph g
+ * must lie inside graph g's vertex range.  Solves on such a handle run one
+ * CG recurrence per (graph, column) and may use one lambda per graph.
+ */
+int hgl_build_laplacian_batched(int32_t G, const int32_t* vtx_offsets_host,
+                                const int32_t* edge_offsets_host, int64_t nnz,
+                                const int32_t* edge_ptr, const int32_t* edge_vtx,
+                                const double* w, hgl_handle** out, hipStream_t stream);
+
+/* Replace the weights w [E] (same rules as at build) and recompute delta(v),
+ * s and c; the structure is reused.  -> HGL_EINVAL on a negative or
+ * non-finite weight (synchronises). */
+int hgl_set_weights(hgl_handle* h, const double* w, hipStream_t stream);
+
+/* Release the handle and its device buffers (NULL is accepted). */
+void hgl_destroy(hgl_handle* h);
+
+/* Sizes of a handle: N, E, nnz, number of graphs (any pointer may be NULL). */
+int hgl_get_sizes(const hgl_handle* h, int32_t* N, int32_t* E, int64_t* nnz, int32_t* G);
+
+/*
+ * Copy the derived quantities of section 2 into caller buffers (any may be
+ * NULL): dv [N] = delta(v), s [N] = delta(v)^-1/2 (0 if delta(v) = 0),
+ * c [E] = w_e/delta(e), vtx_ptr [N+1] and vtx_edge [nnz] = vertex-major CSR
+ * of H, each vertex's hyperedges in increasing id order.
+ */
+int hgl_get_operator(const hgl_handle* h, double* dv, double* s, double* c, int32_t* vtx_ptr,
+                     int32_t* vtx_edge, hipStream_t stream);
+
+/*
+ * Q = (I + L/lambda) P for k columns, computed matrix-free as
+ * Q = (1 + 1/lambda) P - (1/lambda) S H C H' S P with S = diag(s),
+ * C = diag(c) (eq. 1 and the definition of L).  P and Q are N x k, of type
+ * dt (double or float), leading dimensions ldp, ldq >= k; P and Q must not
+ * overlap.  lambda > 0.  On a batched handle every graph uses this lambda.
+ */
+int hgl_apply(hgl_handle* h, double lambda, int32_t dt, const void* P, int64_t ldp, void* Q,
+              int64_t ldq, int32_t k, hipStream_t stream);
+
+/*
+ * Solve (I + L/lambda) F = Y column by column by conjugate gradient, in the
+ * recurrences of the paper's section 3 (eqs. 16-20), each column with its own
+ * alpha and beta.  Y, F: N x k of type double (PLAIN_F64) or float
+ * (F32_F64DOT_RR).  iters_host [G*k] (nullable) receives the iteration count
+ * of each (graph, column), relres_host [G*k] (nullable) the FP64-recomputed
+ * ||y - M f|| / ||y|| of the returned F (0 for a zero column, whose solution
+ * is 0).  Returns HGL_OK when every column met tol, HGL_NOT_CONVERGED when
+ * max_iter was reached first, HGL_EBREAKDOWN on a breakdown, HGL_EINVAL for
+ * lambda <= 0, tol <= 0, k < 1 or a bad pointer/leading dimension.
+ * Synchronises the stream.
+ */
+int hgl_cg_solve(hgl_handle* h, double lambda, const hgl_cg_opts* opts, const void* Y,
+                 int64_t ldy, void* F, int64_t ldf, int32_t k, int32_t* iters_host,
+                 double* relres_host, hipStream_t stream);
+
+/* As hgl_cg_solve with one lambda per graph of a batched handle
+ * (lambdas_host [G]).  All graphs share k; Y and F are the row
+ * concatenations of the graphs' blocks (sum N_g x k). */
+int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg_opts* opts,
+                         const void* Y, int64_t ldy, void* F, int64_t ldf, int32_t k,
+                         int32_t* iters_host, double* relres_host, hipStream_t stream);
+
+/*
+ * Kernel timing (diagnostics).  hgl_profile(h, 1) resets the counters and
+ * makes every later solver call on h bracket each kernel launch with HIP
+ * events recorded on the call's stream; hgl_profile(h, 0) stops it.
+ * hgl_profile_read returns, for one kernel kind, the number of launches
+ * recorded and their summed duration in milliseconds (it synchronises the
+ * device).  Kinds: 0 edge gather (Z = C H' S P), 1 vertex gather with inner
+ * product (M P), 2 CG update (F, R), 3 CG direction (P), 4 reductions,
+ * 5 residual edge gather (FP64), 6 residual vertex gather (FP64),
+ * 7 start-up.  Unknown kind -> HGL_EINVAL.
+ */
+int hgl_profile(hgl_handle* h, int32_t enable);
+int hgl_profile_read(hgl_handle* h, int32_t kind, int64_t* launches, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGL_H */

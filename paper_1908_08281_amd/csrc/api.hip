@@ -1,0 +1,554 @@
+// Handle lifecycle, hypergraph build (section 2 of the paper: incidence,
+// degrees, scales) and validation.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "common.h"
+
+namespace hgl {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+
+int DevBuf::reserve(size_t n) {
+  if (n <= bytes) return HGL_OK;
+  if (p) hipFree(p);
+  p = nullptr;
+  bytes = 0;
+  size_t want = std::max<size_t>(n, 256);
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    p = nullptr;
+    set_error("hipMalloc(%zu bytes) failed: %s", want, hipGetErrorString(e));
+    return HGL_ENOMEM;
+  }
+  bytes = want;
+  return HGL_OK;
+}
+
+void DevBuf::release() {
+  if (p) hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+template <class T>
+static int dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  size_t bytes = std::max<size_t>(count * sizeof(T), 4);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    return HGL_ENOMEM;
+  }
+  return HGL_OK;
+}
+
+int ensure_counters(hgl_handle* h, int slabs, hipStream_t s) {
+  if (h->n_long == 0 || slabs <= h->counter_slabs) return HGL_OK;
+  if (h->long_counter) hipFree(h->long_counter);
+  h->long_counter = nullptr;
+  h->counter_slabs = 0;
+  HGL_TRY(dev_alloc(&h->long_counter, size_t(h->n_long) * slabs));
+  HGL_HIP(hipMemsetAsync(h->long_counter, 0, sizeof(int32_t) * h->n_long * slabs, s));
+  h->counter_slabs = slabs;
+  return HGL_OK;
+}
+
+int ensure_pinned(hgl_handle* h, size_t n) {
+  if (!h->pinned_i) HGL_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->pinned_i), 64 * sizeof(int32_t)));
+  if (n > h->pinned_d_len) {
+    if (h->pinned_d) hipHostFree(h->pinned_d);
+    h->pinned_d = nullptr;
+    h->pinned_d_len = 0;
+    HGL_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->pinned_d), n * sizeof(double)));
+    h->pinned_d_len = n;
+  }
+  return HGL_OK;
+}
+
+static bool aligned(const void* p, int bytes) {
+  return (reinterpret_cast<uintptr_t>(p) % bytes) == 0;
+}
+
+ColShape pick_shape(int k, int elem_bytes, std::initializer_list<const void*> ptrs,
+                    std::initializer_list<int64_t> lds) {
+  ColShape cs;
+  int vmax = elem_bytes == 4 ? 4 : 2;  // 16-byte vector loads at most
+  int V = vmax;
+  while (V > 1) {
+    bool ok = (k % V) == 0;
+    for (int64_t ld : lds) ok = ok && (ld % V) == 0;
+    for (const void* p : ptrs) ok = ok && (p == nullptr || aligned(p, V * elem_bytes));
+    if (ok) break;
+    V >>= 1;
+  }
+  int ncv = (k + V - 1) / V;
+  int GL = 4;
+  while (GL < ncv && GL < 64) GL <<= 1;
+  cs.GL = GL;
+  cs.V = V;
+  cs.slabs = (k + cs.width() - 1) / cs.width();
+  return cs;
+}
+
+// ---------------------------------------------------------------- kernels --
+
+enum : int { kErrEmpty = 1, kErrRange = 2, kErrOrder = 4, kErrWeight = 8, kErrPtr = 16 };
+
+__global__ void k_validate(int32_t E, int64_t nnz, const int32_t* __restrict__ edge_ptr,
+                           const int32_t* __restrict__ edge_vtx, const double* __restrict__ w,
+                           const int32_t* __restrict__ vtx_off, const int32_t* __restrict__ edge_off,
+                           int32_t G, int32_t* __restrict__ err) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0 && (edge_ptr[0] != 0 || int64_t(edge_ptr[E]) != nnz)) {
+    atomicOr(&err[0], kErrPtr);
+    atomicMin(&err[1], 0);
+  }
+  if (e >= E) return;
+  int code = 0;
+  double we = w[e];
+  if (!(we >= 0.0) || !isfinite(we)) code |= kErrWeight;
+  int64_t b = edge_ptr[e], en = edge_ptr[e + 1];
+  if (b < 0 || en > nnz || en < b) {
+    code |= kErrPtr;
+  } else if (en == b) {
+    code |= kErrEmpty;
+  } else {
+    // graph of this edge: largest g with edge_off[g] <= e
+    int lo = 0, hi = G - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (edge_off[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    int32_t v0 = vtx_off[lo], v1 = vtx_off[lo + 1];
+    int32_t prev = -1;
+    for (int64_t j = b; j < en; ++j) {
+      int32_t v = edge_vtx[j];
+      if (v < v0 || v >= v1) code |= kErrRange;
+      if (j > b && v <= prev) code |= kErrOrder;
+      prev = v;
+    }
+  }
+  if (code) {
+    atomicOr(&err[0], code);
+    atomicMin(&err[1], e);
+  }
+}
+
+__global__ void k_validate_w(int32_t E, const double* __restrict__ w, int32_t* __restrict__ err) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double we = w[e];
+  if (!(we >= 0.0) || !isfinite(we)) {
+    atomicOr(&err[0], kErrWeight);
+    atomicMin(&err[1], e);
+  }
+}
+
+// nnz-long arrays: vertex id (sort key) and edge id (sort value) of each entry
+__global__ void k_expand(int32_t E, const int32_t* __restrict__ edge_ptr,
+                         const int32_t* __restrict__ edge_vtx, uint32_t* __restrict__ key,
+                         int32_t* __restrict__ val, int32_t* __restrict__ deg) {
+  int e = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
+  int lane = threadIdx.x % 16;
+  if (e >= E) return;
+  for (int j = edge_ptr[e] + lane; j < edge_ptr[e + 1]; j += 16) {
+    int32_t v = edge_vtx[j];
+    key[j] = uint32_t(v);
+    val[j] = e;
+    atomicAdd(&deg[v], 1);
+  }
+}
+
+__global__ void k_degrees(int32_t N, const int32_t* __restrict__ vtx_ptr,
+                          const int32_t* __restrict__ vtx_edge, const double* __restrict__ w,
+                          double* __restrict__ dv, double* __restrict__ s64,
+                          float* __restrict__ s32) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  double d = 0.0;
+  for (int j = vtx_ptr[v]; j < vtx_ptr[v + 1]; ++j) d += w[vtx_edge[j]];
+  dv[v] = d;
+  double s = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  s64[v] = s;
+  s32[v] = float(s);
+}
+
+__global__ void k_edge_scales(int32_t E, const int32_t* __restrict__ edge_ptr,
+                              const double* __restrict__ w, double* __restrict__ c64,
+                              float* __restrict__ c32) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double c = w[e] / double(edge_ptr[e + 1] - edge_ptr[e]);
+  c64[e] = c;
+  c32[e] = float(c);
+}
+
+__global__ void k_long_flags(int32_t N, const int32_t* __restrict__ vtx_ptr,
+                             int32_t* __restrict__ is_long, int32_t* __restrict__ nch) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  int d = vtx_ptr[v + 1] - vtx_ptr[v];
+  bool L = d > kLongRow;
+  is_long[v] = L ? 1 : 0;
+  nch[v] = L ? (d + kChunk - 1) / kChunk : 0;
+}
+
+__global__ void k_long_fill(int32_t N, const int32_t* __restrict__ vtx_ptr,
+                            const int32_t* __restrict__ is_long, const int32_t* __restrict__ slot_of,
+                            const int32_t* __restrict__ chunk_of, int32_t* __restrict__ long_row,
+                            int32_t* __restrict__ long_chunk0, int32_t* __restrict__ chunk_slot,
+                            int32_t* __restrict__ chunk_begin, int32_t* __restrict__ chunk_end) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N || !is_long[v]) return;
+  int slot = slot_of[v];
+  int c0 = chunk_of[v];
+  long_row[slot] = v;
+  long_chunk0[slot] = c0;
+  int b = vtx_ptr[v], en = vtx_ptr[v + 1];
+  int c = c0;
+  for (int j = b; j < en; j += kChunk, ++c) {
+    chunk_slot[c] = slot;
+    chunk_begin[c] = j;
+    chunk_end[c] = min(j + kChunk, en);
+  }
+}
+
+static int blocks_for(int64_t n, int per) { return int((n + per - 1) / per); }
+
+static int check_error_words(const int32_t* err_host) {
+  if (err_host[0] == 0) return HGL_OK;
+  int c = err_host[0];
+  set_error("invalid hypergraph (first bad hyperedge %d):%s%s%s%s%s", err_host[1],
+            (c & kErrPtr) ? " edge_ptr not a valid CSR offset array;" : "",
+            (c & kErrEmpty) ? " empty hyperedge;" : "",
+            (c & kErrRange) ? " vertex id outside [0,N) (or outside its graph);" : "",
+            (c & kErrOrder) ? " vertex ids not strictly increasing (repeated vertex);" : "",
+            (c & kErrWeight) ? " weight negative or not finite;" : "");
+  return HGL_EINVAL;
+}
+
+static int compute_scales(hgl_handle* h, hipStream_t s) {
+  if (h->N > 0)
+    hipLaunchKernelGGL(k_degrees, dim3(blocks_for(h->N, 256)), dim3(256), 0, s, h->N, h->vtx_ptr,
+                       h->vtx_edge, h->w, h->dv, h->s64, h->s32);
+  if (h->E > 0)
+    hipLaunchKernelGGL(k_edge_scales, dim3(blocks_for(h->E, 256)), dim3(256), 0, s, h->E,
+                       h->edge_ptr, h->w, h->c64, h->c32);
+  HGL_HIP(hipGetLastError());
+  return HGL_OK;
+}
+
+static void free_handle(hgl_handle* h) {
+  if (!h) return;
+  void* ptrs[] = {h->edge_ptr, h->edge_vtx, h->vtx_ptr, h->vtx_edge, h->w, h->dv, h->s64, h->c64,
+                  h->s32, h->c32, h->tile_r0, h->tile_r1, h->tile_seg, h->long_row,
+                  h->chunk_slot, h->chunk_begin, h->chunk_end, h->long_chunk0,
+                  h->long_counter, h->seg_slots, h->long_seg};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  DevBuf* bufs[] = {&h->ws_z, &h->ws_z64, &h->ws_chunk, &h->ws_part, &h->ws_part2,
+                    &h->ws_vec, &h->ws_state, &h->ws_misc};
+  for (DevBuf* b : bufs) b->release();
+  for (auto& b : h->ws_extra) b.release();
+  h->ws_ab.release();
+  if (h->pinned_i) hipHostFree(h->pinned_i);
+  if (h->pinned_d) hipHostFree(h->pinned_d);
+  delete h;
+}
+
+static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off_host, int64_t nnz,
+                 const int32_t* edge_ptr, const int32_t* edge_vtx, const double* w,
+                 hgl_handle** out, hipStream_t s) {
+  HGL_CHECK_ARG(out != nullptr, "out must not be NULL");
+  *out = nullptr;
+  HGL_CHECK_ARG(G >= 1, "number of graphs must be >= 1 (got %d)", G);
+  HGL_CHECK_ARG(vtx_off_host && edge_off_host, "offset arrays must not be NULL");
+  HGL_CHECK_ARG(vtx_off_host[0] == 0 && edge_off_host[0] == 0, "offsets must start at 0");
+  for (int g = 0; g < G; ++g) {
+    HGL_CHECK_ARG(vtx_off_host[g + 1] >= vtx_off_host[g] && edge_off_host[g + 1] >= edge_off_host[g],
+                  "offsets must be non-decreasing (graph %d)", g);
+  }
+  int32_t N = vtx_off_host[G], E = edge_off_host[G];
+  HGL_CHECK_ARG(N >= 1, "N must be >= 1");
+  HGL_CHECK_ARG(E >= 0 && nnz >= 0 && nnz < (int64_t(1) << 31), "E, nnz out of range");
+  HGL_CHECK_ARG(E == 0 || (edge_ptr && edge_vtx && w), "edge_ptr, edge_vtx, w must not be NULL");
+  HGL_CHECK_ARG(nnz >= E, "nnz (%lld) < E (%d): some hyperedge would be empty", (long long)nnz, E);
+
+  hgl_handle* h = new hgl_handle();
+  h->N = N;
+  h->E = E;
+  h->G = G;
+  h->nnz = nnz;
+  hipGetDevice(&h->device);
+  h->vtx_off.assign(vtx_off_host, vtx_off_host + G + 1);
+  h->edge_off.assign(edge_off_host, edge_off_host + G + 1);
+
+  auto fail = [&](int code) {
+    free_handle(h);
+    return code;
+  };
+#define B_TRY(expr)              \
+  do {                           \
+    int _s = (expr);             \
+    if (_s < 0) return fail(_s); \
+  } while (0)
+#define B_HIP(call)                                                                   \
+  do {                                                                                \
+    hipError_t _e = (call);                                                           \
+    if (_e != hipSuccess) {                                                           \
+      set_error("%s failed: %s", #call, hipGetErrorString(_e));                       \
+      return fail(HGL_EDEVICE);                                                       \
+    }                                                                                 \
+  } while (0)
+
+  B_TRY(dev_alloc(&h->edge_ptr, E + 1));
+  B_TRY(dev_alloc(&h->edge_vtx, nnz));
+  B_TRY(dev_alloc(&h->vtx_ptr, N + 1));
+  B_TRY(dev_alloc(&h->vtx_edge, nnz));
+  B_TRY(dev_alloc(&h->w, E));
+  B_TRY(dev_alloc(&h->dv, N));
+  B_TRY(dev_alloc(&h->s64, N));
+  B_TRY(dev_alloc(&h->c64, E));
+  B_TRY(dev_alloc(&h->s32, N));
+  B_TRY(dev_alloc(&h->c32, E));
+  B_TRY(ensure_pinned(h, 64));
+
+  if (E > 0) {
+    B_HIP(hipMemcpyAsync(h->edge_ptr, edge_ptr, sizeof(int32_t) * (E + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz > 0)
+      B_HIP(hipMemcpyAsync(h->edge_vtx, edge_vtx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
+    B_HIP(hipMemcpyAsync(h->w, w, sizeof(double) * E, hipMemcpyDeviceToDevice, s));
+  } else {
+    B_HIP(hipMemsetAsync(h->edge_ptr, 0, sizeof(int32_t), s));
+  }
+
+  // ---- validation (device), before any use of the indices
+  int32_t *d_off = nullptr, *d_err = nullptr;
+  B_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_off), sizeof(int32_t) * (2 * G + 2 + 2), s));
+  d_err = d_off + 2 * G + 2;
+  B_HIP(hipMemcpyAsync(d_off, vtx_off_host, sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
+  B_HIP(hipMemcpyAsync(d_off + G + 1, edge_off_host, sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
+  int32_t err_init[2] = {0, 0x7fffffff};
+  B_HIP(hipMemcpyAsync(d_err, err_init, sizeof(err_init), hipMemcpyHostToDevice, s));
+  if (E > 0)
+    hipLaunchKernelGGL(k_validate, dim3(blocks_for(E, 256)), dim3(256), 0, s, E, nnz, h->edge_ptr,
+                       h->edge_vtx, h->w, d_off, d_off + G + 1, G, d_err);
+  B_HIP(hipGetLastError());
+  B_HIP(hipMemcpyAsync(h->pinned_i, d_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  B_HIP(hipFreeAsync(d_off, s));
+  B_HIP(hipStreamSynchronize(s));
+  {
+    int st = check_error_words(h->pinned_i);
+    if (st < 0) return fail(st);
+  }
+
+  // ---- vertex-major transpose: stable radix sort of (vertex, edge) pairs
+  {
+    uint32_t* keys = nullptr;
+    int32_t* vals = nullptr;
+    int32_t* deg = nullptr;
+    uint32_t* keys_out = nullptr;
+    size_t n2 = std::max<int64_t>(nnz, 1);
+    B_HIP(hipMallocAsync(reinterpret_cast<void**>(&keys), n2 * 4 * 3 + sizeof(int32_t) * (N + 1), s));
+    keys_out = keys + n2;
+    vals = reinterpret_cast<int32_t*>(keys + 2 * n2);
+    deg = reinterpret_cast<int32_t*>(keys + 3 * n2);
+    B_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (N + 1), s));
+    if (E > 0)
+      hipLaunchKernelGGL(k_expand, dim3(blocks_for(E, 16)), dim3(256), 0, s, E, h->edge_ptr,
+                         h->edge_vtx, keys, vals, deg);
+    B_HIP(hipGetLastError());
+    int end_bit = 1;
+    while ((int64_t(1) << end_bit) < N) ++end_bit;
+    size_t tmp_bytes = 0, scan_bytes = 0;
+    B_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys, keys_out, vals, h->vtx_edge,
+                                             int(nnz), 0, end_bit, s));
+    B_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, deg, h->vtx_ptr, N + 1, s));
+    void* tmp = nullptr;
+    B_HIP(hipMallocAsync(&tmp, std::max(tmp_bytes, scan_bytes) + 16, s));
+    if (nnz > 0)
+      B_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys, keys_out, vals, h->vtx_edge,
+                                               int(nnz), 0, end_bit, s));
+    B_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, scan_bytes, deg, h->vtx_ptr, N + 1, s));
+    B_HIP(hipFreeAsync(tmp, s));
+    B_HIP(hipFreeAsync(keys, s));
+  }
+  B_TRY(compute_scales(h, s));
+
+  // ---- row tiles (segment-aligned) for the row-streaming kernels
+  {
+    std::vector<int32_t> r0, r1, sg;
+    for (int g = 0; g < G; ++g)
+      for (int32_t r = vtx_off_host[g]; r < vtx_off_host[g + 1]; r += kTileRows) {
+        r0.push_back(r);
+        r1.push_back(std::min(r + kTileRows, vtx_off_host[g + 1]));
+        sg.push_back(g);
+      }
+    h->n_tiles = int32_t(r0.size());
+    B_TRY(dev_alloc(&h->tile_r0, r0.size()));
+    B_TRY(dev_alloc(&h->tile_r1, r0.size()));
+    B_TRY(dev_alloc(&h->tile_seg, r0.size()));
+    B_HIP(hipMemcpyAsync(h->tile_r0, r0.data(), 4 * r0.size(), hipMemcpyHostToDevice, s));
+    B_HIP(hipMemcpyAsync(h->tile_r1, r1.data(), 4 * r1.size(), hipMemcpyHostToDevice, s));
+    B_HIP(hipMemcpyAsync(h->tile_seg, sg.data(), 4 * sg.size(), hipMemcpyHostToDevice, s));
+    B_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+  }
+
+  // ---- long vertex rows -> chunks
+  {
+    int32_t* tmpi = nullptr;
+    B_HIP(hipMallocAsync(reinterpret_cast<void**>(&tmpi), sizeof(int32_t) * 4 * (size_t(N) + 1), s));
+    int32_t* is_long = tmpi;
+    int32_t* nch = tmpi + (N + 1);
+    int32_t* slot_of = tmpi + 2 * (N + 1);
+    int32_t* chunk_of = tmpi + 3 * (N + 1);
+    B_HIP(hipMemsetAsync(tmpi, 0, sizeof(int32_t) * 4 * (size_t(N) + 1), s));
+    hipLaunchKernelGGL(k_long_flags, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, h->vtx_ptr,
+                       is_long, nch);
+    B_HIP(hipGetLastError());
+    size_t b1 = 0, b2 = 0;
+    B_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b1, is_long, slot_of, N + 1, s));
+    B_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b2, nch, chunk_of, N + 1, s));
+    void* tmp = nullptr;
+    B_HIP(hipMallocAsync(&tmp, std::max(b1, b2) + 16, s));
+    B_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, b1, is_long, slot_of, N + 1, s));
+    B_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, b2, nch, chunk_of, N + 1, s));
+    B_HIP(hipFreeAsync(tmp, s));
+    B_HIP(hipMemcpyAsync(h->pinned_i, slot_of + N, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    B_HIP(hipMemcpyAsync(h->pinned_i + 1, chunk_of + N, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    B_HIP(hipStreamSynchronize(s));
+    h->n_long = h->pinned_i[0];
+    h->n_chunks = h->pinned_i[1];
+    B_TRY(dev_alloc(&h->long_row, h->n_long));
+    B_TRY(dev_alloc(&h->long_chunk0, h->n_long + 1));
+    B_TRY(dev_alloc(&h->chunk_slot, h->n_chunks));
+    B_TRY(dev_alloc(&h->chunk_begin, h->n_chunks));
+    B_TRY(dev_alloc(&h->chunk_end, h->n_chunks));
+    hipLaunchKernelGGL(k_long_fill, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, h->vtx_ptr,
+                       is_long, slot_of, chunk_of, h->long_row, h->long_chunk0, h->chunk_slot,
+                       h->chunk_begin, h->chunk_end);
+    B_HIP(hipGetLastError());
+    B_HIP(hipMemcpyAsync(h->long_chunk0 + h->n_long, &h->n_chunks, sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
+    B_HIP(hipFreeAsync(tmpi, s));
+    // per-graph slot ranges: long rows are listed in increasing vertex id, so
+    // each graph's long rows are contiguous
+    std::vector<int32_t> lr(h->n_long);
+    if (h->n_long)
+      B_HIP(hipMemcpyAsync(lr.data(), h->long_row, 4 * size_t(h->n_long), hipMemcpyDeviceToHost, s));
+    B_HIP(hipStreamSynchronize(s));
+    h->seg_slots_host.assign(4 * G, 0);
+    int t = 0, l = 0;
+    std::vector<int32_t> lseg(h->n_long);
+    for (int g = 0; g < G; ++g) {
+      // tiles were generated graph by graph, so graph g owns a contiguous range
+      int t0 = t;
+      t += (vtx_off_host[g + 1] - vtx_off_host[g] + kTileRows - 1) / kTileRows;
+      int l0 = l;
+      while (l < h->n_long && lr[l] < vtx_off_host[g + 1]) lseg[l++] = g;
+      h->seg_slots_host[4 * g + 0] = t0;
+      h->seg_slots_host[4 * g + 1] = t;
+      h->seg_slots_host[4 * g + 2] = h->n_tiles + l0;
+      h->seg_slots_host[4 * g + 3] = h->n_tiles + l;
+    }
+    B_TRY(dev_alloc(&h->long_seg, h->n_long));
+    if (h->n_long)
+      B_HIP(hipMemcpyAsync(h->long_seg, lseg.data(), 4 * size_t(h->n_long), hipMemcpyHostToDevice, s));
+    B_TRY(dev_alloc(&h->seg_slots, 4 * G));
+    B_HIP(hipMemcpyAsync(h->seg_slots, h->seg_slots_host.data(), 16 * size_t(G), hipMemcpyHostToDevice, s));
+    B_HIP(hipStreamSynchronize(s));
+  }
+  B_TRY(ensure_counters(h, kMaxSlabs, s));
+  B_HIP(hipStreamSynchronize(s));
+#undef B_TRY
+#undef B_HIP
+  *out = h;
+  return HGL_OK;
+}
+
+}  // namespace hgl
+
+using namespace hgl;
+
+extern "C" int hgl_version(void) { return 100; }
+
+extern "C" const char* hgl_last_error(void) { return g_err; }
+
+extern "C" int hgl_build_laplacian(int32_t N, int32_t E, int64_t nnz, const int32_t* edge_ptr,
+                                   const int32_t* edge_vtx, const double* w, hgl_handle** out,
+                                   hipStream_t stream) {
+  clear_error();
+  int32_t vo[2] = {0, N}, eo[2] = {0, E};
+  HGL_CHECK_ARG(N >= 1 && E >= 0, "need N >= 1 and E >= 0 (got N=%d, E=%d)", N, E);
+  return build(1, vo, eo, nnz, edge_ptr, edge_vtx, w, out, stream);
+}
+
+extern "C" int hgl_build_laplacian_batched(int32_t G, const int32_t* vtx_offsets_host,
+                                           const int32_t* edge_offsets_host, int64_t nnz,
+                                           const int32_t* edge_ptr, const int32_t* edge_vtx,
+                                           const double* w, hgl_handle** out, hipStream_t stream) {
+  clear_error();
+  return build(G, vtx_offsets_host, edge_offsets_host, nnz, edge_ptr, edge_vtx, w, out, stream);
+}
+
+extern "C" int hgl_set_weights(hgl_handle* h, const double* w, hipStream_t s) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  HGL_CHECK_ARG(h->E == 0 || w != nullptr, "w is NULL");
+  if (h->E == 0) return HGL_OK;
+  int32_t* d_err = nullptr;
+  HGL_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_err), 2 * sizeof(int32_t), s));
+  int32_t err_init[2] = {0, 0x7fffffff};
+  HGL_HIP(hipMemcpyAsync(d_err, err_init, sizeof(err_init), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_validate_w, dim3(blocks_for(h->E, 256)), dim3(256), 0, s, h->E, w, d_err);
+  HGL_HIP(hipGetLastError());
+  HGL_HIP(hipMemcpyAsync(h->pinned_i, d_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HGL_HIP(hipFreeAsync(d_err, s));
+  HGL_HIP(hipStreamSynchronize(s));
+  HGL_TRY(check_error_words(h->pinned_i));
+  HGL_HIP(hipMemcpyAsync(h->w, w, sizeof(double) * h->E, hipMemcpyDeviceToDevice, s));
+  return compute_scales(h, s);
+}
+
+extern "C" void hgl_destroy(hgl_handle* h) {
+  if (!h) return;
+  hipDeviceSynchronize();
+  free_handle(h);
+}
+
+extern "C" int hgl_get_sizes(const hgl_handle* h, int32_t* N, int32_t* E, int64_t* nnz, int32_t* G) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  if (N) *N = h->N;
+  if (E) *E = h->E;
+  if (nnz) *nnz = h->nnz;
+  if (G) *G = h->G;
+  return HGL_OK;
+}
+
+extern "C" int hgl_get_operator(const hgl_handle* h, double* dv, double* s, double* c,
+                                int32_t* vtx_ptr, int32_t* vtx_edge, hipStream_t st) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  auto D2D = hipMemcpyDeviceToDevice;
+  if (dv) HGL_HIP(hipMemcpyAsync(dv, h->dv, sizeof(double) * h->N, D2D, st));
+  if (s) HGL_HIP(hipMemcpyAsync(s, h->s64, sizeof(double) * h->N, D2D, st));
+  if (c && h->E) HGL_HIP(hipMemcpyAsync(c, h->c64, sizeof(double) * h->E, D2D, st));
+  if (vtx_ptr) HGL_HIP(hipMemcpyAsync(vtx_ptr, h->vtx_ptr, sizeof(int32_t) * (h->N + 1), D2D, st));
+  if (vtx_edge && h->nnz) HGL_HIP(hipMemcpyAsync(vtx_edge, h->vtx_edge, sizeof(int32_t) * h->nnz, D2D, st));
+  return HGL_OK;
+}

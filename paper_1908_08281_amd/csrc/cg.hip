@@ -1,0 +1,487 @@
+// Conjugate gradient for (I + L/lambda) F = Y, every (graph, column) with its
+// own recurrence (paper, section 3, eqs. 16-20):
+//   alpha = r'r / p'Mp,  f += alpha p,  r -= alpha Mp,
+//   beta = r_new'r_new / r'r,  p = r + beta p.
+// One iteration is a fixed sequence of launches on one stream:
+//   edge gather (Z = C H' S P) -> vertex gather (Q = M P, partial p'Q)
+//   -> reduce: alpha -> update (F, R, partial r'r)
+//   -> [residual replacement: R = Y - M F with FP64 accumulation, partial r'r]
+//   -> reduce: beta, convergence -> direction update (P = R + beta P).
+// Inner products are accumulated in FP64 per workgroup and reduced in a fixed
+// order (deterministic).  Converged columns get alpha = 0; once every column
+// has converged the remaining launches of an enqueued chunk return at once.
+#include <algorithm>
+#include <cmath>
+
+#include "kernels.h"
+
+namespace hgl {
+
+enum : int32_t { kActive = 0, kDone = 1, kBreakdown = 2 };
+
+struct CgState {
+  double* yy;      // [G*k] ||y||^2
+  double* rr;      // [G*k] r'r of the current residual
+  double* alpha;   // [G*k]
+  double* beta;    // [G*k]
+  double* relres;  // [G*k] last FP64-recomputed relative residual
+  int32_t* state;  // [G*k]
+  int32_t* iters;  // [G*k]
+};
+
+// ------------------------------------------------------- row-stream kernels --
+
+// Zero the long-row slots of a partial array (those rows are covered by the
+// tile sums in the row-stream kernels).
+__device__ __forceinline__ void zero_long_slots(double* part, int n_tiles, int n_slots, int n_long,
+                                                int k) {
+  const int64_t total = int64_t(n_long) * k;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = i / n_long, l = i % n_long;
+    part[c * n_slots + n_tiles + l] = 0.0;
+  }
+}
+
+// Start: (x0 not given) F = 0, R = Y; then P = R.  Partials of r'r (only when
+// x0 is not given; otherwise the residual pass produced them) and of y'y.
+template <class T, int GL, int V>
+__global__ __launch_bounds__(kBlock) void k_cg_init(int32_t n_tiles, const int32_t* __restrict__ tile_r0,
+                                                    const int32_t* __restrict__ tile_r1, int n_slots,
+                                                    int n_long, const T* __restrict__ Y, int64_t ldy,
+                                                    T* __restrict__ F, int64_t ldf, T* __restrict__ R,
+                                                    T* __restrict__ P, int64_t ld, double* __restrict__ part_rr,
+                                                    double* __restrict__ part_yy, int k, int x0_given) {
+  constexpr int GPB = kBlock / GL, W = GL * V;
+  __shared__ double lds[4 * W];
+  const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
+  const int col = blockIdx.y * W + lane * V;
+  const int t = blockIdx.x;
+  double rr[V], yy[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) rr[i] = yy[i] = 0.0;
+  if (col < k) {
+    for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
+      T y[V], rv[V];
+      load_row<V>(Y + int64_t(r) * ldy + col, y);
+      if (!x0_given) {
+        T z[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          z[i] = T(0);
+          rv[i] = y[i];
+        }
+        store_row<V>(F + int64_t(r) * ldf + col, z);
+        store_row<V>(R + int64_t(r) * ld + col, rv);
+      } else {
+        load_row<V>(R + int64_t(r) * ld + col, rv);
+      }
+      store_row<V>(P + int64_t(r) * ld + col, rv);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        yy[i] += double(y[i]) * double(y[i]);
+        rr[i] += double(rv[i]) * double(rv[i]);
+      }
+    }
+  }
+  double syy = block_colsum<GL, V>(yy, lds);
+  double srr = block_colsum<GL, V>(rr, lds);
+  const int c = blockIdx.y * W + threadIdx.x;
+  if (threadIdx.x < W && c < k) {
+    part_yy[int64_t(c) * n_slots + t] = syy;
+    if (!x0_given) part_rr[int64_t(c) * n_slots + t] = srr;
+  }
+  if (blockIdx.y == 0) {
+    zero_long_slots(part_yy, n_tiles, n_slots, n_long, k);
+    if (!x0_given) zero_long_slots(part_rr, n_tiles, n_slots, n_long, k);
+  }
+}
+
+// F += alpha P, R -= alpha Q; partial r'r.
+template <class T, int GL, int V>
+__global__ __launch_bounds__(kBlock) void k_cg_update(
+    int32_t n_tiles, const int32_t* __restrict__ tile_r0, const int32_t* __restrict__ tile_r1,
+    const int32_t* __restrict__ tile_seg, int n_slots, int n_long, T* __restrict__ F, int64_t ldf,
+    T* __restrict__ R, const T* __restrict__ P, const T* __restrict__ Q, int64_t ld,
+    const double* __restrict__ alpha, double* __restrict__ part_rr, int k, Gate gate) {
+  if (gate.skip()) return;
+  constexpr int GPB = kBlock / GL, W = GL * V;
+  __shared__ double lds[4 * W];
+  const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
+  const int col = blockIdx.y * W + lane * V;
+  const int t = blockIdx.x;
+  const int g = tile_seg[t];
+  double rr[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) rr[i] = 0.0;
+  if (col < k) {
+    T al[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) al[i] = T(alpha[int64_t(g) * k + col + i]);
+    for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
+      T f[V], rv[V], p[V], q[V];
+      load_row<V>(F + int64_t(r) * ldf + col, f);
+      load_row<V>(R + int64_t(r) * ld + col, rv);
+      load_row<V>(P + int64_t(r) * ld + col, p);
+      load_row<V>(Q + int64_t(r) * ld + col, q);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        f[i] += al[i] * p[i];
+        rv[i] -= al[i] * q[i];
+        rr[i] += double(rv[i]) * double(rv[i]);
+      }
+      store_row<V>(F + int64_t(r) * ldf + col, f);
+      store_row<V>(R + int64_t(r) * ld + col, rv);
+    }
+  }
+  double s = block_colsum<GL, V>(rr, lds);
+  const int c = blockIdx.y * W + threadIdx.x;
+  if (threadIdx.x < W && c < k) part_rr[int64_t(c) * n_slots + t] = s;
+  if (blockIdx.y == 0) zero_long_slots(part_rr, n_tiles, n_slots, n_long, k);
+}
+
+// P = R + beta P.
+template <class T, int GL, int V>
+__global__ __launch_bounds__(kBlock) void k_cg_direction(
+    const int32_t* __restrict__ tile_r0, const int32_t* __restrict__ tile_r1,
+    const int32_t* __restrict__ tile_seg, const T* __restrict__ R, T* __restrict__ P, int64_t ld,
+    const double* __restrict__ beta, int k, Gate gate) {
+  if (gate.skip()) return;
+  constexpr int GPB = kBlock / GL, W = GL * V;
+  const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
+  const int col = blockIdx.y * W + lane * V;
+  const int t = blockIdx.x;
+  if (col >= k) return;
+  const int g = tile_seg[t];
+  T be[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) be[i] = T(beta[int64_t(g) * k + col + i]);
+  for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
+    T rv[V], p[V];
+    load_row<V>(R + int64_t(r) * ld + col, rv);
+    load_row<V>(P + int64_t(r) * ld + col, p);
+#pragma unroll
+    for (int i = 0; i < V; ++i) p[i] = rv[i] + be[i] * p[i];
+    store_row<V>(P + int64_t(r) * ld + col, p);
+  }
+}
+
+// --------------------------------------------------------------- reductions --
+
+// Sum of part[col][slots of graph g] in a fixed order by one wave.
+__device__ __forceinline__ double wave_slot_sum(const double* __restrict__ part, int64_t n_slots,
+                                                const int32_t* __restrict__ seg_slots, int g, int col) {
+  const int lane = threadIdx.x % kWave;
+  const int t0 = seg_slots[4 * g], t1 = seg_slots[4 * g + 1];
+  const int l0 = seg_slots[4 * g + 2], l1 = seg_slots[4 * g + 3];
+  const double* p = part + int64_t(col) * n_slots;
+  double s = 0.0;
+  for (int i = t0 + lane; i < t1; i += kWave) s += p[i];
+  for (int i = l0 + lane; i < l1; i += kWave) s += p[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+  return s;
+}
+
+enum class RedOp { Init, Alpha, Beta, Final };
+
+struct RedArgs {
+  int G, k, n_slots;
+  const int32_t* seg_slots;
+  const double* part;   // rr (Init, Beta, Final) or p'Mp (Alpha)
+  const double* part2;  // yy (Init)
+  double tol;
+  int iter;             // iteration index (parity of the flag words)
+  int periodic;         // residual replacement scheduled this iteration
+};
+
+// Flag words: cnt(it) = columns still active after iteration it (cnt(-1) after
+// the start), need(it) = some column claimed convergence before iteration it,
+// so its residual pass must run.  One word per iteration: never reset inside
+// the loop, so no launch can observe a word another launch is clearing.
+struct Words {
+  int32_t* base;
+  int max_iter;
+  __host__ __device__ int32_t* cnt(int it) const { return base + 1 + it; }
+  __host__ __device__ int32_t* need(int it) const { return base + (max_iter + 2) + 1 + it; }
+  __host__ __device__ int32_t* err() const { return base + 2 * (max_iter + 2) + 2; }
+  static size_t count(int max_iter) { return 2 * size_t(max_iter + 2) + 4; }
+};
+
+template <RedOp OP>
+__global__ __launch_bounds__(kBlock) void k_cg_reduce(RedArgs ra, CgState st, Words wd) {
+  const int it = ra.iter;
+  if constexpr (OP == RedOp::Alpha || OP == RedOp::Beta) {
+    if (*wd.cnt(it - 1) == 0) return;
+  }
+  const int wid = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (wid >= ra.G * ra.k) return;
+  const int g = wid / ra.k, col = wid % ra.k;
+  const double sum = wave_slot_sum(ra.part, ra.n_slots, ra.seg_slots, g, col);
+  double sum2 = 0.0;
+  if constexpr (OP == RedOp::Init) sum2 = wave_slot_sum(ra.part2, ra.n_slots, ra.seg_slots, g, col);
+  if (threadIdx.x % kWave != 0) return;
+  const int64_t id = wid;
+  if constexpr (OP == RedOp::Init) {
+    st.yy[id] = sum2;
+    st.rr[id] = sum;
+    st.iters[id] = 0;
+    st.alpha[id] = 0.0;
+    st.beta[id] = 0.0;
+    double rel = sum2 > 0.0 ? sqrt(sum / sum2) : sqrt(sum);
+    st.relres[id] = rel;
+    const bool done = sum2 == 0.0 || rel <= ra.tol;
+    st.state[id] = done ? kDone : kActive;
+    if (!done) atomicAdd(wd.cnt(-1), 1);
+  } else if constexpr (OP == RedOp::Alpha) {
+    if (st.state[id] != kActive) {
+      st.alpha[id] = 0.0;
+      return;
+    }
+    if (!(sum > 0.0) || !isfinite(sum) || !isfinite(st.rr[id])) {
+      st.alpha[id] = 0.0;
+      st.state[id] = kBreakdown;
+      atomicOr(wd.err(), 1);
+      return;
+    }
+    st.alpha[id] = st.rr[id] / sum;
+  } else if constexpr (OP == RedOp::Beta) {
+    if (st.state[id] != kActive) {
+      st.beta[id] = 0.0;
+      return;
+    }
+    st.iters[id] += 1;
+    const bool ran = ra.periodic || *wd.need(it) != 0;
+    const double yy = st.yy[id];
+    const double rel = sqrt(sum / yy);
+    if (ran) st.relres[id] = rel;
+    if (ran && rel <= ra.tol) {
+      st.state[id] = kDone;
+      st.beta[id] = 0.0;
+      st.rr[id] = sum;
+      return;
+    }
+    if (!ran && rel <= ra.tol) *wd.need(it + 1) = 1;
+    if (!isfinite(sum)) {
+      st.state[id] = kBreakdown;
+      atomicOr(wd.err(), 1);
+      st.beta[id] = 0.0;
+      return;
+    }
+    st.beta[id] = sum / st.rr[id];
+    st.rr[id] = sum;
+    atomicAdd(wd.cnt(it), 1);
+  } else {  // Final: true residual of the returned F for unfinished columns
+    if (st.state[id] == kActive) st.relres[id] = st.yy[id] > 0.0 ? sqrt(sum / st.yy[id]) : sqrt(sum);
+  }
+}
+
+// ------------------------------------------------------------------ driver --
+
+template <class T>
+struct CgBuffers {
+  T* R;
+  T* P;
+  T* Q;
+  T* Z;        // E x k, type T
+  double* Z64; // E x k FP64 (residual passes of the FP32 mode)
+  double* part;
+  double* part2;
+  CgState st;
+};
+
+template <class T>
+static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const T* Y, int64_t ldy,
+                  T* F, int64_t ldf, int k, int32_t* iters_host, double* relres_host, hipStream_t s) {
+  const bool fp32 = sizeof(T) == 4;
+  const int N = h->N, E = h->E, G = h->G;
+  const int64_t ld = k;  // internal vectors
+  const int nsl = n_slots(h);
+  // ---------------------------------------------------------- workspace
+  const size_t vec = sizeof(T) * size_t(N) * ld;
+  HGL_TRY(h->ws_vec.reserve(3 * vec + 256));
+  HGL_TRY(h->ws_z.reserve(sizeof(T) * size_t(std::max(E, 1)) * ld));
+  if (fp32) HGL_TRY(h->ws_z64.reserve(sizeof(double) * size_t(std::max(E, 1)) * ld));
+  HGL_TRY(h->ws_part.reserve(sizeof(double) * size_t(nsl) * k));
+  HGL_TRY(h->ws_part2.reserve(sizeof(double) * size_t(nsl) * k));
+  const size_t gk = size_t(G) * k;
+  HGL_TRY(h->ws_state.reserve(sizeof(double) * 5 * gk + sizeof(int32_t) * (2 * gk + Words::count(o->max_iter))));
+  HGL_TRY(ensure_pinned(h, 2 * gk + 8));
+  if (h->n_chunks > 0) HGL_TRY(h->ws_chunk.reserve(sizeof(double) * size_t(h->n_chunks) * k));
+  HGL_TRY(upload_ab(h, lambdas, s));
+  const double* a_seg = h->ws_ab.as<double>();
+  const double* b_seg = a_seg + G;
+
+  CgBuffers<T> b;
+  b.R = h->ws_vec.as<T>();
+  b.P = b.R + size_t(N) * ld;
+  b.Q = b.P + size_t(N) * ld;
+  b.Z = h->ws_z.as<T>();
+  b.Z64 = fp32 ? h->ws_z64.as<double>() : reinterpret_cast<double*>(b.Z);
+  b.part = h->ws_part.as<double>();
+  b.part2 = h->ws_part2.as<double>();
+  double* sd = h->ws_state.as<double>();
+  b.st.yy = sd;
+  b.st.rr = sd + gk;
+  b.st.alpha = sd + 2 * gk;
+  b.st.beta = sd + 3 * gk;
+  b.st.relres = sd + 4 * gk;
+  b.st.state = reinterpret_cast<int32_t*>(sd + 5 * gk);
+  b.st.iters = b.st.state + gk;
+  Words wd{b.st.iters + gk, o->max_iter};
+  HGL_HIP(hipMemsetAsync(wd.base, 0, Words::count(o->max_iter) * sizeof(int32_t), s));
+
+  const ColShape cs = pick_shape(k, sizeof(T), {Y, F, b.R}, {ldy, ldf, ld});
+  const ColShape cs64 = pick_shape(k, 8, {Y, F, b.R}, {ldy, ldf, ld});
+  const int red_blocks = int((gk + 3) / 4);
+  RedArgs ra{G, k, nsl, h->seg_slots, b.part, b.part2, o->tol, 0, 0};
+
+  // residual pass R = Y - M F (FP64 accumulation), partial r'r into b.part
+  auto resid = [&](Gate gate) -> int {
+    if constexpr (sizeof(T) == 4) {
+      HGL_TRY(launch_spmm_edge<float, double>(h, F, ldf, b.Z64, ld, k, cs64, gate, s));
+      HGL_TRY(launch_spmm_vertex<float, double>(h, VMode::Resid, F, ldf, b.Z64, ld, Y, ldy, b.R, ld,
+                                                a_seg, b_seg, b.part, k, cs64, gate, s));
+    } else {
+      HGL_TRY(launch_spmm_edge<double, double>(h, F, ldf, b.Z64, ld, k, cs64, gate, s));
+      HGL_TRY(launch_spmm_vertex<double, double>(h, VMode::Resid, F, ldf, b.Z64, ld, Y, ldy, b.R, ld,
+                                                 a_seg, b_seg, b.part, k, cs64, gate, s));
+    }
+    return HGL_OK;
+  };
+
+  // ------------------------------------------------------------- start
+  if (o->x0_given) HGL_TRY(resid(Gate{}));
+  int rc = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
+    dim3 grid(h->n_tiles, cs.slabs);
+    hipLaunchKernelGGL((k_cg_init<T, GL, V>), grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
+                       h->tile_r1, nsl, h->n_long, Y, ldy, F, ldf, b.R, b.P, ld, b.part, b.part2, k,
+                       o->x0_given ? 1 : 0);
+    HGL_HIP(hipGetLastError());
+    return HGL_OK;
+  });
+  HGL_TRY(rc);
+  ra.iter = -1;
+  hipLaunchKernelGGL((k_cg_reduce<RedOp::Init>), dim3(red_blocks), dim3(kBlock), 0, s, ra, b.st, wd);
+  HGL_HIP(hipGetLastError());
+
+  // ---------------------------------------------------------- iterations
+  auto iteration = [&](int it) -> int {
+    Gate g_prev{wd.cnt(it - 1), nullptr, 1};
+    HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, cs, g_prev, s));
+    HGL_TRY(launch_spmm_vertex<T, T>(h, VMode::ApplyDot, b.P, ld, b.Z, ld, nullptr, 0, b.Q, ld, a_seg,
+                                     b_seg, b.part, k, cs, g_prev, s));
+    RedArgs r = ra;
+    r.iter = it;
+    hipLaunchKernelGGL((k_cg_reduce<RedOp::Alpha>), dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
+    HGL_HIP(hipGetLastError());
+    int rc2 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
+      dim3 grid(h->n_tiles, cs.slabs);
+      hipLaunchKernelGGL((k_cg_update<T, GL, V>), grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
+                         h->tile_r1, h->tile_seg, nsl, h->n_long, F, ldf, b.R, b.P, b.Q, ld,
+                         b.st.alpha, b.part, k, g_prev);
+      HGL_HIP(hipGetLastError());
+      return HGL_OK;
+    });
+    HGL_TRY(rc2);
+    const int periodic = (fp32 && o->rr_period > 0 && (it + 1) % o->rr_period == 0) ? 1 : 0;
+    HGL_TRY(resid(Gate{wd.cnt(it - 1), wd.need(it), periodic}));
+    r.periodic = periodic;
+    hipLaunchKernelGGL((k_cg_reduce<RedOp::Beta>), dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
+    HGL_HIP(hipGetLastError());
+    Gate g_now{wd.cnt(it), nullptr, 1};
+    int rc3 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
+      dim3 grid(h->n_tiles, cs.slabs);
+      hipLaunchKernelGGL((k_cg_direction<T, GL, V>), grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
+                         h->tile_seg, b.R, b.P, ld, b.st.beta, k, g_now);
+      HGL_HIP(hipGetLastError());
+      return HGL_OK;
+    });
+    return rc3;
+  };
+
+  int chunk = o->chunk > 0 ? o->chunk : 4;
+  int it = 0;
+  bool all_done = false;
+  // host check of the start state
+  HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.cnt(-1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HGL_HIP(hipStreamSynchronize(s));
+  all_done = h->pinned_i[0] == 0;
+  while (!all_done && it < o->max_iter) {
+    const int n = std::min(chunk, o->max_iter - it);
+    for (int c = 0; c < n; ++c, ++it) HGL_TRY(iteration(it));
+    HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.cnt(it - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HGL_HIP(hipStreamSynchronize(s));
+    all_done = h->pinned_i[0] == 0;
+  }
+  if (!all_done) {
+    // true residual of the returned F for the unfinished columns
+    HGL_TRY(resid(Gate{}));
+    hipLaunchKernelGGL((k_cg_reduce<RedOp::Final>), dim3(red_blocks), dim3(kBlock), 0, s, ra, b.st, wd);
+    HGL_HIP(hipGetLastError());
+  }
+  // ---------------------------------------------------------- results
+  double* pd = h->pinned_d;
+  HGL_HIP(hipMemcpyAsync(pd, b.st.relres, sizeof(double) * gk, hipMemcpyDeviceToHost, s));
+  HGL_HIP(hipMemcpyAsync(pd + gk, b.st.state, sizeof(int32_t) * 2 * gk, hipMemcpyDeviceToHost, s));
+  HGL_HIP(hipStreamSynchronize(s));
+  const int32_t* state_h = reinterpret_cast<const int32_t*>(pd + gk);
+  const int32_t* iters_h = state_h + gk;
+  bool breakdown = false, unconverged = false;
+  for (size_t i = 0; i < gk; ++i) {
+    if (state_h[i] == kBreakdown) breakdown = true;
+    if (state_h[i] == kActive) unconverged = true;
+    if (relres_host) relres_host[i] = pd[i];
+    if (iters_host) iters_host[i] = iters_h[i];
+  }
+  if (breakdown) {
+    set_error("CG breakdown: p'Mp <= 0 or a non-finite value (negative weight or NaN input?)");
+    return HGL_EBREAKDOWN;
+  }
+  return unconverged ? HGL_NOT_CONVERGED : HGL_OK;
+}
+
+static int cg_entry(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const void* Y,
+                    int64_t ldy, void* F, int64_t ldf, int32_t k, int32_t* iters_host,
+                    double* relres_host, hipStream_t s) {
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  HGL_CHECK_ARG(o != nullptr, "opts is NULL");
+  HGL_CHECK_ARG(lambdas != nullptr, "lambdas is NULL");
+  for (int g = 0; g < h->G; ++g)
+    HGL_CHECK_ARG(lambdas[g] > 0.0 && std::isfinite(lambdas[g]), "lambda must be > 0 (graph %d: %g)", g,
+                  lambdas[g]);
+  HGL_CHECK_ARG(o->tol > 0.0 && std::isfinite(o->tol), "tol must be > 0");
+  HGL_CHECK_ARG(o->max_iter >= 1, "max_iter must be >= 1");
+  HGL_CHECK_ARG(k >= 1, "k must be >= 1");
+  HGL_CHECK_ARG(Y && F, "Y and F must not be NULL");
+  HGL_CHECK_ARG(ldy >= k && ldf >= k, "leading dimensions must be >= k");
+  HGL_CHECK_ARG(o->rr_period >= 0, "rr_period must be >= 0");
+  if (o->mode == HGL_CG_PLAIN_F64)
+    return run_cg<double>(h, lambdas, o, static_cast<const double*>(Y), ldy, static_cast<double*>(F),
+                          ldf, k, iters_host, relres_host, s);
+  if (o->mode == HGL_CG_F32_F64DOT_RR)
+    return run_cg<float>(h, lambdas, o, static_cast<const float*>(Y), ldy, static_cast<float*>(F), ldf,
+                         k, iters_host, relres_host, s);
+  set_error("unknown CG mode %d", o->mode);
+  return HGL_EINVAL;
+}
+
+}  // namespace hgl
+
+using namespace hgl;
+
+extern "C" int hgl_cg_solve(hgl_handle* h, double lambda, const hgl_cg_opts* opts, const void* Y,
+                            int64_t ldy, void* F, int64_t ldf, int32_t k, int32_t* iters_host,
+                            double* relres_host, hipStream_t stream) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  std::vector<double> lams(h->G, lambda);
+  return cg_entry(h, lams.data(), opts, Y, ldy, F, ldf, k, iters_host, relres_host, stream);
+}
+
+extern "C" int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg_opts* opts,
+                                    const void* Y, int64_t ldy, void* F, int64_t ldf, int32_t k,
+                                    int32_t* iters_host, double* relres_host, hipStream_t stream) {
+  clear_error();
+  return cg_entry(h, lambdas_host, opts, Y, ldy, F, ldf, k, iters_host, relres_host, stream);
+}

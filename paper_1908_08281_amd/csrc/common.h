@@ -1,0 +1,193 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/hgl.h"
+
+namespace hgl {
+
+// ---------------------------------------------------------------- errors --
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+struct Status {
+  int code = HGL_OK;
+};
+
+// Return on a HIP error with HGL_EDEVICE and the runtime's message.
+#define HGL_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (call);                                                            \
+    if (_e != hipSuccess) {                                                            \
+      ::hgl::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(_e), __FILE__, \
+                       __LINE__);                                                      \
+      return HGL_EDEVICE;                                                              \
+    }                                                                                  \
+  } while (0)
+
+#define HGL_CHECK_ARG(cond, ...)   \
+  do {                             \
+    if (!(cond)) {                 \
+      ::hgl::set_error(__VA_ARGS__); \
+      return HGL_EINVAL;           \
+    }                              \
+  } while (0)
+
+#define HGL_TRY(...)              \
+  do {                            \
+    int _s = (__VA_ARGS__);       \
+    if (_s < 0) return _s;        \
+  } while (0)
+
+// ------------------------------------------------------------- constants --
+
+constexpr int kBlock = 256;        // threads per workgroup: 4 waves of 64
+constexpr int kWave = 64;
+constexpr int kTileRows = 64;      // rows per tile of the row-streaming kernels
+constexpr int kLongRow = 64;       // vertex rows with more hyperedges are split
+constexpr int kChunk = 256;        // hyperedges per chunk of a split vertex row
+constexpr int kMaxSlabs = 64;      // column slabs (of GL*V columns) per launch
+
+// ------------------------------------------------------ device buffers --
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int reserve(size_t n);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------- the handle --
+
+}  // namespace hgl
+
+struct hgl_handle {
+  int32_t N = 0, E = 0, G = 1;
+  int64_t nnz = 0;
+  int device = 0;
+
+  // structure (device)
+  int32_t* edge_ptr = nullptr;   // [E+1]
+  int32_t* edge_vtx = nullptr;   // [nnz]
+  int32_t* vtx_ptr = nullptr;    // [N+1]
+  int32_t* vtx_edge = nullptr;   // [nnz]
+
+  // weights and scales (device)
+  double* w = nullptr;           // [E]
+  double* dv = nullptr;          // [N]
+  double* s64 = nullptr;         // [N]
+  double* c64 = nullptr;         // [E]
+  float* s32 = nullptr;          // [N]
+  float* c32 = nullptr;          // [E]
+
+  // segments (graphs of a batched handle); host copies
+  std::vector<int32_t> vtx_off, edge_off;   // [G+1]
+
+  // row tiles for row-streaming kernels, segment-aligned (device)
+  int32_t n_tiles = 0;
+  int32_t* tile_r0 = nullptr;    // [n_tiles] first row
+  int32_t* tile_r1 = nullptr;    // [n_tiles] one past last row
+  int32_t* tile_seg = nullptr;   // [n_tiles]
+
+  // vertex rows with more than kLongRow hyperedges, split into chunks (device)
+  int32_t n_long = 0;
+  int32_t n_chunks = 0;
+  int32_t* long_row = nullptr;       // [n_long] vertex id, increasing
+  int32_t* long_seg = nullptr;       // [n_long] graph of the row
+  int32_t* chunk_slot = nullptr;     // [n_chunks] index into long_row
+  int32_t* chunk_begin = nullptr;    // [n_chunks] position in vtx_edge
+  int32_t* chunk_end = nullptr;      // [n_chunks]
+  int32_t* long_chunk0 = nullptr;    // [n_long+1] first chunk of each long row
+  int32_t* long_counter = nullptr;   // [n_long * max_slabs] arrival counters (kept zero)
+  int32_t counter_slabs = 0;
+
+  // per segment: partial-slot ranges {t0, t1, l0, l1} (device, [G*4])
+  int32_t* seg_slots = nullptr;
+  std::vector<int32_t> seg_slots_host;
+
+  // scratch owned by the handle
+  hgl::DevBuf ws_z, ws_z64, ws_chunk, ws_part, ws_part2, ws_vec, ws_state, ws_misc;
+  hgl::DevBuf ws_extra[8];
+  hgl::DevBuf ws_ab;                 // per-graph (1 + 1/lambda, 1/lambda)
+  std::vector<double> ab_cache;      // lambdas held in ws_ab
+
+  // kernel timing (diagnostics)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_pool;                 // free events
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
+  int64_t prof_launches[8] = {0};
+  double prof_ms[8] = {0};
+  hipEvent_t prof_open = nullptr;
+  int prof_kind = -1;
+  int32_t* pinned_i = nullptr;   // host-pinned readback words
+  double* pinned_d = nullptr;
+  size_t pinned_d_len = 0;
+};
+
+namespace hgl {
+
+// Partial-slot count of the reductions: one per tile, one per long row.
+inline int n_slots(const hgl_handle* h) { return h->n_tiles + h->n_long; }
+
+int ensure_counters(hgl_handle* h, int slabs, hipStream_t s);
+int ensure_pinned(hgl_handle* h, size_t n_doubles);
+
+// Launch shape of the column dimension: GL lanes per row, V elements per lane.
+struct ColShape {
+  int GL = 64;
+  int V = 1;
+  int slabs = 1;
+  int width() const { return GL * V; }
+};
+ColShape pick_shape(int k, int elem_bytes, std::initializer_list<const void*> ptrs,
+                    std::initializer_list<int64_t> lds);
+
+// Early-exit gate of a kernel launched inside the CG loop: the kernel does
+// nothing when *active == 0 (every column converged) or when it is a
+// conditional residual pass (*flag == 0 and not periodic).
+struct Gate {
+  const int32_t* active = nullptr;
+  const int32_t* flag = nullptr;
+  int32_t periodic = 1;
+  __device__ __forceinline__ bool skip() const {
+    if (active && *active == 0) return true;
+    if (flag && !periodic && *flag == 0) return true;
+    return false;
+  }
+};
+
+int upload_ab(hgl_handle* h, const double* lambdas_host, hipStream_t st);
+
+// Kernel timing: bracket one launch of a kernel kind (no-ops unless enabled).
+enum ProfKind { kProfEdge = 0, kProfVertex = 1, kProfUpdate = 2, kProfDirection = 3,
+                kProfReduce = 4, kProfResidEdge = 5, kProfResidVertex = 6, kProfStart = 7 };
+void prof_begin(hgl_handle* h, int kind, hipStream_t s);
+void prof_end(hgl_handle* h, hipStream_t s);
+
+// Operator application pieces (spmm.hip).
+enum class VMode { Apply = 0, ApplyDot = 1, Resid = 2 };
+
+// Z = C H' S P: edge-major gather.  TIn = type of P, TAcc = type of Z.
+template <class TIn, class TAcc>
+int launch_spmm_edge(const hgl_handle* h, const TIn* P, int64_t ldp, TAcc* Z, int64_t ldz,
+                     int k, const ColShape& cs, Gate gate, hipStream_t s);
+
+// Vertex-major gather + epilogue.  Apply: Out = a X - b s H Z.  ApplyDot: same
+// and partial <X, Out> per column.  Resid: Out = Y - (a X - b s H Z) with FP64
+// accumulation and partial <Out, Out>.  a, b per segment (device, [G]).
+template <class T, class TZ>
+int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx, const TZ* Z,
+                       int64_t ldz, const T* Y, int64_t ldy, T* Out, int64_t ldo,
+                       const double* a_seg, const double* b_seg, double* part, int k,
+                       const ColShape& cs, Gate gate, hipStream_t s);
+
+}  // namespace hgl

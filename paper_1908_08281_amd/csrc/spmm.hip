@@ -1,0 +1,362 @@
+// Matrix-free application of M = I + L/lambda = (1 + 1/lambda) I - (1/lambda) A
+// with A = S H C H' S (paper, section 2, eq. 1), S = diag(delta(v)^-1/2),
+// C = diag(w_e/delta(e)).  Two gathers, no atomics:
+//   Z = C H' S P        edge-major:   Z[e,:] = c_e * sum_{v in e} s_v P[v,:]
+//   Q = a P - b S H Z   vertex-major: Q[v,:] = a P[v,:] - b s_v sum_{e ni v} Z[e,:]
+// with a = 1 + 1/lambda, b = 1/lambda.  Rows of P, Z, Q are k-wide and
+// contiguous; a group of GL lanes owns one row and each lane moves V
+// consecutive elements per access, so every gathered row is one coalesced
+// 16-byte-per-lane transaction.  Vertex rows with more than kLongRow incident
+// hyperedges (hubs) are split into chunks processed by separate workgroups;
+// the last chunk to arrive sums the chunk partials in chunk order and
+// finishes the row, so results do not depend on scheduling.
+#include "kernels.h"
+
+namespace hgl {
+
+// ------------------------------------------------------------ edge gather --
+
+template <class TIn, class TAcc, int GL, int V>
+__global__ __launch_bounds__(kBlock) void k_spmm_edge(
+    int32_t E, const int32_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_vtx,
+    const TAcc* __restrict__ s, const TAcc* __restrict__ c, const TIn* __restrict__ P, int64_t ldp,
+    TAcc* __restrict__ Z, int64_t ldz, int k, Gate gate) {
+  if (gate.skip()) return;
+  constexpr int GPB = kBlock / GL;
+  const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
+  const int e = blockIdx.x * GPB + grp;
+  const int col = blockIdx.y * (GL * V) + lane * V;
+  if (e >= E || col >= k) return;
+  const int b = edge_ptr[e], en = edge_ptr[e + 1];
+  TAcc acc[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] = TAcc(0);
+  int j = b;
+  for (; j + 4 <= en; j += 4) {
+    int v0 = edge_vtx[j], v1 = edge_vtx[j + 1], v2 = edge_vtx[j + 2], v3 = edge_vtx[j + 3];
+    TAcc s0 = s[v0], s1 = s[v1], s2 = s[v2], s3 = s[v3];
+    TIn x0[V], x1[V], x2[V], x3[V];
+    load_row<V>(P + int64_t(v0) * ldp + col, x0);
+    load_row<V>(P + int64_t(v1) * ldp + col, x1);
+    load_row<V>(P + int64_t(v2) * ldp + col, x2);
+    load_row<V>(P + int64_t(v3) * ldp + col, x3);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      acc[i] += s0 * TAcc(x0[i]);
+      acc[i] += s1 * TAcc(x1[i]);
+      acc[i] += s2 * TAcc(x2[i]);
+      acc[i] += s3 * TAcc(x3[i]);
+    }
+  }
+  for (; j < en; ++j) {
+    int v0 = edge_vtx[j];
+    TAcc s0 = s[v0];
+    TIn x0[V];
+    load_row<V>(P + int64_t(v0) * ldp + col, x0);
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] += s0 * TAcc(x0[i]);
+  }
+  const TAcc ce = c[e];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] *= ce;
+  store_row<V>(Z + int64_t(e) * ldz + col, acc);
+}
+
+template <class TIn, class TAcc>
+int launch_spmm_edge(const hgl_handle* h, const TIn* P, int64_t ldp, TAcc* Z, int64_t ldz, int k,
+                     const ColShape& cs, Gate gate, hipStream_t st) {
+  if (h->E == 0) return HGL_OK;
+  const TAcc* s;
+  const TAcc* c;
+  if constexpr (sizeof(TAcc) == 8) {
+    s = h->s64;
+    c = h->c64;
+  } else {
+    s = h->s32;
+    c = h->c32;
+  }
+  return HGL_DISPATCH_SHAPE(cs, sizeof(TAcc), {
+    constexpr int GPB = kBlock / GL;
+    dim3 grid((h->E + GPB - 1) / GPB, cs.slabs);
+    hipLaunchKernelGGL((k_spmm_edge<TIn, TAcc, GL, V>), grid, dim3(kBlock), 0, st, h->E,
+                       h->edge_ptr, h->edge_vtx, s, c, P, ldp, Z, ldz, k, gate);
+    HGL_HIP(hipGetLastError());
+    return HGL_OK;
+  });
+}
+
+// ---------------------------------------------------------- vertex gather --
+
+struct VertexArgs {
+  int32_t n_tiles;
+  const int32_t* tile_r0;
+  const int32_t* tile_r1;
+  const int32_t* tile_seg;
+  const int32_t* vtx_ptr;
+  const int32_t* vtx_edge;
+  const int32_t* chunk_slot;
+  const int32_t* chunk_begin;
+  const int32_t* chunk_end;
+  const int32_t* long_row;
+  const int32_t* long_seg;
+  const int32_t* long_chunk0;
+  int32_t* long_counter;
+  int32_t counter_slabs;
+  int32_t n_slots;
+  const double* a_seg;
+  const double* b_seg;
+};
+
+// MODE 0: Out = a X - b s H Z.  MODE 1: same + partial <X, Out>.
+// MODE 2: Out = Y - (a X - b s H Z), partial <Out, Out>, all in TZ (FP64).
+template <class T, class TZ, int GL, int V, int MODE>
+__global__ __launch_bounds__(kBlock) void k_spmm_vertex(
+    VertexArgs va, const TZ* __restrict__ s, const T* __restrict__ X, int64_t ldx,
+    const TZ* __restrict__ Z, int64_t ldz, const T* __restrict__ Y, int64_t ldy, T* __restrict__ Out,
+    int64_t ldo, double* __restrict__ part, TZ* __restrict__ chunk_part, int k, Gate gate) {
+  if (gate.skip()) return;
+  constexpr int GPB = kBlock / GL;
+  constexpr int W = GL * V;
+  __shared__ double lds_d[4 * W];
+  __shared__ TZ lds_z[4 * W];
+  __shared__ int s_last;
+  const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
+  const int col = blockIdx.y * W + lane * V;
+  const bool colok = col < k;
+
+  if (int(blockIdx.x) < va.n_tiles) {
+    // ------------------------------------------------ a tile of short rows
+    const int t = blockIdx.x;
+    const int r0 = va.tile_r0[t], r1 = va.tile_r1[t];
+    const int g = va.tile_seg[t];
+    const TZ a = TZ(va.a_seg[g]), bb = TZ(va.b_seg[g]);
+    double dot[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) dot[i] = 0.0;
+    for (int r = r0 + grp; r < r1 && colok; r += GPB) {
+      const int eb = va.vtx_ptr[r], ee = va.vtx_ptr[r + 1];
+      if (ee - eb > kLongRow) continue;  // finished by its chunks
+      TZ acc[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] = TZ(0);
+      int j = eb;
+      for (; j + 4 <= ee; j += 4) {
+        int e0 = va.vtx_edge[j], e1 = va.vtx_edge[j + 1], e2 = va.vtx_edge[j + 2], e3 = va.vtx_edge[j + 3];
+        TZ z0[V], z1[V], z2[V], z3[V];
+        load_row<V>(Z + int64_t(e0) * ldz + col, z0);
+        load_row<V>(Z + int64_t(e1) * ldz + col, z1);
+        load_row<V>(Z + int64_t(e2) * ldz + col, z2);
+        load_row<V>(Z + int64_t(e3) * ldz + col, z3);
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[i] = ((acc[i] + z0[i]) + z1[i]) + z2[i] + z3[i];
+      }
+      for (; j < ee; ++j) {
+        TZ z0[V];
+        load_row<V>(Z + int64_t(va.vtx_edge[j]) * ldz + col, z0);
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[i] += z0[i];
+      }
+      T x[V], o[V];
+      load_row<V>(X + int64_t(r) * ldx + col, x);
+      const TZ sr = s[r];
+      if constexpr (MODE == 2) {
+        T y[V];
+        load_row<V>(Y + int64_t(r) * ldy + col, y);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          TZ ri = TZ(y[i]) - (a * TZ(x[i]) - bb * sr * acc[i]);
+          dot[i] += double(ri) * double(ri);
+          o[i] = T(ri);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          TZ q = a * TZ(x[i]) - bb * sr * acc[i];
+          o[i] = T(q);
+          if constexpr (MODE == 1) dot[i] += double(x[i]) * double(o[i]);
+        }
+      }
+      store_row<V>(Out + int64_t(r) * ldo + col, o);
+    }
+    if constexpr (MODE != 0) {
+      double tot = block_colsum<GL, V>(dot, lds_d);
+      const int c = blockIdx.y * W + threadIdx.x;
+      if (threadIdx.x < W && c < k) part[int64_t(c) * va.n_slots + t] = tot;
+    }
+    return;
+  }
+
+  // ------------------------------------------------ one chunk of a long row
+  const int ch = blockIdx.x - va.n_tiles;
+  const int slot = va.chunk_slot[ch];
+  const int eb = va.chunk_begin[ch], ee = va.chunk_end[ch];
+  TZ acc[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] = TZ(0);
+  if (colok) {
+    for (int j = eb + grp; j < ee; j += GPB) {
+      TZ z0[V];
+      load_row<V>(Z + int64_t(va.vtx_edge[j]) * ldz + col, z0);
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] += z0[i];
+    }
+  }
+  TZ csum = block_colsum<GL, V>(acc, lds_z);
+  {
+    const int c = blockIdx.y * W + threadIdx.x;
+    if (threadIdx.x < W && c < k) chunk_part[int64_t(ch) * k + c] = csum;
+  }
+  __threadfence();
+  __syncthreads();
+  const int nch = va.long_chunk0[slot + 1] - va.long_chunk0[slot];
+  int32_t* counter = va.long_counter + int64_t(slot) * va.counter_slabs + blockIdx.y;
+  if (threadIdx.x == 0) {
+    int prev = atomicAdd(counter, 1);
+    s_last = (prev == nch - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (threadIdx.x == 0) *counter = 0;  // ready for the next launch
+  const int c = blockIdx.y * W + threadIdx.x;
+  if (threadIdx.x >= W || c >= k) return;
+  const int r = va.long_row[slot];
+  const int g = va.long_seg[slot];
+  const TZ a = TZ(va.a_seg[g]), bb = TZ(va.b_seg[g]);
+  const int c0 = va.long_chunk0[slot];
+  TZ sum = TZ(0);
+  for (int q = 0; q < nch; ++q) sum += chunk_part[int64_t(c0 + q) * k + c];
+  const TZ sr = s[r];
+  const TZ x = TZ(X[int64_t(r) * ldx + c]);
+  double d = 0.0;
+  if constexpr (MODE == 2) {
+    TZ ri = TZ(Y[int64_t(r) * ldy + c]) - (a * x - bb * sr * sum);
+    Out[int64_t(r) * ldo + c] = T(ri);
+    d = double(ri) * double(ri);
+  } else {
+    T o = T(a * x - bb * sr * sum);
+    Out[int64_t(r) * ldo + c] = o;
+    d = double(X[int64_t(r) * ldx + c]) * double(o);
+  }
+  if constexpr (MODE != 0) part[int64_t(c) * va.n_slots + va.n_tiles + slot] = d;
+}
+
+template <class T, class TZ>
+int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx, const TZ* Z,
+                       int64_t ldz, const T* Y, int64_t ldy, T* Out, int64_t ldo,
+                       const double* a_seg, const double* b_seg, double* part, int k,
+                       const ColShape& cs, Gate gate, hipStream_t st) {
+  hgl_handle* hm = const_cast<hgl_handle*>(h);
+  if (h->n_chunks > 0 && hm->ws_chunk.bytes < sizeof(TZ) * size_t(h->n_chunks) * k) {
+    // growing a buffer frees the old one: wait for queued work that may use it
+    HGL_HIP(hipStreamSynchronize(st));
+    HGL_TRY(hm->ws_chunk.reserve(sizeof(TZ) * size_t(h->n_chunks) * k));
+  }
+  VertexArgs va{h->n_tiles,     h->tile_r0,    h->tile_r1,    h->tile_seg,   h->vtx_ptr,
+                h->vtx_edge,    h->chunk_slot, h->chunk_begin, h->chunk_end, h->long_row,
+                h->long_seg,    h->long_chunk0, h->long_counter, h->counter_slabs,
+                n_slots(h),     a_seg,         b_seg};
+  const TZ* s;
+  if constexpr (sizeof(TZ) == 8) s = h->s64; else s = h->s32;
+  TZ* cp = hm->ws_chunk.as<TZ>();
+  dim3 grid(h->n_tiles + h->n_chunks, cs.slabs);
+  if (cs.slabs > h->counter_slabs && h->n_long > 0) {
+    set_error("k too large for this build (%d column slabs)", cs.slabs);
+    return HGL_EUNSUPPORTED;
+  }
+  if (mode == VMode::Resid && sizeof(TZ) != 8) {
+    set_error("residual mode needs FP64 accumulation");
+    return HGL_EUNSUPPORTED;
+  }
+  return HGL_DISPATCH_SHAPE(cs, sizeof(T) > sizeof(TZ) ? sizeof(T) : sizeof(TZ), {
+    if (mode == VMode::Apply)
+      hipLaunchKernelGGL((k_spmm_vertex<T, TZ, GL, V, 0>), grid, dim3(kBlock), 0, st, va, s, X, ldx,
+                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
+    else if (mode == VMode::ApplyDot)
+      hipLaunchKernelGGL((k_spmm_vertex<T, TZ, GL, V, 1>), grid, dim3(kBlock), 0, st, va, s, X, ldx,
+                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
+    else if constexpr (sizeof(TZ) == 8)
+      hipLaunchKernelGGL((k_spmm_vertex<T, TZ, GL, V, 2>), grid, dim3(kBlock), 0, st, va, s, X, ldx,
+                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
+    HGL_HIP(hipGetLastError());
+    return HGL_OK;
+  });
+}
+
+template int launch_spmm_edge<float, float>(const hgl_handle*, const float*, int64_t, float*,
+                                            int64_t, int, const ColShape&, Gate, hipStream_t);
+template int launch_spmm_edge<float, double>(const hgl_handle*, const float*, int64_t, double*,
+                                             int64_t, int, const ColShape&, Gate, hipStream_t);
+template int launch_spmm_edge<double, double>(const hgl_handle*, const double*, int64_t, double*,
+                                              int64_t, int, const ColShape&, Gate, hipStream_t);
+template int launch_spmm_vertex<float, float>(const hgl_handle*, VMode, const float*, int64_t,
+                                              const float*, int64_t, const float*, int64_t, float*,
+                                              int64_t, const double*, const double*, double*, int,
+                                              const ColShape&, Gate, hipStream_t);
+template int launch_spmm_vertex<float, double>(const hgl_handle*, VMode, const float*, int64_t,
+                                               const double*, int64_t, const float*, int64_t, float*,
+                                               int64_t, const double*, const double*, double*, int,
+                                               const ColShape&, Gate, hipStream_t);
+template int launch_spmm_vertex<double, double>(const hgl_handle*, VMode, const double*, int64_t,
+                                                const double*, int64_t, const double*, int64_t,
+                                                double*, int64_t, const double*, const double*,
+                                                double*, int, const ColShape&, Gate,
+                                                hipStream_t);
+
+// Per-graph (a, b) = (1 + 1/lambda_g, 1/lambda_g) in a device array [2G].
+int upload_ab(hgl_handle* h, const double* lambdas_host, hipStream_t st) {
+  DevBuf& buf = h->ws_ab;
+  if (buf.p && h->ab_cache.size() == size_t(h->G) &&
+      std::equal(h->ab_cache.begin(), h->ab_cache.end(), lambdas_host))
+    return HGL_OK;
+  h->ab_cache.assign(lambdas_host, lambdas_host + h->G);
+  std::vector<double> ab(2 * h->G);
+  for (int g = 0; g < h->G; ++g) {
+    ab[g] = 1.0 + 1.0 / lambdas_host[g];
+    ab[h->G + g] = 1.0 / lambdas_host[g];
+  }
+  HGL_TRY(ensure_pinned(h, 2 * h->G));
+  HGL_TRY(buf.reserve(sizeof(double) * 2 * h->G));
+  // staged through pinned memory so the copy is truly asynchronous
+  std::copy(ab.begin(), ab.end(), h->pinned_d);
+  HGL_HIP(hipMemcpyAsync(buf.p, h->pinned_d, sizeof(double) * 2 * h->G, hipMemcpyHostToDevice, st));
+  HGL_HIP(hipStreamSynchronize(st));
+  return HGL_OK;
+}
+
+}  // namespace hgl
+
+using namespace hgl;
+
+extern "C" int hgl_apply(hgl_handle* h, double lambda, int32_t dt, const void* P, int64_t ldp,
+                         void* Q, int64_t ldq, int32_t k, hipStream_t st) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  HGL_CHECK_ARG(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0 (got %g)", lambda);
+  HGL_CHECK_ARG(k >= 1, "k must be >= 1");
+  HGL_CHECK_ARG(P && Q, "P and Q must not be NULL");
+  HGL_CHECK_ARG(ldp >= k && ldq >= k, "leading dimensions must be >= k");
+  HGL_CHECK_ARG(dt == HGL_F64 || dt == HGL_F32, "dtype must be HGL_F64 or HGL_F32");
+  std::vector<double> lams(h->G, lambda);
+  HGL_TRY(upload_ab(h, lams.data(), st));
+  const double* a_seg = h->ws_ab.as<double>();
+  const double* b_seg = a_seg + h->G;
+  if (dt == HGL_F32) {
+    ColShape cs = pick_shape(k, 4, {P, Q}, {ldp, ldq, int64_t(k)});
+    HGL_TRY(h->ws_z.reserve(sizeof(float) * size_t(h->E) * k));
+    float* Z = h->ws_z.as<float>();
+    HGL_TRY(launch_spmm_edge<float, float>(h, static_cast<const float*>(P), ldp, Z, k, k, cs, Gate{}, st));
+    HGL_TRY(launch_spmm_vertex<float, float>(h, VMode::Apply, static_cast<const float*>(P), ldp, Z, k,
+                                             nullptr, 0, static_cast<float*>(Q), ldq, a_seg, b_seg,
+                                             nullptr, k, cs, Gate{}, st));
+  } else {
+    ColShape cs = pick_shape(k, 8, {P, Q}, {ldp, ldq, int64_t(k)});
+    HGL_TRY(h->ws_z64.reserve(sizeof(double) * size_t(h->E) * k));
+    double* Z = h->ws_z64.as<double>();
+    HGL_TRY(launch_spmm_edge<double, double>(h, static_cast<const double*>(P), ldp, Z, k, k, cs, Gate{}, st));
+    HGL_TRY(launch_spmm_vertex<double, double>(h, VMode::Apply, static_cast<const double*>(P), ldp, Z,
+                                               k, nullptr, 0, static_cast<double*>(Q), ldq, a_seg,
+                                               b_seg, nullptr, k, cs, Gate{}, st));
+  }
+  return HGL_OK;
+}

@@ -1,0 +1,190 @@
+"""Thin PyTorch-facing binding of the C ABI (include/hgl.h).
+
+Torch supplies device memory and the current HIP stream; every step of the
+computation runs in the library's kernels.  Functions take and return torch
+tensors on a ROCm device; names follow the C entry points without the
+``hgl_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import CgOpts, check
+
+MODES = {"f64": _lib.HGL_CG_PLAIN_F64, "f32": _lib.HGL_CG_F32_F64DOT_RR}
+
+
+def lib():
+    return _lib.load()
+
+
+def _stream(device: torch.device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def _need(t: torch.Tensor, dtype, name: str, device=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a torch tensor on a ROCm device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t
+
+
+def _rows(t: torch.Tensor, name: str) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D row-major tensor with unit column stride")
+    return t.stride(0)
+
+
+class Handle:
+    """Owns an hgl_handle (the built operator of one or more hypergraphs)."""
+
+    def __init__(self, ptr: C.c_void_p, device: torch.device):
+        self._ptr = ptr
+        self.device = device
+        N, E, G = C.c_int32(), C.c_int32(), C.c_int32()
+        nnz = C.c_int64()
+        check(lib().hgl_get_sizes(ptr, C.byref(N), C.byref(E), C.byref(nnz), C.byref(G)),
+              "hgl_get_sizes")
+        self.N, self.E, self.nnz, self.G = N.value, E.value, nnz.value, G.value
+
+    @property
+    def ptr(self) -> C.c_void_p:
+        if self._ptr is None:
+            raise RuntimeError("handle already destroyed")
+        return self._ptr
+
+    def destroy(self):
+        if self._ptr is not None:
+            lib().hgl_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def build_laplacian(edge_ptr: torch.Tensor, edge_vtx: torch.Tensor, w: torch.Tensor, N: int) -> Handle:
+    dev = w.device
+    _need(edge_ptr, torch.int32, "edge_ptr", dev)
+    _need(edge_vtx, torch.int32, "edge_vtx", dev)
+    _need(w, torch.float64, "w", dev)
+    E = edge_ptr.numel() - 1
+    out = C.c_void_p()
+    with torch.cuda.device(dev):
+        check(lib().hgl_build_laplacian(N, E, edge_vtx.numel(), _ptr(edge_ptr), _ptr(edge_vtx), _ptr(w),
+                                        C.byref(out), _stream(dev)), "hgl_build_laplacian")
+    return Handle(out, dev)
+
+
+def build_laplacian_batched(vtx_offsets, edge_offsets, edge_ptr: torch.Tensor, edge_vtx: torch.Tensor,
+                            w: torch.Tensor) -> Handle:
+    dev = w.device
+    _need(edge_ptr, torch.int32, "edge_ptr", dev)
+    _need(edge_vtx, torch.int32, "edge_vtx", dev)
+    _need(w, torch.float64, "w", dev)
+    vo = np.ascontiguousarray(np.asarray(vtx_offsets, dtype=np.int32))
+    eo = np.ascontiguousarray(np.asarray(edge_offsets, dtype=np.int32))
+    G = vo.size - 1
+    out = C.c_void_p()
+    with torch.cuda.device(dev):
+        check(lib().hgl_build_laplacian_batched(
+            G, vo.ctypes.data_as(_lib.I32P), eo.ctypes.data_as(_lib.I32P), edge_vtx.numel(),
+            _ptr(edge_ptr), _ptr(edge_vtx), _ptr(w), C.byref(out), _stream(dev)),
+            "hgl_build_laplacian_batched")
+    return Handle(out, dev)
+
+
+def set_weights(h: Handle, w: torch.Tensor) -> None:
+    _need(w, torch.float64, "w", h.device)
+    if w.numel() != h.E:
+        raise ValueError("w must have E entries")
+    with torch.cuda.device(h.device):
+        check(lib().hgl_set_weights(h.ptr, _ptr(w), _stream(h.device)), "hgl_set_weights")
+
+
+def get_operator(h: Handle) -> dict:
+    dev = h.device
+    dv = torch.empty(h.N, dtype=torch.float64, device=dev)
+    s = torch.empty(h.N, dtype=torch.float64, device=dev)
+    c = torch.empty(max(h.E, 1), dtype=torch.float64, device=dev)
+    vp = torch.empty(h.N + 1, dtype=torch.int32, device=dev)
+    ve = torch.empty(max(h.nnz, 1), dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        check(lib().hgl_get_operator(h.ptr, _ptr(dv), _ptr(s), _ptr(c), _ptr(vp), _ptr(ve),
+                                     _stream(dev)), "hgl_get_operator")
+    return {"dv": dv, "s": s, "c": c[:h.E], "vtx_ptr": vp, "vtx_edge": ve[:h.nnz]}
+
+
+def apply(h: Handle, lam: float, P: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    if P.dtype not in (torch.float32, torch.float64):
+        raise TypeError("P must be float32 or float64")
+    _need(P, P.dtype, "P", h.device)
+    ldp = _rows(P, "P")
+    if P.shape[0] != h.N:
+        raise ValueError("P must have N rows")
+    Q = torch.empty_like(P, memory_format=torch.contiguous_format) if out is None else out
+    ldq = _rows(Q, "out")
+    dt = _lib.HGL_F64 if P.dtype == torch.float64 else _lib.HGL_F32
+    with torch.cuda.device(h.device):
+        check(lib().hgl_apply(h.ptr, float(lam), dt, _ptr(P), ldp, _ptr(Q), ldq, P.shape[1],
+                              _stream(h.device)), "hgl_apply")
+    return Q
+
+
+def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
+        x0: torch.Tensor | None, rr_period: int, chunk: int, batched: bool):
+    m = MODES[mode]
+    dtype = torch.float64 if m == _lib.HGL_CG_PLAIN_F64 else torch.float32
+    _need(Y, dtype, "Y", h.device)
+    ldy = _rows(Y, "Y")
+    if Y.shape[0] != h.N:
+        raise ValueError("Y must have N rows")
+    k = Y.shape[1]
+    if x0 is not None:
+        _need(x0, dtype, "x0", h.device)
+        F = x0.clone(memory_format=torch.contiguous_format)
+    else:
+        F = torch.empty((h.N, k), dtype=dtype, device=h.device)
+    opts = CgOpts(m, float(tol), int(max_iter), 1 if x0 is not None else 0, int(rr_period), int(chunk))
+    iters = np.zeros(h.G * k, dtype=np.int32)
+    rel = np.zeros(h.G * k, dtype=np.float64)
+    with torch.cuda.device(h.device):
+        if batched:
+            la = np.ascontiguousarray(np.asarray(lams, dtype=np.float64))
+            if la.size != h.G:
+                raise ValueError("need one lambda per graph")
+            st = lib().hgl_cg_solve_batched(h.ptr, la.ctypes.data_as(_lib.DP), C.byref(opts), _ptr(Y), ldy,
+                                            _ptr(F), F.stride(0), k, iters.ctypes.data_as(_lib.I32P),
+                                            rel.ctypes.data_as(_lib.DP), _stream(h.device))
+        else:
+            st = lib().hgl_cg_solve(h.ptr, float(lams), C.byref(opts), _ptr(Y), ldy, _ptr(F), F.stride(0), k,
+                                    iters.ctypes.data_as(_lib.I32P), rel.ctypes.data_as(_lib.DP),
+                                    _stream(h.device))
+    check(st, "hgl_cg_solve")
+    return F, iters.reshape(h.G, k), rel.reshape(h.G, k), st
+
+
+def cg_solve(h: Handle, lam: float, Y: torch.Tensor, mode: str = "f32", tol: float = 1e-6,
+             max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8, chunk: int = 0):
+    """Solve (I + L/lam) F = Y.  Returns (F, iters[G,k], relres[G,k], status)."""
+    return _cg(h, lam, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=False)
+
+
+def cg_solve_batched(h: Handle, lams, Y: torch.Tensor, mode: str = "f32", tol: float = 1e-6,
+                     max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8,
+                     chunk: int = 0):
+    """One lambda per graph of a batched handle."""
+    return _cg(h, lams, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=True)

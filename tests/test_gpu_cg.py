@@ -1,0 +1,145 @@
+"""GPU parity: CG solves (section 3, eqs. 16-20) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import laplacian as lap
+from oracle import solve
+from tests.helpers import build, colrelerr, device, hgl, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _dense_solution(p, lam=None):
+    H = lap.incidence_dense(p.N, p.E, p.edge_ptr, p.edge_vtx)
+    return solve.solve_dense(lap.system_matrix(H, p.w, p.lam if lam is None else lam), p.Y)
+
+
+def test_plain_f64_small_config_matches_cholesky():
+    """Plain method, small: N=2000, E=1500, k=50, FP64 CG to relres 1e-10."""
+    import torch
+    dev = device()
+    p = synth.small_plain()
+    say("cg f64 small_plain")
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev)
+    F, iters, rel, st = hgl().cg_solve(h, p.lam, Y, mode="f64", tol=1e-10, max_iter=200)
+    assert st == 0
+    Fo = _dense_solution(p)
+    F = F.cpu().numpy()
+    assert colrelerr(F, Fo).max() <= 2e-10
+    op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
+    rel_oracle = solve.relres(op, F, p.Y)
+    assert np.all(rel_oracle <= 1e-10)
+    assert np.allclose(rel[0], rel_oracle, rtol=1e-3, atol=1e-14)
+    assert iters.max() <= 30
+
+
+@pytest.mark.parametrize("k", [1, 17, 64, 200])
+def test_f32_mixed_matches_oracle(k):
+    import torch
+    dev = device()
+    p = synth.multi_rhs(N=4000, E=3200, k=k, smax=150)
+    say("cg f32", k)
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    tol = 1e-6 / (1 + 1 / p.lam)
+    F, iters, rel, st = hgl().cg_solve(h, p.lam, Y, mode="f32", tol=tol, max_iter=300)
+    assert st == 0
+    Fo = _dense_solution(p)
+    F = F.cpu().numpy()
+    assert colrelerr(F, Fo).max() <= 1e-6
+    op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
+    assert np.all(solve.relres(op, F, p.Y) <= tol * 1.01)
+
+
+def test_zero_column_x0_and_limits():
+    import torch
+    dev = device()
+    p = synth.multi_rhs(N=1500, E=1200, k=6, smax=60)
+    Yn = p.Y.copy()
+    Yn[:, 2] = 0.0
+    h = build(p, dev)
+    Y = torch.from_numpy(Yn).to(dev, torch.float32)
+    F, iters, rel, st = hgl().cg_solve(h, p.lam, Y, tol=1e-6, max_iter=300)
+    assert st == 0 and iters[0, 2] == 0 and float(F[:, 2].abs().max()) == 0.0
+    # warm start from the solution: converged at once
+    F2, iters2, rel2, st2 = hgl().cg_solve(h, p.lam, Y, tol=1e-6, max_iter=300, x0=F)
+    assert st2 == 0 and iters2.max() <= 1
+    # iteration limit -> NOT_CONVERGED, relres of the returned iterate reported
+    F3, iters3, rel3, st3 = hgl().cg_solve(h, p.lam, Y, tol=1e-9, max_iter=1)
+    assert st3 == 1
+    op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
+    ro = solve.relres(op, F3.cpu().double().numpy(), Yn)
+    assert np.allclose(rel3[0], ro, rtol=1e-4, atol=1e-12)
+
+
+def test_breakdown_on_nan_and_bad_lambda():
+    import torch
+    dev = device()
+    p = synth.small_plain(N=300, E=200, k=3)
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    Y[5, 1] = float("nan")
+    with pytest.raises(Exception) as ei:
+        hgl().cg_solve(h, p.lam, Y, tol=1e-6)
+    assert "BREAKDOWN" in str(ei.value)
+    with pytest.raises(Exception) as ei:
+        hgl().cg_solve(h, -1.0, Y, tol=1e-6)
+    assert "EINVAL" in str(ei.value)
+
+
+def test_bitwise_repeatable():
+    import torch
+    dev = device()
+    p = synth.multi_rhs(N=6000, E=5000, k=40, smax=200)
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    a = hgl().cg_solve(h, p.lam, Y, tol=3e-7)[0]
+    b = hgl().cg_solve(h, p.lam, Y, tol=3e-7)[0]
+    assert torch.equal(a, b)
+
+
+def test_batched_graphs_each_match_oracle_and_single_solve():
+    import torch
+    dev = device()
+    p = synth.batch_of_graphs(G=5, nlo=400, nhi=1500, k=12)
+    lams = np.array([0.5, 1.0, 0.25, 2.0, 0.7])
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    say("batched 5 graphs")
+    F, iters, rel, st = hgl().cg_solve_batched(h, lams, Y, tol=2e-7, max_iter=300)
+    assert st == 0
+    F = F.cpu().numpy()
+    for g in range(5):
+        v0, v1 = p.vtx_offsets[g], p.vtx_offsets[g + 1]
+        e0, e1 = p.edge_offsets[g], p.edge_offsets[g + 1]
+        ep = (p.edge_ptr[e0:e1 + 1] - p.edge_ptr[e0]).astype(np.int32)
+        ev = (p.edge_vtx[p.edge_ptr[e0]:p.edge_ptr[e1]] - v0).astype(np.int32)
+        sub = synth.Problem(v1 - v0, e1 - e0, ep, ev, p.w[e0:e1], lams[g], p.Y[v0:v1])
+        Fo = _dense_solution(sub)
+        assert colrelerr(F[v0:v1], Fo).max() <= 1e-6
+        hs = build(sub, dev)
+        Fs = hgl().cg_solve(hs, lams[g], torch.from_numpy(sub.Y).to(dev, torch.float32), tol=2e-7)[0]
+        assert colrelerr(F[v0:v1], Fs.cpu().numpy()).max() <= 1e-6
+
+
+@pytest.mark.slow
+def test_multi_rhs_full_size_against_sparse_oracle():
+    """Full multi-RHS workload (N=50,000, E=40,000, k=200, lambda=0.5) in the
+    bench's launch configuration; every column against the FP64 Tier-2 CG."""
+    import torch
+    dev = device()
+    p = synth.multi_rhs()
+    say("cg f32 full size")
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    tol = 1e-6 / (1 + 1 / p.lam)
+    F, iters, rel, st = hgl().cg_solve(h, p.lam, Y, tol=tol, max_iter=300)
+    assert st == 0
+    op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
+    cols = np.arange(0, 200, 7)
+    fo, _, relo = solve.cg_ranking(op, p.w, p.lam, p.Y[:, cols], tol=1e-13)
+    assert np.all(relo <= 1e-13)
+    assert colrelerr(F.cpu().numpy()[:, cols], fo).max() <= 1e-6
+    assert np.all(solve.relres(op, F.cpu().double().numpy(), p.Y) <= tol * 1.01)
