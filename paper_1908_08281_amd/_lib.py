@@ -55,6 +55,8 @@ SIGNATURES = {
     "hgl_apply": (C.c_int, [P, D, I32, P, I64, P, I64, I32, P]),
     "hgl_cg_solve": (C.c_int, [P, D, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),
     "hgl_cg_solve_batched": (C.c_int, [P, DP, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),
+    "hgl_profile": (C.c_int, [P, I32]),
+    "hgl_profile_read": (C.c_int, [P, I32, C.POINTER(C.c_int64), DP]),
 }
 
 _lib = None

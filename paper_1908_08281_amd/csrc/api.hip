@@ -56,17 +56,6 @@ static int dev_alloc(T** p, size_t count) {
   return HGL_OK;
 }
 
-int ensure_counters(hgl_handle* h, int slabs, hipStream_t s) {
-  if (h->n_long == 0 || slabs <= h->counter_slabs) return HGL_OK;
-  if (h->long_counter) hipFree(h->long_counter);
-  h->long_counter = nullptr;
-  h->counter_slabs = 0;
-  HGL_TRY(dev_alloc(&h->long_counter, size_t(h->n_long) * slabs));
-  HGL_HIP(hipMemsetAsync(h->long_counter, 0, sizeof(int32_t) * h->n_long * slabs, s));
-  h->counter_slabs = slabs;
-  return HGL_OK;
-}
-
 int ensure_pinned(hgl_handle* h, size_t n) {
   if (!h->pinned_i) HGL_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->pinned_i), 64 * sizeof(int32_t)));
   if (n > h->pinned_d_len) {
@@ -77,6 +66,52 @@ int ensure_pinned(hgl_handle* h, size_t n) {
     h->pinned_d_len = n;
   }
   return HGL_OK;
+}
+
+// ------------------------------------------------------------ kernel timing --
+
+static hipEvent_t prof_event(hgl_handle* h) {
+  if (!h->prof_pool.empty()) {
+    hipEvent_t e = h->prof_pool.back();
+    h->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_begin(hgl_handle* h, int kind, hipStream_t s) {
+  if (!h->prof_on) return;
+  hipEvent_t e = prof_event(h);
+  if (!e) return;
+  hipEventRecord(e, s);
+  h->prof_open = e;
+  h->prof_kind = kind;
+}
+
+void prof_end(hgl_handle* h, hipStream_t s) {
+  if (!h->prof_on || !h->prof_open) return;
+  hipEvent_t e = prof_event(h);
+  if (!e) return;
+  hipEventRecord(e, s);
+  h->prof_pending.push_back({h->prof_kind, {h->prof_open, e}});
+  h->prof_open = nullptr;
+}
+
+static void prof_collect(hgl_handle* h) {
+  if (h->prof_pending.empty()) return;
+  hipDeviceSynchronize();
+  for (auto& p : h->prof_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+      h->prof_ms[p.first] += ms;
+      h->prof_launches[p.first] += 1;
+    }
+    h->prof_pool.push_back(p.second.first);
+    h->prof_pool.push_back(p.second.second);
+  }
+  h->prof_pending.clear();
 }
 
 static bool aligned(const void* p, int bytes) {
@@ -257,7 +292,7 @@ static void free_handle(hgl_handle* h) {
   void* ptrs[] = {h->edge_ptr, h->edge_vtx, h->vtx_ptr, h->vtx_edge, h->w, h->dv, h->s64, h->c64,
                   h->s32, h->c32, h->tile_r0, h->tile_r1, h->tile_seg, h->long_row,
                   h->chunk_slot, h->chunk_begin, h->chunk_end, h->long_chunk0,
-                  h->long_counter, h->seg_slots, h->long_seg};
+                  h->seg_slots, h->long_seg};
   for (void* p : ptrs)
     if (p) hipFree(p);
   DevBuf* bufs[] = {&h->ws_z, &h->ws_z64, &h->ws_chunk, &h->ws_part, &h->ws_part2,
@@ -267,6 +302,12 @@ static void free_handle(hgl_handle* h) {
   h->ws_ab.release();
   if (h->pinned_i) hipHostFree(h->pinned_i);
   if (h->pinned_d) hipHostFree(h->pinned_d);
+  for (auto& p : h->prof_pending) {
+    hipEventDestroy(p.second.first);
+    hipEventDestroy(p.second.second);
+  }
+  for (hipEvent_t e : h->prof_pool) hipEventDestroy(e);
+  if (h->prof_open) hipEventDestroy(h->prof_open);
   delete h;
 }
 
@@ -472,7 +513,6 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
     B_HIP(hipMemcpyAsync(h->seg_slots, h->seg_slots_host.data(), 16 * size_t(G), hipMemcpyHostToDevice, s));
     B_HIP(hipStreamSynchronize(s));
   }
-  B_TRY(ensure_counters(h, kMaxSlabs, s));
   B_HIP(hipStreamSynchronize(s));
 #undef B_TRY
 #undef B_HIP
@@ -537,6 +577,28 @@ extern "C" int hgl_get_sizes(const hgl_handle* h, int32_t* N, int32_t* E, int64_
   if (E) *E = h->E;
   if (nnz) *nnz = h->nnz;
   if (G) *G = h->G;
+  return HGL_OK;
+}
+
+extern "C" int hgl_profile(hgl_handle* h, int32_t enable) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  prof_collect(h);
+  for (int i = 0; i < 8; ++i) {
+    h->prof_launches[i] = 0;
+    h->prof_ms[i] = 0.0;
+  }
+  h->prof_on = enable != 0;
+  return HGL_OK;
+}
+
+extern "C" int hgl_profile_read(hgl_handle* h, int32_t kind, int64_t* launches, double* ms) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  HGL_CHECK_ARG(kind >= 0 && kind < 8, "unknown kernel kind %d", kind);
+  prof_collect(h);
+  if (launches) *launches = h->prof_launches[kind];
+  if (ms) *ms = h->prof_ms[kind];
   return HGL_OK;
 }
 

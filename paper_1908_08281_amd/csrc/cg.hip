@@ -168,44 +168,56 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(
 
 // --------------------------------------------------------------- reductions --
 
-// Sum of part[col][slots of graph g] in a fixed order by one wave.
-__device__ __forceinline__ double wave_slot_sum(const double* __restrict__ part, int64_t n_slots,
-                                                const int32_t* __restrict__ seg_slots, int g, int col) {
-  const int lane = threadIdx.x % kWave;
+// Sum of part[col][slots of graph g] in a fixed order by one workgroup; the
+// result is returned to every thread.  Every thread must call it.
+__device__ __forceinline__ double block_slot_sum(const double* __restrict__ part, int64_t n_slots,
+                                                 const int32_t* __restrict__ seg_slots, int g, int col,
+                                                 double* lds /* [4] */) {
   const int t0 = seg_slots[4 * g], t1 = seg_slots[4 * g + 1];
   const int l0 = seg_slots[4 * g + 2], l1 = seg_slots[4 * g + 3];
   const double* p = part + int64_t(col) * n_slots;
   double s = 0.0;
-  for (int i = t0 + lane; i < t1; i += kWave) s += p[i];
-  for (int i = l0 + lane; i < l1; i += kWave) s += p[i];
+  for (int i = t0 + int(threadIdx.x); i < t1; i += kBlock) s += p[i];
+  for (int i = l0 + int(threadIdx.x); i < l1; i += kBlock) s += p[i];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
-  return s;
+  if (threadIdx.x % kWave == 0) lds[threadIdx.x / kWave] = s;
+  __syncthreads();
+  const double tot = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+  __syncthreads();
+  return tot;
 }
 
-enum class RedOp { Init, Alpha, Beta, Final };
+enum class RedOp { Init, Alpha, Beta, Check };
 
 struct RedArgs {
   int G, k, n_slots;
   const int32_t* seg_slots;
-  const double* part;   // rr (Init, Beta, Final) or p'Mp (Alpha)
-  const double* part2;  // yy (Init)
+  const double* part;   // r'r (Init, Beta, Check) or p'Mp (Alpha)
+  const double* part2;  // y'y (Init)
   double tol;
-  int iter;             // iteration index (parity of the flag words)
-  int periodic;         // residual replacement scheduled this iteration
+  int iter;             // iteration index
+  int periodic;         // Beta: the residual was recomputed in this iteration
 };
 
-// Flag words: cnt(it) = columns still active after iteration it (cnt(-1) after
-// the start), need(it) = some column claimed convergence before iteration it,
-// so its residual pass must run.  One word per iteration: never reset inside
-// the loop, so no launch can observe a word another launch is clearing.
+// Flag words: cnt(it) = columns still iterating after iteration it (cnt(-1)
+// after the start); chk(it) = columns still iterating after a check step run
+// between iterations it-1 and it.  One word per step, never reset inside the
+// loop, so no launch can observe a word another launch is clearing.
 struct Words {
   int32_t* base;
   int max_iter;
   __host__ __device__ int32_t* cnt(int it) const { return base + 1 + it; }
-  __host__ __device__ int32_t* need(int it) const { return base + (max_iter + 2) + 1 + it; }
-  __host__ __device__ int32_t* err() const { return base + 2 * (max_iter + 2) + 2; }
-  static size_t count(int max_iter) { return 2 * size_t(max_iter + 2) + 4; }
+  __host__ __device__ int32_t* chk(int it) const { return base + (max_iter + 2) + it; }
+  __host__ __device__ int32_t* err() const { return base + 2 * (max_iter + 2) + 1; }
+  // largest recursive relative residual of the iterating columns after it
+  // (FP64, updated with 64-bit atomics: the offset is kept 8-byte aligned;
+  // base itself is 8-byte aligned)
+  __host__ __device__ static int rmax_offset(int max_iter) { return (2 * (max_iter + 2) + 2 + 1) & ~1; }
+  __host__ __device__ double* rmax(int it) const {
+    return reinterpret_cast<double*>(base + rmax_offset(max_iter)) + it;
+  }
+  static size_t count(int max_iter) { return size_t(rmax_offset(max_iter)) + 2 * size_t(max_iter + 1); }
 };
 
 template <RedOp OP>
@@ -214,13 +226,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_reduce(RedArgs ra, CgState st, Wo
   if constexpr (OP == RedOp::Alpha || OP == RedOp::Beta) {
     if (*wd.cnt(it - 1) == 0) return;
   }
-  const int wid = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  if (wid >= ra.G * ra.k) return;
+  __shared__ double lds[4];
+  const int wid = blockIdx.x;  // one workgroup per (graph, column)
   const int g = wid / ra.k, col = wid % ra.k;
-  const double sum = wave_slot_sum(ra.part, ra.n_slots, ra.seg_slots, g, col);
+  const double sum = block_slot_sum(ra.part, ra.n_slots, ra.seg_slots, g, col, lds);
   double sum2 = 0.0;
-  if constexpr (OP == RedOp::Init) sum2 = wave_slot_sum(ra.part2, ra.n_slots, ra.seg_slots, g, col);
-  if (threadIdx.x % kWave != 0) return;
+  if constexpr (OP == RedOp::Init) sum2 = block_slot_sum(ra.part2, ra.n_slots, ra.seg_slots, g, col, lds);
+  if (threadIdx.x != 0) return;
   const int64_t id = wid;
   if constexpr (OP == RedOp::Init) {
     st.yy[id] = sum2;
@@ -234,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_reduce(RedArgs ra, CgState st, Wo
     st.state[id] = done ? kDone : kActive;
     if (!done) atomicAdd(wd.cnt(-1), 1);
   } else if constexpr (OP == RedOp::Alpha) {
-    if (st.state[id] != kActive) {
+    if (st.state[id] != kActive || st.rr[id] == 0.0) {
       st.alpha[id] = 0.0;
       return;
     }
@@ -251,17 +263,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_reduce(RedArgs ra, CgState st, Wo
       return;
     }
     st.iters[id] += 1;
-    const bool ran = ra.periodic || *wd.need(it) != 0;
+    const bool ran = ra.periodic != 0;  // sum is the recomputed true residual
     const double yy = st.yy[id];
     const double rel = sqrt(sum / yy);
     if (ran) st.relres[id] = rel;
-    if (ran && rel <= ra.tol) {
+    if (ran && rel <= ra.tol) {  // a recomputed residual finishes the column
       st.state[id] = kDone;
       st.beta[id] = 0.0;
       st.rr[id] = sum;
       return;
     }
-    if (!ran && rel <= ra.tol) *wd.need(it + 1) = 1;
     if (!isfinite(sum)) {
       st.state[id] = kBreakdown;
       atomicOr(wd.err(), 1);
@@ -271,8 +282,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_reduce(RedArgs ra, CgState st, Wo
     st.beta[id] = sum / st.rr[id];
     st.rr[id] = sum;
     atomicAdd(wd.cnt(it), 1);
-  } else {  // Final: true residual of the returned F for unfinished columns
-    if (st.state[id] == kActive) st.relres[id] = st.yy[id] > 0.0 ? sqrt(sum / st.yy[id]) : sqrt(sum);
+    atomicMax(reinterpret_cast<unsigned long long*>(wd.rmax(it)),
+              static_cast<unsigned long long>(__double_as_longlong(rel)));
+  } else {  // Check: sum is r'r of the residual Y - M F recomputed in FP64
+    if (st.state[id] != kActive) return;
+    const double rel = st.yy[id] > 0.0 ? sqrt(sum / st.yy[id]) : sqrt(sum);
+    st.relres[id] = rel;
+    // residual replacement: the recursion continues from the recomputed
+    // residual with the same search direction
+    st.rr[id] = sum;
+    if (rel <= ra.tol) st.state[id] = kDone;
+    else atomicAdd(wd.chk(it), 1);
   }
 }
 
@@ -329,29 +349,32 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   b.st.state = reinterpret_cast<int32_t*>(sd + 5 * gk);
   b.st.iters = b.st.state + gk;
   Words wd{b.st.iters + gk, o->max_iter};
+  if (reinterpret_cast<uintptr_t>(wd.rmax(0)) % alignof(double) != 0) {
+    set_error("internal: misaligned FP64 flag words");
+    return HGL_EDEVICE;
+  }
   HGL_HIP(hipMemsetAsync(wd.base, 0, Words::count(o->max_iter) * sizeof(int32_t), s));
 
   const ColShape cs = pick_shape(k, sizeof(T), {Y, F, b.R}, {ldy, ldf, ld});
   const ColShape cs64 = pick_shape(k, 8, {Y, F, b.R}, {ldy, ldf, ld});
-  const int red_blocks = int((gk + 3) / 4);
+  const int red_blocks = int(gk);
   RedArgs ra{G, k, nsl, h->seg_slots, b.part, b.part2, o->tol, 0, 0};
 
   // residual pass R = Y - M F (FP64 accumulation), partial r'r into b.part
   auto resid = [&](Gate gate) -> int {
-    if constexpr (sizeof(T) == 4) {
-      HGL_TRY(launch_spmm_edge<float, double>(h, F, ldf, b.Z64, ld, k, cs64, gate, s));
-      HGL_TRY(launch_spmm_vertex<float, double>(h, VMode::Resid, F, ldf, b.Z64, ld, Y, ldy, b.R, ld,
-                                                a_seg, b_seg, b.part, k, cs64, gate, s));
-    } else {
-      HGL_TRY(launch_spmm_edge<double, double>(h, F, ldf, b.Z64, ld, k, cs64, gate, s));
-      HGL_TRY(launch_spmm_vertex<double, double>(h, VMode::Resid, F, ldf, b.Z64, ld, Y, ldy, b.R, ld,
-                                                 a_seg, b_seg, b.part, k, cs64, gate, s));
-    }
+    prof_begin(h, kProfResidEdge, s);
+    HGL_TRY(launch_spmm_edge<T, double>(h, F, ldf, b.Z64, ld, k, cs64, gate, s));
+    prof_end(h, s);
+    prof_begin(h, kProfResidVertex, s);
+    HGL_TRY(launch_spmm_vertex<T, double>(h, VMode::Resid, F, ldf, b.Z64, ld, Y, ldy, b.R, ld, a_seg,
+                                          b_seg, b.part, k, cs64, gate, s));
+    prof_end(h, s);
     return HGL_OK;
   };
 
   // ------------------------------------------------------------- start
   if (o->x0_given) HGL_TRY(resid(Gate{}));
+  prof_begin(h, kProfStart, s);
   int rc = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
     dim3 grid(h->n_tiles, cs.slabs);
     hipLaunchKernelGGL((k_cg_init<T, GL, V>), grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
@@ -364,17 +387,25 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   ra.iter = -1;
   hipLaunchKernelGGL((k_cg_reduce<RedOp::Init>), dim3(red_blocks), dim3(kBlock), 0, s, ra, b.st, wd);
   HGL_HIP(hipGetLastError());
+  prof_end(h, s);
 
   // ---------------------------------------------------------- iterations
   auto iteration = [&](int it) -> int {
     Gate g_prev{wd.cnt(it - 1), nullptr, 1};
+    prof_begin(h, kProfEdge, s);
     HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, cs, g_prev, s));
+    prof_end(h, s);
+    prof_begin(h, kProfVertex, s);
     HGL_TRY(launch_spmm_vertex<T, T>(h, VMode::ApplyDot, b.P, ld, b.Z, ld, nullptr, 0, b.Q, ld, a_seg,
                                      b_seg, b.part, k, cs, g_prev, s));
+    prof_end(h, s);
     RedArgs r = ra;
     r.iter = it;
+    prof_begin(h, kProfReduce, s);
     hipLaunchKernelGGL((k_cg_reduce<RedOp::Alpha>), dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
     HGL_HIP(hipGetLastError());
+    prof_end(h, s);
+    prof_begin(h, kProfUpdate, s);
     int rc2 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
       dim3 grid(h->n_tiles, cs.slabs);
       hipLaunchKernelGGL((k_cg_update<T, GL, V>), grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
@@ -384,12 +415,16 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       return HGL_OK;
     });
     HGL_TRY(rc2);
-    const int periodic = (fp32 && o->rr_period > 0 && (it + 1) % o->rr_period == 0) ? 1 : 0;
-    HGL_TRY(resid(Gate{wd.cnt(it - 1), wd.need(it), periodic}));
+    prof_end(h, s);
+    const int periodic = (o->rr_period > 0 && (it + 1) % o->rr_period == 0) ? 1 : 0;
+    if (periodic) HGL_TRY(resid(g_prev));
     r.periodic = periodic;
+    prof_begin(h, kProfReduce, s);
     hipLaunchKernelGGL((k_cg_reduce<RedOp::Beta>), dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
     HGL_HIP(hipGetLastError());
+    prof_end(h, s);
     Gate g_now{wd.cnt(it), nullptr, 1};
+    prof_begin(h, kProfDirection, s);
     int rc3 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
       dim3 grid(h->n_tiles, cs.slabs);
       hipLaunchKernelGGL((k_cg_direction<T, GL, V>), grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
@@ -397,29 +432,72 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       HGL_HIP(hipGetLastError());
       return HGL_OK;
     });
+    prof_end(h, s);
     return rc3;
   };
 
-  int chunk = o->chunk > 0 ? o->chunk : 4;
+  // Check step between iterations it-1 and it: recompute R = Y - M F with
+  // FP64 accumulation (residual replacement); columns whose recomputed
+  // residual meets tol are done, the others go on from the same direction.
+  auto check = [&](int it_next) -> int {
+    HGL_TRY(resid(Gate{}));
+    RedArgs r = ra;
+    r.iter = it_next;
+    prof_begin(h, kProfReduce, s);
+    hipLaunchKernelGGL((k_cg_reduce<RedOp::Check>), dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
+    HGL_HIP(hipGetLastError());
+    prof_end(h, s);
+    return HGL_OK;
+  };
+
+  // Iterations are enqueued in chunks; between chunks the host reads the
+  // number of iterating columns and their largest recursive relative
+  // residual.  Once that is below claim*tol, a check step decides on the
+  // recomputed residual.  claim < 1 in FP32 leaves room for the drift of the
+  // FP32 recursion from the true residual.  With chunk = 0 the next chunk is
+  // sized from the observed contraction rate to end where the last column
+  // should reach the claim level.
+  const double claim = fp32 ? 0.5 : 1.0;
   int it = 0;
   bool all_done = false;
-  // host check of the start state
   HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.cnt(-1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HGL_HIP(hipStreamSynchronize(s));
   all_done = h->pinned_i[0] == 0;
+  double r_ref = 1.0;
+  int it_ref = 0;
+  int next = o->chunk > 0 ? o->chunk : 3;
   while (!all_done && it < o->max_iter) {
-    const int n = std::min(chunk, o->max_iter - it);
+    const int n = std::min(next, o->max_iter - it);
     for (int c = 0; c < n; ++c, ++it) HGL_TRY(iteration(it));
     HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.cnt(it - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HGL_HIP(hipMemcpyAsync(h->pinned_d, wd.rmax(it - 1), sizeof(double), hipMemcpyDeviceToHost, s));
     HGL_HIP(hipStreamSynchronize(s));
-    all_done = h->pinned_i[0] == 0;
+    if (h->pinned_i[0] == 0) {
+      all_done = true;  // every column finished on a periodic recomputation
+      break;
+    }
+    const double r_now = h->pinned_d[0];
+    if (r_now <= claim * o->tol) {
+      HGL_TRY(check(it));
+      HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.chk(it), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HGL_HIP(hipStreamSynchronize(s));
+      all_done = h->pinned_i[0] == 0;
+      next = o->chunk > 0 ? o->chunk : 1;
+      continue;
+    }
+    if (o->chunk > 0) continue;
+    const double rate = (r_now > 0.0 && r_ref > 0.0 && it > it_ref)
+                            ? std::pow(r_now / r_ref, 1.0 / double(it - it_ref)) : 1.0;
+    if (!(rate < 0.999)) {
+      next = 4;
+    } else {
+      const double m = std::ceil(std::log(claim * o->tol / r_now) / std::log(rate));
+      next = int(std::min(64.0, std::max(1.0, m)));
+    }
+    r_ref = r_now;
+    it_ref = it;
   }
-  if (!all_done) {
-    // true residual of the returned F for the unfinished columns
-    HGL_TRY(resid(Gate{}));
-    hipLaunchKernelGGL((k_cg_reduce<RedOp::Final>), dim3(red_blocks), dim3(kBlock), 0, s, ra, b.st, wd);
-    HGL_HIP(hipGetLastError());
-  }
+  if (!all_done) HGL_TRY(check(it));  // record the true residual of every unfinished column
   // ---------------------------------------------------------- results
   double* pd = h->pinned_d;
   HGL_HIP(hipMemcpyAsync(pd, b.st.relres, sizeof(double) * gk, hipMemcpyDeviceToHost, s));

@@ -53,7 +53,7 @@ constexpr int kWave = 64;
 constexpr int kTileRows = 64;      // rows per tile of the row-streaming kernels
 constexpr int kLongRow = 64;       // vertex rows with more hyperedges are split
 constexpr int kChunk = 256;        // hyperedges per chunk of a split vertex row
-constexpr int kMaxSlabs = 64;      // column slabs (of GL*V columns) per launch
+constexpr int kStageIdx = 2048;    // hyperedge ids of a tile staged in LDS
 
 // ------------------------------------------------------ device buffers --
 
@@ -107,8 +107,6 @@ struct hgl_handle {
   int32_t* chunk_begin = nullptr;    // [n_chunks] position in vtx_edge
   int32_t* chunk_end = nullptr;      // [n_chunks]
   int32_t* long_chunk0 = nullptr;    // [n_long+1] first chunk of each long row
-  int32_t* long_counter = nullptr;   // [n_long * max_slabs] arrival counters (kept zero)
-  int32_t counter_slabs = 0;
 
   // per segment: partial-slot ranges {t0, t1, l0, l1} (device, [G*4])
   int32_t* seg_slots = nullptr;
@@ -138,7 +136,6 @@ namespace hgl {
 // Partial-slot count of the reductions: one per tile, one per long row.
 inline int n_slots(const hgl_handle* h) { return h->n_tiles + h->n_long; }
 
-int ensure_counters(hgl_handle* h, int slabs, hipStream_t s);
 int ensure_pinned(hgl_handle* h, size_t n_doubles);
 
 // Launch shape of the column dimension: GL lanes per row, V elements per lane.

@@ -25,6 +25,30 @@ __device__ __forceinline__ void store_row(T* __restrict__ p, const T (&x)[V]) {
   *reinterpret_cast<VecT<T, V>*>(p) = t;
 }
 
+// acc += sum_{j in [jb, je)} Z[idx[j], col .. col+V-1], four rows in flight.
+template <int V, class TZ>
+__device__ __forceinline__ void gather_rows(const TZ* __restrict__ Z, int64_t ldz,
+                                            const int32_t* __restrict__ idx, int jb, int je, int col,
+                                            TZ (&acc)[V]) {
+  int j = jb;
+  for (; j + 4 <= je; j += 4) {
+    const int e0 = idx[j], e1 = idx[j + 1], e2 = idx[j + 2], e3 = idx[j + 3];
+    TZ z0[V], z1[V], z2[V], z3[V];
+    load_row<V>(Z + int64_t(e0) * ldz + col, z0);
+    load_row<V>(Z + int64_t(e1) * ldz + col, z1);
+    load_row<V>(Z + int64_t(e2) * ldz + col, z2);
+    load_row<V>(Z + int64_t(e3) * ldz + col, z3);
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] += ((z0[i] + z1[i]) + z2[i]) + z3[i];
+  }
+  for (; j < je; ++j) {
+    TZ z0[V];
+    load_row<V>(Z + int64_t(idx[j]) * ldz + col, z0);
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc[i] += z0[i];
+  }
+}
+
 // Sum, over the groups of a 256-thread block, of per-lane values x[V] whose
 // column is (lane within its GL-wide group, i).  The result for column
 // tid = lane*V + i (tid < GL*V) is returned in thread tid.  Fixed order, so

@@ -100,8 +100,6 @@ struct VertexArgs {
   const int32_t* long_row;
   const int32_t* long_seg;
   const int32_t* long_chunk0;
-  int32_t* long_counter;
-  int32_t counter_slabs;
   int32_t n_slots;
   const double* a_seg;
   const double* b_seg;
@@ -119,7 +117,6 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
   constexpr int W = GL * V;
   __shared__ double lds_d[4 * W];
   __shared__ TZ lds_z[4 * W];
-  __shared__ int s_last;
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
   const int col = blockIdx.y * W + lane * V;
   const bool colok = col < k;
@@ -130,35 +127,33 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
     const int r0 = va.tile_r0[t], r1 = va.tile_r1[t];
     const int g = va.tile_seg[t];
     const TZ a = TZ(va.a_seg[g]), bb = TZ(va.b_seg[g]);
+    // stage the tile's row offsets and (up to kStageIdx) hyperedge ids in LDS:
+    // one coalesced round trip instead of two dependent ones per row
+    __shared__ int32_t s_ptr[kTileRows + 1];
+    __shared__ int32_t s_idx[kStageIdx];
+    const int nr = r1 - r0;
+    for (int i = threadIdx.x; i <= nr; i += kBlock) s_ptr[i] = va.vtx_ptr[r0 + i];
+    __syncthreads();
+    const int base = s_ptr[0];
+    const int staged = min(s_ptr[nr] - base, kStageIdx);
+    for (int i = threadIdx.x; i < staged; i += kBlock) s_idx[i] = va.vtx_edge[base + i];
+    __syncthreads();
     double dot[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) dot[i] = 0.0;
     for (int r = r0 + grp; r < r1 && colok; r += GPB) {
-      const int eb = va.vtx_ptr[r], ee = va.vtx_ptr[r + 1];
+      const int eb = s_ptr[r - r0], ee = s_ptr[r - r0 + 1];
       if (ee - eb > kLongRow) continue;  // finished by its chunks
+      T x[V], o[V];
+      load_row<V>(X + int64_t(r) * ldx + col, x);  // independent of the gather: issue first
+      const TZ sr = s[r];
       TZ acc[V];
 #pragma unroll
       for (int i = 0; i < V; ++i) acc[i] = TZ(0);
-      int j = eb;
-      for (; j + 4 <= ee; j += 4) {
-        int e0 = va.vtx_edge[j], e1 = va.vtx_edge[j + 1], e2 = va.vtx_edge[j + 2], e3 = va.vtx_edge[j + 3];
-        TZ z0[V], z1[V], z2[V], z3[V];
-        load_row<V>(Z + int64_t(e0) * ldz + col, z0);
-        load_row<V>(Z + int64_t(e1) * ldz + col, z1);
-        load_row<V>(Z + int64_t(e2) * ldz + col, z2);
-        load_row<V>(Z + int64_t(e3) * ldz + col, z3);
-#pragma unroll
-        for (int i = 0; i < V; ++i) acc[i] = ((acc[i] + z0[i]) + z1[i]) + z2[i] + z3[i];
-      }
-      for (; j < ee; ++j) {
-        TZ z0[V];
-        load_row<V>(Z + int64_t(va.vtx_edge[j]) * ldz + col, z0);
-#pragma unroll
-        for (int i = 0; i < V; ++i) acc[i] += z0[i];
-      }
-      T x[V], o[V];
-      load_row<V>(X + int64_t(r) * ldx + col, x);
-      const TZ sr = s[r];
+      if (ee - base <= staged)
+        gather_rows<V>(Z, ldz, s_idx, eb - base, ee - base, col, acc);
+      else
+        gather_rows<V>(Z, ldz, va.vtx_edge, eb, ee, col, acc);
       if constexpr (MODE == 2) {
         T y[V];
         load_row<V>(Y + int64_t(r) * ldy + col, y);
@@ -194,38 +189,64 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
 #pragma unroll
   for (int i = 0; i < V; ++i) acc[i] = TZ(0);
   if (colok) {
-    for (int j = eb + grp; j < ee; j += GPB) {
-      TZ z0[V];
-      load_row<V>(Z + int64_t(va.vtx_edge[j]) * ldz + col, z0);
-#pragma unroll
-      for (int i = 0; i < V; ++i) acc[i] += z0[i];
-    }
+    // each group sums a contiguous share of the chunk's hyperedges
+    const int per = (ee - eb + GPB - 1) / GPB;
+    const int jb = eb + grp * per;
+    const int je = min(jb + per, ee);
+    gather_rows<V>(Z, ldz, va.vtx_edge, jb, je, col, acc);
   }
   TZ csum = block_colsum<GL, V>(acc, lds_z);
-  {
-    const int c = blockIdx.y * W + threadIdx.x;
-    if (threadIdx.x < W && c < k) chunk_part[int64_t(ch) * k + c] = csum;
+  const int c = blockIdx.y * W + threadIdx.x;
+  if (threadIdx.x < W && c < k) chunk_part[int64_t(ch) * k + c] = csum;
+}
+
+// Finish the long rows (one workgroup per row and column slab): sum the
+// row's chunk partials, groups taking chunks round-robin, then a fixed-order
+// block reduction (deterministic), and apply the epilogue of MODE.  Runs as
+// its own launch after k_spmm_vertex, so the partials are visible without
+// cross-workgroup fences.
+template <class T, class TZ, int GL, int V, int MODE>
+__global__ __launch_bounds__(kBlock) void k_spmm_vertex_finish(
+    VertexArgs va, const TZ* __restrict__ s, const T* __restrict__ X, int64_t ldx,
+    const T* __restrict__ Y, int64_t ldy, T* __restrict__ Out, int64_t ldo, double* __restrict__ part,
+    const TZ* __restrict__ chunk_part, int k, Gate gate) {
+  if (gate.skip()) return;
+  constexpr int GPB = kBlock / GL;
+  constexpr int W = GL * V;
+  __shared__ TZ lds_z[4 * W];
+  const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
+  const int col = blockIdx.y * W + lane * V;
+  const bool colok = col < k;
+  const int slot = blockIdx.x;
+  const int c0 = va.long_chunk0[slot];
+  const int nch = va.long_chunk0[slot + 1] - c0;
+  TZ acc[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] = TZ(0);
+  if (colok) {
+    int q = grp;
+    for (; q + 3 * GPB < nch; q += 4 * GPB) {
+      TZ p0[V], p1[V], p2[V], p3[V];
+      load_row<V>(chunk_part + int64_t(c0 + q) * k + col, p0);
+      load_row<V>(chunk_part + int64_t(c0 + q + GPB) * k + col, p1);
+      load_row<V>(chunk_part + int64_t(c0 + q + 2 * GPB) * k + col, p2);
+      load_row<V>(chunk_part + int64_t(c0 + q + 3 * GPB) * k + col, p3);
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] += ((p0[i] + p1[i]) + p2[i]) + p3[i];
+    }
+    for (; q < nch; q += GPB) {
+      TZ p0[V];
+      load_row<V>(chunk_part + int64_t(c0 + q) * k + col, p0);
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] += p0[i];
+    }
   }
-  __threadfence();
-  __syncthreads();
-  const int nch = va.long_chunk0[slot + 1] - va.long_chunk0[slot];
-  int32_t* counter = va.long_counter + int64_t(slot) * va.counter_slabs + blockIdx.y;
-  if (threadIdx.x == 0) {
-    int prev = atomicAdd(counter, 1);
-    s_last = (prev == nch - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  if (threadIdx.x == 0) *counter = 0;  // ready for the next launch
+  const TZ sum = block_colsum<GL, V>(acc, lds_z);
   const int c = blockIdx.y * W + threadIdx.x;
   if (threadIdx.x >= W || c >= k) return;
   const int r = va.long_row[slot];
   const int g = va.long_seg[slot];
   const TZ a = TZ(va.a_seg[g]), bb = TZ(va.b_seg[g]);
-  const int c0 = va.long_chunk0[slot];
-  TZ sum = TZ(0);
-  for (int q = 0; q < nch; ++q) sum += chunk_part[int64_t(c0 + q) * k + c];
   const TZ sr = s[r];
   const TZ x = TZ(X[int64_t(r) * ldx + c]);
   double d = 0.0;
@@ -252,32 +273,38 @@ int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx,
     HGL_HIP(hipStreamSynchronize(st));
     HGL_TRY(hm->ws_chunk.reserve(sizeof(TZ) * size_t(h->n_chunks) * k));
   }
-  VertexArgs va{h->n_tiles,     h->tile_r0,    h->tile_r1,    h->tile_seg,   h->vtx_ptr,
-                h->vtx_edge,    h->chunk_slot, h->chunk_begin, h->chunk_end, h->long_row,
-                h->long_seg,    h->long_chunk0, h->long_counter, h->counter_slabs,
-                n_slots(h),     a_seg,         b_seg};
+  VertexArgs va{h->n_tiles,  h->tile_r0,     h->tile_r1,   h->tile_seg, h->vtx_ptr,
+                h->vtx_edge, h->chunk_slot,  h->chunk_begin, h->chunk_end, h->long_row,
+                h->long_seg, h->long_chunk0, n_slots(h),  a_seg,       b_seg};
   const TZ* s;
   if constexpr (sizeof(TZ) == 8) s = h->s64; else s = h->s32;
   TZ* cp = hm->ws_chunk.as<TZ>();
   dim3 grid(h->n_tiles + h->n_chunks, cs.slabs);
-  if (cs.slabs > h->counter_slabs && h->n_long > 0) {
-    set_error("k too large for this build (%d column slabs)", cs.slabs);
-    return HGL_EUNSUPPORTED;
-  }
+  dim3 grid_fin(h->n_long, cs.slabs);
   if (mode == VMode::Resid && sizeof(TZ) != 8) {
     set_error("residual mode needs FP64 accumulation");
     return HGL_EUNSUPPORTED;
   }
   return HGL_DISPATCH_SHAPE(cs, sizeof(T) > sizeof(TZ) ? sizeof(T) : sizeof(TZ), {
-    if (mode == VMode::Apply)
+    if (mode == VMode::Apply) {
       hipLaunchKernelGGL((k_spmm_vertex<T, TZ, GL, V, 0>), grid, dim3(kBlock), 0, st, va, s, X, ldx,
                          Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
-    else if (mode == VMode::ApplyDot)
+      if (h->n_long > 0)
+        hipLaunchKernelGGL((k_spmm_vertex_finish<T, TZ, GL, V, 0>), grid_fin, dim3(kBlock), 0, st, va,
+                           s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
+    } else if (mode == VMode::ApplyDot) {
       hipLaunchKernelGGL((k_spmm_vertex<T, TZ, GL, V, 1>), grid, dim3(kBlock), 0, st, va, s, X, ldx,
                          Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
-    else if constexpr (sizeof(TZ) == 8)
+      if (h->n_long > 0)
+        hipLaunchKernelGGL((k_spmm_vertex_finish<T, TZ, GL, V, 1>), grid_fin, dim3(kBlock), 0, st, va,
+                           s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
+    } else if constexpr (sizeof(TZ) == 8) {
       hipLaunchKernelGGL((k_spmm_vertex<T, TZ, GL, V, 2>), grid, dim3(kBlock), 0, st, va, s, X, ldx,
                          Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
+      if (h->n_long > 0)
+        hipLaunchKernelGGL((k_spmm_vertex_finish<T, TZ, GL, V, 2>), grid_fin, dim3(kBlock), 0, st, va,
+                           s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
+    }
     HGL_HIP(hipGetLastError());
     return HGL_OK;
   });

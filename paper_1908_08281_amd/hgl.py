@@ -188,3 +188,23 @@ def cg_solve_batched(h: Handle, lams, Y: torch.Tensor, mode: str = "f32", tol: f
                      chunk: int = 0):
     """One lambda per graph of a batched handle."""
     return _cg(h, lams, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=True)
+
+
+PROFILE_KINDS = {0: "edge_gather", 1: "vertex_gather", 2: "cg_update", 3: "cg_direction",
+                 4: "reduce", 5: "resid_edge_gather", 6: "resid_vertex_gather", 7: "start"}
+
+
+def profile(h: Handle, enable: bool) -> None:
+    """Reset the kernel-timing counters of h and switch event timing on/off."""
+    check(lib().hgl_profile(h.ptr, 1 if enable else 0), "hgl_profile")
+
+
+def profile_read(h: Handle) -> dict:
+    """{kind name: (launches, total ms)} recorded since the last profile(h, ...)."""
+    out = {}
+    for kind, name in PROFILE_KINDS.items():
+        n = C.c_int64()
+        ms = C.c_double()
+        check(lib().hgl_profile_read(h.ptr, kind, C.byref(n), C.byref(ms)), "hgl_profile_read")
+        out[name] = (n.value, ms.value)
+    return out

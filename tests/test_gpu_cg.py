@@ -74,6 +74,22 @@ def test_zero_column_x0_and_limits():
     assert np.allclose(rel3[0], ro, rtol=1e-4, atol=1e-12)
 
 
+@pytest.mark.parametrize("max_iter", [1, 2, 3, 4, 5])
+def test_iteration_limits_of_every_parity(max_iter):
+    """Regression: the FP64 flag words must stay 8-byte aligned for any max_iter."""
+    import torch
+    dev = device()
+    p = synth.multi_rhs(N=1200, E=1000, k=5, smax=50)
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    say("max_iter", max_iter)
+    F, iters, rel, st = hgl().cg_solve(h, p.lam, Y, tol=1e-12, max_iter=max_iter)
+    assert st == 1 and iters.max() <= max_iter
+    op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
+    ro = solve.relres(op, F.cpu().double().numpy(), p.Y)
+    assert np.allclose(rel[0], ro, rtol=1e-4, atol=1e-12)
+
+
 def test_breakdown_on_nan_and_bad_lambda():
     import torch
     dev = device()
