@@ -161,6 +161,78 @@ int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg
                          const void* Y, int64_t ldy, void* F, int64_t ldf, int32_t k,
                          int32_t* iters_host, double* relres_host, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Block randomized SVD (paper, section 3: Algorithm 1, the tessellation of
+ * eq. 11 and the block inverse of eq. 15).
+ *
+ * The vertices are tessellated into n_blocks contiguous ranges given by
+ * block_offsets_host[n_blocks+1] (0 = o_0 < o_1 < ... < o_n = N).  For each
+ * diagonal block A_bb of the normalised adjacency A (eq. 1) the library runs
+ * Algorithm 1: Y = A_bb Omega, S = orth(Y), then q times
+ * { S~ = orth(A_bb' S), S = orth(A_bb S~) }, B = S' A_bb, B = U~ Sigma V',
+ * U = S U~, keeping the k leading singular triplets.  orth() is CholQR2
+ * (Gram matrices and their Cholesky factors in FP64).  The diagonal blocks of
+ * X = I - A/(1+theta) are full rank, so the low-rank object decomposed is
+ * A_bb; eq. (15) is applied as the identity-plus-low-rank inverse
+ *   (I + L_bb/lambda)^-1 ~ lambda/(1+lambda) [I + U diag(s/(1+lambda-s)) U'].
+ * ------------------------------------------------------------------------ */
+
+enum hgl_sketch {
+  HGL_SKETCH_BF16 = 0,  /* A_bb, Omega and S in BF16; MFMA products accumulate in FP32 */
+  HGL_SKETCH_F64 = 1    /* every product in FP64 (reference precision) */
+};
+
+typedef struct hgl_rsvd_opts {
+  int32_t k;          /* rank kept per block (>= 1) */
+  int32_t p;          /* oversampling: sketch width l = k + p (l <= 96) */
+  int32_t q;          /* subspace iterations (>= 0) */
+  int32_t sketch;     /* enum hgl_sketch */
+  uint64_t seed;      /* Philox4x32-10 key when omega is NULL */
+  double refine_tol;  /* hgl_block_rsvd_invert: target relres of the refinement */
+  int32_t max_refine; /* hgl_block_rsvd_invert: preconditioned CG iteration limit */
+  int32_t chunk;      /* as hgl_cg_opts.chunk */
+} hgl_rsvd_opts;
+
+/*
+ * Algorithm 1 on every diagonal block.  omega_bf16 (nullable, device):
+ * N x l row-major BF16 bit patterns, row v is the sketch row of vertex v
+ * (rows of block b are its rows o_b .. o_{b+1}-1); NULL draws standard
+ * normals from Philox4x32-10 keyed by opts->seed (see hgl_sketch_gaussian).
+ * U_out (device, N x k FP32 row-major): rows of block b hold U_b.
+ * sigma_out (nullable, device, n_blocks x k FP64): singular values of B per
+ * block, decreasing.  Every block needs at least l rows.  Errors: HGL_EINVAL
+ * (bad offsets, l > 96, a block smaller than l, batched handle),
+ * HGL_ECHOLQR (a Gram matrix not positive definite even after the shift).
+ * Synchronises the stream.
+ */
+int hgl_block_rsvd(hgl_handle* h, int32_t n_blocks, const int32_t* block_offsets_host,
+                   const hgl_rsvd_opts* opts, const uint16_t* omega_bf16, float* U_out,
+                   double* sigma_out, hipStream_t stream);
+
+/*
+ * Solve (I + L/lambda) F = Y (Y, F: N x nrhs FP32) with the block inverse
+ * built from hgl_block_rsvd: F0 = blockdiag(M_bb^-1) Y, refined by
+ * preconditioned CG (FP32 vectors, FP64 inner products, residual
+ * replacement) until the FP64-recomputed relres of every column is at most
+ * opts->refine_tol.  iters_host [nrhs], relres_host [nrhs], sigma_out
+ * [n_blocks*k] (device) are nullable.  Returns as hgl_cg_solve.
+ */
+int hgl_block_rsvd_invert(hgl_handle* h, double lambda, int32_t n_blocks,
+                          const int32_t* block_offsets_host, const hgl_rsvd_opts* opts,
+                          const uint16_t* omega_bf16, const float* Y, int64_t ldy, float* F,
+                          int64_t ldf, int32_t nrhs, double* sigma_out, int32_t* iters_host,
+                          double* relres_host, hipStream_t stream);
+
+/*
+ * rows x l standard normals, row-major, rounded to BF16 (bit patterns):
+ * element i (= row*l + col) is normal number i of the stream where counter
+ * c = i/2 of Philox4x32-10 (Salmon et al., SC'11; key = seed, counter =
+ * (c low 32 bits, c high 32 bits, 0, 0)) gives the words (x0, x1, x2, x3)
+ * and the Box-Muller pair from u1 = (x0 + 1)/2^32, u2 = x1/2^32 is
+ * (sqrt(-2 ln u1) cos(2 pi u2), sqrt(-2 ln u1) sin(2 pi u2)).
+ */
+int hgl_sketch_gaussian(int64_t rows, int32_t l, uint64_t seed, uint16_t* out_bf16, hipStream_t stream);
+
 /*
  * Kernel timing (diagnostics).  hgl_profile(h, 1) resets the counters and
  * makes every later solver call on h bracket each kernel launch with HIP
@@ -170,7 +242,8 @@ int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg
  * device).  Kinds: 0 edge gather (Z = C H' S P), 1 vertex gather with inner
  * product (M P), 2 CG update (F, R), 3 CG direction (P), 4 reductions,
  * 5 residual edge gather (FP64), 6 residual vertex gather (FP64),
- * 7 start-up.  Unknown kind -> HGL_EINVAL.
+ * 7 start-up, 8 preconditioner, 9 rSVD products, 10 CholQR, 11 Jacobi,
+ * 12 block extraction, 13 weight gradient.  Kinds 0..15; others -> HGL_EINVAL.
  */
 int hgl_profile(hgl_handle* h, int32_t enable);
 int hgl_profile_read(hgl_handle* h, int32_t kind, int64_t* launches, double* ms);

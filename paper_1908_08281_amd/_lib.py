@@ -31,8 +31,13 @@ class CgOpts(C.Structure):
 
 
 class RsvdOpts(C.Structure):
-    _fields_ = [("k", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("seed", C.c_uint64),
-                ("refine_tol", C.c_double), ("max_refine", C.c_int32), ("chunk", C.c_int32)]
+    _fields_ = [("k", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("sketch", C.c_int32),
+                ("seed", C.c_uint64), ("refine_tol", C.c_double), ("max_refine", C.c_int32),
+                ("chunk", C.c_int32)]
+
+
+HGL_SKETCH_BF16 = 0
+HGL_SKETCH_F64 = 1
 
 
 P = C.c_void_p
@@ -55,6 +60,10 @@ SIGNATURES = {
     "hgl_apply": (C.c_int, [P, D, I32, P, I64, P, I64, I32, P]),
     "hgl_cg_solve": (C.c_int, [P, D, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),
     "hgl_cg_solve_batched": (C.c_int, [P, DP, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),
+    "hgl_block_rsvd": (C.c_int, [P, I32, I32P, C.POINTER(RsvdOpts), P, P, P, P]),
+    "hgl_block_rsvd_invert": (C.c_int, [P, D, I32, I32P, C.POINTER(RsvdOpts), P, P, I64, P, I64, I32, P,
+                                        I32P, DP, P]),
+    "hgl_sketch_gaussian": (C.c_int, [I64, I32, C.c_uint64, P, P]),
     "hgl_profile": (C.c_int, [P, I32]),
     "hgl_profile_read": (C.c_int, [P, I32, C.POINTER(C.c_int64), DP]),
 }

@@ -584,7 +584,7 @@ extern "C" int hgl_profile(hgl_handle* h, int32_t enable) {
   clear_error();
   HGL_CHECK_ARG(h != nullptr, "handle is NULL");
   prof_collect(h);
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < kProfKinds; ++i) {
     h->prof_launches[i] = 0;
     h->prof_ms[i] = 0.0;
   }
@@ -595,7 +595,7 @@ extern "C" int hgl_profile(hgl_handle* h, int32_t enable) {
 extern "C" int hgl_profile_read(hgl_handle* h, int32_t kind, int64_t* launches, double* ms) {
   clear_error();
   HGL_CHECK_ARG(h != nullptr, "handle is NULL");
-  HGL_CHECK_ARG(kind >= 0 && kind < 8, "unknown kernel kind %d", kind);
+  HGL_CHECK_ARG(kind >= 0 && kind < kProfKinds, "unknown kernel kind %d", kind);
   prof_collect(h);
   if (launches) *launches = h->prof_launches[kind];
   if (ms) *ms = h->prof_ms[kind];

@@ -25,6 +25,7 @@ struct CgState {
   double* alpha;   // [G*k]
   double* beta;    // [G*k]
   double* relres;  // [G*k] last FP64-recomputed relative residual
+  double* rz;      // [G*k] r'z (preconditioned) or r'r
   int32_t* state;  // [G*k]
   int32_t* iters;  // [G*k]
 };
@@ -43,15 +44,17 @@ __device__ __forceinline__ void zero_long_slots(double* part, int n_tiles, int n
   }
 }
 
-// Start: (x0 not given) F = 0, R = Y; then P = R.  Partials of r'r (only when
-// x0 is not given; otherwise the residual pass produced them) and of y'y.
+// Start: (x0 not given) F = 0, R = Y; then P = R, or P = Zp when a
+// preconditioned residual Zp is given.  Partials of r'r (only when x0 is not
+// given; otherwise the residual pass produced them) and of y'y.
 template <class T, int GL, int V>
 __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t n_tiles, const int32_t* __restrict__ tile_r0,
                                                     const int32_t* __restrict__ tile_r1, int n_slots,
                                                     int n_long, const T* __restrict__ Y, int64_t ldy,
                                                     T* __restrict__ F, int64_t ldf, T* __restrict__ R,
                                                     T* __restrict__ P, int64_t ld, double* __restrict__ part_rr,
-                                                    double* __restrict__ part_yy, int k, int x0_given) {
+                                                    double* __restrict__ part_yy, int k, int x0_given,
+                                                    const T* __restrict__ Zp) {
   constexpr int GPB = kBlock / GL, W = GL * V;
   __shared__ double lds[4 * W];
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
@@ -76,7 +79,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t n_tiles, const int32
       } else {
         load_row<V>(R + int64_t(r) * ld + col, rv);
       }
-      store_row<V>(P + int64_t(r) * ld + col, rv);
+      if (Zp) {
+        T zv[V];
+        load_row<V>(Zp + int64_t(r) * ld + col, zv);
+        store_row<V>(P + int64_t(r) * ld + col, zv);
+      } else {
+        store_row<V>(P + int64_t(r) * ld + col, rv);
+      }
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         yy[i] += double(y[i]) * double(y[i]);
@@ -195,9 +204,11 @@ struct RedArgs {
   const int32_t* seg_slots;
   const double* part;   // r'r (Init, Beta, Check) or p'Mp (Alpha)
   const double* part2;  // y'y (Init)
+  const double* part3;  // r'z (Init, Beta, Check) when preconditioned
   double tol;
   int iter;             // iteration index
   int periodic;         // Beta: the residual was recomputed in this iteration
+  int has_prec;         // preconditioned: alpha, beta use r'z instead of r'r
 };
 
 // Flag words: cnt(it) = columns still iterating after iteration it (cnt(-1)
@@ -232,11 +243,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_reduce(RedArgs ra, CgState st, Wo
   const double sum = block_slot_sum(ra.part, ra.n_slots, ra.seg_slots, g, col, lds);
   double sum2 = 0.0;
   if constexpr (OP == RedOp::Init) sum2 = block_slot_sum(ra.part2, ra.n_slots, ra.seg_slots, g, col, lds);
+  double rz = sum;  // r'z, = r'r without a preconditioner
+  if constexpr (OP != RedOp::Alpha) {
+    if (ra.has_prec) rz = block_slot_sum(ra.part3, ra.n_slots, ra.seg_slots, g, col, lds);
+  }
   if (threadIdx.x != 0) return;
   const int64_t id = wid;
   if constexpr (OP == RedOp::Init) {
     st.yy[id] = sum2;
     st.rr[id] = sum;
+    st.rz[id] = rz;
     st.iters[id] = 0;
     st.alpha[id] = 0.0;
     st.beta[id] = 0.0;
@@ -246,17 +262,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_reduce(RedArgs ra, CgState st, Wo
     st.state[id] = done ? kDone : kActive;
     if (!done) atomicAdd(wd.cnt(-1), 1);
   } else if constexpr (OP == RedOp::Alpha) {
-    if (st.state[id] != kActive || st.rr[id] == 0.0) {
+    if (st.state[id] != kActive || st.rz[id] == 0.0) {
       st.alpha[id] = 0.0;
       return;
     }
-    if (!(sum > 0.0) || !isfinite(sum) || !isfinite(st.rr[id])) {
+    if (!(sum > 0.0) || !isfinite(sum) || !isfinite(st.rz[id])) {
       st.alpha[id] = 0.0;
       st.state[id] = kBreakdown;
       atomicOr(wd.err(), 1);
       return;
     }
-    st.alpha[id] = st.rr[id] / sum;
+    st.alpha[id] = st.rz[id] / sum;
   } else if constexpr (OP == RedOp::Beta) {
     if (st.state[id] != kActive) {
       st.beta[id] = 0.0;
@@ -271,16 +287,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_reduce(RedArgs ra, CgState st, Wo
       st.state[id] = kDone;
       st.beta[id] = 0.0;
       st.rr[id] = sum;
+      st.rz[id] = rz;
       return;
     }
-    if (!isfinite(sum)) {
+    if (!isfinite(sum) || !isfinite(rz)) {
       st.state[id] = kBreakdown;
       atomicOr(wd.err(), 1);
       st.beta[id] = 0.0;
       return;
     }
-    st.beta[id] = sum / st.rr[id];
+    st.beta[id] = rz / st.rz[id];
     st.rr[id] = sum;
+    st.rz[id] = rz;
     atomicAdd(wd.cnt(it), 1);
     atomicMax(reinterpret_cast<unsigned long long*>(wd.rmax(it)),
               static_cast<unsigned long long>(__double_as_longlong(rel)));
@@ -291,6 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_reduce(RedArgs ra, CgState st, Wo
     // residual replacement: the recursion continues from the recomputed
     // residual with the same search direction
     st.rr[id] = sum;
+    st.rz[id] = rz;
     if (rel <= ra.tol) st.state[id] = kDone;
     else atomicAdd(wd.chk(it), 1);
   }
@@ -307,25 +326,30 @@ struct CgBuffers {
   double* Z64; // E x k FP64 (residual passes of the FP32 mode)
   double* part;
   double* part2;
+  double* part3;
+  T* Zp;       // preconditioned residual (PCG)
   CgState st;
 };
 
 template <class T>
 static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const T* Y, int64_t ldy,
-                  T* F, int64_t ldf, int k, int32_t* iters_host, double* relres_host, hipStream_t s) {
+                  T* F, int64_t ldf, int k, int32_t* iters_host, double* relres_host, const Precond* prec,
+                  hipStream_t s) {
   const bool fp32 = sizeof(T) == 4;
+  const bool has_prec = prec != nullptr;
   const int N = h->N, E = h->E, G = h->G;
   const int64_t ld = k;  // internal vectors
   const int nsl = n_slots(h);
   // ---------------------------------------------------------- workspace
   const size_t vec = sizeof(T) * size_t(N) * ld;
-  HGL_TRY(h->ws_vec.reserve(3 * vec + 256));
+  HGL_TRY(h->ws_vec.reserve((has_prec ? 4 : 3) * vec + 256));
   HGL_TRY(h->ws_z.reserve(sizeof(T) * size_t(std::max(E, 1)) * ld));
   if (fp32) HGL_TRY(h->ws_z64.reserve(sizeof(double) * size_t(std::max(E, 1)) * ld));
   HGL_TRY(h->ws_part.reserve(sizeof(double) * size_t(nsl) * k));
   HGL_TRY(h->ws_part2.reserve(sizeof(double) * size_t(nsl) * k));
+  if (has_prec) HGL_TRY(h->ws_extra[0].reserve(sizeof(double) * size_t(nsl) * k));
   const size_t gk = size_t(G) * k;
-  HGL_TRY(h->ws_state.reserve(sizeof(double) * 5 * gk + sizeof(int32_t) * (2 * gk + Words::count(o->max_iter))));
+  HGL_TRY(h->ws_state.reserve(sizeof(double) * 6 * gk + sizeof(int32_t) * (2 * gk + Words::count(o->max_iter))));
   HGL_TRY(ensure_pinned(h, 2 * gk + 8));
   if (h->n_chunks > 0) HGL_TRY(h->ws_chunk.reserve(sizeof(double) * size_t(h->n_chunks) * k));
   HGL_TRY(upload_ab(h, lambdas, s));
@@ -340,13 +364,16 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   b.Z64 = fp32 ? h->ws_z64.as<double>() : reinterpret_cast<double*>(b.Z);
   b.part = h->ws_part.as<double>();
   b.part2 = h->ws_part2.as<double>();
+  b.part3 = has_prec ? h->ws_extra[0].as<double>() : nullptr;
+  b.Zp = has_prec ? b.Q + size_t(N) * ld : nullptr;
   double* sd = h->ws_state.as<double>();
   b.st.yy = sd;
   b.st.rr = sd + gk;
   b.st.alpha = sd + 2 * gk;
   b.st.beta = sd + 3 * gk;
   b.st.relres = sd + 4 * gk;
-  b.st.state = reinterpret_cast<int32_t*>(sd + 5 * gk);
+  b.st.rz = sd + 5 * gk;
+  b.st.state = reinterpret_cast<int32_t*>(sd + 6 * gk);
   b.st.iters = b.st.state + gk;
   Words wd{b.st.iters + gk, o->max_iter};
   if (reinterpret_cast<uintptr_t>(wd.rmax(0)) % alignof(double) != 0) {
@@ -358,7 +385,17 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   const ColShape cs = pick_shape(k, sizeof(T), {Y, F, b.R}, {ldy, ldf, ld});
   const ColShape cs64 = pick_shape(k, 8, {Y, F, b.R}, {ldy, ldf, ld});
   const int red_blocks = int(gk);
-  RedArgs ra{G, k, nsl, h->seg_slots, b.part, b.part2, o->tol, 0, 0};
+  RedArgs ra{G, k, nsl, h->seg_slots, b.part, b.part2, b.part3, o->tol, 0, 0, has_prec ? 1 : 0};
+
+  // preconditioner: Zp = P^-1 R with partial r'z into part3 (or into part)
+  auto precond = [&](const T* Rin, int64_t ldr, T* Zout, int64_t ldz, double* part, Gate gate) -> int {
+    prof_begin(h, kProfPrecond, s);
+    int st2;
+    if constexpr (sizeof(T) == 4) st2 = prec->apply_f32(prec->ctx, Rin, ldr, Zout, ldz, part, k, gate, s);
+    else st2 = prec->apply_f64(prec->ctx, Rin, ldr, Zout, ldz, part, k, gate, s);
+    prof_end(h, s);
+    return st2;
+  };
 
   // residual pass R = Y - M F (FP64 accumulation), partial r'r into b.part
   auto resid = [&](Gate gate) -> int {
@@ -373,13 +410,17 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   };
 
   // ------------------------------------------------------------- start
-  if (o->x0_given) HGL_TRY(resid(Gate{}));
+  // With a preconditioner and no start given, the start is F0 = P^-1 Y.
+  const bool x0 = o->x0_given || has_prec;
+  if (has_prec && !o->x0_given) HGL_TRY(precond(Y, ldy, F, ldf, nullptr, Gate{}));
+  if (x0) HGL_TRY(resid(Gate{}));
+  if (has_prec) HGL_TRY(precond(b.R, ld, b.Zp, ld, b.part3, Gate{}));
   prof_begin(h, kProfStart, s);
   int rc = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
     dim3 grid(h->n_tiles, cs.slabs);
     hipLaunchKernelGGL((k_cg_init<T, GL, V>), grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
                        h->tile_r1, nsl, h->n_long, Y, ldy, F, ldf, b.R, b.P, ld, b.part, b.part2, k,
-                       o->x0_given ? 1 : 0);
+                       x0 ? 1 : 0, has_prec ? static_cast<const T*>(b.Zp) : nullptr);
     HGL_HIP(hipGetLastError());
     return HGL_OK;
   });
@@ -418,6 +459,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     prof_end(h, s);
     const int periodic = (o->rr_period > 0 && (it + 1) % o->rr_period == 0) ? 1 : 0;
     if (periodic) HGL_TRY(resid(g_prev));
+    if (has_prec) HGL_TRY(precond(b.R, ld, b.Zp, ld, b.part3, g_prev));
     r.periodic = periodic;
     prof_begin(h, kProfReduce, s);
     hipLaunchKernelGGL((k_cg_reduce<RedOp::Beta>), dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
@@ -425,10 +467,11 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     prof_end(h, s);
     Gate g_now{wd.cnt(it), nullptr, 1};
     prof_begin(h, kProfDirection, s);
+    const T* dir_src = has_prec ? b.Zp : b.R;
     int rc3 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
       dim3 grid(h->n_tiles, cs.slabs);
       hipLaunchKernelGGL((k_cg_direction<T, GL, V>), grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
-                         h->tile_seg, b.R, b.P, ld, b.st.beta, k, g_now);
+                         h->tile_seg, dir_src, b.P, ld, b.st.beta, k, g_now);
       HGL_HIP(hipGetLastError());
       return HGL_OK;
     });
@@ -441,6 +484,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   // residual meets tol are done, the others go on from the same direction.
   auto check = [&](int it_next) -> int {
     HGL_TRY(resid(Gate{}));
+    if (has_prec) HGL_TRY(precond(b.R, ld, b.Zp, ld, b.part3, Gate{}));
     RedArgs r = ra;
     r.iter = it_next;
     prof_begin(h, kProfReduce, s);
@@ -519,9 +563,8 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   return unconverged ? HGL_NOT_CONVERGED : HGL_OK;
 }
 
-static int cg_entry(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const void* Y,
-                    int64_t ldy, void* F, int64_t ldf, int32_t k, int32_t* iters_host,
-                    double* relres_host, hipStream_t s) {
+int cg_run(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const void* Y, int64_t ldy, void* F,
+           int64_t ldf, int k, int32_t* iters_host, double* relres_host, const Precond* prec, hipStream_t s) {
   HGL_CHECK_ARG(h != nullptr, "handle is NULL");
   HGL_CHECK_ARG(o != nullptr, "opts is NULL");
   HGL_CHECK_ARG(lambdas != nullptr, "lambdas is NULL");
@@ -536,10 +579,10 @@ static int cg_entry(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, 
   HGL_CHECK_ARG(o->rr_period >= 0, "rr_period must be >= 0");
   if (o->mode == HGL_CG_PLAIN_F64)
     return run_cg<double>(h, lambdas, o, static_cast<const double*>(Y), ldy, static_cast<double*>(F),
-                          ldf, k, iters_host, relres_host, s);
+                          ldf, k, iters_host, relres_host, prec, s);
   if (o->mode == HGL_CG_F32_F64DOT_RR)
     return run_cg<float>(h, lambdas, o, static_cast<const float*>(Y), ldy, static_cast<float*>(F), ldf,
-                         k, iters_host, relres_host, s);
+                         k, iters_host, relres_host, prec, s);
   set_error("unknown CG mode %d", o->mode);
   return HGL_EINVAL;
 }
@@ -554,12 +597,12 @@ extern "C" int hgl_cg_solve(hgl_handle* h, double lambda, const hgl_cg_opts* opt
   clear_error();
   HGL_CHECK_ARG(h != nullptr, "handle is NULL");
   std::vector<double> lams(h->G, lambda);
-  return cg_entry(h, lams.data(), opts, Y, ldy, F, ldf, k, iters_host, relres_host, stream);
+  return cg_run(h, lams.data(), opts, Y, ldy, F, ldf, k, iters_host, relres_host, nullptr, stream);
 }
 
 extern "C" int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg_opts* opts,
                                     const void* Y, int64_t ldy, void* F, int64_t ldf, int32_t k,
                                     int32_t* iters_host, double* relres_host, hipStream_t stream) {
   clear_error();
-  return cg_entry(h, lambdas_host, opts, Y, ldy, F, ldf, k, iters_host, relres_host, stream);
+  return cg_run(h, lambdas_host, opts, Y, ldy, F, ldf, k, iters_host, relres_host, nullptr, stream);
 }

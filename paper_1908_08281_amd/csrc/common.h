@@ -54,6 +54,7 @@ constexpr int kTileRows = 64;      // rows per tile of the row-streaming kernels
 constexpr int kLongRow = 64;       // vertex rows with more hyperedges are split
 constexpr int kChunk = 256;        // hyperedges per chunk of a split vertex row
 constexpr int kStageIdx = 2048;    // hyperedge ids of a tile staged in LDS
+constexpr int kProfKinds = 16;     // kernel kinds of the timing counters
 
 // ------------------------------------------------------ device buffers --
 
@@ -122,8 +123,8 @@ struct hgl_handle {
   bool prof_on = false;
   std::vector<hipEvent_t> prof_pool;                 // free events
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
-  int64_t prof_launches[8] = {0};
-  double prof_ms[8] = {0};
+  int64_t prof_launches[hgl::kProfKinds] = {0};
+  double prof_ms[hgl::kProfKinds] = {0};
   hipEvent_t prof_open = nullptr;
   int prof_kind = -1;
   int32_t* pinned_i = nullptr;   // host-pinned readback words
@@ -166,9 +167,23 @@ int upload_ab(hgl_handle* h, const double* lambdas_host, hipStream_t st);
 
 // Kernel timing: bracket one launch of a kernel kind (no-ops unless enabled).
 enum ProfKind { kProfEdge = 0, kProfVertex = 1, kProfUpdate = 2, kProfDirection = 3,
-                kProfReduce = 4, kProfResidEdge = 5, kProfResidVertex = 6, kProfStart = 7 };
+                kProfReduce = 4, kProfResidEdge = 5, kProfResidVertex = 6, kProfStart = 7,
+                kProfPrecond = 8, kProfGemm = 9, kProfQr = 10, kProfEig = 11, kProfExtract = 12,
+                kProfGrad = 13 };
 void prof_begin(hgl_handle* h, int kind, hipStream_t s);
 void prof_end(hgl_handle* h, hipStream_t s);
+
+// Preconditioner for the CG driver: Z = P^-1 R (k columns), with partial
+// inner products <R_j, Z_j> per row tile written to part (nullable).
+struct Precond {
+  void* ctx = nullptr;
+  int (*apply_f32)(void*, const float*, int64_t, float*, int64_t, double*, int, Gate, hipStream_t) = nullptr;
+  int (*apply_f64)(void*, const double*, int64_t, double*, int64_t, double*, int, Gate, hipStream_t) = nullptr;
+};
+
+// The CG / preconditioned CG driver behind hgl_cg_solve (cg.hip).
+int cg_run(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const void* Y, int64_t ldy, void* F,
+           int64_t ldf, int k, int32_t* iters_host, double* relres_host, const Precond* prec, hipStream_t s);
 
 // Operator application pieces (spmm.hip).
 enum class VMode { Apply = 0, ApplyDot = 1, Resid = 2 };

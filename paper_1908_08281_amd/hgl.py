@@ -190,8 +190,76 @@ def cg_solve_batched(h: Handle, lams, Y: torch.Tensor, mode: str = "f32", tol: f
     return _cg(h, lams, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=True)
 
 
+SKETCH = {"bf16": _lib.HGL_SKETCH_BF16, "f64": _lib.HGL_SKETCH_F64}
+
+
+def _offsets(offsets) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+
+
+def _rsvd_opts(k, p, q, sketch, seed, refine_tol=1e-6, max_refine=500, chunk=0):
+    return _lib.RsvdOpts(int(k), int(p), int(q), SKETCH[sketch], int(seed), float(refine_tol),
+                         int(max_refine), int(chunk))
+
+
+def _omega_ptr(h: Handle, omega, l: int):
+    if omega is None:
+        return C.c_void_p(0)
+    _need(omega, torch.int16, "omega (bf16 bit patterns as int16)", h.device)
+    if omega.shape != (h.N, l) or not omega.is_contiguous():
+        raise ValueError(f"omega must be a contiguous ({h.N}, {l}) int16 tensor")
+    return _ptr(omega)
+
+
+def block_rsvd(h: Handle, offsets, k: int, p: int, q: int, sketch: str = "bf16", omega=None, seed: int = 0):
+    """Algorithm 1 on every diagonal block.  Returns (U [N,k] float32, sigma [n_blocks,k] float64)."""
+    off = _offsets(offsets)
+    nb = off.size - 1
+    U = torch.empty((h.N, k), dtype=torch.float32, device=h.device)
+    sig = torch.empty((nb, k), dtype=torch.float64, device=h.device)
+    opts = _rsvd_opts(k, p, q, sketch, seed)
+    with torch.cuda.device(h.device):
+        check(lib().hgl_block_rsvd(h.ptr, nb, off.ctypes.data_as(_lib.I32P), C.byref(opts),
+                                   _omega_ptr(h, omega, k + p), _ptr(U), _ptr(sig), _stream(h.device)),
+              "hgl_block_rsvd")
+    return U, sig
+
+
+def block_rsvd_invert(h: Handle, lam: float, offsets, Y: torch.Tensor, k: int, p: int, q: int,
+                      sketch: str = "bf16", omega=None, seed: int = 0, refine_tol: float = 5e-7,
+                      max_refine: int = 500, chunk: int = 0):
+    """Block-inverse start + preconditioned CG.  Returns (F, iters, relres, sigma, status)."""
+    off = _offsets(offsets)
+    nb = off.size - 1
+    _need(Y, torch.float32, "Y", h.device)
+    ldy = _rows(Y, "Y")
+    nrhs = Y.shape[1]
+    F = torch.empty((h.N, nrhs), dtype=torch.float32, device=h.device)
+    sig = torch.empty((nb, k), dtype=torch.float64, device=h.device)
+    iters = np.zeros(nrhs, dtype=np.int32)
+    rel = np.zeros(nrhs, dtype=np.float64)
+    opts = _rsvd_opts(k, p, q, sketch, seed, refine_tol, max_refine, chunk)
+    with torch.cuda.device(h.device):
+        st = lib().hgl_block_rsvd_invert(h.ptr, float(lam), nb, off.ctypes.data_as(_lib.I32P), C.byref(opts),
+                                         _omega_ptr(h, omega, k + p), _ptr(Y), ldy, _ptr(F), F.stride(0), nrhs,
+                                         _ptr(sig), iters.ctypes.data_as(_lib.I32P), rel.ctypes.data_as(_lib.DP),
+                                         _stream(h.device))
+    check(st, "hgl_block_rsvd_invert")
+    return F, iters, rel, sig, st
+
+
+def sketch_gaussian(rows: int, l: int, seed: int, device) -> torch.Tensor:
+    """rows x l Philox4x32-10 standard normals rounded to BF16 (bit patterns, int16 tensor)."""
+    out = torch.empty((rows, l), dtype=torch.int16, device=device)
+    with torch.cuda.device(device):
+        check(lib().hgl_sketch_gaussian(int(rows), int(l), int(seed), _ptr(out), _stream(torch.device(device))),
+              "hgl_sketch_gaussian")
+    return out
+
+
 PROFILE_KINDS = {0: "edge_gather", 1: "vertex_gather", 2: "cg_update", 3: "cg_direction",
-                 4: "reduce", 5: "resid_edge_gather", 6: "resid_vertex_gather", 7: "start"}
+                 4: "reduce", 5: "resid_edge_gather", 6: "resid_vertex_gather", 7: "start",
+                 8: "precond", 9: "rsvd_gemm", 10: "cholqr", 11: "jacobi", 12: "extract", 13: "grad"}
 
 
 def profile(h: Handle, enable: bool) -> None:
