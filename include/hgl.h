@@ -233,6 +233,42 @@ int hgl_block_rsvd_invert(hgl_handle* h, double lambda, int32_t n_blocks,
  */
 int hgl_sketch_gaussian(int64_t rows, int32_t l, uint64_t seed, uint16_t* out_bf16, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Weight derivatives (paper, section 2: P(w) of eq. 4 and the steepest-descent
+ * update of w; the paper defers the formula, it is derived from eq. 1).
+ * For N x k matrices P, Q:
+ *   Gamma_e(P,Q) = <u_e(P), u_e(Q)>/delta(e)
+ *                  - 1/2 sum_{v in e} s_v^2 (<P_v, (AQ)_v> + <(AP)_v, Q_v>),
+ *   u_e(P) = sum_{v in e} s_v P_v   (= <P, dA/dw_e Q>, Dv's dependence on w included).
+ * ------------------------------------------------------------------------ */
+
+/*
+ * grad_w [E] (device, FP64) = derivative with respect to w of:
+ *  - G != NULL: a loss l(F) of F = (I + L/lambda)^-1 Y with upstream
+ *    G = dl/dF:  grad_w[e] = Gamma_e(Z, F)/lambda, Z = M^-1 G;
+ *  - G == NULL: the adaptive-weight objective
+ *    J = tr(F'LF) + lambda ||F - Y||^2 + mu ||w||^2 at the given F:
+ *    grad_w[e] = -Gamma_e(F,F) + Gamma_e(Z,F)/lambda + 2 mu w_e,
+ *    Z = M^-1 (2 lambda (M F - Y)) (exact total derivative even when F is
+ *    an approximate solve).
+ * F, G, Y, Z_out: N x k, FP32 when adj->mode is F32_F64DOT_RR, FP64 when
+ * PLAIN_F64; leading dimensions ldf, ldg, ldy, ldz.  The adjoint solve uses
+ * hgl_cg_solve with adj; Z_out (nullable) receives Z (= dl/dY in the G case);
+ * iters_host/relres_host (nullable, [k]) report the adjoint solve.
+ * Single-graph handles only.  Synchronises the stream.
+ */
+int hgl_weight_grad(hgl_handle* h, double lambda, double mu, const void* F, int64_t ldf, const void* G,
+                    int64_t ldg, const void* Y, int64_t ldy, int32_t k, const hgl_cg_opts* adj,
+                    double* grad_w, void* Z_out, int64_t ldz, int32_t* iters_host, double* relres_host,
+                    hipStream_t stream);
+
+/*
+ * w = argmin ||w - v||_2 subject to w >= 0, sum(w) = 1 (the constraints of
+ * eq. 4): w = max(v - tau, 0) with tau chosen so that w sums to one.  v, w:
+ * device FP64 arrays of length E (may alias).  Asynchronous.
+ */
+int hgl_project_simplex(const double* v, double* w, int32_t E, hipStream_t stream);
+
 /*
  * Kernel timing (diagnostics).  hgl_profile(h, 1) resets the counters and
  * makes every later solver call on h bracket each kernel launch with HIP

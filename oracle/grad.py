@@ -91,6 +91,28 @@ def objective_grad(H: np.ndarray, w, lam: float, mu: float, Y: np.ndarray, F=Non
     return -gamma(H, w, F, F) + gamma(H, w, Z, F) / lam + 2.0 * mu * w
 
 
+def gamma_sparse(op, P: np.ndarray, Q: np.ndarray) -> np.ndarray:
+    """Gamma_e(P, Q) for every edge from a ``laplacian.SparseOperator`` (same
+    formula as ``gamma``, written with sparse products for large N)."""
+    s, HT = op.s, op.HT
+    de = np.asarray(HT.sum(axis=1)).ravel()
+    uP = HT @ (s[:, None] * P)
+    uQ = HT @ (s[:, None] * Q)
+    AP, AQ = op.adjacency_apply(P), op.adjacency_apply(Q)
+    t = s ** 2 * (np.einsum("ij,ij->i", P, AQ) + np.einsum("ij,ij->i", AP, Q))
+    return np.einsum("ij,ij->i", uP, uQ) / de - 0.5 * (HT @ t)
+
+
+def objective_grad_sparse(op, w, lam: float, mu: float, Y: np.ndarray, F: np.ndarray, tol: float = 1e-13):
+    """dJ/dw with the sparse tier: the adjoint Z = M^-1 (2 lam (M F - Y)) by
+    FP64 CG (eqs. 16-20) to relres tol."""
+    from .solve import cg_ranking
+    G = 2.0 * lam * (op(F) - Y)
+    Z, _, _ = cg_ranking(op, w, lam, G, tol=tol)
+    # cg_ranking solves X z = lam/(1+lam) g, i.e. M z = g
+    return -gamma_sparse(op, F, F) + gamma_sparse(op, Z, F) / lam + 2.0 * mu * np.asarray(w)
+
+
 def central_difference(fun, w, e: int, h: float) -> float:
     wp = np.array(w, dtype=np.float64)
     wm = wp.copy()

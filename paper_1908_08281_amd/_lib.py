@@ -64,6 +64,8 @@ SIGNATURES = {
     "hgl_block_rsvd_invert": (C.c_int, [P, D, I32, I32P, C.POINTER(RsvdOpts), P, P, I64, P, I64, I32, P,
                                         I32P, DP, P]),
     "hgl_sketch_gaussian": (C.c_int, [I64, I32, C.c_uint64, P, P]),
+    "hgl_weight_grad": (C.c_int, [P, D, D, P, I64, P, I64, P, I64, I32, C.POINTER(CgOpts), P, P, I64, I32P, DP, P]),
+    "hgl_project_simplex": (C.c_int, [P, P, I32, P]),
     "hgl_profile": (C.c_int, [P, I32]),
     "hgl_profile_read": (C.c_int, [P, I32, C.POINTER(C.c_int64), DP]),
 }

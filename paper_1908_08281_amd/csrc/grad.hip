@@ -1,0 +1,304 @@
+// Derivatives with respect to the hyperedge weights (paper, section 2:
+// P(w) of eq. 4 and the steepest-descent weight update) and the projection
+// onto the constraint set {w >= 0, 1'w = 1} of eq. (4).
+//
+// With s_v = delta(v)^-1/2, c_e = w_e/delta(e) and A = S H C H' S (eq. 1),
+//   dA/dw_e = (1/delta(e)) (S h_e)(S h_e)' - 1/2 (D_e A + A D_e),
+//   D_e = diag(s_v^2 [v in e]),
+// so for N x k matrices P, Q
+//   Gamma_e(P, Q) = <P, dA/dw_e Q> = <u_e(P), u_e(Q)>/delta(e) - 1/2 sum_{v in e} t_v,
+//   u_e(P) = sum_{v in e} s_v P_v,  t_v = s_v^2 (<P_v, (AQ)_v> + <(AP)_v, Q_v>).
+// F = M^-1 Y, M = I + L/lambda, gives dF/dw_e = M^-1 (dA/dw_e) F / lambda; a
+// loss with upstream G = dl/dF has dl/dw_e = Gamma_e(Z, F)/lambda with the
+// adjoint Z = M^-1 G (M is symmetric, so the same CG solves it) and
+// dl/dY = Z.  The adaptive-weight objective
+//   J(w) = tr(F'LF) + lambda ||F - Y||^2 + mu ||w||^2
+// has dJ/dw_e = -Gamma_e(F, F) + Gamma_e(Z, F)/lambda + 2 mu w_e with
+// Z = M^-1 (2 lambda (M F - Y)) (total derivative; Dv depends on w).
+// All contractions accumulate in FP64, each edge and vertex in a fixed order.
+#include <algorithm>
+#include <cmath>
+
+#include "kernels.h"
+
+namespace hgl {
+
+template <class T>
+__global__ void k_to_f64(int64_t rows, int k, const T* __restrict__ X, int64_t ldx, double* __restrict__ D) {
+  const int64_t total = rows * k;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x)
+    D[i] = double(X[(i / k) * ldx + i % k]);
+}
+
+// R = 2 lambda_g (MF - Y) in the caller's type (rows of graph g)
+template <class T>
+__global__ void k_objective_rhs(int64_t rows, int k, const double* __restrict__ MF, const T* __restrict__ Y,
+                                int64_t ldy, double lam2, T* __restrict__ R) {
+  const int64_t total = rows * k;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = i / k, c = i % k;
+    R[i] = T(lam2 * (MF[i] - double(Y[r * ldy + c])));
+  }
+}
+
+// Per-vertex contractions (FP64, k-wide rows, one 64-lane wave per vertex):
+//   t1_v = s_v^2 * 2 <F_v, (AF)_v>                       (for Gamma(F, F))
+//   t2_v = s_v^2 (<Z_v, (AF)_v> + <(AZ)_v, F_v>)         (for Gamma(Z, F))
+__global__ __launch_bounds__(kBlock) void k_vertex_terms(int32_t N, int k, const double* __restrict__ s,
+                                                         const double* __restrict__ F, const double* __restrict__ AF,
+                                                         const double* __restrict__ Z, const double* __restrict__ AZ,
+                                                         double* __restrict__ t1, double* __restrict__ t2) {
+  const int v = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (v >= N) return;
+  const int64_t o = int64_t(v) * k;
+  double a = 0.0, b = 0.0;
+  for (int c = lane; c < k; c += kWave) {
+    const double f = F[o + c], af = AF[o + c];
+    a += f * af;
+    if (Z) b += Z[o + c] * af + AZ[o + c] * f;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, kWave);
+    b += __shfl_xor(b, off, kWave);
+  }
+  if (lane == 0) {
+    const double s2 = s[v] * s[v];
+    t1[v] = s2 * 2.0 * a;
+    t2[v] = s2 * b;
+  }
+}
+
+// Per-edge gradient (one wave per hyperedge):
+//   g1 = <u_e(F), u_e(F)>/delta(e) - 1/2 sum_{v in e} t1_v    (= Gamma_e(F, F))
+//   g2 = <u_e(Z), u_e(F)>/delta(e) - 1/2 sum_{v in e} t2_v    (= Gamma_e(Z, F))
+//   grad_e = cf * g1 + cz * g2 + 2 mu w_e
+__global__ __launch_bounds__(kBlock) void k_edge_grad(int32_t E, int k, const int32_t* __restrict__ edge_ptr,
+                                                      const int32_t* __restrict__ edge_vtx,
+                                                      const double* __restrict__ s, const double* __restrict__ F,
+                                                      const double* __restrict__ Z, const double* __restrict__ t1,
+                                                      const double* __restrict__ t2, const double* __restrict__ w,
+                                                      double cf, double cz, double mu, double* __restrict__ grad) {
+  const int e = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (e >= E) return;
+  const int b = edge_ptr[e], en = edge_ptr[e + 1];
+  double ff = 0.0, zf = 0.0;
+  for (int c = lane; c < k; c += kWave) {
+    double uf = 0.0, uz = 0.0;
+    for (int j = b; j < en; ++j) {
+      const int v = edge_vtx[j];
+      const double sv = s[v];
+      uf += sv * F[int64_t(v) * k + c];
+      if (Z) uz += sv * Z[int64_t(v) * k + c];
+    }
+    ff += uf * uf;
+    zf += uz * uf;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    ff += __shfl_xor(ff, off, kWave);
+    zf += __shfl_xor(zf, off, kWave);
+  }
+  if (lane == 0) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int j = b; j < en; ++j) {
+      s1 += t1[edge_vtx[j]];
+      s2 += t2[edge_vtx[j]];
+    }
+    const double de = double(en - b);
+    const double g1 = ff / de - 0.5 * s1;
+    const double g2 = zf / de - 0.5 * s2;
+    grad[e] = cf * g1 + cz * g2 + 2.0 * mu * w[e];
+  }
+}
+
+// ------------------------------------------------------ simplex projection --
+
+// Euclidean projection of v onto {w >= 0, sum w = 1} in one workgroup:
+// bisection for tau with sum max(v - tau, 0) = 1 (the sum decreases in tau),
+// then the exact tau of the support found, (sum_{v_i > tau} v_i - 1)/|support|,
+// recomputed until the support is stable.  Fixed-order reductions.
+__device__ double block_sum(double x, double* lds) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, kWave);
+  if (threadIdx.x % kWave == 0) lds[threadIdx.x / kWave] = x;
+  __syncthreads();
+  const double t = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+  __syncthreads();
+  return t;
+}
+
+__device__ double block_max(double x, double* lds) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, kWave));
+  if (threadIdx.x % kWave == 0) lds[threadIdx.x / kWave] = x;
+  __syncthreads();
+  const double t = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_project_simplex(int32_t E, const double* __restrict__ v,
+                                                            double* __restrict__ w) {
+  __shared__ double lds[4];
+  double mx = -INFINITY, mn = INFINITY;
+  for (int i = threadIdx.x; i < E; i += kBlock) {
+    mx = fmax(mx, v[i]);
+    mn = fmin(mn, v[i]);
+  }
+  mx = block_max(mx, lds);
+  mn = -block_max(-mn, lds);
+  double lo = mn - 1.0, hi = mx;  // f(lo) >= E >= 1 > 0 = f(hi)
+  for (int it = 0; it < 100 && hi - lo > 1e-16 * fmax(1.0, fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    double sacc = 0.0;
+    for (int i = threadIdx.x; i < E; i += kBlock) sacc += fmax(v[i] - mid, 0.0);
+    sacc = block_sum(sacc, lds);
+    if (sacc >= 1.0) lo = mid; else hi = mid;
+  }
+  double tau = 0.5 * (lo + hi);
+  for (int round = 0; round < 4; ++round) {
+    double ssum = 0.0, cnt = 0.0;
+    for (int i = threadIdx.x; i < E; i += kBlock)
+      if (v[i] > tau) {
+        ssum += v[i];
+        cnt += 1.0;
+      }
+    ssum = block_sum(ssum, lds);
+    cnt = block_sum(cnt, lds);
+    const double t2 = cnt > 0.0 ? (ssum - 1.0) / cnt : tau;
+    if (t2 == tau) break;
+    tau = t2;
+  }
+  for (int i = threadIdx.x; i < E; i += kBlock) w[i] = fmax(v[i] - tau, 0.0);
+}
+
+// ------------------------------------------------------------------ driver --
+
+template <class T>
+static int run_grad(hgl_handle* h, double lam, double mu, const T* F, int64_t ldf, const T* G, int64_t ldg,
+                    const T* Y, int64_t ldy, int k, const hgl_cg_opts* adj, double* grad, T* Zout, int64_t ldz,
+                    int32_t* iters_host, double* relres_host, hipStream_t s) {
+  const int N = h->N, E = h->E;
+  const bool objective = G == nullptr;
+  const size_t nk = size_t(N) * k;
+  // buffers: F64, AF, Z64, AZ (N x k FP64), rhs/Z in T (N x k), t1, t2 (N)
+  DevBuf& buf = h->ws_extra[1];
+  DevBuf& bufT = h->ws_extra[2];
+  HGL_TRY(buf.reserve(sizeof(double) * (4 * nk + 2 * size_t(N)) + 256));
+  HGL_TRY(bufT.reserve(sizeof(T) * 2 * nk + 256));
+  double* F64 = buf.as<double>();
+  double* AF = F64 + nk;
+  double* Z64 = AF + nk;
+  double* AZ = Z64 + nk;
+  double* t1 = AZ + nk;
+  double* t2 = t1 + N;
+  T* rhs = bufT.as<T>();
+  T* Zt = rhs + nk;
+  HGL_TRY(h->ws_z64.reserve(sizeof(double) * size_t(std::max(E, 1)) * k));
+  double* Zedge = h->ws_z64.as<double>();
+  const ColShape cs = pick_shape(k, 8, {F64}, {int64_t(k)});
+  const int blocks = int(std::min<int64_t>((int64_t(nk) + 255) / 256, 65535));
+
+  prof_begin(h, kProfGrad, s);
+  hipLaunchKernelGGL((k_to_f64<T>), dim3(blocks), dim3(256), 0, s, int64_t(N), k, F, ldf, F64);
+  HGL_HIP(hipGetLastError());
+  // (a, b) pairs for the products: A X = 0 X - (-1) S H Z; M X = (1+1/lam) X - (1/lam) S H Z
+  DevBuf& abA = h->ws_extra[3];
+  DevBuf& abM = h->ws_extra[4];
+  HGL_TRY(abA.reserve(16 * size_t(h->G)));
+  HGL_TRY(abM.reserve(16 * size_t(h->G)));
+  {
+    std::vector<double> a(2 * h->G), m(2 * h->G);
+    for (int g = 0; g < h->G; ++g) {
+      a[g] = 0.0;
+      a[h->G + g] = -1.0;
+      m[g] = 1.0 + 1.0 / lam;
+      m[h->G + g] = 1.0 / lam;
+    }
+    HGL_TRY(ensure_pinned(h, 4 * h->G + 8));
+    std::copy(a.begin(), a.end(), h->pinned_d);
+    std::copy(m.begin(), m.end(), h->pinned_d + 2 * h->G);
+    HGL_HIP(hipMemcpyAsync(abA.p, h->pinned_d, 16 * size_t(h->G), hipMemcpyHostToDevice, s));
+    HGL_HIP(hipMemcpyAsync(abM.p, h->pinned_d + 2 * h->G, 16 * size_t(h->G), hipMemcpyHostToDevice, s));
+    HGL_HIP(hipStreamSynchronize(s));
+  }
+  auto apply64 = [&](const double* X, double* Out, const DevBuf& ab) -> int {
+    HGL_TRY((launch_spmm_edge<double, double>(h, X, k, Zedge, k, k, cs, Gate{}, s)));
+    return launch_spmm_vertex<double, double>(h, VMode::Apply, X, k, Zedge, k, nullptr, 0, Out, k,
+                                               ab.as<double>(), ab.as<double>() + h->G, nullptr, k, cs, Gate{}, s);
+  };
+  HGL_TRY(apply64(F64, AF, abA));
+  // adjoint right-hand side
+  const T* rhs_ptr = G;
+  int64_t ld_rhs = ldg;
+  if (objective) {
+    HGL_TRY(apply64(F64, AZ, abM));  // AZ used as scratch for M F
+    hipLaunchKernelGGL((k_objective_rhs<T>), dim3(blocks), dim3(256), 0, s, int64_t(N), k, AZ, Y, ldy, 2.0 * lam,
+                       rhs);
+    HGL_HIP(hipGetLastError());
+    rhs_ptr = rhs;
+    ld_rhs = k;
+  }
+  prof_end(h, s);
+  // adjoint solve Z = M^-1 rhs (same operator: M is symmetric)
+  T* Zdst = Zout ? Zout : Zt;
+  const int64_t ldzd = Zout ? ldz : k;
+  std::vector<double> lams(h->G, lam);
+  int st = cg_run(h, lams.data(), adj, rhs_ptr, ld_rhs, Zdst, ldzd, k, iters_host, relres_host, nullptr, s);
+  if (st < 0) return st;
+  prof_begin(h, kProfGrad, s);
+  hipLaunchKernelGGL((k_to_f64<T>), dim3(blocks), dim3(256), 0, s, int64_t(N), k, Zdst, ldzd, Z64);
+  HGL_HIP(hipGetLastError());
+  HGL_TRY(apply64(Z64, AZ, abA));
+  hipLaunchKernelGGL(k_vertex_terms, dim3((N + 3) / 4), dim3(kBlock), 0, s, N, k, h->s64, F64, AF, Z64, AZ, t1, t2);
+  HGL_HIP(hipGetLastError());
+  if (E > 0) {
+    const double cf = objective ? -1.0 : 0.0;
+    const double cz = 1.0 / lam;
+    hipLaunchKernelGGL(k_edge_grad, dim3((E + 3) / 4), dim3(kBlock), 0, s, E, k, h->edge_ptr, h->edge_vtx, h->s64,
+                       F64, Z64, t1, t2, h->w, cf, cz, objective ? mu : 0.0, grad);
+    HGL_HIP(hipGetLastError());
+  }
+  prof_end(h, s);
+  HGL_HIP(hipStreamSynchronize(s));
+  return st;
+}
+
+}  // namespace hgl
+
+using namespace hgl;
+
+extern "C" int hgl_weight_grad(hgl_handle* h, double lambda, double mu, const void* F, int64_t ldf, const void* G,
+                               int64_t ldg, const void* Y, int64_t ldy, int32_t k, const hgl_cg_opts* adj,
+                               double* grad_w, void* Z_out, int64_t ldz, int32_t* iters_host,
+                               double* relres_host, hipStream_t s) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr && adj != nullptr, "handle and adjoint options must not be NULL");
+  HGL_CHECK_ARG(h->G == 1, "the weight gradient needs a single-graph handle");
+  HGL_CHECK_ARG(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0");
+  HGL_CHECK_ARG(std::isfinite(mu), "mu must be finite");
+  HGL_CHECK_ARG(k >= 1 && F && grad_w, "need k >= 1, F and grad_w");
+  HGL_CHECK_ARG(ldf >= k && (G == nullptr || ldg >= k) && (Z_out == nullptr || ldz >= k), "bad leading dimension");
+  HGL_CHECK_ARG(G != nullptr || (Y != nullptr && ldy >= k), "the objective gradient (G = NULL) needs Y");
+  if (adj->mode == HGL_CG_F32_F64DOT_RR)
+    return run_grad<float>(h, lambda, mu, static_cast<const float*>(F), ldf, static_cast<const float*>(G), ldg,
+                           static_cast<const float*>(Y), ldy, k, adj, grad_w, static_cast<float*>(Z_out), ldz,
+                           iters_host, relres_host, s);
+  if (adj->mode == HGL_CG_PLAIN_F64)
+    return run_grad<double>(h, lambda, mu, static_cast<const double*>(F), ldf, static_cast<const double*>(G), ldg,
+                            static_cast<const double*>(Y), ldy, k, adj, grad_w, static_cast<double*>(Z_out), ldz,
+                            iters_host, relres_host, s);
+  set_error("unknown CG mode %d", adj->mode);
+  return HGL_EINVAL;
+}
+
+extern "C" int hgl_project_simplex(const double* v, double* w, int32_t E, hipStream_t s) {
+  clear_error();
+  HGL_CHECK_ARG(E >= 1 && v && w, "need E >= 1 and v, w");
+  hipLaunchKernelGGL(k_project_simplex, dim3(1), dim3(kBlock), 0, s, E, v, w);
+  HGL_HIP(hipGetLastError());
+  return HGL_OK;
+}

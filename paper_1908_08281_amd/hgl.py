@@ -257,6 +257,46 @@ def sketch_gaussian(rows: int, l: int, seed: int, device) -> torch.Tensor:
     return out
 
 
+def weight_grad(h: Handle, lam: float, F: torch.Tensor, G: torch.Tensor | None = None,
+                Y: torch.Tensor | None = None, mu: float = 0.0, mode: str = "f32", tol: float = 1e-6,
+                max_iter: int = 1000, want_z: bool = False):
+    """d/dw of a loss through the solve (G given: upstream dl/dF) or of the
+    objective tr(F'LF) + lam||F-Y||^2 + mu||w||^2 (G None).
+    Returns (grad_w [E] float64, Z or None, adjoint iters, adjoint relres)."""
+    m = MODES[mode]
+    dtype = torch.float64 if m == _lib.HGL_CG_PLAIN_F64 else torch.float32
+    _need(F, dtype, "F", h.device)
+    k = F.shape[1]
+    ldf = _rows(F, "F")
+    ldg = ldy = 0
+    if G is not None:
+        _need(G, dtype, "G", h.device)
+        ldg = _rows(G, "G")
+    if Y is not None:
+        _need(Y, dtype, "Y", h.device)
+        ldy = _rows(Y, "Y")
+    grad = torch.empty(h.E, dtype=torch.float64, device=h.device)
+    Z = torch.empty((h.N, k), dtype=dtype, device=h.device) if want_z else None
+    opts = CgOpts(m, float(tol), int(max_iter), 0, 0, 0)
+    iters = np.zeros(k, dtype=np.int32)
+    rel = np.zeros(k, dtype=np.float64)
+    with torch.cuda.device(h.device):
+        st = lib().hgl_weight_grad(h.ptr, float(lam), float(mu), _ptr(F), ldf, _ptr(G), ldg, _ptr(Y), ldy, k,
+                                   C.byref(opts), _ptr(grad), _ptr(Z), k if Z is not None else 0,
+                                   iters.ctypes.data_as(_lib.I32P), rel.ctypes.data_as(_lib.DP),
+                                   _stream(h.device))
+    check(st, "hgl_weight_grad")
+    return grad, Z, iters, rel
+
+
+def project_simplex(v: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    _need(v, torch.float64, "v")
+    w = torch.empty_like(v) if out is None else out
+    with torch.cuda.device(v.device):
+        check(lib().hgl_project_simplex(_ptr(v), _ptr(w), v.numel(), _stream(v.device)), "hgl_project_simplex")
+    return w
+
+
 PROFILE_KINDS = {0: "edge_gather", 1: "vertex_gather", 2: "cg_update", 3: "cg_direction",
                  4: "reduce", 5: "resid_edge_gather", 6: "resid_vertex_gather", 7: "start",
                  8: "precond", 9: "rsvd_gemm", 10: "cholqr", 11: "jacobi", 12: "extract", 13: "grad"}

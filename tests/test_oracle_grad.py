@@ -76,6 +76,19 @@ def test_homogeneity(seed):
     assert abs(p.w @ grad.gamma(H, p.w, P, Q)) < 1e-12 * np.abs(grad.gamma(H, p.w, P, Q)).sum()
 
 
+def test_sparse_gamma_and_gradient_match_dense():
+    p, H = _tiny(6, N=40, E=25, k=4)
+    op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
+    P = synth.rng_for(1).standard_normal(p.Y.shape)
+    Q = synth.rng_for(2).standard_normal(p.Y.shape)
+    assert np.allclose(grad.gamma_sparse(op, P, Q), grad.gamma(H, p.w, P, Q), atol=1e-13)
+    M = lap.system_matrix(H, p.w, p.lam)
+    F = solve.solve_dense(M, p.Y) + 1e-3 * synth.rng_for(3).standard_normal(p.Y.shape)
+    g_s = grad.objective_grad_sparse(op, p.w, p.lam, 0.05, p.Y, F)
+    g_d = grad.objective_grad(H, p.w, p.lam, 0.05, p.Y, F)
+    assert np.linalg.norm(g_s - g_d) / np.linalg.norm(g_d) < 1e-10
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_simplex_projection_bruteforce(seed):
     rng = synth.rng_for(seed)
