@@ -1,18 +1,30 @@
-"""Throughput benchmark: one JSON line.
+"""Throughput benchmark: one JSON line per workload (the default run prints
+exactly one line, for the multi-RHS CG workload).
 
-Default workload (multi-RHS FP32 CG): G2 hypergraph with N=50,000 vertices,
-E=40,000 hyperedges (power-law sizes in [2,200], Zipf(1.1) vertex
-popularity), Dirichlet(1) weights, lambda=0.5, Y = 50,000 x 200 binary at
-2%; solved by FP32 CG with FP64 inner products and residual replacement to a
-true relative residual of 1e-6/(1+1/lambda), which bounds the forward error
-by 1e-6.  A step is one full solve of all 200 columns with inputs resident
-in HBM.  `value` = solved right-hand sides per second (every column must
-meet the tolerance, checked by the FP64-recomputed residual).
+Workloads (synthetic, seeded; see synth/):
+  multi_rhs  (default) G2 hypergraph N=50,000, E=40,000 (power-law sizes in
+             [2,200], Zipf(1.1) popularity), Dirichlet(1) weights, lambda=0.5,
+             Y = 50,000 x 200 binary at 2%; FP32 CG with FP64 inner products
+             and residual replacement to relres 1e-6/(1+1/lambda) (forward
+             error <= 1e-6).  A step = one full solve; value = solved RHS/s.
+  small      G1, N=2000, E=1500, w=1/E, lambda=1, Y 2000 x 50 at 5%, FP64 CG
+             to relres 1e-10.
+  rsvd       50 diagonal blocks of U[500,1500] rows (N ~ 50,000, G1,
+             E = 0.75 N, lambda=1), k=64, p=10, q=2, BF16 sketch; a step =
+             Algorithm 1 on all blocks; value = blocks/s.  The refined solve
+             (block inverse + PCG, Y N x 50 at 5%) is timed beside it.
+  learn      G1, N=100,000, E=80,000, Y 100,000 x 500 at 5%, lambda=1,
+             mu=0.01; a step = one outer projected-gradient step (forward CG,
+             adjoint gradient, projection, re-weighting); value = steps/s.
+  batch      64 G2 hypergraphs, N_g ~ U[2000,30000], E_g = 0.8 N_g, 100 RHS
+             each at 3%, lambda=0.5, FP32 to relres 1e-6/(1+1/lambda);
+             value = solved RHS/s over the batch.
 
-The roofline object reports the dominant kernel (the vertex-major gather of
-the operator) with its duration measured by HIP events recorded by the
-library around every launch during the timed steps.  The CPU baseline is the
-FP64 oracle's matrix-free CG timed on a bounded sample of the same workload.
+Every value counts only results that met their tolerance (checked by the
+library's FP64-recomputed residuals).  The roofline object is the dominant
+kernel of the step with its duration measured by HIP events that the library
+records around every launch during the timed steps.  The CPU baseline is the
+FP64 oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -28,18 +40,65 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 
 
-def algorithmic_bytes(N, E, nnz, k, elem=4):
-    """Compulsory HBM bytes of the two operator gathers (one launch each)."""
+def gather_bytes(N, E, nnz, k, elem=4):
+    """Compulsory HBM bytes of one launch of each operator gather, and of one
+    CG iteration (F, R, P read and written once, the E x k intermediate
+    written and read once, both CSR index arrays read once)."""
     vertex = elem * k * (E + 2 * N) + 4 * (2 * N + 1 + nnz)    # read Z, P; write Q; vtx_ptr, vtx_edge, s
     edge = elem * k * (N + E) + 4 * (2 * E + 1 + nnz + N)      # read P; write Z; edge_ptr, edge_vtx, c, s
     per_iter = elem * k * (6 * N + 2 * E) + 4 * (2 * nnz + 2 * N + 2 * E)
     return {"vertex_gather": vertex, "edge_gather": edge, "cg_iteration": per_iter}
 
 
-def cpu_baseline(p, tol, budget_s=20.0):
-    """Oracle (FP64 matrix-free CG, one BLAS thread) on a bounded column sample."""
+def _roof(name, n, ms, alg, bound="hbm"):
+    avg = ms / max(n, 1)
+    if bound == "hbm":
+        ach = alg / (avg * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "avg_launch_us": round(avg * 1e3, 2), "launches": n, "algorithmic_bytes_per_launch": int(alg)}
+    ach = alg / (avg * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / BF16_PEAK_TFLOPS, 5), "traffic": None, "kernel": name,
+            "avg_launch_us": round(avg * 1e3, 2), "launches": n, "algorithmic_flops_per_launch": int(alg)}
+
+
+def _kernel_ms(prof):
+    return {k2: [n2, round(m2, 3)] for k2, (n2, m2) in prof.items() if n2}
+
+
+def _upload(p, dev):
+    import torch
+    return tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (p.edge_ptr, p.edge_vtx, p.w))
+
+
+def _line(metric, value, unit, steps, warmup, ms, dtype, config, roof, extra=None, higher=True):
+    out = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms, 4), "higher_is_better": higher, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roof}
+    if extra:
+        out.update(extra)
+    return out
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [fn() for _ in range(steps)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, res
+
+
+# ------------------------------------------------------------------ workloads
+
+def cpu_cg_baseline(p, tol, budget_s=20.0):
+    """Oracle FP64 matrix-free CG (one thread) on the first columns of Y."""
     from threadpoolctl import threadpool_limits
 
     from oracle import laplacian as lap
@@ -49,15 +108,169 @@ def cpu_baseline(p, tol, budget_s=20.0):
     with threadpool_limits(1):
         t0 = time.perf_counter()
         solve.cg_ranking(op, p.w, p.lam, p.Y[:, :cols], tol=tol)
-        t1 = time.perf_counter()
-        probe = t1 - t0
+        probe = time.perf_counter() - t0
         ncols = int(max(cols, min(p.Y.shape[1], cols * budget_s / max(probe, 1e-3))))
         t0 = time.perf_counter()
         solve.cg_ranking(op, p.w, p.lam, p.Y[:, :ncols], tol=tol)
         dt = time.perf_counter() - t0
-    return {"value": ncols / dt, "unit": "RHS/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {ncols} of {p.Y.shape[1]} columns, same hypergraph, FP64 matrix-free CG "
-                      f"to the same relres, {dt:.1f} s"}
+    return {"value": round(ncols / dt, 2), "unit": "RHS/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {ncols} of {p.Y.shape[1]} columns of the same workload, FP64 matrix-free CG "
+                      f"(eqs. 16-20) to the same relres, one thread, {dt:.1f} s"}
+
+
+def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
+    import torch
+
+    from paper_1908_08281_amd import hgl
+    dev = torch.device("cuda:0")
+    k = p.Y.shape[1]
+    dtype = torch.float32 if mode == "f32" else torch.float64
+    ep, ev, w = _upload(p, dev)
+    h = (hgl.build_laplacian_batched(p.vtx_offsets, p.edge_offsets, ep, ev, w) if p.vtx_offsets is not None
+         else hgl.build_laplacian(ep, ev, w, p.N))
+    Y = torch.from_numpy(p.Y).to(dev, dtype)
+    batched = p.vtx_offsets is not None
+    state = {"ok": True, "iters": []}
+
+    def step():
+        if batched:
+            F, it, rel, st = hgl.cg_solve_batched(h, p.lams, Y, mode=mode, tol=tol, rr_period=rr_period)
+        else:
+            F, it, rel, st = hgl.cg_solve(h, p.lam, Y, mode=mode, tol=tol, rr_period=rr_period)
+        state["ok"] = state["ok"] and st == 0 and bool(np.all(rel <= tol))
+        state["iters"].append(int(it.max()))
+
+    for _ in range(a.warmup):
+        step()
+    state["iters"].clear()
+    hgl.profile(h, True)
+    dt, _ = _timed(step, a.steps, 0)
+    prof = hgl.profile_read(h)
+    hgl.profile(h, False)
+    G = h.G
+    ms = 1e3 * dt / a.steps
+    value = a.steps * k * G / dt if state["ok"] else 0.0
+    elem = 4 if mode == "f32" else 8
+    ab = gather_bytes(p.N, p.E, p.nnz, k, elem)
+    nv, mv = prof["vertex_gather"]
+    ne, me = prof["edge_gather"]
+    roof = _roof("vertex_gather", nv, mv, ab["vertex_gather"]) if mv >= me else _roof("edge_gather", ne, me,
+                                                                                       ab["edge_gather"])
+    it_mean = float(np.mean(state["iters"]))
+    cfg = {"workload": name, "N": p.N, "E": p.E, "nnz": p.nnz, "k": k, "graphs": G,
+           "lambda": float(p.lam), "relres_tol": tol,
+           "cg": f"{mode} vectors, fp64 inner products, residual replacement at convergence checks"
+                 + (f" and every {rr_period}" if rr_period else ""),
+           "iterations": it_mean, "all_columns_converged": state["ok"]}
+    extra = {"cg_iteration_gbs": round(ab["cg_iteration"] * it_mean / (ms * 1e-3) / 1e9, 1),
+             "kernel_ms": _kernel_ms(prof)}
+    if with_cpu and not a.no_cpu:
+        extra["cpu_baseline"] = cpu_cg_baseline(p, tol) if not batched else None
+    return _line("solved RHS/s at relres 1e-6" if mode == "f32" else "solved RHS/s at relres 1e-10",
+                 value, "RHS/s", a.steps, a.warmup, ms, mode, cfg, roof, extra)
+
+
+def bench_rsvd(a):
+    import torch
+
+    import synth
+    from paper_1908_08281_amd import hgl
+    dev = torch.device("cuda:0")
+    p = synth.tessellated()
+    k, pp, q = 64, 10, 2
+    l = k + pp
+    nb = len(p.blocks) - 1
+    ep, ev, w = _upload(p, dev)
+    h = hgl.build_laplacian(ep, ev, w, p.N)
+    om = torch.from_numpy(synth.gaussian_sketch(p.N, l, 11)[0].view(np.int16).copy()).to(dev)
+    for _ in range(a.warmup):
+        hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om)
+    hgl.profile(h, True)
+    dt, _ = _timed(lambda: hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om), a.steps, 0)
+    prof = hgl.profile_read(h)
+    hgl.profile(h, False)
+    sizes = np.diff(p.blocks).astype(np.float64)
+    gemm_flops = float(np.sum(2.0 * sizes * sizes * l))           # one product A_bb S per block
+    n_g, ms_g = prof["rsvd_gemm"]
+    roof = _roof("rsvd_gemm", n_g, ms_g, gemm_flops, bound="mfma")
+    nbp = np.ceil(sizes / 64) * 64
+    gemm_bytes = float(np.sum(2 * nbp * nbp + 2 * 2 * nbp * 80 + 4 * nbp * 80))
+    hbm = _roof("rsvd_gemm", n_g, ms_g, gemm_bytes)
+    ms = 1e3 * dt / a.steps
+    # refined solve beside it
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    tol = 1e-6 / (1 + 1 / p.lam)
+    t0 = time.perf_counter()
+    F, it, rel, sig, st = hgl.block_rsvd_invert(h, p.lam, p.blocks, Y, k, pp, q, omega=om, refine_tol=tol)
+    torch.cuda.synchronize()
+    t_inv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    F2, it2, rel2, st2 = hgl.cg_solve(h, p.lam, Y, tol=tol)
+    torch.cuda.synchronize()
+    t_cg = time.perf_counter() - t0
+    cfg = {"workload": "block_rsvd", "N": p.N, "blocks": nb, "block_rows": "U[500,1500]", "k": k, "p": pp, "q": q,
+           "sketch": "bf16 A_bb, split-bf16 basis, fp32 accumulation, fp64 CholQR2 and Jacobi"}
+    extra = {"roofline_hbm": hbm, "kernel_ms": _kernel_ms(prof),
+             "refined_solve": {"nrhs": Y.shape[1], "pcg_iters": int(it.max()), "seconds": round(t_inv, 4),
+                               "converged": st == 0 and bool(np.all(rel <= tol)),
+                               "plain_cg_iters": int(it2.max()), "plain_cg_seconds": round(t_cg, 4)}}
+    if not a.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import laplacian as lap
+        from oracle import rsvd
+        op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
+        vals = synth.gaussian_sketch(p.N, l, 11)[1]
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            done = 0
+            for b in range(nb):
+                o0, o1 = p.blocks[b], p.blocks[b + 1]
+                P = np.zeros((p.N, o1 - o0))
+                P[o0:o1] = np.eye(o1 - o0)
+                Ab = op.adjacency_apply(P)[o0:o1]
+                rsvd.randomized_svd(Ab, vals[o0:o1], q)
+                done += 1
+                if time.perf_counter() - t0 > 20.0:
+                    break
+            dtc = time.perf_counter() - t0
+        extra["cpu_baseline"] = {"value": round(done / dtc, 3), "unit": "blocks/s", "cores": 1, "kind": "oracle",
+                                 "sample": f"first {done} of {nb} blocks, FP64 Algorithm 1 with Householder QR "
+                                           f"(block extraction included), one thread, {dtc:.1f} s"}
+    return _line("rSVD blocks/s", a.steps * nb / dt, "blocks/s", a.steps, a.warmup, ms, "bf16", cfg, roof, extra)
+
+
+def bench_learn(a):
+    import torch
+
+    import synth
+    from paper_1908_08281_amd import hgl
+    from paper_1908_08281_amd.learn import learn_weights
+    dev = torch.device("cuda:0")
+    p = synth.weight_learning()
+    mu = 0.01
+    k = p.Y.shape[1]
+    ep, ev, w = _upload(p, dev)
+    h = hgl.build_laplacian(ep, ev, w, p.N)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    tol = 1e-6 / (1 + 1 / p.lam)
+    w0 = w.clone()
+    wl, recs = learn_weights(h, Y, p.lam, mu, max(a.warmup, 1), w0, tol=tol, history=True)
+    eta = recs[0]["eta"]
+    hgl.profile(h, True)
+    t0 = time.perf_counter()
+    wl, recs = learn_weights(h, Y, p.lam, mu, a.steps, wl, eta=eta, tol=tol, history=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = hgl.profile_read(h)
+    hgl.profile(h, False)
+    ab = gather_bytes(p.N, p.E, p.nnz, k, 4)
+    nv, mv = prof["vertex_gather"]
+    roof = _roof("vertex_gather", nv, mv, ab["vertex_gather"])
+    cfg = {"workload": "weight_learning", "N": p.N, "E": p.E, "nnz": p.nnz, "k": k, "lambda": p.lam, "mu": mu,
+           "eta": eta, "cg_iters_last": recs[-1]["cg_iters"], "adjoint_iters_last": recs[-1]["adjoint_iters"]}
+    return _line("projected-gradient steps/s", a.steps / dt, "steps/s", a.steps, a.warmup, 1e3 * dt / a.steps,
+                 "f32", cfg, roof, {"kernel_ms": _kernel_ms(prof)})
 
 
 def main():
@@ -66,86 +279,33 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--workload", default="multi_rhs",
+                    help="multi_rhs (default), small, rsvd, learn, batch, or a comma list")
     ap.add_argument("--rr-period", type=int, default=0)
-    ap.add_argument("--mode", default="f32", choices=["f32", "f64"])
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the solves shard by "
-              "columns or graphs with no communication, see the design notes", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}): the solves shard by columns, "
+              "blocks or graphs with no communication, so no multi-GPU figure is produced", file=sys.stderr)
         sys.exit(2)
-
-    import torch
-
     import synth
-    from paper_1908_08281_amd import hgl
-
-    dev = torch.device("cuda:0")
-    p = synth.multi_rhs()
-    tol = 1e-6 / (1 + 1 / p.lam)
-    k = p.Y.shape[1]
-    dtype = torch.float32 if a.mode == "f32" else torch.float64
-    ep, ev, w = (torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (p.edge_ptr, p.edge_vtx, p.w))
-    h = hgl.build_laplacian(ep, ev, w, p.N)
-    Y = torch.from_numpy(p.Y).to(dev, dtype)
-
-    for _ in range(a.warmup):
-        hgl.cg_solve(h, p.lam, Y, mode=a.mode, tol=tol, rr_period=a.rr_period)
-    torch.cuda.synchronize()
-    hgl.profile(h, True)
-    iters_all = []
-    ok = True
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        F, iters, rel, st = hgl.cg_solve(h, p.lam, Y, mode=a.mode, tol=tol, rr_period=a.rr_period)
-        ok = ok and st == 0 and bool(np.all(rel <= tol))
-        iters_all.append(int(iters.max()))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = hgl.profile_read(h)
-    hgl.profile(h, False)
-
-    ms_per_step = 1e3 * dt / a.steps
-    value = a.steps * k / dt if ok else 0.0
-    elem = 4 if a.mode == "f32" else 8
-    ab = algorithmic_bytes(p.N, p.E, p.nnz, k, elem)
-    n_v, ms_v = prof["vertex_gather"]
-    n_e, ms_e = prof["edge_gather"]
-    dom, n_dom, ms_dom = ("vertex_gather", n_v, ms_v) if ms_v >= ms_e else ("edge_gather", n_e, ms_e)
-    avg_ms = ms_dom / max(n_dom, 1)
-    achieved = ab[dom] / (avg_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
-            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": n_dom,
-            "algorithmic_bytes_per_launch": ab[dom]}
-    iters_mean = float(np.mean(iters_all))
-    cg_gbs = ab["cg_iteration"] * iters_mean / (ms_per_step * 1e-3) / 1e9
-    out = {
-        "metric": "solved RHS/s at relres 1e-6",
-        "value": round(value, 1),
-        "unit": "RHS/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if a.mode == "f32" else "f64",
-        "data": "synthetic",
-        "config": {"workload": "multi_rhs_cg", "N": p.N, "E": p.E, "nnz": p.nnz, "k": k,
-                   "lambda": p.lam, "relres_tol": tol, "hyperedge_sizes": "power law 2.1 in [2,200]",
-                   "vertex_popularity": "zipf 1.1", "weights": "dirichlet(1)", "rhs": "binary 2%",
-                   "cg": f"{a.mode} vectors, fp64 dots, residual replacement at claims"
-                         + (f" and every {a.rr_period}" if a.rr_period else ""),
-                   "iterations": iters_mean, "all_columns_converged": ok},
-        "roofline": roof,
-        "cg_iteration_gbs": round(cg_gbs, 1),
-        "kernel_ms": {k2: [n2, round(m2, 3)] for k2, (n2, m2) in prof.items()},
-    }
-    if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p, tol)
-    print(json.dumps(out), flush=True)
+    for wl in a.workload.split(","):
+        if wl == "multi_rhs":
+            p = synth.multi_rhs()
+            out = bench_cg(a, "multi_rhs_cg", p, "f32", 1e-6 / (1 + 1 / p.lam), a.rr_period)
+        elif wl == "small":
+            p = synth.small_plain()
+            out = bench_cg(a, "small_plain_cg_f64", p, "f64", 1e-10)
+        elif wl == "batch":
+            p = synth.batch_of_graphs()
+            out = bench_cg(a, "batched_64_graphs", p, "f32", 1e-6 / (1 + 1 / 0.5))
+        elif wl == "rsvd":
+            out = bench_rsvd(a)
+        elif wl == "learn":
+            out = bench_learn(a)
+        else:
+            print(f"unknown workload {wl}", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

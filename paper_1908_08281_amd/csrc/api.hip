@@ -300,6 +300,7 @@ static void free_handle(hgl_handle* h) {
   for (DevBuf* b : bufs) b->release();
   for (auto& b : h->ws_extra) b.release();
   h->ws_ab.release();
+  if (h->rsvd_free) h->rsvd_free(h->rsvd_ws);
   if (h->pinned_i) hipHostFree(h->pinned_i);
   if (h->pinned_d) hipHostFree(h->pinned_d);
   for (auto& p : h->prof_pending) {

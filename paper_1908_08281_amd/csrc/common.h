@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hgl.h"
+#include "hgl.h"
 
 namespace hgl {
 
@@ -118,6 +118,10 @@ struct hgl_handle {
   hgl::DevBuf ws_extra[8];
   hgl::DevBuf ws_ab;                 // per-graph (1 + 1/lambda, 1/lambda)
   std::vector<double> ab_cache;      // lambdas held in ws_ab
+
+  // block rSVD workspace (owned, freed by rsvd_free)
+  void* rsvd_ws = nullptr;
+  void (*rsvd_free)(void*) = nullptr;
 
   // kernel timing (diagnostics)
   bool prof_on = false;

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -185,19 +186,43 @@ __global__ __launch_bounds__(kBlock) void k_gemm_bf16(BlockMeta bm, const uint16
   const int r0 = t * 64 + wave * 16;
   const int li = lane % 16, kq = lane / 16;
   const uint16_t* Ab = A + bm.aoff[b] + int64_t(r0 + li) * nbp + kq * 8;
-  const uint16_t* Sb = ST + bm.yoff[b] + int64_t(li) * nbp + kq * 8;
+  // S' (hi and lo) is shared by the four waves: stage 128-wide K chunks of it
+  // in LDS (rows padded by 8 elements against bank conflicts)
+  constexpr int KC = 128, KP = KC + 8;
+  __shared__ uint16_t sst[2 * LP * KP];
+  const uint16_t* STb = ST + bm.yoff[b];
   floatx4 acc[NT];
 #pragma unroll
   for (int n = 0; n < NT; ++n) acc[n] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < nbp; k0 += 32) {
-    const bf16x8 a = *reinterpret_cast<const bf16x8*>(Ab + k0);
+  for (int k0 = 0; k0 < nbp; k0 += KC) {
+    const int kc = min(KC, nbp - k0);   // 64 or 128 (nbp is a multiple of 64)
+    const int nsteps = kc / 32;
+    bf16x8 a[KC / 32];
 #pragma unroll
-    for (int n = 0; n < NT; ++n) {
-      const uint16_t* sp = Sb + int64_t(n) * 16 * nbp + k0;
-      const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(sp);
-      const bf16x8 blo = *reinterpret_cast<const bf16x8*>(sp + lo_off);
-      acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bhi, acc[n], 0, 0, 0);
-      acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, blo, acc[n], 0, 0, 0);
+    for (int ks = 0; ks < KC / 32; ++ks)
+      if (ks < nsteps) a[ks] = *reinterpret_cast<const bf16x8*>(Ab + k0 + ks * 32);
+    // cooperative copy: (hi/lo, row j < LP, 8-element segment) -> LDS
+    const int segs = kc / 8;
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * LP * segs; q += kBlock) {
+      const int half = q / (LP * segs), rem = q - half * (LP * segs);
+      const int j = rem / segs, sg = rem - j * segs;
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(STb + half * lo_off + int64_t(j) * nbp + k0 + sg * 8);
+      *reinterpret_cast<bf16x8*>(&sst[(half * LP + j) * KP + sg * 8]) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KC / 32; ++ks) {
+      if (ks < nsteps) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          const uint16_t* sp = &sst[(n * 16 + li) * KP + ks * 32 + kq * 8];
+          const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(sp);
+          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(sp + LP * KP);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], bhi, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], blo, acc[n], 0, 0, 0);
+        }
+      }
     }
   }
   float* Yb = Y + bm.yoff[b];
@@ -228,230 +253,377 @@ __global__ __launch_bounds__(kBlock) void k_gemm_f64(BlockMeta bm, const double*
 
 // ----------------------------------------------------------------- Gram --
 
-// G_b = Y_b' Y_b over the first l columns (FP64 accumulation), rows staged
-// through LDS 32 at a time; thread t owns the upper-triangle pairs t, t+256, ...
-constexpr int kGramPairsPerThread = (kMaxLP * (kMaxLP + 1) / 2 + kBlock - 1) / kBlock;
+// G_b = Y_b' Y_b over the first l columns (FP64 accumulation) in two steps:
+// every 64-row tile of a block writes its partial upper triangle (pair
+// p <-> (i, j), i <= j, row-major over the triangle), then the kernel that
+// consumes G_b (Cholesky or Jacobi, one workgroup per block) sums its tiles'
+// partials in tile order (deterministic).
 
+// LDS[r][c] (row stride lds_ld) <- src[r][c] (row stride src_ld) for r < rows,
+// c < cols, as one flat loop so that several global loads are in flight.
+template <class TS>
+__device__ __forceinline__ void stage_rows(double* lds, int lds_ld, const TS* __restrict__ src, int64_t src_ld,
+                                           int rows, int cols) {
+  const int total = rows * cols;
+#pragma unroll 4
+  for (int q = threadIdx.x; q < total; q += kBlock) {
+    const int r = q / cols, c = q - r * cols;
+    lds[r * lds_ld + c] = double(src[int64_t(r) * src_ld + c]);
+  }
+}
+
+__device__ __forceinline__ void pair_of(int p, int l, int& i, int& j) {
+  int ii = 0, rem = p;
+  while (rem >= l - ii) {
+    rem -= l - ii;
+    ++ii;
+  }
+  i = ii;
+  j = ii + rem;
+}
+
+// t -> (i, m) with m <= i, row-major over a lower triangle.
+__device__ __forceinline__ void tri_of(int t, int& i, int& m) {
+  int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  i = r;
+  m = t - r * (r + 1) / 2;
+}
+
+// One 64-row tile: each thread owns a 4 x 4 block (I <= J) of the Gram matrix
+// and accumulates it over the tile's rows from LDS (8 loads per 16 FMAs).
 template <class TY>
-__global__ __launch_bounds__(kBlock) void k_gram(BlockMeta bm, const TY* __restrict__ Y, double* __restrict__ G) {
-  __shared__ double tile[32 * kMaxLP];
-  const int b = blockIdx.x;
+__global__ __launch_bounds__(kBlock) void k_gram_tiles(BlockMeta bm, const TY* __restrict__ Y,
+                                                       double* __restrict__ part) {
+  __shared__ __align__(16) double tile[64 * kMaxLP];
+  const int b = bm.item_b[blockIdx.x], t = bm.item_t[blockIdx.x];
   const int n = bm.off[b + 1] - bm.off[b];
   const int l = bm.l, LP = bm.LP;
+  const int l4 = (l + 3) & ~3;
   const int npairs = l * (l + 1) / 2;
-  int pi[kGramPairsPerThread], pj[kGramPairsPerThread];
-  double acc[kGramPairsPerThread];
-  int np = 0;
-  for (int p = threadIdx.x; p < npairs; p += kBlock) {
-    int i = 0, rem = p;
-    while (rem >= l - i) {
-      rem -= l - i;
-      ++i;
-    }
-    pi[np] = i;
-    pj[np] = i + rem;
-    acc[np] = 0.0;
-    ++np;
+  const int r0 = t * 64;
+  const int rows = max(0, min(64, n - r0));
+  const TY* Yb = Y + bm.yoff[b] + int64_t(r0) * LP;
+  // columns [l, l4) read as zero
+  for (int q = threadIdx.x; q < rows * l4; q += kBlock) {
+    const int r = q / l4, c = q - r * l4;
+    tile[r * kMaxLP + c] = c < l ? double(Yb[int64_t(r) * LP + c]) : 0.0;
   }
-  const TY* Yb = Y + bm.yoff[b];
-  for (int r0 = 0; r0 < n; r0 += 32) {
-    const int rows = min(32, n - r0);
-    __syncthreads();
-    for (int q = threadIdx.x; q < rows * l; q += kBlock) {
-      const int rr = q / l, cc = q % l;
-      tile[rr * kMaxLP + cc] = double(Yb[int64_t(r0 + rr) * LP + cc]);
-    }
-    __syncthreads();
+  __syncthreads();
+  double* out = part + int64_t(blockIdx.x) * npairs;
+  const int nb4 = l4 / 4, nblk = nb4 * (nb4 + 1) / 2;
+  for (int q = threadIdx.x; q < nblk; q += kBlock) {
+    int J, I;
+    tri_of(q, J, I);
+    double acc[4][4];
 #pragma unroll
-    for (int a = 0; a < kGramPairsPerThread; ++a) {
-      if (a < np) {
-        double sacc = acc[a];
-        for (int rr = 0; rr < rows; ++rr) sacc += tile[rr * kMaxLP + pi[a]] * tile[rr * kMaxLP + pj[a]];
-        acc[a] = sacc;
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    for (int rr = 0; rr < rows; ++rr) {
+      const double* row = tile + rr * kMaxLP;
+      double a[4], c[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        a[x] = row[4 * I + x];
+        c[x] = row[4 * J + x];
       }
-    }
-  }
-  double* Gb = G + int64_t(b) * LP * LP;
 #pragma unroll
-  for (int a = 0; a < kGramPairsPerThread; ++a) {
-    if (a < np) {
-      Gb[pi[a] * LP + pj[a]] = acc[a];
-      Gb[pj[a] * LP + pi[a]] = acc[a];
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * c[y];
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int i = 4 * I + x;
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int j = 4 * J + y;
+        if (i <= j && j < l) out[i * l - i * (i - 1) / 2 + (j - i)] = acc[x][y];
+      }
     }
   }
 }
 
-// ------------------------------------------------------ Cholesky, inverse --
+// Threads of the dense per-block kernels (Cholesky, Jacobi): one workgroup per
+// diagonal block, 16 waves, so that one step of their l-step loops is a
+// single pass of independent updates between two barriers.
+constexpr int kDense = 1024;
 
-// In LDS: L = chol(G) (lower), then Linv = L^-1 (lower), written to Li.
+// A (l x l in LDS, row-major) <- G_b: the block's tile partials summed in tile
+// order (deterministic), upper triangle mirrored.
+__device__ __forceinline__ void stage_gram(const BlockMeta& bm, const int32_t* __restrict__ item0,
+                                           const double* __restrict__ part, int b, double* A) {
+  const int l = bm.l, npairs = l * (l + 1) / 2;
+  const int i0 = item0[b], i1 = item0[b + 1];
+  for (int p = threadIdx.x; p < npairs; p += kDense) {
+    double sacc = 0.0;
+#pragma unroll 8
+    for (int it = i0; it < i1; ++it) sacc += part[int64_t(it) * npairs + p];
+    int i, j;
+    pair_of(p, l, i, j);
+    A[i * l + j] = sacc;
+    A[j * l + i] = sacc;
+  }
+}
+
+// L^-1 of the Cholesky factor of G_b = Y_b' Y_b (summed from the Gram tile
+// partials), written to Li (LP x LP, lower, zero padded).
+// One elimination on [G | I] with unscaled pivots: step j subtracts
+// A[i][j] A[m][j] / A[j][j] from the trailing triangle of G (m > j) and
+// A[i][j] B[j][c] / A[j][j] from the rows i > j of B (c <= j).  Afterwards
+// L[i][j] = A[i][j] / sqrt(A[j][j]) and L^-1[i][c] = B[i][c] / sqrt(A[i][i]).
+// Every thread owns fixed entries of both lower triangles and keeps them in
+// registers; step j reads only column j of A, row j of B and the pivot, which
+// it does not write, so each step is one barrier.
 // A non-positive or non-finite pivot triggers one retry with the shift
 // 11 (n l + l (l+1)) u trace(G) (shifted CholQR, Fukaya et al. 2020); a
 // second failure sets fail[b].
-__global__ __launch_bounds__(kBlock) void k_chol_inv(BlockMeta bm, const double* __restrict__ G,
-                                                     double* __restrict__ Li, int32_t* __restrict__ fail) {
+constexpr int kOwn = (kMaxLP * (kMaxLP + 1) / 2 + kDense - 1) / kDense;  // entries per thread
+__global__ __launch_bounds__(kDense) void k_chol_inv(BlockMeta bm, const int32_t* __restrict__ item0,
+                                                     const double* __restrict__ part, double* __restrict__ Li,
+                                                     int32_t* __restrict__ fail) {
   extern __shared__ double sm[];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x, tid = threadIdx.x;
   const int l = bm.l, LP = bm.LP;
   const int n = bm.off[b + 1] - bm.off[b];
-  double* L = sm;             // l x l
-  double* X = sm + l * l;     // l x l
-  __shared__ int s_bad;
+  const int ntri = l * (l + 1) / 2;
+  double* A = sm;             // l x l, row-major
+  double* B = sm + l * l;     // l x l, row-major (lower triangle used)
   __shared__ double s_tr;
-  const double* Gb = G + int64_t(b) * LP * LP;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    if (threadIdx.x == 0) {
-      double tr = 0.0;
-      for (int i = 0; i < l; ++i) tr += Gb[i * LP + i];
-      s_tr = tr;
-      s_bad = 0;
+  int oi[kOwn], om[kOwn];     // owned (row, column), column <= row
+#pragma unroll
+  for (int u = 0; u < kOwn; ++u) {
+    const int t = tid + u * kDense;
+    if (t < ntri) tri_of(t, oi[u], om[u]);
+    else oi[u] = om[u] = -1;
+  }
+  double a[kOwn], bx[kOwn];
+  for (int attempt = 0;; ++attempt) {
+    stage_gram(bm, item0, part, b, A);
+    __syncthreads();
+    double shift = 0.0;
+    if (attempt > 0) {
+      if (tid < kWave) {
+        double t = 0.0;
+        for (int i = tid; i < l; i += kWave) t += A[i * l + i];
+        for (int o2 = 32; o2 >= 1; o2 >>= 1) t += __shfl_xor(t, o2, kWave);
+        if (tid == 0) s_tr = t;
+      }
+      __syncthreads();
+      shift = 11.0 * (double(n) * l + double(l) * (l + 1)) * 1.1102230246251565e-16 * s_tr;
+    }
+#pragma unroll
+    for (int u = 0; u < kOwn; ++u) {
+      a[u] = bx[u] = 0.0;
+      if (oi[u] >= 0) {
+        a[u] = A[oi[u] * l + om[u]] + (oi[u] == om[u] ? shift : 0.0);
+        bx[u] = oi[u] == om[u] ? 1.0 : 0.0;
+      }
     }
     __syncthreads();
-    const double shift = attempt == 0 ? 0.0 : 11.0 * (double(n) * l + double(l) * (l + 1)) * 1.1102230246251565e-16 * s_tr;
-    for (int q = threadIdx.x; q < l * l; q += kBlock) {
-      const int i = q / l, j = q % l;
-      L[q] = Gb[i * LP + j] + (i == j ? shift : 0.0);
-    }
+#pragma unroll
+    for (int u = 0; u < kOwn; ++u)
+      if (oi[u] >= 0) {
+        A[oi[u] * l + om[u]] = a[u];
+        B[oi[u] * l + om[u]] = bx[u];
+      }
     __syncthreads();
+    bool ok = true;
     for (int j = 0; j < l; ++j) {
-      if (threadIdx.x == 0) {
-        const double piv = L[j * l + j];
-        if (!(piv > 0.0) || !isfinite(piv)) s_bad = 1;
-        L[j * l + j] = sqrt(fmax(piv, 0.0));
+      // every thread reads the same pivot, so the exit is uniform
+      const double piv = A[j * l + j];
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        ok = false;
+        break;
       }
-      __syncthreads();
-      if (s_bad) break;
-      const double d = L[j * l + j];
-      for (int i = j + 1 + threadIdx.x; i < l; i += kBlock) L[i * l + j] /= d;
-      __syncthreads();
-      const int m = l - j - 1;  // trailing (m x m) lower triangle
-      for (int q = threadIdx.x; q < m * m; q += kBlock) {
-        const int i = j + 1 + q / m, c = j + 1 + q % m;
-        if (c <= i) L[i * l + c] -= L[i * l + j] * L[c * l + j];
+      const double inv = 1.0 / piv;
+      double ca[kOwn], cm[kOwn], rb[kOwn];
+#pragma unroll
+      for (int u = 0; u < kOwn; ++u) {
+        const int i = oi[u], m = om[u];
+        const bool live = i > j;   // rows below the pivot only
+        ca[u] = live ? A[i * l + j] : 0.0;
+        cm[u] = (live && m > j) ? A[m * l + j] : 0.0;
+        rb[u] = (live && m <= j) ? B[j * l + m] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kOwn; ++u) {
+        const int i = oi[u], m = om[u];
+        if (i > j) {
+          if (m > j) {
+            a[u] -= ca[u] * cm[u] * inv;
+            A[i * l + m] = a[u];
+          } else {
+            bx[u] -= ca[u] * rb[u] * inv;
+            B[i * l + m] = bx[u];
+          }
+        }
       }
       __syncthreads();
     }
-    __syncthreads();
-    if (!s_bad) break;
-    __syncthreads();
-  }
-  if (s_bad) {
-    if (threadIdx.x == 0) fail[b] = 1;
-    return;
-  }
-  // X = L^-1 by forward substitution, one column per thread
-  for (int cidx = threadIdx.x; cidx < l; cidx += kBlock) {
-    for (int i = 0; i < l; ++i) X[i * l + cidx] = 0.0;
-    for (int i = cidx; i < l; ++i) {
-      double sacc = (i == cidx) ? 1.0 : 0.0;
-      for (int m2 = cidx; m2 < i; ++m2) sacc -= L[i * l + m2] * X[m2 * l + cidx];
-      X[i * l + cidx] = sacc / L[i * l + i];
+    if (ok) break;
+    if (attempt == 1) {
+      if (tid == 0) fail[b] = 1;
+      return;
     }
+    __syncthreads();
   }
-  __syncthreads();
   double* Lb = Li + int64_t(b) * LP * LP;
-  for (int q = threadIdx.x; q < LP * LP; q += kBlock) {
-    const int i = q / LP, j = q % LP;
-    Lb[q] = (i < l && j < l) ? X[i * l + j] : 0.0;
+  for (int q = tid; q < LP * LP; q += kDense) {
+    const int i = q / LP, c = q - i * LP;
+    Lb[q] = (i < l && c <= i) ? B[i * l + c] / sqrt(A[i * l + i]) : 0.0;
   }
 }
 
 // S = Y L^-T on a 64-row tile: S[r][j] = sum_{i<=j} Y[r][i] Linv[j][i] (j < l),
 // zero for j >= l and rows >= n_b.  Writes S (row-major) and ST (transposed,
-// the next GEMM operand: BF16 in the BF16 mode).
-template <class TY, class TST>
+// the next GEMM operand: BF16 hi/lo pair in the BF16 mode).  Thread (g, h)
+// owns rows g + 16x (x < 4) and columns h*CP + c (c < CP = LP/16); Y rows
+// sit in LDS at an odd stride so the 16 rows a wave reads hit distinct banks.
+template <class TY, class TST, int LP>
 __global__ __launch_bounds__(kBlock) void k_apply_rinv(BlockMeta bm, const TY* __restrict__ Y,
                                                        const double* __restrict__ Li, TY* __restrict__ S,
                                                        TST* __restrict__ ST, int64_t lo_off) {
-  extern __shared__ double sm[];
+  constexpr int CP = LP / 16, LDY = LP + 1;
+  __shared__ double Lt[LP * LP];       // Linv, row-major, zero above the diagonal and beyond l
+  __shared__ double Yt[64 * LDY];
   const int b = bm.item_b[blockIdx.x], t = bm.item_t[blockIdx.x];
   const int n = bm.off[b + 1] - bm.off[b], nbp = bm.nbp[b];
-  const int l = bm.l, LP = bm.LP;
-  double* Lt = sm;                  // l x l
-  double* Yt = sm + l * l;          // 64 x l
-  const double* Lb = Li + int64_t(b) * LP * LP;
-  for (int q = threadIdx.x; q < l * l; q += kBlock) Lt[q] = Lb[(q / l) * LP + q % l];
-  const TY* Yb = Y + bm.yoff[b];
-  for (int q = threadIdx.x; q < 64 * l; q += kBlock) {
-    const int r = t * 64 + q / l;
-    Yt[q] = r < n ? double(Yb[int64_t(r) * LP + q % l]) : 0.0;
-  }
+  const int l = bm.l;
+  stage_rows(Lt, LP, Li + int64_t(b) * LP * LP, LP, LP, LP);
+  // rows beyond n_b are zero in Y (zero rows of the padded A_bb)
+  stage_rows(Yt, LDY, Y + bm.yoff[b] + int64_t(t) * 64 * LP, LP, 64, LP);
   __syncthreads();
+  const int g = threadIdx.x % 16, h = threadIdx.x / 16;
+  const int j0 = h * CP;
+  double acc[4][CP];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int c = 0; c < CP; ++c) acc[x][c] = 0.0;
+  const int iend = min(l, j0 + CP);   // Linv[j][i] = 0 for i > j
+  for (int i = 0; i < iend; ++i) {
+    double y[4], lv[CP];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) y[x] = Yt[(g + 16 * x) * LDY + i];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) lv[c] = Lt[(j0 + c) * LP + i];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int c = 0; c < CP; ++c) acc[x][c] += y[x] * lv[c];
+  }
   TY* Sb = S + bm.yoff[b];
   TST* STb = ST + bm.yoff[b];
-  for (int q = threadIdx.x; q < 64 * LP; q += kBlock) {
-    const int rr = q % 64, j = q / 64;  // consecutive threads: consecutive rows (coalesced ST)
-    const int r = t * 64 + rr;
-    double acc = 0.0;
-    if (j < l && r < n) {
-      const double* yr = Yt + rr * l;
-      const double* lj = Lt + j * l;
-      for (int i = 0; i <= j; ++i) acc += yr[i] * lj[i];
-    }
-    Sb[int64_t(r) * LP + j] = TY(acc);
-    if constexpr (sizeof(TST) == 2) {
-      // hi + lo BF16 pair (the lo half lives y_elems further on)
-      const float f = float(acc);
-      const uint16_t hi = f32_to_bf16_rne(f);
-      STb[int64_t(j) * nbp + r] = hi;
-      STb[lo_off + int64_t(j) * nbp + r] = f32_to_bf16_rne(f - bf16_to_f32(hi));
-    } else {
-      STb[int64_t(j) * nbp + r] = acc;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int r = t * 64 + g + 16 * x;
+    const bool live = r < n;
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      const int j = j0 + c;
+      const double v = (live && j < l) ? acc[x][c] : 0.0;
+      Sb[int64_t(r) * LP + j] = TY(v);
+      if constexpr (sizeof(TST) == 2) {
+        // hi + lo BF16 pair (the lo half lives lo_off elements further on)
+        const float f = float(v);
+        const uint16_t hi = f32_to_bf16_rne(f);
+        STb[int64_t(j) * nbp + r] = hi;
+        STb[lo_off + int64_t(j) * nbp + r] = f32_to_bf16_rne(f - bf16_to_f32(hi));
+      } else {
+        STb[int64_t(j) * nbp + r] = v;
+      }
     }
   }
 }
 
 // --------------------------------------------------------------- Jacobi --
 
-// Eigen-decomposition of the symmetric l x l matrix G_b (= B B') by parallel
-// cyclic Jacobi (round-robin pairing: l/2 disjoint rotations per round, l-1
-// rounds per sweep; rotation of Golub & Van Loan, sym.schur2).  Writes the k
-// largest eigenvalues' square roots (singular values of B, decreasing) and
-// the matching eigenvectors (columns of Ut, l x k).
-__global__ __launch_bounds__(kBlock) void k_jacobi(BlockMeta bm, const double* __restrict__ G,
-                                                   double* __restrict__ sig, double* __restrict__ Ut,
-                                                   int max_sweeps) {
+// Eigen-decomposition of the symmetric l x l matrix G_b (= B B', summed from
+// the Gram tile partials) by parallel cyclic Jacobi: round-robin pairing
+// (circle method) gives l/2 disjoint index pairs per round, l-1 rounds per
+// sweep; each pair's rotation is the one of Golub & Van Loan, sym.schur2.
+// With J the product of a round's disjoint rotations, J'AJ restricted to the
+// pair blocks (a, b) is J_a' A_ab J_b, so a round is one pass over independent
+// 2 x 2 blocks, done in place (upper blocks a <= b, mirrored), plus V <- V J
+// on the same blocks of V.  Writes the k largest eigenvalues' square roots
+// (singular values of B, decreasing) and the matching eigenvectors (columns
+// of Ut, l x k).
+// kJT = 2 x 2 blocks per thread and round: 3 covers l <= 80, 4 covers l <= 96.
+template <int kJT>
+__global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* __restrict__ item0,
+                                                   const double* __restrict__ part, double* __restrict__ sig,
+                                                   double* __restrict__ Ut, int max_sweeps) {
   extern __shared__ double sm[];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x, tid = threadIdx.x;
   const int l = bm.l, LP = bm.LP, kk = bm.kk;
-  const int ne = l + (l & 1);  // even count (a dummy index pairs with the odd one out)
+  const int ne = l + (l & 1);  // even count (a dummy index l pairs with the odd one out)
   const int half = ne / 2;
-  double* A = sm;              // l x l
-  double* V = sm + l * l;      // l x l
-  double* cs = sm + 2 * l * l; // [half][2]
-  int* pp = reinterpret_cast<int*>(cs + 2 * half);  // [half][2]
-  __shared__ double s_off[4], s_diag[4];
-  const double* Gb = G + int64_t(b) * LP * LP;
-  for (int q = threadIdx.x; q < l * l; q += kBlock) {
-    const int i = q / l, j = q % l;
-    A[q] = Gb[i * LP + j];
-    V[q] = (i == j) ? 1.0 : 0.0;
-  }
+  double* A = sm;                                            // l x l
+  double* V = sm + l * l;                                    // l x l
+  double2* rot = reinterpret_cast<double2*>(sm + 2 * l * l);  // [half] (c, s)
+  int2* pq = reinterpret_cast<int2*>(rot + half);            // [half] (p, q), p < q
+  int* rank = reinterpret_cast<int*>(pq + half);             // [l]
+  constexpr int NW = kDense / kWave;
+  __shared__ double s_off[NW], s_dg[NW];
+  stage_gram(bm, item0, part, b, A);
+  for (int q = tid; q < l * l; q += kDense) V[q] = (q / l == q % l) ? 1.0 : 0.0;
   __syncthreads();
+  const int nA = half * (half + 1) / 2, nT = nA + half * half;
+  // this thread's blocks t = tid + u * kDense: A blocks (a <= b) first, then
+  // V blocks (row pair a, column pair b); tk_a = -1 for none
+  int tk_a[kJT], tk_b[kJT];
+  bool tk_isA[kJT];
+#pragma unroll
+  for (int u = 0; u < kJT; ++u) {
+    const int t = tid + u * kDense;
+    tk_a[u] = tk_b[u] = -1;
+    tk_isA[u] = false;
+    if (t < nA) {
+      tri_of(t, tk_b[u], tk_a[u]);
+      tk_isA[u] = true;
+    } else if (t < nT) {
+      tk_a[u] = (t - nA) / half;
+      tk_b[u] = (t - nA) - tk_a[u] * half;
+    }
+  }
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // convergence: off-diagonal mass against the diagonal (fixed-order sums)
     double off = 0.0, dg = 0.0;
-    for (int q = threadIdx.x; q < l * l; q += kBlock) {
-      const int i = q / l, j = q % l;
-      if (i != j) off += A[q] * A[q]; else dg += A[q] * A[q];
+    for (int q = tid; q < l * l; q += kDense) {
+      const double v = A[q] * A[q];
+      if (q / l != q % l) off += v; else dg += v;
     }
     for (int o2 = 32; o2 >= 1; o2 >>= 1) {
       off += __shfl_xor(off, o2, kWave);
       dg += __shfl_xor(dg, o2, kWave);
     }
-    if (threadIdx.x % kWave == 0) {
-      s_off[threadIdx.x / kWave] = off;
-      s_diag[threadIdx.x / kWave] = dg;
+    if (tid % kWave == 0) {
+      s_off[tid / kWave] = off;
+      s_dg[tid / kWave] = dg;
     }
     __syncthreads();
-    const double off_t = ((s_off[0] + s_off[1]) + s_off[2]) + s_off[3];
-    const double dg_t = ((s_diag[0] + s_diag[1]) + s_diag[2]) + s_diag[3];
+    double off_t = 0.0, dg_t = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      off_t += s_off[w];
+      dg_t += s_dg[w];
+    }
     __syncthreads();
-    if (off_t <= 1e-30 * dg_t) break;
+    // off-diagonal Frobenius norm below 1e-13 of the diagonal's: eigenvalue
+    // errors are then of order off^2/gap, far below the FP64 CholQR noise
+    if (off_t <= 1e-26 * dg_t) break;
     for (int round = 0; round < ne - 1; ++round) {
-      for (int pr = threadIdx.x; pr < half; pr += kBlock) {
+      if (tid < half) {
         // circle method: slot 0 fixed, the others rotate
-        auto at = [&](int slot) { return slot == 0 ? 0 : 1 + ((slot - 1 + round) % (ne - 1)); };
-        int p = at(pr), q = at(ne - 1 - pr);
+        auto at = [&](int slot) {
+          if (slot == 0) return 0;
+          int v = slot - 1 + round;
+          if (v >= ne - 1) v -= ne - 1;
+          return 1 + v;
+        };
+        int p = at(tid), q = at(ne - 1 - tid);
         if (p > q) {
           const int tmp = p;
           p = q;
@@ -467,121 +639,191 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(BlockMeta bm, const double* _
             s = tt * c;
           }
         }
-        pp[2 * pr] = p;
-        pp[2 * pr + 1] = q;
-        cs[2 * pr] = c;
-        cs[2 * pr + 1] = s;
+        rot[tid] = make_double2(c, s);
+        pq[tid] = make_int2(p, q);
       }
       __syncthreads();
-      // rows: A <- J' A
-      for (int w = threadIdx.x; w < half * l; w += kBlock) {
-        const int pr = w / l, col = w % l;
-        const int p = pp[2 * pr], q = pp[2 * pr + 1];
-        if (q >= l) continue;
-        const double c = cs[2 * pr], s = cs[2 * pr + 1];
-        const double ap = A[p * l + col], aq = A[q * l + col];
-        A[p * l + col] = c * ap - s * aq;
-        A[q * l + col] = s * ap + c * aq;
+      // phase 2: this thread's blocks, all loads before any store (the
+      // blocks are disjoint; the compiler cannot see that)
+      int2 PA[kJT], PB[kJT];
+      double2 RA[kJT], RB[kJT];
+      double x[kJT][4];
+#pragma unroll
+      for (int u = 0; u < kJT; ++u) {
+        PA[u] = tk_a[u] >= 0 ? pq[tk_a[u]] : make_int2(0, l);
+        PB[u] = tk_a[u] >= 0 ? pq[tk_b[u]] : make_int2(0, l);
+        RA[u] = (tk_a[u] >= 0 && tk_isA[u]) ? rot[tk_a[u]] : make_double2(1.0, 0.0);
+        RB[u] = tk_a[u] >= 0 ? rot[tk_b[u]] : make_double2(1.0, 0.0);
       }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int w = threadIdx.x; w < half * l; w += kBlock) {
-        const int pr = w / l, row = w % l;
-        const int p = pp[2 * pr], q = pp[2 * pr + 1];
-        if (q >= l) continue;
-        const double c = cs[2 * pr], s = cs[2 * pr + 1];
-        const double ap = A[row * l + p], aq = A[row * l + q];
-        A[row * l + p] = c * ap - s * aq;
-        A[row * l + q] = s * ap + c * aq;
-        const double vp = V[row * l + p], vq = V[row * l + q];
-        V[row * l + p] = c * vp - s * vq;
-        V[row * l + q] = s * vp + c * vq;
+#pragma unroll
+      for (int u = 0; u < kJT; ++u) {
+        const double* M = tk_isA[u] ? A : V;
+        const bool q0 = PA[u].y < l, q1 = PB[u].y < l, live = tk_a[u] >= 0;
+        x[u][0] = live ? M[PA[u].x * l + PB[u].x] : 0.0;
+        x[u][1] = (live && q1) ? M[PA[u].x * l + PB[u].y] : 0.0;
+        x[u][2] = (live && q0) ? M[PA[u].y * l + PB[u].x] : 0.0;
+        x[u][3] = (live && q0 && q1) ? M[PA[u].y * l + PB[u].y] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kJT; ++u) {
+        if (tk_a[u] < 0) continue;
+        // rows by J_a' (p' = c p - s q, q' = s p + c q; identity for V), then
+        // columns by J_b
+        const double ca = RA[u].x, sa = RA[u].y, cb = RB[u].x, sb = RB[u].y;
+        const double r00 = ca * x[u][0] - sa * x[u][2], r01 = ca * x[u][1] - sa * x[u][3];
+        const double r10 = sa * x[u][0] + ca * x[u][2], r11 = sa * x[u][1] + ca * x[u][3];
+        const double y00 = cb * r00 - sb * r01, y01 = sb * r00 + cb * r01;
+        const double y10 = cb * r10 - sb * r11, y11 = sb * r10 + cb * r11;
+        const int pa = PA[u].x, qa = PA[u].y, pb = PB[u].x, qb = PB[u].y;
+        const bool q0 = qa < l, q1 = qb < l;
+        if (!tk_isA[u]) {
+          V[pa * l + pb] = y00;
+          if (q1) V[pa * l + qb] = y01;
+          if (q0) V[qa * l + pb] = y10;
+          if (q0 && q1) V[qa * l + qb] = y11;
+        } else if (tk_a[u] == tk_b[u]) {
+          // the pair's own 2 x 2 block: diagonalised; kept exactly symmetric
+          A[pa * l + pa] = y00;
+          if (q0) {
+            A[qa * l + qa] = y11;
+            A[pa * l + qa] = y01;
+            A[qa * l + pa] = y01;
+          }
+        } else {
+          A[pa * l + pb] = y00;
+          A[pb * l + pa] = y00;
+          if (q1) {
+            A[pa * l + qb] = y01;
+            A[qb * l + pa] = y01;
+          }
+          if (q0) {
+            A[qa * l + pb] = y10;
+            A[pb * l + qa] = y10;
+          }
+          if (q0 && q1) {
+            A[qa * l + qb] = y11;
+            A[qb * l + qa] = y11;
+          }
+        }
       }
       __syncthreads();
     }
   }
   // rank by decreasing eigenvalue (ties by index): output the leading kk
-  for (int i = threadIdx.x; i < l; i += kBlock) {
+  for (int i = tid; i < l; i += kDense) {
     const double li = A[i * l + i];
-    int rank = 0;
+    int r = 0;
     for (int j = 0; j < l; ++j) {
       const double lj = A[j * l + j];
-      rank += (lj > li) || (lj == li && j < i);
+      r += (lj > li) || (lj == li && j < i);
     }
-    if (rank < kk) {
-      sig[int64_t(b) * kk + rank] = sqrt(fmax(li, 0.0));
-      for (int r = 0; r < l; ++r) Ut[int64_t(b) * LP * kk + int64_t(r) * kk + rank] = V[r * l + i];
-    }
+    rank[i] = r;
+    if (r < kk) sig[int64_t(b) * kk + r] = sqrt(fmax(li, 0.0));
+  }
+  __syncthreads();
+  for (int q = tid; q < l * l; q += kDense) {
+    const int r = q / l, i = q - r * l;
+    if (rank[i] < kk) Ut[int64_t(b) * LP * kk + int64_t(r) * kk + rank[i]] = V[q];
   }
 }
 
 // U[o_b + r][c] = sum_{i<l} S_b[r][i] Ut_b[i][c], c < kk (global N x kk, FP32).
-template <class TY>
+// Thread (g, h) owns rows g + 16x (x < 4) and columns h*CP + c (c < CP).
+template <class TY, int LP>
 __global__ __launch_bounds__(kBlock) void k_basis(BlockMeta bm, const TY* __restrict__ S,
                                                   const double* __restrict__ Ut, float* __restrict__ U) {
+  constexpr int CP = LP / 16, LDS_ = LP + 1;
+  __shared__ double Ub[LP * LP];     // Ut_b, rows < l, columns < kk (zero beyond)
+  __shared__ double St[64 * LDS_];
   const int b = bm.item_b[blockIdx.x], t = bm.item_t[blockIdx.x];
   const int o = bm.off[b], n = bm.off[b + 1] - o;
-  const int l = bm.l, LP = bm.LP, kk = bm.kk;
-  const double* Ub = Ut + int64_t(b) * LP * kk;
-  const TY* Sb = S + bm.yoff[b];
-  for (int q = threadIdx.x; q < 64 * kk; q += kBlock) {
-    const int r = t * 64 + q / kk, c = q % kk;
+  const int l = bm.l, kk = bm.kk;
+  const double* Utb = Ut + int64_t(b) * LP * kk;
+  for (int q = threadIdx.x; q < l * LP; q += kBlock) {
+    const int i = q / LP, c = q - i * LP;
+    Ub[q] = c < kk ? Utb[int64_t(i) * kk + c] : 0.0;
+  }
+  stage_rows(St, LDS_, S + bm.yoff[b] + int64_t(t) * 64 * LP, LP, 64, l);
+  __syncthreads();
+  const int g = threadIdx.x % 16, h = threadIdx.x / 16;
+  const int c0 = h * CP;
+  if (c0 >= kk) return;
+  double acc[4][CP];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int c = 0; c < CP; ++c) acc[x][c] = 0.0;
+  for (int i = 0; i < l; ++i) {
+    double sv[4], uv[CP];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) sv[x] = St[(g + 16 * x) * LDS_ + i];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) uv[c] = Ub[i * LP + c0 + c];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int c = 0; c < CP; ++c) acc[x][c] += sv[x] * uv[c];
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int r = t * 64 + g + 16 * x;
     if (r >= n) continue;
-    double acc = 0.0;
-    for (int i = 0; i < l; ++i) acc += double(Sb[int64_t(r) * LP + i]) * Ub[int64_t(i) * kk + c];
-    U[int64_t(o + r) * kk + c] = float(acc);
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+      if (c0 + c < kk) U[int64_t(o + r) * kk + c0 + c] = float(acc[x][c]);
   }
 }
 
 // ------------------------------------------------ block preconditioner --
 
-// dT_b = diag(d_b) U_b' R_b for 64 columns of R per launch column slab:
-// d_i = sigma_i / (1 + lambda - sigma_i).  One workgroup per (block, slab).
+// dT_b = diag(d_b) U_b' R_b, d_i = sigma_i / (1 + lambda - sigma_i), in two
+// steps: every (64-row tile, 64-column slab) writes its partial product
+// (kk x 64, FP64), then the tiles of a block are summed in tile order.
 constexpr int kPrecT = 24;  // outputs per thread: kk * 64 <= 256 * kPrecT
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_prec_t(BlockMeta bm, const float* __restrict__ U,
-                                                   const double* __restrict__ sig, double lam,
-                                                   const T* __restrict__ R, int64_t ldr, int nrhs,
-                                                   double* __restrict__ dT) {
-  __shared__ float su[32 * kMaxLP];
-  __shared__ double sr[32 * 64];
-  const int b = blockIdx.x, c0 = blockIdx.y * 64;
+__global__ __launch_bounds__(kBlock) void k_prec_t_tiles(BlockMeta bm, const float* __restrict__ U,
+                                                         const T* __restrict__ R, int64_t ldr, int nrhs,
+                                                         double* __restrict__ part) {
+  __shared__ double su[64 * kMaxLP];
+  __shared__ double sr[64 * 64];
+  const int b = bm.item_b[blockIdx.x], t = bm.item_t[blockIdx.x];
+  const int c0 = blockIdx.y * 64;
   const int o = bm.off[b], n = bm.off[b + 1] - o, kk = bm.kk;
   const int nc = min(64, nrhs - c0);
-  double acc[kPrecT];
-#pragma unroll
-  for (int a = 0; a < kPrecT; ++a) acc[a] = 0.0;
-  for (int r0 = 0; r0 < n; r0 += 32) {
-    const int rows = min(32, n - r0);
-    __syncthreads();
-    for (int q = threadIdx.x; q < rows * kk; q += kBlock) su[q] = U[int64_t(o + r0 + q / kk) * kk + q % kk];
-    for (int q = threadIdx.x; q < rows * 64; q += kBlock) {
-      const int rr = q / 64, cc = q % 64;
-      sr[q] = cc < nc ? double(R[int64_t(o + r0 + rr) * ldr + c0 + cc]) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < kPrecT; ++a) {
-      const int w = threadIdx.x + a * kBlock;
-      if (w < kk * 64) {
-        const int i = w / 64, cc = w % 64;
-        double sacc = acc[a];
-        for (int rr = 0; rr < rows; ++rr) sacc += double(su[rr * kk + i]) * sr[rr * 64 + cc];
-        acc[a] = sacc;
-      }
-    }
-  }
+  const int r0 = t * 64;
+  const int rows = max(0, min(64, n - r0));
+  stage_rows(su, kk, U + int64_t(o + r0) * kk, kk, rows, kk);
+  stage_rows(sr, 64, R + int64_t(o + r0) * ldr + c0, ldr, rows, nc);
+  __syncthreads();
+  double* out = part + (int64_t(blockIdx.x) * gridDim.y + blockIdx.y) * kk * 64;
 #pragma unroll
   for (int a = 0; a < kPrecT; ++a) {
     const int w = threadIdx.x + a * kBlock;
     if (w < kk * 64) {
-      const int i = w / 64, cc = w % 64;
-      if (cc < nc) {
-        const double si = sig[int64_t(b) * kk + i];
-        dT[(int64_t(b) * kk + i) * nrhs + c0 + cc] = acc[a] * si / (1.0 + lam - si);
-      }
+      const int i = w >> 6, cc = w & 63;
+      double sacc = 0.0;
+      if (cc < nc)
+        for (int rr = 0; rr < rows; ++rr) sacc += su[rr * kk + i] * sr[rr * 64 + cc];
+      out[w] = sacc;
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_prec_t_reduce(BlockMeta bm, const int32_t* __restrict__ item0,
+                                                          const double* __restrict__ part, const double* __restrict__ sig,
+                                                          double lam, int nrhs, int slabs, double* __restrict__ dT) {
+  const int b = blockIdx.x;
+  const int kk = bm.kk;
+  const int w = blockIdx.y * kBlock + threadIdx.x;  // over kk * nrhs outputs
+  if (w >= kk * nrhs) return;
+  const int i = w / nrhs, c = w - i * nrhs;
+  const int slab = c >> 6, cc = c & 63;
+  double sacc = 0.0;
+#pragma unroll 8
+  for (int it = item0[b]; it < item0[b + 1]; ++it)
+    sacc += part[(int64_t(it) * slabs + slab) * kk * 64 + i * 64 + cc];
+  const double si = sig[int64_t(b) * kk + i];
+  dT[(int64_t(b) * kk + i) * nrhs + c] = sacc * si / (1.0 + lam - si);
 }
 
 // Z = lambda/(1+lambda) (R + U dT_b) row by row over the CG tiles, with the
@@ -646,17 +888,36 @@ __global__ __launch_bounds__(kBlock) void k_prec_z(BlockMeta bm, int32_t n_tiles
 
 // -------------------------------------------------------------- driver --
 
+// Workspace of the block rSVD; kept by the handle between calls (buffers
+// only grow), so repeated calls allocate nothing.
 struct Rsvd {
   int nb = 0, l = 0, LP = 0, kk = 0;
   bool f64 = false;
-  std::vector<int32_t> off, nbp, item_b, item_t;
+  std::vector<int32_t> off, nbp, item_b, item_t, item0;
   std::vector<int64_t> aoff, yoff;
   int64_t a_elems = 0, y_elems = 0;
   int max_nbp = 0;
   // device
-  DevBuf meta, A, Y, S, ST, G, Li, Ut, sig, fail, omega;
+  DevBuf meta, A, Y, S, ST, Gpart, Li, Ut, sig, fail, omega, U, dT, Tpart;
+  const int32_t* item0_d = nullptr;
   BlockMeta bm{};
 };
+
+static void rsvd_delete(void* p) {
+  Rsvd* R = static_cast<Rsvd*>(p);
+  DevBuf* bufs[] = {&R->meta, &R->A, &R->Y, &R->S, &R->ST, &R->Gpart, &R->Li,
+                    &R->Ut, &R->sig, &R->fail, &R->omega, &R->U, &R->dT, &R->Tpart};
+  for (DevBuf* b : bufs) b->release();
+  delete R;
+}
+
+static Rsvd& rsvd_of(hgl_handle* h) {
+  if (!h->rsvd_ws) {
+    h->rsvd_ws = new Rsvd();
+    h->rsvd_free = &rsvd_delete;
+  }
+  return *static_cast<Rsvd*>(h->rsvd_ws);
+}
 
 static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs, const hgl_rsvd_opts* o,
                       hipStream_t s) {
@@ -666,9 +927,13 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
   R.LP = (R.l + 15) / 16 * 16;
   R.f64 = o->sketch == HGL_SKETCH_F64;
   R.off.assign(offs, offs + n_blocks + 1);
-  R.nbp.resize(n_blocks);
-  R.aoff.resize(n_blocks);
-  R.yoff.resize(n_blocks);
+  R.nbp.assign(n_blocks, 0);
+  R.aoff.assign(n_blocks, 0);
+  R.yoff.assign(n_blocks, 0);
+  R.item_b.clear();
+  R.item_t.clear();
+  R.item0.assign(n_blocks + 1, 0);
+  R.max_nbp = 0;
   int64_t a = 0, y = 0;
   for (int b = 0; b < n_blocks; ++b) {
     const int n = offs[b + 1] - offs[b];
@@ -679,15 +944,17 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
     R.yoff[b] = y;
     a += int64_t(p) * p;
     y += int64_t(p) * R.LP;
+    R.item0[b] = int32_t(R.item_b.size());
     for (int t = 0; t < p / 64; ++t) {
       R.item_b.push_back(b);
       R.item_t.push_back(t);
     }
   }
+  R.item0[n_blocks] = int32_t(R.item_b.size());
   R.a_elems = a;
   R.y_elems = y;
   const size_t nI = R.item_b.size();
-  const size_t meta_bytes = 4 * (n_blocks + 1) + 4 * n_blocks + 8 * 2 * n_blocks + 4 * 2 * nI + 64;
+  const size_t meta_bytes = 4 * (n_blocks + 1) + 4 * n_blocks + 8 * 2 * n_blocks + 4 * 2 * nI + 4 * (n_blocks + 1) + 64;
   HGL_TRY(R.meta.reserve(meta_bytes));
   std::vector<char> host(meta_bytes, 0);
   size_t pos = 0;
@@ -704,6 +971,7 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
   const size_t p_nbp = put(R.nbp.data(), 4 * n_blocks, 4);
   const size_t p_ib = put(R.item_b.data(), 4 * nI, 4);
   const size_t p_it = put(R.item_t.data(), 4 * nI, 4);
+  const size_t p_i0 = put(R.item0.data(), 4 * (n_blocks + 1), 4);
   HGL_TRY(ensure_pinned(h, (pos + 7) / 8 + 8));
   std::memcpy(h->pinned_d, host.data(), pos);
   HGL_HIP(hipMemcpyAsync(R.meta.p, h->pinned_d, pos, hipMemcpyHostToDevice, s));
@@ -713,12 +981,13 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
                    reinterpret_cast<const int32_t*>(base + p_off), reinterpret_cast<const int32_t*>(base + p_nbp),
                    reinterpret_cast<const int64_t*>(base + p_aoff), reinterpret_cast<const int64_t*>(base + p_yoff),
                    reinterpret_cast<const int32_t*>(base + p_ib), reinterpret_cast<const int32_t*>(base + p_it)};
+  R.item0_d = reinterpret_cast<const int32_t*>(base + p_i0);
+  HGL_TRY(R.Gpart.reserve(8 * nI * size_t(R.l) * (R.l + 1) / 2));
   const size_t ea = R.f64 ? 8 : 2, ey = R.f64 ? 8 : 4;
   HGL_TRY(R.A.reserve(ea * R.a_elems));
   HGL_TRY(R.Y.reserve(ey * R.y_elems));
   HGL_TRY(R.S.reserve(ey * R.y_elems));
   HGL_TRY(R.ST.reserve(ea * R.y_elems * (R.f64 ? 1 : 2)));  // BF16: hi and lo halves
-  HGL_TRY(R.G.reserve(8 * size_t(n_blocks) * R.LP * R.LP));
   HGL_TRY(R.Li.reserve(8 * size_t(n_blocks) * R.LP * R.LP));
   HGL_TRY(R.Ut.reserve(8 * size_t(n_blocks) * R.LP * R.kk));
   HGL_TRY(R.sig.reserve(8 * size_t(n_blocks) * R.kk));
@@ -741,34 +1010,42 @@ static int allow_lds(K kernel, size_t bytes) {
   return HGL_OK;
 }
 
+// Calls f(std::integral_constant<int, LP>{}) for the supported padded widths.
+template <class F>
+static int with_lp(int LP, F&& f) {
+  switch (LP) {
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    case 48: return f(std::integral_constant<int, 48>{});
+    case 64: return f(std::integral_constant<int, 64>{});
+    case 80: return f(std::integral_constant<int, 80>{});
+    case 96: return f(std::integral_constant<int, 96>{});
+    default: set_error("unsupported padded sketch width %d", LP); return HGL_EUNSUPPORTED;
+  }
+}
+
 static int launch_gemm(Rsvd& R, hipStream_t s) {
   const int n_items = int(R.item_b.size());
   if (R.f64) {
     hipLaunchKernelGGL(k_gemm_f64, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.A.as<double>(),
                        R.ST.as<double>(), R.Y.as<double>());
   } else {
-    const uint16_t* A = R.A.as<uint16_t>();
-    const uint16_t* ST = R.ST.as<uint16_t>();
-    float* Y = R.Y.as<float>();
-    const int64_t lo = R.y_elems;
-    const dim3 g(n_items), blk(kBlock);
-    switch (R.LP) {
-      case 16: hipLaunchKernelGGL(k_gemm_bf16<16>, g, blk, 0, s, R.bm, A, ST, lo, Y); break;
-      case 32: hipLaunchKernelGGL(k_gemm_bf16<32>, g, blk, 0, s, R.bm, A, ST, lo, Y); break;
-      case 48: hipLaunchKernelGGL(k_gemm_bf16<48>, g, blk, 0, s, R.bm, A, ST, lo, Y); break;
-      case 64: hipLaunchKernelGGL(k_gemm_bf16<64>, g, blk, 0, s, R.bm, A, ST, lo, Y); break;
-      case 80: hipLaunchKernelGGL(k_gemm_bf16<80>, g, blk, 0, s, R.bm, A, ST, lo, Y); break;
-      case 96: hipLaunchKernelGGL(k_gemm_bf16<96>, g, blk, 0, s, R.bm, A, ST, lo, Y); break;
-      default: set_error("unsupported padded sketch width %d", R.LP); return HGL_EUNSUPPORTED;
-    }
+    HGL_TRY(with_lp(R.LP, [&](auto c) {
+      constexpr int LP = decltype(c)::value;
+      hipLaunchKernelGGL(k_gemm_bf16<LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.A.as<uint16_t>(),
+                         R.ST.as<uint16_t>(), R.y_elems, R.Y.as<float>());
+      return HGL_OK;
+    }));
   }
   HGL_HIP(hipGetLastError());
   return HGL_OK;
 }
 
+// Gram tile partials of Yb (summed by the consuming kernel).
 template <class TY>
 static int launch_gram(Rsvd& R, const DevBuf& Yb, hipStream_t s) {
-  hipLaunchKernelGGL((k_gram<TY>), dim3(R.nb), dim3(kBlock), 0, s, R.bm, Yb.as<TY>(), R.G.as<double>());
+  const int n_items = int(R.item_b.size());
+  hipLaunchKernelGGL((k_gram_tiles<TY>), dim3(n_items), dim3(kBlock), 0, s, R.bm, Yb.as<TY>(), R.Gpart.as<double>());
   HGL_HIP(hipGetLastError());
   return HGL_OK;
 }
@@ -778,18 +1055,20 @@ template <class TY, class TST>
 static int cholqr2(hgl_handle* h, Rsvd& R, hipStream_t s) {
   const int n_items = int(R.item_b.size());
   const size_t lds_chol = sizeof(double) * 2 * R.l * R.l;
-  const size_t lds_rinv = sizeof(double) * (R.l * R.l + 64 * R.l);
   HGL_TRY(allow_lds(k_chol_inv, lds_chol));
-  HGL_TRY(allow_lds(k_apply_rinv<TY, TST>, lds_rinv));
   prof_begin(h, kProfQr, s);
   for (int pass = 0; pass < 2; ++pass) {
     DevBuf& in = pass == 0 ? R.Y : R.S;
     DevBuf& out = pass == 0 ? R.S : R.Y;
     HGL_TRY(launch_gram<TY>(R, in, s));
-    hipLaunchKernelGGL(k_chol_inv, dim3(R.nb), dim3(kBlock), lds_chol, s, R.bm, R.G.as<double>(),
+    hipLaunchKernelGGL(k_chol_inv, dim3(R.nb), dim3(kDense), lds_chol, s, R.bm, R.item0_d, R.Gpart.as<double>(),
                        R.Li.as<double>(), R.fail.as<int32_t>());
-    hipLaunchKernelGGL((k_apply_rinv<TY, TST>), dim3(n_items), dim3(kBlock), lds_rinv, s, R.bm, in.as<TY>(),
-                       R.Li.as<double>(), out.as<TY>(), R.ST.as<TST>(), R.y_elems);
+    HGL_TRY(with_lp(R.LP, [&](auto c) {
+      constexpr int LP = decltype(c)::value;
+      hipLaunchKernelGGL((k_apply_rinv<TY, TST, LP>), dim3(n_items), dim3(kBlock), 0, s, R.bm, in.as<TY>(),
+                         R.Li.as<double>(), out.as<TY>(), R.ST.as<TST>(), R.y_elems);
+      return HGL_OK;
+    }));
     HGL_HIP(hipGetLastError());
   }
   prof_end(h, s);
@@ -851,9 +1130,11 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
   prof_begin(h, kProfEig, s);
   HGL_TRY(launch_gram<TY>(R, R.Y, s));
   const int half = (R.l + (R.l & 1)) / 2;
-  const size_t lds_j = sizeof(double) * (2 * R.l * R.l + 2 * half) + sizeof(int) * 2 * half + 16;
-  HGL_TRY(allow_lds(k_jacobi, lds_j));
-  hipLaunchKernelGGL(k_jacobi, dim3(R.nb), dim3(kBlock), lds_j, s, R.bm, R.G.as<double>(), R.sig.as<double>(),
+  const size_t lds_j = sizeof(double) * (2 * R.l * R.l + 2 * half) + sizeof(int) * (2 * half + R.l);
+  const bool wide = half * (half + 1) / 2 + half * half > 3 * kDense;
+  auto jac = wide ? &k_jacobi<4> : &k_jacobi<3>;
+  HGL_TRY(allow_lds(jac, lds_j));
+  hipLaunchKernelGGL(jac, dim3(R.nb), dim3(kDense), lds_j, s, R.bm, R.item0_d, R.Gpart.as<double>(), R.sig.as<double>(),
                      R.Ut.as<double>(), 30);
   HGL_HIP(hipGetLastError());
   prof_end(h, s);
@@ -878,12 +1159,16 @@ static int check_opts(hgl_handle* h, int n_blocks, const int32_t* offs, const hg
 
 static int finish_rsvd(hgl_handle* h, Rsvd& R, float* U_out, double* sigma_out, hipStream_t s) {
   const int n_items = int(R.item_b.size());
-  if (R.f64)
-    hipLaunchKernelGGL((k_basis<double>), dim3(n_items), dim3(kBlock), 0, s, R.bm, R.S.as<double>(),
-                       R.Ut.as<double>(), U_out);
-  else
-    hipLaunchKernelGGL((k_basis<float>), dim3(n_items), dim3(kBlock), 0, s, R.bm, R.S.as<float>(),
-                       R.Ut.as<double>(), U_out);
+  HGL_TRY(with_lp(R.LP, [&](auto c) {
+    constexpr int LP = decltype(c)::value;
+    if (R.f64)
+      hipLaunchKernelGGL((k_basis<double, LP>), dim3(n_items), dim3(kBlock), 0, s, R.bm, R.S.as<double>(),
+                         R.Ut.as<double>(), U_out);
+    else
+      hipLaunchKernelGGL((k_basis<float, LP>), dim3(n_items), dim3(kBlock), 0, s, R.bm, R.S.as<float>(),
+                         R.Ut.as<double>(), U_out);
+    return HGL_OK;
+  }));
   HGL_HIP(hipGetLastError());
   if (sigma_out)
     HGL_HIP(hipMemcpyAsync(sigma_out, R.sig.p, sizeof(double) * R.nb * R.kk, hipMemcpyDeviceToDevice, s));
@@ -925,8 +1210,12 @@ static int prec_apply(void* ctx, const T* Rm, int64_t ldr, T* Z, int64_t ldz, do
   BlockPrec* P = static_cast<BlockPrec*>(ctx);
   Rsvd& R = *P->R;
   hgl_handle* h = P->h;
-  hipLaunchKernelGGL((k_prec_t<T>), dim3(R.nb, (nrhs + 63) / 64), dim3(kBlock), 0, s, R.bm, P->U,
-                     R.sig.as<double>(), P->lam, Rm, ldr, nrhs, P->dT->as<double>());
+  const int slabs = (nrhs + 63) / 64;
+  const int n_items = int(R.item_b.size());
+  hipLaunchKernelGGL((k_prec_t_tiles<T>), dim3(n_items, slabs), dim3(kBlock), 0, s, R.bm, P->U, Rm, ldr, nrhs,
+                     R.Tpart.as<double>());
+  hipLaunchKernelGGL(k_prec_t_reduce, dim3(R.nb, (R.kk * nrhs + kBlock - 1) / kBlock), dim3(kBlock), 0, s, R.bm,
+                     R.item0_d, R.Tpart.as<double>(), R.sig.as<double>(), P->lam, nrhs, slabs, P->dT->as<double>());
   HGL_HIP(hipGetLastError());
   const ColShape cs = pick_shape(nrhs, sizeof(T), {Rm, Z}, {ldr, ldz});
   const double g = P->lam / (1.0 + P->lam);
@@ -949,7 +1238,7 @@ extern "C" int hgl_block_rsvd(hgl_handle* h, int32_t n_blocks, const int32_t* bl
   clear_error();
   HGL_TRY(check_opts(h, n_blocks, block_offsets_host, o));
   HGL_CHECK_ARG(U_out != nullptr, "U_out must not be NULL");
-  Rsvd R;
+  Rsvd& R = rsvd_of(h);
   HGL_TRY(rsvd_setup(h, R, n_blocks, block_offsets_host, o, s));
   HGL_TRY(rsvd_any(h, R, o, omega_bf16, s));
   return finish_rsvd(h, R, U_out, sigma_out, s);
@@ -965,19 +1254,15 @@ extern "C" int hgl_block_rsvd_invert(hgl_handle* h, double lambda, int32_t n_blo
   HGL_CHECK_ARG(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0");
   HGL_CHECK_ARG(Y && F && nrhs >= 1 && ldy >= nrhs && ldf >= nrhs, "bad Y/F/nrhs/leading dimensions");
   HGL_CHECK_ARG(o->refine_tol > 0.0, "refine_tol must be > 0");
-  Rsvd R;
+  Rsvd& R = rsvd_of(h);
   HGL_TRY(rsvd_setup(h, R, n_blocks, block_offsets_host, o, s));
   HGL_TRY(rsvd_any(h, R, o, omega_bf16, s));
-  DevBuf U, dT;
-  HGL_TRY(U.reserve(sizeof(float) * size_t(h->N) * R.kk));
-  HGL_TRY(dT.reserve(sizeof(double) * size_t(n_blocks) * R.kk * nrhs));
-  int st = finish_rsvd(h, R, U.as<float>(), sigma_out, s);
-  if (st < 0) {
-    U.release();
-    dT.release();
-    return st;
-  }
-  BlockPrec bp{h, &R, U.as<float>(), lambda, &dT};
+  HGL_TRY(R.U.reserve(sizeof(float) * size_t(h->N) * R.kk));
+  HGL_TRY(R.dT.reserve(sizeof(double) * size_t(n_blocks) * R.kk * nrhs));
+  HGL_TRY(R.Tpart.reserve(sizeof(double) * R.item_b.size() * size_t((nrhs + 63) / 64) * R.kk * 64));
+  int st = finish_rsvd(h, R, R.U.as<float>(), sigma_out, s);
+  if (st < 0) return st;
+  BlockPrec bp{h, &R, R.U.as<float>(), lambda, &R.dT};
   Precond pc;
   pc.ctx = &bp;
   pc.apply_f32 = &prec_apply<float>;
@@ -992,8 +1277,6 @@ extern "C" int hgl_block_rsvd_invert(hgl_handle* h, double lambda, int32_t n_blo
   std::vector<double> lams(h->G, lambda);
   st = cg_run(h, lams.data(), &co, Y, ldy, F, ldf, nrhs, iters_host, relres_host, &pc, s);
   HGL_HIP(hipStreamSynchronize(s));
-  U.release();
-  dT.release();
   return st;
 }
 
