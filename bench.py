@@ -282,12 +282,22 @@ def main():
     ap.add_argument("--workload", default="multi_rhs",
                     help="multi_rhs (default), small, rsvd, learn, batch, or a comma list")
     ap.add_argument("--rr-period", type=int, default=0)
+    ap.add_argument("--calib", action="store_true",
+                    help="first copy 1 GiB device to device (the known-size kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}): the solves shard by columns, "
               "blocks or graphs with no communication, so no multi-GPU figure is produced", file=sys.stderr)
         sys.exit(2)
     import synth
+    if a.calib:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for wl in a.workload.split(","):
         if wl == "multi_rhs":
             p = synth.multi_rhs()

@@ -262,6 +262,18 @@ __global__ void k_long_fill(int32_t N, const int32_t* __restrict__ vtx_ptr,
   }
 }
 
+__global__ void k_long_edge_flags(int32_t E, const int32_t* __restrict__ edge_ptr, int32_t* __restrict__ is_long) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  is_long[e] = edge_ptr[e + 1] - edge_ptr[e] > kLongEdge ? 1 : 0;
+}
+
+__global__ void k_long_edge_fill(int32_t E, const int32_t* __restrict__ is_long, const int32_t* __restrict__ slot_of,
+                                 int32_t* __restrict__ long_edge) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E && is_long[e]) long_edge[slot_of[e]] = e;
+}
+
 static int blocks_for(int64_t n, int per) { return int((n + per - 1) / per); }
 
 static int check_error_words(const int32_t* err_host) {
@@ -292,7 +304,7 @@ static void free_handle(hgl_handle* h) {
   void* ptrs[] = {h->edge_ptr, h->edge_vtx, h->vtx_ptr, h->vtx_edge, h->w, h->dv, h->s64, h->c64,
                   h->s32, h->c32, h->tile_r0, h->tile_r1, h->tile_seg, h->long_row,
                   h->chunk_slot, h->chunk_begin, h->chunk_end, h->long_chunk0,
-                  h->seg_slots, h->long_seg};
+                  h->seg_slots, h->long_seg, h->long_edge};
   for (void* p : ptrs)
     if (p) hipFree(p);
   DevBuf* bufs[] = {&h->ws_z, &h->ws_z64, &h->ws_chunk, &h->ws_part, &h->ws_part2,
@@ -513,6 +525,30 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
     B_TRY(dev_alloc(&h->seg_slots, 4 * G));
     B_HIP(hipMemcpyAsync(h->seg_slots, h->seg_slots_host.data(), 16 * size_t(G), hipMemcpyHostToDevice, s));
     B_HIP(hipStreamSynchronize(s));
+  }
+  // ---- long hyperedges (one workgroup each in the edge gather)
+  if (E > 0) {
+    int32_t* tmpi = nullptr;
+    B_HIP(hipMallocAsync(reinterpret_cast<void**>(&tmpi), sizeof(int32_t) * 2 * (size_t(E) + 1), s));
+    int32_t* is_long = tmpi;
+    int32_t* slot_of = tmpi + (E + 1);
+    B_HIP(hipMemsetAsync(tmpi, 0, sizeof(int32_t) * 2 * (size_t(E) + 1), s));
+    hipLaunchKernelGGL(k_long_edge_flags, dim3(blocks_for(E, 256)), dim3(256), 0, s, E, h->edge_ptr, is_long);
+    B_HIP(hipGetLastError());
+    size_t b1 = 0;
+    B_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b1, is_long, slot_of, E + 1, s));
+    void* tmp = nullptr;
+    B_HIP(hipMallocAsync(&tmp, b1 + 16, s));
+    B_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, b1, is_long, slot_of, E + 1, s));
+    B_HIP(hipFreeAsync(tmp, s));
+    B_HIP(hipMemcpyAsync(h->pinned_i, slot_of + E, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    B_HIP(hipStreamSynchronize(s));
+    h->n_long_edge = h->pinned_i[0];
+    B_TRY(dev_alloc(&h->long_edge, h->n_long_edge));
+    hipLaunchKernelGGL(k_long_edge_fill, dim3(blocks_for(E, 256)), dim3(256), 0, s, E, is_long, slot_of,
+                       h->long_edge);
+    B_HIP(hipGetLastError());
+    B_HIP(hipFreeAsync(tmpi, s));
   }
   B_HIP(hipStreamSynchronize(s));
 #undef B_TRY

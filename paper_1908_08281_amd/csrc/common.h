@@ -50,10 +50,12 @@ struct Status {
 
 constexpr int kBlock = 256;        // threads per workgroup: 4 waves of 64
 constexpr int kWave = 64;
-constexpr int kTileRows = 64;      // rows per tile of the row-streaming kernels
-constexpr int kLongRow = 64;       // vertex rows with more hyperedges are split
-constexpr int kChunk = 256;        // hyperedges per chunk of a split vertex row
+constexpr int kTileRows = 32;      // rows per tile of the row-streaming kernels
+constexpr int kLongRow = 32;       // vertex rows with more hyperedges are split
+constexpr int kChunk = 128;        // hyperedges per chunk of a split vertex row
 constexpr int kStageIdx = 2048;    // hyperedge ids of a tile staged in LDS
+constexpr int kGather = 8;         // gathered rows in flight per lane group
+constexpr int kLongEdge = 32;      // hyperedges with more members get a whole workgroup
 constexpr int kProfKinds = 16;     // kernel kinds of the timing counters
 
 // ------------------------------------------------------ device buffers --
@@ -108,6 +110,10 @@ struct hgl_handle {
   int32_t* chunk_begin = nullptr;    // [n_chunks] position in vtx_edge
   int32_t* chunk_end = nullptr;      // [n_chunks]
   int32_t* long_chunk0 = nullptr;    // [n_long+1] first chunk of each long row
+
+  // hyperedges with more than kLongEdge members, increasing id (device)
+  int32_t n_long_edge = 0;
+  int32_t* long_edge = nullptr;      // [n_long_edge]
 
   // per segment: partial-slot ranges {t0, t1, l0, l1} (device, [G*4])
   int32_t* seg_slots = nullptr;

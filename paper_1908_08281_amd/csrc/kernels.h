@@ -25,27 +25,35 @@ __device__ __forceinline__ void store_row(T* __restrict__ p, const T (&x)[V]) {
   *reinterpret_cast<VecT<T, V>*>(p) = t;
 }
 
-// acc += sum_{j in [jb, je)} Z[idx[j], col .. col+V-1], four rows in flight.
+// acc += sum_{j in [jb, je)} Z[idx[j], col .. col+V-1], kGather rows in
+// flight: every batch issues all its loads before the sums (masked past je,
+// so a short row costs one round trip), and the batch is summed in a fixed
+// order.
 template <int V, class TZ>
 __device__ __forceinline__ void gather_rows(const TZ* __restrict__ Z, int64_t ldz,
                                             const int32_t* __restrict__ idx, int jb, int je, int col,
                                             TZ (&acc)[V]) {
-  int j = jb;
-  for (; j + 4 <= je; j += 4) {
-    const int e0 = idx[j], e1 = idx[j + 1], e2 = idx[j + 2], e3 = idx[j + 3];
-    TZ z0[V], z1[V], z2[V], z3[V];
-    load_row<V>(Z + int64_t(e0) * ldz + col, z0);
-    load_row<V>(Z + int64_t(e1) * ldz + col, z1);
-    load_row<V>(Z + int64_t(e2) * ldz + col, z2);
-    load_row<V>(Z + int64_t(e3) * ldz + col, z3);
+  for (int j = jb; j < je; j += kGather) {
+    int e[kGather];
 #pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] += ((z0[i] + z1[i]) + z2[i]) + z3[i];
-  }
-  for (; j < je; ++j) {
-    TZ z0[V];
-    load_row<V>(Z + int64_t(idx[j]) * ldz + col, z0);
+    for (int u = 0; u < kGather; ++u) e[u] = j + u < je ? idx[j + u] : -1;
+    TZ z[kGather][V];
 #pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] += z0[i];
+    for (int u = 0; u < kGather; ++u) {
+      if (e[u] >= 0) {
+        load_row<V>(Z + int64_t(e[u]) * ldz + col, z[u]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) z[u][i] = TZ(0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      TZ sum = z[0][i];
+#pragma unroll
+      for (int u = 1; u < kGather; ++u) sum += z[u][i];
+      acc[i] += sum;
+    }
   }
 }
 

@@ -16,50 +16,76 @@ namespace hgl {
 
 // ------------------------------------------------------------ edge gather --
 
+// acc += sum_{j in [jb, je)} s[idx[j]] P[idx[j], col .. col+V-1], kGather
+// member rows in flight (masked past je), summed in a fixed order.
+template <int V, class TIn, class TAcc>
+__device__ __forceinline__ void gather_scaled(const TIn* __restrict__ P, int64_t ldp, const TAcc* __restrict__ s,
+                                              const int32_t* __restrict__ idx, int jb, int je, int col,
+                                              TAcc (&acc)[V]) {
+  for (int j = jb; j < je; j += kGather) {
+    int v[kGather];
+#pragma unroll
+    for (int u = 0; u < kGather; ++u) v[u] = j + u < je ? idx[j + u] : -1;
+    TAcc sv[kGather];
+    TIn x[kGather][V];
+#pragma unroll
+    for (int u = 0; u < kGather; ++u) {
+      if (v[u] >= 0) {
+        sv[u] = s[v[u]];
+        load_row<V>(P + int64_t(v[u]) * ldp + col, x[u]);
+      } else {
+        sv[u] = TAcc(0);
+#pragma unroll
+        for (int i = 0; i < V; ++i) x[u][i] = TIn(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kGather; ++u)
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[i] += sv[u] * TAcc(x[u][i]);
+  }
+}
+
+// Workgroups [0, n_short_wg) take GPB consecutive hyperedges, one per lane
+// group, and skip the long ones (more than kLongEdge members); each further
+// workgroup takes one long hyperedge, its groups summing contiguous shares
+// of the members, combined by a fixed-order block reduction.
 template <class TIn, class TAcc, int GL, int V>
 __global__ __launch_bounds__(kBlock) void k_spmm_edge(
     int32_t E, const int32_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_vtx,
+    int32_t n_short_wg, const int32_t* __restrict__ long_edge,
     const TAcc* __restrict__ s, const TAcc* __restrict__ c, const TIn* __restrict__ P, int64_t ldp,
     TAcc* __restrict__ Z, int64_t ldz, int k, Gate gate) {
   if (gate.skip()) return;
-  constexpr int GPB = kBlock / GL;
+  constexpr int GPB = kBlock / GL, W = GL * V;
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
-  const int e = blockIdx.x * GPB + grp;
-  const int col = blockIdx.y * (GL * V) + lane * V;
-  if (e >= E || col >= k) return;
-  const int b = edge_ptr[e], en = edge_ptr[e + 1];
+  const int col = blockIdx.y * W + lane * V;
   TAcc acc[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) acc[i] = TAcc(0);
-  int j = b;
-  for (; j + 4 <= en; j += 4) {
-    int v0 = edge_vtx[j], v1 = edge_vtx[j + 1], v2 = edge_vtx[j + 2], v3 = edge_vtx[j + 3];
-    TAcc s0 = s[v0], s1 = s[v1], s2 = s[v2], s3 = s[v3];
-    TIn x0[V], x1[V], x2[V], x3[V];
-    load_row<V>(P + int64_t(v0) * ldp + col, x0);
-    load_row<V>(P + int64_t(v1) * ldp + col, x1);
-    load_row<V>(P + int64_t(v2) * ldp + col, x2);
-    load_row<V>(P + int64_t(v3) * ldp + col, x3);
+  if (int(blockIdx.x) < n_short_wg) {
+    const int e = blockIdx.x * GPB + grp;
+    if (e >= E || col >= k) return;
+    const int b = edge_ptr[e], en = edge_ptr[e + 1];
+    if (en - b > kLongEdge) return;
+    gather_scaled<V>(P, ldp, s, edge_vtx, b, en, col, acc);
+    const TAcc ce = c[e];
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-      acc[i] += s0 * TAcc(x0[i]);
-      acc[i] += s1 * TAcc(x1[i]);
-      acc[i] += s2 * TAcc(x2[i]);
-      acc[i] += s3 * TAcc(x3[i]);
-    }
+    for (int i = 0; i < V; ++i) acc[i] *= ce;
+    store_row<V>(Z + int64_t(e) * ldz + col, acc);
+    return;
   }
-  for (; j < en; ++j) {
-    int v0 = edge_vtx[j];
-    TAcc s0 = s[v0];
-    TIn x0[V];
-    load_row<V>(P + int64_t(v0) * ldp + col, x0);
-#pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] += s0 * TAcc(x0[i]);
+  __shared__ TAcc lds[4 * W];
+  const int e = long_edge[blockIdx.x - n_short_wg];
+  const int b = edge_ptr[e], en = edge_ptr[e + 1];
+  if (col < k) {
+    const int per = (en - b + GPB - 1) / GPB;
+    const int jb = b + grp * per;
+    gather_scaled<V>(P, ldp, s, edge_vtx, jb, min(jb + per, en), col, acc);
   }
-  const TAcc ce = c[e];
-#pragma unroll
-  for (int i = 0; i < V; ++i) acc[i] *= ce;
-  store_row<V>(Z + int64_t(e) * ldz + col, acc);
+  const TAcc sum = block_colsum<GL, V>(acc, lds);
+  const int cc = blockIdx.y * W + threadIdx.x;
+  if (threadIdx.x < W && cc < k) Z[int64_t(e) * ldz + cc] = c[e] * sum;
 }
 
 template <class TIn, class TAcc>
@@ -77,9 +103,10 @@ int launch_spmm_edge(const hgl_handle* h, const TIn* P, int64_t ldp, TAcc* Z, in
   }
   return HGL_DISPATCH_SHAPE(cs, sizeof(TAcc), {
     constexpr int GPB = kBlock / GL;
-    dim3 grid((h->E + GPB - 1) / GPB, cs.slabs);
+    const int n_short = (h->E + GPB - 1) / GPB;
+    dim3 grid(n_short + h->n_long_edge, cs.slabs);
     hipLaunchKernelGGL((k_spmm_edge<TIn, TAcc, GL, V>), grid, dim3(kBlock), 0, st, h->E,
-                       h->edge_ptr, h->edge_vtx, s, c, P, ldp, Z, ldz, k, gate);
+                       h->edge_ptr, h->edge_vtx, n_short, h->long_edge, s, c, P, ldp, Z, ldz, k, gate);
     HGL_HIP(hipGetLastError());
     return HGL_OK;
   });
