@@ -43,22 +43,111 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 
 
-def gather_bytes(N, E, nnz, k, elem=4):
-    """Compulsory HBM bytes of one launch of each operator gather, and of one
-    CG iteration (F, R, P read and written once, the E x k intermediate
-    written and read once, both CSR index arrays read once)."""
-    vertex = elem * k * (E + 2 * N) + 4 * (2 * N + 1 + nnz)    # read Z, P; write Q; vtx_ptr, vtx_edge, s
-    edge = elem * k * (N + E) + 4 * (2 * E + 1 + nnz + N)      # read P; write Z; edge_ptr, edge_vtx, c, s
+def gather_bytes(N, E, nnz, k, elem=4, covered=None, hubs=0):
+    """Algorithmic HBM bytes of one launch of each operator-gather kernel, and
+    of one CG iteration.
+
+    edge_gather (k_spmm_edge): read the P rows of the vertices that lie in
+    some hyperedge (`covered`), write Z (E x k); edge_ptr, edge_vtx, c, s.
+    vertex_gather (k_spmm_vertex, one launch): read every Z row once, read P
+    and write Q for the N - hubs rows it finishes itself (hub rows, more
+    hyperedges than the hub threshold, are finished by a separate launch);
+    vtx_ptr, vtx_edge, s.
+    cg_iteration: F, R, P read and written once, the E x k intermediate
+    written and read once, both CSR index arrays read once."""
+    covered = N if covered is None else covered
+    vertex = elem * k * (E + 2 * (N - hubs)) + 4 * (N + 1 + nnz + (N - hubs))
+    edge = elem * k * (covered + E) + 4 * (2 * E + 1 + nnz + covered)
     per_iter = elem * k * (6 * N + 2 * E) + 4 * (2 * nnz + 2 * N + 2 * E)
     return {"vertex_gather": vertex, "edge_gather": edge, "cg_iteration": per_iter}
 
 
-def _roof(name, n, ms, alg, bound="hbm"):
+# ------------------------------------------------------- profile summaries
+
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_1908_08281_amd/csrc/spmm.hip", "paper_1908_08281_amd/csrc/kernels.h",
+                  "paper_1908_08281_amd/csrc/common.h", "paper_1908_08281_amd/csrc/cg.hip"]
+
+
+def sources_digest():
+    """SHA-256 over the sources of the operator and CG kernels: a stored
+    counter figure is used only while the kernels it measured are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "").strip()
+
+
+def summarize_counters(fetch_csv, write_csv, kernel, workload, command, calib_bytes=1 << 30):
+    """Per-dispatch HBM traffic of `kernel` (base name, e.g. k_spmm_vertex;
+    its most-dispatched instance) from two rocprofv3 --pmc runs (FETCH_SIZE,
+    WRITE_SIZE; KiB per dispatch), each scaled by what the same counter reads
+    for the calibration copy of `calib_bytes` (the largest
+    __amd_rocclr_copyBuffer dispatch of the run)."""
+    import collections
+    import csv
+
+    def per_kernel(path, counter):
+        vals, calib = collections.defaultdict(list), []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            name = _short(r["Kernel_Name"])
+            if "copyBuffer" in name:
+                calib.append(v)
+            elif name.split("::")[-1].startswith(kernel + "<") or name.split("::")[-1] == kernel:
+                vals[name].append(v)
+        inst = max(vals, key=lambda n2: len(vals[n2]))
+        factor = calib_bytes / (max(calib) * 1024.0)
+        return sum(vals[inst]) / len(vals[inst]) * 1024.0 * factor, factor, len(vals[inst]), inst
+
+    fb, ff, nf, inst = per_kernel(fetch_csv, "FETCH_SIZE")
+    wb, wf, nw, _ = per_kernel(write_csv, "WRITE_SIZE")
+    return {"kernel": kernel, "instance": inst, "workload": workload, "fetch_bytes_per_launch": round(fb),
+            "write_bytes_per_launch": round(wb), "traffic_bytes_per_launch": round(fb + wb),
+            "fetch_scale": round(ff, 4), "write_scale": round(wf, 4), "dispatches": [nf, nw],
+            "calibration": f"{calib_bytes} B device-to-device copy (bench.py --calib)",
+            "sources_sha256": sources_digest(), "command": command}
+
+
+def summarize_stats(stats_csv, workload, command, top=16):
+    """Text table of a rocprofv3 --kernel-trace --stats run."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# rocprofv3 kernel statistics: {workload}", "", f"command: {command}", "",
+             f"{'kernel':70s} {'calls':>6s} {'avg_us':>9s} {'total_ms':>9s} {'pct':>6s}"]
+    for r in rows[:top]:
+        lines.append(f"{_short(r['Name'])[:70]:70s} {r['Calls']:>6s} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:9.3f} {float(r['Percentage']):6.2f}")
+    return "\n".join(lines) + "\n"
+
+
+def stored_traffic(kernel, workload):
+    """Traffic per launch from the committed counter summary, or None when
+    there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(PROFILES, f"{workload}_{kernel}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel") != kernel or rec.get("sources_sha256") != sources_digest():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def _roof(name, n, ms, alg, bound="hbm", traffic=None):
     avg = ms / max(n, 1)
     if bound == "hbm":
         ach = alg / (avg * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
                 "avg_launch_us": round(avg * 1e3, 2), "launches": n, "algorithmic_bytes_per_launch": int(alg)}
     ach = alg / (avg * 1e-3) / 1e12
     return {"bound": "mfma", "achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -151,17 +240,21 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
     ms = 1e3 * dt / a.steps
     value = a.steps * k * G / dt if state["ok"] else 0.0
     elem = 4 if mode == "f32" else 8
-    ab = gather_bytes(p.N, p.E, p.nnz, k, elem)
+    part = h.partition()
+    covered = int(np.unique(p.edge_vtx).size)
+    ab = gather_bytes(p.N, p.E, p.nnz, k, elem, covered, part["hub_rows"])
     nv, mv = prof["vertex_gather"]
     ne, me = prof["edge_gather"]
-    roof = _roof("vertex_gather", nv, mv, ab["vertex_gather"]) if mv >= me else _roof("edge_gather", ne, me,
-                                                                                       ab["edge_gather"])
+    if mv >= me:
+        roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_gather"], traffic=stored_traffic("k_spmm_vertex", name))
+    else:
+        roof = _roof("k_spmm_edge", ne, me, ab["edge_gather"], traffic=stored_traffic("k_spmm_edge", name))
     it_mean = float(np.mean(state["iters"]))
     cfg = {"workload": name, "N": p.N, "E": p.E, "nnz": p.nnz, "k": k, "graphs": G,
            "lambda": float(p.lam), "relres_tol": tol,
            "cg": f"{mode} vectors, fp64 inner products, residual replacement at convergence checks"
                  + (f" and every {rr_period}" if rr_period else ""),
-           "iterations": it_mean, "all_columns_converged": state["ok"]}
+           "iterations": it_mean, "all_columns_converged": state["ok"], "partition": part}
     extra = {"cg_iteration_gbs": round(ab["cg_iteration"] * it_mean / (ms * 1e-3) / 1e9, 1),
              "kernel_ms": _kernel_ms(prof)}
     if with_cpu and not a.no_cpu:
@@ -282,10 +375,28 @@ def main():
     ap.add_argument("--workload", default="multi_rhs",
                     help="multi_rhs (default), small, rsvd, learn, batch, or a comma list")
     ap.add_argument("--rr-period", type=int, default=0)
+    ap.add_argument("--summarize", nargs="+", metavar="ARG",
+                    help="write profile summaries and exit: 'stats STATS_CSV WORKLOAD COMMAND' or "
+                         "'counters FETCH_CSV WRITE_CSV KERNEL WORKLOAD COMMAND'")
     ap.add_argument("--calib", action="store_true",
                     help="first copy 1 GiB device to device (the known-size kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
     a = ap.parse_args()
+    if a.summarize:
+        os.makedirs(PROFILES, exist_ok=True)
+        kind = a.summarize[0]
+        if kind == "stats":
+            stats_csv, workload, command = a.summarize[1:4]
+            out = os.path.join(PROFILES, f"{workload}_kernel_stats.txt")
+            with open(out, "w") as fh:
+                fh.write(summarize_stats(stats_csv, workload, command))
+        else:
+            fetch_csv, write_csv, kernel, workload, command = a.summarize[1:6]
+            out = os.path.join(PROFILES, f"{workload}_{kernel}_traffic.json")
+            with open(out, "w") as fh:
+                json.dump(summarize_counters(fetch_csv, write_csv, kernel, workload, command), fh, indent=1)
+        print(out)
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}): the solves shard by columns, "
               "blocks or graphs with no communication, so no multi-GPU figure is produced", file=sys.stderr)

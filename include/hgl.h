@@ -120,6 +120,15 @@ void hgl_destroy(hgl_handle* h);
 int hgl_get_sizes(const hgl_handle* h, int32_t* N, int32_t* E, int64_t* nnz, int32_t* G);
 
 /*
+ * Work partition of the operator gathers (diagnostics; any pointer may be
+ * NULL): row tiles of the vertex gather, hub vertex rows (split into chunks
+ * and finished by a separate launch) with their chunk count, and hyperedges
+ * large enough to take a whole workgroup in the edge gather.
+ */
+int hgl_get_partition(const hgl_handle* h, int32_t* n_tiles, int32_t* n_hub_rows, int32_t* n_hub_chunks,
+                      int32_t* n_long_edges);
+
+/*
  * Copy the derived quantities of section 2 into caller buffers (any may be
  * NULL): dv [N] = delta(v), s [N] = delta(v)^-1/2 (0 if delta(v) = 0),
  * c [E] = w_e/delta(e), vtx_ptr [N+1] and vtx_edge [nnz] = vertex-major CSR
@@ -271,15 +280,18 @@ int hgl_project_simplex(const double* v, double* w, int32_t E, hipStream_t strea
 
 /*
  * Kernel timing (diagnostics).  hgl_profile(h, 1) resets the counters and
- * makes every later solver call on h bracket each kernel launch with HIP
- * events recorded on the call's stream; hgl_profile(h, 0) stops it.
- * hgl_profile_read returns, for one kernel kind, the number of launches
- * recorded and their summed duration in milliseconds (it synchronises the
- * device).  Kinds: 0 edge gather (Z = C H' S P), 1 vertex gather with inner
- * product (M P), 2 CG update (F, R), 3 CG direction (P), 4 reductions,
- * 5 residual edge gather (FP64), 6 residual vertex gather (FP64),
- * 7 start-up, 8 preconditioner, 9 rSVD products, 10 CholQR, 11 Jacobi,
- * 12 block extraction, 13 weight gradient.  Kinds 0..15; others -> HGL_EINVAL.
+ * makes every later solver call on h launch its kernels with start/stop
+ * events that the runtime stamps at each kernel's own start and end
+ * (hipExtLaunchKernel); hgl_profile(h, 0) stops it.  hgl_profile_read
+ * returns, for one kernel kind, the number of kernel launches recorded and
+ * their summed duration in milliseconds (it synchronises the device).
+ * Kinds: 0 edge gather (Z = C H' S P), 1 vertex gather with inner product
+ * (M P, rows up to the hub threshold and hub-row chunks), 2 CG update (F, R),
+ * 3 CG direction (P), 4 reductions, 5 residual edge gather (FP64),
+ * 6 residual vertex gather (FP64), 7 start-up, 8 preconditioner, 9 rSVD
+ * products, 10 CholQR, 11 Jacobi, 12 block extraction, 13 weight gradient,
+ * 14 hub-row finish of every vertex gather.  Kinds 0..15; others ->
+ * HGL_EINVAL.
  */
 int hgl_profile(hgl_handle* h, int32_t enable);
 int hgl_profile_read(hgl_handle* h, int32_t kind, int64_t* launches, double* ms);

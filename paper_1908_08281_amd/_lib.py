@@ -56,6 +56,7 @@ SIGNATURES = {
     "hgl_set_weights": (C.c_int, [P, P, P]),
     "hgl_destroy": (None, [P]),
     "hgl_get_sizes": (C.c_int, [P, I32P, I32P, C.POINTER(C.c_int64), I32P]),
+    "hgl_get_partition": (C.c_int, [P, I32P, I32P, I32P, I32P]),
     "hgl_get_operator": (C.c_int, [P, P, P, P, P, P, P]),
     "hgl_apply": (C.c_int, [P, D, I32, P, I64, P, I64, I32, P]),
     "hgl_cg_solve": (C.c_int, [P, D, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),

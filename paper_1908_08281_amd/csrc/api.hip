@@ -70,7 +70,7 @@ int ensure_pinned(hgl_handle* h, size_t n) {
 
 // ------------------------------------------------------------ kernel timing --
 
-static hipEvent_t prof_event(hgl_handle* h) {
+hipEvent_t prof_event(hgl_handle* h) {
   if (!h->prof_pool.empty()) {
     hipEvent_t e = h->prof_pool.back();
     h->prof_pool.pop_back();
@@ -81,23 +81,11 @@ static hipEvent_t prof_event(hgl_handle* h) {
   return e;
 }
 
-void prof_begin(hgl_handle* h, int kind, hipStream_t s) {
-  if (!h->prof_on) return;
-  hipEvent_t e = prof_event(h);
-  if (!e) return;
-  hipEventRecord(e, s);
-  h->prof_open = e;
-  h->prof_kind = kind;
+void prof_begin(hgl_handle* h, int kind, hipStream_t) {
+  if (h->prof_on) h->prof_kind = kind;
 }
 
-void prof_end(hgl_handle* h, hipStream_t s) {
-  if (!h->prof_on || !h->prof_open) return;
-  hipEvent_t e = prof_event(h);
-  if (!e) return;
-  hipEventRecord(e, s);
-  h->prof_pending.push_back({h->prof_kind, {h->prof_open, e}});
-  h->prof_open = nullptr;
-}
+void prof_end(hgl_handle* h, hipStream_t) { h->prof_kind = -1; }
 
 static void prof_collect(hgl_handle* h) {
   if (h->prof_pending.empty()) return;
@@ -208,18 +196,32 @@ __global__ void k_expand(int32_t E, const int32_t* __restrict__ edge_ptr,
   }
 }
 
-__global__ void k_degrees(int32_t N, const int32_t* __restrict__ vtx_ptr,
-                          const int32_t* __restrict__ vtx_edge, const double* __restrict__ w,
-                          double* __restrict__ dv, double* __restrict__ s64,
-                          float* __restrict__ s32) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= N) return;
+// dv[v] = sum of w_e over the hyperedges of v (the vertex degree of eq. 1),
+// one wave per vertex: lane l takes entries l, l+64, ... with four loads in
+// flight, then a fixed xor-shuffle tree (deterministic).  s = dv^-1/2, and 0
+// for an isolated vertex (dv = 0).
+__global__ __launch_bounds__(256) void k_degrees(int32_t N, const int32_t* __restrict__ vtx_ptr,
+                                                 const int32_t* __restrict__ vtx_edge, const double* __restrict__ w,
+                                                 double* __restrict__ dv, double* __restrict__ s64,
+                                                 float* __restrict__ s32) {
+  const int v = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (v >= N) return;  // uniform per wave
+  const int en = vtx_ptr[v + 1];
   double d = 0.0;
-  for (int j = vtx_ptr[v]; j < vtx_ptr[v + 1]; ++j) d += w[vtx_edge[j]];
-  dv[v] = d;
-  double s = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
-  s64[v] = s;
-  s32[v] = float(s);
+  int j = vtx_ptr[v] + lane;
+  for (; j + 3 * 64 < en; j += 4 * 64) {
+    const double w0 = w[vtx_edge[j]], w1 = w[vtx_edge[j + 64]];
+    const double w2 = w[vtx_edge[j + 128]], w3 = w[vtx_edge[j + 192]];
+    d += ((w0 + w1) + w2) + w3;
+  }
+  for (; j < en; j += 64) d += w[vtx_edge[j]];
+  for (int off = 32; off >= 1; off >>= 1) d += __shfl_xor(d, off, 64);
+  if (lane == 0) {
+    dv[v] = d;
+    const double sv = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    s64[v] = sv;
+    s32[v] = float(sv);
+  }
 }
 
 __global__ void k_edge_scales(int32_t E, const int32_t* __restrict__ edge_ptr,
@@ -290,7 +292,7 @@ static int check_error_words(const int32_t* err_host) {
 
 static int compute_scales(hgl_handle* h, hipStream_t s) {
   if (h->N > 0)
-    hipLaunchKernelGGL(k_degrees, dim3(blocks_for(h->N, 256)), dim3(256), 0, s, h->N, h->vtx_ptr,
+    hipLaunchKernelGGL(k_degrees, dim3(blocks_for(h->N, 4)), dim3(256), 0, s, h->N, h->vtx_ptr,
                        h->vtx_edge, h->w, h->dv, h->s64, h->s32);
   if (h->E > 0)
     hipLaunchKernelGGL(k_edge_scales, dim3(blocks_for(h->E, 256)), dim3(256), 0, s, h->E,
@@ -320,7 +322,6 @@ static void free_handle(hgl_handle* h) {
     hipEventDestroy(p.second.second);
   }
   for (hipEvent_t e : h->prof_pool) hipEventDestroy(e);
-  if (h->prof_open) hipEventDestroy(h->prof_open);
   delete h;
 }
 
@@ -614,6 +615,17 @@ extern "C" int hgl_get_sizes(const hgl_handle* h, int32_t* N, int32_t* E, int64_
   if (E) *E = h->E;
   if (nnz) *nnz = h->nnz;
   if (G) *G = h->G;
+  return HGL_OK;
+}
+
+extern "C" int hgl_get_partition(const hgl_handle* h, int32_t* n_tiles, int32_t* n_hub_rows,
+                                 int32_t* n_hub_chunks, int32_t* n_long_edges) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  if (n_tiles) *n_tiles = h->n_tiles;
+  if (n_hub_rows) *n_hub_rows = h->n_long;
+  if (n_hub_chunks) *n_hub_chunks = h->n_chunks;
+  if (n_long_edges) *n_long_edges = h->n_long_edge;
   return HGL_OK;
 }
 

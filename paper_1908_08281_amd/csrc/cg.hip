@@ -418,7 +418,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   prof_begin(h, kProfStart, s);
   int rc = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
     dim3 grid(h->n_tiles, cs.slabs);
-    hipLaunchKernelGGL((k_cg_init<T, GL, V>), grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
+    launch(h, -1, k_cg_init<T, GL, V>, grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
                        h->tile_r1, nsl, h->n_long, Y, ldy, F, ldf, b.R, b.P, ld, b.part, b.part2, k,
                        x0 ? 1 : 0, has_prec ? static_cast<const T*>(b.Zp) : nullptr);
     HGL_HIP(hipGetLastError());
@@ -426,7 +426,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   });
   HGL_TRY(rc);
   ra.iter = -1;
-  hipLaunchKernelGGL((k_cg_reduce<RedOp::Init>), dim3(red_blocks), dim3(kBlock), 0, s, ra, b.st, wd);
+  launch(h, -1, k_cg_reduce<RedOp::Init>, dim3(red_blocks), dim3(kBlock), 0, s, ra, b.st, wd);
   HGL_HIP(hipGetLastError());
   prof_end(h, s);
 
@@ -443,13 +443,13 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     RedArgs r = ra;
     r.iter = it;
     prof_begin(h, kProfReduce, s);
-    hipLaunchKernelGGL((k_cg_reduce<RedOp::Alpha>), dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
+    launch(h, -1, k_cg_reduce<RedOp::Alpha>, dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
     HGL_HIP(hipGetLastError());
     prof_end(h, s);
     prof_begin(h, kProfUpdate, s);
     int rc2 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
       dim3 grid(h->n_tiles, cs.slabs);
-      hipLaunchKernelGGL((k_cg_update<T, GL, V>), grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
+      launch(h, -1, k_cg_update<T, GL, V>, grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
                          h->tile_r1, h->tile_seg, nsl, h->n_long, F, ldf, b.R, b.P, b.Q, ld,
                          b.st.alpha, b.part, k, g_prev);
       HGL_HIP(hipGetLastError());
@@ -462,7 +462,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     if (has_prec) HGL_TRY(precond(b.R, ld, b.Zp, ld, b.part3, g_prev));
     r.periodic = periodic;
     prof_begin(h, kProfReduce, s);
-    hipLaunchKernelGGL((k_cg_reduce<RedOp::Beta>), dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
+    launch(h, -1, k_cg_reduce<RedOp::Beta>, dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
     HGL_HIP(hipGetLastError());
     prof_end(h, s);
     Gate g_now{wd.cnt(it), nullptr, 1};
@@ -470,7 +470,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     const T* dir_src = has_prec ? b.Zp : b.R;
     int rc3 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
       dim3 grid(h->n_tiles, cs.slabs);
-      hipLaunchKernelGGL((k_cg_direction<T, GL, V>), grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
+      launch(h, -1, k_cg_direction<T, GL, V>, grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
                          h->tile_seg, dir_src, b.P, ld, b.st.beta, k, g_now);
       HGL_HIP(hipGetLastError());
       return HGL_OK;
@@ -488,7 +488,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     RedArgs r = ra;
     r.iter = it_next;
     prof_begin(h, kProfReduce, s);
-    hipLaunchKernelGGL((k_cg_reduce<RedOp::Check>), dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
+    launch(h, -1, k_cg_reduce<RedOp::Check>, dim3(red_blocks), dim3(kBlock), 0, s, r, b.st, wd);
     HGL_HIP(hipGetLastError());
     prof_end(h, s);
     return HGL_OK;

@@ -1,6 +1,7 @@
 // Internal declarations shared by the library's translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -135,8 +136,7 @@ struct hgl_handle {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
   int64_t prof_launches[hgl::kProfKinds] = {0};
   double prof_ms[hgl::kProfKinds] = {0};
-  hipEvent_t prof_open = nullptr;
-  int prof_kind = -1;
+  int prof_kind = -1;                                // open kind (prof_begin), or -1
   int32_t* pinned_i = nullptr;   // host-pinned readback words
   double* pinned_d = nullptr;
   size_t pinned_d_len = 0;
@@ -179,9 +179,31 @@ int upload_ab(hgl_handle* h, const double* lambdas_host, hipStream_t st);
 enum ProfKind { kProfEdge = 0, kProfVertex = 1, kProfUpdate = 2, kProfDirection = 3,
                 kProfReduce = 4, kProfResidEdge = 5, kProfResidVertex = 6, kProfStart = 7,
                 kProfPrecond = 8, kProfGemm = 9, kProfQr = 10, kProfEig = 11, kProfExtract = 12,
-                kProfGrad = 13 };
+                kProfGrad = 13, kProfFinish = 14 };
 void prof_begin(hgl_handle* h, int kind, hipStream_t s);
 void prof_end(hgl_handle* h, hipStream_t s);
+hipEvent_t prof_event(hgl_handle* h);
+
+// Launch one kernel.  While timing is enabled and a kind is open (prof_begin,
+// or `kind` >= 0), the dispatch carries start/stop events that the runtime
+// stamps at this kernel's own start and end, credited to that kind.
+template <class F, class... Args>
+inline void launch(const hgl_handle* hc, int kind, F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s,
+                   Args... args) {
+  hgl_handle* h = const_cast<hgl_handle*>(hc);
+  const int kd = kind >= 0 ? kind : h->prof_kind;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof_on && kd >= 0) {
+    e0 = prof_event(h);
+    e1 = prof_event(h);
+  }
+  if (e0 && e1) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, s, e0, e1, 0, args...);
+    h->prof_pending.push_back({kd, {e0, e1}});
+  } else {
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, s, nullptr, nullptr, 0, args...);
+  }
+}
 
 // Preconditioner for the CG driver: Z = P^-1 R (k columns), with partial
 // inner products <R_j, Z_j> per row tile written to part (nullable).

@@ -203,7 +203,7 @@ static int run_grad(hgl_handle* h, double lam, double mu, const T* F, int64_t ld
   const int blocks = int(std::min<int64_t>((int64_t(nk) + 255) / 256, 65535));
 
   prof_begin(h, kProfGrad, s);
-  hipLaunchKernelGGL((k_to_f64<T>), dim3(blocks), dim3(256), 0, s, int64_t(N), k, F, ldf, F64);
+  launch(h, -1, k_to_f64<T>, dim3(blocks), dim3(256), 0, s, int64_t(N), k, F, ldf, F64);
   HGL_HIP(hipGetLastError());
   // (a, b) pairs for the products: A X = 0 X - (-1) S H Z; M X = (1+1/lam) X - (1/lam) S H Z
   DevBuf& abA = h->ws_extra[3];
@@ -236,7 +236,7 @@ static int run_grad(hgl_handle* h, double lam, double mu, const T* F, int64_t ld
   int64_t ld_rhs = ldg;
   if (objective) {
     HGL_TRY(apply64(F64, AZ, abM));  // AZ used as scratch for M F
-    hipLaunchKernelGGL((k_objective_rhs<T>), dim3(blocks), dim3(256), 0, s, int64_t(N), k, AZ, Y, ldy, 2.0 * lam,
+    launch(h, -1, k_objective_rhs<T>, dim3(blocks), dim3(256), 0, s, int64_t(N), k, AZ, Y, ldy, 2.0 * lam,
                        rhs);
     HGL_HIP(hipGetLastError());
     rhs_ptr = rhs;
@@ -250,15 +250,15 @@ static int run_grad(hgl_handle* h, double lam, double mu, const T* F, int64_t ld
   int st = cg_run(h, lams.data(), adj, rhs_ptr, ld_rhs, Zdst, ldzd, k, iters_host, relres_host, nullptr, s);
   if (st < 0) return st;
   prof_begin(h, kProfGrad, s);
-  hipLaunchKernelGGL((k_to_f64<T>), dim3(blocks), dim3(256), 0, s, int64_t(N), k, Zdst, ldzd, Z64);
+  launch(h, -1, k_to_f64<T>, dim3(blocks), dim3(256), 0, s, int64_t(N), k, Zdst, ldzd, Z64);
   HGL_HIP(hipGetLastError());
   HGL_TRY(apply64(Z64, AZ, abA));
-  hipLaunchKernelGGL(k_vertex_terms, dim3((N + 3) / 4), dim3(kBlock), 0, s, N, k, h->s64, F64, AF, Z64, AZ, t1, t2);
+  launch(h, -1, k_vertex_terms, dim3((N + 3) / 4), dim3(kBlock), 0, s, N, k, h->s64, F64, AF, Z64, AZ, t1, t2);
   HGL_HIP(hipGetLastError());
   if (E > 0) {
     const double cf = objective ? -1.0 : 0.0;
     const double cz = 1.0 / lam;
-    hipLaunchKernelGGL(k_edge_grad, dim3((E + 3) / 4), dim3(kBlock), 0, s, E, k, h->edge_ptr, h->edge_vtx, h->s64,
+    launch(h, -1, k_edge_grad, dim3((E + 3) / 4), dim3(kBlock), 0, s, E, k, h->edge_ptr, h->edge_vtx, h->s64,
                        F64, Z64, t1, t2, h->w, cf, cz, objective ? mu : 0.0, grad);
     HGL_HIP(hipGetLastError());
   }

@@ -1024,15 +1024,15 @@ static int with_lp(int LP, F&& f) {
   }
 }
 
-static int launch_gemm(Rsvd& R, hipStream_t s) {
+static int launch_gemm(hgl_handle* h, Rsvd& R, hipStream_t s) {
   const int n_items = int(R.item_b.size());
   if (R.f64) {
-    hipLaunchKernelGGL(k_gemm_f64, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.A.as<double>(),
+    launch(h, -1, k_gemm_f64, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.A.as<double>(),
                        R.ST.as<double>(), R.Y.as<double>());
   } else {
     HGL_TRY(with_lp(R.LP, [&](auto c) {
       constexpr int LP = decltype(c)::value;
-      hipLaunchKernelGGL(k_gemm_bf16<LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.A.as<uint16_t>(),
+      launch(h, -1, k_gemm_bf16<LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.A.as<uint16_t>(),
                          R.ST.as<uint16_t>(), R.y_elems, R.Y.as<float>());
       return HGL_OK;
     }));
@@ -1043,9 +1043,9 @@ static int launch_gemm(Rsvd& R, hipStream_t s) {
 
 // Gram tile partials of Yb (summed by the consuming kernel).
 template <class TY>
-static int launch_gram(Rsvd& R, const DevBuf& Yb, hipStream_t s) {
+static int launch_gram(hgl_handle* h, Rsvd& R, const DevBuf& Yb, hipStream_t s) {
   const int n_items = int(R.item_b.size());
-  hipLaunchKernelGGL((k_gram_tiles<TY>), dim3(n_items), dim3(kBlock), 0, s, R.bm, Yb.as<TY>(), R.Gpart.as<double>());
+  launch(h, -1, k_gram_tiles<TY>, dim3(n_items), dim3(kBlock), 0, s, R.bm, Yb.as<TY>(), R.Gpart.as<double>());
   HGL_HIP(hipGetLastError());
   return HGL_OK;
 }
@@ -1060,12 +1060,12 @@ static int cholqr2(hgl_handle* h, Rsvd& R, hipStream_t s) {
   for (int pass = 0; pass < 2; ++pass) {
     DevBuf& in = pass == 0 ? R.Y : R.S;
     DevBuf& out = pass == 0 ? R.S : R.Y;
-    HGL_TRY(launch_gram<TY>(R, in, s));
-    hipLaunchKernelGGL(k_chol_inv, dim3(R.nb), dim3(kDense), lds_chol, s, R.bm, R.item0_d, R.Gpart.as<double>(),
+    HGL_TRY(launch_gram<TY>(h, R, in, s));
+    launch(h, -1, k_chol_inv, dim3(R.nb), dim3(kDense), lds_chol, s, R.bm, R.item0_d, R.Gpart.as<double>(),
                        R.Li.as<double>(), R.fail.as<int32_t>());
     HGL_TRY(with_lp(R.LP, [&](auto c) {
       constexpr int LP = decltype(c)::value;
-      hipLaunchKernelGGL((k_apply_rinv<TY, TST, LP>), dim3(n_items), dim3(kBlock), 0, s, R.bm, in.as<TY>(),
+      launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, in.as<TY>(),
                          R.Li.as<double>(), out.as<TY>(), R.ST.as<TST>(), R.y_elems);
       return HGL_OK;
     }));
@@ -1090,11 +1090,11 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
     prof_begin(h, kProfExtract, s);
     if (R.f64) {
       HGL_TRY(allow_lds(k_extract_blocks<double>, lds_ex));
-      hipLaunchKernelGGL((k_extract_blocks<double>), grid, dim3(kBlock), lds_ex, s, R.bm, h->vtx_ptr, h->vtx_edge,
+      launch(h, -1, k_extract_blocks<double>, grid, dim3(kBlock), lds_ex, s, R.bm, h->vtx_ptr, h->vtx_edge,
                          h->edge_ptr, h->edge_vtx, h->s64, h->c64, R.A.as<double>(), R.max_nbp);
     } else {
       HGL_TRY(allow_lds(k_extract_blocks<uint16_t>, lds_ex));
-      hipLaunchKernelGGL((k_extract_blocks<uint16_t>), grid, dim3(kBlock), lds_ex, s, R.bm, h->vtx_ptr, h->vtx_edge,
+      launch(h, -1, k_extract_blocks<uint16_t>, grid, dim3(kBlock), lds_ex, s, R.bm, h->vtx_ptr, h->vtx_edge,
                          h->edge_ptr, h->edge_vtx, h->s64, h->c64, R.A.as<uint16_t>(), R.max_nbp);
     }
     HGL_HIP(hipGetLastError());
@@ -1105,17 +1105,17 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
   if (!om) {
     HGL_TRY(R.omega.reserve(sizeof(uint16_t) * size_t(h->N) * R.l + 16));
     const int64_t pairs = (int64_t(h->N) * R.l + 1) / 2;
-    hipLaunchKernelGGL(k_philox_sketch, dim3(int((pairs + 255) / 256)), dim3(256), 0, s, int64_t(h->N), R.l,
+    launch(h, -1, k_philox_sketch, dim3(int((pairs + 255) / 256)), dim3(256), 0, s, int64_t(h->N), R.l,
                        o->seed, R.omega.as<uint16_t>());
     om = R.omega.as<uint16_t>();
   }
-  hipLaunchKernelGGL((k_sketch_to_st<TST>), dim3(64, R.nb), dim3(256), 0, s, R.bm, om, R.ST.as<TST>(),
+  launch(h, -1, k_sketch_to_st<TST>, dim3(64, R.nb), dim3(256), 0, s, R.bm, om, R.ST.as<TST>(),
                      R.y_elems);
   HGL_HIP(hipGetLastError());
   // 3. Y = A Omega, S = orth(Y); q subspace iterations
   auto gemm = [&]() -> int {
     prof_begin(h, kProfGemm, s);
-    const int st = launch_gemm(R, s);
+    const int st = launch_gemm(h, R, s);
     prof_end(h, s);
     return st;
   };
@@ -1128,13 +1128,13 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
   // 4. W = A S; B B' = W'W; Jacobi; U = S U~
   HGL_TRY(gemm());  // W in R.Y, basis S in R.S
   prof_begin(h, kProfEig, s);
-  HGL_TRY(launch_gram<TY>(R, R.Y, s));
+  HGL_TRY(launch_gram<TY>(h, R, R.Y, s));
   const int half = (R.l + (R.l & 1)) / 2;
   const size_t lds_j = sizeof(double) * (2 * R.l * R.l + 2 * half) + sizeof(int) * (2 * half + R.l);
   const bool wide = half * (half + 1) / 2 + half * half > 3 * kDense;
   auto jac = wide ? &k_jacobi<4> : &k_jacobi<3>;
   HGL_TRY(allow_lds(jac, lds_j));
-  hipLaunchKernelGGL(jac, dim3(R.nb), dim3(kDense), lds_j, s, R.bm, R.item0_d, R.Gpart.as<double>(), R.sig.as<double>(),
+  launch(h, -1, jac, dim3(R.nb), dim3(kDense), lds_j, s, R.bm, R.item0_d, R.Gpart.as<double>(), R.sig.as<double>(),
                      R.Ut.as<double>(), 30);
   HGL_HIP(hipGetLastError());
   prof_end(h, s);
@@ -1162,10 +1162,10 @@ static int finish_rsvd(hgl_handle* h, Rsvd& R, float* U_out, double* sigma_out, 
   HGL_TRY(with_lp(R.LP, [&](auto c) {
     constexpr int LP = decltype(c)::value;
     if (R.f64)
-      hipLaunchKernelGGL((k_basis<double, LP>), dim3(n_items), dim3(kBlock), 0, s, R.bm, R.S.as<double>(),
+      launch(h, -1, k_basis<double, LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.S.as<double>(),
                          R.Ut.as<double>(), U_out);
     else
-      hipLaunchKernelGGL((k_basis<float, LP>), dim3(n_items), dim3(kBlock), 0, s, R.bm, R.S.as<float>(),
+      launch(h, -1, k_basis<float, LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.S.as<float>(),
                          R.Ut.as<double>(), U_out);
     return HGL_OK;
   }));
@@ -1212,15 +1212,15 @@ static int prec_apply(void* ctx, const T* Rm, int64_t ldr, T* Z, int64_t ldz, do
   hgl_handle* h = P->h;
   const int slabs = (nrhs + 63) / 64;
   const int n_items = int(R.item_b.size());
-  hipLaunchKernelGGL((k_prec_t_tiles<T>), dim3(n_items, slabs), dim3(kBlock), 0, s, R.bm, P->U, Rm, ldr, nrhs,
+  launch(h, -1, k_prec_t_tiles<T>, dim3(n_items, slabs), dim3(kBlock), 0, s, R.bm, P->U, Rm, ldr, nrhs,
                      R.Tpart.as<double>());
-  hipLaunchKernelGGL(k_prec_t_reduce, dim3(R.nb, (R.kk * nrhs + kBlock - 1) / kBlock), dim3(kBlock), 0, s, R.bm,
+  launch(h, -1, k_prec_t_reduce, dim3(R.nb, (R.kk * nrhs + kBlock - 1) / kBlock), dim3(kBlock), 0, s, R.bm,
                      R.item0_d, R.Tpart.as<double>(), R.sig.as<double>(), P->lam, nrhs, slabs, P->dT->as<double>());
   HGL_HIP(hipGetLastError());
   const ColShape cs = pick_shape(nrhs, sizeof(T), {Rm, Z}, {ldr, ldz});
   const double g = P->lam / (1.0 + P->lam);
   return HGL_DISPATCH_SHAPE(cs, sizeof(T), {
-    hipLaunchKernelGGL((k_prec_z<T, GL, V>), dim3(h->n_tiles, cs.slabs), dim3(kBlock), 0, s, R.bm, h->n_tiles,
+    launch(h, -1, k_prec_z<T, GL, V>, dim3(h->n_tiles, cs.slabs), dim3(kBlock), 0, s, R.bm, h->n_tiles,
                        h->tile_r0, h->tile_r1, n_slots(h), h->n_long, P->U, P->dT->as<double>(), g, Rm, ldr, Z,
                        ldz, nrhs, part, gate);
     HGL_HIP(hipGetLastError());

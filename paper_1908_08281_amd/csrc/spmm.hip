@@ -105,7 +105,7 @@ int launch_spmm_edge(const hgl_handle* h, const TIn* P, int64_t ldp, TAcc* Z, in
     constexpr int GPB = kBlock / GL;
     const int n_short = (h->E + GPB - 1) / GPB;
     dim3 grid(n_short + h->n_long_edge, cs.slabs);
-    hipLaunchKernelGGL((k_spmm_edge<TIn, TAcc, GL, V>), grid, dim3(kBlock), 0, st, h->E,
+    launch(h, -1, k_spmm_edge<TIn, TAcc, GL, V>, grid, dim3(kBlock), 0, st, h->E,
                        h->edge_ptr, h->edge_vtx, n_short, h->long_edge, s, c, P, ldp, Z, ldz, k, gate);
     HGL_HIP(hipGetLastError());
     return HGL_OK;
@@ -314,22 +314,22 @@ int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx,
   }
   return HGL_DISPATCH_SHAPE(cs, sizeof(T) > sizeof(TZ) ? sizeof(T) : sizeof(TZ), {
     if (mode == VMode::Apply) {
-      hipLaunchKernelGGL((k_spmm_vertex<T, TZ, GL, V, 0>), grid, dim3(kBlock), 0, st, va, s, X, ldx,
+      launch(h, -1, k_spmm_vertex<T, TZ, GL, V, 0>, grid, dim3(kBlock), 0, st, va, s, X, ldx,
                          Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
       if (h->n_long > 0)
-        hipLaunchKernelGGL((k_spmm_vertex_finish<T, TZ, GL, V, 0>), grid_fin, dim3(kBlock), 0, st, va,
+        launch(h, kProfFinish, k_spmm_vertex_finish<T, TZ, GL, V, 0>, grid_fin, dim3(kBlock), 0, st, va,
                            s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
     } else if (mode == VMode::ApplyDot) {
-      hipLaunchKernelGGL((k_spmm_vertex<T, TZ, GL, V, 1>), grid, dim3(kBlock), 0, st, va, s, X, ldx,
+      launch(h, -1, k_spmm_vertex<T, TZ, GL, V, 1>, grid, dim3(kBlock), 0, st, va, s, X, ldx,
                          Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
       if (h->n_long > 0)
-        hipLaunchKernelGGL((k_spmm_vertex_finish<T, TZ, GL, V, 1>), grid_fin, dim3(kBlock), 0, st, va,
+        launch(h, kProfFinish, k_spmm_vertex_finish<T, TZ, GL, V, 1>, grid_fin, dim3(kBlock), 0, st, va,
                            s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
     } else if constexpr (sizeof(TZ) == 8) {
-      hipLaunchKernelGGL((k_spmm_vertex<T, TZ, GL, V, 2>), grid, dim3(kBlock), 0, st, va, s, X, ldx,
+      launch(h, -1, k_spmm_vertex<T, TZ, GL, V, 2>, grid, dim3(kBlock), 0, st, va, s, X, ldx,
                          Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
       if (h->n_long > 0)
-        hipLaunchKernelGGL((k_spmm_vertex_finish<T, TZ, GL, V, 2>), grid_fin, dim3(kBlock), 0, st, va,
+        launch(h, kProfFinish, k_spmm_vertex_finish<T, TZ, GL, V, 2>, grid_fin, dim3(kBlock), 0, st, va,
                            s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
     }
     HGL_HIP(hipGetLastError());

@@ -58,6 +58,13 @@ class Handle:
               "hgl_get_sizes")
         self.N, self.E, self.nnz, self.G = N.value, E.value, nnz.value, G.value
 
+    def partition(self) -> dict:
+        """Work partition of the operator gathers (row tiles, hub rows and
+        their chunks, hyperedges handled by a whole workgroup)."""
+        v = [C.c_int32() for _ in range(4)]
+        check(lib().hgl_get_partition(self.ptr, *(C.byref(x) for x in v)), "hgl_get_partition")
+        return dict(zip(("tiles", "hub_rows", "hub_chunks", "long_edges"), (x.value for x in v)))
+
     @property
     def ptr(self) -> C.c_void_p:
         if self._ptr is None:
@@ -299,7 +306,8 @@ def project_simplex(v: torch.Tensor, out: torch.Tensor | None = None) -> torch.T
 
 PROFILE_KINDS = {0: "edge_gather", 1: "vertex_gather", 2: "cg_update", 3: "cg_direction",
                  4: "reduce", 5: "resid_edge_gather", 6: "resid_vertex_gather", 7: "start",
-                 8: "precond", 9: "rsvd_gemm", 10: "cholqr", 11: "jacobi", 12: "extract", 13: "grad"}
+                 8: "precond", 9: "rsvd_gemm", 10: "cholqr", 11: "jacobi", 12: "extract", 13: "grad",
+                 14: "hub_row_finish"}
 
 
 def profile(h: Handle, enable: bool) -> None:
