@@ -155,6 +155,21 @@ def _roof(name, n, ms, alg, bound="hbm", traffic=None):
             "avg_launch_us": round(avg * 1e3, 2), "launches": n, "algorithmic_flops_per_launch": int(alg)}
 
 
+def _breakdown(h, fn, n):
+    """Every kernel of `n` further steps timed by launch events (diagnostics,
+    outside the timed region: stamping every launch costs dispatch time)."""
+    import torch
+
+    from paper_1908_08281_amd import hgl
+    hgl.profile(h, True)
+    for _ in range(n):
+        fn()
+    torch.cuda.synchronize()
+    prof = hgl.profile_read(h)
+    hgl.profile(h, False)
+    return _kernel_ms(prof)
+
+
 def _kernel_ms(prof):
     return {k2: [n2, round(m2, 3)] for k2, (n2, m2) in prof.items() if n2}
 
@@ -223,19 +238,22 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
 
     def step():
         if batched:
-            F, it, rel, st = hgl.cg_solve_batched(h, p.lams, Y, mode=mode, tol=tol, rr_period=rr_period)
+            F, it, rel, st = hgl.cg_solve_batched(h, p.lams, Y, mode=mode, tol=tol, rr_period=rr_period,
+                                                  form=a.form)
         else:
-            F, it, rel, st = hgl.cg_solve(h, p.lam, Y, mode=mode, tol=tol, rr_period=rr_period)
+            F, it, rel, st = hgl.cg_solve(h, p.lam, Y, mode=mode, tol=tol, rr_period=rr_period, form=a.form)
         state["ok"] = state["ok"] and st == 0 and bool(np.all(rel <= tol))
         state["iters"].append(int(it.max()))
 
     for _ in range(a.warmup):
         step()
     state["iters"].clear()
-    hgl.profile(h, True)
+    # only the two gather kernels carry launch events in the timed steps
+    hgl.profile(h, True, kinds=["vertex_gather", "edge_gather"])
     dt, _ = _timed(step, a.steps, 0)
     prof = hgl.profile_read(h)
     hgl.profile(h, False)
+    breakdown = _breakdown(h, step, max(2, a.steps // 5))
     G = h.G
     ms = 1e3 * dt / a.steps
     value = a.steps * k * G / dt if state["ok"] else 0.0
@@ -252,11 +270,12 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
     it_mean = float(np.mean(state["iters"]))
     cfg = {"workload": name, "N": p.N, "E": p.E, "nnz": p.nnz, "k": k, "graphs": G,
            "lambda": float(p.lam), "relres_tol": tol,
-           "cg": f"{mode} vectors, fp64 inner products, residual replacement at convergence checks"
+           "cg": f"{a.form} recurrence, {mode} vectors, fp64 inner products, residual replacement at "
+                 f"convergence checks"
                  + (f" and every {rr_period}" if rr_period else ""),
            "iterations": it_mean, "all_columns_converged": state["ok"], "partition": part}
     extra = {"cg_iteration_gbs": round(ab["cg_iteration"] * it_mean / (ms * 1e-3) / 1e9, 1),
-             "kernel_ms": _kernel_ms(prof)}
+             "kernel_ms": breakdown}
     if with_cpu and not a.no_cpu:
         extra["cpu_baseline"] = cpu_cg_baseline(p, tol) if not batched else None
     return _line("solved RHS/s at relres 1e-6" if mode == "f32" else "solved RHS/s at relres 1e-10",
@@ -278,10 +297,11 @@ def bench_rsvd(a):
     om = torch.from_numpy(synth.gaussian_sketch(p.N, l, 11)[0].view(np.int16).copy()).to(dev)
     for _ in range(a.warmup):
         hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om)
-    hgl.profile(h, True)
+    hgl.profile(h, True, kinds=["rsvd_gemm"])
     dt, _ = _timed(lambda: hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om), a.steps, 0)
     prof = hgl.profile_read(h)
     hgl.profile(h, False)
+    breakdown = _breakdown(h, lambda: hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om), max(2, a.steps // 5))
     sizes = np.diff(p.blocks).astype(np.float64)
     gemm_flops = float(np.sum(2.0 * sizes * sizes * l))           # one product A_bb S per block
     n_g, ms_g = prof["rsvd_gemm"]
@@ -303,7 +323,7 @@ def bench_rsvd(a):
     t_cg = time.perf_counter() - t0
     cfg = {"workload": "block_rsvd", "N": p.N, "blocks": nb, "block_rows": "U[500,1500]", "k": k, "p": pp, "q": q,
            "sketch": "bf16 A_bb, split-bf16 basis, fp32 accumulation, fp64 CholQR2 and Jacobi"}
-    extra = {"roofline_hbm": hbm, "kernel_ms": _kernel_ms(prof),
+    extra = {"roofline_hbm": hbm, "kernel_ms": breakdown,
              "refined_solve": {"nrhs": Y.shape[1], "pcg_iters": int(it.max()), "seconds": round(t_inv, 4),
                                "converged": st == 0 and bool(np.all(rel <= tol)),
                                "plain_cg_iters": int(it2.max()), "plain_cg_seconds": round(t_cg, 4)}}
@@ -350,20 +370,22 @@ def bench_learn(a):
     w0 = w.clone()
     wl, recs = learn_weights(h, Y, p.lam, mu, max(a.warmup, 1), w0, tol=tol, history=True)
     eta = recs[0]["eta"]
-    hgl.profile(h, True)
+    hgl.profile(h, True, kinds=["vertex_gather"])
     t0 = time.perf_counter()
     wl, recs = learn_weights(h, Y, p.lam, mu, a.steps, wl, eta=eta, tol=tol, history=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = hgl.profile_read(h)
     hgl.profile(h, False)
-    ab = gather_bytes(p.N, p.E, p.nnz, k, 4)
+    part = h.partition()
+    ab = gather_bytes(p.N, p.E, p.nnz, k, 4, int(np.unique(p.edge_vtx).size), part["hub_rows"])
     nv, mv = prof["vertex_gather"]
-    roof = _roof("vertex_gather", nv, mv, ab["vertex_gather"])
+    roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_gather"])
     cfg = {"workload": "weight_learning", "N": p.N, "E": p.E, "nnz": p.nnz, "k": k, "lambda": p.lam, "mu": mu,
            "eta": eta, "cg_iters_last": recs[-1]["cg_iters"], "adjoint_iters_last": recs[-1]["adjoint_iters"]}
     return _line("projected-gradient steps/s", a.steps / dt, "steps/s", a.steps, a.warmup, 1e3 * dt / a.steps,
-                 "f32", cfg, roof, {"kernel_ms": _kernel_ms(prof)})
+                 "f32", cfg, roof, {"kernel_ms": _breakdown(
+                     h, lambda: learn_weights(h, Y, p.lam, mu, 1, wl, eta=eta, tol=tol), 1)})
 
 
 def main():
@@ -375,6 +397,8 @@ def main():
     ap.add_argument("--workload", default="multi_rhs",
                     help="multi_rhs (default), small, rsvd, learn, batch, or a comma list")
     ap.add_argument("--rr-period", type=int, default=0)
+    ap.add_argument("--form", default="textbook", choices=["textbook", "cg"],
+                    help="CG recurrence: textbook (default) or Chronopoulos-Gear")
     ap.add_argument("--summarize", nargs="+", metavar="ARG",
                     help="write profile summaries and exit: 'stats STATS_CSV WORKLOAD COMMAND' or "
                          "'counters FETCH_CSV WRITE_CSV KERNEL WORKLOAD COMMAND'")

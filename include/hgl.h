@@ -70,6 +70,10 @@ typedef struct hgl_cg_opts {
   int32_t x0_given;   /* 1: F holds the starting guess on entry; 0: start from 0 */
   int32_t rr_period;  /* residual replacement period (F32 mode); 0 = only on claims */
   int32_t chunk;      /* iterations enqueued between host convergence checks; 0 = automatic */
+  int32_t form;       /* recurrence without a preconditioner: 0 = textbook (eqs. 16-20 as
+                         written), 1 = Chronopoulos-Gear (one reduction per iteration, the
+                         same iterates in exact arithmetic); with a preconditioner the
+                         textbook form is always used */
 } hgl_cg_opts;
 
 /* Library version, e.g. 100 for 0.1.0. */
@@ -279,10 +283,12 @@ int hgl_weight_grad(hgl_handle* h, double lambda, double mu, const void* F, int6
 int hgl_project_simplex(const double* v, double* w, int32_t E, hipStream_t stream);
 
 /*
- * Kernel timing (diagnostics).  hgl_profile(h, 1) resets the counters and
- * makes every later solver call on h launch its kernels with start/stop
- * events that the runtime stamps at each kernel's own start and end
- * (hipExtLaunchKernel); hgl_profile(h, 0) stops it.  hgl_profile_read
+ * Kernel timing (diagnostics).  hgl_profile(h, enable) resets the counters;
+ * with enable = 1 every later solver call on h launches its kernels with
+ * start/stop events that the runtime stamps at each kernel's own start and
+ * end (hipExtLaunchKernel); with enable = a bit mask other than 1, only the
+ * kinds whose bit is set (bit k = kind k) carry events, so that timing one
+ * kernel perturbs the rest of the launch stream little; enable = 0 stops it.  hgl_profile_read
  * returns, for one kernel kind, the number of kernel launches recorded and
  * their summed duration in milliseconds (it synchronises the device).
  * Kinds: 0 edge gather (Z = C H' S P), 1 vertex gather with inner product

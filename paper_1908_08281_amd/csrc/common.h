@@ -111,13 +111,16 @@ struct hgl_handle {
   int32_t* chunk_begin = nullptr;    // [n_chunks] position in vtx_edge
   int32_t* chunk_end = nullptr;      // [n_chunks]
   int32_t* long_chunk0 = nullptr;    // [n_long+1] first chunk of each long row
+  int32_t* hub_slot = nullptr;       // [N] index into long_row, -1 for other rows
 
   // hyperedges with more than kLongEdge members, increasing id (device)
   int32_t n_long_edge = 0;
   int32_t* long_edge = nullptr;      // [n_long_edge]
 
-  // per segment: partial-slot ranges {t0, t1, l0, l1} (device, [G*4])
+  // per segment: partial-slot ranges {t0, t1, l0, l1} (device, [G*4]) over
+  // tiles + long rows, and {t0, t1, c0, c1} over tiles + chunks (the CG step)
   int32_t* seg_slots = nullptr;
+  int32_t* seg_slots_cg = nullptr;
   std::vector<int32_t> seg_slots_host;
 
   // scratch owned by the handle
@@ -132,6 +135,7 @@ struct hgl_handle {
 
   // kernel timing (diagnostics)
   bool prof_on = false;
+  uint32_t prof_mask = 0;                             // kinds whose launches are stamped
   std::vector<hipEvent_t> prof_pool;                 // free events
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
   int64_t prof_launches[hgl::kProfKinds] = {0};
@@ -146,6 +150,8 @@ namespace hgl {
 
 // Partial-slot count of the reductions: one per tile, one per long row.
 inline int n_slots(const hgl_handle* h) { return h->n_tiles + h->n_long; }
+// ... and of the CG step's two inner products: one per tile, one per chunk.
+inline int n_slots_cg(const hgl_handle* h) { return h->n_tiles + h->n_chunks; }
 
 int ensure_pinned(hgl_handle* h, size_t n_doubles);
 
@@ -193,7 +199,7 @@ inline void launch(const hgl_handle* hc, int kind, F kernel, dim3 grid, dim3 blo
   hgl_handle* h = const_cast<hgl_handle*>(hc);
   const int kd = kind >= 0 ? kind : h->prof_kind;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (h->prof_on && kd >= 0) {
+  if (h->prof_on && kd >= 0 && ((h->prof_mask >> kd) & 1u)) {
     e0 = prof_event(h);
     e1 = prof_event(h);
   }
@@ -219,6 +225,14 @@ int cg_run(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const voi
 
 // Operator application pieces (spmm.hip).
 enum class VMode { Apply = 0, ApplyDot = 1, Resid = 2 };
+
+// The CG step's vertex gather: W = a X - b s H Z for rows up to the hub
+// threshold, chunk partials of the hub rows into the handle's chunk buffer,
+// partials of <X, X> into part and <X, W> into part2 ([k][n_slots_cg]).
+template <class T>
+int launch_spmm_vertex_cg(const hgl_handle* h, const T* X, int64_t ldx, const T* Z, int64_t ldz, T* W,
+                          int64_t ldw, const double* a_seg, const double* b_seg, double* part, double* part2,
+                          int k, const ColShape& cs, Gate gate, hipStream_t s);
 
 // Z = C H' S P: edge-major gather.  TIn = type of P, TAcc = type of Z.
 template <class TIn, class TAcc>

@@ -876,12 +876,12 @@ __global__ __launch_bounds__(kBlock) void k_prec_z(BlockMeta bm, int32_t n_tiles
   if (part) {
     double s = block_colsum<GL, V>(dot, lds);
     const int c = blockIdx.y * W + threadIdx.x;
-    if (threadIdx.x < W && c < nrhs) part[int64_t(c) * n_slots + t] = s;
+    if (threadIdx.x < W && c < nrhs) part[int64_t(t) * nrhs + c] = s;
     if (blockIdx.y == 0) {
       const int64_t total = int64_t(n_long) * nrhs;
       for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
            i += int64_t(gridDim.x) * blockDim.x)
-        part[(i / n_long) * n_slots + n_tiles + i % n_long] = 0.0;
+        part[int64_t(n_tiles) * nrhs + i] = 0.0;
     }
   }
 }

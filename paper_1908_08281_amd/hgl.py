@@ -151,8 +151,11 @@ def apply(h: Handle, lam: float, P: torch.Tensor, out: torch.Tensor | None = Non
     return Q
 
 
+FORMS = {"textbook": 0, "cg": 1}
+
+
 def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
-        x0: torch.Tensor | None, rr_period: int, chunk: int, batched: bool):
+        x0: torch.Tensor | None, rr_period: int, chunk: int, batched: bool, form: str = "textbook"):
     m = MODES[mode]
     dtype = torch.float64 if m == _lib.HGL_CG_PLAIN_F64 else torch.float32
     _need(Y, dtype, "Y", h.device)
@@ -165,7 +168,8 @@ def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
         F = x0.clone(memory_format=torch.contiguous_format)
     else:
         F = torch.empty((h.N, k), dtype=dtype, device=h.device)
-    opts = CgOpts(m, float(tol), int(max_iter), 1 if x0 is not None else 0, int(rr_period), int(chunk))
+    opts = CgOpts(m, float(tol), int(max_iter), 1 if x0 is not None else 0, int(rr_period), int(chunk),
+                  FORMS[form])
     iters = np.zeros(h.G * k, dtype=np.int32)
     rel = np.zeros(h.G * k, dtype=np.float64)
     with torch.cuda.device(h.device):
@@ -185,16 +189,19 @@ def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
 
 
 def cg_solve(h: Handle, lam: float, Y: torch.Tensor, mode: str = "f32", tol: float = 1e-6,
-             max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8, chunk: int = 0):
-    """Solve (I + L/lam) F = Y.  Returns (F, iters[G,k], relres[G,k], status)."""
-    return _cg(h, lam, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=False)
+             max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8, chunk: int = 0,
+             form: str = "textbook"):
+    """Solve (I + L/lam) F = Y.  Returns (F, iters[G,k], relres[G,k], status).
+    form: "textbook" (eqs. 16-20 as written) or "cg" (Chronopoulos-Gear
+    recurrence, one reduction per iteration)."""
+    return _cg(h, lam, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=False, form=form)
 
 
 def cg_solve_batched(h: Handle, lams, Y: torch.Tensor, mode: str = "f32", tol: float = 1e-6,
                      max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8,
-                     chunk: int = 0):
+                     chunk: int = 0, form: str = "textbook"):
     """One lambda per graph of a batched handle."""
-    return _cg(h, lams, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=True)
+    return _cg(h, lams, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=True, form=form)
 
 
 SKETCH = {"bf16": _lib.HGL_SKETCH_BF16, "f64": _lib.HGL_SKETCH_F64}
@@ -284,7 +291,7 @@ def weight_grad(h: Handle, lam: float, F: torch.Tensor, G: torch.Tensor | None =
         ldy = _rows(Y, "Y")
     grad = torch.empty(h.E, dtype=torch.float64, device=h.device)
     Z = torch.empty((h.N, k), dtype=dtype, device=h.device) if want_z else None
-    opts = CgOpts(m, float(tol), int(max_iter), 0, 0, 0)
+    opts = CgOpts(m, float(tol), int(max_iter), 0, 0, 0, 0)
     iters = np.zeros(k, dtype=np.int32)
     rel = np.zeros(k, dtype=np.float64)
     with torch.cuda.device(h.device):
@@ -310,9 +317,19 @@ PROFILE_KINDS = {0: "edge_gather", 1: "vertex_gather", 2: "cg_update", 3: "cg_di
                  14: "hub_row_finish"}
 
 
-def profile(h: Handle, enable: bool) -> None:
-    """Reset the kernel-timing counters of h and switch event timing on/off."""
-    check(lib().hgl_profile(h.ptr, 1 if enable else 0), "hgl_profile")
+def profile(h: Handle, enable: bool, kinds=None) -> None:
+    """Reset the kernel-timing counters of h and switch event timing on/off.
+    `kinds` (names or numbers of PROFILE_KINDS) limits the stamped launches
+    to those kernels; None stamps every launch."""
+    mask = 1
+    if enable and kinds is not None:
+        names = {v: k for k, v in PROFILE_KINDS.items()}
+        mask = 0
+        for kd in kinds:
+            mask |= 1 << (names[kd] if isinstance(kd, str) else int(kd))
+        if mask == 1:  # kind 0 alone: 1 means "all", so add an unused bit
+            mask |= 1 << 15
+    check(lib().hgl_profile(h.ptr, mask if enable else 0), "hgl_profile")
 
 
 def profile_read(h: Handle) -> dict:

@@ -15,15 +15,16 @@ def _dense_solution(p, lam=None):
     return solve.solve_dense(lap.system_matrix(H, p.w, p.lam if lam is None else lam), p.Y)
 
 
-def test_plain_f64_small_config_matches_cholesky():
+@pytest.mark.parametrize("form", ["cg", "textbook"])
+def test_plain_f64_small_config_matches_cholesky(form):
     """Plain method, small: N=2000, E=1500, k=50, FP64 CG to relres 1e-10."""
     import torch
     dev = device()
     p = synth.small_plain()
-    say("cg f64 small_plain")
+    say("cg f64 small_plain", form)
     h = build(p, dev)
     Y = torch.from_numpy(p.Y).to(dev)
-    F, iters, rel, st = hgl().cg_solve(h, p.lam, Y, mode="f64", tol=1e-10, max_iter=200)
+    F, iters, rel, st = hgl().cg_solve(h, p.lam, Y, mode="f64", tol=1e-10, max_iter=200, form=form)
     assert st == 0
     Fo = _dense_solution(p)
     F = F.cpu().numpy()
@@ -35,16 +36,17 @@ def test_plain_f64_small_config_matches_cholesky():
     assert iters.max() <= 30
 
 
+@pytest.mark.parametrize("form", ["cg", "textbook"])
 @pytest.mark.parametrize("k", [1, 17, 64, 200])
-def test_f32_mixed_matches_oracle(k):
+def test_f32_mixed_matches_oracle(k, form):
     import torch
     dev = device()
     p = synth.multi_rhs(N=4000, E=3200, k=k, smax=150)
-    say("cg f32", k)
+    say("cg f32", k, form)
     h = build(p, dev)
     Y = torch.from_numpy(p.Y).to(dev, torch.float32)
     tol = 1e-6 / (1 + 1 / p.lam)
-    F, iters, rel, st = hgl().cg_solve(h, p.lam, Y, mode="f32", tol=tol, max_iter=300)
+    F, iters, rel, st = hgl().cg_solve(h, p.lam, Y, mode="f32", tol=tol, max_iter=300, form=form)
     assert st == 0
     Fo = _dense_solution(p)
     F = F.cpu().numpy()
