@@ -238,10 +238,9 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
 
     def step():
         if batched:
-            F, it, rel, st = hgl.cg_solve_batched(h, p.lams, Y, mode=mode, tol=tol, rr_period=rr_period,
-                                                  form=a.form)
+            F, it, rel, st = hgl.cg_solve_batched(h, p.lams, Y, mode=mode, tol=tol, rr_period=rr_period)
         else:
-            F, it, rel, st = hgl.cg_solve(h, p.lam, Y, mode=mode, tol=tol, rr_period=rr_period, form=a.form)
+            F, it, rel, st = hgl.cg_solve(h, p.lam, Y, mode=mode, tol=tol, rr_period=rr_period)
         state["ok"] = state["ok"] and st == 0 and bool(np.all(rel <= tol))
         state["iters"].append(int(it.max()))
 
@@ -270,8 +269,7 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
     it_mean = float(np.mean(state["iters"]))
     cfg = {"workload": name, "N": p.N, "E": p.E, "nnz": p.nnz, "k": k, "graphs": G,
            "lambda": float(p.lam), "relres_tol": tol,
-           "cg": f"{a.form} recurrence, {mode} vectors, fp64 inner products, residual replacement at "
-                 f"convergence checks"
+           "cg": f"{mode} vectors, fp64 inner products, residual replacement at convergence checks"
                  + (f" and every {rr_period}" if rr_period else ""),
            "iterations": it_mean, "all_columns_converged": state["ok"], "partition": part}
     extra = {"cg_iteration_gbs": round(ab["cg_iteration"] * it_mean / (ms * 1e-3) / 1e9, 1),
@@ -397,8 +395,6 @@ def main():
     ap.add_argument("--workload", default="multi_rhs",
                     help="multi_rhs (default), small, rsvd, learn, batch, or a comma list")
     ap.add_argument("--rr-period", type=int, default=0)
-    ap.add_argument("--form", default="textbook", choices=["textbook", "cg"],
-                    help="CG recurrence: textbook (default) or Chronopoulos-Gear")
     ap.add_argument("--summarize", nargs="+", metavar="ARG",
                     help="write profile summaries and exit: 'stats STATS_CSV WORKLOAD COMMAND' or "
                          "'counters FETCH_CSV WRITE_CSV KERNEL WORKLOAD COMMAND'")

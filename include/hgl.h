@@ -70,10 +70,6 @@ typedef struct hgl_cg_opts {
   int32_t x0_given;   /* 1: F holds the starting guess on entry; 0: start from 0 */
   int32_t rr_period;  /* residual replacement period (F32 mode); 0 = only on claims */
   int32_t chunk;      /* iterations enqueued between host convergence checks; 0 = automatic */
-  int32_t form;       /* recurrence without a preconditioner: 0 = textbook (eqs. 16-20 as
-                         written), 1 = Chronopoulos-Gear (one reduction per iteration, the
-                         same iterates in exact arithmetic); with a preconditioner the
-                         textbook form is always used */
 } hgl_cg_opts;
 
 /* Library version, e.g. 100 for 0.1.0. */

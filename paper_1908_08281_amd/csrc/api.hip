@@ -248,12 +248,9 @@ __global__ void k_long_fill(int32_t N, const int32_t* __restrict__ vtx_ptr,
                             const int32_t* __restrict__ is_long, const int32_t* __restrict__ slot_of,
                             const int32_t* __restrict__ chunk_of, int32_t* __restrict__ long_row,
                             int32_t* __restrict__ long_chunk0, int32_t* __restrict__ chunk_slot,
-                            int32_t* __restrict__ chunk_begin, int32_t* __restrict__ chunk_end,
-                            int32_t* __restrict__ hub_slot) {
+                            int32_t* __restrict__ chunk_begin, int32_t* __restrict__ chunk_end) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= N) return;
-  hub_slot[v] = is_long[v] ? slot_of[v] : -1;
-  if (!is_long[v]) return;
+  if (v >= N || !is_long[v]) return;
   int slot = slot_of[v];
   int c0 = chunk_of[v];
   long_row[slot] = v;
@@ -309,7 +306,7 @@ static void free_handle(hgl_handle* h) {
   void* ptrs[] = {h->edge_ptr, h->edge_vtx, h->vtx_ptr, h->vtx_edge, h->w, h->dv, h->s64, h->c64,
                   h->s32, h->c32, h->tile_r0, h->tile_r1, h->tile_seg, h->long_row,
                   h->chunk_slot, h->chunk_begin, h->chunk_end, h->long_chunk0,
-                  h->seg_slots, h->long_seg, h->long_edge, h->hub_slot, h->seg_slots_cg};
+                  h->seg_slots, h->long_seg, h->long_edge};
   for (void* p : ptrs)
     if (p) hipFree(p);
   DevBuf* bufs[] = {&h->ws_z, &h->ws_z64, &h->ws_chunk, &h->ws_part, &h->ws_part2,
@@ -496,23 +493,20 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
     B_TRY(dev_alloc(&h->chunk_slot, h->n_chunks));
     B_TRY(dev_alloc(&h->chunk_begin, h->n_chunks));
     B_TRY(dev_alloc(&h->chunk_end, h->n_chunks));
-    B_TRY(dev_alloc(&h->hub_slot, N));
     hipLaunchKernelGGL(k_long_fill, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, h->vtx_ptr,
                        is_long, slot_of, chunk_of, h->long_row, h->long_chunk0, h->chunk_slot,
-                       h->chunk_begin, h->chunk_end, h->hub_slot);
+                       h->chunk_begin, h->chunk_end);
     B_HIP(hipGetLastError());
     B_HIP(hipMemcpyAsync(h->long_chunk0 + h->n_long, &h->n_chunks, sizeof(int32_t),
                          hipMemcpyHostToDevice, s));
     B_HIP(hipFreeAsync(tmpi, s));
     // per-graph slot ranges: long rows are listed in increasing vertex id, so
     // each graph's long rows are contiguous
-    std::vector<int32_t> lr(h->n_long), lc0(h->n_long + 1);
+    std::vector<int32_t> lr(h->n_long);
     if (h->n_long)
       B_HIP(hipMemcpyAsync(lr.data(), h->long_row, 4 * size_t(h->n_long), hipMemcpyDeviceToHost, s));
-    B_HIP(hipMemcpyAsync(lc0.data(), h->long_chunk0, 4 * size_t(h->n_long + 1), hipMemcpyDeviceToHost, s));
     B_HIP(hipStreamSynchronize(s));
     h->seg_slots_host.assign(4 * G, 0);
-    std::vector<int32_t> seg_cg(4 * G, 0);
     int t = 0, l = 0;
     std::vector<int32_t> lseg(h->n_long);
     for (int g = 0; g < G; ++g) {
@@ -525,19 +519,12 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
       h->seg_slots_host[4 * g + 1] = t;
       h->seg_slots_host[4 * g + 2] = h->n_tiles + l0;
       h->seg_slots_host[4 * g + 3] = h->n_tiles + l;
-      // the chunks of a graph's long rows are contiguous too
-      seg_cg[4 * g + 0] = t0;
-      seg_cg[4 * g + 1] = t;
-      seg_cg[4 * g + 2] = h->n_tiles + lc0[l0];
-      seg_cg[4 * g + 3] = h->n_tiles + lc0[l];
     }
     B_TRY(dev_alloc(&h->long_seg, h->n_long));
     if (h->n_long)
       B_HIP(hipMemcpyAsync(h->long_seg, lseg.data(), 4 * size_t(h->n_long), hipMemcpyHostToDevice, s));
     B_TRY(dev_alloc(&h->seg_slots, 4 * G));
     B_HIP(hipMemcpyAsync(h->seg_slots, h->seg_slots_host.data(), 16 * size_t(G), hipMemcpyHostToDevice, s));
-    B_TRY(dev_alloc(&h->seg_slots_cg, 4 * G));
-    B_HIP(hipMemcpyAsync(h->seg_slots_cg, seg_cg.data(), 16 * size_t(G), hipMemcpyHostToDevice, s));
     B_HIP(hipStreamSynchronize(s));
   }
   // ---- long hyperedges (one workgroup each in the edge gather)

@@ -2,21 +2,14 @@
 // own recurrence (paper, section 3, eqs. 16-20):
 //   alpha = r'r / p'Mp,  f += alpha p,  r -= alpha Mp,
 //   beta = r_new'r_new / r'r,  p = r + beta p.
-// The textbook sequence (below) is the default.  Without a preconditioner the
-// recurrence can instead be carried in the Chronopoulos-Gear form (opts->form
-// = 1; one reduction per iteration, the same iterates in exact arithmetic):
-//   W = M R, gamma = r'r, delta = w'r,
-//   beta = gamma / gamma_old, alpha = gamma / (delta - beta gamma / alpha_old),
-//   P = R + beta P, S = W + beta S (S = M P), F += alpha P, R -= alpha S,
-// four launches per iteration: edge gather (Z = C H' S R) -> vertex gather
-// (W, partials of gamma and delta) -> reduce (alpha, beta, convergence)
-// -> fused update.  The textbook sequence (always used with a preconditioner):
+// One iteration is a fixed sequence of launches on one stream:
 //   edge gather (Z = C H' S P) -> vertex gather (Q = M P, partial p'Q)
-//   -> reduce: alpha -> update (F, R, partial r'r) -> [preconditioner]
-//   -> reduce: beta, convergence -> direction update (P = Z + beta P).
+//   [-> hub-row finish] -> reduce: alpha -> update (F, R, partial r'r)
+//   -> [preconditioner] -> reduce: beta, convergence
+//   -> direction update (P = R + beta P, or Z + beta P with a preconditioner).
 // Residual replacement (R = Y - M F with FP64 accumulation) runs at host
-// checks and optionally every rr_period iterations; after it the Chronopoulos-
-// Gear recurrence restarts from the recomputed residual (beta = 0).
+// checks and optionally every rr_period iterations; the recursion continues
+// from the recomputed residual with the same search direction.
 // Inner products are accumulated in FP64 per workgroup and reduced in a fixed
 // order (deterministic).  Converged columns get alpha = 0; once every column
 // has converged the remaining launches of an enqueued chunk return at once.
@@ -38,7 +31,6 @@ struct CgState {
   double* rz;      // [G*k] r'z (preconditioned) or r'r
   int32_t* state;  // [G*k]
   int32_t* iters;  // [G*k]
-  int32_t* first;  // [G*k] 1: the next Chronopoulos-Gear step restarts (beta = 0)
 };
 
 // ------------------------------------------------------- row-stream kernels --
@@ -185,75 +177,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(
   }
 }
 
-// Chronopoulos-Gear update: P = R + beta P, S = W + beta S (P = R, S = W at a
-// restart, beta = 0: the old P, S are not read), F += alpha P, R -= alpha S.
-// A hub row's W was not written by the vertex gather: it is a R - b s_r
-// (sum of the row's chunk partials, in chunk order).
-template <class T, int GL, int V>
-__global__ __launch_bounds__(kBlock) void k_cg_step_update(
-    const int32_t* __restrict__ tile_r0, const int32_t* __restrict__ tile_r1, const int32_t* __restrict__ tile_seg,
-    const int32_t* __restrict__ hub_slot, const int32_t* __restrict__ long_chunk0, const T* __restrict__ chunk_part,
-    const T* __restrict__ s, const double* __restrict__ a_seg, const double* __restrict__ b_seg,
-    T* __restrict__ F, int64_t ldf, T* __restrict__ R, T* __restrict__ P, T* __restrict__ S,
-    const T* __restrict__ Wv, int64_t ld, const double* __restrict__ alpha, const double* __restrict__ beta, int k,
-    Gate gate) {
-  if (gate.skip()) return;
-  constexpr int GPB = kBlock / GL, W = GL * V;
-  const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
-  const int col = blockIdx.y * W + lane * V;
-  const int t = blockIdx.x;
-  if (col >= k) return;
-  const int g = tile_seg[t];
-  T al[V], be[V];
-  bool restart = true;
-#pragma unroll
-  for (int i = 0; i < V; ++i) {
-    al[i] = T(alpha[int64_t(g) * k + col + i]);
-    be[i] = T(beta[int64_t(g) * k + col + i]);
-    restart = restart && be[i] == T(0);
-  }
-  const T a = T(a_seg[g]), bb = T(b_seg[g]);
-  for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
-    const int hs = hub_slot[r];
-    T rv[V], wv[V], pv[V], sv[V], fv[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) pv[i] = sv[i] = T(0);
-    load_row<V>(R + int64_t(r) * ld + col, rv);
-    load_row<V>(F + int64_t(r) * ldf + col, fv);
-    if (!restart) {
-      load_row<V>(P + int64_t(r) * ld + col, pv);
-      load_row<V>(S + int64_t(r) * ld + col, sv);
-    }
-    load_row<V>(Wv + int64_t(r) * ld + col, wv);  // stale for a hub row (rebuilt below)
-    if (hs >= 0) {
-      T acc[V];
-#pragma unroll
-      for (int i = 0; i < V; ++i) acc[i] = T(0);
-      for (int ch = long_chunk0[hs]; ch < long_chunk0[hs + 1]; ++ch) {
-        T cpv[V];
-        load_row<V>(chunk_part + int64_t(ch) * k + col, cpv);
-#pragma unroll
-        for (int i = 0; i < V; ++i) acc[i] += cpv[i];
-      }
-      const T sr = s[r];
-#pragma unroll
-      for (int i = 0; i < V; ++i) wv[i] = a * rv[i] - bb * sr * acc[i];
-    }
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      // a column with beta = 0 restarts: the old P, S may hold anything
-      pv[i] = be[i] == T(0) ? rv[i] : rv[i] + be[i] * pv[i];
-      sv[i] = be[i] == T(0) ? wv[i] : wv[i] + be[i] * sv[i];
-      fv[i] += al[i] * pv[i];
-      rv[i] -= al[i] * sv[i];
-    }
-    store_row<V>(P + int64_t(r) * ld + col, pv);
-    store_row<V>(S + int64_t(r) * ld + col, sv);
-    store_row<V>(F + int64_t(r) * ldf + col, fv);
-    store_row<V>(R + int64_t(r) * ld + col, rv);
-  }
-}
-
 // --------------------------------------------------------------- reductions --
 
 // Partial sums are stored slot-major, part[slot][k]: the workgroup that
@@ -291,13 +214,13 @@ __device__ __forceinline__ double slot_sum(const double* __restrict__ part, int 
   return tot;
 }
 
-enum class RedOp { Init, Alpha, Beta, Check, Step };
+enum class RedOp { Init, Alpha, Beta, Check };
 
 struct RedArgs {
   int G, k, n_slots;
   const int32_t* seg_slots;
-  const double* part;   // r'r (Init, Beta, Check, Step) or p'Mp (Alpha)
-  const double* part2;  // y'y (Init) or w'r (Step)
+  const double* part;   // r'r (Init, Beta, Check) or p'Mp (Alpha)
+  const double* part2;  // y'y (Init)
   const double* part3;  // r'z (Init, Beta, Check) when preconditioned
   double tol;
   int iter;             // iteration index
@@ -328,7 +251,7 @@ struct Words {
 template <RedOp OP>
 __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState st, Words wd) {
   const int it = ra.iter;
-  if constexpr (OP == RedOp::Alpha || OP == RedOp::Beta || OP == RedOp::Step) {
+  if constexpr (OP == RedOp::Alpha || OP == RedOp::Beta) {
     if (*wd.cnt(it - 1) == 0) return;
   }
   __shared__ double lds[kRedStripes][kRedCols + 1];
@@ -338,9 +261,9 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
   const int col = (blockIdx.x % ngrp) * kRedCols + threadIdx.x % kRedCols;
   const double sum = slot_sum(ra.part, ra.k, ra.seg_slots, g, col, lds);
   double sum2 = 0.0;
-  if constexpr (OP == RedOp::Init || OP == RedOp::Step) sum2 = slot_sum(ra.part2, ra.k, ra.seg_slots, g, col, lds);
+  if constexpr (OP == RedOp::Init) sum2 = slot_sum(ra.part2, ra.k, ra.seg_slots, g, col, lds);
   double rz = sum;  // r'z, = r'r without a preconditioner
-  if constexpr (OP != RedOp::Alpha && OP != RedOp::Step) {
+  if constexpr (OP != RedOp::Alpha) {
     if (ra.has_prec) rz = slot_sum(ra.part3, ra.k, ra.seg_slots, g, col, lds);
   }
   if (threadIdx.x >= kRedCols || col >= ra.k) return;
@@ -352,7 +275,6 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
     st.iters[id] = 0;
     st.alpha[id] = 0.0;
     st.beta[id] = 0.0;
-    st.first[id] = 1;
     double rel = sum2 > 0.0 ? sqrt(sum / sum2) : sqrt(sum);
     st.relres[id] = rel;
     const bool done = sum2 == 0.0 || rel <= ra.tol;
@@ -403,50 +325,12 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
     if (st.state[id] != kActive) return;
     const double rel = st.yy[id] > 0.0 ? sqrt(sum / st.yy[id]) : sqrt(sum);
     st.relres[id] = rel;
-    // residual replacement: the textbook recursion continues from the
-    // recomputed residual with the same search direction; the
-    // Chronopoulos-Gear recursion restarts from it (first = 1)
+    // residual replacement: the recursion continues from the recomputed
+    // residual with the same search direction
     st.rr[id] = sum;
     st.rz[id] = rz;
-    st.first[id] = 1;
     if (rel <= ra.tol) st.state[id] = kDone;
     else atomicAdd(wd.chk(it), 1);
-  } else if constexpr (OP == RedOp::Step) {
-    // Chronopoulos-Gear: sum = gamma = r'r, sum2 = delta = w'r of r_it
-    st.beta[id] = 0.0;
-    if (st.state[id] != kActive) {
-      st.alpha[id] = 0.0;
-      return;
-    }
-    if (!isfinite(sum) || !isfinite(sum2)) {
-      st.alpha[id] = 0.0;
-      st.state[id] = kBreakdown;
-      atomicOr(wd.err(), 1);
-      return;
-    }
-    if (sum == 0.0) {  // exact solution
-      st.alpha[id] = 0.0;
-      st.relres[id] = 0.0;
-      st.state[id] = kDone;
-      return;
-    }
-    const bool restart = st.first[id] != 0;
-    const double beta = restart ? 0.0 : sum / st.rr[id];
-    const double den = restart ? sum2 : sum2 - beta * sum / st.alpha[id];
-    if (!(den > 0.0) || !isfinite(den)) {
-      st.alpha[id] = 0.0;
-      st.state[id] = kBreakdown;
-      atomicOr(wd.err(), 1);
-      return;
-    }
-    st.alpha[id] = sum / den;
-    st.beta[id] = beta;
-    st.rr[id] = sum;
-    st.first[id] = 0;
-    st.iters[id] += 1;
-    atomicAdd(wd.cnt(it), 1);
-    atomicMax(reinterpret_cast<unsigned long long*>(wd.rmax(it)),
-              static_cast<unsigned long long>(__double_as_longlong(sqrt(sum / st.yy[id]))));
   }
 }
 
@@ -456,8 +340,7 @@ template <class T>
 struct CgBuffers {
   T* R;
   T* P;
-  T* Q;        // M P (textbook form) or W = M R (Chronopoulos-Gear form)
-  T* S;        // M P by recurrence (Chronopoulos-Gear form)
+  T* Q;        // M P
   T* Z;        // E x k, type T
   double* Z64; // E x k FP64 (residual passes of the FP32 mode)
   double* part;
@@ -473,21 +356,19 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
                   hipStream_t s) {
   const bool fp32 = sizeof(T) == 4;
   const bool has_prec = prec != nullptr;
-  const bool cgs = !has_prec && o->form == 1;  // Chronopoulos-Gear form
   const int N = h->N, E = h->E, G = h->G;
   const int64_t ld = k;  // internal vectors
   const int nsl = n_slots(h);
   // ---------------------------------------------------------- workspace
   const size_t vec = sizeof(T) * size_t(N) * ld;
-  HGL_TRY(h->ws_vec.reserve(4 * vec + 256));
+  HGL_TRY(h->ws_vec.reserve((has_prec ? 4 : 3) * vec + 256));
   HGL_TRY(h->ws_z.reserve(sizeof(T) * size_t(std::max(E, 1)) * ld));
   if (fp32) HGL_TRY(h->ws_z64.reserve(sizeof(double) * size_t(std::max(E, 1)) * ld));
-  const int nsl_max = std::max(nsl, n_slots_cg(h));
-  HGL_TRY(h->ws_part.reserve(sizeof(double) * size_t(nsl_max) * k));
-  HGL_TRY(h->ws_part2.reserve(sizeof(double) * size_t(nsl_max) * k));
+  HGL_TRY(h->ws_part.reserve(sizeof(double) * size_t(nsl) * k));
+  HGL_TRY(h->ws_part2.reserve(sizeof(double) * size_t(nsl) * k));
   if (has_prec) HGL_TRY(h->ws_extra[0].reserve(sizeof(double) * size_t(nsl) * k));
   const size_t gk = size_t(G) * k;
-  HGL_TRY(h->ws_state.reserve(sizeof(double) * 6 * gk + sizeof(int32_t) * (3 * gk + 2 + Words::count(o->max_iter))));
+  HGL_TRY(h->ws_state.reserve(sizeof(double) * 6 * gk + sizeof(int32_t) * (2 * gk + 2 + Words::count(o->max_iter))));
   HGL_TRY(ensure_pinned(h, 2 * gk + 8));
   if (h->n_chunks > 0) HGL_TRY(h->ws_chunk.reserve(sizeof(double) * size_t(h->n_chunks) * k));
   HGL_TRY(upload_ab(h, lambdas, s));
@@ -504,7 +385,6 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   b.part2 = h->ws_part2.as<double>();
   b.part3 = has_prec ? h->ws_extra[0].as<double>() : nullptr;
   b.Zp = has_prec ? b.Q + size_t(N) * ld : nullptr;
-  b.S = cgs ? b.Q + size_t(N) * ld : nullptr;
   double* sd = h->ws_state.as<double>();
   b.st.yy = sd;
   b.st.rr = sd + gk;
@@ -514,9 +394,8 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   b.st.rz = sd + 5 * gk;
   b.st.state = reinterpret_cast<int32_t*>(sd + 6 * gk);
   b.st.iters = b.st.state + gk;
-  b.st.first = b.st.iters + gk;
   // flag words start 8-byte aligned (they hold FP64 maxima)
-  int32_t* words = b.st.first + gk;
+  int32_t* words = b.st.iters + gk;
   if (reinterpret_cast<uintptr_t>(words) % 8 != 0) ++words;
   Words wd{words, o->max_iter};
   if (reinterpret_cast<uintptr_t>(wd.rmax(0)) % alignof(double) != 0) {
@@ -574,40 +453,6 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   prof_end(h, s);
 
   // ---------------------------------------------------------- iterations
-  // Chronopoulos-Gear iteration (no preconditioner)
-  const RedArgs ra_step{G, k, n_slots_cg(h), h->seg_slots_cg, b.part, b.part2, nullptr, o->tol, 0, 0, 0};
-  auto iteration_cgs = [&](int it) -> int {
-    Gate g_prev{wd.cnt(it - 1), nullptr, 1};
-    prof_begin(h, kProfEdge, s);
-    HGL_TRY(launch_spmm_edge<T, T>(h, b.R, ld, b.Z, ld, k, cs, g_prev, s));
-    prof_end(h, s);
-    prof_begin(h, kProfVertex, s);
-    HGL_TRY(launch_spmm_vertex_cg<T>(h, b.R, ld, b.Z, ld, b.Q, ld, a_seg, b_seg, b.part, b.part2, k, cs, g_prev, s));
-    prof_end(h, s);
-    RedArgs r = ra_step;
-    r.iter = it;
-    prof_begin(h, kProfReduce, s);
-    launch(h, -1, k_cg_reduce<RedOp::Step>, dim3(red_blocks), dim3(kRedThreads), 0, s, r, b.st, wd);
-    HGL_HIP(hipGetLastError());
-    prof_end(h, s);
-    Gate g_now{wd.cnt(it), nullptr, 1};
-    prof_begin(h, kProfUpdate, s);
-    int rc2 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
-      dim3 grid(h->n_tiles, cs.slabs);
-      const T* sc;
-      if constexpr (sizeof(T) == 8) sc = h->s64; else sc = h->s32;
-      launch(h, -1, k_cg_step_update<T, GL, V>, grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1, h->tile_seg,
-             h->hub_slot, h->long_chunk0, static_cast<const T*>(h->ws_chunk.as<T>()), sc, a_seg, b_seg, F, ldf,
-             b.R, b.P, b.S, static_cast<const T*>(b.Q), ld, static_cast<const double*>(b.st.alpha),
-             static_cast<const double*>(b.st.beta), k, g_now);
-      HGL_HIP(hipGetLastError());
-      return HGL_OK;
-    });
-    HGL_TRY(rc2);
-    prof_end(h, s);
-    return HGL_OK;
-  };
-
   auto iteration = [&](int it) -> int {
     Gate g_prev{wd.cnt(it - 1), nullptr, 1};
     prof_begin(h, kProfEdge, s);
@@ -689,16 +534,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   int next = o->chunk > 0 ? o->chunk : 3;
   while (!all_done && it < o->max_iter) {
     const int n = std::min(next, o->max_iter - it);
-    for (int c = 0; c < n; ++c, ++it) {
-      if (cgs) {
-        HGL_TRY(iteration_cgs(it));
-        // periodic residual replacement (no host decision): recompute R,
-        // restart the recurrence of the columns that go on
-        if (o->rr_period > 0 && (it + 1) % o->rr_period == 0 && it + 1 < o->max_iter) HGL_TRY(check(it + 1));
-      } else {
-        HGL_TRY(iteration(it));
-      }
-    }
+    for (int c = 0; c < n; ++c, ++it) HGL_TRY(iteration(it));
     HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.cnt(it - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HGL_HIP(hipMemcpyAsync(h->pinned_d, wd.rmax(it - 1), sizeof(double), hipMemcpyDeviceToHost, s));
     HGL_HIP(hipStreamSynchronize(s));
@@ -709,10 +545,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     const double r_now = h->pinned_d[0];
     const double rate = (r_now > 0.0 && r_ref > 0.0 && it > it_ref)
                             ? std::pow(r_now / r_ref, 1.0 / double(it - it_ref)) : 1.0;
-    // the Chronopoulos-Gear step measures the residual before its update:
-    // the iterate is one contraction further on
-    const double r_eff = (cgs && rate < 1.0) ? r_now * rate : r_now;
-    if (r_eff <= claim * o->tol) {
+    if (r_now <= claim * o->tol) {
       HGL_TRY(check(it));
       HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.chk(it), sizeof(int32_t), hipMemcpyDeviceToHost, s));
       HGL_HIP(hipStreamSynchronize(s));
@@ -724,7 +557,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     if (!(rate < 0.999)) {
       next = 4;
     } else {
-      const double m = std::ceil(std::log(claim * o->tol / r_eff) / std::log(rate));
+      const double m = std::ceil(std::log(claim * o->tol / r_now) / std::log(rate));
       next = int(std::min(64.0, std::max(1.0, m)));
     }
     r_ref = r_now;
@@ -766,7 +599,6 @@ int cg_run(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const voi
   HGL_CHECK_ARG(Y && F, "Y and F must not be NULL");
   HGL_CHECK_ARG(ldy >= k && ldf >= k, "leading dimensions must be >= k");
   HGL_CHECK_ARG(o->rr_period >= 0, "rr_period must be >= 0");
-  HGL_CHECK_ARG(o->form == 0 || o->form == 1, "form must be 0 (textbook) or 1 (Chronopoulos-Gear)");
   if (o->mode == HGL_CG_PLAIN_F64)
     return run_cg<double>(h, lambdas, o, static_cast<const double*>(Y), ldy, static_cast<double*>(F),
                           ldf, k, iters_host, relres_host, prec, s);

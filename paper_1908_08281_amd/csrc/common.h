@@ -111,16 +111,14 @@ struct hgl_handle {
   int32_t* chunk_begin = nullptr;    // [n_chunks] position in vtx_edge
   int32_t* chunk_end = nullptr;      // [n_chunks]
   int32_t* long_chunk0 = nullptr;    // [n_long+1] first chunk of each long row
-  int32_t* hub_slot = nullptr;       // [N] index into long_row, -1 for other rows
 
   // hyperedges with more than kLongEdge members, increasing id (device)
   int32_t n_long_edge = 0;
   int32_t* long_edge = nullptr;      // [n_long_edge]
 
   // per segment: partial-slot ranges {t0, t1, l0, l1} (device, [G*4]) over
-  // tiles + long rows, and {t0, t1, c0, c1} over tiles + chunks (the CG step)
+  // tiles + long rows
   int32_t* seg_slots = nullptr;
-  int32_t* seg_slots_cg = nullptr;
   std::vector<int32_t> seg_slots_host;
 
   // scratch owned by the handle
@@ -150,8 +148,6 @@ namespace hgl {
 
 // Partial-slot count of the reductions: one per tile, one per long row.
 inline int n_slots(const hgl_handle* h) { return h->n_tiles + h->n_long; }
-// ... and of the CG step's two inner products: one per tile, one per chunk.
-inline int n_slots_cg(const hgl_handle* h) { return h->n_tiles + h->n_chunks; }
 
 int ensure_pinned(hgl_handle* h, size_t n_doubles);
 
@@ -225,14 +221,6 @@ int cg_run(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const voi
 
 // Operator application pieces (spmm.hip).
 enum class VMode { Apply = 0, ApplyDot = 1, Resid = 2 };
-
-// The CG step's vertex gather: W = a X - b s H Z for rows up to the hub
-// threshold, chunk partials of the hub rows into the handle's chunk buffer,
-// partials of <X, X> into part and <X, W> into part2 ([k][n_slots_cg]).
-template <class T>
-int launch_spmm_vertex_cg(const hgl_handle* h, const T* X, int64_t ldx, const T* Z, int64_t ldz, T* W,
-                          int64_t ldw, const double* a_seg, const double* b_seg, double* part, double* part2,
-                          int k, const ColShape& cs, Gate gate, hipStream_t s);
 
 // Z = C H' S P: edge-major gather.  TIn = type of P, TAcc = type of Z.
 template <class TIn, class TAcc>

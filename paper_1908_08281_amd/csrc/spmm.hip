@@ -134,20 +134,11 @@ struct VertexArgs {
 
 // MODE 0: Out = a X - b s H Z.  MODE 1: same + partial <X, Out>.
 // MODE 2: Out = Y - (a X - b s H Z), partial <Out, Out>, all in TZ (FP64).
-// MODE 3 (the CG step): Out = a X - b s H Z for the rows up to the hub
-// threshold, partials <X, X> (into part) and <X, Out> (into part2) over
-// n_slots_cg = tiles + chunks slots.  A hub row's Out is left to the
-// consumer, which sums the row's chunk partials; its share of both inner
-// products is written by its chunks: <X, Out> is linear in the chunk sums,
-//   <x, a x - b s_r sum_c cp_c> = a <x, x> - b s_r sum_c <x, cp_c>,
-// so chunk c writes -b s_r <x, cp_c> (plus a <x, x> and <x, x> when it is
-// the row's first chunk), and no separate finishing launch is needed.
 template <class T, class TZ, int GL, int V, int MODE>
 __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
     VertexArgs va, const TZ* __restrict__ s, const T* __restrict__ X, int64_t ldx,
     const TZ* __restrict__ Z, int64_t ldz, const T* __restrict__ Y, int64_t ldy, T* __restrict__ Out,
-    int64_t ldo, double* __restrict__ part, TZ* __restrict__ chunk_part, int k, Gate gate,
-    double* __restrict__ part2, int32_t n_slots_cg) {
+    int64_t ldo, double* __restrict__ part, TZ* __restrict__ chunk_part, int k, Gate gate) {
   if (gate.skip()) return;
   constexpr int GPB = kBlock / GL;
   constexpr int W = GL * V;
@@ -174,9 +165,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
     const int staged = min(s_ptr[nr] - base, kStageIdx);
     for (int i = threadIdx.x; i < staged; i += kBlock) s_idx[i] = va.vtx_edge[base + i];
     __syncthreads();
-    double dot[V], dot2[V];
+    double dot[V];
 #pragma unroll
-    for (int i = 0; i < V; ++i) dot[i] = dot2[i] = 0.0;
+    for (int i = 0; i < V; ++i) dot[i] = 0.0;
     for (int r = r0 + grp; r < r1 && colok; r += GPB) {
       const int eb = s_ptr[r - r0], ee = s_ptr[r - r0 + 1];
       if (ee - eb > kLongRow) continue;  // finished by its chunks
@@ -205,23 +196,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
           TZ q = a * TZ(x[i]) - bb * sr * acc[i];
           o[i] = T(q);
           if constexpr (MODE == 1) dot[i] += double(x[i]) * double(o[i]);
-          if constexpr (MODE == 3) {
-            dot[i] += double(x[i]) * double(x[i]);
-            dot2[i] += double(x[i]) * double(o[i]);
-          }
         }
       }
       store_row<V>(Out + int64_t(r) * ldo + col, o);
     }
-    if constexpr (MODE == 3) {
-      const double tot = block_colsum<GL, V>(dot, lds_d);
-      const double tot2 = block_colsum<GL, V>(dot2, lds_d);
-      const int c = blockIdx.y * W + threadIdx.x;
-      if (threadIdx.x < W && c < k) {
-        part[int64_t(t) * k + c] = tot;
-        part2[int64_t(t) * k + c] = tot2;
-      }
-    } else if constexpr (MODE != 0) {
+    if constexpr (MODE != 0) {
       double tot = block_colsum<GL, V>(dot, lds_d);
       const int c = blockIdx.y * W + threadIdx.x;
       if (threadIdx.x < W && c < k) part[int64_t(t) * k + c] = tot;
@@ -245,18 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
   }
   TZ csum = block_colsum<GL, V>(acc, lds_z);
   const int c = blockIdx.y * W + threadIdx.x;
-  if (threadIdx.x >= W || c >= k) return;
-  chunk_part[int64_t(ch) * k + c] = csum;
-  if constexpr (MODE == 3) {
-    const int r = va.long_row[slot];
-    const int g = va.long_seg[slot];
-    const bool first = ch == va.long_chunk0[slot];
-    const double x = double(X[int64_t(r) * ldx + c]);
-    const double xx = first ? x * x : 0.0;
-    part[int64_t(va.n_tiles + ch) * k + c] = xx;
-    part2[int64_t(va.n_tiles + ch) * k + c] =
-        va.a_seg[g] * xx - va.b_seg[g] * double(s[r]) * x * double(csum);
-  }
+  if (threadIdx.x < W && c < k) chunk_part[int64_t(ch) * k + c] = csum;
 }
 
 // Finish the long rows (one workgroup per row and column slab): sum the
@@ -347,22 +315,19 @@ int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx,
   return HGL_DISPATCH_SHAPE(cs, sizeof(T) > sizeof(TZ) ? sizeof(T) : sizeof(TZ), {
     if (mode == VMode::Apply) {
       launch(h, -1, k_spmm_vertex<T, TZ, GL, V, 0>, grid, dim3(kBlock), 0, st, va, s, X, ldx,
-                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate,
-                         static_cast<double*>(nullptr), 0);
+                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
       if (h->n_long > 0)
         launch(h, kProfFinish, k_spmm_vertex_finish<T, TZ, GL, V, 0>, grid_fin, dim3(kBlock), 0, st, va,
                            s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
     } else if (mode == VMode::ApplyDot) {
       launch(h, -1, k_spmm_vertex<T, TZ, GL, V, 1>, grid, dim3(kBlock), 0, st, va, s, X, ldx,
-                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate,
-                         static_cast<double*>(nullptr), 0);
+                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
       if (h->n_long > 0)
         launch(h, kProfFinish, k_spmm_vertex_finish<T, TZ, GL, V, 1>, grid_fin, dim3(kBlock), 0, st, va,
                            s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
     } else if constexpr (sizeof(TZ) == 8) {
       launch(h, -1, k_spmm_vertex<T, TZ, GL, V, 2>, grid, dim3(kBlock), 0, st, va, s, X, ldx,
-                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate,
-                         static_cast<double*>(nullptr), 0);
+                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
       if (h->n_long > 0)
         launch(h, kProfFinish, k_spmm_vertex_finish<T, TZ, GL, V, 2>, grid_fin, dim3(kBlock), 0, st, va,
                            s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
@@ -371,37 +336,6 @@ int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx,
     return HGL_OK;
   });
 }
-
-template <class T>
-int launch_spmm_vertex_cg(const hgl_handle* h, const T* X, int64_t ldx, const T* Z, int64_t ldz, T* Wout,
-                          int64_t ldw, const double* a_seg, const double* b_seg, double* part, double* part2,
-                          int k, const ColShape& cs, Gate gate, hipStream_t st) {
-  hgl_handle* hm = const_cast<hgl_handle*>(h);
-  if (h->n_chunks > 0 && hm->ws_chunk.bytes < sizeof(T) * size_t(h->n_chunks) * k) {
-    HGL_HIP(hipStreamSynchronize(st));
-    HGL_TRY(hm->ws_chunk.reserve(sizeof(T) * size_t(h->n_chunks) * k));
-  }
-  VertexArgs va{h->n_tiles,  h->tile_r0,     h->tile_r1,   h->tile_seg, h->vtx_ptr,
-                h->vtx_edge, h->chunk_slot,  h->chunk_begin, h->chunk_end, h->long_row,
-                h->long_seg, h->long_chunk0, n_slots(h),  a_seg,       b_seg};
-  const T* s;
-  if constexpr (sizeof(T) == 8) s = h->s64; else s = h->s32;
-  T* cp = hm->ws_chunk.as<T>();
-  dim3 grid(h->n_tiles + h->n_chunks, cs.slabs);
-  return HGL_DISPATCH_SHAPE(cs, sizeof(T), {
-    launch(h, -1, k_spmm_vertex<T, T, GL, V, 3>, grid, dim3(kBlock), 0, st, va, s, X, ldx, Z, ldz,
-           static_cast<const T*>(nullptr), int64_t(0), Wout, ldw, part, cp, k, gate, part2, n_slots_cg(h));
-    HGL_HIP(hipGetLastError());
-    return HGL_OK;
-  });
-}
-
-template int launch_spmm_vertex_cg<float>(const hgl_handle*, const float*, int64_t, const float*, int64_t, float*,
-                                          int64_t, const double*, const double*, double*, double*, int,
-                                          const ColShape&, Gate, hipStream_t);
-template int launch_spmm_vertex_cg<double>(const hgl_handle*, const double*, int64_t, const double*, int64_t,
-                                           double*, int64_t, const double*, const double*, double*, double*, int,
-                                           const ColShape&, Gate, hipStream_t);
 
 template int launch_spmm_edge<float, float>(const hgl_handle*, const float*, int64_t, float*,
                                             int64_t, int, const ColShape&, Gate, hipStream_t);

@@ -151,11 +151,8 @@ def apply(h: Handle, lam: float, P: torch.Tensor, out: torch.Tensor | None = Non
     return Q
 
 
-FORMS = {"textbook": 0, "cg": 1}
-
-
 def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
-        x0: torch.Tensor | None, rr_period: int, chunk: int, batched: bool, form: str = "textbook"):
+        x0: torch.Tensor | None, rr_period: int, chunk: int, batched: bool):
     m = MODES[mode]
     dtype = torch.float64 if m == _lib.HGL_CG_PLAIN_F64 else torch.float32
     _need(Y, dtype, "Y", h.device)
@@ -168,8 +165,7 @@ def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
         F = x0.clone(memory_format=torch.contiguous_format)
     else:
         F = torch.empty((h.N, k), dtype=dtype, device=h.device)
-    opts = CgOpts(m, float(tol), int(max_iter), 1 if x0 is not None else 0, int(rr_period), int(chunk),
-                  FORMS[form])
+    opts = CgOpts(m, float(tol), int(max_iter), 1 if x0 is not None else 0, int(rr_period), int(chunk))
     iters = np.zeros(h.G * k, dtype=np.int32)
     rel = np.zeros(h.G * k, dtype=np.float64)
     with torch.cuda.device(h.device):
@@ -189,19 +185,16 @@ def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
 
 
 def cg_solve(h: Handle, lam: float, Y: torch.Tensor, mode: str = "f32", tol: float = 1e-6,
-             max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8, chunk: int = 0,
-             form: str = "textbook"):
-    """Solve (I + L/lam) F = Y.  Returns (F, iters[G,k], relres[G,k], status).
-    form: "textbook" (eqs. 16-20 as written) or "cg" (Chronopoulos-Gear
-    recurrence, one reduction per iteration)."""
-    return _cg(h, lam, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=False, form=form)
+             max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8, chunk: int = 0):
+    """Solve (I + L/lam) F = Y.  Returns (F, iters[G,k], relres[G,k], status)."""
+    return _cg(h, lam, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=False)
 
 
 def cg_solve_batched(h: Handle, lams, Y: torch.Tensor, mode: str = "f32", tol: float = 1e-6,
                      max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8,
-                     chunk: int = 0, form: str = "textbook"):
+                     chunk: int = 0):
     """One lambda per graph of a batched handle."""
-    return _cg(h, lams, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=True, form=form)
+    return _cg(h, lams, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=True)
 
 
 SKETCH = {"bf16": _lib.HGL_SKETCH_BF16, "f64": _lib.HGL_SKETCH_F64}
@@ -291,7 +284,7 @@ def weight_grad(h: Handle, lam: float, F: torch.Tensor, G: torch.Tensor | None =
         ldy = _rows(Y, "Y")
     grad = torch.empty(h.E, dtype=torch.float64, device=h.device)
     Z = torch.empty((h.N, k), dtype=dtype, device=h.device) if want_z else None
-    opts = CgOpts(m, float(tol), int(max_iter), 0, 0, 0, 0)
+    opts = CgOpts(m, float(tol), int(max_iter), 0, 0, 0)
     iters = np.zeros(k, dtype=np.int32)
     rel = np.zeros(k, dtype=np.float64)
     with torch.cuda.device(h.device):
