@@ -20,7 +20,13 @@
 
 namespace hgl {
 
-enum : int32_t { kActive = 0, kDone = 1, kBreakdown = 2 };
+// Column states.  A column whose recursive residual falls to the claim level
+// stops until a host-scheduled check recomputes its residual: done if that
+// meets tol, else active again.  In the iteration where it claims, its
+// search direction is still updated (kClaimNew), so that a column that goes
+// on after a check resumes with P = R + beta P consistent with its residual;
+// from the next iteration on it is frozen (kClaimed: alpha = 0, P kept).
+enum : int32_t { kActive = 0, kDone = 1, kBreakdown = 2, kClaimed = 3, kClaimNew = 4 };
 
 struct CgState {
   double* yy;      // [G*k] ||y||^2
@@ -151,12 +157,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
   if (blockIdx.y == 0) zero_long_slots(part_rr, n_tiles, n_slots, n_long, k);
 }
 
-// P = R + beta P.
+// P = R + beta P for the iterating columns; a claimed column keeps P.
 template <class T, int GL, int V>
 __global__ __launch_bounds__(kBlock) void k_cg_direction(
     const int32_t* __restrict__ tile_r0, const int32_t* __restrict__ tile_r1,
     const int32_t* __restrict__ tile_seg, const T* __restrict__ R, T* __restrict__ P, int64_t ld,
-    const double* __restrict__ beta, int k, Gate gate) {
+    const double* __restrict__ beta, const int32_t* __restrict__ state, int k, Gate gate) {
   if (gate.skip()) return;
   constexpr int GPB = kBlock / GL, W = GL * V;
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
@@ -165,14 +171,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(
   if (col >= k) return;
   const int g = tile_seg[t];
   T be[V];
+  bool keep[V];
 #pragma unroll
-  for (int i = 0; i < V; ++i) be[i] = T(beta[int64_t(g) * k + col + i]);
+  for (int i = 0; i < V; ++i) {
+    be[i] = T(beta[int64_t(g) * k + col + i]);
+    keep[i] = state[int64_t(g) * k + col + i] == kClaimed;
+  }
   for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
     T rv[V], p[V];
     load_row<V>(R + int64_t(r) * ld + col, rv);
     load_row<V>(P + int64_t(r) * ld + col, p);
 #pragma unroll
-    for (int i = 0; i < V; ++i) p[i] = rv[i] + be[i] * p[i];
+    for (int i = 0; i < V; ++i) p[i] = keep[i] ? p[i] : rv[i] + be[i] * p[i];
     store_row<V>(P + int64_t(r) * ld + col, p);
   }
 }
@@ -223,6 +233,7 @@ struct RedArgs {
   const double* part2;  // y'y (Init)
   const double* part3;  // r'z (Init, Beta, Check) when preconditioned
   double tol;
+  double claim;         // Beta: recursive relres at which a column stops for a check
   int iter;             // iteration index
   int periodic;         // Beta: the residual was recomputed in this iteration
   int has_prec;         // preconditioned: alpha, beta use r'z instead of r'r
@@ -281,6 +292,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
     st.state[id] = done ? kDone : kActive;
     if (!done) atomicAdd(wd.cnt(-1), 1);
   } else if constexpr (OP == RedOp::Alpha) {
+    if (st.state[id] == kClaimNew) st.state[id] = kClaimed;
     if (st.state[id] != kActive || st.rz[id] == 0.0) {
       st.alpha[id] = 0.0;
       return;
@@ -318,19 +330,28 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
     st.beta[id] = rz / st.rz[id];
     st.rr[id] = sum;
     st.rz[id] = rz;
+    if (rel <= ra.claim * ra.tol) {  // stop for a check
+      st.state[id] = kClaimNew;
+      return;
+    }
     atomicAdd(wd.cnt(it), 1);
     atomicMax(reinterpret_cast<unsigned long long*>(wd.rmax(it)),
               static_cast<unsigned long long>(__double_as_longlong(rel)));
   } else if constexpr (OP == RedOp::Check) {  // sum: r'r of Y - M F recomputed in FP64
-    if (st.state[id] != kActive) return;
+    const int32_t sid = st.state[id];
+    if (sid != kActive && sid != kClaimed && sid != kClaimNew) return;
     const double rel = st.yy[id] > 0.0 ? sqrt(sum / st.yy[id]) : sqrt(sum);
     st.relres[id] = rel;
     // residual replacement: the recursion continues from the recomputed
     // residual with the same search direction
     st.rr[id] = sum;
     st.rz[id] = rz;
-    if (rel <= ra.tol) st.state[id] = kDone;
-    else atomicAdd(wd.chk(it), 1);
+    if (rel <= ra.tol) {
+      st.state[id] = kDone;
+    } else {
+      st.state[id] = kActive;
+      atomicAdd(wd.chk(it), 1);
+    }
   }
 }
 
@@ -407,7 +428,10 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   const ColShape cs = pick_shape(k, sizeof(T), {Y, F, b.R}, {ldy, ldf, ld});
   const ColShape cs64 = pick_shape(k, 8, {Y, F, b.R}, {ldy, ldf, ld});
   const int red_blocks = G * ((k + kRedCols - 1) / kRedCols);
-  RedArgs ra{G, k, nsl, h->seg_slots, b.part, b.part2, b.part3, o->tol, 0, 0, has_prec ? 1 : 0};
+  // claim < 1 in FP32 leaves room for the drift of the FP32 recursion from
+  // the true residual
+  const double claim = fp32 ? 0.5 : 1.0;
+  RedArgs ra{G, k, nsl, h->seg_slots, b.part, b.part2, b.part3, o->tol, claim, 0, 0, has_prec ? 1 : 0};
 
   // preconditioner: Zp = P^-1 R with partial r'z into part3 (or into part)
   auto precond = [&](const T* Rin, int64_t ldr, T* Zout, int64_t ldz, double* part, Gate gate) -> int {
@@ -493,7 +517,8 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     int rc3 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
       dim3 grid(h->n_tiles, cs.slabs);
       launch(h, -1, k_cg_direction<T, GL, V>, grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
-                         h->tile_seg, dir_src, b.P, ld, b.st.beta, k, g_now);
+                         h->tile_seg, dir_src, b.P, ld, b.st.beta, static_cast<const int32_t*>(b.st.state), k,
+                         g_now);
       HGL_HIP(hipGetLastError());
       return HGL_OK;
     });
@@ -517,49 +542,46 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   };
 
   // Iterations are enqueued in chunks; between chunks the host reads the
-  // number of iterating columns and their largest recursive relative
-  // residual.  Once that is below claim*tol, a check step decides on the
-  // recomputed residual.  claim < 1 in FP32 leaves room for the drift of the
-  // FP32 recursion from the true residual.  With chunk = 0 the next chunk is
-  // sized from the observed contraction rate to end where the last column
-  // should reach the claim level.
-  const double claim = fp32 ? 0.5 : 1.0;
+  // number of columns still iterating (neither claimed nor finished) and
+  // their largest recursive relative residual.  When no column iterates, a
+  // check step decides every claimed column on its recomputed residual.
+  // Iterations enqueued after the last claim are gated no-ops, so a chunk may
+  // overshoot cheaply: the first is sized from the CG bound with
+  // kappa(M) <= 1 + 1/lambda (the spectrum of L lies in [0, 1]), later ones
+  // from the observed contraction rate (chunk = 0), or fixed (chunk > 0).
+  double lam_min = lambdas[0];
+  for (int g = 1; g < G; ++g) lam_min = std::min(lam_min, lambdas[g]);
+  const double kappa = 1.0 + 1.0 / lam_min;
+  const double rho = (std::sqrt(kappa) - 1.0) / (std::sqrt(kappa) + 1.0);
+  auto chunk_for = [&](double r_now, double rate) {
+    if (!(rate < 0.999) || !(r_now > 0.0)) return 4;
+    const double m = std::ceil(std::log(claim * o->tol / r_now) / std::log(rate));
+    return int(std::min(64.0, std::max(1.0, m)));
+  };
   int it = 0;
   bool all_done = false;
-  HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.cnt(-1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HGL_HIP(hipStreamSynchronize(s));
-  all_done = h->pinned_i[0] == 0;
-  double r_ref = 1.0;
+  double r_ref = -1.0;
   int it_ref = 0;
-  int next = o->chunk > 0 ? o->chunk : 3;
+  int next = o->chunk > 0 ? o->chunk : std::max(2, chunk_for(2.0 * std::sqrt(kappa), rho));
   while (!all_done && it < o->max_iter) {
     const int n = std::min(next, o->max_iter - it);
     for (int c = 0; c < n; ++c, ++it) HGL_TRY(iteration(it));
     HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.cnt(it - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HGL_HIP(hipMemcpyAsync(h->pinned_d, wd.rmax(it - 1), sizeof(double), hipMemcpyDeviceToHost, s));
     HGL_HIP(hipStreamSynchronize(s));
-    if (h->pinned_i[0] == 0) {
-      all_done = true;  // every column finished on a periodic recomputation
-      break;
-    }
-    const double r_now = h->pinned_d[0];
-    const double rate = (r_now > 0.0 && r_ref > 0.0 && it > it_ref)
-                            ? std::pow(r_now / r_ref, 1.0 / double(it - it_ref)) : 1.0;
-    if (r_now <= claim * o->tol) {
+    if (h->pinned_i[0] == 0) {  // every column claimed, finished or broken down
       HGL_TRY(check(it));
       HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.chk(it), sizeof(int32_t), hipMemcpyDeviceToHost, s));
       HGL_HIP(hipStreamSynchronize(s));
       all_done = h->pinned_i[0] == 0;
-      next = o->chunk > 0 ? o->chunk : 1;
+      next = o->chunk > 0 ? o->chunk : 2;  // columns that go on are close to the end
+      r_ref = -1.0;
       continue;
     }
-    if (o->chunk > 0) continue;
-    if (!(rate < 0.999)) {
-      next = 4;
-    } else {
-      const double m = std::ceil(std::log(claim * o->tol / r_now) / std::log(rate));
-      next = int(std::min(64.0, std::max(1.0, m)));
-    }
+    const double r_now = h->pinned_d[0];
+    const double rate = (r_ref > 0.0 && r_now > 0.0 && it > it_ref)
+                            ? std::pow(r_now / r_ref, 1.0 / double(it - it_ref)) : rho;
+    if (o->chunk <= 0) next = chunk_for(r_now, rate);
     r_ref = r_now;
     it_ref = it;
   }
