@@ -235,20 +235,26 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
     Y = torch.from_numpy(p.Y).to(dev, dtype)
     batched = p.vtx_offsets is not None
     state = {"ok": True, "iters": []}
+    out = torch.empty_like(Y)  # one output buffer, so that a recorded graph is replayed
+    graph = bool(a.graph)
+    tune = bool(a.tune)
 
     def step():
         if batched:
-            F, it, rel, st = hgl.cg_solve_batched(h, p.lams, Y, mode=mode, tol=tol, rr_period=rr_period)
+            F, it, rel, st = hgl.cg_solve_batched(h, p.lams, Y, mode=mode, tol=tol, rr_period=rr_period,
+                                                  graph=graph, out=out, tune=tune)
         else:
-            F, it, rel, st = hgl.cg_solve(h, p.lam, Y, mode=mode, tol=tol, rr_period=rr_period)
+            F, it, rel, st = hgl.cg_solve(h, p.lam, Y, mode=mode, tol=tol, rr_period=rr_period, graph=graph,
+                                          out=out, tune=tune)
         state["ok"] = state["ok"] and st == 0 and bool(np.all(rel <= tol))
         state["iters"].append(int(it.max()))
 
     for _ in range(a.warmup):
         step()
     state["iters"].clear()
-    # only the two gather kernels carry launch events in the timed steps
-    hgl.profile(h, True, kinds=["vertex_gather", "edge_gather"])
+    # in the timed steps every 4th launch of the two gather kernels carries
+    # launch events (stamping every launch would slow the stream by ~7%)
+    hgl.profile(h, True, kinds=["vertex_gather", "edge_gather"], every=4)
     dt, _ = _timed(step, a.steps, 0)
     prof = hgl.profile_read(h)
     hgl.profile(h, False)
@@ -270,6 +276,7 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
     cfg = {"workload": name, "N": p.N, "E": p.E, "nnz": p.nnz, "k": k, "graphs": G,
            "lambda": float(p.lam), "relres_tol": tol,
            "cg": f"{mode} vectors, fp64 inner products, residual replacement at convergence checks"
+                 + (", first chunk of iterations as a replayed HIP graph" if graph else "")
                  + (f" and every {rr_period}" if rr_period else ""),
            "iterations": it_mean, "all_columns_converged": state["ok"], "partition": part}
     extra = {"cg_iteration_gbs": round(ab["cg_iteration"] * it_mean / (ms * 1e-3) / 1e9, 1),
@@ -395,6 +402,11 @@ def main():
     ap.add_argument("--workload", default="multi_rhs",
                     help="multi_rhs (default), small, rsvd, learn, batch, or a comma list")
     ap.add_argument("--rr-period", type=int, default=0)
+    ap.add_argument("--tune", type=int, default=1,
+                    help="1: column shapes of the CG kernels picked by the library's autotuner (default)")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="1: run the first CG iteration chunk as a recorded HIP graph (off while kernels are "
+                         "timed), 0: direct launches (default)")
     ap.add_argument("--summarize", nargs="+", metavar="ARG",
                     help="write profile summaries and exit: 'stats STATS_CSV WORKLOAD COMMAND' or "
                          "'counters FETCH_CSV WRITE_CSV KERNEL WORKLOAD COMMAND'")

@@ -70,6 +70,16 @@ typedef struct hgl_cg_opts {
   int32_t x0_given;   /* 1: F holds the starting guess on entry; 0: start from 0 */
   int32_t rr_period;  /* residual replacement period (F32 mode); 0 = only on claims */
   int32_t chunk;      /* iterations enqueued between host convergence checks; 0 = automatic */
+  int32_t graph;      /* 1: the first chunk of iterations runs as a HIP graph, captured on
+                         first use and replayed by later solves on the handle with the same
+                         arguments (pointers, sizes, options); 0: direct launches.  Ignored
+                         while kernel timing (hgl_profile) is on. */
+  int32_t tune;       /* 1: the column shape of the kernels (lanes per row, vector width,
+                         column slabs) is picked by timing the operator gathers on first use
+                         for this k and element size and cached in the handle (a one-time
+                         cost of a few milliseconds; the grouping of the FP64 partial sums
+                         follows the shape, so results can differ at rounding level from
+                         tune = 0); 0: the widest-vector shape */
 } hgl_cg_opts;
 
 /* Library version, e.g. 100 for 0.1.0. */
@@ -282,9 +292,10 @@ int hgl_project_simplex(const double* v, double* w, int32_t E, hipStream_t strea
  * Kernel timing (diagnostics).  hgl_profile(h, enable) resets the counters;
  * with enable = 1 every later solver call on h launches its kernels with
  * start/stop events that the runtime stamps at each kernel's own start and
- * end (hipExtLaunchKernel); with enable = a bit mask other than 1, only the
- * kinds whose bit is set (bit k = kind k) carry events, so that timing one
- * kernel perturbs the rest of the launch stream little; enable = 0 stops it.  hgl_profile_read
+ * end (hipExtLaunchKernel); with enable other than 1, bits 0..15 select the
+ * kinds that carry events (bit k = kind k) and bits 16..23, when nonzero,
+ * stamp only every n-th launch of each such kind, so that timing one kernel
+ * perturbs the launch stream little; enable = 0 stops it.  hgl_profile_read
  * returns, for one kernel kind, the number of kernel launches recorded and
  * their summed duration in milliseconds (it synchronises the device).
  * Kinds: 0 edge gather (Z = C H' S P), 1 vertex gather with inner product

@@ -27,7 +27,8 @@ _STATUS_NAMES = {0: "HGL_OK", 1: "HGL_NOT_CONVERGED", -1: "HGL_EINVAL", -2: "HGL
 
 class CgOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("x0_given", C.c_int32), ("rr_period", C.c_int32), ("chunk", C.c_int32)]
+                ("x0_given", C.c_int32), ("rr_period", C.c_int32), ("chunk", C.c_int32),
+                ("graph", C.c_int32), ("tune", C.c_int32)]
 
 
 class RsvdOpts(C.Structure):

@@ -315,6 +315,8 @@ static void free_handle(hgl_handle* h) {
   for (auto& b : h->ws_extra) b.release();
   h->ws_ab.release();
   if (h->rsvd_free) h->rsvd_free(h->rsvd_ws);
+  if (h->cg_graph) hipGraphExecDestroy(h->cg_graph);
+  if (h->capture_stream) hipStreamDestroy(h->capture_stream);
   if (h->pinned_i) hipHostFree(h->pinned_i);
   if (h->pinned_d) hipHostFree(h->pinned_d);
   for (auto& p : h->prof_pending) {
@@ -638,7 +640,9 @@ extern "C" int hgl_profile(hgl_handle* h, int32_t enable) {
     h->prof_ms[i] = 0.0;
   }
   h->prof_on = enable != 0;
-  h->prof_mask = enable == 1 ? 0xffffffffu : uint32_t(enable);
+  h->prof_mask = enable == 1 ? 0xffffffffu : (uint32_t(enable) & 0xffffu);
+  h->prof_every = enable == 1 ? 1u : std::max(1u, (uint32_t(enable) >> 16) & 0xffu);
+  for (int i = 0; i < kProfKinds; ++i) h->prof_count[i] = 0;
   return HGL_OK;
 }
 

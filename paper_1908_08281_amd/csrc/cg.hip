@@ -15,6 +15,7 @@
 // has converged the remaining launches of an enqueued chunk return at once.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "kernels.h"
 
@@ -374,7 +375,10 @@ struct CgBuffers {
 template <class T>
 static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const T* Y, int64_t ldy,
                   T* F, int64_t ldf, int k, int32_t* iters_host, double* relres_host, const Precond* prec,
-                  hipStream_t s) {
+                  hipStream_t s_user) {
+  // the stream every launch below goes to (the capture stream while a chunk
+  // of iterations is being recorded into a graph)
+  hipStream_t s = s_user;
   const bool fp32 = sizeof(T) == 4;
   const bool has_prec = prec != nullptr;
   const int N = h->N, E = h->E, G = h->G;
@@ -425,7 +429,10 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   }
   HGL_HIP(hipMemsetAsync(wd.base, 0, Words::count(o->max_iter) * sizeof(int32_t), s));
 
+  // row-streaming kernels: the widest-vector shape; operator gathers: the
+  // autotuned one (the partial-sum layout does not depend on either)
   const ColShape cs = pick_shape(k, sizeof(T), {Y, F, b.R}, {ldy, ldf, ld});
+  const ColShape csg = o->tune ? tune_shape<T>(h, k, cs, Y, ldy, b.Z, b.Q, a_seg, b_seg, s) : cs;
   const ColShape cs64 = pick_shape(k, 8, {Y, F, b.R}, {ldy, ldf, ld});
   const int red_blocks = G * ((k + kRedCols - 1) / kRedCols);
   // claim < 1 in FP32 leaves room for the drift of the FP32 recursion from
@@ -480,11 +487,11 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   auto iteration = [&](int it) -> int {
     Gate g_prev{wd.cnt(it - 1), nullptr, 1};
     prof_begin(h, kProfEdge, s);
-    HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, cs, g_prev, s));
+    HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, csg, g_prev, s));
     prof_end(h, s);
     prof_begin(h, kProfVertex, s);
     HGL_TRY(launch_spmm_vertex<T, T>(h, VMode::ApplyDot, b.P, ld, b.Z, ld, nullptr, 0, b.Q, ld, a_seg,
-                                     b_seg, b.part, k, cs, g_prev, s));
+                                     b_seg, b.part, k, csg, g_prev, s));
     prof_end(h, s);
     RedArgs r = ra;
     r.iter = it;
@@ -558,6 +565,46 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     const double m = std::ceil(std::log(claim * o->tol / r_now) / std::log(rate));
     return int(std::min(64.0, std::max(1.0, m)));
   };
+  // The first chunk as a HIP graph: recorded on first use, replayed while
+  // every argument it bakes in (pointers, sizes, options) is unchanged.
+  const bool use_graph = o->graph != 0 && !h->prof_on;
+  auto graph_chunk = [&](int n) -> int {
+    auto u = [](const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); };
+    uint64_t tol_bits;
+    std::memcpy(&tol_bits, &o->tol, sizeof(tol_bits));
+    const std::vector<uint64_t> key = {
+        sizeof(T), uint64_t(k), uint64_t(G), uint64_t(n), uint64_t(ldy), uint64_t(ldf), u(Y), u(F),
+        u(h->ws_vec.p), u(h->ws_z.p), u(h->ws_z64.p), u(h->ws_part.p), u(h->ws_part2.p), u(h->ws_extra[0].p),
+        u(h->ws_state.p), u(h->ws_chunk.p), u(h->ws_ab.p), u(prec ? prec->ctx : nullptr), uint64_t(o->rr_period),
+        tol_bits, uint64_t(cs.GL), uint64_t(cs.V), uint64_t(cs.slabs), uint64_t(csg.GL), uint64_t(csg.V),
+        uint64_t(csg.slabs), u(wd.base), uint64_t(o->max_iter)};
+    if (!h->cg_graph || key != h->cg_graph_key) {
+      if (h->cg_graph) {
+        HGL_HIP(hipGraphExecDestroy(h->cg_graph));
+        h->cg_graph = nullptr;
+      }
+      if (!h->capture_stream) HGL_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      s = h->capture_stream;
+      HGL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      int rc = HGL_OK;
+      for (int c = 0; c < n && rc == HGL_OK; ++c) rc = iteration(c);
+      const hipError_t e = hipStreamEndCapture(s, &graph);
+      s = s_user;
+      if (rc != HGL_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+      }
+      HGL_HIP(e);
+      const hipError_t e2 = hipGraphInstantiate(&h->cg_graph, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      HGL_HIP(e2);
+      h->cg_graph_key = key;
+    }
+    HGL_HIP(hipGraphLaunch(h->cg_graph, s));
+    return HGL_OK;
+  };
+
   int it = 0;
   bool all_done = false;
   double r_ref = -1.0;
@@ -565,7 +612,12 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   int next = o->chunk > 0 ? o->chunk : std::max(2, chunk_for(2.0 * std::sqrt(kappa), rho));
   while (!all_done && it < o->max_iter) {
     const int n = std::min(next, o->max_iter - it);
-    for (int c = 0; c < n; ++c, ++it) HGL_TRY(iteration(it));
+    if (use_graph && it == 0) {
+      HGL_TRY(graph_chunk(n));
+      it += n;
+    } else {
+      for (int c = 0; c < n; ++c, ++it) HGL_TRY(iteration(it));
+    }
     HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.cnt(it - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HGL_HIP(hipMemcpyAsync(h->pinned_d, wd.rmax(it - 1), sizeof(double), hipMemcpyDeviceToHost, s));
     HGL_HIP(hipStreamSynchronize(s));

@@ -4,7 +4,9 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
+#include <tuple>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -134,11 +136,20 @@ struct hgl_handle {
   // kernel timing (diagnostics)
   bool prof_on = false;
   uint32_t prof_mask = 0;                             // kinds whose launches are stamped
+  uint32_t prof_every = 1;                            // stamp every n-th launch of such a kind
+  uint64_t prof_count[hgl::kProfKinds] = {0};         // launches seen per kind
   std::vector<hipEvent_t> prof_pool;                 // free events
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
   int64_t prof_launches[hgl::kProfKinds] = {0};
   double prof_ms[hgl::kProfKinds] = {0};
   int prof_kind = -1;                                // open kind (prof_begin), or -1
+  // autotuned column shapes: {k, element size, base V} -> {GL, V, slabs}
+  std::vector<std::array<int, 6>> tuned;
+  // CG iterations captured as a HIP graph (first chunk of a solve), replayed
+  // while the solve's arguments stay the same
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t cg_graph = nullptr;
+  std::vector<uint64_t> cg_graph_key;
   int32_t* pinned_i = nullptr;   // host-pinned readback words
   double* pinned_d = nullptr;
   size_t pinned_d_len = 0;
@@ -160,6 +171,16 @@ struct ColShape {
 };
 ColShape pick_shape(int k, int elem_bytes, std::initializer_list<const void*> ptrs,
                     std::initializer_list<int64_t> lds);
+
+// Autotuner: the column shape under which the two operator gathers run
+// fastest for k columns of the given element size, among the shapes that
+// `base` (pick_shape's, with the widest valid vector) admits: narrower
+// vectors, fewer lanes per row with more column slabs.  Timed once on X
+// (N x k, leading dimension ldx) with scratch outputs Z (E x k) and Q (N x k),
+// then cached in the handle under (k, element size, base vector width).
+template <class T>
+ColShape tune_shape(hgl_handle* h, int k, const ColShape& base, const T* X, int64_t ldx, T* Z, T* Q,
+                    const double* a_seg, const double* b_seg, hipStream_t s);
 
 // Early-exit gate of a kernel launched inside the CG loop: the kernel does
 // nothing when *active == 0 (every column converged) or when it is a
@@ -195,7 +216,7 @@ inline void launch(const hgl_handle* hc, int kind, F kernel, dim3 grid, dim3 blo
   hgl_handle* h = const_cast<hgl_handle*>(hc);
   const int kd = kind >= 0 ? kind : h->prof_kind;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (h->prof_on && kd >= 0 && ((h->prof_mask >> kd) & 1u)) {
+  if (h->prof_on && kd >= 0 && ((h->prof_mask >> kd) & 1u) && (h->prof_count[kd]++ % h->prof_every) == 0) {
     e0 = prof_event(h);
     e1 = prof_event(h);
   }
@@ -203,7 +224,12 @@ inline void launch(const hgl_handle* hc, int kind, F kernel, dim3 grid, dim3 blo
     hipExtLaunchKernelGGL(kernel, grid, block, shm, s, e0, e1, 0, args...);
     h->prof_pending.push_back({kd, {e0, e1}});
   } else {
-    hipExtLaunchKernelGGL(kernel, grid, block, shm, s, nullptr, nullptr, 0, args...);
+    // plain launch (also what stream capture records into a graph)
+    auto actual = std::tuple<Args...>{args...};
+    auto formal = validateArgsCountType(kernel, actual);
+    void* kargs[sizeof...(Args) > 0 ? sizeof...(Args) : 1];
+    pArgs<0>(formal, kargs);
+    hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, kargs, shm, s);
   }
 }
 

@@ -337,6 +337,71 @@ int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx,
   });
 }
 
+template <class T>
+ColShape tune_shape(hgl_handle* h, int k, const ColShape& base, const T* X, int64_t ldx, T* Z, T* Q,
+                    const double* a_seg, const double* b_seg, hipStream_t s) {
+  for (const auto& e : h->tuned)
+    if (e[0] == k && e[1] == int(sizeof(T)) && e[2] == base.V) {
+      ColShape cs;
+      cs.GL = e[3];
+      cs.V = e[4];
+      cs.slabs = e[5];
+      return cs;
+    }
+  // candidates: vector width V' <= base.V; lanes from the smallest power of
+  // two covering the row down to 8 (more column slabs)
+  std::vector<ColShape> cand;
+  for (int V = base.V; V >= 1; V >>= 1) {
+    const int need = (k + V - 1) / V;
+    int GL = 4;
+    while (GL < need && GL < 64) GL <<= 1;
+    for (int gl = GL; gl >= 8 && cand.size() < 12; gl >>= 1) {
+      ColShape cs;
+      cs.GL = gl;
+      cs.V = V;
+      cs.slabs = (k + gl * V - 1) / (gl * V);
+      if (cs.slabs > 16) break;
+      cand.push_back(cs);
+    }
+  }
+  if (cand.empty()) cand.push_back(base);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ColShape best = base;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return base;
+  }
+  float best_ms = 1e30f;
+  for (const ColShape& cs : cand) {
+    auto once = [&]() -> bool {
+      return launch_spmm_edge<T, T>(h, X, ldx, Z, k, k, cs, Gate{}, s) == HGL_OK &&
+             launch_spmm_vertex<T, T>(h, VMode::Apply, X, ldx, Z, k, nullptr, 0, Q, k, a_seg, b_seg, nullptr, k,
+                                      cs, Gate{}, s) == HGL_OK;
+    };
+    if (!once()) continue;  // warm-up (and shape check)
+    hipEventRecord(e0, s);
+    bool ok = true;
+    for (int rep = 0; rep < 3 && ok; ++rep) ok = once();
+    hipEventRecord(e1, s);
+    float ms = 0.f;
+    if (!ok || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cs;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  clear_error();
+  h->tuned.push_back({k, int(sizeof(T)), base.V, best.GL, best.V, best.slabs});
+  return best;
+}
+
+template ColShape tune_shape<float>(hgl_handle*, int, const ColShape&, const float*, int64_t, float*, float*,
+                                    const double*, const double*, hipStream_t);
+template ColShape tune_shape<double>(hgl_handle*, int, const ColShape&, const double*, int64_t, double*, double*,
+                                     const double*, const double*, hipStream_t);
+
 template int launch_spmm_edge<float, float>(const hgl_handle*, const float*, int64_t, float*,
                                             int64_t, int, const ColShape&, Gate, hipStream_t);
 template int launch_spmm_edge<float, double>(const hgl_handle*, const float*, int64_t, double*,

@@ -152,7 +152,8 @@ def apply(h: Handle, lam: float, P: torch.Tensor, out: torch.Tensor | None = Non
 
 
 def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
-        x0: torch.Tensor | None, rr_period: int, chunk: int, batched: bool):
+        x0: torch.Tensor | None, rr_period: int, chunk: int, batched: bool, graph: bool = False,
+        out: torch.Tensor | None = None, tune: bool = False):
     m = MODES[mode]
     dtype = torch.float64 if m == _lib.HGL_CG_PLAIN_F64 else torch.float32
     _need(Y, dtype, "Y", h.device)
@@ -160,12 +161,21 @@ def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
     if Y.shape[0] != h.N:
         raise ValueError("Y must have N rows")
     k = Y.shape[1]
-    if x0 is not None:
+    if out is not None:
+        _need(out, dtype, "out", h.device)
+        if tuple(out.shape) != (h.N, k):
+            raise ValueError("out must be N x k")
+        _rows(out, "out")
+        F = out
+        if x0 is not None:
+            F.copy_(x0)
+    elif x0 is not None:
         _need(x0, dtype, "x0", h.device)
         F = x0.clone(memory_format=torch.contiguous_format)
     else:
         F = torch.empty((h.N, k), dtype=dtype, device=h.device)
-    opts = CgOpts(m, float(tol), int(max_iter), 1 if x0 is not None else 0, int(rr_period), int(chunk))
+    opts = CgOpts(m, float(tol), int(max_iter), 1 if x0 is not None else 0, int(rr_period), int(chunk),
+                  1 if graph else 0, 1 if tune else 0)
     iters = np.zeros(h.G * k, dtype=np.int32)
     rel = np.zeros(h.G * k, dtype=np.float64)
     with torch.cuda.device(h.device):
@@ -185,16 +195,24 @@ def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
 
 
 def cg_solve(h: Handle, lam: float, Y: torch.Tensor, mode: str = "f32", tol: float = 1e-6,
-             max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8, chunk: int = 0):
-    """Solve (I + L/lam) F = Y.  Returns (F, iters[G,k], relres[G,k], status)."""
-    return _cg(h, lam, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=False)
+             max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8, chunk: int = 0,
+             graph: bool = False, out: torch.Tensor | None = None, tune: bool = False):
+    """Solve (I + L/lam) F = Y.  Returns (F, iters[G,k], relres[G,k], status).
+    graph: run the first chunk of iterations as a HIP graph, recorded once
+    and replayed by later solves with the same arguments (pass the same
+    `out` tensor to keep F's address, and so the graph, from call to call).
+    tune: pick the kernels' column shape by timing (cached per handle)."""
+    return _cg(h, lam, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=False, graph=graph, out=out,
+               tune=tune)
 
 
 def cg_solve_batched(h: Handle, lams, Y: torch.Tensor, mode: str = "f32", tol: float = 1e-6,
                      max_iter: int = 1000, x0: torch.Tensor | None = None, rr_period: int = 8,
-                     chunk: int = 0):
-    """One lambda per graph of a batched handle."""
-    return _cg(h, lams, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=True)
+                     chunk: int = 0, graph: bool = False, out: torch.Tensor | None = None,
+                     tune: bool = False):
+    """One lambda per graph of a batched handle (graph, out, tune: as for cg_solve)."""
+    return _cg(h, lams, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=True, graph=graph, out=out,
+               tune=tune)
 
 
 SKETCH = {"bf16": _lib.HGL_SKETCH_BF16, "f64": _lib.HGL_SKETCH_F64}
@@ -284,7 +302,7 @@ def weight_grad(h: Handle, lam: float, F: torch.Tensor, G: torch.Tensor | None =
         ldy = _rows(Y, "Y")
     grad = torch.empty(h.E, dtype=torch.float64, device=h.device)
     Z = torch.empty((h.N, k), dtype=dtype, device=h.device) if want_z else None
-    opts = CgOpts(m, float(tol), int(max_iter), 0, 0, 0)
+    opts = CgOpts(m, float(tol), int(max_iter), 0, 0, 0, 0, 0)
     iters = np.zeros(k, dtype=np.int32)
     rel = np.zeros(k, dtype=np.float64)
     with torch.cuda.device(h.device):
@@ -310,10 +328,11 @@ PROFILE_KINDS = {0: "edge_gather", 1: "vertex_gather", 2: "cg_update", 3: "cg_di
                  14: "hub_row_finish"}
 
 
-def profile(h: Handle, enable: bool, kinds=None) -> None:
+def profile(h: Handle, enable: bool, kinds=None, every: int = 1) -> None:
     """Reset the kernel-timing counters of h and switch event timing on/off.
     `kinds` (names or numbers of PROFILE_KINDS) limits the stamped launches
-    to those kernels; None stamps every launch."""
+    to those kernels, and `every` > 1 stamps only every n-th launch of each;
+    kinds=None stamps every launch."""
     mask = 1
     if enable and kinds is not None:
         names = {v: k for k, v in PROFILE_KINDS.items()}
@@ -322,6 +341,7 @@ def profile(h: Handle, enable: bool, kinds=None) -> None:
             mask |= 1 << (names[kd] if isinstance(kd, str) else int(kd))
         if mask == 1:  # kind 0 alone: 1 means "all", so add an unused bit
             mask |= 1 << 15
+        mask |= (max(1, min(255, int(every))) & 0xFF) << 16
     check(lib().hgl_profile(h.ptr, mask if enable else 0), "hgl_profile")
 
 

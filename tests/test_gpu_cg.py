@@ -159,3 +159,56 @@ def test_multi_rhs_full_size_against_sparse_oracle():
     assert np.all(relo <= 1e-13)
     assert colrelerr(F.cpu().numpy()[:, cols], fo).max() <= 1e-6
     assert np.all(solve.relres(op, F.cpu().double().numpy(), p.Y) <= tol * 1.01)
+
+
+def test_graph_replay_matches_direct_launches():
+    """The first chunk of iterations recorded as a HIP graph: every replay
+    (new data at the same addresses, eager solves and synchronisations in
+    between) gives bitwise the result of direct launches; a new output
+    address records a new graph."""
+    import torch
+    dev = device()
+    p = synth.multi_rhs(N=3000, E=2400, k=24, smax=120)
+    h = build(p, dev)
+    tol = 1e-6 / (1 + 1 / p.lam)
+    rng = synth.rng_for(21)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    out = torch.empty_like(Y)
+    Fo = None
+    for rep in range(3):
+        say("graph replay", rep)
+        if rep > 0:  # new right-hand sides at the same address
+            Y.copy_(torch.from_numpy((rng.random(p.Y.shape) < 0.03).astype(np.float32)).to(dev))
+        F_eager, it_e, rel_e, st_e = hgl().cg_solve(h, p.lam, Y, tol=tol, rr_period=0)
+        torch.cuda.synchronize()
+        F_g, it_g, rel_g, st_g = hgl().cg_solve(h, p.lam, Y, tol=tol, rr_period=0, graph=True, out=out)
+        torch.cuda.synchronize()
+        assert st_e == 0 and st_g == 0
+        assert torch.equal(F_g, F_eager)
+        assert np.array_equal(it_g, it_e) and np.array_equal(rel_g, rel_e)
+        if Fo is None:
+            Fo = _dense_solution(p)
+            assert colrelerr(F_g.cpu().numpy(), Fo).max() <= 1e-6
+    out2 = torch.empty_like(Y)
+    F2, _, _, st2 = hgl().cg_solve(h, p.lam, Y, tol=tol, rr_period=0, graph=True, out=out2)
+    F3, _, _, _ = hgl().cg_solve(h, p.lam, Y, tol=tol, rr_period=0)
+    assert st2 == 0 and torch.equal(F2, F3)
+
+
+@pytest.mark.parametrize("k", [24, 200])
+def test_autotuned_shape_matches_oracle_and_is_cached(k):
+    """The autotuner picks the column shape by timing on first use; the
+    solve still meets the oracle bar, and later solves reuse the cached shape
+    (bitwise the same result)."""
+    import torch
+    dev = device()
+    p = synth.multi_rhs(N=3000, E=2400, k=k, smax=120)
+    h = build(p, dev)
+    tol = 1e-6 / (1 + 1 / p.lam)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    say("autotune", k)
+    F1, _, _, st1 = hgl().cg_solve(h, p.lam, Y, tol=tol, tune=True)
+    F2, _, _, st2 = hgl().cg_solve(h, p.lam, Y, tol=tol, tune=True)
+    assert st1 == 0 and st2 == 0
+    assert torch.equal(F1, F2)
+    assert colrelerr(F1.cpu().numpy(), _dense_solution(p)).max() <= 1e-6
