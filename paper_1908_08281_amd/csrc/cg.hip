@@ -218,9 +218,13 @@ __device__ __forceinline__ double slot_sum(const double* __restrict__ part, int 
   }
   lds[j][l] = s;
   __syncthreads();
-  double tot = 0.0;
-  if (j == 0)
-    for (int q = 0; q < kRedStripes; ++q) tot += lds[q][l];
+  // fixed pairwise tree over the stripes
+#pragma unroll
+  for (int half = kRedStripes / 2; half >= 1; half >>= 1) {
+    if (j < half) lds[j][l] += lds[j + half][l];
+    __syncthreads();
+  }
+  const double tot = lds[0][l];
   __syncthreads();
   return tot;
 }
@@ -278,81 +282,108 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
   if constexpr (OP != RedOp::Alpha) {
     if (ra.has_prec) rz = slot_sum(ra.part3, ra.k, ra.seg_slots, g, col, lds);
   }
-  if (threadIdx.x >= kRedCols || col >= ra.k) return;
-  const int64_t id = int64_t(g) * ra.k + col;
+  if (threadIdx.x >= kRedCols) return;
+  // the per-column step: the counters it raises are added up over the
+  // workgroup's columns first, so each flag word takes one atomic per
+  // workgroup (lanes 0 .. kRedCols-1 of wave 0)
+  int add_cnt = 0, add_chk = 0, add_err = 0;
+  double rel_max = -1.0;
+  if (col < ra.k) {
+    const int64_t id = int64_t(g) * ra.k + col;
+    do {
+      if constexpr (OP == RedOp::Init) {
+        st.yy[id] = sum2;
+        st.rr[id] = sum;
+        st.rz[id] = rz;
+        st.iters[id] = 0;
+        st.alpha[id] = 0.0;
+        st.beta[id] = 0.0;
+        const double rel = sum2 > 0.0 ? sqrt(sum / sum2) : sqrt(sum);
+        st.relres[id] = rel;
+        const bool done = sum2 == 0.0 || rel <= ra.tol;
+        st.state[id] = done ? kDone : kActive;
+        add_cnt = done ? 0 : 1;
+      } else if constexpr (OP == RedOp::Alpha) {
+        if (st.state[id] == kClaimNew) st.state[id] = kClaimed;
+        if (st.state[id] != kActive || st.rz[id] == 0.0) {
+          st.alpha[id] = 0.0;
+          break;
+        }
+        if (!(sum > 0.0) || !isfinite(sum) || !isfinite(st.rz[id])) {
+          st.alpha[id] = 0.0;
+          st.state[id] = kBreakdown;
+          add_err = 1;
+          break;
+        }
+        st.alpha[id] = st.rz[id] / sum;
+      } else if constexpr (OP == RedOp::Beta) {
+        if (st.state[id] != kActive) {
+          st.beta[id] = 0.0;
+          break;
+        }
+        st.iters[id] += 1;
+        const bool ran = ra.periodic != 0;  // sum is the recomputed true residual
+        const double rel = sqrt(sum / st.yy[id]);
+        if (ran) st.relres[id] = rel;
+        if (ran && rel <= ra.tol) {  // a recomputed residual finishes the column
+          st.state[id] = kDone;
+          st.beta[id] = 0.0;
+          st.rr[id] = sum;
+          st.rz[id] = rz;
+          break;
+        }
+        if (!isfinite(sum) || !isfinite(rz)) {
+          st.state[id] = kBreakdown;
+          st.beta[id] = 0.0;
+          add_err = 1;
+          break;
+        }
+        st.beta[id] = rz / st.rz[id];
+        st.rr[id] = sum;
+        st.rz[id] = rz;
+        if (rel <= ra.claim * ra.tol) {  // stop for a check
+          st.state[id] = kClaimNew;
+          break;
+        }
+        add_cnt = 1;
+        rel_max = rel;
+      } else {  // Check: sum is r'r of Y - M F recomputed in FP64
+        const int32_t sid = st.state[id];
+        if (sid != kActive && sid != kClaimed && sid != kClaimNew) break;
+        const double rel = st.yy[id] > 0.0 ? sqrt(sum / st.yy[id]) : sqrt(sum);
+        st.relres[id] = rel;
+        // residual replacement: the recursion continues from the recomputed
+        // residual with the same search direction
+        st.rr[id] = sum;
+        st.rz[id] = rz;
+        if (rel <= ra.tol) {
+          st.state[id] = kDone;
+        } else {
+          st.state[id] = kActive;
+          add_chk = 1;
+        }
+      }
+    } while (false);
+  }
+#pragma unroll
+  for (int off = kRedCols / 2; off >= 1; off >>= 1) {
+    add_cnt += __shfl_xor(add_cnt, off, kRedCols);
+    add_chk += __shfl_xor(add_chk, off, kRedCols);
+    add_err |= __shfl_xor(add_err, off, kRedCols);
+    rel_max = fmax(rel_max, __shfl_xor(rel_max, off, kRedCols));
+  }
+  if (threadIdx.x != 0) return;
+  if (add_err) atomicOr(wd.err(), 1);
   if constexpr (OP == RedOp::Init) {
-    st.yy[id] = sum2;
-    st.rr[id] = sum;
-    st.rz[id] = rz;
-    st.iters[id] = 0;
-    st.alpha[id] = 0.0;
-    st.beta[id] = 0.0;
-    double rel = sum2 > 0.0 ? sqrt(sum / sum2) : sqrt(sum);
-    st.relres[id] = rel;
-    const bool done = sum2 == 0.0 || rel <= ra.tol;
-    st.state[id] = done ? kDone : kActive;
-    if (!done) atomicAdd(wd.cnt(-1), 1);
-  } else if constexpr (OP == RedOp::Alpha) {
-    if (st.state[id] == kClaimNew) st.state[id] = kClaimed;
-    if (st.state[id] != kActive || st.rz[id] == 0.0) {
-      st.alpha[id] = 0.0;
-      return;
-    }
-    if (!(sum > 0.0) || !isfinite(sum) || !isfinite(st.rz[id])) {
-      st.alpha[id] = 0.0;
-      st.state[id] = kBreakdown;
-      atomicOr(wd.err(), 1);
-      return;
-    }
-    st.alpha[id] = st.rz[id] / sum;
+    if (add_cnt) atomicAdd(wd.cnt(-1), add_cnt);
   } else if constexpr (OP == RedOp::Beta) {
-    if (st.state[id] != kActive) {
-      st.beta[id] = 0.0;
-      return;
+    if (add_cnt) {
+      atomicAdd(wd.cnt(it), add_cnt);
+      atomicMax(reinterpret_cast<unsigned long long*>(wd.rmax(it)),
+                static_cast<unsigned long long>(__double_as_longlong(rel_max)));
     }
-    st.iters[id] += 1;
-    const bool ran = ra.periodic != 0;  // sum is the recomputed true residual
-    const double yy = st.yy[id];
-    const double rel = sqrt(sum / yy);
-    if (ran) st.relres[id] = rel;
-    if (ran && rel <= ra.tol) {  // a recomputed residual finishes the column
-      st.state[id] = kDone;
-      st.beta[id] = 0.0;
-      st.rr[id] = sum;
-      st.rz[id] = rz;
-      return;
-    }
-    if (!isfinite(sum) || !isfinite(rz)) {
-      st.state[id] = kBreakdown;
-      atomicOr(wd.err(), 1);
-      st.beta[id] = 0.0;
-      return;
-    }
-    st.beta[id] = rz / st.rz[id];
-    st.rr[id] = sum;
-    st.rz[id] = rz;
-    if (rel <= ra.claim * ra.tol) {  // stop for a check
-      st.state[id] = kClaimNew;
-      return;
-    }
-    atomicAdd(wd.cnt(it), 1);
-    atomicMax(reinterpret_cast<unsigned long long*>(wd.rmax(it)),
-              static_cast<unsigned long long>(__double_as_longlong(rel)));
-  } else if constexpr (OP == RedOp::Check) {  // sum: r'r of Y - M F recomputed in FP64
-    const int32_t sid = st.state[id];
-    if (sid != kActive && sid != kClaimed && sid != kClaimNew) return;
-    const double rel = st.yy[id] > 0.0 ? sqrt(sum / st.yy[id]) : sqrt(sum);
-    st.relres[id] = rel;
-    // residual replacement: the recursion continues from the recomputed
-    // residual with the same search direction
-    st.rr[id] = sum;
-    st.rz[id] = rz;
-    if (rel <= ra.tol) {
-      st.state[id] = kDone;
-    } else {
-      st.state[id] = kActive;
-      atomicAdd(wd.chk(it), 1);
-    }
+  } else if constexpr (OP == RedOp::Check) {
+    if (add_chk) atomicAdd(wd.chk(it), add_chk);
   }
 }
 
