@@ -349,8 +349,9 @@ ColShape tune_shape(hgl_handle* h, int k, const ColShape& base, const T* X, int6
       return cs;
     }
   // candidates: vector width V' <= base.V; lanes from the smallest power of
-  // two covering the row down to 8 (more column slabs)
-  std::vector<ColShape> cand;
+  // two covering the row down to 8 (more column slabs); the default (base)
+  // comes first and is kept unless another candidate is 5% faster
+  std::vector<ColShape> cand{base};
   for (int V = base.V; V >= 1; V >>= 1) {
     const int need = (k + V - 1) / V;
     int GL = 4;
@@ -361,17 +362,17 @@ ColShape tune_shape(hgl_handle* h, int k, const ColShape& base, const T* X, int6
       cs.V = V;
       cs.slabs = (k + gl * V - 1) / (gl * V);
       if (cs.slabs > 16) break;
+      if (cs.GL == base.GL && cs.V == base.V && cs.slabs == base.slabs) continue;
       cand.push_back(cs);
     }
   }
-  if (cand.empty()) cand.push_back(base);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ColShape best = base;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) hipEventDestroy(e0);
     return base;
   }
-  float best_ms = 1e30f;
+  float best_ms = 1e30f, base_ms = -1.f;
   for (const ColShape& cs : cand) {
     auto once = [&]() -> bool {
       return launch_spmm_edge<T, T>(h, X, ldx, Z, k, k, cs, Gate{}, s) == HGL_OK &&
@@ -385,6 +386,7 @@ ColShape tune_shape(hgl_handle* h, int k, const ColShape& base, const T* X, int6
     hipEventRecord(e1, s);
     float ms = 0.f;
     if (!ok || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
+    if (cs.GL == base.GL && cs.V == base.V && cs.slabs == base.slabs) base_ms = ms;
     if (ms < best_ms) {
       best_ms = ms;
       best = cs;
@@ -393,6 +395,9 @@ ColShape tune_shape(hgl_handle* h, int k, const ColShape& base, const T* X, int6
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   clear_error();
+  // keep the default unless another shape is clearly faster (timing noise
+  // must not flip the choice from one process to the next)
+  if (base_ms > 0.f && best_ms > 0.95f * base_ms) best = base;
   h->tuned.push_back({k, int(sizeof(T)), base.V, best.GL, best.V, best.slabs});
   return best;
 }
