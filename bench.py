@@ -129,15 +129,18 @@ def summarize_stats(stats_csv, workload, command, top=16):
     return "\n".join(lines) + "\n"
 
 
-def stored_traffic(kernel, workload):
+def stored_traffic(kernel, workload, instance):
     """Traffic per launch from the committed counter summary, or None when
-    there is none or the kernel sources changed since it was taken."""
+    there is none, the kernel sources changed since it was taken, or it was
+    taken of another template instance (column shape) of the kernel."""
     path = os.path.join(PROFILES, f"{workload}_{kernel}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("kernel") != kernel or rec.get("sources_sha256") != sources_digest():
+        return None
+    if rec.get("instance", "").split("::")[-1] != instance:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -268,10 +271,17 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
     ab = gather_bytes(p.N, p.E, p.nnz, k, elem, covered, part["hub_rows"])
     nv, mv = prof["vertex_gather"]
     ne, me = prof["edge_gather"]
+    # template instances the solves ran (the column shape may be autotuned)
+    gl, vw, _ = h.gather_shape()
+    t = "float" if mode == "f32" else "double"
+    inst_v, inst_e = f"k_spmm_vertex<{t}, {t}, {gl}, {vw}, 1>", f"k_spmm_edge<{t}, {t}, {gl}, {vw}>"
     if mv >= me:
-        roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_gather"], traffic=stored_traffic("k_spmm_vertex", name))
+        roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_gather"],
+                     traffic=stored_traffic("k_spmm_vertex", name, inst_v))
+        roof["instance"] = inst_v
     else:
-        roof = _roof("k_spmm_edge", ne, me, ab["edge_gather"], traffic=stored_traffic("k_spmm_edge", name))
+        roof = _roof("k_spmm_edge", ne, me, ab["edge_gather"], traffic=stored_traffic("k_spmm_edge", name, inst_e))
+        roof["instance"] = inst_e
     it_mean = float(np.mean(state["iters"]))
     cfg = {"workload": name, "N": p.N, "E": p.E, "nnz": p.nnz, "k": k, "graphs": G,
            "lambda": float(p.lam), "relres_tol": tol,

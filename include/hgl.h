@@ -139,6 +139,26 @@ int hgl_get_partition(const hgl_handle* h, int32_t* n_tiles, int32_t* n_hub_rows
                       int32_t* n_long_edges);
 
 /*
+ * Diagnostics: the column shape under which the two operator gathers of the
+ * most recent CG solve on this handle ran, written to the caller's host array
+ * shape3 = {lanes per row, elements per lane, column slabs}; all zero before
+ * the first solve.  With the autotuner on (hgl_cg_opts.tune) it is the tuned
+ * shape.  Errors: HGL_EINVAL for a NULL argument.
+ */
+int hgl_get_gather_shape(const hgl_handle* h, int32_t* shape3);
+
+/*
+ * Diagnostics of the most recent CG solve on this handle (hgl_cg_solve,
+ * hgl_cg_solve_batched, and the refinement of hgl_block_rsvd_invert),
+ * written to the caller's host array stats4 = {iterations enqueued, chunks
+ * of iterations enqueued between host synchronisations, check steps
+ * (FP64-recomputed residuals deciding claimed columns), check steps after
+ * which some column went on iterating}; all zero before the first solve.
+ * Errors: HGL_EINVAL for a NULL argument.
+ */
+int hgl_get_cg_stats(const hgl_handle* h, int32_t* stats4);
+
+/*
  * Copy the derived quantities of section 2 into caller buffers (any may be
  * NULL): dv [N] = delta(v), s [N] = delta(v)^-1/2 (0 if delta(v) = 0),
  * c [E] = w_e/delta(e), vtx_ptr [N+1] and vtx_edge [nnz] = vertex-major CSR

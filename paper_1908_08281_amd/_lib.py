@@ -58,6 +58,8 @@ SIGNATURES = {
     "hgl_destroy": (None, [P]),
     "hgl_get_sizes": (C.c_int, [P, I32P, I32P, C.POINTER(C.c_int64), I32P]),
     "hgl_get_partition": (C.c_int, [P, I32P, I32P, I32P, I32P]),
+    "hgl_get_gather_shape": (C.c_int, [P, I32P]),
+    "hgl_get_cg_stats": (C.c_int, [P, I32P]),
     "hgl_get_operator": (C.c_int, [P, P, P, P, P, P, P]),
     "hgl_apply": (C.c_int, [P, D, I32, P, I64, P, I64, I32, P]),
     "hgl_cg_solve": (C.c_int, [P, D, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),

@@ -631,6 +631,22 @@ extern "C" int hgl_get_partition(const hgl_handle* h, int32_t* n_tiles, int32_t*
   return HGL_OK;
 }
 
+extern "C" int hgl_get_gather_shape(const hgl_handle* h, int32_t* shape3) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  HGL_CHECK_ARG(shape3 != nullptr, "shape3 is NULL");
+  for (int i = 0; i < 3; ++i) shape3[i] = h->last_shape[i];
+  return HGL_OK;
+}
+
+extern "C" int hgl_get_cg_stats(const hgl_handle* h, int32_t* stats4) {
+  clear_error();
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  HGL_CHECK_ARG(stats4 != nullptr, "stats4 is NULL");
+  for (int i = 0; i < 4; ++i) stats4[i] = h->last_cg[i];
+  return HGL_OK;
+}
+
 extern "C" int hgl_profile(hgl_handle* h, int32_t enable) {
   clear_error();
   HGL_CHECK_ARG(h != nullptr, "handle is NULL");

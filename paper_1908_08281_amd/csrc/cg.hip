@@ -8,8 +8,9 @@
 //   -> [preconditioner] -> reduce: beta, convergence
 //   -> direction update (P = R + beta P, or Z + beta P with a preconditioner).
 // Residual replacement (R = Y - M F with FP64 accumulation) runs at host
-// checks and optionally every rr_period iterations; the recursion continues
-// from the recomputed residual with the same search direction.
+// checks and optionally every rr_period iterations.  After a periodic one the
+// recursion continues from the recomputed residual with the same search
+// direction; a column that a check sends back to iterate restarts (P = R).
 // Inner products are accumulated in FP64 per workgroup and reduced in a fixed
 // order (deterministic).  Converged columns get alpha = 0; once every column
 // has converged the remaining launches of an enqueued chunk return at once.
@@ -22,12 +23,10 @@
 namespace hgl {
 
 // Column states.  A column whose recursive residual falls to the claim level
-// stops until a host-scheduled check recomputes its residual: done if that
-// meets tol, else active again.  In the iteration where it claims, its
-// search direction is still updated (kClaimNew), so that a column that goes
-// on after a check resumes with P = R + beta P consistent with its residual;
-// from the next iteration on it is frozen (kClaimed: alpha = 0, P kept).
-enum : int32_t { kActive = 0, kDone = 1, kBreakdown = 2, kClaimed = 3, kClaimNew = 4 };
+// stops (kClaimed: alpha = 0, P kept) until a host-scheduled check
+// recomputes its residual: done if that meets tol, else active again,
+// restarted from the recomputed residual.
+enum : int32_t { kActive = 0, kDone = 1, kBreakdown = 2, kClaimed = 3 };
 
 struct CgState {
   double* yy;      // [G*k] ||y||^2
@@ -194,27 +193,36 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(
 // owns a slot writes one contiguous row.  A reduction workgroup (kRedThreads
 // threads) owns kRedCols columns of one graph: thread (lane l = tid %
 // kRedCols, stripe j = tid / kRedCols) adds slots j, j + stripes, ... of
-// column c0 + l (a stripe reads kRedCols contiguous values per slot), then
-// one thread per column adds the stripes in order, so the sum is
-// deterministic.  The result is valid in stripe-0 threads.
+// column c0 + l (a stripe reads kRedCols contiguous values per slot; the
+// graph's tiles, then its long rows), kRedBurst independent loads in flight
+// per round, then the stripes are added by a fixed pairwise tree, so the sum
+// is deterministic.  The result is valid in stripe-0 threads.
 constexpr int kRedCols = 8;
 constexpr int kRedThreads = 1024;
 constexpr int kRedStripes = kRedThreads / kRedCols;
+constexpr int kRedBurst = 16;
 __device__ __forceinline__ double slot_sum(const double* __restrict__ part, int k, const int32_t* __restrict__ seg_slots,
                                            int g, int col, double (*lds)[kRedCols + 1]) {
   const int l = threadIdx.x % kRedCols, j = threadIdx.x / kRedCols;
   const int t0 = seg_slots[4 * g], t1 = seg_slots[4 * g + 1];
   const int l0 = seg_slots[4 * g + 2], l1 = seg_slots[4 * g + 3];
+  const int nt = t1 - t0, n = nt + (l1 - l0);
   double s = 0.0;
   if (col < k) {
-    int i = t0 + j;
-    for (; i + 3 * kRedStripes < t1; i += 4 * kRedStripes) {
-      const double a0 = part[int64_t(i) * k + col], a1 = part[int64_t(i + kRedStripes) * k + col];
-      const double a2 = part[int64_t(i + 2 * kRedStripes) * k + col], a3 = part[int64_t(i + 3 * kRedStripes) * k + col];
-      s += ((a0 + a1) + a2) + a3;
+    for (int i = j; i < n; i += kRedBurst * kRedStripes) {
+      double x[kRedBurst];
+#pragma unroll
+      for (int u = 0; u < kRedBurst; ++u) {
+        const int v = i + u * kRedStripes;
+        const int slot = v < nt ? t0 + v : l0 + (v - nt);
+        x[u] = v < n ? part[int64_t(slot) * k + col] : 0.0;
+      }
+#pragma unroll
+      for (int w = kRedBurst / 2; w >= 1; w >>= 1)
+#pragma unroll
+        for (int u = 0; u < w; ++u) x[u] += x[u + w];
+      s += x[0];
     }
-    for (; i < t1; i += kRedStripes) s += part[int64_t(i) * k + col];
-    for (i = l0 + j; i < l1; i += kRedStripes) s += part[int64_t(i) * k + col];
   }
   lds[j][l] = s;
   __syncthreads();
@@ -246,7 +254,8 @@ struct RedArgs {
 
 // Flag words: cnt(it) = columns still iterating after iteration it (cnt(-1)
 // after the start); chk(it) = columns still iterating after a check step run
-// between iterations it-1 and it.  One word per step, never reset inside the
+// between iterations it-1 and it (the check adds them to cnt(it-1) as well,
+// which gates iteration it).  One word per step, never reset inside the
 // loop, so no launch can observe a word another launch is clearing.
 struct Words {
   int32_t* base;
@@ -304,7 +313,6 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
         st.state[id] = done ? kDone : kActive;
         add_cnt = done ? 0 : 1;
       } else if constexpr (OP == RedOp::Alpha) {
-        if (st.state[id] == kClaimNew) st.state[id] = kClaimed;
         if (st.state[id] != kActive || st.rz[id] == 0.0) {
           st.alpha[id] = 0.0;
           break;
@@ -342,24 +350,28 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
         st.rr[id] = sum;
         st.rz[id] = rz;
         if (rel <= ra.claim * ra.tol) {  // stop for a check
-          st.state[id] = kClaimNew;
+          st.state[id] = kClaimed;
           break;
         }
         add_cnt = 1;
         rel_max = rel;
       } else {  // Check: sum is r'r of Y - M F recomputed in FP64
         const int32_t sid = st.state[id];
-        if (sid != kActive && sid != kClaimed && sid != kClaimNew) break;
+        if (sid != kActive && sid != kClaimed) break;
         const double rel = st.yy[id] > 0.0 ? sqrt(sum / st.yy[id]) : sqrt(sum);
         st.relres[id] = rel;
         // residual replacement: the recursion continues from the recomputed
-        // residual with the same search direction
+        // residual
         st.rr[id] = sum;
         st.rz[id] = rz;
         if (rel <= ra.tol) {
           st.state[id] = kDone;
         } else {
+          // restart: the direction is rebuilt from the recomputed residual
+          // (P = R, beta = 0), since the old one was scaled to a recursive
+          // residual that may have drifted far from the true one
           st.state[id] = kActive;
+          st.beta[id] = 0.0;
           add_chk = 1;
         }
       }
@@ -383,7 +395,10 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
                 static_cast<unsigned long long>(__double_as_longlong(rel_max)));
     }
   } else if constexpr (OP == RedOp::Check) {
-    if (add_chk) atomicAdd(wd.chk(it), add_chk);
+    if (add_chk) {
+      atomicAdd(wd.chk(it), add_chk);
+      atomicAdd(wd.cnt(it - 1), add_chk);  // iteration it runs for them
+    }
   }
 }
 
@@ -464,6 +479,9 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   // autotuned one (the partial-sum layout does not depend on either)
   const ColShape cs = pick_shape(k, sizeof(T), {Y, F, b.R}, {ldy, ldf, ld});
   const ColShape csg = o->tune ? tune_shape<T>(h, k, cs, Y, ldy, b.Z, b.Q, a_seg, b_seg, s) : cs;
+  h->last_shape[0] = csg.GL;
+  h->last_shape[1] = csg.V;
+  h->last_shape[2] = csg.slabs;
   const ColShape cs64 = pick_shape(k, 8, {Y, F, b.R}, {ldy, ldf, ld});
   const int red_blocks = G * ((k + kRedCols - 1) / kRedCols);
   // claim < 1 in FP32 leaves room for the drift of the FP32 recursion from
@@ -566,7 +584,8 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
 
   // Check step between iterations it-1 and it: recompute R = Y - M F with
   // FP64 accumulation (residual replacement); columns whose recomputed
-  // residual meets tol are done, the others go on from the same direction.
+  // residual meets tol are done, the others restart from it (restart(): P =
+  // R, or the preconditioned residual, since beta = 0 for them).
   auto check = [&](int it_next) -> int {
     HGL_TRY(resid(Gate{}));
     if (has_prec) HGL_TRY(precond(b.R, ld, b.Zp, ld, b.part3, Gate{}));
@@ -577,6 +596,20 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     HGL_HIP(hipGetLastError());
     prof_end(h, s);
     return HGL_OK;
+  };
+  auto restart = [&]() -> int {
+    prof_begin(h, kProfDirection, s);
+    const T* dir_src = has_prec ? b.Zp : b.R;
+    int rc4 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
+      dim3 grid(h->n_tiles, cs.slabs);
+      launch(h, -1, k_cg_direction<T, GL, V>, grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
+                         h->tile_seg, dir_src, b.P, ld, b.st.beta, static_cast<const int32_t*>(b.st.state), k,
+                         Gate{});
+      HGL_HIP(hipGetLastError());
+      return HGL_OK;
+    });
+    prof_end(h, s);
+    return rc4;
   };
 
   // Iterations are enqueued in chunks; between chunks the host reads the
@@ -637,12 +670,14 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   };
 
   int it = 0;
+  int n_chunks = 0, n_checks = 0, n_resumed = 0;
   bool all_done = false;
   double r_ref = -1.0;
   int it_ref = 0;
   int next = o->chunk > 0 ? o->chunk : std::max(2, chunk_for(2.0 * std::sqrt(kappa), rho));
   while (!all_done && it < o->max_iter) {
     const int n = std::min(next, o->max_iter - it);
+    ++n_chunks;
     if (use_graph && it == 0) {
       HGL_TRY(graph_chunk(n));
       it += n;
@@ -657,6 +692,11 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.chk(it), sizeof(int32_t), hipMemcpyDeviceToHost, s));
       HGL_HIP(hipStreamSynchronize(s));
       all_done = h->pinned_i[0] == 0;
+      ++n_checks;
+      if (!all_done) {
+        ++n_resumed;
+        HGL_TRY(restart());
+      }
       next = o->chunk > 0 ? o->chunk : 2;  // columns that go on are close to the end
       r_ref = -1.0;
       continue;
@@ -668,7 +708,14 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     r_ref = r_now;
     it_ref = it;
   }
-  if (!all_done) HGL_TRY(check(it));  // record the true residual of every unfinished column
+  if (!all_done) {
+    HGL_TRY(check(it));  // record the true residual of every unfinished column
+    ++n_checks;
+  }
+  h->last_cg[0] = it;
+  h->last_cg[1] = n_chunks;
+  h->last_cg[2] = n_checks;
+  h->last_cg[3] = n_resumed;
   // ---------------------------------------------------------- results
   double* pd = h->pinned_d;
   HGL_HIP(hipMemcpyAsync(pd, b.st.relres, sizeof(double) * gk, hipMemcpyDeviceToHost, s));

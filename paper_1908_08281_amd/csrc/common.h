@@ -145,6 +145,11 @@ struct hgl_handle {
   int prof_kind = -1;                                // open kind (prof_begin), or -1
   // autotuned column shapes: {k, element size, base V} -> {GL, V, slabs}
   std::vector<std::array<int, 6>> tuned;
+  // column shape {GL, V, slabs} of the operator gathers of the latest CG solve
+  int32_t last_shape[3] = {0, 0, 0};
+  // latest CG solve: {iterations enqueued, chunks, check steps, check steps
+  // after which columns went on iterating}
+  int32_t last_cg[4] = {0, 0, 0, 0};
   // CG iterations captured as a HIP graph (first chunk of a solve), replayed
   // while the solve's arguments stay the same
   hipStream_t capture_stream = nullptr;
@@ -183,7 +188,7 @@ ColShape tune_shape(hgl_handle* h, int k, const ColShape& base, const T* X, int6
                     const double* a_seg, const double* b_seg, hipStream_t s);
 
 // Early-exit gate of a kernel launched inside the CG loop: the kernel does
-// nothing when *active == 0 (every column converged) or when it is a
+// nothing when *active == 0 (no column iterates) or when it is a
 // conditional residual pass (*flag == 0 and not periodic).
 struct Gate {
   const int32_t* active = nullptr;

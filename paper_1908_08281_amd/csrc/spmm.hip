@@ -8,7 +8,7 @@
 // consecutive elements per access, so every gathered row is one coalesced
 // 16-byte-per-lane transaction.  Vertex rows with more than kLongRow incident
 // hyperedges (hubs) are split into chunks processed by separate workgroups;
-// the last chunk to arrive sums the chunk partials in chunk order and
+// a second launch sums each row's chunk partials in a fixed order and
 // finishes the row, so results do not depend on scheduling.
 #include "kernels.h"
 

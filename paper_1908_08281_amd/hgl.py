@@ -65,6 +65,20 @@ class Handle:
         check(lib().hgl_get_partition(self.ptr, *(C.byref(x) for x in v)), "hgl_get_partition")
         return dict(zip(("tiles", "hub_rows", "hub_chunks", "long_edges"), (x.value for x in v)))
 
+    def gather_shape(self) -> tuple:
+        """(lanes per row, elements per lane, column slabs) of the operator
+        gathers of the latest CG solve on this handle; zeros before one."""
+        v = (C.c_int32 * 3)()
+        check(lib().hgl_get_gather_shape(self.ptr, v), "hgl_get_gather_shape")
+        return tuple(int(x) for x in v)
+
+    def cg_stats(self) -> dict:
+        """Iterations enqueued, chunks, check steps and check steps after
+        which columns went on, of the latest CG solve on this handle."""
+        v = (C.c_int32 * 4)()
+        check(lib().hgl_get_cg_stats(self.ptr, v), "hgl_get_cg_stats")
+        return dict(zip(("iterations", "chunks", "checks", "resumed"), (int(x) for x in v)))
+
     @property
     def ptr(self) -> C.c_void_p:
         if self._ptr is None:

@@ -207,8 +207,56 @@ def test_autotuned_shape_matches_oracle_and_is_cached(k):
     tol = 1e-6 / (1 + 1 / p.lam)
     Y = torch.from_numpy(p.Y).to(dev, torch.float32)
     say("autotune", k)
+    assert h.gather_shape() == (0, 0, 0)
     F1, _, _, st1 = hgl().cg_solve(h, p.lam, Y, tol=tol, tune=True)
+    shape1 = h.gather_shape()
     F2, _, _, st2 = hgl().cg_solve(h, p.lam, Y, tol=tol, tune=True)
     assert st1 == 0 and st2 == 0
+    gl, v, slabs = shape1
+    assert gl in (4, 8, 16, 32, 64) and v in (1, 2, 4) and slabs >= 1
+    assert gl * v * slabs >= k and gl * v * (slabs - 1) < k
+    assert h.gather_shape() == shape1
     assert torch.equal(F1, F2)
     assert colrelerr(F1.cpu().numpy(), _dense_solution(p)).max() <= 1e-6
+
+
+def test_claimed_columns_restart_after_a_failed_check():
+    """FP32 CG near its attainable accuracy (no periodic residual
+    replacement): the FP32 recursion drifts from the true residual, so a
+    check step finds claimed columns short of tol; they restart from the
+    recomputed residual and every column still reaches tol in the true FP64
+    residual.  A tol below what FP32 F can attain ends at max_iter with
+    status 'not converged' and the true residual reported."""
+    import torch
+    dev = device()
+    p = synth.multi_rhs(N=3000, E=2400, k=16, smax=120)
+    h = build(p, dev)
+    H = lap.incidence_dense(p.N, p.E, p.edge_ptr, p.edge_vtx)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+
+    def true_relres(F, lam):
+        M = lap.system_matrix(H, p.w, lam)
+        Fn = F.cpu().numpy().astype(np.float64)
+        return np.linalg.norm(p.Y - M @ Fn, axis=0) / np.linalg.norm(p.Y, axis=0)
+
+    resumed = 0
+    for lam, tol in ((0.5, 1e-7), (0.1, 1e-7), (0.01, 1e-6), (0.01, 3e-7)):
+        say("restart", lam, tol)
+        F, it, rel, st = hgl().cg_solve(h, lam, Y, tol=tol, max_iter=3000, rr_period=0)
+        stats = h.cg_stats()
+        assert st == 0, (lam, tol, stats)
+        assert stats["checks"] >= 1 and stats["iterations"] >= int(it.max())
+        tr = true_relres(F, lam)
+        # the reported relres is the FP64 residual of the returned FP32 F
+        assert np.allclose(rel[0], tr, rtol=1e-6, atol=0)
+        assert tr.max() <= tol
+        resumed += stats["resumed"]
+    assert resumed >= 1, "no check step sent a column back: the cases do not test the restart"
+
+    say("restart: unattainable tol")
+    F, it, rel, st = hgl().cg_solve(h, 0.002, Y, tol=1e-6, max_iter=200, rr_period=0)
+    stats = h.cg_stats()
+    assert st == 1 and stats["iterations"] == 200 and stats["resumed"] >= 1
+    tr = true_relres(F, 0.002)
+    assert np.allclose(rel[0], tr, rtol=1e-6, atol=0)
+    assert tr.max() > 1e-6
