@@ -49,17 +49,22 @@ def gather_bytes(N, E, nnz, k, elem=4, covered=None, hubs=0):
 
     edge_gather (k_spmm_edge): read the P rows of the vertices that lie in
     some hyperedge (`covered`), write Z (E x k); edge_ptr, edge_vtx, c, s.
-    vertex_gather (k_spmm_vertex, one launch): read every Z row once, read P
-    and write Q for the N - hubs rows it finishes itself (hub rows, more
-    hyperedges than the hub threshold, are finished by a separate launch);
+    vertex_gather (k_spmm_vertex applying M, one launch): read every Z row
+    once, read P and write Q for the N - hubs rows it finishes itself (hub
+    rows, more hyperedges than the hub threshold, are finished by a separate
+    launch); vtx_ptr, vtx_edge, s.
+    vertex_step (k_spmm_vertex as the fused CG step): read every Z row once,
+    read P, F, R and write F, R for the N - hubs rows it finishes itself;
     vtx_ptr, vtx_edge, s.
-    cg_iteration: F, R, P read and written once, the E x k intermediate
-    written and read once, both CSR index arrays read once."""
+    cg_iteration: a lower bound, F, R, P read and written once, the E x k
+    intermediate written and read once, both CSR index arrays read once."""
     covered = N if covered is None else covered
-    vertex = elem * k * (E + 2 * (N - hubs)) + 4 * (N + 1 + nnz + (N - hubs))
+    idx = 4 * (N + 1 + nnz + (N - hubs))
+    vertex = elem * k * (E + 2 * (N - hubs)) + idx
+    step = elem * k * (E + 5 * (N - hubs)) + idx
     edge = elem * k * (covered + E) + 4 * (2 * E + 1 + nnz + covered)
     per_iter = elem * k * (6 * N + 2 * E) + 4 * (2 * nnz + 2 * N + 2 * E)
-    return {"vertex_gather": vertex, "edge_gather": edge, "cg_iteration": per_iter}
+    return {"vertex_gather": vertex, "vertex_step": step, "edge_gather": edge, "cg_iteration": per_iter}
 
 
 # ------------------------------------------------------- profile summaries
@@ -274,9 +279,9 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
     # template instances the solves ran (the column shape may be autotuned)
     gl, vw, _ = h.gather_shape()
     t = "float" if mode == "f32" else "double"
-    inst_v, inst_e = f"k_spmm_vertex<{t}, {t}, {gl}, {vw}, 1>", f"k_spmm_edge<{t}, {t}, {gl}, {vw}>"
+    inst_v, inst_e = f"k_spmm_vertex<{t}, {t}, {gl}, {vw}, 3>", f"k_spmm_edge<{t}, {t}, {gl}, {vw}, true>"
     if mv >= me:
-        roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_gather"],
+        roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_step"],
                      traffic=stored_traffic("k_spmm_vertex", name, inst_v))
         roof["instance"] = inst_v
     else:
@@ -395,7 +400,7 @@ def bench_learn(a):
     part = h.partition()
     ab = gather_bytes(p.N, p.E, p.nnz, k, 4, int(np.unique(p.edge_vtx).size), part["hub_rows"])
     nv, mv = prof["vertex_gather"]
-    roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_gather"])
+    roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_step"])
     cfg = {"workload": "weight_learning", "N": p.N, "E": p.E, "nnz": p.nnz, "k": k, "lambda": p.lam, "mu": mu,
            "eta": eta, "cg_iters_last": recs[-1]["cg_iters"], "adjoint_iters_last": recs[-1]["adjoint_iters"]}
     return _line("projected-gradient steps/s", a.steps / dt, "steps/s", a.steps, a.warmup, 1e3 * dt / a.steps,

@@ -306,7 +306,7 @@ static void free_handle(hgl_handle* h) {
   void* ptrs[] = {h->edge_ptr, h->edge_vtx, h->vtx_ptr, h->vtx_edge, h->w, h->dv, h->s64, h->c64,
                   h->s32, h->c32, h->tile_r0, h->tile_r1, h->tile_seg, h->long_row,
                   h->chunk_slot, h->chunk_begin, h->chunk_end, h->long_chunk0,
-                  h->seg_slots, h->long_seg, h->long_edge};
+                  h->seg_slots, h->long_seg, h->long_edge, h->etile_e0, h->etile_e1, h->seg_eslots};
   for (void* p : ptrs)
     if (p) hipFree(p);
   DevBuf* bufs[] = {&h->ws_z, &h->ws_z64, &h->ws_chunk, &h->ws_part, &h->ws_part2,
@@ -552,6 +552,41 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
                        h->long_edge);
     B_HIP(hipGetLastError());
     B_HIP(hipFreeAsync(tmpi, s));
+  }
+  // ---- edge tiles (graph-aligned) of the edge gather, and per graph the
+  // slot ranges of its partial sums: tiles, then long hyperedges (listed in
+  // increasing id, so each graph's are contiguous)
+  {
+    std::vector<int32_t> e0, e1;
+    for (int g = 0; g < G; ++g)
+      for (int32_t e = edge_off_host[g]; e < edge_off_host[g + 1]; e += kEdgeTile) {
+        e0.push_back(e);
+        e1.push_back(std::min(e + kEdgeTile, edge_off_host[g + 1]));
+      }
+    h->n_etiles = int32_t(e0.size());
+    B_TRY(dev_alloc(&h->etile_e0, e0.size()));
+    B_TRY(dev_alloc(&h->etile_e1, e1.size()));
+    if (!e0.empty()) {
+      B_HIP(hipMemcpyAsync(h->etile_e0, e0.data(), 4 * e0.size(), hipMemcpyHostToDevice, s));
+      B_HIP(hipMemcpyAsync(h->etile_e1, e1.data(), 4 * e1.size(), hipMemcpyHostToDevice, s));
+    }
+    std::vector<int32_t> le(h->n_long_edge);
+    if (h->n_long_edge)
+      B_HIP(hipMemcpyAsync(le.data(), h->long_edge, 4 * size_t(h->n_long_edge), hipMemcpyDeviceToHost, s));
+    B_HIP(hipStreamSynchronize(s));
+    h->seg_eslots_host.assign(4 * G, 0);
+    int t = 0, l = 0;
+    for (int g = 0; g < G; ++g) {
+      const int t0 = t, l0 = l;
+      t += (edge_off_host[g + 1] - edge_off_host[g] + kEdgeTile - 1) / kEdgeTile;
+      while (l < h->n_long_edge && le[l] < edge_off_host[g + 1]) ++l;
+      h->seg_eslots_host[4 * g + 0] = t0;
+      h->seg_eslots_host[4 * g + 1] = t;
+      h->seg_eslots_host[4 * g + 2] = h->n_etiles + l0;
+      h->seg_eslots_host[4 * g + 3] = h->n_etiles + l;
+    }
+    B_TRY(dev_alloc(&h->seg_eslots, 4 * G));
+    B_HIP(hipMemcpyAsync(h->seg_eslots, h->seg_eslots_host.data(), 16 * size_t(G), hipMemcpyHostToDevice, s));
   }
   B_HIP(hipStreamSynchronize(s));
 #undef B_TRY

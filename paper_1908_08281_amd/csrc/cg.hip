@@ -54,7 +54,8 @@ __device__ __forceinline__ void zero_long_slots(double* part, int n_tiles, int n
 
 // Start: (x0 not given) F = 0, R = Y; then P = R, or P = Zp when a
 // preconditioned residual Zp is given.  Partials of r'r (only when x0 is not
-// given; otherwise the residual pass produced them) and of y'y.
+// given; otherwise the residual pass produced them), of y'y, and (part_pp
+// not null) of p'p over the tiles.
 template <class T, int GL, int V>
 __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t n_tiles, const int32_t* __restrict__ tile_r0,
                                                     const int32_t* __restrict__ tile_r1, int n_slots,
@@ -62,15 +63,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t n_tiles, const int32
                                                     T* __restrict__ F, int64_t ldf, T* __restrict__ R,
                                                     T* __restrict__ P, int64_t ld, double* __restrict__ part_rr,
                                                     double* __restrict__ part_yy, int k, int x0_given,
-                                                    const T* __restrict__ Zp) {
+                                                    const T* __restrict__ Zp, double* __restrict__ part_pp) {
   constexpr int GPB = kBlock / GL, W = GL * V;
   __shared__ double lds[4 * W];
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
   const int col = blockIdx.y * W + lane * V;
   const int t = blockIdx.x;
-  double rr[V], yy[V];
+  double rr[V], yy[V], pp[V];
 #pragma unroll
-  for (int i = 0; i < V; ++i) rr[i] = yy[i] = 0.0;
+  for (int i = 0; i < V; ++i) rr[i] = yy[i] = pp[i] = 0.0;
   if (col < k) {
     for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
       T y[V], rv[V];
@@ -87,26 +88,30 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t n_tiles, const int32
       } else {
         load_row<V>(R + int64_t(r) * ld + col, rv);
       }
+      T pv[V];
       if (Zp) {
-        T zv[V];
-        load_row<V>(Zp + int64_t(r) * ld + col, zv);
-        store_row<V>(P + int64_t(r) * ld + col, zv);
+        load_row<V>(Zp + int64_t(r) * ld + col, pv);
       } else {
-        store_row<V>(P + int64_t(r) * ld + col, rv);
+#pragma unroll
+        for (int i = 0; i < V; ++i) pv[i] = rv[i];
       }
+      store_row<V>(P + int64_t(r) * ld + col, pv);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         yy[i] += double(y[i]) * double(y[i]);
         rr[i] += double(rv[i]) * double(rv[i]);
+        pp[i] += double(pv[i]) * double(pv[i]);
       }
     }
   }
   double syy = block_colsum<GL, V>(yy, lds);
   double srr = block_colsum<GL, V>(rr, lds);
+  double spp = part_pp ? block_colsum<GL, V>(pp, lds) : 0.0;
   const int c = blockIdx.y * W + threadIdx.x;
   if (threadIdx.x < W && c < k) {
     part_yy[int64_t(t) * k + c] = syy;
     if (!x0_given) part_rr[int64_t(t) * k + c] = srr;
+    if (part_pp) part_pp[int64_t(t) * k + c] = spp;
   }
   if (blockIdx.y == 0) {
     zero_long_slots(part_yy, n_tiles, n_slots, n_long, k);
@@ -158,32 +163,48 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
 }
 
 // P = R + beta P for the iterating columns; a claimed column keeps P.
+// part_pp (nullable): tile partials of p'p of the new P (the vertex half of
+// the next p'Mp).
 template <class T, int GL, int V>
 __global__ __launch_bounds__(kBlock) void k_cg_direction(
     const int32_t* __restrict__ tile_r0, const int32_t* __restrict__ tile_r1,
     const int32_t* __restrict__ tile_seg, const T* __restrict__ R, T* __restrict__ P, int64_t ld,
-    const double* __restrict__ beta, const int32_t* __restrict__ state, int k, Gate gate) {
+    const double* __restrict__ beta, const int32_t* __restrict__ state, int k, Gate gate,
+    double* __restrict__ part_pp) {
   if (gate.skip()) return;
   constexpr int GPB = kBlock / GL, W = GL * V;
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
   const int col = blockIdx.y * W + lane * V;
   const int t = blockIdx.x;
-  if (col >= k) return;
-  const int g = tile_seg[t];
-  T be[V];
-  bool keep[V];
+  double pp[V];
 #pragma unroll
-  for (int i = 0; i < V; ++i) {
-    be[i] = T(beta[int64_t(g) * k + col + i]);
-    keep[i] = state[int64_t(g) * k + col + i] == kClaimed;
+  for (int i = 0; i < V; ++i) pp[i] = 0.0;
+  if (col < k) {
+    const int g = tile_seg[t];
+    T be[V];
+    bool keep[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      be[i] = T(beta[int64_t(g) * k + col + i]);
+      keep[i] = state[int64_t(g) * k + col + i] == kClaimed;
+    }
+    for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
+      T rv[V], p[V];
+      load_row<V>(R + int64_t(r) * ld + col, rv);
+      load_row<V>(P + int64_t(r) * ld + col, p);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        p[i] = keep[i] ? p[i] : rv[i] + be[i] * p[i];
+        pp[i] += double(p[i]) * double(p[i]);
+      }
+      store_row<V>(P + int64_t(r) * ld + col, p);
+    }
   }
-  for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
-    T rv[V], p[V];
-    load_row<V>(R + int64_t(r) * ld + col, rv);
-    load_row<V>(P + int64_t(r) * ld + col, p);
-#pragma unroll
-    for (int i = 0; i < V; ++i) p[i] = keep[i] ? p[i] : rv[i] + be[i] * p[i];
-    store_row<V>(P + int64_t(r) * ld + col, p);
+  if (part_pp) {
+    __shared__ double lds[4 * W];
+    const double spp = block_colsum<GL, V>(pp, lds);
+    const int c = blockIdx.y * W + threadIdx.x;
+    if (threadIdx.x < W && c < k) part_pp[int64_t(t) * k + c] = spp;
   }
 }
 
@@ -202,10 +223,10 @@ constexpr int kRedThreads = 1024;
 constexpr int kRedStripes = kRedThreads / kRedCols;
 constexpr int kRedBurst = 16;
 __device__ __forceinline__ double slot_sum(const double* __restrict__ part, int k, const int32_t* __restrict__ seg_slots,
-                                           int g, int col, double (*lds)[kRedCols + 1]) {
+                                           int g, int col, double (*lds)[kRedCols + 1], bool with_long = true) {
   const int l = threadIdx.x % kRedCols, j = threadIdx.x / kRedCols;
   const int t0 = seg_slots[4 * g], t1 = seg_slots[4 * g + 1];
-  const int l0 = seg_slots[4 * g + 2], l1 = seg_slots[4 * g + 3];
+  const int l0 = seg_slots[4 * g + 2], l1 = with_long ? seg_slots[4 * g + 3] : l0;
   const int nt = t1 - t0, n = nt + (l1 - l0);
   double s = 0.0;
   if (col < k) {
@@ -242,9 +263,15 @@ enum class RedOp { Init, Alpha, Beta, Check };
 struct RedArgs {
   int G, k, n_slots;
   const int32_t* seg_slots;
-  const double* part;   // r'r (Init, Beta, Check) or p'Mp (Alpha)
+  const double* part;   // r'r (Init, Beta, Check) or p'Mp (Alpha, not split)
   const double* part2;  // y'y (Init)
   const double* part3;  // r'z (Init, Beta, Check) when preconditioned
+  // Alpha with p'Mp split as a p'p - b sum_e c_e |(H' S p)_e|^2 (eq. 1):
+  // tile partials of p'p and edge-slot partials of the hyperedge sum
+  const double* pp;     // null: p'Mp from part
+  const double* epart;
+  const int32_t* seg_eslots;
+  const double* ab;     // [2G]: a_g = 1 + 1/lambda_g, then b_g = 1/lambda_g
   double tol;
   double claim;         // Beta: recursive relres at which a column stops for a check
   int iter;             // iteration index
@@ -284,7 +311,18 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
   const int ngrp = (ra.k + kRedCols - 1) / kRedCols;
   const int g = blockIdx.x / ngrp;
   const int col = (blockIdx.x % ngrp) * kRedCols + threadIdx.x % kRedCols;
-  const double sum = slot_sum(ra.part, ra.k, ra.seg_slots, g, col, lds);
+  double sum;
+  if constexpr (OP == RedOp::Alpha) {
+    if (ra.pp) {
+      const double spp = slot_sum(ra.pp, ra.k, ra.seg_slots, g, col, lds, false);
+      const double se = slot_sum(ra.epart, ra.k, ra.seg_eslots, g, col, lds);
+      sum = ra.ab[g] * spp - ra.ab[ra.G + g] * se;
+    } else {
+      sum = slot_sum(ra.part, ra.k, ra.seg_slots, g, col, lds);
+    }
+  } else {
+    sum = slot_sum(ra.part, ra.k, ra.seg_slots, g, col, lds);
+  }
   double sum2 = 0.0;
   if constexpr (OP == RedOp::Init) sum2 = slot_sum(ra.part2, ra.k, ra.seg_slots, g, col, lds);
   double rz = sum;  // r'z, = r'r without a preconditioner
@@ -415,6 +453,8 @@ struct CgBuffers {
   double* part2;
   double* part3;
   T* Zp;       // preconditioned residual (PCG)
+  double* pp;     // p'p tile partials (fused step)
+  double* epart;  // edge-slot partials of sum_e c_e |(H' S p)_e|^2 (fused step)
   CgState st;
 };
 
@@ -427,6 +467,11 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   hipStream_t s = s_user;
   const bool fp32 = sizeof(T) == 4;
   const bool has_prec = prec != nullptr;
+  // Without a preconditioner the step is fused: p'Mp = a p'p - b sum_e c_e
+  // |(H' S p)_e|^2 is reduced from the direction and edge-gather partials
+  // before the vertex gather, which then applies F += alpha P, R -= alpha Q
+  // with Q kept in registers (no Q round trip, no separate update pass).
+  const bool fused = !has_prec;
   const int N = h->N, E = h->E, G = h->G;
   const int64_t ld = k;  // internal vectors
   const int nsl = n_slots(h);
@@ -437,7 +482,9 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   if (fp32) HGL_TRY(h->ws_z64.reserve(sizeof(double) * size_t(std::max(E, 1)) * ld));
   HGL_TRY(h->ws_part.reserve(sizeof(double) * size_t(nsl) * k));
   HGL_TRY(h->ws_part2.reserve(sizeof(double) * size_t(nsl) * k));
-  if (has_prec) HGL_TRY(h->ws_extra[0].reserve(sizeof(double) * size_t(nsl) * k));
+  // part3 (r'z) with a preconditioner; p'p tile partials when fused
+  HGL_TRY(h->ws_extra[0].reserve(sizeof(double) * size_t(nsl) * k));
+  if (fused) HGL_TRY(h->ws_extra[5].reserve(sizeof(double) * size_t(std::max(n_eslots(h), 1)) * k));
   const size_t gk = size_t(G) * k;
   HGL_TRY(h->ws_state.reserve(sizeof(double) * 6 * gk + sizeof(int32_t) * (2 * gk + 2 + Words::count(o->max_iter))));
   HGL_TRY(ensure_pinned(h, 2 * gk + 8));
@@ -455,6 +502,8 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   b.part = h->ws_part.as<double>();
   b.part2 = h->ws_part2.as<double>();
   b.part3 = has_prec ? h->ws_extra[0].as<double>() : nullptr;
+  b.pp = fused ? h->ws_extra[0].as<double>() : nullptr;
+  b.epart = fused ? h->ws_extra[5].as<double>() : nullptr;
   b.Zp = has_prec ? b.Q + size_t(N) * ld : nullptr;
   double* sd = h->ws_state.as<double>();
   b.st.yy = sd;
@@ -487,7 +536,8 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   // claim < 1 in FP32 leaves room for the drift of the FP32 recursion from
   // the true residual
   const double claim = fp32 ? 0.5 : 1.0;
-  RedArgs ra{G, k, nsl, h->seg_slots, b.part, b.part2, b.part3, o->tol, claim, 0, 0, has_prec ? 1 : 0};
+  RedArgs ra{G,      k,       nsl,           h->seg_slots, b.part, b.part2, b.part3, b.pp,
+             b.epart, h->seg_eslots, a_seg, o->tol, claim,  0,      0,       has_prec ? 1 : 0};
 
   // preconditioner: Zp = P^-1 R with partial r'z into part3 (or into part)
   auto precond = [&](const T* Rin, int64_t ldr, T* Zout, int64_t ldz, double* part, Gate gate) -> int {
@@ -522,7 +572,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     dim3 grid(h->n_tiles, cs.slabs);
     launch(h, -1, k_cg_init<T, GL, V>, grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
                        h->tile_r1, nsl, h->n_long, Y, ldy, F, ldf, b.R, b.P, ld, b.part, b.part2, k,
-                       x0 ? 1 : 0, has_prec ? static_cast<const T*>(b.Zp) : nullptr);
+                       x0 ? 1 : 0, has_prec ? static_cast<const T*>(b.Zp) : nullptr, b.pp);
     HGL_HIP(hipGetLastError());
     return HGL_OK;
   });
@@ -535,30 +585,46 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   // ---------------------------------------------------------- iterations
   auto iteration = [&](int it) -> int {
     Gate g_prev{wd.cnt(it - 1), nullptr, 1};
-    prof_begin(h, kProfEdge, s);
-    HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, csg, g_prev, s));
-    prof_end(h, s);
-    prof_begin(h, kProfVertex, s);
-    HGL_TRY(launch_spmm_vertex<T, T>(h, VMode::ApplyDot, b.P, ld, b.Z, ld, nullptr, 0, b.Q, ld, a_seg,
-                                     b_seg, b.part, k, csg, g_prev, s));
-    prof_end(h, s);
     RedArgs r = ra;
     r.iter = it;
-    prof_begin(h, kProfReduce, s);
-    launch(h, -1, k_cg_reduce<RedOp::Alpha>, dim3(red_blocks), dim3(kRedThreads), 0, s, r, b.st, wd);
-    HGL_HIP(hipGetLastError());
-    prof_end(h, s);
-    prof_begin(h, kProfUpdate, s);
-    int rc2 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
-      dim3 grid(h->n_tiles, cs.slabs);
-      launch(h, -1, k_cg_update<T, GL, V>, grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
-                         h->tile_r1, h->tile_seg, nsl, h->n_long, F, ldf, b.R, b.P, b.Q, ld,
-                         b.st.alpha, b.part, k, g_prev);
+    if (fused) {
+      // edge gather + hyperedge half of p'Mp -> alpha -> vertex gather with
+      // the update (partial r'r of the new R)
+      prof_begin(h, kProfEdge, s);
+      HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, csg, g_prev, s, b.epart));
+      prof_end(h, s);
+      prof_begin(h, kProfReduce, s);
+      launch(h, -1, k_cg_reduce<RedOp::Alpha>, dim3(red_blocks), dim3(kRedThreads), 0, s, r, b.st, wd);
       HGL_HIP(hipGetLastError());
-      return HGL_OK;
-    });
-    HGL_TRY(rc2);
-    prof_end(h, s);
+      prof_end(h, s);
+      prof_begin(h, kProfVertex, s);
+      HGL_TRY(launch_spmm_vertex<T, T>(h, VMode::Step, b.P, ld, b.Z, ld, nullptr, 0, nullptr, 0, a_seg, b_seg,
+                                       b.part, k, csg, g_prev, s, UpdArgs<T>{F, ldf, b.R, ld, b.st.alpha}));
+      prof_end(h, s);
+    } else {
+      prof_begin(h, kProfEdge, s);
+      HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, csg, g_prev, s));
+      prof_end(h, s);
+      prof_begin(h, kProfVertex, s);
+      HGL_TRY(launch_spmm_vertex<T, T>(h, VMode::ApplyDot, b.P, ld, b.Z, ld, nullptr, 0, b.Q, ld, a_seg,
+                                       b_seg, b.part, k, csg, g_prev, s));
+      prof_end(h, s);
+      prof_begin(h, kProfReduce, s);
+      launch(h, -1, k_cg_reduce<RedOp::Alpha>, dim3(red_blocks), dim3(kRedThreads), 0, s, r, b.st, wd);
+      HGL_HIP(hipGetLastError());
+      prof_end(h, s);
+      prof_begin(h, kProfUpdate, s);
+      int rc2 = HGL_DISPATCH_SHAPE(cs, sizeof(T), {
+        dim3 grid(h->n_tiles, cs.slabs);
+        launch(h, -1, k_cg_update<T, GL, V>, grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
+                           h->tile_r1, h->tile_seg, nsl, h->n_long, F, ldf, b.R, b.P, b.Q, ld,
+                           b.st.alpha, b.part, k, g_prev);
+        HGL_HIP(hipGetLastError());
+        return HGL_OK;
+      });
+      HGL_TRY(rc2);
+      prof_end(h, s);
+    }
     const int periodic = (o->rr_period > 0 && (it + 1) % o->rr_period == 0) ? 1 : 0;
     if (periodic) HGL_TRY(resid(g_prev));
     if (has_prec) HGL_TRY(precond(b.R, ld, b.Zp, ld, b.part3, g_prev));
@@ -574,7 +640,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       dim3 grid(h->n_tiles, cs.slabs);
       launch(h, -1, k_cg_direction<T, GL, V>, grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
                          h->tile_seg, dir_src, b.P, ld, b.st.beta, static_cast<const int32_t*>(b.st.state), k,
-                         g_now);
+                         g_now, b.pp);
       HGL_HIP(hipGetLastError());
       return HGL_OK;
     });
@@ -604,7 +670,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       dim3 grid(h->n_tiles, cs.slabs);
       launch(h, -1, k_cg_direction<T, GL, V>, grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
                          h->tile_seg, dir_src, b.P, ld, b.st.beta, static_cast<const int32_t*>(b.st.state), k,
-                         Gate{});
+                         Gate{}, b.pp);
       HGL_HIP(hipGetLastError());
       return HGL_OK;
     });
@@ -639,7 +705,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     const std::vector<uint64_t> key = {
         sizeof(T), uint64_t(k), uint64_t(G), uint64_t(n), uint64_t(ldy), uint64_t(ldf), u(Y), u(F),
         u(h->ws_vec.p), u(h->ws_z.p), u(h->ws_z64.p), u(h->ws_part.p), u(h->ws_part2.p), u(h->ws_extra[0].p),
-        u(h->ws_state.p), u(h->ws_chunk.p), u(h->ws_ab.p), u(prec ? prec->ctx : nullptr), uint64_t(o->rr_period),
+        u(h->ws_state.p), u(h->ws_chunk.p), u(h->ws_ab.p), u(h->ws_extra[5].p), u(prec ? prec->ctx : nullptr), uint64_t(o->rr_period),
         tol_bits, uint64_t(cs.GL), uint64_t(cs.V), uint64_t(cs.slabs), uint64_t(csg.GL), uint64_t(csg.V),
         uint64_t(csg.slabs), u(wd.base), uint64_t(o->max_iter)};
     if (!h->cg_graph || key != h->cg_graph_key) {

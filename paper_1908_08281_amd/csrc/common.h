@@ -7,6 +7,7 @@
 #include <array>
 #include <cstdint>
 #include <tuple>
+#include <type_traits>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -59,6 +60,8 @@ constexpr int kChunk = 128;        // hyperedges per chunk of a split vertex row
 constexpr int kStageIdx = 2048;    // hyperedge ids of a tile staged in LDS
 constexpr int kGather = 8;         // gathered rows in flight per lane group
 constexpr int kLongEdge = 32;      // hyperedges with more members get a whole workgroup
+constexpr int kEdgeTile = 32;      // hyperedges per workgroup of the edge gather
+constexpr int kEdgeStageIdx = 1024;  // member ids of an edge tile staged in LDS
 constexpr int kProfKinds = 16;     // kernel kinds of the timing counters
 
 // ------------------------------------------------------ device buffers --
@@ -117,6 +120,15 @@ struct hgl_handle {
   // hyperedges with more than kLongEdge members, increasing id (device)
   int32_t n_long_edge = 0;
   int32_t* long_edge = nullptr;      // [n_long_edge]
+
+  // edge tiles of the edge gather: kEdgeTile consecutive hyperedges of one
+  // graph (device); per graph the slot ranges {t0, t1, l0, l1} of the edge
+  // gather's partial sums over tiles + long hyperedges (device [G*4], host)
+  int32_t n_etiles = 0;
+  int32_t* etile_e0 = nullptr;       // [n_etiles]
+  int32_t* etile_e1 = nullptr;       // [n_etiles]
+  int32_t* seg_eslots = nullptr;
+  std::vector<int32_t> seg_eslots_host;
 
   // per segment: partial-slot ranges {t0, t1, l0, l1} (device, [G*4]) over
   // tiles + long rows
@@ -251,20 +263,37 @@ int cg_run(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const voi
            int64_t ldf, int k, int32_t* iters_host, double* relres_host, const Precond* prec, hipStream_t s);
 
 // Operator application pieces (spmm.hip).
-enum class VMode { Apply = 0, ApplyDot = 1, Resid = 2 };
+enum class VMode { Apply = 0, ApplyDot = 1, Resid = 2, Step = 3 };
+
+// Operands of the fused CG step (VMode::Step); unused by the other modes.
+template <class T>
+struct UpdArgs {
+  T* F = nullptr;
+  int64_t ldf = 0;
+  T* R = nullptr;
+  int64_t ldr = 0;
+  const double* alpha = nullptr;  // [G*k]
+};
 
 // Z = C H' S P: edge-major gather.  TIn = type of P, TAcc = type of Z.
+// part (nullable): FP64 partial sums of sum_e c_e |(H' S P)_e|^2 per column,
+// slot-major over the edge slots (edge tiles, then long hyperedges).
 template <class TIn, class TAcc>
 int launch_spmm_edge(const hgl_handle* h, const TIn* P, int64_t ldp, TAcc* Z, int64_t ldz,
-                     int k, const ColShape& cs, Gate gate, hipStream_t s);
+                     int k, const ColShape& cs, Gate gate, hipStream_t s, double* part = nullptr);
+
+// Edge-slot count of the edge gather's partial sums.
+inline int n_eslots(const hgl_handle* h) { return h->n_etiles + h->n_long_edge; }
 
 // Vertex-major gather + epilogue.  Apply: Out = a X - b s H Z.  ApplyDot: same
 // and partial <X, Out> per column.  Resid: Out = Y - (a X - b s H Z) with FP64
-// accumulation and partial <Out, Out>.  a, b per segment (device, [G]).
+// accumulation and partial <Out, Out>.  Step (T = TZ, X = P): with Q = a P -
+// b s H Z kept in registers, u.F += alpha P, u.R -= alpha Q and partial
+// <R, R> of the new R.  a, b per segment (device, [G]).
 template <class T, class TZ>
 int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx, const TZ* Z,
                        int64_t ldz, const T* Y, int64_t ldy, T* Out, int64_t ldo,
                        const double* a_seg, const double* b_seg, double* part, int k,
-                       const ColShape& cs, Gate gate, hipStream_t s);
+                       const ColShape& cs, Gate gate, hipStream_t s, UpdArgs<T> u = {});
 
 }  // namespace hgl

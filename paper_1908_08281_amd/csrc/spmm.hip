@@ -46,51 +46,99 @@ __device__ __forceinline__ void gather_scaled(const TIn* __restrict__ P, int64_t
   }
 }
 
-// Workgroups [0, n_short_wg) take GPB consecutive hyperedges, one per lane
-// group, and skip the long ones (more than kLongEdge members); each further
-// workgroup takes one long hyperedge, its groups summing contiguous shares
-// of the members, combined by a fixed-order block reduction.
-template <class TIn, class TAcc, int GL, int V>
+// Workgroups [0, n_etiles) take one edge tile each (kEdgeTile consecutive
+// hyperedges of one graph, offsets and member ids staged in LDS), one
+// hyperedge per lane group at a time, skipping the long ones (more than
+// kLongEdge members); each further workgroup takes one long hyperedge, its
+// groups summing contiguous shares of the members, combined by a fixed-order
+// block reduction.  DOT: the workgroup also writes the FP64 partial
+// sum_e c_e |u_e|^2 per column (u_e = (H' S P)_e, so Z_e = c_e u_e) to
+// part[slot][k], slot = tile, or n_etiles + long-hyperedge index: the
+// hyperedge half of p'Mp (eq. 1).
+struct EdgeArgs {
+  int32_t n_etiles;
+  const int32_t* etile_e0;
+  const int32_t* etile_e1;
+  const int32_t* edge_ptr;
+  const int32_t* edge_vtx;
+  const int32_t* long_edge;
+};
+
+template <class TIn, class TAcc, int GL, int V, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmm_edge(
-    int32_t E, const int32_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_vtx,
-    int32_t n_short_wg, const int32_t* __restrict__ long_edge,
-    const TAcc* __restrict__ s, const TAcc* __restrict__ c, const TIn* __restrict__ P, int64_t ldp,
-    TAcc* __restrict__ Z, int64_t ldz, int k, Gate gate) {
+    EdgeArgs ea, const TAcc* __restrict__ s, const TAcc* __restrict__ c, const TIn* __restrict__ P, int64_t ldp,
+    TAcc* __restrict__ Z, int64_t ldz, double* __restrict__ part, int k, Gate gate) {
   if (gate.skip()) return;
   constexpr int GPB = kBlock / GL, W = GL * V;
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
   const int col = blockIdx.y * W + lane * V;
+  const int cc = blockIdx.y * W + threadIdx.x;
+  __shared__ double lds_raw[4 * W];  // block reductions (either branch)
+  if (int(blockIdx.x) < ea.n_etiles) {
+    const int t = blockIdx.x;
+    const int e0 = ea.etile_e0[t], e1 = ea.etile_e1[t];
+    __shared__ int32_t s_ptr[kEdgeTile + 1];
+    __shared__ int32_t s_idx[kEdgeStageIdx];
+    const int ne = e1 - e0;
+    for (int i = threadIdx.x; i <= ne; i += kBlock) s_ptr[i] = ea.edge_ptr[e0 + i];
+    __syncthreads();
+    const int base = s_ptr[0];
+    const int staged = min(s_ptr[ne] - base, kEdgeStageIdx);
+    for (int i = threadIdx.x; i < staged; i += kBlock) s_idx[i] = ea.edge_vtx[base + i];
+    __syncthreads();
+    double dot[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) dot[i] = 0.0;
+    if (col < k) {
+      for (int e = e0 + grp; e < e1; e += GPB) {
+        const int b = s_ptr[e - e0], en = s_ptr[e - e0 + 1];
+        if (en - b > kLongEdge) continue;
+        TAcc acc[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[i] = TAcc(0);
+        if (en - base <= staged)
+          gather_scaled<V>(P, ldp, s, s_idx, b - base, en - base, col, acc);
+        else
+          gather_scaled<V>(P, ldp, s, ea.edge_vtx, b, en, col, acc);
+        const TAcc ce = c[e];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const TAcc z = ce * acc[i];
+          if constexpr (DOT) dot[i] += double(acc[i]) * double(z);
+          acc[i] = z;
+        }
+        store_row<V>(Z + int64_t(e) * ldz + col, acc);
+      }
+    }
+    if constexpr (DOT) {
+      const double tot = block_colsum<GL, V>(dot, lds_raw);
+      if (threadIdx.x < W && cc < k) part[int64_t(t) * k + cc] = tot;
+    }
+    return;
+  }
+  TAcc* lds = reinterpret_cast<TAcc*>(lds_raw);
+  const int li = blockIdx.x - ea.n_etiles;
+  const int e = ea.long_edge[li];
+  const int b = ea.edge_ptr[e], en = ea.edge_ptr[e + 1];
   TAcc acc[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) acc[i] = TAcc(0);
-  if (int(blockIdx.x) < n_short_wg) {
-    const int e = blockIdx.x * GPB + grp;
-    if (e >= E || col >= k) return;
-    const int b = edge_ptr[e], en = edge_ptr[e + 1];
-    if (en - b > kLongEdge) return;
-    gather_scaled<V>(P, ldp, s, edge_vtx, b, en, col, acc);
-    const TAcc ce = c[e];
-#pragma unroll
-    for (int i = 0; i < V; ++i) acc[i] *= ce;
-    store_row<V>(Z + int64_t(e) * ldz + col, acc);
-    return;
-  }
-  __shared__ TAcc lds[4 * W];
-  const int e = long_edge[blockIdx.x - n_short_wg];
-  const int b = edge_ptr[e], en = edge_ptr[e + 1];
   if (col < k) {
     const int per = (en - b + GPB - 1) / GPB;
     const int jb = b + grp * per;
-    gather_scaled<V>(P, ldp, s, edge_vtx, jb, min(jb + per, en), col, acc);
+    gather_scaled<V>(P, ldp, s, ea.edge_vtx, jb, min(jb + per, en), col, acc);
   }
   const TAcc sum = block_colsum<GL, V>(acc, lds);
-  const int cc = blockIdx.y * W + threadIdx.x;
-  if (threadIdx.x < W && cc < k) Z[int64_t(e) * ldz + cc] = c[e] * sum;
+  if (threadIdx.x < W && cc < k) {
+    const TAcc z = c[e] * sum;
+    Z[int64_t(e) * ldz + cc] = z;
+    if constexpr (DOT) part[int64_t(ea.n_etiles + li) * k + cc] = double(sum) * double(z);
+  }
 }
 
 template <class TIn, class TAcc>
 int launch_spmm_edge(const hgl_handle* h, const TIn* P, int64_t ldp, TAcc* Z, int64_t ldz, int k,
-                     const ColShape& cs, Gate gate, hipStream_t st) {
+                     const ColShape& cs, Gate gate, hipStream_t st, double* part) {
   if (h->E == 0) return HGL_OK;
   const TAcc* s;
   const TAcc* c;
@@ -101,12 +149,15 @@ int launch_spmm_edge(const hgl_handle* h, const TIn* P, int64_t ldp, TAcc* Z, in
     s = h->s32;
     c = h->c32;
   }
+  const EdgeArgs ea{h->n_etiles, h->etile_e0, h->etile_e1, h->edge_ptr, h->edge_vtx, h->long_edge};
   return HGL_DISPATCH_SHAPE(cs, sizeof(TAcc), {
-    constexpr int GPB = kBlock / GL;
-    const int n_short = (h->E + GPB - 1) / GPB;
-    dim3 grid(n_short + h->n_long_edge, cs.slabs);
-    launch(h, -1, k_spmm_edge<TIn, TAcc, GL, V>, grid, dim3(kBlock), 0, st, h->E,
-                       h->edge_ptr, h->edge_vtx, n_short, h->long_edge, s, c, P, ldp, Z, ldz, k, gate);
+    dim3 grid(h->n_etiles + h->n_long_edge, cs.slabs);
+    if (part)
+      launch(h, -1, k_spmm_edge<TIn, TAcc, GL, V, true>, grid, dim3(kBlock), 0, st, ea, s, c, P, ldp, Z, ldz,
+             part, k, gate);
+    else
+      launch(h, -1, k_spmm_edge<TIn, TAcc, GL, V, false>, grid, dim3(kBlock), 0, st, ea, s, c, P, ldp, Z, ldz,
+             part, k, gate);
     HGL_HIP(hipGetLastError());
     return HGL_OK;
   });
@@ -134,11 +185,13 @@ struct VertexArgs {
 
 // MODE 0: Out = a X - b s H Z.  MODE 1: same + partial <X, Out>.
 // MODE 2: Out = Y - (a X - b s H Z), partial <Out, Out>, all in TZ (FP64).
+// MODE 3 (CG step with X = P): Q = a P - b s H Z stays in registers;
+// F += alpha P, R -= alpha Q (u.F, u.R), partial <R, R> of the new R.
 template <class T, class TZ, int GL, int V, int MODE>
 __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
     VertexArgs va, const TZ* __restrict__ s, const T* __restrict__ X, int64_t ldx,
     const TZ* __restrict__ Z, int64_t ldz, const T* __restrict__ Y, int64_t ldy, T* __restrict__ Out,
-    int64_t ldo, double* __restrict__ part, TZ* __restrict__ chunk_part, int k, Gate gate) {
+    int64_t ldo, double* __restrict__ part, TZ* __restrict__ chunk_part, int k, Gate gate, UpdArgs<T> u) {
   if (gate.skip()) return;
   constexpr int GPB = kBlock / GL;
   constexpr int W = GL * V;
@@ -166,13 +219,22 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
     for (int i = threadIdx.x; i < staged; i += kBlock) s_idx[i] = va.vtx_edge[base + i];
     __syncthreads();
     double dot[V];
+    T al[V];
 #pragma unroll
-    for (int i = 0; i < V; ++i) dot[i] = 0.0;
+    for (int i = 0; i < V; ++i) {
+      dot[i] = 0.0;
+      if constexpr (MODE == 3) al[i] = colok ? T(u.alpha[int64_t(g) * k + col + i]) : T(0);
+    }
     for (int r = r0 + grp; r < r1 && colok; r += GPB) {
       const int eb = s_ptr[r - r0], ee = s_ptr[r - r0 + 1];
       if (ee - eb > kLongRow) continue;  // finished by its chunks
       T x[V], o[V];
       load_row<V>(X + int64_t(r) * ldx + col, x);  // independent of the gather: issue first
+      T fv[V], rv[V];
+      if constexpr (MODE == 3) {
+        load_row<V>(u.F + int64_t(r) * u.ldf + col, fv);
+        load_row<V>(u.R + int64_t(r) * u.ldr + col, rv);
+      }
       const TZ sr = s[r];
       TZ acc[V];
 #pragma unroll
@@ -196,9 +258,19 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
           TZ q = a * TZ(x[i]) - bb * sr * acc[i];
           o[i] = T(q);
           if constexpr (MODE == 1) dot[i] += double(x[i]) * double(o[i]);
+          if constexpr (MODE == 3) {
+            fv[i] += al[i] * x[i];
+            rv[i] -= al[i] * o[i];
+            dot[i] += double(rv[i]) * double(rv[i]);
+          }
         }
       }
-      store_row<V>(Out + int64_t(r) * ldo + col, o);
+      if constexpr (MODE == 3) {
+        store_row<V>(u.F + int64_t(r) * u.ldf + col, fv);
+        store_row<V>(u.R + int64_t(r) * u.ldr + col, rv);
+      } else {
+        store_row<V>(Out + int64_t(r) * ldo + col, o);
+      }
     }
     if constexpr (MODE != 0) {
       double tot = block_colsum<GL, V>(dot, lds_d);
@@ -236,7 +308,7 @@ template <class T, class TZ, int GL, int V, int MODE>
 __global__ __launch_bounds__(kBlock) void k_spmm_vertex_finish(
     VertexArgs va, const TZ* __restrict__ s, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ldy, T* __restrict__ Out, int64_t ldo, double* __restrict__ part,
-    const TZ* __restrict__ chunk_part, int k, Gate gate) {
+    const TZ* __restrict__ chunk_part, int k, Gate gate, UpdArgs<T> u) {
   if (gate.skip()) return;
   constexpr int GPB = kBlock / GL;
   constexpr int W = GL * V;
@@ -281,6 +353,17 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex_finish(
     TZ ri = TZ(Y[int64_t(r) * ldy + c]) - (a * x - bb * sr * sum);
     Out[int64_t(r) * ldo + c] = T(ri);
     d = double(ri) * double(ri);
+  } else if constexpr (MODE == 3) {
+    const T o = T(a * x - bb * sr * sum);
+    const T xv = X[int64_t(r) * ldx + c];
+    const T al = T(u.alpha[int64_t(g) * k + c]);
+    T fv = u.F[int64_t(r) * u.ldf + c];
+    T rv = u.R[int64_t(r) * u.ldr + c];
+    fv += al * xv;
+    rv -= al * o;
+    u.F[int64_t(r) * u.ldf + c] = fv;
+    u.R[int64_t(r) * u.ldr + c] = rv;
+    d = double(rv) * double(rv);
   } else {
     T o = T(a * x - bb * sr * sum);
     Out[int64_t(r) * ldo + c] = o;
@@ -293,7 +376,7 @@ template <class T, class TZ>
 int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx, const TZ* Z,
                        int64_t ldz, const T* Y, int64_t ldy, T* Out, int64_t ldo,
                        const double* a_seg, const double* b_seg, double* part, int k,
-                       const ColShape& cs, Gate gate, hipStream_t st) {
+                       const ColShape& cs, Gate gate, hipStream_t st, UpdArgs<T> u) {
   hgl_handle* hm = const_cast<hgl_handle*>(h);
   if (h->n_chunks > 0 && hm->ws_chunk.bytes < sizeof(TZ) * size_t(h->n_chunks) * k) {
     // growing a buffer frees the old one: wait for queued work that may use it
@@ -312,25 +395,26 @@ int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx,
     set_error("residual mode needs FP64 accumulation");
     return HGL_EUNSUPPORTED;
   }
+  if (mode == VMode::Step && (!u.F || !u.R || !u.alpha || !part)) {
+    set_error("internal: CG step mode needs F, R, alpha and partial sums");
+    return HGL_EINVAL;
+  }
+  auto run = [&](auto kv, auto kf) {
+    launch(h, -1, kv, grid, dim3(kBlock), 0, st, va, s, X, ldx, Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate, u);
+    if (h->n_long > 0)
+      launch(h, kProfFinish, kf, grid_fin, dim3(kBlock), 0, st, va, s, X, ldx, Y, ldy, Out, ldo, part,
+             static_cast<const TZ*>(cp), k, gate, u);
+  };
   return HGL_DISPATCH_SHAPE(cs, sizeof(T) > sizeof(TZ) ? sizeof(T) : sizeof(TZ), {
     if (mode == VMode::Apply) {
-      launch(h, -1, k_spmm_vertex<T, TZ, GL, V, 0>, grid, dim3(kBlock), 0, st, va, s, X, ldx,
-                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
-      if (h->n_long > 0)
-        launch(h, kProfFinish, k_spmm_vertex_finish<T, TZ, GL, V, 0>, grid_fin, dim3(kBlock), 0, st, va,
-                           s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
+      run(k_spmm_vertex<T, TZ, GL, V, 0>, k_spmm_vertex_finish<T, TZ, GL, V, 0>);
     } else if (mode == VMode::ApplyDot) {
-      launch(h, -1, k_spmm_vertex<T, TZ, GL, V, 1>, grid, dim3(kBlock), 0, st, va, s, X, ldx,
-                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
-      if (h->n_long > 0)
-        launch(h, kProfFinish, k_spmm_vertex_finish<T, TZ, GL, V, 1>, grid_fin, dim3(kBlock), 0, st, va,
-                           s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
+      run(k_spmm_vertex<T, TZ, GL, V, 1>, k_spmm_vertex_finish<T, TZ, GL, V, 1>);
+    } else if (mode == VMode::Step) {
+      if constexpr (std::is_same<T, TZ>::value)
+        run(k_spmm_vertex<T, TZ, GL, V, 3>, k_spmm_vertex_finish<T, TZ, GL, V, 3>);
     } else if constexpr (sizeof(TZ) == 8) {
-      launch(h, -1, k_spmm_vertex<T, TZ, GL, V, 2>, grid, dim3(kBlock), 0, st, va, s, X, ldx,
-                         Z, ldz, Y, ldy, Out, ldo, part, cp, k, gate);
-      if (h->n_long > 0)
-        launch(h, kProfFinish, k_spmm_vertex_finish<T, TZ, GL, V, 2>, grid_fin, dim3(kBlock), 0, st, va,
-                           s, X, ldx, Y, ldy, Out, ldo, part, cp, k, gate);
+      run(k_spmm_vertex<T, TZ, GL, V, 2>, k_spmm_vertex_finish<T, TZ, GL, V, 2>);
     }
     HGL_HIP(hipGetLastError());
     return HGL_OK;
@@ -408,24 +492,24 @@ template ColShape tune_shape<double>(hgl_handle*, int, const ColShape&, const do
                                      const double*, const double*, hipStream_t);
 
 template int launch_spmm_edge<float, float>(const hgl_handle*, const float*, int64_t, float*,
-                                            int64_t, int, const ColShape&, Gate, hipStream_t);
+                                            int64_t, int, const ColShape&, Gate, hipStream_t, double*);
 template int launch_spmm_edge<float, double>(const hgl_handle*, const float*, int64_t, double*,
-                                             int64_t, int, const ColShape&, Gate, hipStream_t);
+                                             int64_t, int, const ColShape&, Gate, hipStream_t, double*);
 template int launch_spmm_edge<double, double>(const hgl_handle*, const double*, int64_t, double*,
-                                              int64_t, int, const ColShape&, Gate, hipStream_t);
+                                              int64_t, int, const ColShape&, Gate, hipStream_t, double*);
 template int launch_spmm_vertex<float, float>(const hgl_handle*, VMode, const float*, int64_t,
                                               const float*, int64_t, const float*, int64_t, float*,
                                               int64_t, const double*, const double*, double*, int,
-                                              const ColShape&, Gate, hipStream_t);
+                                              const ColShape&, Gate, hipStream_t, UpdArgs<float>);
 template int launch_spmm_vertex<float, double>(const hgl_handle*, VMode, const float*, int64_t,
                                                const double*, int64_t, const float*, int64_t, float*,
                                                int64_t, const double*, const double*, double*, int,
-                                               const ColShape&, Gate, hipStream_t);
+                                               const ColShape&, Gate, hipStream_t, UpdArgs<float>);
 template int launch_spmm_vertex<double, double>(const hgl_handle*, VMode, const double*, int64_t,
                                                 const double*, int64_t, const double*, int64_t,
                                                 double*, int64_t, const double*, const double*,
                                                 double*, int, const ColShape&, Gate,
-                                                hipStream_t);
+                                                hipStream_t, UpdArgs<double>);
 
 // Per-graph (a, b) = (1 + 1/lambda_g, 1/lambda_g) in a device array [2G].
 int upload_ab(hgl_handle* h, const double* lambdas_host, hipStream_t st) {
