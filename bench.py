@@ -277,9 +277,10 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
     nv, mv = prof["vertex_gather"]
     ne, me = prof["edge_gather"]
     # template instances the solves ran (the column shape may be autotuned)
-    gl, vw, _ = h.gather_shape()
+    shp = h.gather_shape()
     t = "float" if mode == "f32" else "double"
-    inst_v, inst_e = f"k_spmm_vertex<{t}, {t}, {gl}, {vw}, 3>", f"k_spmm_edge<{t}, {t}, {gl}, {vw}, true>"
+    inst_v = f"k_spmm_vertex<{t}, {t}, {shp['vertex'][0]}, {shp['vertex'][1]}, 3>"
+    inst_e = f"k_spmm_edge<{t}, {t}, {shp['edge'][0]}, {shp['edge'][1]}, true>"
     if mv >= me:
         roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_step"],
                      traffic=stored_traffic("k_spmm_vertex", name, inst_v))

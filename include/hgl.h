@@ -139,13 +139,14 @@ int hgl_get_partition(const hgl_handle* h, int32_t* n_tiles, int32_t* n_hub_rows
                       int32_t* n_long_edges);
 
 /*
- * Diagnostics: the column shape under which the two operator gathers of the
+ * Diagnostics: the column shapes under which the two operator gathers of the
  * most recent CG solve on this handle ran, written to the caller's host array
- * shape3 = {lanes per row, elements per lane, column slabs}; all zero before
- * the first solve.  With the autotuner on (hgl_cg_opts.tune) it is the tuned
- * shape.  Errors: HGL_EINVAL for a NULL argument.
+ * shape6 = {lanes per row, elements per lane, column slabs} of the edge
+ * gather, then the same of the vertex gather; all zero before the first
+ * solve.  With the autotuner on (hgl_cg_opts.tune) they are the tuned shapes.
+ * Errors: HGL_EINVAL for a NULL argument.
  */
-int hgl_get_gather_shape(const hgl_handle* h, int32_t* shape3);
+int hgl_get_gather_shape(const hgl_handle* h, int32_t* shape6);
 
 /*
  * Diagnostics of the most recent CG solve on this handle (hgl_cg_solve,

@@ -666,11 +666,11 @@ extern "C" int hgl_get_partition(const hgl_handle* h, int32_t* n_tiles, int32_t*
   return HGL_OK;
 }
 
-extern "C" int hgl_get_gather_shape(const hgl_handle* h, int32_t* shape3) {
+extern "C" int hgl_get_gather_shape(const hgl_handle* h, int32_t* shape6) {
   clear_error();
   HGL_CHECK_ARG(h != nullptr, "handle is NULL");
-  HGL_CHECK_ARG(shape3 != nullptr, "shape3 is NULL");
-  for (int i = 0; i < 3; ++i) shape3[i] = h->last_shape[i];
+  HGL_CHECK_ARG(shape6 != nullptr, "shape6 is NULL");
+  for (int i = 0; i < 6; ++i) shape6[i] = h->last_shape[i];
   return HGL_OK;
 }
 

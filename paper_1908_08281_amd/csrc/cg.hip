@@ -212,56 +212,89 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(
 
 // Partial sums are stored slot-major, part[slot][k]: the workgroup that
 // owns a slot writes one contiguous row.  A reduction workgroup (kRedThreads
-// threads) owns kRedCols columns of one graph: thread (lane l = tid %
-// kRedCols, stripe j = tid / kRedCols) adds slots j, j + stripes, ... of
+// threads, 16 waves) owns kRedCols columns of one graph: thread (lane l = tid
+// % kRedCols, stripe j = tid / kRedCols) adds slots j, j + stripes, ... of
 // column c0 + l (a stripe reads kRedCols contiguous values per slot; the
-// graph's tiles, then its long rows), kRedBurst independent loads in flight
-// per round, then the stripes are added by a fixed pairwise tree, so the sum
-// is deterministic.  The result is valid in stripe-0 threads.
+// graph's tiles, then its long rows), kRedBurst independent loads per array
+// in flight per round.  The stripes are then added by a fixed butterfly of
+// lane exchanges inside each wave and one across the 16 waves, so every sum
+// is deterministic.  Results are valid in wave 0.
 constexpr int kRedCols = 8;
 constexpr int kRedThreads = 1024;
 constexpr int kRedStripes = kRedThreads / kRedCols;
+constexpr int kRedWaves = kRedThreads / 64;
 constexpr int kRedBurst = 16;
-__device__ __forceinline__ double slot_sum(const double* __restrict__ part, int k, const int32_t* __restrict__ seg_slots,
-                                           int g, int col, double (*lds)[kRedCols + 1], bool with_long = true) {
-  const int l = threadIdx.x % kRedCols, j = threadIdx.x / kRedCols;
-  const int t0 = seg_slots[4 * g], t1 = seg_slots[4 * g + 1];
-  const int l0 = seg_slots[4 * g + 2], l1 = with_long ? seg_slots[4 * g + 3] : l0;
-  const int nt = t1 - t0, n = nt + (l1 - l0);
-  double s = 0.0;
+static_assert(kRedWaves == 16 && kRedCols == 8, "the cross-wave step pairs waves w and w + 8");
+
+// One partial-sum array and its slot ranges (tiles [t0, t1), long rows or
+// long hyperedges [l0, l1)) for one graph.
+struct SlotSrc {
+  const double* p;
+  int t0, t1, l0, l1;
+};
+
+__device__ __forceinline__ double wave_stripe_sum(double v) {
+  // lanes holding the same column differ in lane-id bits 3..5
+#pragma unroll
+  for (int m = kRedCols; m < 64; m <<= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+template <int NS>
+__device__ __forceinline__ void slot_sums(const SlotSrc (&src)[NS], int k, int col, double (&out)[NS],
+                                          double* lds /* [kRedWaves * NS * kRedCols] */) {
+  const int j = threadIdx.x / kRedCols;
+  double acc[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) acc[q] = 0.0;
   if (col < k) {
-    for (int i = j; i < n; i += kRedBurst * kRedStripes) {
-      double x[kRedBurst];
+    int nt[NS], n[NS], nmax = 0;
 #pragma unroll
-      for (int u = 0; u < kRedBurst; ++u) {
-        const int v = i + u * kRedStripes;
-        const int slot = v < nt ? t0 + v : l0 + (v - nt);
-        x[u] = v < n ? part[int64_t(slot) * k + col] : 0.0;
+    for (int q = 0; q < NS; ++q) {
+      nt[q] = src[q].t1 - src[q].t0;
+      n[q] = nt[q] + (src[q].l1 - src[q].l0);
+      nmax = max(nmax, n[q]);
+    }
+    for (int i = j; i < nmax; i += kRedBurst * kRedStripes) {
+      double x[NS][kRedBurst];
+#pragma unroll
+      for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int u = 0; u < kRedBurst; ++u) {
+          const int v = i + u * kRedStripes;
+          const int slot = v < nt[q] ? src[q].t0 + v : src[q].l0 + (v - nt[q]);
+          x[q][u] = v < n[q] ? src[q].p[int64_t(slot) * k + col] : 0.0;
+        }
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+#pragma unroll
+        for (int w = kRedBurst / 2; w >= 1; w >>= 1)
+#pragma unroll
+          for (int u = 0; u < w; ++u) x[q][u] += x[q][u + w];
+        acc[q] += x[q][0];
       }
-#pragma unroll
-      for (int w = kRedBurst / 2; w >= 1; w >>= 1)
-#pragma unroll
-        for (int u = 0; u < w; ++u) x[u] += x[u + w];
-      s += x[0];
     }
   }
-  lds[j][l] = s;
-  __syncthreads();
-  // fixed pairwise tree over the stripes
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
-  for (int half = kRedStripes / 2; half >= 1; half >>= 1) {
-    if (j < half) lds[j][l] += lds[j + half][l];
-    __syncthreads();
+  for (int q = 0; q < NS; ++q) {
+    acc[q] = wave_stripe_sum(acc[q]);
+    if (lane < kRedCols) lds[(wave * NS + q) * kRedCols + lane] = acc[q];
   }
-  const double tot = lds[0][l];
   __syncthreads();
-  return tot;
+  if (wave == 0) {
+    const int w2 = lane / kRedCols, l2 = lane % kRedCols;
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+      out[q] = wave_stripe_sum(lds[(w2 * NS + q) * kRedCols + l2] + lds[((w2 + 8) * NS + q) * kRedCols + l2]);
+  }
 }
 
 enum class RedOp { Init, Alpha, Beta, Check };
 
 struct RedArgs {
   int G, k, n_slots;
+  int32_t slots1[4], eslots1[4];  // the slot ranges when G == 1 (no loads)
   const int32_t* seg_slots;
   const double* part;   // r'r (Init, Beta, Check) or p'Mp (Alpha, not split)
   const double* part2;  // y'y (Init)
@@ -303,31 +336,88 @@ struct Words {
 template <RedOp OP>
 __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState st, Words wd) {
   const int it = ra.iter;
-  if constexpr (OP == RedOp::Alpha || OP == RedOp::Beta) {
-    if (*wd.cnt(it - 1) == 0) return;
-  }
-  __shared__ double lds[kRedStripes][kRedCols + 1];
-  // one workgroup per (graph, group of kRedCols columns)
+  // one workgroup per (graph, group of kRedCols columns); every load that
+  // does not depend on the sums is issued first
   const int ngrp = (ra.k + kRedCols - 1) / kRedCols;
   const int g = blockIdx.x / ngrp;
   const int col = (blockIdx.x % ngrp) * kRedCols + threadIdx.x % kRedCols;
-  double sum;
-  if constexpr (OP == RedOp::Alpha) {
-    if (ra.pp) {
-      const double spp = slot_sum(ra.pp, ra.k, ra.seg_slots, g, col, lds, false);
-      const double se = slot_sum(ra.epart, ra.k, ra.seg_eslots, g, col, lds);
-      sum = ra.ab[g] * spp - ra.ab[ra.G + g] * se;
-    } else {
-      sum = slot_sum(ra.part, ra.k, ra.seg_slots, g, col, lds);
-    }
-  } else {
-    sum = slot_sum(ra.part, ra.k, ra.seg_slots, g, col, lds);
+  const bool lead = threadIdx.x < kRedCols && col < ra.k;
+  const int64_t id = int64_t(g) * ra.k + col;
+  int gate = 1;
+  if constexpr (OP == RedOp::Alpha || OP == RedOp::Beta) gate = *wd.cnt(it - 1);
+  int32_t st0 = 0, it0 = 0;
+  double rz0 = 0.0, yy0 = 0.0;
+  if (lead && OP != RedOp::Init) {
+    st0 = st.state[id];
+    rz0 = st.rz[id];
+    if constexpr (OP == RedOp::Beta || OP == RedOp::Check) yy0 = st.yy[id];
+    if constexpr (OP == RedOp::Beta) it0 = st.iters[id];
   }
-  double sum2 = 0.0;
-  if constexpr (OP == RedOp::Init) sum2 = slot_sum(ra.part2, ra.k, ra.seg_slots, g, col, lds);
-  double rz = sum;  // r'z, = r'r without a preconditioner
-  if constexpr (OP != RedOp::Alpha) {
-    if (ra.has_prec) rz = slot_sum(ra.part3, ra.k, ra.seg_slots, g, col, lds);
+  const bool split = OP == RedOp::Alpha && ra.pp != nullptr;
+  double ag = 0.0, bg = 0.0;
+  if (split) {
+    ag = ra.ab[g];
+    bg = ra.ab[ra.G + g];
+  }
+  if (gate == 0) return;  // uniform: no column iterates
+  int sl[4], esl[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    sl[i] = ra.G == 1 ? ra.slots1[i] : ra.seg_slots[4 * g + i];
+    esl[i] = ra.G == 1 ? ra.eslots1[i] : (split ? ra.seg_eslots[4 * g + i] : 0);
+  }
+  const SlotSrc all{nullptr, sl[0], sl[1], sl[2], sl[3]};
+  __shared__ double lds[kRedWaves * 2 * kRedCols];
+  double sum = 0.0, sum2 = 0.0, rz = 0.0;
+  if constexpr (OP == RedOp::Alpha) {
+    if (split) {
+      // p'Mp = a p'p - b sum_e c_e |u_e|^2: p'p over the tiles only
+      const SlotSrc src[2] = {{ra.pp, sl[0], sl[1], sl[2], sl[2]}, {ra.epart, esl[0], esl[1], esl[2], esl[3]}};
+      double o[2];
+      slot_sums<2>(src, ra.k, col, o, lds);
+      sum = ag * o[0] - bg * o[1];
+    } else {
+      SlotSrc src[1] = {all};
+      src[0].p = ra.part;
+      double o[1];
+      slot_sums<1>(src, ra.k, col, o, lds);
+      sum = o[0];
+    }
+  } else if constexpr (OP == RedOp::Init) {
+    SlotSrc src[2] = {all, all};
+    src[0].p = ra.part;
+    src[1].p = ra.part2;
+    double o[2];
+    slot_sums<2>(src, ra.k, col, o, lds);
+    sum = o[0];
+    sum2 = o[1];
+  } else {
+    if (ra.has_prec) {
+      SlotSrc src[2] = {all, all};
+      src[0].p = ra.part;
+      src[1].p = ra.part3;
+      double o[2];
+      slot_sums<2>(src, ra.k, col, o, lds);
+      sum = o[0];
+      rz = o[1];
+    } else {
+      SlotSrc src[1] = {all};
+      src[0].p = ra.part;
+      double o[1];
+      slot_sums<1>(src, ra.k, col, o, lds);
+      sum = o[0];
+    }
+  }
+  if (OP == RedOp::Init && ra.has_prec) {
+    // r'z of the start: its own pass (three arrays)
+    SlotSrc src[1] = {all};
+    src[0].p = ra.part3;
+    double o[1];
+    __syncthreads();
+    slot_sums<1>(src, ra.k, col, o, lds);
+    rz = o[0];
+  } else if (!ra.has_prec) {
+    rz = sum;  // r'z = r'r without a preconditioner
   }
   if (threadIdx.x >= kRedCols) return;
   // the per-column step: the counters it raises are added up over the
@@ -336,7 +426,6 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
   int add_cnt = 0, add_chk = 0, add_err = 0;
   double rel_max = -1.0;
   if (col < ra.k) {
-    const int64_t id = int64_t(g) * ra.k + col;
     do {
       if constexpr (OP == RedOp::Init) {
         st.yy[id] = sum2;
@@ -351,25 +440,25 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
         st.state[id] = done ? kDone : kActive;
         add_cnt = done ? 0 : 1;
       } else if constexpr (OP == RedOp::Alpha) {
-        if (st.state[id] != kActive || st.rz[id] == 0.0) {
+        if (st0 != kActive || rz0 == 0.0) {
           st.alpha[id] = 0.0;
           break;
         }
-        if (!(sum > 0.0) || !isfinite(sum) || !isfinite(st.rz[id])) {
+        if (!(sum > 0.0) || !isfinite(sum) || !isfinite(rz0)) {
           st.alpha[id] = 0.0;
           st.state[id] = kBreakdown;
           add_err = 1;
           break;
         }
-        st.alpha[id] = st.rz[id] / sum;
+        st.alpha[id] = rz0 / sum;
       } else if constexpr (OP == RedOp::Beta) {
-        if (st.state[id] != kActive) {
+        if (st0 != kActive) {
           st.beta[id] = 0.0;
           break;
         }
-        st.iters[id] += 1;
+        st.iters[id] = it0 + 1;
         const bool ran = ra.periodic != 0;  // sum is the recomputed true residual
-        const double rel = sqrt(sum / st.yy[id]);
+        const double rel = sqrt(sum / yy0);
         if (ran) st.relres[id] = rel;
         if (ran && rel <= ra.tol) {  // a recomputed residual finishes the column
           st.state[id] = kDone;
@@ -384,7 +473,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
           add_err = 1;
           break;
         }
-        st.beta[id] = rz / st.rz[id];
+        st.beta[id] = rz / rz0;
         st.rr[id] = sum;
         st.rz[id] = rz;
         if (rel <= ra.claim * ra.tol) {  // stop for a check
@@ -394,9 +483,8 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
         add_cnt = 1;
         rel_max = rel;
       } else {  // Check: sum is r'r of Y - M F recomputed in FP64
-        const int32_t sid = st.state[id];
-        if (sid != kActive && sid != kClaimed) break;
-        const double rel = st.yy[id] > 0.0 ? sqrt(sum / st.yy[id]) : sqrt(sum);
+        if (st0 != kActive && st0 != kClaimed) break;
+        const double rel = yy0 > 0.0 ? sqrt(sum / yy0) : sqrt(sum);
         st.relres[id] = rel;
         // residual replacement: the recursion continues from the recomputed
         // residual
@@ -527,17 +615,29 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   // row-streaming kernels: the widest-vector shape; operator gathers: the
   // autotuned one (the partial-sum layout does not depend on either)
   const ColShape cs = pick_shape(k, sizeof(T), {Y, F, b.R}, {ldy, ldf, ld});
-  const ColShape csg = o->tune ? tune_shape<T>(h, k, cs, Y, ldy, b.Z, b.Q, a_seg, b_seg, s) : cs;
-  h->last_shape[0] = csg.GL;
-  h->last_shape[1] = csg.V;
-  h->last_shape[2] = csg.slabs;
+  GatherShapes gs{cs, cs};
+  if (o->tune) {
+    // tuned on the solver's own launches, with alpha = 0 so that F (which
+    // may hold x0) and R (rewritten by the start) keep their values
+    HGL_HIP(hipMemsetAsync(b.st.alpha, 0, sizeof(double) * gk, s));
+    gs = tune_shapes<T>(h, k, cs, Y, ldy, b.Z, UpdArgs<T>{F, ldf, b.R, ld, b.st.alpha}, b.epart, b.part, a_seg,
+                        b_seg, s);
+  }
+  const ColShape cse = gs.edge, csv = gs.vertex;
+  const int32_t shapes[6] = {cse.GL, cse.V, cse.slabs, csv.GL, csv.V, csv.slabs};
+  std::copy(shapes, shapes + 6, h->last_shape);
   const ColShape cs64 = pick_shape(k, 8, {Y, F, b.R}, {ldy, ldf, ld});
   const int red_blocks = G * ((k + kRedCols - 1) / kRedCols);
   // claim < 1 in FP32 leaves room for the drift of the FP32 recursion from
   // the true residual
   const double claim = fp32 ? 0.5 : 1.0;
-  RedArgs ra{G,      k,       nsl,           h->seg_slots, b.part, b.part2, b.part3, b.pp,
-             b.epart, h->seg_eslots, a_seg, o->tol, claim,  0,      0,       has_prec ? 1 : 0};
+  RedArgs ra{G,           k,     nsl,    {0, 0, 0, 0}, {0, 0, 0, 0}, h->seg_slots, b.part, b.part2,
+             b.part3,     b.pp,  b.epart, h->seg_eslots, a_seg, o->tol, claim, 0, 0, has_prec ? 1 : 0};
+  if (G == 1)
+    for (int i = 0; i < 4; ++i) {
+      ra.slots1[i] = h->seg_slots_host[i];
+      ra.eslots1[i] = h->seg_eslots_host[i];
+    }
 
   // preconditioner: Zp = P^-1 R with partial r'z into part3 (or into part)
   auto precond = [&](const T* Rin, int64_t ldr, T* Zout, int64_t ldz, double* part, Gate gate) -> int {
@@ -591,7 +691,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       // edge gather + hyperedge half of p'Mp -> alpha -> vertex gather with
       // the update (partial r'r of the new R)
       prof_begin(h, kProfEdge, s);
-      HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, csg, g_prev, s, b.epart));
+      HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, cse, g_prev, s, b.epart));
       prof_end(h, s);
       prof_begin(h, kProfReduce, s);
       launch(h, -1, k_cg_reduce<RedOp::Alpha>, dim3(red_blocks), dim3(kRedThreads), 0, s, r, b.st, wd);
@@ -599,15 +699,15 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       prof_end(h, s);
       prof_begin(h, kProfVertex, s);
       HGL_TRY(launch_spmm_vertex<T, T>(h, VMode::Step, b.P, ld, b.Z, ld, nullptr, 0, nullptr, 0, a_seg, b_seg,
-                                       b.part, k, csg, g_prev, s, UpdArgs<T>{F, ldf, b.R, ld, b.st.alpha}));
+                                       b.part, k, csv, g_prev, s, UpdArgs<T>{F, ldf, b.R, ld, b.st.alpha}));
       prof_end(h, s);
     } else {
       prof_begin(h, kProfEdge, s);
-      HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, csg, g_prev, s));
+      HGL_TRY(launch_spmm_edge<T, T>(h, b.P, ld, b.Z, ld, k, cse, g_prev, s));
       prof_end(h, s);
       prof_begin(h, kProfVertex, s);
       HGL_TRY(launch_spmm_vertex<T, T>(h, VMode::ApplyDot, b.P, ld, b.Z, ld, nullptr, 0, b.Q, ld, a_seg,
-                                       b_seg, b.part, k, csg, g_prev, s));
+                                       b_seg, b.part, k, csv, g_prev, s));
       prof_end(h, s);
       prof_begin(h, kProfReduce, s);
       launch(h, -1, k_cg_reduce<RedOp::Alpha>, dim3(red_blocks), dim3(kRedThreads), 0, s, r, b.st, wd);
@@ -706,8 +806,9 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
         sizeof(T), uint64_t(k), uint64_t(G), uint64_t(n), uint64_t(ldy), uint64_t(ldf), u(Y), u(F),
         u(h->ws_vec.p), u(h->ws_z.p), u(h->ws_z64.p), u(h->ws_part.p), u(h->ws_part2.p), u(h->ws_extra[0].p),
         u(h->ws_state.p), u(h->ws_chunk.p), u(h->ws_ab.p), u(h->ws_extra[5].p), u(prec ? prec->ctx : nullptr), uint64_t(o->rr_period),
-        tol_bits, uint64_t(cs.GL), uint64_t(cs.V), uint64_t(cs.slabs), uint64_t(csg.GL), uint64_t(csg.V),
-        uint64_t(csg.slabs), u(wd.base), uint64_t(o->max_iter)};
+        tol_bits, uint64_t(cs.GL), uint64_t(cs.V), uint64_t(cs.slabs), uint64_t(cse.GL), uint64_t(cse.V),
+        uint64_t(cse.slabs), uint64_t(csv.GL), uint64_t(csv.V), uint64_t(csv.slabs), u(wd.base),
+        uint64_t(o->max_iter)};
     if (!h->cg_graph || key != h->cg_graph_key) {
       if (h->cg_graph) {
         HGL_HIP(hipGraphExecDestroy(h->cg_graph));

@@ -155,10 +155,12 @@ struct hgl_handle {
   int64_t prof_launches[hgl::kProfKinds] = {0};
   double prof_ms[hgl::kProfKinds] = {0};
   int prof_kind = -1;                                // open kind (prof_begin), or -1
-  // autotuned column shapes: {k, element size, base V} -> {GL, V, slabs}
-  std::vector<std::array<int, 6>> tuned;
-  // column shape {GL, V, slabs} of the operator gathers of the latest CG solve
-  int32_t last_shape[3] = {0, 0, 0};
+  // autotuned column shapes: {k, element size, base V} -> {GL, V, slabs} of
+  // the edge gather, then of the vertex gather
+  std::vector<std::array<int, 9>> tuned;
+  // column shapes {GL, V, slabs} of the edge, then the vertex gather of the
+  // latest CG solve
+  int32_t last_shape[6] = {0, 0, 0, 0, 0, 0};
   // latest CG solve: {iterations enqueued, chunks, check steps, check steps
   // after which columns went on iterating}
   int32_t last_cg[4] = {0, 0, 0, 0};
@@ -189,15 +191,33 @@ struct ColShape {
 ColShape pick_shape(int k, int elem_bytes, std::initializer_list<const void*> ptrs,
                     std::initializer_list<int64_t> lds);
 
-// Autotuner: the column shape under which the two operator gathers run
+// Column shapes of the two operator gathers.
+struct GatherShapes {
+  ColShape edge, vertex;
+};
+
+// Operands of the fused CG step (VMode::Step); unused by the other modes.
+template <class T>
+struct UpdArgs {
+  T* F = nullptr;
+  int64_t ldf = 0;
+  T* R = nullptr;
+  int64_t ldr = 0;
+  const double* alpha = nullptr;  // [G*k]
+};
+
+// Autotuner: the column shapes under which the edge gather (with its
+// hyperedge partials) and the vertex gather (as the fused CG step) each run
 // fastest for k columns of the given element size, among the shapes that
 // `base` (pick_shape's, with the widest valid vector) admits: narrower
 // vectors, fewer lanes per row with more column slabs.  Timed once on X
-// (N x k, leading dimension ldx) with scratch outputs Z (E x k) and Q (N x k),
+// (N x k, leading dimension ldx) with scratch Z (E x k), u.F and u.R
+// (u.alpha must be zero, so that F and R keep their values), epart and part,
 // then cached in the handle under (k, element size, base vector width).
 template <class T>
-ColShape tune_shape(hgl_handle* h, int k, const ColShape& base, const T* X, int64_t ldx, T* Z, T* Q,
-                    const double* a_seg, const double* b_seg, hipStream_t s);
+GatherShapes tune_shapes(hgl_handle* h, int k, const ColShape& base, const T* X, int64_t ldx, T* Z,
+                         UpdArgs<T> u, double* epart, double* part, const double* a_seg, const double* b_seg,
+                         hipStream_t s);
 
 // Early-exit gate of a kernel launched inside the CG loop: the kernel does
 // nothing when *active == 0 (no column iterates) or when it is a
@@ -265,15 +285,6 @@ int cg_run(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const voi
 // Operator application pieces (spmm.hip).
 enum class VMode { Apply = 0, ApplyDot = 1, Resid = 2, Step = 3 };
 
-// Operands of the fused CG step (VMode::Step); unused by the other modes.
-template <class T>
-struct UpdArgs {
-  T* F = nullptr;
-  int64_t ldf = 0;
-  T* R = nullptr;
-  int64_t ldr = 0;
-  const double* alpha = nullptr;  // [G*k]
-};
 
 // Z = C H' S P: edge-major gather.  TIn = type of P, TAcc = type of Z.
 // part (nullable): FP64 partial sums of sum_e c_e |(H' S P)_e|^2 per column,

@@ -422,19 +422,20 @@ int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx,
 }
 
 template <class T>
-ColShape tune_shape(hgl_handle* h, int k, const ColShape& base, const T* X, int64_t ldx, T* Z, T* Q,
-                    const double* a_seg, const double* b_seg, hipStream_t s) {
+GatherShapes tune_shapes(hgl_handle* h, int k, const ColShape& base, const T* X, int64_t ldx, T* Z,
+                         UpdArgs<T> u, double* epart, double* part, const double* a_seg, const double* b_seg,
+                         hipStream_t s) {
   for (const auto& e : h->tuned)
     if (e[0] == k && e[1] == int(sizeof(T)) && e[2] == base.V) {
-      ColShape cs;
-      cs.GL = e[3];
-      cs.V = e[4];
-      cs.slabs = e[5];
-      return cs;
+      GatherShapes g;
+      g.edge = ColShape{e[3], e[4], e[5]};
+      g.vertex = ColShape{e[6], e[7], e[8]};
+      return g;
     }
   // candidates: vector width V' <= base.V; lanes from the smallest power of
   // two covering the row down to 8 (more column slabs); the default (base)
-  // comes first and is kept unless another candidate is 5% faster
+  // comes first and is kept for a kernel unless another candidate runs that
+  // kernel 5% faster
   std::vector<ColShape> cand{base};
   for (int V = base.V; V >= 1; V >>= 1) {
     const int need = (k + V - 1) / V;
@@ -450,46 +451,64 @@ ColShape tune_shape(hgl_handle* h, int k, const ColShape& base, const T* X, int6
       cand.push_back(cs);
     }
   }
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  ColShape best = base;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    if (e0) hipEventDestroy(e0);
-    return base;
-  }
-  float best_ms = 1e30f, base_ms = -1.f;
+  GatherShapes best{base, base};
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& e2 : ev)
+        if (e2) hipEventDestroy(e2);
+      return best;
+    }
+  float best_e = 1e30f, best_v = 1e30f, base_e = -1.f, base_v = -1.f;
   for (const ColShape& cs : cand) {
-    auto once = [&]() -> bool {
-      return launch_spmm_edge<T, T>(h, X, ldx, Z, k, k, cs, Gate{}, s) == HGL_OK &&
-             launch_spmm_vertex<T, T>(h, VMode::Apply, X, ldx, Z, k, nullptr, 0, Q, k, a_seg, b_seg, nullptr, k,
-                                      cs, Gate{}, s) == HGL_OK;
+    // the solver's own launches: edge gather with the hyperedge partials,
+    // vertex gather as the fused step (u.alpha is zero: F and R keep their
+    // values)
+    auto edge = [&]() { return launch_spmm_edge<T, T>(h, X, ldx, Z, k, k, cs, Gate{}, s, epart) == HGL_OK; };
+    auto vertex = [&]() {
+      return launch_spmm_vertex<T, T>(h, VMode::Step, X, ldx, Z, k, nullptr, 0, nullptr, 0, a_seg, b_seg, part, k,
+                                      cs, Gate{}, s, u) == HGL_OK;
     };
-    if (!once()) continue;  // warm-up (and shape check)
-    hipEventRecord(e0, s);
+    if (!edge() || !vertex()) continue;  // warm-up (and shape check)
+    hipEventRecord(ev[0], s);
     bool ok = true;
-    for (int rep = 0; rep < 3 && ok; ++rep) ok = once();
-    hipEventRecord(e1, s);
-    float ms = 0.f;
-    if (!ok || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
-    if (cs.GL == base.GL && cs.V == base.V && cs.slabs == base.slabs) base_ms = ms;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = cs;
+    for (int rep = 0; rep < 3 && ok; ++rep) ok = edge();
+    hipEventRecord(ev[1], s);
+    for (int rep = 0; rep < 3 && ok; ++rep) ok = vertex();
+    hipEventRecord(ev[2], s);
+    float me = 0.f, mv = 0.f;
+    if (!ok || hipEventSynchronize(ev[2]) != hipSuccess || hipEventElapsedTime(&me, ev[0], ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&mv, ev[1], ev[2]) != hipSuccess)
+      continue;
+    if (cs.GL == base.GL && cs.V == base.V && cs.slabs == base.slabs) {
+      base_e = me;
+      base_v = mv;
+    }
+    if (me < best_e) {
+      best_e = me;
+      best.edge = cs;
+    }
+    if (mv < best_v) {
+      best_v = mv;
+      best.vertex = cs;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  for (auto& e : ev) hipEventDestroy(e);
   clear_error();
   // keep the default unless another shape is clearly faster (timing noise
   // must not flip the choice from one process to the next)
-  if (base_ms > 0.f && best_ms > 0.95f * base_ms) best = base;
-  h->tuned.push_back({k, int(sizeof(T)), base.V, best.GL, best.V, best.slabs});
+  if (base_e > 0.f && best_e > 0.95f * base_e) best.edge = base;
+  if (base_v > 0.f && best_v > 0.95f * base_v) best.vertex = base;
+  h->tuned.push_back({k, int(sizeof(T)), base.V, best.edge.GL, best.edge.V, best.edge.slabs, best.vertex.GL,
+                      best.vertex.V, best.vertex.slabs});
   return best;
 }
 
-template ColShape tune_shape<float>(hgl_handle*, int, const ColShape&, const float*, int64_t, float*, float*,
-                                    const double*, const double*, hipStream_t);
-template ColShape tune_shape<double>(hgl_handle*, int, const ColShape&, const double*, int64_t, double*, double*,
-                                     const double*, const double*, hipStream_t);
+template GatherShapes tune_shapes<float>(hgl_handle*, int, const ColShape&, const float*, int64_t, float*,
+                                         UpdArgs<float>, double*, double*, const double*, const double*, hipStream_t);
+template GatherShapes tune_shapes<double>(hgl_handle*, int, const ColShape&, const double*, int64_t, double*,
+                                          UpdArgs<double>, double*, double*, const double*, const double*,
+                                          hipStream_t);
 
 template int launch_spmm_edge<float, float>(const hgl_handle*, const float*, int64_t, float*,
                                             int64_t, int, const ColShape&, Gate, hipStream_t, double*);

@@ -65,12 +65,14 @@ class Handle:
         check(lib().hgl_get_partition(self.ptr, *(C.byref(x) for x in v)), "hgl_get_partition")
         return dict(zip(("tiles", "hub_rows", "hub_chunks", "long_edges"), (x.value for x in v)))
 
-    def gather_shape(self) -> tuple:
-        """(lanes per row, elements per lane, column slabs) of the operator
-        gathers of the latest CG solve on this handle; zeros before one."""
-        v = (C.c_int32 * 3)()
+    def gather_shape(self) -> dict:
+        """{"edge": (lanes per row, elements per lane, column slabs), "vertex":
+        (...)} of the operator gathers of the latest CG solve on this handle;
+        zeros before one."""
+        v = (C.c_int32 * 6)()
         check(lib().hgl_get_gather_shape(self.ptr, v), "hgl_get_gather_shape")
-        return tuple(int(x) for x in v)
+        x = [int(a) for a in v]
+        return {"edge": tuple(x[:3]), "vertex": tuple(x[3:])}
 
     def cg_stats(self) -> dict:
         """Iterations enqueued, chunks, check steps and check steps after

@@ -207,14 +207,14 @@ def test_autotuned_shape_matches_oracle_and_is_cached(k):
     tol = 1e-6 / (1 + 1 / p.lam)
     Y = torch.from_numpy(p.Y).to(dev, torch.float32)
     say("autotune", k)
-    assert h.gather_shape() == (0, 0, 0)
+    assert h.gather_shape() == {"edge": (0, 0, 0), "vertex": (0, 0, 0)}
     F1, _, _, st1 = hgl().cg_solve(h, p.lam, Y, tol=tol, tune=True)
     shape1 = h.gather_shape()
     F2, _, _, st2 = hgl().cg_solve(h, p.lam, Y, tol=tol, tune=True)
     assert st1 == 0 and st2 == 0
-    gl, v, slabs = shape1
-    assert gl in (4, 8, 16, 32, 64) and v in (1, 2, 4) and slabs >= 1
-    assert gl * v * slabs >= k and gl * v * (slabs - 1) < k
+    for gl, v, slabs in shape1.values():
+        assert gl in (4, 8, 16, 32, 64) and v in (1, 2, 4) and slabs >= 1
+        assert gl * v * slabs >= k and gl * v * (slabs - 1) < k
     assert h.gather_shape() == shape1
     assert torch.equal(F1, F2)
     assert colrelerr(F1.cpu().numpy(), _dense_solution(p)).max() <= 1e-6
