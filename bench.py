@@ -209,25 +209,32 @@ def _timed(fn, steps, warmup):
 
 # ------------------------------------------------------------------ workloads
 
-def cpu_cg_baseline(p, tol, budget_s=20.0):
-    """Oracle FP64 matrix-free CG (one thread) on the first columns of Y."""
+def cpu_cg_baseline(p, tol, budget_s=15.0):
+    """Oracle FP64 matrix-free CG (one thread) on a bounded sample of the
+    workload: the first columns of Y, or whole solves of all of them repeated
+    until about budget_s of CPU time."""
     from threadpoolctl import threadpool_limits
 
     from oracle import laplacian as lap
     from oracle import solve
     op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
     cols = 4
+    k = p.Y.shape[1]
     with threadpool_limits(1):
         t0 = time.perf_counter()
         solve.cg_ranking(op, p.w, p.lam, p.Y[:, :cols], tol=tol)
         probe = time.perf_counter() - t0
-        ncols = int(max(cols, min(p.Y.shape[1], cols * budget_s / max(probe, 1e-3))))
+        ncols = int(max(cols, min(k, cols * budget_s / max(probe, 1e-3))))
+        reps, dt = 0, 0.0
         t0 = time.perf_counter()
-        solve.cg_ranking(op, p.w, p.lam, p.Y[:, :ncols], tol=tol)
-        dt = time.perf_counter() - t0
-    return {"value": round(ncols / dt, 2), "unit": "RHS/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {ncols} of {p.Y.shape[1]} columns of the same workload, FP64 matrix-free CG "
-                      f"(eqs. 16-20) to the same relres, one thread, {dt:.1f} s"}
+        while reps == 0 or (ncols == k and dt < budget_s * 0.6 and reps < 8):
+            solve.cg_ranking(op, p.w, p.lam, p.Y[:, :ncols], tol=tol)
+            reps += 1
+            dt = time.perf_counter() - t0
+    what = f"first {ncols} of {k} columns" if ncols < k else f"all {k} columns, {reps} solves"
+    return {"value": round(reps * ncols / dt, 2), "unit": "RHS/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what} of the same workload, FP64 matrix-free CG (eqs. 16-20) to the same relres, "
+                      f"one thread, {dt:.1f} s"}
 
 
 def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
