@@ -353,8 +353,9 @@ constexpr int kDense = 1024;
 
 // A (l x l in LDS, row-major) <- G_b: the block's tile partials summed in tile
 // order (deterministic), upper triangle mirrored.
+template <class TA>
 __device__ __forceinline__ void stage_gram(const BlockMeta& bm, const int32_t* __restrict__ item0,
-                                           const double* __restrict__ part, int b, double* A) {
+                                           const double* __restrict__ part, int b, TA* A) {
   const int l = bm.l, npairs = l * (l + 1) / 2;
   const int i0 = item0[b], i1 = item0[b + 1];
   for (int p = threadIdx.x; p < npairs; p += kDense) {
@@ -363,8 +364,8 @@ __device__ __forceinline__ void stage_gram(const BlockMeta& bm, const int32_t* _
     for (int it = i0; it < i1; ++it) sacc += part[int64_t(it) * npairs + p];
     int i, j;
     pair_of(p, l, i, j);
-    A[i * l + j] = sacc;
-    A[j * l + i] = sacc;
+    A[i * l + j] = TA(sacc);
+    A[j * l + i] = TA(sacc);
   }
 }
 
@@ -552,7 +553,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_rinv(BlockMeta bm, const TY* _
 // (singular values of B, decreasing) and the matching eigenvectors (columns
 // of Ut, l x k).
 // kJT = 2 x 2 blocks per thread and round: 3 covers l <= 80, 4 covers l <= 96.
-template <int kJT>
+// TJ = arithmetic of the sweeps: FP64, or FP32 where the matrix comes from a
+// BF16 sketch (its entries carry errors far above FP32 rounding); the sweeps
+// stop when the off-diagonal Frobenius norm is below 1e-13 (FP64) or 1e-5
+// (FP32) of the diagonal's.
+template <class TJ>
+struct Rot {
+  TJ c, s;
+};
+template <int kJT, class TJ>
 __global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* __restrict__ item0,
                                                    const double* __restrict__ part, double* __restrict__ sig,
                                                    double* __restrict__ Ut, int max_sweeps) {
@@ -561,15 +570,17 @@ __global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* 
   const int l = bm.l, LP = bm.LP, kk = bm.kk;
   const int ne = l + (l & 1);  // even count (a dummy index l pairs with the odd one out)
   const int half = ne / 2;
-  double* A = sm;                                            // l x l
-  double* V = sm + l * l;                                    // l x l
-  double2* rot = reinterpret_cast<double2*>(sm + 2 * l * l);  // [half] (c, s)
-  int2* pq = reinterpret_cast<int2*>(rot + half);            // [half] (p, q), p < q
-  int* rank = reinterpret_cast<int*>(pq + half);             // [l]
+  constexpr double kStop = sizeof(TJ) == 8 ? 1e-26 : 1e-10;   // squared relative off-diagonal norm
+  constexpr TJ kTiny = sizeof(TJ) == 8 ? TJ(1e-300) : TJ(1e-30);
+  TJ* A = reinterpret_cast<TJ*>(sm);                       // l x l
+  TJ* V = A + l * l;                                       // l x l
+  Rot<TJ>* rot = reinterpret_cast<Rot<TJ>*>(V + l * l);   // [half] (c, s)
+  int2* pq = reinterpret_cast<int2*>(rot + half);          // [half] (p, q), p < q
+  int* rank = reinterpret_cast<int*>(pq + half);           // [l]
   constexpr int NW = kDense / kWave;
   __shared__ double s_off[NW], s_dg[NW];
   stage_gram(bm, item0, part, b, A);
-  for (int q = tid; q < l * l; q += kDense) V[q] = (q / l == q % l) ? 1.0 : 0.0;
+  for (int q = tid; q < l * l; q += kDense) V[q] = (q / l == q % l) ? TJ(1) : TJ(0);
   __syncthreads();
   const int nA = half * (half + 1) / 2, nT = nA + half * half;
   // this thread's blocks t = tid + u * kDense: A blocks (a <= b) first, then
@@ -593,7 +604,7 @@ __global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* 
     // convergence: off-diagonal mass against the diagonal (fixed-order sums)
     double off = 0.0, dg = 0.0;
     for (int q = tid; q < l * l; q += kDense) {
-      const double v = A[q] * A[q];
+      const double v = double(A[q]) * double(A[q]);
       if (q / l != q % l) off += v; else dg += v;
     }
     for (int o2 = 32; o2 >= 1; o2 >>= 1) {
@@ -611,9 +622,9 @@ __global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* 
       dg_t += s_dg[w];
     }
     __syncthreads();
-    // off-diagonal Frobenius norm below 1e-13 of the diagonal's: eigenvalue
-    // errors are then of order off^2/gap, far below the FP64 CholQR noise
-    if (off_t <= 1e-26 * dg_t) break;
+    // eigenvalue errors are then of order off^2/gap: far below the FP64
+    // CholQR noise, or the BF16 sketch's
+    if (off_t <= kStop * dg_t) break;
     for (int round = 0; round < ne - 1; ++round) {
       if (tid < half) {
         // circle method: slot 0 fixed, the others rotate
@@ -629,51 +640,51 @@ __global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* 
           p = q;
           q = tmp;
         }
-        double c = 1.0, s = 0.0;
+        TJ c = TJ(1), s = TJ(0);
         if (q < l) {
-          const double apq = A[p * l + q];
-          if (fabs(apq) > 1e-300) {
-            const double tau = (A[q * l + q] - A[p * l + p]) / (2.0 * apq);
-            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + tt * tt);
+          const TJ apq = A[p * l + q];
+          if (fabs(apq) > kTiny) {
+            const TJ tau = (A[q * l + q] - A[p * l + p]) / (TJ(2) * apq);
+            const TJ tt = (tau >= TJ(0) ? TJ(1) : TJ(-1)) / (fabs(tau) + sqrt(TJ(1) + tau * tau));
+            c = TJ(1) / sqrt(TJ(1) + tt * tt);
             s = tt * c;
           }
         }
-        rot[tid] = make_double2(c, s);
+        rot[tid] = Rot<TJ>{c, s};
         pq[tid] = make_int2(p, q);
       }
       __syncthreads();
       // phase 2: this thread's blocks, all loads before any store (the
       // blocks are disjoint; the compiler cannot see that)
       int2 PA[kJT], PB[kJT];
-      double2 RA[kJT], RB[kJT];
-      double x[kJT][4];
+      Rot<TJ> RA[kJT], RB[kJT];
+      TJ x[kJT][4];
 #pragma unroll
       for (int u = 0; u < kJT; ++u) {
         PA[u] = tk_a[u] >= 0 ? pq[tk_a[u]] : make_int2(0, l);
         PB[u] = tk_a[u] >= 0 ? pq[tk_b[u]] : make_int2(0, l);
-        RA[u] = (tk_a[u] >= 0 && tk_isA[u]) ? rot[tk_a[u]] : make_double2(1.0, 0.0);
-        RB[u] = tk_a[u] >= 0 ? rot[tk_b[u]] : make_double2(1.0, 0.0);
+        RA[u] = (tk_a[u] >= 0 && tk_isA[u]) ? rot[tk_a[u]] : Rot<TJ>{TJ(1), TJ(0)};
+        RB[u] = tk_a[u] >= 0 ? rot[tk_b[u]] : Rot<TJ>{TJ(1), TJ(0)};
       }
 #pragma unroll
       for (int u = 0; u < kJT; ++u) {
-        const double* M = tk_isA[u] ? A : V;
+        const TJ* M = tk_isA[u] ? A : V;
         const bool q0 = PA[u].y < l, q1 = PB[u].y < l, live = tk_a[u] >= 0;
-        x[u][0] = live ? M[PA[u].x * l + PB[u].x] : 0.0;
-        x[u][1] = (live && q1) ? M[PA[u].x * l + PB[u].y] : 0.0;
-        x[u][2] = (live && q0) ? M[PA[u].y * l + PB[u].x] : 0.0;
-        x[u][3] = (live && q0 && q1) ? M[PA[u].y * l + PB[u].y] : 0.0;
+        x[u][0] = live ? M[PA[u].x * l + PB[u].x] : TJ(0);
+        x[u][1] = (live && q1) ? M[PA[u].x * l + PB[u].y] : TJ(0);
+        x[u][2] = (live && q0) ? M[PA[u].y * l + PB[u].x] : TJ(0);
+        x[u][3] = (live && q0 && q1) ? M[PA[u].y * l + PB[u].y] : TJ(0);
       }
 #pragma unroll
       for (int u = 0; u < kJT; ++u) {
         if (tk_a[u] < 0) continue;
         // rows by J_a' (p' = c p - s q, q' = s p + c q; identity for V), then
         // columns by J_b
-        const double ca = RA[u].x, sa = RA[u].y, cb = RB[u].x, sb = RB[u].y;
-        const double r00 = ca * x[u][0] - sa * x[u][2], r01 = ca * x[u][1] - sa * x[u][3];
-        const double r10 = sa * x[u][0] + ca * x[u][2], r11 = sa * x[u][1] + ca * x[u][3];
-        const double y00 = cb * r00 - sb * r01, y01 = sb * r00 + cb * r01;
-        const double y10 = cb * r10 - sb * r11, y11 = sb * r10 + cb * r11;
+        const TJ ca = RA[u].c, sa = RA[u].s, cb = RB[u].c, sb = RB[u].s;
+        const TJ r00 = ca * x[u][0] - sa * x[u][2], r01 = ca * x[u][1] - sa * x[u][3];
+        const TJ r10 = sa * x[u][0] + ca * x[u][2], r11 = sa * x[u][1] + ca * x[u][3];
+        const TJ y00 = cb * r00 - sb * r01, y01 = sb * r00 + cb * r01;
+        const TJ y10 = cb * r10 - sb * r11, y11 = sb * r10 + cb * r11;
         const int pa = PA[u].x, qa = PA[u].y, pb = PB[u].x, qb = PB[u].y;
         const bool q0 = qa < l, q1 = qb < l;
         if (!tk_isA[u]) {
@@ -723,7 +734,7 @@ __global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* 
   __syncthreads();
   for (int q = tid; q < l * l; q += kDense) {
     const int r = q / l, i = q - r * l;
-    if (rank[i] < kk) Ut[int64_t(b) * LP * kk + int64_t(r) * kk + rank[i]] = V[q];
+    if (rank[i] < kk) Ut[int64_t(b) * LP * kk + int64_t(r) * kk + rank[i]] = double(V[q]);
   }
 }
 
@@ -1052,12 +1063,12 @@ static int launch_gram(hgl_handle* h, Rsvd& R, const DevBuf& Yb, hipStream_t s) 
 
 // S, ST <- orth(Y) by CholQR2 (Y is overwritten by the first pass).
 template <class TY, class TST>
-static int cholqr2(hgl_handle* h, Rsvd& R, hipStream_t s) {
+static int cholqr(hgl_handle* h, Rsvd& R, hipStream_t s, int passes) {
   const int n_items = int(R.item_b.size());
   const size_t lds_chol = sizeof(double) * 2 * R.l * R.l;
   HGL_TRY(allow_lds(k_chol_inv, lds_chol));
   prof_begin(h, kProfQr, s);
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     DevBuf& in = pass == 0 ? R.Y : R.S;
     DevBuf& out = pass == 0 ? R.S : R.Y;
     HGL_TRY(launch_gram<TY>(h, R, in, s));
@@ -1073,7 +1084,7 @@ static int cholqr2(hgl_handle* h, Rsvd& R, hipStream_t s) {
   }
   prof_end(h, s);
   // after two passes the basis is in R.Y; keep it in R.S
-  std::swap(R.Y, R.S);
+  if (passes == 2) std::swap(R.Y, R.S);
   return HGL_OK;
 }
 
@@ -1119,20 +1130,29 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
     prof_end(h, s);
     return st;
   };
+  // Orthonormalisation by CholQR2 (two passes) where the basis must be
+  // orthonormal to working precision: the one the Rayleigh-Ritz step uses,
+  // and every one of an FP64 sketch.  Between the products of a BF16 sketch
+  // one pass suffices: it only has to keep the basis well conditioned, and
+  // the next product and the final CholQR2 act on the subspace it spans.
+  auto orth = [&](bool last) { return cholqr<TY, TST>(h, R, s, (last || R.f64) ? 2 : 1); };
   HGL_TRY(gemm());
-  HGL_TRY((cholqr2<TY, TST>(h, R, s)));
+  HGL_TRY(orth(o->q == 0));
   for (int i = 0; i < 2 * o->q; ++i) {
     HGL_TRY(gemm());
-    HGL_TRY((cholqr2<TY, TST>(h, R, s)));
+    HGL_TRY(orth(i == 2 * o->q - 1));
   }
   // 4. W = A S; B B' = W'W; Jacobi; U = S U~
   HGL_TRY(gemm());  // W in R.Y, basis S in R.S
   prof_begin(h, kProfEig, s);
   HGL_TRY(launch_gram<TY>(h, R, R.Y, s));
   const int half = (R.l + (R.l & 1)) / 2;
-  const size_t lds_j = sizeof(double) * (2 * R.l * R.l + 2 * half) + sizeof(int) * (2 * half + R.l);
+  // FP32 sweeps for a BF16 sketch, FP64 otherwise
+  const size_t tj = R.f64 ? sizeof(double) : sizeof(float);
+  const size_t lds_j = tj * (2 * R.l * R.l + 2 * half) + sizeof(int) * (2 * half + R.l);
   const bool wide = half * (half + 1) / 2 + half * half > 3 * kDense;
-  auto jac = wide ? &k_jacobi<4> : &k_jacobi<3>;
+  auto jac = R.f64 ? (wide ? &k_jacobi<4, double> : &k_jacobi<3, double>)
+                   : (wide ? &k_jacobi<4, float> : &k_jacobi<3, float>);
   HGL_TRY(allow_lds(jac, lds_j));
   launch(h, -1, jac, dim3(R.nb), dim3(kDense), lds_j, s, R.bm, R.item0_d, R.Gpart.as<double>(), R.sig.as<double>(),
                      R.Ut.as<double>(), 30);
