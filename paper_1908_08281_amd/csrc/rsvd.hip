@@ -194,23 +194,43 @@ __global__ __launch_bounds__(kBlock) void k_gemm_bf16(BlockMeta bm, const uint16
   floatx4 acc[NT];
 #pragma unroll
   for (int n = 0; n < NT; ++n) acc[n] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < nbp; k0 += KC) {
+  // software pipeline over 128-wide K chunks: the next chunk's A fragments
+  // and S' segments are loaded into registers while this chunk's MFMAs run
+  // (compile-time counts: 2 LP KC/8 segments over kBlock threads, segments
+  // past the chunk's width skipped)
+  constexpr int SEGS = KC / 8, NQ = 2 * LP * SEGS / kBlock;
+  static_assert(2 * LP * SEGS % kBlock == 0, "copy loop");
+  bf16x8 a[KC / 32], v[NQ];
+  auto fetch = [&](int k0) {
     const int kc = min(KC, nbp - k0);   // 64 or 128 (nbp is a multiple of 64)
-    const int nsteps = kc / 32;
-    bf16x8 a[KC / 32];
 #pragma unroll
     for (int ks = 0; ks < KC / 32; ++ks)
-      if (ks < nsteps) a[ks] = *reinterpret_cast<const bf16x8*>(Ab + k0 + ks * 32);
-    // cooperative copy: (hi/lo, row j < LP, 8-element segment) -> LDS
-    const int segs = kc / 8;
-    __syncthreads();
-    for (int q = threadIdx.x; q < 2 * LP * segs; q += kBlock) {
-      const int half = q / (LP * segs), rem = q - half * (LP * segs);
-      const int j = rem / segs, sg = rem - j * segs;
-      const bf16x8 v = *reinterpret_cast<const bf16x8*>(STb + half * lo_off + int64_t(j) * nbp + k0 + sg * 8);
-      *reinterpret_cast<bf16x8*>(&sst[(half * LP + j) * KP + sg * 8]) = v;
+      if (ks < kc / 32) a[ks] = *reinterpret_cast<const bf16x8*>(Ab + k0 + ks * 32);
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      const int q = threadIdx.x + u * kBlock;
+      const int half = q / (LP * SEGS), rem = q - half * (LP * SEGS);
+      const int j = rem / SEGS, sg = rem - j * SEGS;
+      if (sg < kc / 8) v[u] = *reinterpret_cast<const bf16x8*>(STb + half * lo_off + int64_t(j) * nbp + k0 + sg * 8);
     }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < nbp; k0 += KC) {
+    const int kc = min(KC, nbp - k0);
+    const int nsteps = kc / 32;
+    __syncthreads();  // the previous chunk's MFMAs are done with sst
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      const int q = threadIdx.x + u * kBlock;
+      const int half = q / (LP * SEGS), rem = q - half * (LP * SEGS);
+      const int j = rem / SEGS, sg = rem - j * SEGS;
+      if (sg < kc / 8) *reinterpret_cast<bf16x8*>(&sst[(half * LP + j) * KP + sg * 8]) = v[u];
+    }
+    bf16x8 ac[KC / 32];
+#pragma unroll
+    for (int ks = 0; ks < KC / 32; ++ks) ac[ks] = a[ks];
     __syncthreads();
+    if (k0 + KC < nbp) fetch(k0 + KC);
 #pragma unroll
     for (int ks = 0; ks < KC / 32; ++ks) {
       if (ks < nsteps) {
@@ -219,8 +239,8 @@ __global__ __launch_bounds__(kBlock) void k_gemm_bf16(BlockMeta bm, const uint16
           const uint16_t* sp = &sst[(n * 16 + li) * KP + ks * 32 + kq * 8];
           const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(sp);
           const bf16x8 blo = *reinterpret_cast<const bf16x8*>(sp + LP * KP);
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], bhi, acc[n], 0, 0, 0);
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], blo, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[ks], bhi, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[ks], blo, acc[n], 0, 0, 0);
         }
       }
     }
