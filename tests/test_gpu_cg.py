@@ -161,6 +161,40 @@ def test_multi_rhs_full_size_against_sparse_oracle():
     assert np.all(solve.relres(op, F.cpu().double().numpy(), p.Y) <= tol * 1.01)
 
 
+@pytest.mark.slow
+def test_batch_full_size_against_sparse_oracle():
+    """Full batching workload (64 graphs, N_g ~ U[2000, 30000], about 1e6
+    vertices, k=100, lambda=0.5) in the bench's launch configuration (no
+    periodic replacement, autotuned shapes): every column's FP64 true
+    residual on the sampled graphs, and sampled columns against the FP64
+    Tier-2 CG of each sampled graph on its own."""
+    import torch
+    dev = device()
+    p = synth.batch_of_graphs()
+    say("cg f32 batch full size")
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    tol = 1e-6 / (1 + 1 / 0.5)
+    F, iters, rel, st = hgl().cg_solve_batched(h, p.lams, Y, tol=tol, max_iter=300, rr_period=0, tune=True)
+    assert st == 0 and np.all(rel <= tol)
+    F = F.cpu().double().numpy()
+    G = len(p.lams)
+    sizes = np.diff(p.vtx_offsets)
+    graphs = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 42})
+    cols = np.arange(3, 100, 13)
+    for g in graphs:
+        v0, v1 = p.vtx_offsets[g], p.vtx_offsets[g + 1]
+        e0, e1 = p.edge_offsets[g], p.edge_offsets[g + 1]
+        ep = (p.edge_ptr[e0:e1 + 1] - p.edge_ptr[e0]).astype(np.int32)
+        ev = (p.edge_vtx[p.edge_ptr[e0]:p.edge_ptr[e1]] - v0).astype(np.int32)
+        op = lap.SparseOperator(v1 - v0, e1 - e0, ep, ev, p.w[e0:e1], p.lams[g])
+        assert np.all(solve.relres(op, F[v0:v1], p.Y[v0:v1]) <= tol * 1.01), g
+        fo, _, relo = solve.cg_ranking(op, p.w[e0:e1], p.lams[g], p.Y[v0:v1][:, cols], tol=1e-13)
+        assert np.all(relo <= 1e-13)
+        assert colrelerr(F[v0:v1][:, cols], fo).max() <= 1e-6, g
+    assert G == 64
+
+
 def test_graph_replay_matches_direct_launches():
     """The first chunk of iterations recorded as a HIP graph: every replay
     (new data at the same addresses, eager solves and synchronisations in

@@ -153,3 +153,35 @@ def test_full_size_gradient_against_sparse_oracle():
     g_o = ograd.objective_grad_sparse(op, p.w, p.lam, mu, p.Y, F.cpu().double().numpy())
     assert relerr(g, g_o) <= 1e-5
     assert abs(p.w @ g - 2 * mu * p.w @ p.w) <= 1e-6 * float(np.abs(p.w * g).sum())
+
+
+@pytest.mark.slow
+def test_full_size_gradient_k500_homogeneity_and_additivity():
+    """The differentiation workload as the bench runs it (N=100,000,
+    E=80,000, all 500 tag columns; FP32 solve and adjoint to relres 5e-7).
+    The FP64 oracle needs minutes at k=500, so the full launch is pinned by
+    properties that hold at any size: homogeneity (sum_e w_e dL/dw_e =
+    2 mu |w|^2, A being degree-0 homogeneous in w) and additivity over the
+    columns (the loss is a sum over columns, so the gradient of all 500 is
+    the sum of the gradients of two halves, each its own launch, minus one
+    2 mu w).  The 16-column launch is checked against the oracle above."""
+    import torch
+    dev = device()
+    p = synth.weight_learning()
+    mu = 0.01
+    tol = 1e-6 / (1 + 1 / p.lam)
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    say("grad full size k=500")
+    F, _, rel, st = hgl().cg_solve(h, p.lam, Y, tol=tol)
+    assert st == 0 and np.all(rel <= tol)
+    g, _, _, _ = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=tol)
+    g = g.cpu().numpy()
+    assert abs(p.w @ g - 2 * mu * p.w @ p.w) <= 1e-6 * float(np.abs(p.w * g).sum())
+    halves = []
+    for c0, c1 in ((0, 250), (250, 500)):
+        gh, _, _, _ = hgl().weight_grad(h, p.lam, F[:, c0:c1].contiguous(), Y=Y[:, c0:c1].contiguous(), mu=mu,
+                                        tol=tol)
+        halves.append(gh.cpu().numpy() - 2 * mu * p.w)
+    assert relerr(g - 2 * mu * p.w, halves[0] + halves[1]) <= 1e-6
+
