@@ -575,8 +575,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_rinv(BlockMeta bm, const TY* _
 // kJT = 2 x 2 blocks per thread and round: 3 covers l <= 80, 4 covers l <= 96.
 // TJ = arithmetic of the sweeps: FP64, or FP32 where the matrix comes from a
 // BF16 sketch (its entries carry errors far above FP32 rounding); the sweeps
-// stop when the off-diagonal Frobenius norm is below 1e-13 (FP64) or 1e-5
-// (FP32) of the diagonal's.
+// stop when the off-diagonal Frobenius norm is below 1e-13 (FP64) or 1e-4
+// (FP32: eigenvalue errors of order 1e-8 relative, eigenvector errors of
+// order 1e-4 over the relative gap, both below the BF16 sketch's 4e-3) of
+// the diagonal's.
 template <class TJ>
 struct Rot {
   TJ c, s;
@@ -590,7 +592,7 @@ __global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* 
   const int l = bm.l, LP = bm.LP, kk = bm.kk;
   const int ne = l + (l & 1);  // even count (a dummy index l pairs with the odd one out)
   const int half = ne / 2;
-  constexpr double kStop = sizeof(TJ) == 8 ? 1e-26 : 1e-10;   // squared relative off-diagonal norm
+  constexpr double kStop = sizeof(TJ) == 8 ? 1e-26 : 1e-8;   // squared relative off-diagonal norm
   constexpr TJ kTiny = sizeof(TJ) == 8 ? TJ(1e-300) : TJ(1e-30);
   TJ* A = reinterpret_cast<TJ*>(sm);                       // l x l
   TJ* V = A + l * l;                                       // l x l
