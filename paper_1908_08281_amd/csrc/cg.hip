@@ -24,9 +24,11 @@ namespace hgl {
 
 // Column states.  A column whose recursive residual falls to the claim level
 // stops (kClaimed: alpha = 0, P kept) until a host-scheduled check
-// recomputes its residual: done if that meets tol, else active again,
-// restarted from the recomputed residual.
-enum : int32_t { kActive = 0, kDone = 1, kBreakdown = 2, kClaimed = 3 };
+// recomputes its residual: done if that meets tol, else restarted from the
+// recomputed residual (kRestart: the restart launch sets P = R, the next
+// alpha step makes it active).  A check that finds a column still active
+// replaces its residual and leaves its direction.
+enum : int32_t { kActive = 0, kDone = 1, kBreakdown = 2, kClaimed = 3, kRestart = 4 };
 
 struct CgState {
   double* yy;      // [G*k] ||y||^2
@@ -163,6 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
 }
 
 // P = R + beta P for the iterating columns; a claimed column keeps P.
+// restart_only: P = R (beta is 0 for them) for the columns in kRestart only,
+// every other column keeps P.
 // part_pp (nullable): tile partials of p'p of the new P (the vertex half of
 // the next p'Mp).
 template <class T, int GL, int V>
@@ -170,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(
     const int32_t* __restrict__ tile_r0, const int32_t* __restrict__ tile_r1,
     const int32_t* __restrict__ tile_seg, const T* __restrict__ R, T* __restrict__ P, int64_t ld,
     const double* __restrict__ beta, const int32_t* __restrict__ state, int k, Gate gate,
-    double* __restrict__ part_pp) {
+    double* __restrict__ part_pp, int restart_only) {
   if (gate.skip()) return;
   constexpr int GPB = kBlock / GL, W = GL * V;
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
@@ -186,7 +190,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       be[i] = T(beta[int64_t(g) * k + col + i]);
-      keep[i] = state[int64_t(g) * k + col + i] == kClaimed;
+      const int32_t sc = state[int64_t(g) * k + col + i];
+      keep[i] = restart_only ? sc != kRestart : sc == kClaimed;
     }
     for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
       T rv[V], p[V];
@@ -440,6 +445,10 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
         st.state[id] = done ? kDone : kActive;
         add_cnt = done ? 0 : 1;
       } else if constexpr (OP == RedOp::Alpha) {
+        if (st0 == kRestart) {
+          st.state[id] = kActive;  // its restart direction is in place
+          st0 = kActive;
+        }
         if (st0 != kActive || rz0 == 0.0) {
           st.alpha[id] = 0.0;
           break;
@@ -483,7 +492,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
         add_cnt = 1;
         rel_max = rel;
       } else {  // Check: sum is r'r of Y - M F recomputed in FP64
-        if (st0 != kActive && st0 != kClaimed) break;
+        if (st0 != kActive && st0 != kClaimed && st0 != kRestart) break;
         const double rel = yy0 > 0.0 ? sqrt(sum / yy0) : sqrt(sum);
         st.relres[id] = rel;
         // residual replacement: the recursion continues from the recomputed
@@ -492,11 +501,13 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
         st.rz[id] = rz;
         if (rel <= ra.tol) {
           st.state[id] = kDone;
+        } else if (st0 == kActive) {
+          add_chk = 1;  // still iterating: keeps its direction
         } else {
           // restart: the direction is rebuilt from the recomputed residual
           // (P = R, beta = 0), since the old one was scaled to a recursive
           // residual that may have drifted far from the true one
-          st.state[id] = kActive;
+          st.state[id] = kRestart;
           st.beta[id] = 0.0;
           add_chk = 1;
         }
@@ -740,7 +751,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       dim3 grid(h->n_tiles, cs.slabs);
       launch(h, -1, k_cg_direction<T, GL, V>, grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
                          h->tile_seg, dir_src, b.P, ld, b.st.beta, static_cast<const int32_t*>(b.st.state), k,
-                         g_now, b.pp);
+                         g_now, b.pp, 0);
       HGL_HIP(hipGetLastError());
       return HGL_OK;
     });
@@ -770,7 +781,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       dim3 grid(h->n_tiles, cs.slabs);
       launch(h, -1, k_cg_direction<T, GL, V>, grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
                          h->tile_seg, dir_src, b.P, ld, b.st.beta, static_cast<const int32_t*>(b.st.state), k,
-                         Gate{}, b.pp);
+                         Gate{}, b.pp, 1);
       HGL_HIP(hipGetLastError());
       return HGL_OK;
     });
@@ -841,6 +852,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   bool all_done = false;
   double r_ref = -1.0;
   int it_ref = 0;
+  int checked_at = -1;
   int next = o->chunk > 0 ? o->chunk : std::max(2, chunk_for(2.0 * std::sqrt(kappa), rho));
   while (!all_done && it < o->max_iter) {
     const int n = std::min(next, o->max_iter - it);
@@ -851,19 +863,31 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     } else {
       for (int c = 0; c < n; ++c, ++it) HGL_TRY(iteration(it));
     }
+    // A chunk sized to reach the claim level (chunk = 0) is followed at once
+    // by a check, so that the usual solve needs one host synchronisation: a
+    // column still iterating at the check only has its residual replaced.
+    const bool speculate = o->chunk <= 0;
+    if (speculate) HGL_TRY(check(it));
     HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.cnt(it - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HGL_HIP(hipMemcpyAsync(h->pinned_d, wd.rmax(it - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+    if (speculate) HGL_HIP(hipMemcpyAsync(h->pinned_i + 1, wd.chk(it), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HGL_HIP(hipStreamSynchronize(s));
-    if (h->pinned_i[0] == 0) {  // every column claimed, finished or broken down
+    const int iterating = h->pinned_i[0];
+    if (iterating == 0 && !speculate) {  // every column claimed, finished or broken down
       HGL_TRY(check(it));
-      HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.chk(it), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HGL_HIP(hipMemcpyAsync(h->pinned_i + 1, wd.chk(it), sizeof(int32_t), hipMemcpyDeviceToHost, s));
       HGL_HIP(hipStreamSynchronize(s));
-      all_done = h->pinned_i[0] == 0;
+    }
+    if (speculate || iterating == 0) {
+      checked_at = it;
       ++n_checks;
+      all_done = h->pinned_i[1] == 0;
       if (!all_done) {
         ++n_resumed;
-        HGL_TRY(restart());
+        HGL_TRY(restart());  // P = R for the restarted columns only
       }
+    }
+    if (iterating == 0) {
       next = o->chunk > 0 ? o->chunk : 2;  // columns that go on are close to the end
       r_ref = -1.0;
       continue;
@@ -875,7 +899,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     r_ref = r_now;
     it_ref = it;
   }
-  if (!all_done) {
+  if (!all_done && checked_at != it) {
     HGL_TRY(check(it));  // record the true residual of every unfinished column
     ++n_checks;
   }
@@ -893,7 +917,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   bool breakdown = false, unconverged = false;
   for (size_t i = 0; i < gk; ++i) {
     if (state_h[i] == kBreakdown) breakdown = true;
-    if (state_h[i] == kActive) unconverged = true;
+    if (state_h[i] == kActive || state_h[i] == kClaimed || state_h[i] == kRestart) unconverged = true;
     if (relres_host) relres_host[i] = pd[i];
     if (iters_host) iters_host[i] = iters_h[i];
   }
