@@ -300,3 +300,68 @@ def test_claimed_columns_restart_after_a_failed_check():
     tr = true_relres(F, 0.002)
     assert np.allclose(rel[0], tr, rtol=1e-6, atol=0)
     assert tr.max() > 1e-6
+
+
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+def test_degenerate_hypergraphs(mode):
+    """Edge cases of the fused step: no hyperedges at all (no edge tiles, the
+    hyperedge half of p'Mp empty: F = lambda/(1+lambda) Y exactly up to
+    rounding), a batch in which one graph has no hyperedges, and a
+    hypergraph whose hyperedges are all large enough for a whole workgroup
+    each (no short hyperedge in any edge tile)."""
+    import torch
+    dev = device()
+    dt = torch.float32 if mode == "f32" else torch.float64
+    tol = 2e-7 if mode == "f32" else 1e-12
+    bar = 1e-6 if mode == "f32" else 1e-10
+    rng = synth.rng_for(11)
+    lam = 0.7
+    # 1. no hyperedges
+    N, k = 500, 7
+    Y0 = rng.standard_normal((N, k))
+    p0 = synth.Problem(N, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), lam, Y0)
+    say("degenerate: E = 0", mode)
+    h0 = build(p0, dev)
+    F, it, rel, st = hgl().cg_solve(h0, lam, torch.from_numpy(Y0).to(dev, dt), mode=mode, tol=tol)
+    assert st == 0
+    assert colrelerr(F.cpu().double().numpy(), lam / (1 + lam) * Y0).max() <= bar
+    # 2. all hyperedges large (40..90 members)
+    N2, E2, k2 = 600, 25, 5
+    sizes = rng.integers(40, 91, size=E2)
+    ev = np.concatenate([np.sort(rng.choice(N2, size=s, replace=False)) for s in sizes]).astype(np.int32)
+    ep = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    w2 = rng.uniform(0.2, 1.0, size=E2)
+    Y2 = rng.standard_normal((N2, k2))
+    p2 = synth.Problem(N2, E2, ep, ev, w2, lam, Y2)
+    say("degenerate: all hyperedges large", mode)
+    h2 = build(p2, dev)
+    assert h2.partition()["long_edges"] == E2
+    F2, it2, rel2, st2 = hgl().cg_solve(h2, lam, torch.from_numpy(Y2).to(dev, dt), mode=mode, tol=tol)
+    assert st2 == 0
+    assert colrelerr(F2.cpu().double().numpy(), _dense_solution(p2)).max() <= bar
+    # 3. a batch whose middle graph has no hyperedges
+    pb = synth.batch_of_graphs(G=3, nlo=300, nhi=700, k=4)
+    v0, v1 = pb.vtx_offsets[1], pb.vtx_offsets[2]
+    e0, e1 = pb.edge_offsets[1], pb.edge_offsets[2]
+    keep = np.r_[0:e0, e1:pb.E]
+    counts = np.diff(pb.edge_ptr)[keep]
+    starts = pb.edge_ptr[:-1][keep]
+    ev3 = np.concatenate([pb.edge_vtx[s:s + c] for s, c in zip(starts, counts)]).astype(np.int32)
+    ep3 = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    eo3 = pb.edge_offsets.copy()
+    eo3[2:] -= e1 - e0
+    p3 = synth.Problem(pb.N, pb.E - (e1 - e0), ep3, ev3, pb.w[keep], lam, pb.Y, vtx_offsets=pb.vtx_offsets,
+                       edge_offsets=eo3, lams=np.array([0.5, lam, 2.0]))
+    say("degenerate: batch with an empty graph", mode)
+    h3 = build(p3, dev)
+    F3, it3, rel3, st3 = hgl().cg_solve_batched(h3, p3.lams, torch.from_numpy(p3.Y).to(dev, dt), mode=mode, tol=tol)
+    assert st3 == 0
+    F3 = F3.cpu().double().numpy()
+    assert colrelerr(F3[v0:v1], lam / (1 + lam) * p3.Y[v0:v1]).max() <= bar
+    for g in (0, 2):
+        a0, a1 = p3.vtx_offsets[g], p3.vtx_offsets[g + 1]
+        b0, b1 = eo3[g], eo3[g + 1]
+        epg = (ep3[b0:b1 + 1] - ep3[b0]).astype(np.int32)
+        evg = (ev3[ep3[b0]:ep3[b1]] - a0).astype(np.int32)
+        sub = synth.Problem(a1 - a0, b1 - b0, epg, evg, p3.w[b0:b1], p3.lams[g], p3.Y[a0:a1])
+        assert colrelerr(F3[a0:a1], _dense_solution(sub)).max() <= bar
