@@ -69,17 +69,19 @@ typedef struct hgl_cg_opts {
   int32_t max_iter;   /* iteration limit (>= 1) */
   int32_t x0_given;   /* 1: F holds the starting guess on entry; 0: start from 0 */
   int32_t rr_period;  /* residual replacement period (F32 mode); 0 = only on claims */
-  int32_t chunk;      /* iterations enqueued between host convergence checks; 0 = automatic */
+  int32_t chunk;      /* iterations enqueued between host convergence checks; 0 = automatic:
+                         each chunk is sized from the convergence rate to reach the claim level
+                         and is followed at once by an FP64 residual check */
   int32_t graph;      /* 1: the first chunk of iterations runs as a HIP graph, captured on
                          first use and replayed by later solves on the handle with the same
                          arguments (pointers, sizes, options); 0: direct launches.  Ignored
                          while kernel timing (hgl_profile) is on. */
-  int32_t tune;       /* 1: the column shape of the kernels (lanes per row, vector width,
-                         column slabs) is picked by timing the operator gathers on first use
-                         for this k and element size and cached in the handle (a one-time
-                         cost of a few milliseconds; the grouping of the FP64 partial sums
-                         follows the shape, so results can differ at rounding level from
-                         tune = 0); 0: the widest-vector shape */
+  int32_t tune;       /* 1: the column shapes of the two operator gathers (lanes per row,
+                         vector width, column slabs) are picked by timing each gather on
+                         first use for this k and element size and cached in the handle (a
+                         one-time cost of a few milliseconds; the grouping of the FP64
+                         partial sums follows the shape, so results can differ at rounding
+                         level from tune = 0); 0: the widest-vector shape */
 } hgl_cg_opts;
 
 /* Library version, e.g. 100 for 0.1.0. */
@@ -181,7 +183,11 @@ int hgl_apply(hgl_handle* h, double lambda, int32_t dt, const void* P, int64_t l
 /*
  * Solve (I + L/lambda) F = Y column by column by conjugate gradient, in the
  * recurrences of the paper's section 3 (eqs. 16-20), each column with its own
- * alpha and beta.  Y, F: N x k of type double (PLAIN_F64) or float
+ * alpha and beta (p'Mp obtained as (1 + 1/lambda) p'p - (1/lambda)
+ * sum_e c_e |(H' S p)_e|^2, eq. 1, so that the update runs inside the
+ * operator product).  A column whose recursive residual reaches the claim
+ * level stops until an FP64 residual check: it finishes if the recomputed
+ * residual meets tol, and otherwise restarts its search direction from it.  Y, F: N x k of type double (PLAIN_F64) or float
  * (F32_F64DOT_RR).  iters_host [G*k] (nullable) receives the iteration count
  * of each (graph, column), relres_host [G*k] (nullable) the FP64-recomputed
  * ||y - M f|| / ||y|| of the returned F (0 for a zero column, whose solution
@@ -210,8 +216,11 @@ int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg
  * diagonal block A_bb of the normalised adjacency A (eq. 1) the library runs
  * Algorithm 1: Y = A_bb Omega, S = orth(Y), then q times
  * { S~ = orth(A_bb' S), S = orth(A_bb S~) }, B = S' A_bb, B = U~ Sigma V',
- * U = S U~, keeping the k leading singular triplets.  orth() is CholQR2
- * (Gram matrices and their Cholesky factors in FP64).  The diagonal blocks of
+ * U = S U~, keeping the k leading singular triplets.  orth() is CholQR
+ * (Gram matrices and their Cholesky factors in FP64): two passes for the
+ * basis of the last step and throughout an FP64 sketch, one pass between the
+ * products of a BF16 sketch.  The small symmetric eigenproblem of B B' is
+ * solved by parallel cyclic Jacobi, in FP32 sweeps for a BF16 sketch.  The diagonal blocks of
  * X = I - A/(1+theta) are full rank, so the low-rank object decomposed is
  * A_bb; eq. (15) is applied as the identity-plus-low-rank inverse
  *   (I + L_bb/lambda)^-1 ~ lambda/(1+lambda) [I + U diag(s/(1+lambda-s)) U'].
