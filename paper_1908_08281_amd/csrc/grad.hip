@@ -116,63 +116,101 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad(int32_t E, int k, const in
 
 // ------------------------------------------------------ simplex projection --
 
-// Euclidean projection of v onto {w >= 0, sum w = 1} in one workgroup:
-// bisection for tau with sum max(v - tau, 0) = 1 (the sum decreases in tau),
-// then the exact tau of the support found, (sum_{v_i > tau} v_i - 1)/|support|,
-// recomputed until the support is stable.  Fixed-order reductions.
-__device__ double block_sum(double x, double* lds) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, kWave);
-  if (threadIdx.x % kWave == 0) lds[threadIdx.x / kWave] = x;
-  __syncthreads();
-  const double t = ((lds[0] + lds[1]) + lds[2]) + lds[3];
-  __syncthreads();
-  return t;
-}
+// Euclidean projection of v onto {w >= 0, sum w = 1} in one workgroup of
+// kProj threads.  tau solves f(tau) = sum max(v - tau, 0) = 1 (f decreases
+// in tau): each pass over v evaluates f at kSect points splitting the
+// bracket [lo, hi] evenly and keeps the sub-interval where f crosses 1, then
+// the exact tau of the support found, (sum_{v_i > tau} v_i - 1)/|support|,
+// is recomputed until the support is stable.  Per-thread sums in a fixed
+// stride order and fixed-order block reductions: deterministic.
+constexpr int kProj = 1024, kProjWaves = kProj / kWave, kSect = 8;
 
-__device__ double block_max(double x, double* lds) {
+// Sums over the workgroup of x[0 .. n-1] (n <= kSect), returned to every thread.
+template <int n>
+__device__ void block_sums(double (&x)[n], double* lds /* [kProjWaves * kSect] */) {
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, kWave));
-  if (threadIdx.x % kWave == 0) lds[threadIdx.x / kWave] = x;
+  for (int m = 0; m < n; ++m)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x[m] += __shfl_xor(x[m], off, kWave);
+  if (threadIdx.x % kWave == 0)
+#pragma unroll
+    for (int m = 0; m < n; ++m) lds[(threadIdx.x / kWave) * kSect + m] = x[m];
   __syncthreads();
-  const double t = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
-  __syncthreads();
-  return t;
-}
-
-__global__ __launch_bounds__(kBlock) void k_project_simplex(int32_t E, const double* __restrict__ v,
-                                                            double* __restrict__ w) {
-  __shared__ double lds[4];
-  double mx = -INFINITY, mn = INFINITY;
-  for (int i = threadIdx.x; i < E; i += kBlock) {
-    mx = fmax(mx, v[i]);
-    mn = fmin(mn, v[i]);
+#pragma unroll
+  for (int m = 0; m < n; ++m) {
+    double t = 0.0;
+    for (int w = 0; w < kProjWaves; ++w) t += lds[w * kSect + m];
+    x[m] = t;
   }
-  mx = block_max(mx, lds);
-  mn = -block_max(-mn, lds);
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kProj) void k_project_simplex(int32_t E, const double* __restrict__ v,
+                                                           double* __restrict__ w) {
+  __shared__ double lds[kProjWaves * kSect];
+  double mm[2] = {-INFINITY, -INFINITY};  // max v, max -v
+  for (int i = threadIdx.x; i < E; i += kProj) {
+    mm[0] = fmax(mm[0], v[i]);
+    mm[1] = fmax(mm[1], -v[i]);
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mm[m] = fmax(mm[m], __shfl_xor(mm[m], off, kWave));
+  if (threadIdx.x % kWave == 0) {
+    lds[(threadIdx.x / kWave) * kSect] = mm[0];
+    lds[(threadIdx.x / kWave) * kSect + 1] = mm[1];
+  }
+  __syncthreads();
+  double mx = -INFINITY, mn = INFINITY;
+  for (int wv = 0; wv < kProjWaves; ++wv) {
+    mx = fmax(mx, lds[wv * kSect]);
+    mn = fmin(mn, -lds[wv * kSect + 1]);
+  }
+  __syncthreads();
   double lo = mn - 1.0, hi = mx;  // f(lo) >= E >= 1 > 0 = f(hi)
-  for (int it = 0; it < 100 && hi - lo > 1e-16 * fmax(1.0, fabs(hi)); ++it) {
-    const double mid = 0.5 * (lo + hi);
-    double sacc = 0.0;
-    for (int i = threadIdx.x; i < E; i += kBlock) sacc += fmax(v[i] - mid, 0.0);
-    sacc = block_sum(sacc, lds);
-    if (sacc >= 1.0) lo = mid; else hi = mid;
+  for (int pass = 0; pass < 40 && hi - lo > 1e-16 * fmax(1.0, fabs(hi)); ++pass) {
+    double tau[kSect], f[kSect];
+#pragma unroll
+    for (int m = 0; m < kSect; ++m) {
+      tau[m] = lo + (hi - lo) * double(m + 1) / double(kSect + 1);
+      f[m] = 0.0;
+    }
+    // eight loads in flight per round; entries past E read as -inf (adding 0)
+    for (int i0 = threadIdx.x; i0 < E; i0 += 8 * kProj) {
+      double vi[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) vi[u] = i0 + u * kProj < E ? v[i0 + u * kProj] : -INFINITY;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int m = 0; m < kSect; ++m) f[m] += fmax(vi[u] - tau[m], 0.0);
+    }
+    block_sums<kSect>(f, lds);
+    // f is decreasing: the crossing lies after the last point with f >= 1
+    double nlo = lo, nhi = hi;
+#pragma unroll
+    for (int m = 0; m < kSect; ++m) {
+      if (f[m] >= 1.0) nlo = tau[m];
+      else if (nhi == hi) nhi = tau[m];
+    }
+    lo = nlo;
+    hi = nhi;
   }
   double tau = 0.5 * (lo + hi);
-  for (int round = 0; round < 4; ++round) {
-    double ssum = 0.0, cnt = 0.0;
-    for (int i = threadIdx.x; i < E; i += kBlock)
+  for (int round = 0; round < 8; ++round) {
+    double sc[2] = {0.0, 0.0};  // sum and count of the support
+    for (int i = threadIdx.x; i < E; i += kProj)
       if (v[i] > tau) {
-        ssum += v[i];
-        cnt += 1.0;
+        sc[0] += v[i];
+        sc[1] += 1.0;
       }
-    ssum = block_sum(ssum, lds);
-    cnt = block_sum(cnt, lds);
-    const double t2 = cnt > 0.0 ? (ssum - 1.0) / cnt : tau;
+    block_sums<2>(sc, lds);
+    const double t2 = sc[1] > 0.0 ? (sc[0] - 1.0) / sc[1] : tau;
     if (t2 == tau) break;
     tau = t2;
   }
-  for (int i = threadIdx.x; i < E; i += kBlock) w[i] = fmax(v[i] - tau, 0.0);
+  for (int i = threadIdx.x; i < E; i += kProj) w[i] = fmax(v[i] - tau, 0.0);
 }
 
 // ------------------------------------------------------------------ driver --
@@ -298,7 +336,7 @@ extern "C" int hgl_weight_grad(hgl_handle* h, double lambda, double mu, const vo
 extern "C" int hgl_project_simplex(const double* v, double* w, int32_t E, hipStream_t s) {
   clear_error();
   HGL_CHECK_ARG(E >= 1 && v && w, "need E >= 1 and v, w");
-  hipLaunchKernelGGL(k_project_simplex, dim3(1), dim3(kBlock), 0, s, E, v, w);
+  hipLaunchKernelGGL(k_project_simplex, dim3(1), dim3(kProj), 0, s, E, v, w);
   HGL_HIP(hipGetLastError());
   return HGL_OK;
 }
