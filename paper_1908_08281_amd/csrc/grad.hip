@@ -148,28 +148,27 @@ __device__ void block_sums(double (&x)[n], double* lds /* [kProjWaves * kSect] *
 __global__ __launch_bounds__(kProj) void k_project_simplex(int32_t E, const double* __restrict__ v,
                                                            double* __restrict__ w) {
   __shared__ double lds[kProjWaves * kSect];
-  double mm[2] = {-INFINITY, -INFINITY};  // max v, max -v
+  // max v and sum v: tau lies in [max(vmax - 1, (sum v - 1)/E), vmax] (the
+  // largest entry alone gives at most 1; tau = (sum v - 1)/E would give
+  // every entry, so f there is >= 1)
+  double mx = -INFINITY, sm[1] = {0.0};
   for (int i = threadIdx.x; i < E; i += kProj) {
-    mm[0] = fmax(mm[0], v[i]);
-    mm[1] = fmax(mm[1], -v[i]);
+    mx = fmax(mx, v[i]);
+    sm[0] += v[i];
   }
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) mm[m] = fmax(mm[m], __shfl_xor(mm[m], off, kWave));
-  if (threadIdx.x % kWave == 0) {
-    lds[(threadIdx.x / kWave) * kSect] = mm[0];
-    lds[(threadIdx.x / kWave) * kSect + 1] = mm[1];
-  }
+  for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+  if (threadIdx.x % kWave == 0) lds[(threadIdx.x / kWave) * kSect + 1] = mx;
   __syncthreads();
-  double mx = -INFINITY, mn = INFINITY;
-  for (int wv = 0; wv < kProjWaves; ++wv) {
-    mx = fmax(mx, lds[wv * kSect]);
-    mn = fmin(mn, -lds[wv * kSect + 1]);
-  }
+  mx = -INFINITY;
+  for (int wv = 0; wv < kProjWaves; ++wv) mx = fmax(mx, lds[wv * kSect + 1]);
   __syncthreads();
-  double lo = mn - 1.0, hi = mx;  // f(lo) >= E >= 1 > 0 = f(hi)
-  for (int pass = 0; pass < 40 && hi - lo > 1e-16 * fmax(1.0, fabs(hi)); ++pass) {
+  block_sums<1>(sm, lds);
+  double lo = fmax(mx - 1.0, (sm[0] - 1.0) / double(E)), hi = mx;
+  // sectioning narrows the bracket by (kSect + 1) per pass; seven passes
+  // leave about 2e-7 of it, after which the support iteration below needs a
+  // round or two
+  for (int pass = 0; pass < 7 && hi > lo; ++pass) {
     double tau[kSect], f[kSect];
 #pragma unroll
     for (int m = 0; m < kSect; ++m) {
@@ -197,8 +196,11 @@ __global__ __launch_bounds__(kProj) void k_project_simplex(int32_t E, const doub
     lo = nlo;
     hi = nhi;
   }
-  double tau = 0.5 * (lo + hi);
-  for (int round = 0; round < 8; ++round) {
+  // support iteration from below (f(lo) >= 1, so lo <= tau*): tau <- (sum
+  // of the entries above tau - 1)/their count increases to tau* and stops
+  // there once the support is stable
+  double tau = lo;
+  for (int round = 0; round < 64; ++round) {
     double sc[2] = {0.0, 0.0};  // sum and count of the support
     for (int i = threadIdx.x; i < E; i += kProj)
       if (v[i] > tau) {
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(kProj) void k_project_simplex(int32_t E, const doub
       }
     block_sums<2>(sc, lds);
     const double t2 = sc[1] > 0.0 ? (sc[0] - 1.0) / sc[1] : tau;
-    if (t2 == tau) break;
+    if (!(t2 > tau)) break;
     tau = t2;
   }
   for (int i = threadIdx.x; i < E; i += kProj) w[i] = fmax(v[i] - tau, 0.0);
