@@ -30,23 +30,15 @@ __global__ void k_to_f64(int64_t rows, int k, const T* __restrict__ X, int64_t l
     D[i] = double(X[(i / k) * ldx + i % k]);
 }
 
-// R = 2 lambda_g (MF - Y) in the caller's type (rows of graph g)
-template <class T>
-__global__ void k_objective_rhs(int64_t rows, int k, const double* __restrict__ MF, const T* __restrict__ Y,
-                                int64_t ldy, double lam2, T* __restrict__ R) {
-  const int64_t total = rows * k;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t r = i / k, c = i % k;
-    R[i] = T(lam2 * (MF[i] - double(Y[r * ldy + c])));
-  }
-}
-
 // Per-vertex contractions (FP64, k-wide rows, one 64-lane wave per vertex):
 //   t1_v = s_v^2 * 2 <F_v, (AF)_v>                       (for Gamma(F, F))
 //   t2_v = s_v^2 (<Z_v, (AF)_v> + <(AZ)_v, F_v>)         (for Gamma(Z, F))
+// F and Z in the caller's type TF (row strides ldf, ldz), AF and AZ FP64.
+template <class TF>
 __global__ __launch_bounds__(kBlock) void k_vertex_terms(int32_t N, int k, const double* __restrict__ s,
-                                                         const double* __restrict__ F, const double* __restrict__ AF,
-                                                         const double* __restrict__ Z, const double* __restrict__ AZ,
+                                                         const TF* __restrict__ F, int64_t ldf,
+                                                         const double* __restrict__ AF, const TF* __restrict__ Z,
+                                                         int64_t ldz, const double* __restrict__ AZ,
                                                          double* __restrict__ t1, double* __restrict__ t2) {
   const int v = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
@@ -54,9 +46,9 @@ __global__ __launch_bounds__(kBlock) void k_vertex_terms(int32_t N, int k, const
   const int64_t o = int64_t(v) * k;
   double a = 0.0, b = 0.0;
   for (int c = lane; c < k; c += kWave) {
-    const double f = F[o + c], af = AF[o + c];
+    const double f = double(F[int64_t(v) * ldf + c]), af = AF[o + c];
     a += f * af;
-    if (Z) b += Z[o + c] * af + AZ[o + c] * f;
+    if (Z) b += double(Z[int64_t(v) * ldz + c]) * af + AZ[o + c] * f;
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -74,12 +66,15 @@ __global__ __launch_bounds__(kBlock) void k_vertex_terms(int32_t N, int k, const
 //   g1 = <u_e(F), u_e(F)>/delta(e) - 1/2 sum_{v in e} t1_v    (= Gamma_e(F, F))
 //   g2 = <u_e(Z), u_e(F)>/delta(e) - 1/2 sum_{v in e} t2_v    (= Gamma_e(Z, F))
 //   grad_e = cf * g1 + cz * g2 + 2 mu w_e
+// F and Z in the caller's type TF (row strides ldf, ldz), accumulated in FP64.
+template <class TF>
 __global__ __launch_bounds__(kBlock) void k_edge_grad(int32_t E, int k, const int32_t* __restrict__ edge_ptr,
                                                       const int32_t* __restrict__ edge_vtx,
-                                                      const double* __restrict__ s, const double* __restrict__ F,
-                                                      const double* __restrict__ Z, const double* __restrict__ t1,
-                                                      const double* __restrict__ t2, const double* __restrict__ w,
-                                                      double cf, double cz, double mu, double* __restrict__ grad) {
+                                                      const double* __restrict__ s, const TF* __restrict__ F,
+                                                      int64_t ldf, const TF* __restrict__ Z, int64_t ldz,
+                                                      const double* __restrict__ t1, const double* __restrict__ t2,
+                                                      const double* __restrict__ w, double cf, double cz, double mu,
+                                                      double* __restrict__ grad) {
   const int e = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   if (e >= E) return;
@@ -90,8 +85,8 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad(int32_t E, int k, const in
     for (int j = b; j < en; ++j) {
       const int v = edge_vtx[j];
       const double sv = s[v];
-      uf += sv * F[int64_t(v) * k + c];
-      if (Z) uz += sv * Z[int64_t(v) * k + c];
+      uf += sv * double(F[int64_t(v) * ldf + c]);
+      if (Z) uz += sv * double(Z[int64_t(v) * ldz + c]);
     }
     ff += uf * uf;
     zf += uz * uf;
@@ -111,6 +106,15 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad(int32_t E, int k, const in
     const double g1 = ff / de - 0.5 * s1;
     const double g2 = zf / de - 0.5 * s2;
     grad[e] = cf * g1 + cz * g2 + 2.0 * mu * w[e];
+  }
+}
+
+template <class T>
+__global__ void k_scale(int64_t rows, int k, T* __restrict__ X, int64_t ldx, double a) {
+  const int64_t total = rows * k;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    T& x = X[(i / k) * ldx + i % k];
+    x = T(a * double(x));
   }
 }
 
@@ -271,14 +275,18 @@ static int run_grad(hgl_handle* h, double lam, double mu, const T* F, int64_t ld
                                                ab.as<double>(), ab.as<double>() + h->G, nullptr, k, cs, Gate{}, s);
   };
   HGL_TRY(apply64(F64, AF, abA));
-  // adjoint right-hand side
+  // adjoint right-hand side: G, or for the objective R = Y - M F from the FP64
+  // residual pass (accumulated in FP64, so the small difference keeps its
+  // digits); then Z' = M^-1 R and Z = -2 lambda Z' (M^-1 is linear), so the
+  // adjoint term Gamma(Z, F)/lambda = -2 Gamma(Z', F)
   const T* rhs_ptr = G;
   int64_t ld_rhs = ldg;
   if (objective) {
-    HGL_TRY(apply64(F64, AZ, abM));  // AZ used as scratch for M F
-    launch(h, -1, k_objective_rhs<T>, dim3(blocks), dim3(256), 0, s, int64_t(N), k, AZ, Y, ldy, 2.0 * lam,
-                       rhs);
-    HGL_HIP(hipGetLastError());
+    HGL_TRY(h->ws_part.reserve(sizeof(double) * size_t(n_slots(h)) * k));
+    const ColShape csr = pick_shape(k, 8, {F, Y, rhs, Zedge}, {ldf, ldy, int64_t(k)});
+    HGL_TRY((launch_spmm_edge<T, double>(h, F, ldf, Zedge, k, k, csr, Gate{}, s)));
+    HGL_TRY((launch_spmm_vertex<T, double>(h, VMode::Resid, F, ldf, Zedge, k, Y, ldy, rhs, k, abM.as<double>(),
+                                           abM.as<double>() + h->G, h->ws_part.as<double>(), k, csr, Gate{}, s)));
     rhs_ptr = rhs;
     ld_rhs = k;
   }
@@ -293,13 +301,21 @@ static int run_grad(hgl_handle* h, double lam, double mu, const T* F, int64_t ld
   launch(h, -1, k_to_f64<T>, dim3(blocks), dim3(256), 0, s, int64_t(N), k, Zdst, ldzd, Z64);
   HGL_HIP(hipGetLastError());
   HGL_TRY(apply64(Z64, AZ, abA));
-  launch(h, -1, k_vertex_terms, dim3((N + 3) / 4), dim3(kBlock), 0, s, N, k, h->s64, F64, AF, Z64, AZ, t1, t2);
+  // the contractions read F and Z in the caller's type (FP32 -> FP64 is exact)
+  launch(h, -1, k_vertex_terms<T>, dim3((N + 3) / 4), dim3(kBlock), 0, s, N, k, h->s64, F, ldf,
+         static_cast<const double*>(AF), static_cast<const T*>(Zdst), ldzd, static_cast<const double*>(AZ), t1, t2);
   HGL_HIP(hipGetLastError());
   if (E > 0) {
     const double cf = objective ? -1.0 : 0.0;
-    const double cz = 1.0 / lam;
-    launch(h, -1, k_edge_grad, dim3((E + 3) / 4), dim3(kBlock), 0, s, E, k, h->edge_ptr, h->edge_vtx, h->s64,
-                       F64, Z64, t1, t2, h->w, cf, cz, objective ? mu : 0.0, grad);
+    const double cz = objective ? -2.0 : 1.0 / lam;
+    launch(h, -1, k_edge_grad<T>, dim3((E + 3) / 4), dim3(kBlock), 0, s, E, k, h->edge_ptr, h->edge_vtx, h->s64,
+           F, ldf, static_cast<const T*>(Zdst), ldzd, static_cast<const double*>(t1), static_cast<const double*>(t2),
+           static_cast<const double*>(h->w), cf, cz, objective ? mu : 0.0, grad);
+    HGL_HIP(hipGetLastError());
+  }
+  if (objective && Zout) {
+    // the caller's Z = -2 lambda Z'
+    launch(h, -1, k_scale<T>, dim3(blocks), dim3(256), 0, s, int64_t(N), k, Zout, ldz, -2.0 * lam);
     HGL_HIP(hipGetLastError());
   }
   prof_end(h, s);

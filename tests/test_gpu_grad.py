@@ -55,6 +55,13 @@ def test_objective_gradient_matches_oracle_and_homogeneity():
     # degree-0 homogeneity of A in w: sum_e w_e dJ/dw_e = 2 mu ||w||^2
     lhs = float(p.w @ g)
     assert abs(lhs - 2 * mu * p.w @ p.w) <= 1e-6 * float(np.abs(p.w * g).sum())
+    # the adjoint handed back: Z = M^-1 (2 lambda (M F - Y)), same gradient
+    g2, Z, _, _ = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=3e-7, want_z=True)
+    assert np.array_equal(g2.cpu().numpy(), g)
+    Fd = F.cpu().double().numpy()
+    M = lap.system_matrix(H, p.w, p.lam)
+    Z_o = solve.solve_dense(M, 2.0 * p.lam * (M @ Fd - p.Y))
+    assert relerr(Z.cpu().double().numpy(), Z_o) <= 1e-5
 
 
 def test_objective_gradient_matches_richardson_fd():
