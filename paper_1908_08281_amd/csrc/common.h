@@ -296,7 +296,8 @@ int launch_spmm_edge(const hgl_handle* h, const TIn* P, int64_t ldp, TAcc* Z, in
 // Edge-slot count of the edge gather's partial sums.
 inline int n_eslots(const hgl_handle* h) { return h->n_etiles + h->n_long_edge; }
 
-// Vertex-major gather + epilogue.  Apply: Out = a X - b s H Z.  ApplyDot: same
+// Vertex-major gather + epilogue.  Apply: Out = a X - b s H Z (X may be null
+// for a = 0).  ApplyDot: same
 // and partial <X, Out> per column.  Resid: Out = Y - (a X - b s H Z) with FP64
 // accumulation and partial <Out, Out>.  Step (T = TZ, X = P): with Q = a P -
 // b s H Z kept in registers, u.F += alpha P, u.R -= alpha Q and partial

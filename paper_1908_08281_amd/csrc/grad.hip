@@ -23,13 +23,6 @@
 
 namespace hgl {
 
-template <class T>
-__global__ void k_to_f64(int64_t rows, int k, const T* __restrict__ X, int64_t ldx, double* __restrict__ D) {
-  const int64_t total = rows * k;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x)
-    D[i] = double(X[(i / k) * ldx + i % k]);
-}
-
 // Per-vertex contractions (FP64, k-wide rows, one 64-lane wave per vertex):
 //   t1_v = s_v^2 * 2 <F_v, (AF)_v>                       (for Gamma(F, F))
 //   t2_v = s_v^2 (<Z_v, (AF)_v> + <(AZ)_v, F_v>)         (for Gamma(Z, F))
@@ -228,27 +221,22 @@ static int run_grad(hgl_handle* h, double lam, double mu, const T* F, int64_t ld
   const int N = h->N, E = h->E;
   const bool objective = G == nullptr;
   const size_t nk = size_t(N) * k;
-  // buffers: F64, AF, Z64, AZ (N x k FP64), rhs/Z in T (N x k), t1, t2 (N)
+  // buffers: AF, AZ (N x k FP64), rhs/Z in T (N x k), t1, t2 (N)
   DevBuf& buf = h->ws_extra[1];
   DevBuf& bufT = h->ws_extra[2];
-  HGL_TRY(buf.reserve(sizeof(double) * (4 * nk + 2 * size_t(N)) + 256));
+  HGL_TRY(buf.reserve(sizeof(double) * (2 * nk + 2 * size_t(N)) + 256));
   HGL_TRY(bufT.reserve(sizeof(T) * 2 * nk + 256));
-  double* F64 = buf.as<double>();
-  double* AF = F64 + nk;
-  double* Z64 = AF + nk;
-  double* AZ = Z64 + nk;
+  double* AF = buf.as<double>();
+  double* AZ = AF + nk;
   double* t1 = AZ + nk;
   double* t2 = t1 + N;
   T* rhs = bufT.as<T>();
   T* Zt = rhs + nk;
   HGL_TRY(h->ws_z64.reserve(sizeof(double) * size_t(std::max(E, 1)) * k));
   double* Zedge = h->ws_z64.as<double>();
-  const ColShape cs = pick_shape(k, 8, {F64}, {int64_t(k)});
   const int blocks = int(std::min<int64_t>((int64_t(nk) + 255) / 256, 65535));
 
   prof_begin(h, kProfGrad, s);
-  launch(h, -1, k_to_f64<T>, dim3(blocks), dim3(256), 0, s, int64_t(N), k, F, ldf, F64);
-  HGL_HIP(hipGetLastError());
   // (a, b) pairs for the products: A X = 0 X - (-1) S H Z; M X = (1+1/lam) X - (1/lam) S H Z
   DevBuf& abA = h->ws_extra[3];
   DevBuf& abM = h->ws_extra[4];
@@ -269,12 +257,17 @@ static int run_grad(hgl_handle* h, double lam, double mu, const T* F, int64_t ld
     HGL_HIP(hipMemcpyAsync(abM.p, h->pinned_d + 2 * h->G, 16 * size_t(h->G), hipMemcpyHostToDevice, s));
     HGL_HIP(hipStreamSynchronize(s));
   }
-  auto apply64 = [&](const double* X, double* Out, const DevBuf& ab) -> int {
-    HGL_TRY((launch_spmm_edge<double, double>(h, X, k, Zedge, k, k, cs, Gate{}, s)));
-    return launch_spmm_vertex<double, double>(h, VMode::Apply, X, k, Zedge, k, nullptr, 0, Out, k,
-                                               ab.as<double>(), ab.as<double>() + h->G, nullptr, k, cs, Gate{}, s);
+  // A X in FP64 from X in the caller's type: the edge gather accumulates in
+  // FP64 (exact products of the stored values), the vertex gather takes no
+  // X (a = 0 for A)
+  auto applyA = [&](const T* X, int64_t ldx, double* Out) -> int {
+    const ColShape csa = pick_shape(k, 8, {X, Zedge, Out}, {ldx, int64_t(k)});
+    HGL_TRY((launch_spmm_edge<T, double>(h, X, ldx, Zedge, k, k, csa, Gate{}, s)));
+    return launch_spmm_vertex<double, double>(h, VMode::Apply, nullptr, 0, Zedge, k, nullptr, 0, Out, k,
+                                               abA.as<double>(), abA.as<double>() + h->G, nullptr, k, csa, Gate{},
+                                               s);
   };
-  HGL_TRY(apply64(F64, AF, abA));
+  HGL_TRY(applyA(F, ldf, AF));
   // adjoint right-hand side: G, or for the objective R = Y - M F from the FP64
   // residual pass (accumulated in FP64, so the small difference keeps its
   // digits); then Z' = M^-1 R and Z = -2 lambda Z' (M^-1 is linear), so the
@@ -298,9 +291,7 @@ static int run_grad(hgl_handle* h, double lam, double mu, const T* F, int64_t ld
   int st = cg_run(h, lams.data(), adj, rhs_ptr, ld_rhs, Zdst, ldzd, k, iters_host, relres_host, nullptr, s);
   if (st < 0) return st;
   prof_begin(h, kProfGrad, s);
-  launch(h, -1, k_to_f64<T>, dim3(blocks), dim3(256), 0, s, int64_t(N), k, Zdst, ldzd, Z64);
-  HGL_HIP(hipGetLastError());
-  HGL_TRY(apply64(Z64, AZ, abA));
+  HGL_TRY(applyA(Zdst, ldzd, AZ));
   // the contractions read F and Z in the caller's type (FP32 -> FP64 is exact)
   launch(h, -1, k_vertex_terms<T>, dim3((N + 3) / 4), dim3(kBlock), 0, s, N, k, h->s64, F, ldf,
          static_cast<const double*>(AF), static_cast<const T*>(Zdst), ldzd, static_cast<const double*>(AZ), t1, t2);

@@ -183,7 +183,8 @@ struct VertexArgs {
   const double* b_seg;
 };
 
-// MODE 0: Out = a X - b s H Z.  MODE 1: same + partial <X, Out>.
+// MODE 0: Out = a X - b s H Z (X may be null when a = 0: Out = -b s H Z).
+// MODE 1: same + partial <X, Out>.
 // MODE 2: Out = Y - (a X - b s H Z), partial <Out, Out>, all in TZ (FP64).
 // MODE 3 (CG step with X = P): Q = a P - b s H Z stays in registers;
 // F += alpha P, R -= alpha Q (u.F, u.R), partial <R, R> of the new R.
@@ -229,7 +230,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
       const int eb = s_ptr[r - r0], ee = s_ptr[r - r0 + 1];
       if (ee - eb > kLongRow) continue;  // finished by its chunks
       T x[V], o[V];
-      load_row<V>(X + int64_t(r) * ldx + col, x);  // independent of the gather: issue first
+      // independent of the gather: issued first (MODE 0 may have no X: a = 0)
+      if (MODE != 0 || X) {
+        load_row<V>(X + int64_t(r) * ldx + col, x);
+      } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) x[i] = T(0);
+      }
       T fv[V], rv[V];
       if constexpr (MODE == 3) {
         load_row<V>(u.F + int64_t(r) * u.ldf + col, fv);
@@ -347,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex_finish(
   const int g = va.long_seg[slot];
   const TZ a = TZ(va.a_seg[g]), bb = TZ(va.b_seg[g]);
   const TZ sr = s[r];
-  const TZ x = TZ(X[int64_t(r) * ldx + c]);
+  const TZ x = (MODE != 0 || X) ? TZ(X[int64_t(r) * ldx + c]) : TZ(0);
   double d = 0.0;
   if constexpr (MODE == 2) {
     TZ ri = TZ(Y[int64_t(r) * ldy + c]) - (a * x - bb * sr * sum);
