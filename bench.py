@@ -410,7 +410,9 @@ def bench_learn(a):
     nv, mv = prof["vertex_gather"]
     roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_step"])
     cfg = {"workload": "weight_learning", "N": p.N, "E": p.E, "nnz": p.nnz, "k": k, "lambda": p.lam, "mu": mu,
-           "eta": eta, "cg_iters_last": recs[-1]["cg_iters"], "adjoint_iters_last": recs[-1]["adjoint_iters"]}
+           "eta": eta, "cg": "f32 vectors, fp64 inner products, residual replacement at convergence checks; "
+                             "forward solve, adjoint solve, FP64 gradient contractions, simplex projection per step",
+           "cg_iters_last": recs[-1]["cg_iters"], "adjoint_iters_last": recs[-1]["adjoint_iters"]}
     return _line("projected-gradient steps/s", a.steps / dt, "steps/s", a.steps, a.warmup, 1e3 * dt / a.steps,
                  "f32", cfg, roof, {"kernel_ms": _breakdown(
                      h, lambda: learn_weights(h, Y, p.lam, mu, 1, wl, eta=eta, tol=tol), 1)})

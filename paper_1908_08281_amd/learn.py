@@ -42,15 +42,18 @@ class HypergraphSolve(torch.autograd.Function):
 
 
 def learn_weights(handle, Y: torch.Tensor, lam: float, mu: float, steps: int, w0: torch.Tensor,
-                  eta: float | None = None, tol: float = 1e-6, mode: str = "f32", history: bool = False):
+                  eta: float | None = None, tol: float = 1e-6, mode: str = "f32", history: bool = False,
+                  rr_period: int = 0):
     """Projected-gradient descent on the simplex for the adaptive-weight
     objective.  eta None: fixed step 0.5 ||w0||_inf / ||g0 - mean(g0)||_inf
-    chosen at step 0.  Returns (w, per-step records)."""
+    chosen at step 0.  rr_period: periodic residual replacement of the
+    forward solves (0: only at the claim checks, which verify every column's
+    FP64 residual anyway).  Returns (w, per-step records)."""
     w = w0.clone()
     recs = []
     for t in range(steps):
         hgl.set_weights(handle, w)
-        F, iters, rel, st = hgl.cg_solve(handle, lam, Y, mode=mode, tol=tol)
+        F, iters, rel, st = hgl.cg_solve(handle, lam, Y, mode=mode, tol=tol, rr_period=rr_period)
         g, _, ait, _ = hgl.weight_grad(handle, lam, F, Y=Y, mu=mu, mode=mode, tol=tol)
         if eta is None:
             gc = g - g.mean()
