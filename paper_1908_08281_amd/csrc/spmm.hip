@@ -188,8 +188,10 @@ struct VertexArgs {
 // MODE 2: Out = Y - (a X - b s H Z), partial <Out, Out>, all in TZ (FP64).
 // MODE 3 (CG step with X = P): Q = a P - b s H Z stays in registers;
 // F += alpha P, R -= alpha Q (u.F, u.R), partial <R, R> of the new R.
+// At least 5 waves per SIMD: the fused step (MODE 3) with its row prefetch
+// then fits in 96 VGPRs without spilling; the other modes use fewer anyway.
 template <class T, class TZ, int GL, int V, int MODE>
-__global__ __launch_bounds__(kBlock) void k_spmm_vertex(
+__global__ __launch_bounds__(kBlock, 5) void k_spmm_vertex(
     VertexArgs va, const TZ* __restrict__ s, const T* __restrict__ X, int64_t ldx,
     const TZ* __restrict__ Z, int64_t ldz, const T* __restrict__ Y, int64_t ldy, T* __restrict__ Out,
     int64_t ldo, double* __restrict__ part, TZ* __restrict__ chunk_part, int k, Gate gate, UpdArgs<T> u) {
@@ -212,6 +214,26 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
     // one coalesced round trip instead of two dependent ones per row
     __shared__ int32_t s_ptr[kTileRows + 1];
     __shared__ int32_t s_idx[kStageIdx];
+    // the row streams (X; F and R in MODE 3) do not depend on the gather.
+    // MODE 3 issues each group's first row before the staging and each
+    // further row while the group gathers the row before it; the other modes
+    // keep their registers (and so their occupancy) and load a row when they
+    // reach it.  MODE 0 may have no X (a = 0).
+    constexpr bool kAhead = MODE == 3;
+    T x[V] = {}, fv[V] = {}, rv[V] = {};
+    auto fetch = [&](int r, T (&xx)[V], T (&ff)[V], T (&rr)[V]) {
+      if (MODE != 0 || X) {
+        load_row<V>(X + int64_t(r) * ldx + col, xx);
+      } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) xx[i] = T(0);
+      }
+      if constexpr (MODE == 3) {
+        load_row<V>(u.F + int64_t(r) * u.ldf + col, ff);
+        load_row<V>(u.R + int64_t(r) * u.ldr + col, rr);
+      }
+    };
+    if (kAhead && r0 + grp < r1 && colok) fetch(r0 + grp, x, fv, rv);
     const int nr = r1 - r0;
     for (int i = threadIdx.x; i <= nr; i += kBlock) s_ptr[i] = va.vtx_ptr[r0 + i];
     __syncthreads();
@@ -228,55 +250,58 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex(
     }
     for (int r = r0 + grp; r < r1 && colok; r += GPB) {
       const int eb = s_ptr[r - r0], ee = s_ptr[r - r0 + 1];
-      if (ee - eb > kLongRow) continue;  // finished by its chunks
-      T x[V], o[V];
-      // independent of the gather: issued first (MODE 0 may have no X: a = 0)
-      if (MODE != 0 || X) {
-        load_row<V>(X + int64_t(r) * ldx + col, x);
+      T xn[V] = {}, fn[V] = {}, rn[V] = {};
+      if constexpr (kAhead) {
+        if (r + GPB < r1) fetch(r + GPB, xn, fn, rn);
       } else {
-#pragma unroll
-        for (int i = 0; i < V; ++i) x[i] = T(0);
+        fetch(r, x, fv, rv);
       }
-      T fv[V], rv[V];
-      if constexpr (MODE == 3) {
-        load_row<V>(u.F + int64_t(r) * u.ldf + col, fv);
-        load_row<V>(u.R + int64_t(r) * u.ldr + col, rv);
-      }
-      const TZ sr = s[r];
-      TZ acc[V];
+      if (ee - eb <= kLongRow) {  // longer rows are finished by their chunks
+        T o[V];
+        const TZ sr = s[r];
+        TZ acc[V];
 #pragma unroll
-      for (int i = 0; i < V; ++i) acc[i] = TZ(0);
-      if (ee - base <= staged)
-        gather_rows<V>(Z, ldz, s_idx, eb - base, ee - base, col, acc);
-      else
-        gather_rows<V>(Z, ldz, va.vtx_edge, eb, ee, col, acc);
-      if constexpr (MODE == 2) {
-        T y[V];
-        load_row<V>(Y + int64_t(r) * ldy + col, y);
+        for (int i = 0; i < V; ++i) acc[i] = TZ(0);
+        if (ee - base <= staged)
+          gather_rows<V>(Z, ldz, s_idx, eb - base, ee - base, col, acc);
+        else
+          gather_rows<V>(Z, ldz, va.vtx_edge, eb, ee, col, acc);
+        if constexpr (MODE == 2) {
+          T y[V];
+          load_row<V>(Y + int64_t(r) * ldy + col, y);
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-          TZ ri = TZ(y[i]) - (a * TZ(x[i]) - bb * sr * acc[i]);
-          dot[i] += double(ri) * double(ri);
-          o[i] = T(ri);
-        }
-      } else {
+          for (int i = 0; i < V; ++i) {
+            TZ ri = TZ(y[i]) - (a * TZ(x[i]) - bb * sr * acc[i]);
+            dot[i] += double(ri) * double(ri);
+            o[i] = T(ri);
+          }
+        } else {
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-          TZ q = a * TZ(x[i]) - bb * sr * acc[i];
-          o[i] = T(q);
-          if constexpr (MODE == 1) dot[i] += double(x[i]) * double(o[i]);
-          if constexpr (MODE == 3) {
-            fv[i] += al[i] * x[i];
-            rv[i] -= al[i] * o[i];
-            dot[i] += double(rv[i]) * double(rv[i]);
+          for (int i = 0; i < V; ++i) {
+            TZ q = a * TZ(x[i]) - bb * sr * acc[i];
+            o[i] = T(q);
+            if constexpr (MODE == 1) dot[i] += double(x[i]) * double(o[i]);
+            if constexpr (MODE == 3) {
+              fv[i] += al[i] * x[i];
+              rv[i] -= al[i] * o[i];
+              dot[i] += double(rv[i]) * double(rv[i]);
+            }
           }
         }
+        if constexpr (MODE == 3) {
+          store_row<V>(u.F + int64_t(r) * u.ldf + col, fv);
+          store_row<V>(u.R + int64_t(r) * u.ldr + col, rv);
+        } else {
+          store_row<V>(Out + int64_t(r) * ldo + col, o);
+        }
       }
-      if constexpr (MODE == 3) {
-        store_row<V>(u.F + int64_t(r) * u.ldf + col, fv);
-        store_row<V>(u.R + int64_t(r) * u.ldr + col, rv);
-      } else {
-        store_row<V>(Out + int64_t(r) * ldo + col, o);
+      if constexpr (kAhead) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          x[i] = xn[i];
+          fv[i] = fn[i];
+          rv[i] = rn[i];
+        }
       }
     }
     if constexpr (MODE != 0) {
