@@ -1,5 +1,6 @@
-"""Algorithm 1 (randomized SVD via subspace iteration), the diagonal-block
-tessellation (eq. 11) and the block inverse (eq. 15), FP64.
+"""Algorithm 1 (randomized SVD via subspace iteration), its power-scheme
+variant (eq. 10), the diagonal-block tessellation (eq. 11) and the block
+inverse (eq. 15), FP64.
 
 Readings:
 * the paper writes pi both for the oversampling (l = k + pi) and for the number
@@ -51,11 +52,37 @@ def randomized_svd(X: np.ndarray, Omega: np.ndarray, q: int):
     return S @ Ut, sigma, Vt.T
 
 
-def block_inverse_factors(A_blocks, omegas, k: int, q: int):
-    """Per block: leading-k (U_b, sigma_b) of Algorithm 1 on A_bb."""
+def power_sketch(X: np.ndarray, Omega: np.ndarray, q: int) -> np.ndarray:
+    """Eq. (10): Y = (X X')^q X Omega, formed by repeated products with no
+    orthonormalisation in between (the exponent is the number of iterations
+    q; the paper reuses the oversampling's symbol for it)."""
+    Y = X @ Omega
+    for _ in range(q):
+        Y = X @ (X.T @ Y)
+    return Y
+
+
+def randomized_svd_power(X: np.ndarray, Omega: np.ndarray, q: int):
+    """Algorithm 1 with steps 2-3 replaced by eq. (10): S is an orthonormal
+    basis of range((X X')^q X Omega) from one QR factorisation, then B = S'X,
+    B = Ut Sigma V', U = S Ut as in steps 4-6.  In exact arithmetic S spans
+    the subspace of Algorithm 1; in floating point the directions of small
+    singular values are lost to rounding as q grows (the paper's caveat)."""
+    S = orth(power_sketch(X, Omega, q))
+    B = S.T @ X
+    Ut, sigma, Vt = np.linalg.svd(B, full_matrices=False)
+    return S @ Ut, sigma, Vt.T
+
+
+def block_inverse_factors(A_blocks, omegas, k: int, q: int, scheme: str = "subspace"):
+    """Per block: leading-k (U_b, sigma_b) of Algorithm 1 on A_bb
+    (scheme "power": with the sketch of eq. (10) in place of steps 2-3)."""
+    if scheme not in ("subspace", "power"):
+        raise ValueError(f"unknown scheme {scheme!r}")
+    svd = randomized_svd if scheme == "subspace" else randomized_svd_power
     out = []
     for Ab, Om in zip(A_blocks, omegas):
-        U, s, _ = randomized_svd(Ab, Om, q)
+        U, s, _ = svd(Ab, Om, q)
         kk = min(k, s.size)
         out.append((U[:, :kk], s[:kk]))
     return out

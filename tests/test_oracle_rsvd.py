@@ -48,6 +48,73 @@ def test_subspace_equals_power_scheme_range():
     assert not np.allclose(U1 @ U1.T, Sp @ Sp.T, atol=1e-4)
 
 
+def _spectrum(m, base, seed):
+    """Non-symmetric m x m matrix with singular values base**i (i = 0 .. m-1)."""
+    rng = synth.rng_for(seed)
+    Q1, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    sv = base ** np.arange(m)
+    return Q1 @ np.diag(sv) @ Q2.T, sv
+
+
+@pytest.mark.parametrize("q", [0, 1, 3])
+def test_power_sketch_is_eq10(q):
+    """Eq. (10) literally: (X X')^q X Omega, for a non-symmetric X (X'X in place
+    of X X', or a dropped X, fails)."""
+    X, _ = _spectrum(40, 0.95, 12)
+    Om = synth.rng_for(13).standard_normal((40, 6))
+    want = np.linalg.matrix_power(X @ X.T, q) @ X @ Om
+    got = rsvd.power_sketch(X, Om, q)
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_power_scheme_exact_rank_recovery(q):
+    X = _lowrank(120, 9, 1)
+    Om = synth.rng_for(2).standard_normal((120, 14))
+    U, s, V = rsvd.randomized_svd_power(X, Om, q)
+    k = 9
+    approx = U[:, :k] @ np.diag(s[:k]) @ V[:, :k].T
+    assert np.linalg.norm(X - approx) / np.linalg.norm(X) < 1e-11
+    assert np.allclose(s[:k], np.linalg.svd(X, compute_uv=False)[:k], rtol=1e-11)
+
+
+def test_power_scheme_matches_algorithm1_on_a_mild_spectrum():
+    """Same subspace in exact arithmetic, so with a slowly decaying spectrum the
+    two schemes agree to rounding, truncation error included."""
+    X, sv = _spectrum(60, 0.9, 11)
+    Om = synth.rng_for(14).standard_normal((60, 12))
+    U1, s1, _ = rsvd.randomized_svd(X, Om, 2)
+    U2, s2, _ = rsvd.randomized_svd_power(X, Om, 2)
+    assert np.allclose(s1, s2, rtol=1e-10)
+    assert np.allclose(U1[:, :8] @ U1[:, :8].T, U2[:, :8] @ U2[:, :8].T, atol=1e-9)
+    # the truncation error itself is far above that: the test compares something
+    assert np.abs(s1[:8] - sv[:8]).max() > 1e-4
+
+
+def test_power_scheme_loses_small_directions():
+    """The paper's caveat for eq. (10): without the orthonormalisation between
+    products, directions whose singular values fall by more than the working
+    precision over 2q+1 products are lost; Algorithm 1 keeps them."""
+    X, sv = _spectrum(60, 0.5, 11)
+    Om = synth.rng_for(15).standard_normal((60, 12))
+    _, s1, _ = rsvd.randomized_svd(X, Om, 4)
+    _, s2, _ = rsvd.randomized_svd_power(X, Om, 4)
+    assert np.max(np.abs(s1[:8] - sv[:8]) / sv[:8]) < 1e-12
+    assert np.max(np.abs(s2[:8] - sv[:8]) / sv[:8]) > 0.1
+
+
+def test_block_factors_scheme():
+    X, _ = _spectrum(30, 0.8, 16)
+    A = 0.5 * (X + X.T)
+    Om = synth.rng_for(17).standard_normal((30, 8))
+    (Up, sp), = rsvd.block_inverse_factors([A], [Om], 6, 2, scheme="power")
+    U, s, _ = rsvd.randomized_svd_power(A, Om, 2)
+    assert np.array_equal(sp, s[:6]) and np.array_equal(Up, U[:, :6])
+    with pytest.raises(ValueError):
+        rsvd.block_inverse_factors([A], [Om], 6, 2, scheme="qr-free")
+
+
 def test_ritz_values_interlace():
     p = synth.random_small(7, 80, 60, 2, 6)
     H = lap.incidence_dense(p.N, p.E, p.edge_ptr, p.edge_vtx)
