@@ -13,6 +13,9 @@ Workloads (synthetic, seeded; see synth/):
              E = 0.75 N, lambda=1), k=64, p=10, q=2, BF16 sketch; a step =
              Algorithm 1 on all blocks; value = blocks/s.  The refined solve
              (block inverse + PCG, Y N x 50 at 5%) is timed beside it.
+  rsvd_power the rsvd workload with the power-scheme sketch of eq. 10 in
+             place of Algorithm 1's steps 2-3; also reports the kept
+             singular values' deviation from Algorithm 1 on the same sketch.
   learn      G1, N=100,000, E=80,000, Y 100,000 x 500 at 5%, lambda=1,
              mu=0.01; a step = one outer projected-gradient step (forward CG,
              adjoint gradient, projection, re-weighting); value = steps/s.
@@ -310,7 +313,7 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
                  value, "RHS/s", a.steps, a.warmup, ms, mode, cfg, roof, extra)
 
 
-def bench_rsvd(a):
+def bench_rsvd(a, scheme="subspace"):
     import torch
 
     import synth
@@ -323,13 +326,14 @@ def bench_rsvd(a):
     ep, ev, w = _upload(p, dev)
     h = hgl.build_laplacian(ep, ev, w, p.N)
     om = torch.from_numpy(synth.gaussian_sketch(p.N, l, 11)[0].view(np.int16).copy()).to(dev)
+    run = lambda: hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om, scheme=scheme)  # noqa: E731
     for _ in range(a.warmup):
-        hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om)
+        run()
     hgl.profile(h, True, kinds=["rsvd_gemm"])
-    dt, _ = _timed(lambda: hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om), a.steps, 0)
+    dt, _ = _timed(run, a.steps, 0)
     prof = hgl.profile_read(h)
     hgl.profile(h, False)
-    breakdown = _breakdown(h, lambda: hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om), max(2, a.steps // 5))
+    breakdown = _breakdown(h, run, max(2, a.steps // 5))
     sizes = np.diff(p.blocks).astype(np.float64)
     gemm_flops = float(np.sum(2.0 * sizes * sizes * l))           # one product A_bb S per block
     n_g, ms_g = prof["rsvd_gemm"]
@@ -342,19 +346,30 @@ def bench_rsvd(a):
     Y = torch.from_numpy(p.Y).to(dev, torch.float32)
     tol = 1e-6 / (1 + 1 / p.lam)
     t0 = time.perf_counter()
-    F, it, rel, sig, st = hgl.block_rsvd_invert(h, p.lam, p.blocks, Y, k, pp, q, omega=om, refine_tol=tol)
+    F, it, rel, sig, st = hgl.block_rsvd_invert(h, p.lam, p.blocks, Y, k, pp, q, omega=om, refine_tol=tol,
+                                                scheme=scheme)
     torch.cuda.synchronize()
     t_inv = time.perf_counter() - t0
     t0 = time.perf_counter()
     F2, it2, rel2, st2 = hgl.cg_solve(h, p.lam, Y, tol=tol)
     torch.cuda.synchronize()
     t_cg = time.perf_counter() - t0
-    cfg = {"workload": "block_rsvd", "N": p.N, "blocks": nb, "block_rows": "U[500,1500]", "k": k, "p": pp, "q": q,
-           "sketch": "bf16 A_bb, split-bf16 basis, fp32 accumulation, fp64 CholQR2 and Jacobi"}
+    cfg = {"workload": "block_rsvd" if scheme == "subspace" else "block_rsvd_power", "N": p.N, "blocks": nb,
+           "block_rows": "U[500,1500]", "k": k, "p": pp, "q": q,
+           "sketch": "bf16 A_bb, split-bf16 basis, fp32 accumulation, fp64 CholQR2 and Jacobi",
+           "scheme": "Algorithm 1 (orthonormalised after every product)" if scheme == "subspace" else
+                     "power scheme of eq. 10 (2q+1 products, one CholQR2)"}
     extra = {"roofline_hbm": hbm, "kernel_ms": breakdown,
              "refined_solve": {"nrhs": Y.shape[1], "pcg_iters": int(it.max()), "seconds": round(t_inv, 4),
                                "converged": st == 0 and bool(np.all(rel <= tol)),
                                "plain_cg_iters": int(it2.max()), "plain_cg_seconds": round(t_cg, 4)}}
+    if scheme == "power":
+        # accuracy against Algorithm 1 on the same sketch: relative deviation
+        # of the kept singular values, worst block
+        _, s_pow = run()
+        _, s_sub = hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om)
+        dev_rel = ((s_pow - s_sub).abs() / s_sub.abs()).max().item()
+        extra["sigma_vs_algorithm1"] = {"max_rel_dev": dev_rel, "blocks": nb, "k": k}
     if not a.no_cpu:
         from threadpoolctl import threadpool_limits
 
@@ -370,14 +385,16 @@ def bench_rsvd(a):
                 P = np.zeros((p.N, o1 - o0))
                 P[o0:o1] = np.eye(o1 - o0)
                 Ab = op.adjacency_apply(P)[o0:o1]
-                rsvd.randomized_svd(Ab, vals[o0:o1], q)
+                (rsvd.randomized_svd if scheme == "subspace" else rsvd.randomized_svd_power)(Ab, vals[o0:o1], q)
                 done += 1
                 if time.perf_counter() - t0 > 20.0:
                     break
             dtc = time.perf_counter() - t0
         extra["cpu_baseline"] = {"value": round(done / dtc, 3), "unit": "blocks/s", "cores": 1, "kind": "oracle",
-                                 "sample": f"first {done} of {nb} blocks, FP64 Algorithm 1 with Householder QR "
-                                           f"(block extraction included), one thread, {dtc:.1f} s"}
+                                 "sample": f"first {done} of {nb} blocks, FP64 "
+                                           + ("Algorithm 1" if scheme == "subspace" else "eq. 10 power scheme")
+                                           + f" with Householder QR (block extraction included), one thread, "
+                                             f"{dtc:.1f} s"}
     return _line("rSVD blocks/s", a.steps * nb / dt, "blocks/s", a.steps, a.warmup, ms, "bf16", cfg, roof, extra)
 
 
@@ -425,7 +442,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workload", default="multi_rhs",
-                    help="multi_rhs (default), small, rsvd, learn, batch, or a comma list")
+                    help="multi_rhs (default), small, rsvd, rsvd_power, learn, batch, or a comma list")
     ap.add_argument("--rr-period", type=int, default=0)
     ap.add_argument("--tune", type=int, default=1,
                     help="1: column shapes of the CG kernels picked by the library's autotuner (default)")
@@ -478,6 +495,8 @@ def main():
             out = bench_cg(a, "batched_64_graphs", p, "f32", 1e-6 / (1 + 1 / 0.5))
         elif wl == "rsvd":
             out = bench_rsvd(a)
+        elif wl == "rsvd_power":
+            out = bench_rsvd(a, scheme="power")
         elif wl == "learn":
             out = bench_learn(a)
         else:

@@ -231,6 +231,21 @@ enum hgl_sketch {
   HGL_SKETCH_F64 = 1    /* every product in FP64 (reference precision) */
 };
 
+/* How the basis S is formed (paper, section 3, eq. 10 and Algorithm 1). */
+enum hgl_rsvd_scheme {
+  HGL_RSVD_SUBSPACE = 0, /* Algorithm 1: orth() after every product (default) */
+  HGL_RSVD_POWER = 1     /* eq. 10: Y = (A_bb A_bb')^q A_bb Omega by 2q+1
+                            products with nothing in between (the next
+                            product's operand is Y itself, rounded to the
+                            sketch's operand format), then one two-pass orth().
+                            Fewer launches; the paper warns it is more
+                            sensitive to rounding, and with a fast-decaying
+                            spectrum the directions of small singular values
+                            are lost as q grows.  The final CholQR then sees
+                            an ill-conditioned Gram matrix and may need its
+                            shifted retry, or fail with HGL_ECHOLQR. */
+};
+
 typedef struct hgl_rsvd_opts {
   int32_t k;          /* rank kept per block (>= 1) */
   int32_t p;          /* oversampling: sketch width l = k + p (l <= 96) */
@@ -240,6 +255,7 @@ typedef struct hgl_rsvd_opts {
   double refine_tol;  /* hgl_block_rsvd_invert: target relres of the refinement */
   int32_t max_refine; /* hgl_block_rsvd_invert: preconditioned CG iteration limit */
   int32_t chunk;      /* as hgl_cg_opts.chunk */
+  int32_t scheme;     /* enum hgl_rsvd_scheme (0: Algorithm 1) */
 } hgl_rsvd_opts;
 
 /*

@@ -34,11 +34,13 @@ class CgOpts(C.Structure):
 class RsvdOpts(C.Structure):
     _fields_ = [("k", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("sketch", C.c_int32),
                 ("seed", C.c_uint64), ("refine_tol", C.c_double), ("max_refine", C.c_int32),
-                ("chunk", C.c_int32)]
+                ("chunk", C.c_int32), ("scheme", C.c_int32)]
 
 
 HGL_SKETCH_BF16 = 0
 HGL_SKETCH_F64 = 1
+HGL_RSVD_SUBSPACE = 0
+HGL_RSVD_POWER = 1
 
 
 P = C.c_void_p

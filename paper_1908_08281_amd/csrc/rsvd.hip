@@ -498,6 +498,18 @@ __global__ __launch_bounds__(kDense) void k_chol_inv(BlockMeta bm, const int32_t
   }
 }
 
+// Li <- identity on each block's l x l corner (zero elsewhere in LP x LP):
+// k_apply_rinv with it lays Y out as the next product's operand unchanged
+// (the power scheme of eq. 10, which has no orthonormalisation between
+// products).
+__global__ __launch_bounds__(256) void k_identity_factor(int64_t n, int LP, int l, double* __restrict__ Li) {
+  for (int64_t q = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; q < n; q += int64_t(gridDim.x) * blockDim.x) {
+    const int r = int(q % (int64_t(LP) * LP));
+    const int i = r / LP, j = r - i * LP;
+    Li[q] = (i == j && i < l) ? 1.0 : 0.0;
+  }
+}
+
 // S = Y L^-T on a 64-row tile: S[r][j] = sum_{i<=j} Y[r][i] Linv[j][i] (j < l),
 // zero for j >= l and rows >= n_b.  Writes S (row-major) and ST (transposed,
 // the next GEMM operand: BF16 hi/lo pair in the BF16 mode).  Thread (g, h)
@@ -1145,7 +1157,7 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
   launch(h, -1, k_sketch_to_st<TST>, dim3(64, R.nb), dim3(256), 0, s, R.bm, om, R.ST.as<TST>(),
                      R.y_elems);
   HGL_HIP(hipGetLastError());
-  // 3. Y = A Omega, S = orth(Y); q subspace iterations
+  // 3. Y = A Omega, S = orth(Y); q subspace iterations (or the power scheme)
   auto gemm = [&]() -> int {
     prof_begin(h, kProfGemm, s);
     const int st = launch_gemm(h, R, s);
@@ -1159,10 +1171,36 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
   // the next product and the final CholQR2 act on the subspace it spans.
   auto orth = [&](bool last) { return cholqr<TY, TST>(h, R, s, (last || R.f64) ? 2 : 1); };
   HGL_TRY(gemm());
-  HGL_TRY(orth(o->q == 0));
-  for (int i = 0; i < 2 * o->q; ++i) {
-    HGL_TRY(gemm());
-    HGL_TRY(orth(i == 2 * o->q - 1));
+  if (o->scheme == HGL_RSVD_POWER) {
+    // eq. 10: Y = (A A')^q A Omega (A_bb is symmetric: 2q + 1 products with
+    // A), each product's result laid out unchanged as the next operand, and
+    // one two-pass CholQR of the last Y
+    if (o->q > 0) {
+      const int64_t n = int64_t(R.nb) * R.LP * R.LP;
+      launch(h, -1, k_identity_factor, dim3(int(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, s, n,
+             R.LP, R.l, R.Li.as<double>());
+      HGL_HIP(hipGetLastError());
+    }
+    const int n_items = int(R.item_b.size());
+    for (int i = 0; i < 2 * o->q; ++i) {
+      prof_begin(h, kProfQr, s);
+      HGL_TRY(with_lp(R.LP, [&](auto c) {
+        constexpr int LP = decltype(c)::value;
+        launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.Y.as<TY>(),
+               R.Li.as<double>(), R.S.as<TY>(), R.ST.as<TST>(), R.y_elems);
+        return HGL_OK;
+      }));
+      HGL_HIP(hipGetLastError());
+      prof_end(h, s);
+      HGL_TRY(gemm());
+    }
+    HGL_TRY(orth(true));
+  } else {
+    HGL_TRY(orth(o->q == 0));
+    for (int i = 0; i < 2 * o->q; ++i) {
+      HGL_TRY(gemm());
+      HGL_TRY(orth(i == 2 * o->q - 1));
+    }
   }
   // 4. W = A S; B B' = W'W; Jacobi; U = S U~
   HGL_TRY(gemm());  // W in R.Y, basis S in R.S
@@ -1193,6 +1231,7 @@ static int check_opts(hgl_handle* h, int n_blocks, const int32_t* offs, const hg
   HGL_CHECK_ARG(o->k >= 1 && o->p >= 0 && o->q >= 0, "need k >= 1, p >= 0, q >= 0");
   HGL_CHECK_ARG(o->k + o->p <= kMaxLP, "k + p must be <= %d", kMaxLP);
   HGL_CHECK_ARG(o->sketch == HGL_SKETCH_BF16 || o->sketch == HGL_SKETCH_F64, "unknown sketch precision");
+  HGL_CHECK_ARG(o->scheme == HGL_RSVD_SUBSPACE || o->scheme == HGL_RSVD_POWER, "unknown rSVD scheme %d", o->scheme);
   for (int b = 0; b < n_blocks; ++b)
     HGL_CHECK_ARG(offs[b + 1] - offs[b] >= o->k + o->p,
                   "block %d has %d rows, fewer than k + p = %d", b, offs[b + 1] - offs[b], o->k + o->p);

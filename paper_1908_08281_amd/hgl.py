@@ -232,15 +232,16 @@ def cg_solve_batched(h: Handle, lams, Y: torch.Tensor, mode: str = "f32", tol: f
 
 
 SKETCH = {"bf16": _lib.HGL_SKETCH_BF16, "f64": _lib.HGL_SKETCH_F64}
+SCHEME = {"subspace": _lib.HGL_RSVD_SUBSPACE, "power": _lib.HGL_RSVD_POWER}
 
 
 def _offsets(offsets) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
 
 
-def _rsvd_opts(k, p, q, sketch, seed, refine_tol=1e-6, max_refine=500, chunk=0):
+def _rsvd_opts(k, p, q, sketch, seed, refine_tol=1e-6, max_refine=500, chunk=0, scheme="subspace"):
     return _lib.RsvdOpts(int(k), int(p), int(q), SKETCH[sketch], int(seed), float(refine_tol),
-                         int(max_refine), int(chunk))
+                         int(max_refine), int(chunk), SCHEME[scheme])
 
 
 def _omega_ptr(h: Handle, omega, l: int):
@@ -252,13 +253,15 @@ def _omega_ptr(h: Handle, omega, l: int):
     return _ptr(omega)
 
 
-def block_rsvd(h: Handle, offsets, k: int, p: int, q: int, sketch: str = "bf16", omega=None, seed: int = 0):
-    """Algorithm 1 on every diagonal block.  Returns (U [N,k] float32, sigma [n_blocks,k] float64)."""
+def block_rsvd(h: Handle, offsets, k: int, p: int, q: int, sketch: str = "bf16", omega=None, seed: int = 0,
+               scheme: str = "subspace"):
+    """Algorithm 1 on every diagonal block ("power": with the sketch of eq. 10 in place of its
+    steps 2-3).  Returns (U [N,k] float32, sigma [n_blocks,k] float64)."""
     off = _offsets(offsets)
     nb = off.size - 1
     U = torch.empty((h.N, k), dtype=torch.float32, device=h.device)
     sig = torch.empty((nb, k), dtype=torch.float64, device=h.device)
-    opts = _rsvd_opts(k, p, q, sketch, seed)
+    opts = _rsvd_opts(k, p, q, sketch, seed, scheme=scheme)
     with torch.cuda.device(h.device):
         check(lib().hgl_block_rsvd(h.ptr, nb, off.ctypes.data_as(_lib.I32P), C.byref(opts),
                                    _omega_ptr(h, omega, k + p), _ptr(U), _ptr(sig), _stream(h.device)),
@@ -268,7 +271,7 @@ def block_rsvd(h: Handle, offsets, k: int, p: int, q: int, sketch: str = "bf16",
 
 def block_rsvd_invert(h: Handle, lam: float, offsets, Y: torch.Tensor, k: int, p: int, q: int,
                       sketch: str = "bf16", omega=None, seed: int = 0, refine_tol: float = 5e-7,
-                      max_refine: int = 500, chunk: int = 0):
+                      max_refine: int = 500, chunk: int = 0, scheme: str = "subspace"):
     """Block-inverse start + preconditioned CG.  Returns (F, iters, relres, sigma, status)."""
     off = _offsets(offsets)
     nb = off.size - 1
@@ -279,7 +282,7 @@ def block_rsvd_invert(h: Handle, lam: float, offsets, Y: torch.Tensor, k: int, p
     sig = torch.empty((nb, k), dtype=torch.float64, device=h.device)
     iters = np.zeros(nrhs, dtype=np.int32)
     rel = np.zeros(nrhs, dtype=np.float64)
-    opts = _rsvd_opts(k, p, q, sketch, seed, refine_tol, max_refine, chunk)
+    opts = _rsvd_opts(k, p, q, sketch, seed, refine_tol, max_refine, chunk, scheme)
     with torch.cuda.device(h.device):
         st = lib().hgl_block_rsvd_invert(h.ptr, float(lam), nb, off.ctypes.data_as(_lib.I32P), C.byref(opts),
                                          _omega_ptr(h, omega, k + p), _ptr(Y), ldy, _ptr(F), F.stride(0), nrhs,
