@@ -207,6 +207,35 @@ int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg
                          const void* Y, int64_t ldy, void* F, int64_t ldf, int32_t k,
                          int32_t* iters_host, double* relres_host, hipStream_t stream);
 
+/*
+ * The latency path for small hypergraphs (paper, section 4: one query vector
+ * per test image on a graph of a few thousand vertices, solved by CG,
+ * eqs. 16-20).  Solves (I + L/lambda) F = Y like hgl_cg_solve in the
+ * HGL_CG_F32_F64DOT_RR mode, but each column is one workgroup that runs its
+ * whole solve in a single launch (one launch for all k columns; columns are
+ * independent, so many queries run side by side).
+ *  Y, F: device, N x k FP32 row-major with leading dimensions ldy, ldf >= k.
+ *    F holds the starting guess on entry when opts->x0_given, and the result
+ *    on exit.
+ *  opts: mode must be HGL_CG_F32_F64DOT_RR; tol, max_iter and x0_given as in
+ *    hgl_cg_solve; rr_period, chunk, graph and tune are ignored.  A column's
+ *    recursive residual that reaches tol/2 triggers a recomputation of
+ *    Y - M F with FP64 accumulation; the column finishes when that meets tol
+ *    and otherwise restarts from it.  An all-zero column gives F = 0 and
+ *    relres 0 after 0 iterations.
+ *  iters_host [k], relres_host [k] (nullable, host): iterations and the
+ *    FP64-recomputed relative residual per column.
+ * Needs a single-graph handle and 4 N + 8 E bytes of LDS (rounded; at most
+ * 159 KB, about N + 2E <= 40,000): larger graphs -> HGL_EUNSUPPORTED, as is
+ * the FP64 mode.  Returns HGL_OK, HGL_NOT_CONVERGED (a column reached
+ * max_iter), HGL_EBREAKDOWN (p'Mp <= 0 or not finite, e.g. NaN input) or
+ * HGL_EINVAL (bad arguments).  Uses the handle's workspace (3 N k floats)
+ * and synchronises the stream.
+ */
+int hgl_cg_solve_wg(hgl_handle* h, double lambda, const hgl_cg_opts* opts, const float* Y, int64_t ldy,
+                    float* F, int64_t ldf, int32_t k, int32_t* iters_host, double* relres_host,
+                    hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Block randomized SVD (paper, section 3: Algorithm 1, the tessellation of
  * eq. 11 and the block inverse of eq. 15).

@@ -169,7 +169,7 @@ def apply(h: Handle, lam: float, P: torch.Tensor, out: torch.Tensor | None = Non
 
 def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
         x0: torch.Tensor | None, rr_period: int, chunk: int, batched: bool, graph: bool = False,
-        out: torch.Tensor | None = None, tune: bool = False):
+        out: torch.Tensor | None = None, tune: bool = False, wg: bool = False):
     m = MODES[mode]
     dtype = torch.float64 if m == _lib.HGL_CG_PLAIN_F64 else torch.float32
     _need(Y, dtype, "Y", h.device)
@@ -203,10 +203,10 @@ def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
                                             _ptr(F), F.stride(0), k, iters.ctypes.data_as(_lib.I32P),
                                             rel.ctypes.data_as(_lib.DP), _stream(h.device))
         else:
-            st = lib().hgl_cg_solve(h.ptr, float(lams), C.byref(opts), _ptr(Y), ldy, _ptr(F), F.stride(0), k,
-                                    iters.ctypes.data_as(_lib.I32P), rel.ctypes.data_as(_lib.DP),
-                                    _stream(h.device))
-    check(st, "hgl_cg_solve")
+            fn = lib().hgl_cg_solve_wg if wg else lib().hgl_cg_solve
+            st = fn(h.ptr, float(lams), C.byref(opts), _ptr(Y), ldy, _ptr(F), F.stride(0), k,
+                    iters.ctypes.data_as(_lib.I32P), rel.ctypes.data_as(_lib.DP), _stream(h.device))
+    check(st, "hgl_cg_solve_wg" if wg else "hgl_cg_solve")
     return F, iters.reshape(h.G, k), rel.reshape(h.G, k), st
 
 
@@ -220,6 +220,13 @@ def cg_solve(h: Handle, lam: float, Y: torch.Tensor, mode: str = "f32", tol: flo
     tune: pick the kernels' column shape by timing (cached per handle)."""
     return _cg(h, lam, Y, mode, tol, max_iter, x0, rr_period, chunk, batched=False, graph=graph, out=out,
                tune=tune)
+
+
+def cg_solve_wg(h: Handle, lam: float, Y: torch.Tensor, tol: float = 1e-6, max_iter: int = 1000,
+                x0: torch.Tensor | None = None, out: torch.Tensor | None = None):
+    """The latency path for small graphs: each column's whole FP32 solve runs in one workgroup of
+    one launch (hgl_cg_solve_wg).  Returns (F, iters[1,k], relres[1,k], status) as cg_solve."""
+    return _cg(h, lam, Y, "f32", tol, max_iter, x0, 0, 0, batched=False, out=out, wg=True)
 
 
 def cg_solve_batched(h: Handle, lams, Y: torch.Tensor, mode: str = "f32", tol: float = 1e-6,

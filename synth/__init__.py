@@ -198,6 +198,17 @@ def multi_rhs(seed_offset: int = 0, N: int = 50_000, E: int = 40_000, k: int = 2
                    binary_rhs(N, k, 0.02, s + 1), name=f"g2_N{N}_E{E}_k{k}", tol=1e-6)
 
 
+def single_query(seed_offset: int = 0, N: int = 5867, E: int = 4694, k: int = 1292,
+                 smax: int = 200) -> Problem:
+    """The paper's query shape: one RHS per test image (1292 images) on a graph of
+    m = 5867 vertices (section 4, Table 1); G2 structure (alpha 2.1, sizes
+    [2,200], Zipf 1.1) with E = 0.8 N, Dirichlet(1) w, lambda 0.5, Y at 2%."""
+    s = BASE_SEED + 6 + 1000 * seed_offset
+    ep, ev = powerlaw_hyperedges(N, E, 2.1, 2, smax, 1.1, s)
+    return Problem(N, E, ep, ev, dirichlet_weights(E, s + 2), 0.5,
+                   binary_rhs(N, k, 0.02, s + 1), name=f"g2_N{N}_E{E}_k{k}", tol=1e-6)
+
+
 def tessellated(seed_offset: int = 0, n_blocks: int = 50, lo: int = 500, hi: int = 1500,
                 k_rhs: int = 50) -> Problem:
     """Block rSVD workload: G1 at N = sum of block sizes, E = 0.75 N, w = 1/E, lambda 1, Y at 5%."""
