@@ -314,6 +314,7 @@ static void free_handle(hgl_handle* h) {
   for (DevBuf* b : bufs) b->release();
   for (auto& b : h->ws_extra) b.release();
   h->ws_ab.release();
+  h->wg_tab.release();
   if (h->rsvd_free) h->rsvd_free(h->rsvd_ws);
   if (h->cg_graph) hipGraphExecDestroy(h->cg_graph);
   if (h->capture_stream) hipStreamDestroy(h->capture_stream);

@@ -7,28 +7,38 @@
 // with M = I + L/lambda, in a single launch, and the columns of Y are
 // independent workgroups (one launch solves many queries at once).
 //
-// Per workgroup (column j):
-//   LDS:    Ps[N]  (FP32) = s o p, the scaled direction the edge gather reads;
-//           Z[E]   (FP64) = c_e u_e with u_e = sum_{v in e} s_v p_v (eq. 1).
-//   global: the column's F, R and P in column-contiguous workspaces (each row
-//           is read and written by the thread that owns it).
-// One iteration: edge gather Z and the FP64 partial sum_e c_e u_e^2; one
+// Each thread owns an even share (at most kSlots entries) of each CSR of H,
+// edge-major and vertex-major: 16-bit indices, a bitmask of the entries that
+// end a row, the length of a leading run that continues a row begun in an
+// earlier thread's share, the ordinal of its first row that starts in the
+// share, and the number of following threads that its last row runs into.
+// A gather loads its thread's share (19 independent words from a table that
+// stays in L2) and then works from LDS only.  The vectors f, r, p and the
+// scale s of a thread's kRowsPT vertex rows (v = thread + i * 1024) and c of
+// its kEdgesPT hyperedges stay in registers for the whole solve.
+// LDS holds Ps = s o p (FP64), U / Z over the hyperedges (FP64), H Z over the
+// vertex rows that have hyperedges (FP64), one carry word per thread and the
+// column of Y (FP32, read again by the residual checks).
+//
+// One iteration: the edge gather u_e = sum_{v in e} s_v p_v (each thread
+// sums its share; rows that cross shares are finished by adding the
+// following threads' leading partial sums, in thread order), Z_e = c_e u_e
+// and the FP64 partial sum_e c_e u_e^2 by the hyperedge owners; one
 // workgroup reduction gives p'Mp = a p'p - b sum_e c_e u_e^2 (the split of
 // p'Mp used by the multi-kernel path, a = 1 + 1/lambda, b = 1/lambda) and
-// alpha; the vertex gather forms (Mp)_v = a p_v - b s_v (H Z)_v and applies
-// f += alpha p, r -= alpha Mp; a second reduction gives r'r and beta; the
-// direction update p = r + beta p.  Short rows and hyperedges are summed by
-// one thread each, two at a time with their loads issued together; rows with
-// more than kLongRow hyperedges are split into the handle's chunks of at
-// most kChunk entries and hyperedges with more than kLongEdge members are
-// taken whole, each by a group of 16 lanes with 8 loads in flight per lane.
+// alpha; the vertex gather (H Z)_v the same way; the row owners form
+// (Mp)_v = a p_v - b s_v (H Z)_v and apply f += alpha p, r -= alpha Mp; a
+// second reduction gives r'r and beta; the owners update p = r + beta p.
 // Every sum has a fixed order, so results are bitwise repeatable.
 //
 // Convergence follows the FP32 mode of the multi-kernel solver: when the
-// recursive residual reaches claim * tol, the true residual Y - M F is
-// recomputed with FP64 accumulation; the column finishes if it meets tol,
-// and otherwise restarts from it (beta = 0).
+// recursive residual reaches tol/2, the true residual Y - M F is recomputed
+// with FP64 accumulation (s o f in FP64); the column finishes if it meets
+// tol, and otherwise restarts from it (beta = 0).
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
+#include <vector>
 
 #include "common.h"
 
@@ -37,37 +47,24 @@ namespace {
 
 constexpr int kWg = 1024;
 constexpr int kWgWaves = kWg / 64;
-constexpr int kWgGather = 8;  // gathered entries in flight per thread and row
-constexpr int kGrp = 16;      // lanes of a group summing one long row chunk or hyperedge
-constexpr int kGroups = kWg / kGrp;
-constexpr int kPerLane = kChunk / kGrp;  // entries in flight per lane of a group
-// dynamic LDS of one workgroup (Ps and Z); the rest of the 160 KB holds the
-// reduction scratch
+constexpr int kSlots = 32;             // CSR entries per thread (per CSR)
+constexpr int kSlotW = kSlots / 2;     // words of packed 16-bit indices
+constexpr int kTabCsr = kSlotW + 3;    // table words per thread and CSR
+constexpr int kRowsPT = 6;             // vertex rows owned per thread (N <= 6144)
+constexpr int kEdgesPT = 6;            // hyperedges owned per thread (E <= 6144)
 constexpr size_t kWgLdsMax = 159 * 1024;
 
 struct WgArgs {
-  int32_t N, E;
-  const int32_t* edge_ptr;
-  const int32_t* edge_vtx;
-  const int32_t* vtx_ptr;
-  const int32_t* vtx_edge;
+  int32_t N, E, nq;
+  const uint32_t* tab_e;  // edge-major CSR share table [kTabCsr][kWg]
+  const uint32_t* tab_v;  // vertex-major CSR share table [kTabCsr][kWg]
+  const int32_t* rowq;    // [kRowsPT][kWg] ordinal of row (thread + i kWg) among rows with hyperedges, or -1
   const float* s;
   const float* c;
-  const int32_t* long_edge;
-  int32_t n_long_edge;
-  const int32_t* long_row;
-  int32_t n_long;
-  const int32_t* long_chunk0;  // [n_long + 1] first chunk of each long row
-  const int32_t* chunk_begin;  // [n_chunks] entry range in vtx_edge
-  const int32_t* chunk_end;
-  int32_t n_chunks;
   const float* Y;
   int64_t ldy;
-  float* F;        // caller's F (row-major, ldf): x0 on entry when x0 != 0, result on exit
+  float* F;  // x0 on entry when x0 != 0, the result on exit (row-major, ldf)
   int64_t ldf;
-  float* Fw;       // workspaces [k][N], column j at j * N
-  float* Rw;
-  float* Pw;
   double a, b, tol2, claim2;
   int32_t max_iter, x0;
   int32_t* iters;
@@ -75,21 +72,33 @@ struct WgArgs {
   int32_t* status;
 };
 
+// A thread's share of one CSR (see the table layout in share_table).
+struct Share {
+  uint32_t w[kSlotW];
+  uint32_t q0;    // ordinal of the first row that starts in the share
+  uint32_t hm;    // head | cnt << 6 | span << 12
+  uint32_t mask;  // bit i: entry i ends its row
+};
+
+__device__ __forceinline__ void load_share(const uint32_t* tab, Share& sh) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int w = 0; w < kSlotW; ++w) sh.w[w] = tab[w * kWg + t];
+  sh.q0 = tab[kSlotW * kWg + t];
+  sh.hm = tab[(kSlotW + 1) * kWg + t];
+  sh.mask = tab[(kSlotW + 2) * kWg + t];
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
   return x;
 }
 
-// Sum over a group of kGrp consecutive lanes (fixed butterfly).
-__device__ __forceinline__ double grp_sum(double x) {
-#pragma unroll
-  for (int m = kGrp / 2; m >= 1; m >>= 1) x += __shfl_xor(x, m);
-  return x;
-}
-
-// Workgroup sums of x and y, identical in every thread (fixed order: a
-// lane butterfly per wave, then the waves' sums in wave order).
+// Workgroup sums of x and y, identical in every thread, in a fixed order:
+// a lane butterfly per wave, then wave 0's first kWgWaves lanes add the
+// waves' sums by a butterfly of their own and broadcast the two totals.
+// red: 2 * kWgWaves + 2 doubles.
 __device__ __forceinline__ void wg_sum2(double& x, double& y, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   x = wave_sum(x);
@@ -99,155 +108,126 @@ __device__ __forceinline__ void wg_sum2(double& x, double& y, double* red) {
     red[kWgWaves + wave] = y;
   }
   __syncthreads();
-  double sx = 0.0, sy = 0.0;
+  if (wave == 0) {
+    double sx = lane < kWgWaves ? red[lane] : 0.0;
+    double sy = lane < kWgWaves ? red[kWgWaves + lane] : 0.0;
 #pragma unroll
-  for (int w = 0; w < kWgWaves; ++w) {
-    sx += red[w];
-    sy += red[kWgWaves + w];
-  }
-  __syncthreads();  // red is reused by the next call
-  x = sx;
-  y = sy;
-}
-
-// Sum of val[idx[b + q]] over q in [q0, m), kWgGather entries in flight.
-template <class TV>
-__device__ __forceinline__ double row_tail(const int32_t* idx, const TV* val, int b, int q0, int m) {
-  double acc = 0.0;
-  for (int q = q0; q < m; q += kWgGather) {
-    int j[kWgGather];
-#pragma unroll
-    for (int u = 0; u < kWgGather; ++u) j[u] = q + u < m ? idx[b + q + u] : -1;
-#pragma unroll
-    for (int u = 0; u < kWgGather; ++u) acc += j[u] >= 0 ? double(val[j[u]]) : 0.0;
-  }
-  return acc;
-}
-
-// Short CSR rows (at most `lim` entries), two rows per thread at a time
-// (rows r and r + kWg): the offsets of both rows, then the first kWgGather
-// entries of both, are issued before either is consumed, so a thread waits
-// about twice per two rows instead of twice per row.  For each row r < n
-// with at most lim entries, calls f(r, sum of val[idx[j]] over its entries,
-// in entry order).
-template <class TV, class Fn>
-__device__ __forceinline__ void short_rows(int n, const int32_t* ptr, const int32_t* idx, const TV* val, int lim,
-                                           Fn&& f) {
-  for (int r0 = threadIdx.x; r0 < n; r0 += 2 * kWg) {
-    const int r1 = r0 + kWg;
-    const int b0 = ptr[r0];
-    int m0 = ptr[r0 + 1] - b0;
-    const int b1 = r1 < n ? ptr[r1] : 0;
-    int m1 = r1 < n ? ptr[r1 + 1] - b1 : 0;
-    if (m0 > lim) m0 = -1;  // a long row: done elsewhere
-    if (m1 > lim) m1 = -1;
-    int j0[kWgGather], j1[kWgGather];
-#pragma unroll
-    for (int u = 0; u < kWgGather; ++u) {
-      j0[u] = u < m0 ? idx[b0 + u] : -1;
-      j1[u] = u < m1 ? idx[b1 + u] : -1;
+    for (int m = kWgWaves / 2; m >= 1; m >>= 1) {
+      sx += __shfl_xor(sx, m);
+      sy += __shfl_xor(sy, m);
     }
-    double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-    for (int u = 0; u < kWgGather; ++u) {
-      a0 += j0[u] >= 0 ? double(val[j0[u]]) : 0.0;
-      a1 += j1[u] >= 0 ? double(val[j1[u]]) : 0.0;
-    }
-    if (m0 > kWgGather) a0 += row_tail(idx, val, b0, kWgGather, m0);
-    if (m1 > kWgGather) a1 += row_tail(idx, val, b1, kWgGather, m1);
-    if (m0 >= 0) f(r0, a0);
-    if (m1 >= 0 && r1 < n) f(r1, a1);
-  }
-}
-
-// Sum of val[idx[j]] over j in [b, en) by a group of kGrp lanes: lane gl
-// takes j = b + gl + kGrp u (kPerLane entries in flight per batch); the
-// result is valid in every lane of the group.
-template <class TV>
-__device__ __forceinline__ double group_range(const int32_t* idx, const TV* val, int b, int en, int gl) {
-  double acc = 0.0;
-  for (int j0 = b; j0 < en; j0 += kGrp * kPerLane) {
-    int j[kPerLane];
-#pragma unroll
-    for (int u = 0; u < kPerLane; ++u) {
-      const int q = j0 + gl + kGrp * u;
-      j[u] = q < en ? idx[q] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < kPerLane; ++u) acc += j[u] >= 0 ? double(val[j[u]]) : 0.0;
-  }
-  return grp_sum(acc);
-}
-
-// Z_e = c_e u_e, u_e = sum_{v in e} Ps_v, for every hyperedge; returns this
-// thread's share of sum_e c_e u_e^2.  Ends with a barrier (Z complete).
-__device__ __forceinline__ double edge_phase(const WgArgs& A, const float* Ps, double* Z) {
-  const int g = threadIdx.x / kGrp, gl = threadIdx.x % kGrp;
-  double ep = 0.0;
-  // hyperedges with more than kLongEdge members: a group each
-  for (int i = g; i < A.n_long_edge; i += kGroups) {
-    const int e = A.long_edge[i];
-    const double u = group_range(A.edge_vtx, Ps, A.edge_ptr[e], A.edge_ptr[e + 1], gl);
-    if (gl == 0) {
-      const double z = double(A.c[e]) * u;
-      Z[e] = z;
-      ep += u * z;
+    if (lane == 0) {
+      red[2 * kWgWaves] = sx;
+      red[2 * kWgWaves + 1] = sy;
     }
   }
-  short_rows(A.E, A.edge_ptr, A.edge_vtx, Ps, kLongEdge, [&](int e, double u) {
-    const double z = double(A.c[e]) * u;
-    Z[e] = z;
-    ep += u * z;
-  });
   __syncthreads();
-  return ep;
+  x = red[2 * kWgWaves];
+  y = red[2 * kWgWaves + 1];
+  __syncthreads();  // red is reused by the next call
 }
 
-// Calls f(v, (H Z)_v) once for every row.  Rows with more than kLongRow
-// hyperedges are split into the handle's chunks of at most kChunk entries:
-// a group sums each chunk into cpart, and after a barrier thread i adds long
-// row i's chunks in order.  Ends with the calls of the long rows (no barrier
-// after them).
-template <class Fn>
-__device__ __forceinline__ void vertex_phase(const WgArgs& A, const double* Z, double* cpart, Fn&& f) {
-  const int g = threadIdx.x / kGrp, gl = threadIdx.x % kGrp;
-  for (int ch = g; ch < A.n_chunks; ch += kGroups) {
-    const double hz = group_range(A.vtx_edge, Z, A.chunk_begin[ch], A.chunk_end[ch], gl);
-    if (gl == 0) cpart[ch] = hz;
+// Row sums of val over one CSR: out[q] = sum of val[idx] over row q's
+// entries, in entry order.  A thread sums its share (tab: the CSR's share
+// table); a row that starts in it and runs on is finished, after a barrier,
+// by adding the leading partial sums (carry) of the following `span` threads
+// in thread order.  Ends with a barrier (out complete).
+template <class TV, class TO>
+__device__ __attribute__((noinline)) void share_gather(const uint32_t* tab, const TV* val, TO* out, double* carry) {
+  Share sh;
+  load_share(tab, sh);
+  const int head = int(sh.hm & 63u), cnt = int((sh.hm >> 6) & 63u), span = int(sh.hm >> 12);
+  double acc = 0.0, lead = 0.0;
+  int q = int(sh.q0);
+#pragma unroll
+  for (int i = 0; i < kSlots; ++i) {
+    if (i < cnt) {
+      acc += double(val[(sh.w[i >> 1] >> ((i & 1) * 16)) & 0xffffu]);
+      if ((sh.mask >> i) & 1u) {
+        if (i < head) {
+          lead = acc;  // the end of a row begun in an earlier share
+        } else {
+          out[q] = TO(acc);
+          ++q;
+        }
+        acc = 0.0;
+      }
+    }
+    // at most 8 LDS loads in flight: the whole share at once would need 64
+    // registers for its values and spill the solver's vectors
+    if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
   }
-  short_rows(A.N, A.vtx_ptr, A.vtx_edge, Z, kLongRow, f);
-  __syncthreads();  // chunk sums complete
-  for (int i = threadIdx.x; i < A.n_long; i += kWg) {
-    double hz = 0.0;
-    for (int c = A.long_chunk0[i]; c < A.long_chunk0[i + 1]; ++c) hz += cpart[c];
-    f(A.long_row[i], hz);
+  const bool open = cnt > 0 && !((sh.mask >> (cnt - 1)) & 1u);  // the last row runs on
+  if (open && head == cnt) lead = acc;                          // the whole share is inside one row
+  carry[threadIdx.x] = lead;
+  __syncthreads();
+  if (open && head < cnt) {
+    // four interleaved partial sums (a fixed order), so the loads of a long
+    // span overlap
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    const double* cs = carry + threadIdx.x + 1;
+    int u = 0;
+    for (; u + 4 <= span; u += 4) {
+      t0 += cs[u];
+      t1 += cs[u + 1];
+      t2 += cs[u + 2];
+      t3 += cs[u + 3];
+    }
+    for (; u < span; ++u) t0 += cs[u];
+    out[q] = TO(acc + ((t0 + t1) + (t2 + t3)));
   }
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
-  extern __shared__ __align__(16) unsigned char wg_lds[];
-  __shared__ double red[2 * kWgWaves];
-  const int tid = threadIdx.x;
-  const int col = blockIdx.x;
-  const int N = A.N;
-  float* Ps = reinterpret_cast<float*>(wg_lds);
-  double* Z = reinterpret_cast<double*>(wg_lds + ((size_t(N) * sizeof(float) + 15) & ~size_t(15)));
-  double* cpart = Z + A.E;  // [n_chunks] chunk sums of the long rows
-  float* Fw = A.Fw + int64_t(col) * N;
-  float* Rw = A.Rw + int64_t(col) * N;
-  float* Pw = A.Pw + int64_t(col) * N;
+  extern __shared__ __align__(16) double wg_lds[];
+  __shared__ double red[2 * kWgWaves + 2];
+  const int tid = threadIdx.x, col = blockIdx.x;
+  const int N = A.N, E = A.E;
+  // Ps and U hold FP32 values during the iterations and FP64 values in the
+  // residual checks (the same bytes; FP64 needs the full regions)
+  double* Psd = wg_lds;       // [N]  s o f (checks)
+  double* Ud = Psd + N;       // [E]  u_e, then Z_e = c_e u_e (checks)
+  float* Psf = reinterpret_cast<float*>(Psd);  // s o p (iterations)
+  float* Uf = reinterpret_cast<float*>(Ud);    // u_e, then Z_e (iterations)
+  double* HZ = Ud + E;        // [nq]
+  double* carry = HZ + A.nq;  // [kWg]
+  float* Ys = reinterpret_cast<float*>(carry + kWg);  // [N]
+  float s[kRowsPT], f[kRowsPT], r[kRowsPT], p[kRowsPT], ce[kEdgesPT];
+  int qv[kRowsPT];
+#pragma unroll
+  for (int i = 0; i < kRowsPT; ++i) {
+    const int v = tid + i * kWg;
+    s[i] = v < N ? A.s[v] : 0.f;
+    qv[i] = A.rowq[i * kWg + tid];
+    f[i] = r[i] = p[i] = 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < kEdgesPT; ++i) {
+    const int e = tid + i * kWg;
+    ce[i] = e < E ? A.c[e] : 0.f;
+  }
   const float* Y = A.Y + col;
   const double a = A.a, bb = A.b;
 
-  // ||y||^2
+  // ||y||^2; the column of Y into LDS
   double yy = 0.0, unused = 0.0;
-  for (int v = tid; v < N; v += kWg) {
-    const double y = Y[int64_t(v) * A.ldy];
-    yy += y * y;
+#pragma unroll
+  for (int i = 0; i < kRowsPT; ++i) {
+    const int v = tid + i * kWg;
+    if (v < N) {
+      const float y = Y[int64_t(v) * A.ldy];
+      Ys[v] = y;
+      yy += double(y) * double(y);
+    }
   }
   wg_sum2(yy, unused, red);
   if (yy == 0.0) {  // zero column: f = 0 exactly
-    for (int v = tid; v < N; v += kWg) A.F[int64_t(v) * A.ldf + col] = 0.f;
+#pragma unroll
+    for (int i = 0; i < kRowsPT; ++i) {
+      const int v = tid + i * kWg;
+      if (v < N) A.F[int64_t(v) * A.ldf + col] = 0.f;
+    }
     if (tid == 0) {
       A.iters[col] = 0;
       A.relres[col] = 0.0;
@@ -256,46 +236,78 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
     return;
   }
 
-  // True residual R = Y - M F with FP64 accumulation, then the restart
-  // direction P = R; returns r'r (FP64 values) in rr and p'p in pp.
-  auto check = [&](double& rr, double& pp) {
-    for (int v = tid; v < N; v += kWg) Ps[v] = A.s[v] * Fw[v];
-    __syncthreads();
-    edge_phase(A, Ps, Z);
-    double r2 = 0.0;
-    vertex_phase(A, Z, cpart, [&](int v, double hz) {
-      const double f = Fw[v];
-      const double rt = double(Y[int64_t(v) * A.ldy]) - (a * f - bb * double(A.s[v]) * hz);
-      Rw[v] = float(rt);
-      r2 += rt * rt;
-    });
-    __syncthreads();  // R of the long rows (written by wave lanes) before the direction
-    double p2 = 0.0;
-    for (int v = tid; v < N; v += kWg) {
-      const float p = Rw[v];
-      Pw[v] = p;
-      Ps[v] = A.s[v] * p;
-      p2 += double(p) * double(p);
+  // Edge gather from Ps (complete on entry; T = float in the iterations,
+  // double in the checks): Z in U; returns this thread's share of
+  // sum_e c_e u_e^2.  Z is complete after the caller's next barrier.
+  auto edge_phase = [&](auto* Ps, auto* U) __attribute__((always_inline)) -> double {
+    using T = std::remove_pointer_t<decltype(U)>;
+    share_gather(A.tab_e, Ps, U, carry);
+    double ep = 0.0;
+#pragma unroll
+    for (int i = 0; i < kEdgesPT; ++i) {
+      const int e = tid + i * kWg;
+      if (e < E) {
+        const double u = U[e];
+        const double z = double(ce[i]) * u;
+        U[e] = T(z);
+        ep += u * z;
+      }
     }
-    wg_sum2(r2, p2, red);  // its barriers also publish Ps
+    return ep;
+  };
+  // Vertex gather from Z (complete on entry); fn(i, v, (H Z)_v) per owned row.
+  auto vertex_phase = [&](auto* U, auto&& fn) __attribute__((always_inline)) {
+    share_gather(A.tab_v, U, HZ, carry);
+#pragma unroll
+    for (int i = 0; i < kRowsPT; ++i) {
+      const int v = tid + i * kWg;
+      if (v < N) fn(i, v, qv[i] >= 0 ? HZ[qv[i]] : 0.0);
+    }
+  };
+  // True residual r = y - M f with FP64 accumulation, then the restart
+  // direction p = r; returns r'r (FP64 values) in rr and p'p in pp.
+  auto check = [&](double& rr, double& pp) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < kRowsPT; ++i) {
+      const int v = tid + i * kWg;
+      if (v < N) Psd[v] = double(s[i]) * double(f[i]);
+    }
+    __syncthreads();
+    edge_phase(Psd, Ud);
+    __syncthreads();  // Z complete
+    double r2 = 0.0, p2 = 0.0;
+    vertex_phase(Ud, [&](int i, int v, double hz) __attribute__((always_inline)) {
+      const double rt = double(Ys[v]) - (a * double(f[i]) - bb * double(s[i]) * hz);
+      r[i] = float(rt);
+      p[i] = r[i];
+      Psf[v] = float(double(s[i]) * double(p[i]));  // Psd is no longer read
+      r2 += rt * rt;
+      p2 += double(p[i]) * double(p[i]);
+    });
+    wg_sum2(r2, p2, red);  // its barriers publish Ps
     rr = r2;
     pp = p2;
   };
 
-  double rr, pp;
+  double rr = 0.0, pp = 0.0;
+  bool need_check = A.x0 != 0;  // a given start is checked (and restarted from) first
   if (A.x0) {
-    for (int v = tid; v < N; v += kWg) Fw[v] = A.F[int64_t(v) * A.ldf + col];
-    __syncthreads();
-    check(rr, pp);
+#pragma unroll
+    for (int i = 0; i < kRowsPT; ++i) {
+      const int v = tid + i * kWg;
+      if (v < N) f[i] = A.F[int64_t(v) * A.ldf + col];
+    }
   } else {
     double p2 = 0.0;
-    for (int v = tid; v < N; v += kWg) {
-      const float y = Y[int64_t(v) * A.ldy];
-      Fw[v] = 0.f;
-      Rw[v] = y;
-      Pw[v] = y;
-      Ps[v] = A.s[v] * y;
-      p2 += double(y) * double(y);
+#pragma unroll
+    for (int i = 0; i < kRowsPT; ++i) {
+      const int v = tid + i * kWg;
+      if (v < N) {
+        const float y = Ys[v];
+        r[i] = p[i] = y;
+        Psf[v] = float(double(s[i]) * double(y));
+        p2 += double(y) * double(y);
+      }
     }
     double r2 = p2;
     wg_sum2(r2, p2, red);
@@ -304,12 +316,12 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
   }
 
   int it = 0, st = 1;
-  double rel2 = rr / yy;
-  bool fresh = A.x0 != 0;  // rr is a true residual (just checked)
+  double rel2 = 1.0;
   for (;;) {
-    if (rr <= A.claim2 * yy || it >= A.max_iter) {
-      double rt = rr, p2 = pp;
-      if (!fresh) check(rt, p2);
+    if (need_check || rr <= A.claim2 * yy || it >= A.max_iter) {
+      double rt, p2;
+      check(rt, p2);
+      need_check = false;
       rel2 = rt / yy;
       if (rel2 <= A.tol2) {
         st = 0;
@@ -321,13 +333,11 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
       }
       rr = rt;  // restart from the true residual (beta = 0); rt > tol^2 yy > claim^2 yy
       pp = p2;
-      fresh = true;
     }
-    fresh = false;
     // p'Mp = a p'p - b sum_e c_e u_e^2
-    double ep = edge_phase(A, Ps, Z);
+    double ep = edge_phase(Psf, Uf);
     double unused2 = 0.0;
-    wg_sum2(ep, unused2, red);
+    wg_sum2(ep, unused2, red);  // its barriers complete Z
     const double pmp = a * pp - bb * ep;
     if (!(pmp > 0.0) || !std::isfinite(pmp)) {
       st = -4;
@@ -336,35 +346,39 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
     const double alpha = rr / pmp;
     const float al = float(alpha);
     double r2 = 0.0;
-    vertex_phase(A, Z, cpart, [&](int v, double hz) {
-      const float p = Pw[v];
-      const double q = a * double(p) - bb * double(A.s[v]) * hz;
-      const float f = Fw[v] + al * p;
-      const float r = Rw[v] - float(alpha * q);
-      Fw[v] = f;
-      Rw[v] = r;
-      r2 += double(r) * double(r);
+    vertex_phase(Uf, [&](int i, int, double hz) __attribute__((always_inline)) {
+      const double q = a * double(p[i]) - bb * double(s[i]) * hz;
+      f[i] += al * p[i];
+      r[i] -= float(alpha * q);
+      r2 += double(r[i]) * double(r[i]);
     });
     double unused3 = 0.0;
-    wg_sum2(r2, unused3, red);  // also orders the long rows' R before the direction
+    wg_sum2(r2, unused3, red);
     ++it;
     const double beta = r2 / rr;
     rr = r2;
     if (rr <= A.claim2 * yy || it >= A.max_iter) continue;  // the check restarts or finishes
     const float be = float(beta);
     double p2 = 0.0;
-    for (int v = tid; v < N; v += kWg) {
-      const float p = Rw[v] + be * Pw[v];
-      Pw[v] = p;
-      Ps[v] = A.s[v] * p;
-      p2 += double(p) * double(p);
+#pragma unroll
+    for (int i = 0; i < kRowsPT; ++i) {
+      const int v = tid + i * kWg;
+      if (v < N) {
+        p[i] = r[i] + be * p[i];
+        Psf[v] = float(double(s[i]) * double(p[i]));
+        p2 += double(p[i]) * double(p[i]);
+      }
     }
     double unused4 = 0.0;
     wg_sum2(p2, unused4, red);  // its barriers publish Ps to the edge gather
     pp = p2;
   }
 
-  for (int v = tid; v < N; v += kWg) A.F[int64_t(v) * A.ldf + col] = Fw[v];
+#pragma unroll
+  for (int i = 0; i < kRowsPT; ++i) {
+    const int v = tid + i * kWg;
+    if (v < N) A.F[int64_t(v) * A.ldf + col] = f[i];
+  }
   if (tid == 0) {
     A.iters[col] = it;
     A.relres[col] = std::sqrt(rel2);
@@ -372,12 +386,91 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
   }
 }
 
-}  // namespace
-
-size_t cg_wg_lds_bytes(int N, int E, int n_chunks) {
-  return ((size_t(N) * sizeof(float) + 15) & ~size_t(15)) + (size_t(E) + size_t(n_chunks)) * sizeof(double);
+// Share table of one CSR with `rows` rows (ptr [rows+1], idx [nnz]) into
+// out [kTabCsr][kWg]: thread t takes entries [t nnz / kWg, (t+1) nnz / kWg).
+// Word layout per thread: kSlotW words of 16-bit index pairs (entry 2w in
+// the low half), q0 = ordinal (ord[row]) of the first row that starts in the
+// share, hm = head | cnt << 6 | span << 12 (head: leading entries that end or
+// continue a row begun earlier; cnt: entries; span: following threads that
+// the share's last row runs into), mask: bit i when entry i ends its row.
+// Returns false if a share exceeds kSlots entries or an index 16 bits.
+bool share_table(int rows, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx,
+                 const std::vector<int32_t>& ord, uint32_t* out) {
+  const int64_t nnz = ptr[rows];
+  std::vector<int32_t> rowof(static_cast<size_t>(nnz));
+  for (int r = 0; r < rows; ++r)
+    for (int32_t j = ptr[r]; j < ptr[r + 1]; ++j) rowof[j] = r;
+  auto lo = [&](int t) { return int64_t(t) * nnz / kWg; };
+  for (int t = 0; t < kWg; ++t) {
+    const int64_t s0 = lo(t), s1 = lo(t + 1);
+    const int cnt = int(s1 - s0);
+    if (cnt > kSlots) return false;
+    uint32_t mask = 0;
+    for (int i = 0; i < cnt; ++i) {
+      const int32_t x = idx[size_t(s0 + i)];
+      if (x < 0 || x > 0xffff) return false;
+      out[size_t(i / 2) * kWg + t] |= uint32_t(x) << (16 * (i & 1));
+      if (s0 + i == ptr[rowof[size_t(s0 + i)] + 1] - 1) mask |= 1u << i;
+    }
+    int head = 0;
+    if (cnt > 0 && ptr[rowof[size_t(s0)]] < s0)
+      head = int(std::min<int64_t>(cnt, ptr[rowof[size_t(s0)] + 1] - s0));
+    const uint32_t q0 = head < cnt ? uint32_t(ord[rowof[size_t(s0 + head)]]) : 0u;
+    int span = 0;
+    if (cnt > 0 && !((mask >> (cnt - 1)) & 1u)) {
+      const int64_t last = ptr[rowof[size_t(s1 - 1)] + 1] - 1;
+      int t2 = t + 1;
+      while (lo(t2 + 1) <= last) ++t2;
+      span = t2 - t;
+    }
+    out[size_t(kSlotW) * kWg + t] = q0;
+    out[size_t(kSlotW + 1) * kWg + t] = uint32_t(head) | uint32_t(cnt) << 6 | uint32_t(span) << 12;
+    out[size_t(kSlotW + 2) * kWg + t] = mask;
+  }
+  return true;
 }
 
+// Builds the share tables of both CSRs and the owned-row ordinals once per
+// handle (the structure of H never changes after the build).
+int build_tables(hgl_handle* h, hipStream_t s) {
+  if (h->wg_nq >= 0) return HGL_OK;
+  const int N = h->N, E = h->E;
+  const int64_t nnz = h->nnz;
+  std::vector<int32_t> ep(static_cast<size_t>(E) + 1), ev(static_cast<size_t>(nnz)), vp(static_cast<size_t>(N) + 1),
+      ve(static_cast<size_t>(nnz));
+  HGL_HIP(hipMemcpyAsync(ep.data(), h->edge_ptr, sizeof(int32_t) * ep.size(), hipMemcpyDeviceToHost, s));
+  HGL_HIP(hipMemcpyAsync(vp.data(), h->vtx_ptr, sizeof(int32_t) * vp.size(), hipMemcpyDeviceToHost, s));
+  if (nnz > 0) {
+    HGL_HIP(hipMemcpyAsync(ev.data(), h->edge_vtx, sizeof(int32_t) * ev.size(), hipMemcpyDeviceToHost, s));
+    HGL_HIP(hipMemcpyAsync(ve.data(), h->vtx_edge, sizeof(int32_t) * ve.size(), hipMemcpyDeviceToHost, s));
+  }
+  HGL_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> ord_e(size_t(E) + 1), ord_v(size_t(N) + 1, -1);
+  for (int e = 0; e < E; ++e) ord_e[e] = e;
+  int nq = 0;
+  for (int v = 0; v < N; ++v)
+    if (vp[v + 1] > vp[v]) ord_v[v] = nq++;
+  const size_t words = size_t(2 * kTabCsr + kRowsPT) * kWg;
+  std::vector<uint32_t> tab(words, 0u);
+  if (!share_table(E, ep, ev, ord_e, tab.data()) ||
+      !share_table(N, vp, ve, ord_v, tab.data() + size_t(kTabCsr) * kWg)) {
+    set_error("hypergraph too large for the one-workgroup solver (more than %d incidences per thread)", kSlots);
+    return HGL_EUNSUPPORTED;
+  }
+  int32_t* rowq = reinterpret_cast<int32_t*>(tab.data() + size_t(2 * kTabCsr) * kWg);
+  for (int i = 0; i < kRowsPT; ++i)
+    for (int t = 0; t < kWg; ++t) {
+      const int v = t + i * kWg;
+      rowq[size_t(i) * kWg + t] = v < N ? ord_v[v] : -1;
+    }
+  HGL_TRY(h->wg_tab.reserve(sizeof(uint32_t) * words));
+  HGL_HIP(hipMemcpyAsync(h->wg_tab.p, tab.data(), sizeof(uint32_t) * words, hipMemcpyHostToDevice, s));
+  HGL_HIP(hipStreamSynchronize(s));
+  h->wg_nq = nq;
+  return HGL_OK;
+}
+
+}  // namespace
 }  // namespace hgl
 
 using namespace hgl;
@@ -398,44 +491,38 @@ extern "C" int hgl_cg_solve_wg(hgl_handle* h, double lambda, const hgl_cg_opts* 
     set_error("the one-workgroup solver runs the FP32 mode only (mode %d)", o->mode);
     return HGL_EUNSUPPORTED;
   }
-  const size_t lds = cg_wg_lds_bytes(h->N, h->E, h->n_chunks);
+  if (h->N > kRowsPT * kWg || h->E > kEdgesPT * kWg) {
+    set_error("graph too large for the one-workgroup solver: N = %d, E = %d (at most %d each)", h->N, h->E,
+              kRowsPT * kWg);
+    return HGL_EUNSUPPORTED;
+  }
+  HGL_TRY(build_tables(h, s));
+  const size_t lds = sizeof(double) * (size_t(h->N) + size_t(h->E) + size_t(h->wg_nq) + kWg) +
+                     sizeof(float) * size_t(h->N);
   if (lds > kWgLdsMax) {
     set_error("graph too large for the one-workgroup solver: N = %d, E = %d need %zu B of LDS (at most %zu)",
               h->N, h->E, lds, kWgLdsMax);
     return HGL_EUNSUPPORTED;
   }
-  const size_t vec = sizeof(float) * size_t(h->N) * k;
-  HGL_TRY(h->ws_vec.reserve(3 * vec + 256));
   HGL_TRY(h->ws_state.reserve(size_t(k) * (sizeof(double) + 2 * sizeof(int32_t)) + 64));
   HGL_TRY(ensure_pinned(h, 2 * size_t(k)));
-  float* base = h->ws_vec.as<float>();
   double* relres_d = h->ws_state.as<double>();
   int32_t* iters_d = reinterpret_cast<int32_t*>(relres_d + k);
   int32_t* status_d = iters_d + k;
+  const uint32_t* tab = h->wg_tab.as<uint32_t>();
   WgArgs A;
   A.N = h->N;
   A.E = h->E;
-  A.edge_ptr = h->edge_ptr;
-  A.edge_vtx = h->edge_vtx;
-  A.vtx_ptr = h->vtx_ptr;
-  A.vtx_edge = h->vtx_edge;
+  A.nq = h->wg_nq;
+  A.tab_e = tab;
+  A.tab_v = tab + size_t(kTabCsr) * kWg;
+  A.rowq = reinterpret_cast<const int32_t*>(tab + size_t(2 * kTabCsr) * kWg);
   A.s = h->s32;
   A.c = h->c32;
-  A.long_edge = h->long_edge;
-  A.n_long_edge = h->n_long_edge;
-  A.long_row = h->long_row;
-  A.n_long = h->n_long;
-  A.long_chunk0 = h->long_chunk0;
-  A.chunk_begin = h->chunk_begin;
-  A.chunk_end = h->chunk_end;
-  A.n_chunks = h->n_chunks;
   A.Y = Y;
   A.ldy = ldy;
   A.F = F;
   A.ldf = ldf;
-  A.Fw = base;
-  A.Rw = base + size_t(h->N) * k;
-  A.Pw = base + 2 * size_t(h->N) * k;
   A.a = 1.0 + 1.0 / lambda;
   A.b = 1.0 / lambda;
   A.tol2 = o->tol * o->tol;
