@@ -16,6 +16,11 @@ Workloads (synthetic, seeded; see synth/):
   rsvd_power the rsvd workload with the power-scheme sketch of eq. 10 in
              place of Algorithm 1's steps 2-3; also reports the kept
              singular values' deviation from Algorithm 1 on the same sketch.
+  single     the paper's query shape: G2 (alpha 2.1, sizes [2,200], Zipf
+             1.1) at N=5867, E=4694, lambda=0.5, one RHS per test image
+             (1292); value = latency of one query (us, lower is better)
+             through the one-workgroup solver; the 1292 queries in one call
+             and the multi-kernel solver are reported beside it.
   learn      G1, N=100,000, E=80,000, Y 100,000 x 500 at 5%, lambda=1,
              mu=0.01; a step = one outer projected-gradient step (forward CG,
              adjoint gradient, projection, re-weighting); value = steps/s.
@@ -89,7 +94,7 @@ def sources_digest():
 
 
 def _short(name):
-    return name.split("(")[0].replace("void ", "").strip()
+    return name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").strip()
 
 
 def summarize_counters(fetch_csv, write_csv, kernel, workload, command, calib_bytes=1 << 30):
@@ -398,6 +403,64 @@ def bench_rsvd(a, scheme="subspace"):
     return _line("rSVD blocks/s", a.steps * nb / dt, "blocks/s", a.steps, a.warmup, ms, "bf16", cfg, roof, extra)
 
 
+def bench_single(a):
+    """The paper's query shape (section 4): one RHS per test image on a
+    5,867-vertex graph; latency of one query through the one-workgroup
+    solver, and the 1292 queries of the paper's test set in one call."""
+    import torch
+
+    import synth
+    from paper_1908_08281_amd import hgl
+    dev = torch.device("cuda:0")
+    p = synth.single_query()
+    k = p.Y.shape[1]
+    tol = 1e-6 / (1 + 1 / p.lam)
+    ep, ev, w = _upload(p, dev)
+    h = hgl.build_laplacian(ep, ev, w, p.N)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    Y1 = Y[:, :1].contiguous()
+    out1, outk = torch.empty_like(Y1), torch.empty_like(Y)
+    steps1 = max(a.steps, 20)
+    stepsk = max(a.steps // 4, 5)
+    dt1, r1 = _timed(lambda: hgl.cg_solve_wg(h, p.lam, Y1, tol=tol, out=out1), steps1, max(a.warmup, 3))
+    dtk, rk = _timed(lambda: hgl.cg_solve_wg(h, p.lam, Y, tol=tol, out=outk), stepsk, max(a.warmup, 1))
+    ok = all(r[3] == 0 and bool(np.all(r[2] <= tol)) for r in r1 + rk)
+    mk1, _ = _timed(lambda: hgl.cg_solve(h, p.lam, Y1, tol=tol), steps1, 3)
+    mkk, _ = _timed(lambda: hgl.cg_solve(h, p.lam, Y, tol=tol), stepsk, 1)
+    lat_ms = 1e3 * dt1 / steps1
+    # compulsory bytes of one query: y and f (4 N each), s (4 N), c (4 E),
+    # and the per-thread tables of both CSRs (read once per gather, from L2)
+    alg = 4.0 * (3 * p.N + p.E)
+    roof = _roof("k_cg_wg", 1, lat_ms, alg)
+    roof["note"] = ("one workgroup per query: bound by the latency of its gathers and barriers, not by HBM; "
+                    "achieved counts the compulsory bytes over the whole call")
+    cfg = {"workload": "single_query_cg", "N": p.N, "E": p.E, "nnz": p.nnz, "k": 1, "lambda": p.lam,
+           "tol": tol, "solver": "one-workgroup CG (hgl_cg_solve_wg), FP32 vectors, FP64 sums and checks"}
+    extra = {"converged": ok, "iterations": int(r1[-1][1].max()),
+             "multi_kernel_latency_us": round(1e6 * mk1 / steps1, 1),
+             "throughput": {"queries": k, "one_workgroup_rhs_per_s": round(stepsk * k / dtk, 1),
+                            "multi_kernel_rhs_per_s": round(stepsk * k / mkk, 1)}}
+    if not a.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import laplacian as lap
+        from oracle import solve
+        op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            done = 0
+            while done < k and time.perf_counter() - t0 < 10.0:
+                solve.cg_ranking(op, p.w, p.lam, p.Y[:, done:done + 1], tol=tol)
+                done += 1
+            dtc = time.perf_counter() - t0
+        extra["cpu_baseline"] = {"value": round(1e6 * dtc / done, 1), "unit": "us per query", "cores": 1,
+                                 "kind": "oracle",
+                                 "sample": f"first {done} of {k} queries one at a time, FP64 matrix-free CG "
+                                           f"(eqs. 16-20) to the same relres, one thread, {dtc:.1f} s"}
+    return _line("single-query solve latency", 1e3 * lat_ms, "us", steps1, max(a.warmup, 3), lat_ms, "f32", cfg,
+                 roof, extra, higher=False)
+
+
 def bench_learn(a):
     import torch
 
@@ -442,7 +505,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workload", default="multi_rhs",
-                    help="multi_rhs (default), small, rsvd, rsvd_power, learn, batch, or a comma list")
+                    help="multi_rhs (default), small, rsvd, rsvd_power, single, learn, batch, or a comma list")
     ap.add_argument("--rr-period", type=int, default=0)
     ap.add_argument("--tune", type=int, default=1,
                     help="1: column shapes of the CG kernels picked by the library's autotuner (default)")
@@ -497,6 +560,8 @@ def main():
             out = bench_rsvd(a)
         elif wl == "rsvd_power":
             out = bench_rsvd(a, scheme="power")
+        elif wl == "single":
+            out = bench_single(a)
         elif wl == "learn":
             out = bench_learn(a)
         else:

@@ -225,12 +225,16 @@ int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg
  *    relres 0 after 0 iterations.
  *  iters_host [k], relres_host [k] (nullable, host): iterations and the
  *    FP64-recomputed relative residual per column.
- * Needs a single-graph handle and 4 N + 8 E bytes of LDS (rounded; at most
- * 159 KB, about N + 2E <= 40,000): larger graphs -> HGL_EUNSUPPORTED, as is
- * the FP64 mode.  Returns HGL_OK, HGL_NOT_CONVERGED (a column reached
- * max_iter), HGL_EBREAKDOWN (p'Mp <= 0 or not finite, e.g. NaN input) or
- * HGL_EINVAL (bad arguments).  Uses the handle's workspace (3 N k floats)
- * and synchronises the stream.
+ * Limits (the paper's query graphs are well inside them): a single-graph
+ * handle, N <= 6144 and E <= 6144, at most 32,768 incidences (each of the
+ * 1024 threads holds at most 32 of each of the two CSRs of H), and
+ * 8 (N + E + N' + 1024) + 4 N bytes of LDS at most 159 KB (N': vertices with
+ * at least one hyperedge); beyond them, and for the FP64 mode,
+ * HGL_EUNSUPPORTED.  The first call on a handle builds and keeps the
+ * per-thread tables (about 180 KB of device memory; synchronises).  Returns
+ * HGL_OK, HGL_NOT_CONVERGED (a column reached max_iter), HGL_EBREAKDOWN
+ * (p'Mp <= 0 or not finite, e.g. NaN input) or HGL_EINVAL (bad arguments).
+ * Synchronises the stream.
  */
 int hgl_cg_solve_wg(hgl_handle* h, double lambda, const hgl_cg_opts* opts, const float* Y, int64_t ldy,
                     float* F, int64_t ldf, int32_t k, int32_t* iters_host, double* relres_host,

@@ -118,6 +118,31 @@ def test_x0_limits_and_breakdown():
     assert "EINVAL" in str(ei.value)
 
 
+@pytest.mark.parametrize("case", ["sparse", "all_vertex_edge"])
+def test_share_boundaries(case):
+    """The per-thread shares of the CSRs: fewer incidences than threads
+    (empty shares inside row spans) and one hyperedge over all vertices (a row
+    running through hundreds of shares), against dense Cholesky."""
+    import torch
+    dev = device()
+    rng = synth.rng_for(101)
+    if case == "sparse":
+        N, E = 400, 90
+        edges = [sorted(rng.choice(N, size=int(rng.integers(2, 5)), replace=False)) for _ in range(E)]
+    else:
+        N, E = 3000, 1200
+        edges = [list(range(N))] + [sorted(rng.choice(N, size=int(rng.integers(2, 9)), replace=False))
+                                    for _ in range(E - 1)]
+    ep, ev = synth.explicit_hyperedges(edges)
+    p = synth.Problem(N, E, ep, ev, rng.uniform(0.2, 1.0, size=E), 0.6, rng.standard_normal((N, 9)))
+    tol = 1e-6 / (1 + 1 / p.lam)
+    say("cg_wg share boundaries", case, "nnz", len(ev))
+    h = build(p, dev)
+    F, it, rel, st = hgl().cg_solve_wg(h, p.lam, torch.from_numpy(p.Y).to(dev, torch.float32), tol=tol)
+    assert st == 0 and np.all(rel <= tol)
+    assert colrelerr(F.cpu().double().numpy(), _dense_solution(p, p.Y)).max() <= 1e-6
+
+
 def test_no_hyperedges_and_unsupported_requests():
     import torch
     from paper_1908_08281_amd import _lib
@@ -141,7 +166,14 @@ def test_no_hyperedges_and_unsupported_requests():
                                  C.c_void_p(F64.data_ptr()), k, k, None, None,
                                  C.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
     assert st == _lib.HGL_EUNSUPPORTED
-    # a graph whose Ps and Z do not fit one workgroup's LDS
+    # more incidences than the threads' shares hold (N and E within bounds)
+    ep, ev = synth.uniform_hyperedges(6000, 5000, 8, 12, 98)
+    pc = synth.Problem(6000, 5000, ep, ev, synth.uniform_weights(5000), lam, np.ones((6000, 1)))
+    hc = build(pc, dev)
+    with pytest.raises(Exception) as ei:
+        hgl().cg_solve_wg(hc, lam, torch.ones((6000, 1), dtype=torch.float32, device=dev))
+    assert "EUNSUPPORTED" in str(ei.value)
+    # a graph above the row and hyperedge bounds
     ep, ev = synth.uniform_hyperedges(30000, 24000, 2, 6, 99)
     pb = synth.Problem(30000, 24000, ep, ev, synth.uniform_weights(24000), lam, np.ones((30000, 1)))
     hb = build(pb, dev)
