@@ -312,6 +312,16 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
            "iterations": it_mean, "all_columns_converged": state["ok"], "partition": part}
     extra = {"cg_iteration_gbs": round(ab["cg_iteration"] * it_mean / (ms * 1e-3) / 1e9, 1),
              "kernel_ms": breakdown}
+    if mode == "f32" and not batched:
+        # the plain FP64 solve on the GPU to the same FP64-checked relres (equal
+        # accuracy), after the timed steps
+        Y64 = Y.double()
+        out64 = torch.empty_like(Y64)
+        d64, r64 = _timed(lambda: hgl.cg_solve(h, p.lam, Y64, mode="f64", tol=tol, out=out64), 3, 1)
+        extra["plain_f64_solve"] = {
+            "ms_per_solve": round(1e3 * d64 / 3, 4), "iterations": int(r64[-1][1].max()),
+            "converged": all(r[3] == 0 and bool(np.all(r[2] <= tol)) for r in r64),
+            "f32_speedup": round((d64 / 3) / (dt / a.steps), 3)}
     if with_cpu and not a.no_cpu:
         extra["cpu_baseline"] = cpu_cg_baseline(p, tol) if not batched else None
     return _line("solved RHS/s at relres 1e-6" if mode == "f32" else "solved RHS/s at relres 1e-10",
@@ -368,6 +378,16 @@ def bench_rsvd(a, scheme="subspace"):
              "refined_solve": {"nrhs": Y.shape[1], "pcg_iters": int(it.max()), "seconds": round(t_inv, 4),
                                "converged": st == 0 and bool(np.all(rel <= tol)),
                                "plain_cg_iters": int(it2.max()), "plain_cg_seconds": round(t_cg, 4)}}
+    if scheme == "subspace":
+        # the FP64 sketch (every product in FP64) on the same inputs: its time,
+        # and the refined solve it gives (equal accuracy: the same tolerance)
+        d64, _ = _timed(lambda: hgl.block_rsvd(h, p.blocks, k, pp, q, sketch="f64", omega=om), 3, 1)
+        F6, it6, rel6, sig6, st6 = hgl.block_rsvd_invert(h, p.lam, p.blocks, Y, k, pp, q, sketch="f64", omega=om,
+                                                         refine_tol=tol)
+        extra["f64_sketch"] = {"ms_per_batch": round(1e3 * d64 / 3, 4),
+                               "bf16_speedup": round((d64 / 3) / (dt / a.steps), 3),
+                               "pcg_iters": int(it6.max()),
+                               "converged": st6 == 0 and bool(np.all(rel6 <= tol))}
     if scheme == "power":
         # accuracy against Algorithm 1 on the same sketch: relative deviation
         # of the kept singular values, worst block
