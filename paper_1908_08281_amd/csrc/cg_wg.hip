@@ -434,6 +434,10 @@ bool share_table(int rows, const std::vector<int32_t>& ptr, const std::vector<in
 // handle (the structure of H never changes after the build).
 int build_tables(hgl_handle* h, hipStream_t s) {
   if (h->wg_nq >= 0) return HGL_OK;
+  if (h->wg_nq == -2) {  // refused before: the structure of H does not change
+    set_error("hypergraph too large for the one-workgroup solver (more than %d incidences per thread)", kSlots);
+    return HGL_EUNSUPPORTED;
+  }
   const int N = h->N, E = h->E;
   const int64_t nnz = h->nnz;
   std::vector<int32_t> ep(static_cast<size_t>(E) + 1), ev(static_cast<size_t>(nnz)), vp(static_cast<size_t>(N) + 1),
@@ -454,6 +458,7 @@ int build_tables(hgl_handle* h, hipStream_t s) {
   std::vector<uint32_t> tab(words, 0u);
   if (!share_table(E, ep, ev, ord_e, tab.data()) ||
       !share_table(N, vp, ve, ord_v, tab.data() + size_t(kTabCsr) * kWg)) {
+    h->wg_nq = -2;
     set_error("hypergraph too large for the one-workgroup solver (more than %d incidences per thread)", kSlots);
     return HGL_EUNSUPPORTED;
   }
