@@ -225,13 +225,16 @@ int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg
  *    relres 0 after 0 iterations.
  *  iters_host [k], relres_host [k] (nullable, host): iterations and the
  *    FP64-recomputed relative residual per column.
- * Limits (the paper's query graphs are well inside them): a single-graph
- * handle, N <= 6144 and E <= 6144, at most 32,768 incidences (each of the
- * 1024 threads holds at most 32 of each of the two CSRs of H), and
+ * On a batched handle every (graph, column) pair is one workgroup (one
+ * lambda for all graphs here; hgl_cg_solve_wg_batched takes one per graph),
+ * and iters_host, relres_host are [G k], graph-major.
+ * Limits per graph (the paper's query graphs are well inside them):
+ * N <= 6144 and E <= 6144, at most 32,768 incidences (each of the 1024
+ * threads holds at most 32 of each of the two CSRs of H), and
  * 8 (N + E + N' + 1024) + 4 N bytes of LDS at most 159 KB (N': vertices with
  * at least one hyperedge); beyond them, and for the FP64 mode,
  * HGL_EUNSUPPORTED.  The first call on a handle builds and keeps the
- * per-thread tables (about 180 KB of device memory; synchronises).  Returns
+ * per-thread tables (about 180 KB of device memory per graph; synchronises).  Returns
  * HGL_OK, HGL_NOT_CONVERGED (a column reached max_iter), HGL_EBREAKDOWN
  * (p'Mp <= 0 or not finite, e.g. NaN input) or HGL_EINVAL (bad arguments).
  * Synchronises the stream.
@@ -239,6 +242,13 @@ int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg
 int hgl_cg_solve_wg(hgl_handle* h, double lambda, const hgl_cg_opts* opts, const float* Y, int64_t ldy,
                     float* F, int64_t ldf, int32_t k, int32_t* iters_host, double* relres_host,
                     hipStream_t stream);
+
+/* As hgl_cg_solve_wg with one lambda per graph of a batched handle
+ * (lambdas_host [G]); Y and F are the row concatenations of the graphs'
+ * blocks (sum N_g x k), as for hgl_cg_solve_batched. */
+int hgl_cg_solve_wg_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg_opts* opts,
+                            const float* Y, int64_t ldy, float* F, int64_t ldf, int32_t k,
+                            int32_t* iters_host, double* relres_host, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Block randomized SVD (paper, section 3: Algorithm 1, the tessellation of

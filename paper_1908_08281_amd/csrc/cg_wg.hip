@@ -54,20 +54,29 @@ constexpr int kRowsPT = 6;             // vertex rows owned per thread (N <= 614
 constexpr int kEdgesPT = 6;            // hyperedges owned per thread (E <= 6144)
 constexpr size_t kWgLdsMax = 159 * 1024;
 
+constexpr size_t kTabWords = size_t(2 * kTabCsr + kRowsPT) * kWg;  // one graph's tables
+constexpr int kDesc = 5;                                             // N, E, N', vertex and edge offsets
+
+// Per graph g (of a batched handle; one graph otherwise) the table holds
+// kTabWords words at g kTabWords: the edge-major share table [kTabCsr][kWg],
+// the vertex-major one, and [kRowsPT][kWg] ordinals of the owned rows among
+// the graph's rows with hyperedges (-1: none or past N_g).  desc[kDesc g ..]
+// gives N_g, E_g, N'_g (rows with hyperedges) and the graph's first vertex
+// and hyperedge; its CSR shares use graph-local ids.
 struct WgArgs {
-  int32_t N, E, nq;
-  const uint32_t* tab_e;  // edge-major CSR share table [kTabCsr][kWg]
-  const uint32_t* tab_v;  // vertex-major CSR share table [kTabCsr][kWg]
-  const int32_t* rowq;    // [kRowsPT][kWg] ordinal of row (thread + i kWg) among rows with hyperedges, or -1
+  const uint32_t* tab;
+  const int32_t* desc;
+  const double* ab;  // [2 G]: a_g = 1 + 1/lambda_g at g, b_g = 1/lambda_g at G + g
+  int32_t G, k;
   const float* s;
   const float* c;
   const float* Y;
   int64_t ldy;
   float* F;  // x0 on entry when x0 != 0, the result on exit (row-major, ldf)
   int64_t ldf;
-  double a, b, tol2, claim2;
+  double tol2, claim2;
   int32_t max_iter, x0;
-  int32_t* iters;
+  int32_t* iters;  // [G k], graph-major
   double* relres;
   int32_t* status;
 };
@@ -182,8 +191,16 @@ __device__ __attribute__((noinline)) void share_gather(const uint32_t* tab, cons
 __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
   extern __shared__ __align__(16) double wg_lds[];
   __shared__ double red[2 * kWgWaves + 2];
-  const int tid = threadIdx.x, col = blockIdx.x;
-  const int N = A.N, E = A.E;
+  const int tid = threadIdx.x, col = blockIdx.x, g = blockIdx.y;
+  const int32_t* dg = A.desc + kDesc * g;
+  const int N = dg[0], E = dg[1], nq = dg[2], voff = dg[3], eoff = dg[4];
+  const uint32_t* tab_e = A.tab + size_t(g) * kTabWords;
+  const uint32_t* tab_v = tab_e + size_t(kTabCsr) * kWg;
+  const int32_t* rowq = reinterpret_cast<const int32_t*>(tab_e + size_t(2 * kTabCsr) * kWg);
+  const float* sg = A.s + voff;
+  const float* cg = A.c + eoff;
+  float* Fo = A.F + int64_t(voff) * A.ldf + col;
+  const int o = g * A.k + col;  // this (graph, column)'s output slot
   // Ps and U hold FP32 values during the iterations and FP64 values in the
   // residual checks (the same bytes; FP64 needs the full regions)
   double* Psd = wg_lds;       // [N]  s o f (checks)
@@ -191,24 +208,24 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
   float* Psf = reinterpret_cast<float*>(Psd);  // s o p (iterations)
   float* Uf = reinterpret_cast<float*>(Ud);    // u_e, then Z_e (iterations)
   double* HZ = Ud + E;        // [nq]
-  double* carry = HZ + A.nq;  // [kWg]
+  double* carry = HZ + nq;    // [kWg]
   float* Ys = reinterpret_cast<float*>(carry + kWg);  // [N]
   float s[kRowsPT], f[kRowsPT], r[kRowsPT], p[kRowsPT], ce[kEdgesPT];
   int qv[kRowsPT];
 #pragma unroll
   for (int i = 0; i < kRowsPT; ++i) {
     const int v = tid + i * kWg;
-    s[i] = v < N ? A.s[v] : 0.f;
-    qv[i] = A.rowq[i * kWg + tid];
+    s[i] = v < N ? sg[v] : 0.f;
+    qv[i] = rowq[i * kWg + tid];
     f[i] = r[i] = p[i] = 0.f;
   }
 #pragma unroll
   for (int i = 0; i < kEdgesPT; ++i) {
     const int e = tid + i * kWg;
-    ce[i] = e < E ? A.c[e] : 0.f;
+    ce[i] = e < E ? cg[e] : 0.f;
   }
-  const float* Y = A.Y + col;
-  const double a = A.a, bb = A.b;
+  const float* Y = A.Y + int64_t(voff) * A.ldy + col;
+  const double a = A.ab[g], bb = A.ab[A.G + g];
 
   // ||y||^2; the column of Y into LDS
   double yy = 0.0, unused = 0.0;
@@ -226,12 +243,12 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
 #pragma unroll
     for (int i = 0; i < kRowsPT; ++i) {
       const int v = tid + i * kWg;
-      if (v < N) A.F[int64_t(v) * A.ldf + col] = 0.f;
+      if (v < N) Fo[int64_t(v) * A.ldf] = 0.f;
     }
     if (tid == 0) {
-      A.iters[col] = 0;
-      A.relres[col] = 0.0;
-      A.status[col] = 0;
+      A.iters[o] = 0;
+      A.relres[o] = 0.0;
+      A.status[o] = 0;
     }
     return;
   }
@@ -241,7 +258,7 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
   // sum_e c_e u_e^2.  Z is complete after the caller's next barrier.
   auto edge_phase = [&](auto* Ps, auto* U) __attribute__((always_inline)) -> double {
     using T = std::remove_pointer_t<decltype(U)>;
-    share_gather(A.tab_e, Ps, U, carry);
+    share_gather(tab_e, Ps, U, carry);
     double ep = 0.0;
 #pragma unroll
     for (int i = 0; i < kEdgesPT; ++i) {
@@ -257,7 +274,7 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
   };
   // Vertex gather from Z (complete on entry); fn(i, v, (H Z)_v) per owned row.
   auto vertex_phase = [&](auto* U, auto&& fn) __attribute__((always_inline)) {
-    share_gather(A.tab_v, U, HZ, carry);
+    share_gather(tab_v, U, HZ, carry);
 #pragma unroll
     for (int i = 0; i < kRowsPT; ++i) {
       const int v = tid + i * kWg;
@@ -295,7 +312,7 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
 #pragma unroll
     for (int i = 0; i < kRowsPT; ++i) {
       const int v = tid + i * kWg;
-      if (v < N) f[i] = A.F[int64_t(v) * A.ldf + col];
+      if (v < N) f[i] = Fo[int64_t(v) * A.ldf];
     }
   } else {
     double p2 = 0.0;
@@ -377,12 +394,12 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
 #pragma unroll
   for (int i = 0; i < kRowsPT; ++i) {
     const int v = tid + i * kWg;
-    if (v < N) A.F[int64_t(v) * A.ldf + col] = f[i];
+    if (v < N) Fo[int64_t(v) * A.ldf] = f[i];
   }
   if (tid == 0) {
-    A.iters[col] = it;
-    A.relres[col] = std::sqrt(rel2);
-    A.status[col] = st;
+    A.iters[o] = it;
+    A.relres[o] = std::sqrt(rel2);
+    A.status[o] = st;
   }
 }
 
@@ -430,18 +447,20 @@ bool share_table(int rows, const std::vector<int32_t>& ptr, const std::vector<in
   return true;
 }
 
-// Builds the share tables of both CSRs and the owned-row ordinals once per
-// handle (the structure of H never changes after the build).
+// Builds, once per handle, every graph's share tables (graph-local ids),
+// owned-row ordinals and descriptor, and the LDS size of the largest graph
+// (the structure of H never changes after the build).
 int build_tables(hgl_handle* h, hipStream_t s) {
-  if (h->wg_nq >= 0) return HGL_OK;
-  if (h->wg_nq == -2) {  // refused before: the structure of H does not change
-    set_error("hypergraph too large for the one-workgroup solver (more than %d incidences per thread)", kSlots);
+  if (h->wg_lds >= 0) return HGL_OK;
+  if (h->wg_lds == -2) {  // refused before
+    set_error("a graph is too large for the one-workgroup solver (N, E <= %d, at most %d incidences per "
+              "thread and CSR)", kRowsPT * kWg, kSlots);
     return HGL_EUNSUPPORTED;
   }
-  const int N = h->N, E = h->E;
+  const int N = h->N, E = h->E, G = h->G;
   const int64_t nnz = h->nnz;
-  std::vector<int32_t> ep(static_cast<size_t>(E) + 1), ev(static_cast<size_t>(nnz)), vp(static_cast<size_t>(N) + 1),
-      ve(static_cast<size_t>(nnz));
+  std::vector<int32_t> ep(static_cast<size_t>(E) + 1), ev(static_cast<size_t>(nnz)),
+      vp(static_cast<size_t>(N) + 1), ve(static_cast<size_t>(nnz));
   HGL_HIP(hipMemcpyAsync(ep.data(), h->edge_ptr, sizeof(int32_t) * ep.size(), hipMemcpyDeviceToHost, s));
   HGL_HIP(hipMemcpyAsync(vp.data(), h->vtx_ptr, sizeof(int32_t) * vp.size(), hipMemcpyDeviceToHost, s));
   if (nnz > 0) {
@@ -449,30 +468,126 @@ int build_tables(hgl_handle* h, hipStream_t s) {
     HGL_HIP(hipMemcpyAsync(ve.data(), h->vtx_edge, sizeof(int32_t) * ve.size(), hipMemcpyDeviceToHost, s));
   }
   HGL_HIP(hipStreamSynchronize(s));
-  std::vector<int32_t> ord_e(size_t(E) + 1), ord_v(size_t(N) + 1, -1);
-  for (int e = 0; e < E; ++e) ord_e[e] = e;
-  int nq = 0;
-  for (int v = 0; v < N; ++v)
-    if (vp[v + 1] > vp[v]) ord_v[v] = nq++;
-  const size_t words = size_t(2 * kTabCsr + kRowsPT) * kWg;
-  std::vector<uint32_t> tab(words, 0u);
-  if (!share_table(E, ep, ev, ord_e, tab.data()) ||
-      !share_table(N, vp, ve, ord_v, tab.data() + size_t(kTabCsr) * kWg)) {
-    h->wg_nq = -2;
-    set_error("hypergraph too large for the one-workgroup solver (more than %d incidences per thread)", kSlots);
+  const size_t desc_words = size_t(kDesc) * G;
+  std::vector<uint32_t> tab(size_t(G) * kTabWords + desc_words, 0u);
+  int32_t* desc = reinterpret_cast<int32_t*>(tab.data() + size_t(G) * kTabWords);
+  size_t lds_max = 0;
+  bool ok = true;
+  for (int g = 0; g < G && ok; ++g) {
+    const int v0 = h->vtx_off[g], v1 = h->vtx_off[g + 1], e0 = h->edge_off[g], e1 = h->edge_off[g + 1];
+    const int Ng = v1 - v0, Eg = e1 - e0;
+    if (Ng > kRowsPT * kWg || Eg > kEdgesPT * kWg) {
+      ok = false;
+      break;
+    }
+    // the graph's CSRs with local ids
+    std::vector<int32_t> lep(size_t(Eg) + 1), lev, lvp(size_t(Ng) + 1), lve;
+    for (int e = 0; e <= Eg; ++e) lep[e] = ep[e0 + e] - ep[e0];
+    lev.reserve(size_t(lep[Eg]));
+    for (int32_t j = ep[e0]; j < ep[e1]; ++j) lev.push_back(ev[j] - v0);
+    for (int v = 0; v <= Ng; ++v) lvp[v] = vp[v0 + v] - vp[v0];
+    lve.reserve(size_t(lvp[Ng]));
+    for (int32_t j = vp[v0]; j < vp[v1]; ++j) lve.push_back(ve[j] - e0);
+    std::vector<int32_t> ord_e(size_t(Eg) + 1), ord_v(size_t(Ng) + 1, -1);
+    for (int e = 0; e < Eg; ++e) ord_e[e] = e;
+    int nq = 0;
+    for (int v = 0; v < Ng; ++v)
+      if (lvp[v + 1] > lvp[v]) ord_v[v] = nq++;
+    uint32_t* tg = tab.data() + size_t(g) * kTabWords;
+    if (!share_table(Eg, lep, lev, ord_e, tg) || !share_table(Ng, lvp, lve, ord_v, tg + size_t(kTabCsr) * kWg)) {
+      ok = false;
+      break;
+    }
+    int32_t* rowq = reinterpret_cast<int32_t*>(tg + size_t(2 * kTabCsr) * kWg);
+    for (int i = 0; i < kRowsPT; ++i)
+      for (int t = 0; t < kWg; ++t) {
+        const int v = t + i * kWg;
+        rowq[size_t(i) * kWg + t] = v < Ng ? ord_v[v] : -1;
+      }
+    desc[kDesc * g + 0] = Ng;
+    desc[kDesc * g + 1] = Eg;
+    desc[kDesc * g + 2] = nq;
+    desc[kDesc * g + 3] = v0;
+    desc[kDesc * g + 4] = e0;
+    lds_max = std::max(lds_max, sizeof(double) * (size_t(Ng) + size_t(Eg) + size_t(nq) + kWg) +
+                                    sizeof(float) * size_t(Ng));
+  }
+  if (!ok || lds_max > kWgLdsMax) {
+    h->wg_lds = -2;
+    set_error("a graph is too large for the one-workgroup solver (N, E <= %d, at most %d incidences per "
+              "thread and CSR, %zu B of LDS)", kRowsPT * kWg, kSlots, kWgLdsMax);
     return HGL_EUNSUPPORTED;
   }
-  int32_t* rowq = reinterpret_cast<int32_t*>(tab.data() + size_t(2 * kTabCsr) * kWg);
-  for (int i = 0; i < kRowsPT; ++i)
-    for (int t = 0; t < kWg; ++t) {
-      const int v = t + i * kWg;
-      rowq[size_t(i) * kWg + t] = v < N ? ord_v[v] : -1;
-    }
-  HGL_TRY(h->wg_tab.reserve(sizeof(uint32_t) * words));
-  HGL_HIP(hipMemcpyAsync(h->wg_tab.p, tab.data(), sizeof(uint32_t) * words, hipMemcpyHostToDevice, s));
+  HGL_TRY(h->wg_tab.reserve(sizeof(uint32_t) * tab.size()));
+  HGL_HIP(hipMemcpyAsync(h->wg_tab.p, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice, s));
   HGL_HIP(hipStreamSynchronize(s));
-  h->wg_nq = nq;
+  h->wg_lds = int32_t(lds_max);
   return HGL_OK;
+}
+
+int run_wg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, const float* Y, int64_t ldy, float* F,
+           int64_t ldf, int32_t k, int32_t* iters_host, double* relres_host, hipStream_t s) {
+  HGL_CHECK_ARG(h != nullptr && o != nullptr && lambdas != nullptr, "handle, opts and lambdas must not be NULL");
+  for (int g = 0; g < h->G; ++g)
+    HGL_CHECK_ARG(lambdas[g] > 0.0 && std::isfinite(lambdas[g]), "lambda must be > 0 (graph %d: %g)", g,
+                  lambdas[g]);
+  HGL_CHECK_ARG(o->tol > 0.0 && std::isfinite(o->tol), "tol must be > 0");
+  HGL_CHECK_ARG(o->max_iter >= 1, "max_iter must be >= 1");
+  HGL_CHECK_ARG(k >= 1, "k must be >= 1");
+  HGL_CHECK_ARG(Y && F, "Y and F must not be NULL");
+  HGL_CHECK_ARG(ldy >= k && ldf >= k, "leading dimensions must be >= k");
+  if (o->mode != HGL_CG_F32_F64DOT_RR) {
+    set_error("the one-workgroup solver runs the FP32 mode only (mode %d)", o->mode);
+    return HGL_EUNSUPPORTED;
+  }
+  HGL_TRY(build_tables(h, s));
+  HGL_TRY(upload_ab(h, lambdas, s));
+  const size_t gk = size_t(h->G) * k;
+  HGL_TRY(h->ws_state.reserve(gk * (sizeof(double) + 2 * sizeof(int32_t)) + 64));
+  HGL_TRY(ensure_pinned(h, 2 * gk));
+  double* relres_d = h->ws_state.as<double>();
+  int32_t* iters_d = reinterpret_cast<int32_t*>(relres_d + gk);
+  int32_t* status_d = iters_d + gk;
+  const uint32_t* tab = h->wg_tab.as<uint32_t>();
+  WgArgs A;
+  A.tab = tab;
+  A.desc = reinterpret_cast<const int32_t*>(tab + size_t(h->G) * kTabWords);
+  A.ab = h->ws_ab.as<double>();
+  A.G = h->G;
+  A.k = k;
+  A.s = h->s32;
+  A.c = h->c32;
+  A.Y = Y;
+  A.ldy = ldy;
+  A.F = F;
+  A.ldf = ldf;
+  A.tol2 = o->tol * o->tol;
+  A.claim2 = 0.25 * A.tol2;  // claims at tol / 2, as the multi-kernel FP32 mode
+  A.max_iter = o->max_iter;
+  A.x0 = o->x0_given ? 1 : 0;
+  A.iters = iters_d;
+  A.relres = relres_d;
+  A.status = status_d;
+  const size_t lds = size_t(h->wg_lds);
+  if (lds > 64 * 1024)
+    HGL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_wg), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(lds)));
+  launch(h, -1, k_cg_wg, dim3(k, h->G), dim3(kWg), uint32_t(lds), s, A);
+  HGL_HIP(hipGetLastError());
+  double* pd = h->pinned_d;
+  HGL_HIP(hipMemcpyAsync(pd, relres_d, sizeof(double) * gk + 2 * sizeof(int32_t) * gk, hipMemcpyDeviceToHost, s));
+  HGL_HIP(hipStreamSynchronize(s));
+  const int32_t* pi = reinterpret_cast<const int32_t*>(pd + gk);
+  int rc = HGL_OK;
+  for (size_t j = 0; j < gk; ++j) {
+    if (relres_host) relres_host[j] = pd[j];
+    if (iters_host) iters_host[j] = pi[j];
+    const int32_t st = pi[gk + j];
+    if (st == -4) rc = HGL_EBREAKDOWN;
+    else if (st == 1 && rc == HGL_OK) rc = HGL_NOT_CONVERGED;
+  }
+  if (rc == HGL_EBREAKDOWN) set_error("CG breakdown (p'Mp <= 0 or not finite) in a column");
+  return rc;
 }
 
 }  // namespace
@@ -484,76 +599,14 @@ extern "C" int hgl_cg_solve_wg(hgl_handle* h, double lambda, const hgl_cg_opts* 
                                float* F, int64_t ldf, int32_t k, int32_t* iters_host, double* relres_host,
                                hipStream_t s) {
   clear_error();
-  HGL_CHECK_ARG(h != nullptr && o != nullptr, "handle and opts must not be NULL");
-  HGL_CHECK_ARG(h->G == 1, "the one-workgroup solver needs a single-graph handle");
-  HGL_CHECK_ARG(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0 (%g)", lambda);
-  HGL_CHECK_ARG(o->tol > 0.0 && std::isfinite(o->tol), "tol must be > 0");
-  HGL_CHECK_ARG(o->max_iter >= 1, "max_iter must be >= 1");
-  HGL_CHECK_ARG(k >= 1, "k must be >= 1");
-  HGL_CHECK_ARG(Y && F, "Y and F must not be NULL");
-  HGL_CHECK_ARG(ldy >= k && ldf >= k, "leading dimensions must be >= k");
-  if (o->mode != HGL_CG_F32_F64DOT_RR) {
-    set_error("the one-workgroup solver runs the FP32 mode only (mode %d)", o->mode);
-    return HGL_EUNSUPPORTED;
-  }
-  if (h->N > kRowsPT * kWg || h->E > kEdgesPT * kWg) {
-    set_error("graph too large for the one-workgroup solver: N = %d, E = %d (at most %d each)", h->N, h->E,
-              kRowsPT * kWg);
-    return HGL_EUNSUPPORTED;
-  }
-  HGL_TRY(build_tables(h, s));
-  const size_t lds = sizeof(double) * (size_t(h->N) + size_t(h->E) + size_t(h->wg_nq) + kWg) +
-                     sizeof(float) * size_t(h->N);
-  if (lds > kWgLdsMax) {
-    set_error("graph too large for the one-workgroup solver: N = %d, E = %d need %zu B of LDS (at most %zu)",
-              h->N, h->E, lds, kWgLdsMax);
-    return HGL_EUNSUPPORTED;
-  }
-  HGL_TRY(h->ws_state.reserve(size_t(k) * (sizeof(double) + 2 * sizeof(int32_t)) + 64));
-  HGL_TRY(ensure_pinned(h, 2 * size_t(k)));
-  double* relres_d = h->ws_state.as<double>();
-  int32_t* iters_d = reinterpret_cast<int32_t*>(relres_d + k);
-  int32_t* status_d = iters_d + k;
-  const uint32_t* tab = h->wg_tab.as<uint32_t>();
-  WgArgs A;
-  A.N = h->N;
-  A.E = h->E;
-  A.nq = h->wg_nq;
-  A.tab_e = tab;
-  A.tab_v = tab + size_t(kTabCsr) * kWg;
-  A.rowq = reinterpret_cast<const int32_t*>(tab + size_t(2 * kTabCsr) * kWg);
-  A.s = h->s32;
-  A.c = h->c32;
-  A.Y = Y;
-  A.ldy = ldy;
-  A.F = F;
-  A.ldf = ldf;
-  A.a = 1.0 + 1.0 / lambda;
-  A.b = 1.0 / lambda;
-  A.tol2 = o->tol * o->tol;
-  A.claim2 = 0.25 * A.tol2;  // claims at tol / 2, as the multi-kernel FP32 mode
-  A.max_iter = o->max_iter;
-  A.x0 = o->x0_given ? 1 : 0;
-  A.iters = iters_d;
-  A.relres = relres_d;
-  A.status = status_d;
-  if (lds > 64 * 1024)
-    HGL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_wg), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                int(lds)));
-  launch(h, -1, k_cg_wg, dim3(k), dim3(kWg), uint32_t(lds), s, A);
-  HGL_HIP(hipGetLastError());
-  double* pd = h->pinned_d;
-  HGL_HIP(hipMemcpyAsync(pd, relres_d, sizeof(double) * k + 2 * sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));
-  HGL_HIP(hipStreamSynchronize(s));
-  const int32_t* pi = reinterpret_cast<const int32_t*>(pd + k);
-  int rc = HGL_OK;
-  for (int j = 0; j < k; ++j) {
-    if (relres_host) relres_host[j] = pd[j];
-    if (iters_host) iters_host[j] = pi[j];
-    const int32_t st = pi[k + j];
-    if (st == -4) rc = HGL_EBREAKDOWN;
-    else if (st == 1 && rc == HGL_OK) rc = HGL_NOT_CONVERGED;
-  }
-  if (rc == HGL_EBREAKDOWN) set_error("CG breakdown (p'Mp <= 0 or not finite) in a column");
-  return rc;
+  HGL_CHECK_ARG(h != nullptr, "handle is NULL");
+  std::vector<double> lams(h->G, lambda);
+  return run_wg(h, lams.data(), o, Y, ldy, F, ldf, k, iters_host, relres_host, s);
+}
+
+extern "C" int hgl_cg_solve_wg_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg_opts* o,
+                                       const float* Y, int64_t ldy, float* F, int64_t ldf, int32_t k,
+                                       int32_t* iters_host, double* relres_host, hipStream_t s) {
+  clear_error();
+  return run_wg(h, lambdas_host, o, Y, ldy, F, ldf, k, iters_host, relres_host, s);
 }

@@ -139,8 +139,8 @@ struct hgl_handle {
   hgl::DevBuf ws_z, ws_z64, ws_chunk, ws_part, ws_part2, ws_vec, ws_state, ws_misc;
   hgl::DevBuf ws_extra[8];
   hgl::DevBuf ws_ab;                 // per-graph (1 + 1/lambda, 1/lambda)
-  hgl::DevBuf wg_tab;                // one-workgroup CG: per-thread CSR slices (built on first use)
-  int32_t wg_nq = -1;                // one-workgroup CG: vertex rows with hyperedges (-1: not built)
+  hgl::DevBuf wg_tab;                // one-workgroup CG: per-graph share tables and descriptors
+  int32_t wg_lds = -1;               // one-workgroup CG: LDS bytes of the largest graph (-1: not built, -2: refused)
   std::vector<double> ab_cache;      // lambdas held in ws_ab
 
   // block rSVD workspace (owned, freed by rsvd_free)

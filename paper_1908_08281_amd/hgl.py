@@ -199,9 +199,9 @@ def _cg(h: Handle, lams, Y: torch.Tensor, mode: str, tol: float, max_iter: int,
             la = np.ascontiguousarray(np.asarray(lams, dtype=np.float64))
             if la.size != h.G:
                 raise ValueError("need one lambda per graph")
-            st = lib().hgl_cg_solve_batched(h.ptr, la.ctypes.data_as(_lib.DP), C.byref(opts), _ptr(Y), ldy,
-                                            _ptr(F), F.stride(0), k, iters.ctypes.data_as(_lib.I32P),
-                                            rel.ctypes.data_as(_lib.DP), _stream(h.device))
+            fn = lib().hgl_cg_solve_wg_batched if wg else lib().hgl_cg_solve_batched
+            st = fn(h.ptr, la.ctypes.data_as(_lib.DP), C.byref(opts), _ptr(Y), ldy, _ptr(F), F.stride(0), k,
+                    iters.ctypes.data_as(_lib.I32P), rel.ctypes.data_as(_lib.DP), _stream(h.device))
         else:
             fn = lib().hgl_cg_solve_wg if wg else lib().hgl_cg_solve
             st = fn(h.ptr, float(lams), C.byref(opts), _ptr(Y), ldy, _ptr(F), F.stride(0), k,
@@ -224,9 +224,16 @@ def cg_solve(h: Handle, lam: float, Y: torch.Tensor, mode: str = "f32", tol: flo
 
 def cg_solve_wg(h: Handle, lam: float, Y: torch.Tensor, tol: float = 1e-6, max_iter: int = 1000,
                 x0: torch.Tensor | None = None, out: torch.Tensor | None = None):
-    """The latency path for small graphs: each column's whole FP32 solve runs in one workgroup of
-    one launch (hgl_cg_solve_wg).  Returns (F, iters[1,k], relres[1,k], status) as cg_solve."""
+    """The latency path for small graphs: each (graph, column)'s whole FP32 solve runs in one
+    workgroup of one launch (hgl_cg_solve_wg).  Returns (F, iters[G,k], relres[G,k], status) as
+    cg_solve."""
     return _cg(h, lam, Y, "f32", tol, max_iter, x0, 0, 0, batched=False, out=out, wg=True)
+
+
+def cg_solve_wg_batched(h: Handle, lams, Y: torch.Tensor, tol: float = 1e-6, max_iter: int = 1000,
+                        x0: torch.Tensor | None = None, out: torch.Tensor | None = None):
+    """cg_solve_wg with one lambda per graph of a batched handle (hgl_cg_solve_wg_batched)."""
+    return _cg(h, lams, Y, "f32", tol, max_iter, x0, 0, 0, batched=True, out=out, wg=True)
 
 
 def cg_solve_batched(h: Handle, lams, Y: torch.Tensor, mode: str = "f32", tol: float = 1e-6,

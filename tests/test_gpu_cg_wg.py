@@ -180,3 +180,58 @@ def test_no_hyperedges_and_unsupported_requests():
     with pytest.raises(Exception) as ei:
         hgl().cg_solve_wg(hb, lam, torch.ones((30000, 1), dtype=torch.float32, device=dev))
     assert "EUNSUPPORTED" in str(ei.value)
+
+
+def _graph(p, g):
+    """Graph g of a batched problem as a problem of its own (local ids)."""
+    v0, v1 = int(p.vtx_offsets[g]), int(p.vtx_offsets[g + 1])
+    e0, e1 = int(p.edge_offsets[g]), int(p.edge_offsets[g + 1])
+    ep = (p.edge_ptr[e0:e1 + 1] - p.edge_ptr[e0]).astype(np.int32)
+    ev = (p.edge_vtx[p.edge_ptr[e0]:p.edge_ptr[e1]] - v0).astype(np.int32)
+    return synth.Problem(v1 - v0, e1 - e0, ep, ev, p.w[e0:e1], float(p.lams[g]), p.Y[v0:v1])
+
+
+def test_batched_graphs_against_cholesky():
+    """Six G2 graphs of 300-5000 vertices, one without hyperedges, one lambda
+    per graph: every (graph, column) is its own workgroup; each graph's
+    block against dense Cholesky, and the whole batch against the
+    multi-kernel batched solver."""
+    import torch
+    dev = device()
+    pb = synth.batch_of_graphs(seed_offset=3, G=6, nlo=300, nhi=5000, k=7, smax=100)
+    # graph 2 loses its hyperedges (an operator of (1 + 1/lambda) I there)
+    e0, e1 = int(pb.edge_offsets[2]), int(pb.edge_offsets[3])
+    keep = np.r_[0:e0, e1:pb.E]
+    counts = np.diff(pb.edge_ptr)[keep]
+    starts = pb.edge_ptr[:-1][keep]
+    ev = np.concatenate([pb.edge_vtx[s:s + c] for s, c in zip(starts, counts)]).astype(np.int32)
+    ep = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    eoff = pb.edge_offsets.copy()
+    eoff[3:] -= e1 - e0
+    lams = np.array([0.5, 0.3, 0.8, 0.5, 1.0, 0.4])
+    p = synth.Problem(pb.N, pb.E - (e1 - e0), ep, ev, pb.w[keep], 0.5, pb.Y, vtx_offsets=pb.vtx_offsets,
+                      edge_offsets=eoff, lams=lams)
+    tol = 1e-6 / (1 + 1 / lams.min())
+    say("cg_wg batched graphs", p.N)
+    h = build(p, dev)
+    Yd = torch.from_numpy(p.Y).to(dev, torch.float32)
+    F, it, rel, st = hgl().cg_solve_wg_batched(h, lams, Yd, tol=tol)
+    assert st == 0 and it.shape == (6, 7) and np.all(rel <= tol)
+    F = F.cpu().double().numpy()
+    for g in range(6):
+        q = _graph(p, g)
+        v0, v1 = int(p.vtx_offsets[g]), int(p.vtx_offsets[g + 1])
+        assert colrelerr(F[v0:v1], _dense_solution(q, q.Y)).max() <= 1e-6, g
+    Fm, itm, relm, stm = hgl().cg_solve_batched(h, lams, Yd, tol=tol)
+    assert stm == 0
+    assert colrelerr(F, Fm.cpu().double().numpy()).max() <= 2e-6
+
+
+def test_batched_graph_too_large_is_refused():
+    import torch
+    dev = device()
+    p = synth.batch_of_graphs(seed_offset=4, G=3, nlo=6500, nhi=7000, k=2, smax=50)
+    h = build(p, dev)
+    with pytest.raises(Exception) as ei:
+        hgl().cg_solve_wg_batched(h, p.lams, torch.from_numpy(p.Y).to(dev, torch.float32))
+    assert "EUNSUPPORTED" in str(ei.value)
