@@ -4,8 +4,9 @@
 // of a few thousand vertices (section 4); a multi-kernel CG step there is
 // bound by the per-launch latency of its six kernels, not by memory.  Here
 // one workgroup of 1024 threads runs a column's whole solve, eqs. 16-20
-// with M = I + L/lambda, in a single launch, and the columns of Y are
-// independent workgroups (one launch solves many queries at once).
+// with M = I + L/lambda, in a single launch, and the columns of Y (and the
+// graphs of a batched handle) are independent workgroups (one launch solves
+// many queries at once).
 //
 // Each thread owns an even share (at most kSlots entries) of each CSR of H,
 // edge-major and vertex-major: 16-bit indices, a bitmask of the entries that
@@ -16,7 +17,8 @@
 // stays in L2) and then works from LDS only.  The vectors f, r, p and the
 // scale s of a thread's kRowsPT vertex rows (v = thread + i * 1024) and c of
 // its kEdgesPT hyperedges stay in registers for the whole solve.
-// LDS holds Ps = s o p (FP64), U / Z over the hyperedges (FP64), H Z over the
+// LDS holds Ps = s o p and U / Z over the hyperedges (FP32 values during the
+// iterations, FP64 in the residual checks, in the same bytes), H Z over the
 // vertex rows that have hyperedges (FP64), one carry word per thread and the
 // column of Y (FP32, read again by the residual checks).
 //
