@@ -198,12 +198,29 @@ def _upload(p, dev):
     return tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (p.edge_ptr, p.edge_vtx, p.w))
 
 
+def _host_info():
+    """The host the CPU baseline ran on: CPU model, cores in this process's
+    affinity mask, and the BLAS threads the oracle was limited to."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "affinity_cores": len(os.sched_getaffinity(0)), "blas_threads": 1}
+
+
 def _line(metric, value, unit, steps, warmup, ms, dtype, config, roof, extra=None, higher=True):
     out = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": steps,
            "warmup": warmup, "ms_per_step": round(ms, 4), "higher_is_better": higher, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roof}
     if extra:
         out.update(extra)
+    if isinstance(out.get("cpu_baseline"), dict):
+        out["cpu_baseline"]["host"] = _host_info()
     return out
 
 
@@ -315,6 +332,26 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
            "iterations": it_mean, "all_columns_converged": state["ok"], "partition": part}
     extra = {"cg_iteration_gbs": round(ab["cg_iteration"] * it_mean / (ms * 1e-3) / 1e9, 1),
              "kernel_ms": breakdown}
+    if batched:
+        # the same graphs as G separate single-graph solves, one after another
+        # (handles built outside the timing)
+        subs = []
+        for g in range(G):
+            v0, v1 = int(p.vtx_offsets[g]), int(p.vtx_offsets[g + 1])
+            e0, e1 = int(p.edge_offsets[g]), int(p.edge_offsets[g + 1])
+            sep = (p.edge_ptr[e0:e1 + 1] - p.edge_ptr[e0]).astype(np.int32)
+            sev = (p.edge_vtx[p.edge_ptr[e0]:p.edge_ptr[e1]] - v0).astype(np.int32)
+            hg = hgl.build_laplacian(torch.from_numpy(sep).to(dev), torch.from_numpy(sev).to(dev),
+                                     torch.from_numpy(np.ascontiguousarray(p.w[e0:e1])).to(dev), v1 - v0)
+            subs.append((hg, float(p.lams[g]), Y[v0:v1].contiguous()))
+
+        def separate():
+            for hg, lam_g, Yg in subs:
+                hgl.cg_solve(hg, lam_g, Yg, mode=mode, tol=tol, rr_period=rr_period, tune=tune)
+
+        d_sep, _ = _timed(separate, 2, 1)
+        extra["separate_solves"] = {"graphs": G, "ms": round(1e3 * d_sep / 2, 3),
+                                    "batched_speedup": round((d_sep / 2) / (dt / a.steps), 3)}
     if mode == "f32" and not batched:
         # the plain FP64 solve on the GPU to the same FP64-checked relres (equal
         # accuracy), after the timed steps
@@ -574,6 +611,9 @@ def main():
     ap.add_argument("--summarize", nargs="+", metavar="ARG",
                     help="write profile summaries and exit: 'stats STATS_CSV WORKLOAD COMMAND' or "
                          "'counters FETCH_CSV WRITE_CSV KERNEL WORKLOAD COMMAND'")
+    ap.add_argument("--peaks", type=int, default=1,
+                    help="1: measure the achievable HBM GB/s and BF16 MFMA TFLOP/s with the library's probes "
+                         "first and report each roofline against them too (frac_measured)")
     ap.add_argument("--calib", action="store_true",
                     help="first copy 1 GiB device to device (the known-size kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
@@ -605,6 +645,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    peaks = None
+    if a.peaks:
+        # the device's achievable peaks, measured with the library's own probes
+        from paper_1908_08281_amd import hgl
+        peaks = hgl.measure_peaks("cuda:0")
     for wl in a.workload.split(","):
         if wl == "multi_rhs":
             p = synth.multi_rhs()
@@ -628,6 +673,11 @@ def main():
         else:
             print(f"unknown workload {wl}", file=sys.stderr)
             sys.exit(2)
+        roof = out.get("roofline")
+        if peaks and isinstance(roof, dict):
+            meas = peaks["hbm_gbs"] if roof["bound"] == "hbm" else peaks["bf16_mfma_tflops"]
+            roof["measured_peak"] = meas
+            roof["frac_measured"] = round(roof["achieved"] / meas, 4)
         print(json.dumps(out), flush=True)
 
 

@@ -398,6 +398,24 @@ int hgl_project_simplex(const double* v, double* w, int32_t E, hipStream_t strea
 int hgl_profile(hgl_handle* h, int32_t enable);
 int hgl_profile_read(hgl_handle* h, int32_t kind, int64_t* launches, double* ms);
 
+/* ------------------------------------------------------------------------
+ * Measurement probes (not part of the method): the device's achievable
+ * peaks, the measured denominators of the roofline fractions.
+ * ------------------------------------------------------------------------ */
+
+/* Copy `bytes` (a positive multiple of 16; src, dst 16-byte aligned device
+ * buffers that do not overlap) with a 16-bytes-per-lane grid-stride kernel.
+ * Moves 2 * bytes through HBM when both buffers exceed the last-level cache.
+ * Asynchronous. */
+int hgl_peak_copy(const void* src, void* dst, int64_t bytes, hipStream_t stream);
+
+/* `workgroups` workgroups of 4 waves; every wave runs `iters` rounds of eight
+ * independent v_mfma_f32_16x16x32_bf16 on register operands (16,384 flops
+ * each): 524,288 * workgroups * iters flops in all.  out (device,
+ * `workgroups` floats) is written only if a sum reaches a sentinel it does
+ * not reach.  Asynchronous. */
+int hgl_peak_mfma_bf16(float* out, int32_t workgroups, int32_t iters, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

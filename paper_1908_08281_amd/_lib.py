@@ -68,6 +68,8 @@ SIGNATURES = {
     "hgl_cg_solve_batched": (C.c_int, [P, DP, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),
     "hgl_cg_solve_wg": (C.c_int, [P, D, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),
     "hgl_cg_solve_wg_batched": (C.c_int, [P, DP, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),
+    "hgl_peak_copy": (C.c_int, [P, P, I64, P]),
+    "hgl_peak_mfma_bf16": (C.c_int, [P, I32, I32, P]),
     "hgl_block_rsvd": (C.c_int, [P, I32, I32P, C.POINTER(RsvdOpts), P, P, P, P]),
     "hgl_block_rsvd_invert": (C.c_int, [P, D, I32, I32P, C.POINTER(RsvdOpts), P, P, I64, P, I64, I32, P,
                                         I32P, DP, P]),

@@ -306,6 +306,40 @@ def block_rsvd_invert(h: Handle, lam: float, offsets, Y: torch.Tensor, k: int, p
     return F, iters, rel, sig, st
 
 
+def measure_peaks(device, copy_bytes: int = 1 << 30, reps: int = 10) -> dict:
+    """Achievable HBM GB/s (a copy of copy_bytes between two buffers, each
+    larger than the last-level cache; 2 * copy_bytes moved per copy) and
+    achievable dense BF16 MFMA TFLOP/s, each the best of `reps` timed calls."""
+    dev = torch.device(device)
+    src = torch.empty(copy_bytes, dtype=torch.uint8, device=dev)
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    wg, iters = 256 * 8, 1000
+    out = torch.zeros(wg, dtype=torch.float32, device=dev)
+    st = _stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best(fn):
+        fn()
+        ms = float("inf")
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms = min(ms, e0.elapsed_time(e1))
+        return ms
+
+    with torch.cuda.device(dev):
+        t_copy = best(lambda: check(lib().hgl_peak_copy(_ptr(src), _ptr(dst), copy_bytes, st), "hgl_peak_copy"))
+        t_mfma = best(lambda: check(lib().hgl_peak_mfma_bf16(_ptr(out), wg, iters, st), "hgl_peak_mfma_bf16"))
+    if not torch.equal(src[:4096], dst[:4096]):
+        raise RuntimeError("hgl_peak_copy produced a wrong copy")
+    return {"hbm_gbs": round(2 * copy_bytes / (t_copy * 1e-3) / 1e9, 1),
+            "bf16_mfma_tflops": round(524288.0 * wg * iters / (t_mfma * 1e-3) / 1e12, 1),
+            "copy_bytes": copy_bytes}
+
+
 def sketch_gaussian(rows: int, l: int, seed: int, device) -> torch.Tensor:
     """rows x l Philox4x32-10 standard normals rounded to BF16 (bit patterns, int16 tensor)."""
     out = torch.empty((rows, l), dtype=torch.int16, device=device)
