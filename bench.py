@@ -277,24 +277,27 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
          else hgl.build_laplacian(ep, ev, w, p.N))
     Y = torch.from_numpy(p.Y).to(dev, dtype)
     batched = p.vtx_offsets is not None
-    state = {"ok": True, "iters": []}
+    state = {"ok": True, "iters": [], "ms": []}
     out = torch.empty_like(Y)  # one output buffer, so that a recorded graph is replayed
     graph = bool(a.graph)
     tune = bool(a.tune)
 
     def step():
+        t0 = time.perf_counter()  # each solve synchronises before it returns
         if batched:
             F, it, rel, st = hgl.cg_solve_batched(h, p.lams, Y, mode=mode, tol=tol, rr_period=rr_period,
                                                   graph=graph, out=out, tune=tune)
         else:
             F, it, rel, st = hgl.cg_solve(h, p.lam, Y, mode=mode, tol=tol, rr_period=rr_period, graph=graph,
                                           out=out, tune=tune)
+        state["ms"].append(1e3 * (time.perf_counter() - t0))
         state["ok"] = state["ok"] and st == 0 and bool(np.all(rel <= tol))
         state["iters"].append(int(it.max()))
 
     for _ in range(a.warmup):
         step()
     state["iters"].clear()
+    state["ms"].clear()
     # in the timed steps every 4th launch of the two gather kernels carries
     # launch events (stamping every launch would slow the stream by ~7%)
     hgl.profile(h, True, kinds=["vertex_gather", "edge_gather"], every=4)
@@ -330,7 +333,9 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
                  + (", first chunk of iterations as a replayed HIP graph" if graph else "")
                  + (f" and every {rr_period}" if rr_period else ""),
            "iterations": it_mean, "all_columns_converged": state["ok"], "partition": part}
-    extra = {"cg_iteration_gbs": round(ab["cg_iteration"] * it_mean / (ms * 1e-3) / 1e9, 1),
+    it_gbs = ab["cg_iteration"] * it_mean / (ms * 1e-3) / 1e9
+    extra = {"cg_iteration_gbs": round(it_gbs, 1), "cg_iteration_frac": round(it_gbs / HBM_PEAK_GBS, 4),
+             "ms_per_step_median": round(float(np.median(state["ms"][:a.steps])), 4),
              "kernel_ms": breakdown}
     if batched:
         # the same graphs as G separate single-graph solves, one after another
