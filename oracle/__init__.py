@@ -11,6 +11,8 @@ library computes, written from the paper (Karantaidis, Sarridis, Kotropoulos,
 * ``rsvd``       -- Algorithm 1 (randomized SVD by subspace iteration), the
   diagonal-block tessellation (eq. 11) and the block inverse (eq. 15, read as
   the identity-plus-low-rank form), and preconditioned CG.
+* ``schur``      -- the 2x2 block inverse through Schur complements (eqs.
+  12-14) under nested tessellation, with eq. 15 at the smallest submatrices.
 * ``grad``       -- derivative of the weight objective P(w) (eq. 4) and of
   losses through the solve, plus finite differences.
 * ``simplex``    -- Euclidean projection onto {w >= 0, 1'w = 1} (constraints of
@@ -20,4 +22,4 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the HIP library
 and imports nothing from it.
 """
-from . import laplacian, solve, rsvd, grad, simplex  # noqa: F401
+from . import laplacian, solve, rsvd, schur, grad, simplex  # noqa: F401
