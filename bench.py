@@ -52,6 +52,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
 def gather_bytes(N, E, nnz, k, elem=4, covered=None, hubs=0):
@@ -161,7 +162,7 @@ def stored_traffic(kernel, workload, instance):
     return rec["traffic_bytes_per_launch"]
 
 
-def _roof(name, n, ms, alg, bound="hbm", traffic=None):
+def _roof(name, n, ms, alg, bound="hbm", traffic=None, dtype="bf16"):
     avg = ms / max(n, 1)
     if bound == "hbm":
         ach = alg / (avg * 1e-3) / 1e9
@@ -169,8 +170,9 @@ def _roof(name, n, ms, alg, bound="hbm", traffic=None):
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
                 "avg_launch_us": round(avg * 1e3, 2), "launches": n, "algorithmic_bytes_per_launch": int(alg)}
     ach = alg / (avg * 1e-3) / 1e12
-    return {"bound": "mfma", "achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(ach / BF16_PEAK_TFLOPS, 5), "traffic": None, "kernel": name,
+    peak = BF16_PEAK_TFLOPS if dtype == "bf16" else FP32_MFMA_PEAK_TFLOPS
+    return {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s", "dtype": dtype,
+            "frac": round(ach / peak, 5), "traffic": None, "kernel": name,
             "avg_launch_us": round(avg * 1e3, 2), "launches": n, "algorithmic_flops_per_launch": int(alg)}
 
 
@@ -373,6 +375,74 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
                  value, "RHS/s", a.steps, a.warmup, ms, mode, cfg, roof, extra)
 
 
+def bench_schur(a, min_block=50):
+    """The Schur-complement block inverse (eqs. 12-14, nested tessellation
+    down to min_block, exact leaves) of the 50 tessellated blocks, then the
+    solve it preconditions."""
+    import torch
+
+    import synth
+    from paper_1908_08281_amd import hgl
+    dev = torch.device("cuda:0")
+    p = synth.tessellated()
+    nb = len(p.blocks) - 1
+    ep, ev, w = _upload(p, dev)
+    h = hgl.build_laplacian(ep, ev, w, p.N)
+    run = lambda: hgl.block_schur_inverse(h, p.lam, p.blocks, min_block)  # noqa: E731
+    for _ in range(a.warmup):
+        run()
+    flops = hgl.block_schur_plan(p.blocks, min_block)["flops"]
+    hgl.profile(h, True, kinds=["dense_gemm"])
+    dt, _ = _timed(run, a.steps, 0)
+    prof = hgl.profile_read(h)
+    hgl.profile(h, False)
+    breakdown = _breakdown(h, run, max(2, a.steps // 5))
+    n_g, ms_g = prof["dense_gemm"]
+    roof = _roof("k_schur_gemm", n_g, ms_g, flops * a.steps / max(n_g, 1), bound="mfma", dtype="fp32")
+    ms = 1e3 * dt / a.steps
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    tol = 1e-6 / (1 + 1 / p.lam)
+    hgl.block_schur_invert(h, p.lam, p.blocks, Y, min_block=min_block, refine_tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F, it, rel, st = hgl.block_schur_invert(h, p.lam, p.blocks, Y, min_block=min_block, refine_tol=tol)
+    torch.cuda.synchronize()
+    t_inv = time.perf_counter() - t0
+    hgl.block_rsvd_invert(h, p.lam, p.blocks, Y, 64, 10, 2, refine_tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, it_r, rel_r, _, st_r = hgl.block_rsvd_invert(h, p.lam, p.blocks, Y, 64, 10, 2, refine_tol=tol)
+    torch.cuda.synchronize()
+    t_rsvd = time.perf_counter() - t0
+    cfg = {"workload": "block_schur", "N": p.N, "blocks": nb, "block_rows": "U[500,1500]", "min_block": min_block,
+           "products": "fp32 MFMA 16x16x4, fp32 accumulation", "leaves": "fp64 Gauss-Jordan in LDS"}
+    extra = {"kernel_ms": breakdown, "flops_per_batch": flops,
+             "refined_solve": {"nrhs": Y.shape[1], "pcg_iters": int(it.max()), "seconds": round(t_inv, 4),
+                               "converged": st == 0 and bool(np.all(rel <= tol)),
+                               "rsvd_pcg_iters": int(it_r.max()), "rsvd_seconds": round(t_rsvd, 4),
+                               "rsvd_converged": st_r == 0 and bool(np.all(rel_r <= tol))}}
+    if not a.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import laplacian as lap
+        from oracle import schur
+        Hs = lap.incidence_sparse(p.N, p.E, p.edge_ptr, p.edge_vtx)
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            done = 0
+            for b in range(nb):
+                schur.schur_inverse(schur.system_block(Hs, p.w, p.lam, p.blocks[b], p.blocks[b + 1]), min_block)
+                done += 1
+                if time.perf_counter() - t0 > 20.0:
+                    break
+            dtc = time.perf_counter() - t0
+        extra["cpu_baseline"] = {"value": round(done / dtc, 3), "unit": "blocks/s", "cores": 1, "kind": "oracle",
+                                 "sample": f"first {done} of {nb} blocks, FP64 eqs. 12-15 with SVD leaves "
+                                           f"(block extraction included), one thread, {dtc:.1f} s"}
+    return _line("Schur block inverses/s", a.steps * nb / dt, "blocks/s", a.steps, a.warmup, ms, "f32", cfg, roof,
+                 extra)
+
+
 def bench_rsvd(a, scheme="subspace"):
     import torch
 
@@ -389,14 +459,14 @@ def bench_rsvd(a, scheme="subspace"):
     run = lambda: hgl.block_rsvd(h, p.blocks, k, pp, q, omega=om, scheme=scheme)  # noqa: E731
     for _ in range(a.warmup):
         run()
-    hgl.profile(h, True, kinds=["rsvd_gemm"])
+    hgl.profile(h, True, kinds=["dense_gemm"])
     dt, _ = _timed(run, a.steps, 0)
     prof = hgl.profile_read(h)
     hgl.profile(h, False)
     breakdown = _breakdown(h, run, max(2, a.steps // 5))
     sizes = np.diff(p.blocks).astype(np.float64)
     gemm_flops = float(np.sum(2.0 * sizes * sizes * l))           # one product A_bb S per block
-    n_g, ms_g = prof["rsvd_gemm"]
+    n_g, ms_g = prof["dense_gemm"]
     roof = _roof("rsvd_gemm", n_g, ms_g, gemm_flops, bound="mfma")
     nbp = np.ceil(sizes / 64) * 64
     gemm_bytes = float(np.sum(2 * nbp * nbp + 2 * 2 * nbp * 80 + 4 * nbp * 80))
@@ -605,7 +675,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workload", default="multi_rhs",
-                    help="multi_rhs (default), small, rsvd, rsvd_power, single, batch_small, learn, batch, "
+                    help="multi_rhs (default), small, rsvd, rsvd_power, schur, single, batch_small, learn, batch, "
                          "or a comma list")
     ap.add_argument("--rr-period", type=int, default=0)
     ap.add_argument("--tune", type=int, default=1,
@@ -669,6 +739,8 @@ def main():
             out = bench_rsvd(a)
         elif wl == "rsvd_power":
             out = bench_rsvd(a, scheme="power")
+        elif wl == "schur":
+            out = bench_schur(a)
         elif wl == "single":
             out = bench_single(a)
         elif wl == "batch_small":
@@ -679,7 +751,7 @@ def main():
             print(f"unknown workload {wl}", file=sys.stderr)
             sys.exit(2)
         roof = out.get("roofline")
-        if peaks and isinstance(roof, dict):
+        if peaks and isinstance(roof, dict) and (roof["bound"] == "hbm" or roof.get("dtype") == "bf16"):
             meas = peaks["hbm_gbs"] if roof["bound"] == "hbm" else peaks["bf16_mfma_tflops"]
             roof["measured_peak"] = meas
             roof["frac_measured"] = round(roof["achieved"] / meas, 4)

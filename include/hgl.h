@@ -342,6 +342,68 @@ int hgl_block_rsvd_invert(hgl_handle* h, double lambda, int32_t n_blocks,
 int hgl_sketch_gaussian(int64_t rows, int32_t l, uint64_t seed, uint16_t* out_bf16, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Block inverse through Schur complements (paper, section 3, eqs. 12-14)
+ * under nested tessellation, eq. 15 at the smallest submatrices.
+ *
+ * Every diagonal block M_bb = (I + L/lambda)[o_b, o_b+1) of n rows is
+ * split into 2x2 blocks with floor(n/2) rows in the first, recursively
+ * while both halves keep at least min_block rows.  A split block's inverse
+ * is [[Z1^-1, -X11^-1 X12 Z2^-1], [-Z2^-1 X21 X11^-1, Z2^-1]] with
+ * Z1 = X11 - X12 X22^-1 X21 (eq. 13), Z2 = X22 - X21 X11^-1 X12 (eq. 14),
+ * and the four inverses X11^-1, X22^-1, Z1^-1, Z2^-1 are the same
+ * construction one level down.  The smallest submatrices (min_block to
+ * 2 min_block - 1 rows) are inverted exactly (FP64 Gauss-Jordan: eq. 15
+ * with all singular values gives the same matrix); the products run in
+ * FP32 on MFMA.  So the result is M_bb^-1 up to FP32 rounding.
+ *
+ * Limits: single-graph handle; 16 <= min_block <= 64; every block 1 to 4096
+ * rows, offsets covering [0, N).  Errors: HGL_EINVAL (arguments),
+ * HGL_EUNSUPPORTED (a leaf over 127 rows), HGL_EDEVICE.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * The inverse of every diagonal block.  inv_out (device, nullable): the
+ * blocks' inverses packed in block order, block b as n_b x n_b FP32
+ * row-major at element offset sum_{c<b} n_c^2.  flops_out (host, nullable):
+ * the algorithmic flops of the products (2 m n k each).  The workspace
+ * (about 12 sum n_b^2 floats) and the plan stay in the handle and are
+ * reused while the blocks and min_block are unchanged.  Synchronises the
+ * stream.
+ */
+int hgl_block_schur_inverse(hgl_handle* h, double lambda, int32_t n_blocks, const int32_t* block_offsets_host,
+                            int32_t min_block, float* inv_out, double* flops_out, hipStream_t stream);
+
+/*
+ * Solve (I + L/lambda) F = Y (Y, F: N x nrhs FP32, device, row-major) with
+ * the block inverse as the preconditioner: F0 = blockdiag(M_bb^-1) Y, then
+ * preconditioned CG (FP32 vectors, FP64 inner products, residual
+ * replacement) until every column's FP64-recomputed relres is at most
+ * refine_tol or max_refine iterations ran.  chunk as hgl_cg_opts.chunk.
+ * iters_host, relres_host [nrhs] nullable.  Returns as hgl_cg_solve.
+ */
+int hgl_block_schur_invert(hgl_handle* h, double lambda, int32_t n_blocks, const int32_t* block_offsets_host,
+                           int32_t min_block, double refine_tol, int32_t max_refine, int32_t chunk,
+                           const float* Y, int64_t ldy, float* F, int64_t ldf, int32_t nrhs, int32_t* iters_host,
+                           double* relres_host, hipStream_t stream);
+
+/*
+ * The execution plan of hgl_block_schur_inverse, host only (no device call),
+ * for inspection.  counts7: {products, leaves, phases, workspace elements,
+ * inverse elements, product tiles, flops}.  Optional outputs (host, sized
+ * from counts7 by a first call with NULLs):
+ *   tasks  [products x 13]: a, b, c, d (element offsets into the workspace),
+ *          lda, ldb, ldc, ldd, m, n, k, alpha, beta of D = alpha A B + beta C;
+ *   leaves [leaves x 5]: in, out, ldi, ldo, n (out = inverse of in);
+ *   phases [phases x 5]: first tile, tiles, first leaf, leaves, largest leaf;
+ *   tiles  [tiles x 2]: product, (tile row << 16) | tile column (64 x 64);
+ *   moff   [n_blocks]: workspace offset of M_bb (n_b x n_b row-major).
+ * Block b's inverse sits at offset sum_{c<b} n_c^2 (ld n_b).  Within a
+ * phase the leaves and products are independent; phases run in order.
+ */
+int hgl_block_schur_plan(int32_t n_blocks, const int32_t* block_offsets_host, int32_t min_block, int64_t* counts7,
+                         int64_t* tasks, int64_t* leaves, int32_t* phases, int64_t* tiles, int64_t* moff);
+
+/* ------------------------------------------------------------------------
  * Weight derivatives (paper, section 2: P(w) of eq. 4 and the steepest-descent
  * update of w; the paper defers the formula, it is derived from eq. 1).
  * For N x k matrices P, Q:

@@ -49,6 +49,7 @@ I64 = C.c_int64
 D = C.c_double
 I32P = C.POINTER(C.c_int32)
 DP = C.POINTER(C.c_double)
+I64P = C.POINTER(C.c_int64)
 
 # name -> (restype, argtypes); every entry point the header declares
 SIGNATURES = {
@@ -74,6 +75,9 @@ SIGNATURES = {
     "hgl_block_rsvd_invert": (C.c_int, [P, D, I32, I32P, C.POINTER(RsvdOpts), P, P, I64, P, I64, I32, P,
                                         I32P, DP, P]),
     "hgl_sketch_gaussian": (C.c_int, [I64, I32, C.c_uint64, P, P]),
+    "hgl_block_schur_inverse": (C.c_int, [P, D, I32, I32P, I32, P, DP, P]),
+    "hgl_block_schur_invert": (C.c_int, [P, D, I32, I32P, I32, D, I32, I32, P, I64, P, I64, I32, I32P, DP, P]),
+    "hgl_block_schur_plan": (C.c_int, [I32, I32P, I32, I64P, I64P, I64P, I32P, I64P, I64P]),
     "hgl_weight_grad": (C.c_int, [P, D, D, P, I64, P, I64, P, I64, I32, C.POINTER(CgOpts), P, P, I64, I32P, DP, P]),
     "hgl_project_simplex": (C.c_int, [P, P, I32, P]),
     "hgl_profile": (C.c_int, [P, I32]),

@@ -316,6 +316,7 @@ static void free_handle(hgl_handle* h) {
   h->ws_ab.release();
   h->wg_tab.release();
   if (h->rsvd_free) h->rsvd_free(h->rsvd_ws);
+  if (h->schur_free) h->schur_free(h->schur_ws);
   if (h->cg_graph) hipGraphExecDestroy(h->cg_graph);
   if (h->capture_stream) hipStreamDestroy(h->capture_stream);
   if (h->pinned_i) hipHostFree(h->pinned_i);

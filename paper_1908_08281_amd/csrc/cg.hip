@@ -813,13 +813,14 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     auto u = [](const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); };
     uint64_t tol_bits;
     std::memcpy(&tol_bits, &o->tol, sizeof(tol_bits));
-    const std::vector<uint64_t> key = {
+    std::vector<uint64_t> key = {
         sizeof(T), uint64_t(k), uint64_t(G), uint64_t(n), uint64_t(ldy), uint64_t(ldf), u(Y), u(F),
         u(h->ws_vec.p), u(h->ws_z.p), u(h->ws_z64.p), u(h->ws_part.p), u(h->ws_part2.p), u(h->ws_extra[0].p),
         u(h->ws_state.p), u(h->ws_chunk.p), u(h->ws_ab.p), u(h->ws_extra[5].p), u(prec ? prec->ctx : nullptr), uint64_t(o->rr_period),
         tol_bits, uint64_t(cs.GL), uint64_t(cs.V), uint64_t(cs.slabs), uint64_t(cse.GL), uint64_t(cse.V),
         uint64_t(cse.slabs), uint64_t(csv.GL), uint64_t(csv.V), uint64_t(csv.slabs), u(wd.base),
         uint64_t(o->max_iter)};
+    if (prec) for (uint64_t v : prec->key) key.push_back(v);
     if (!h->cg_graph || key != h->cg_graph_key) {
       if (h->cg_graph) {
         HGL_HIP(hipGraphExecDestroy(h->cg_graph));

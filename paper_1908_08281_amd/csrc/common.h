@@ -146,6 +146,9 @@ struct hgl_handle {
   // block rSVD workspace (owned, freed by rsvd_free)
   void* rsvd_ws = nullptr;
   void (*rsvd_free)(void*) = nullptr;
+  // Schur-complement block inverse workspace (owned, freed by schur_free)
+  void* schur_ws = nullptr;
+  void (*schur_free)(void*) = nullptr;
 
   // kernel timing (diagnostics)
   bool prof_on = false;
@@ -241,7 +244,7 @@ int upload_ab(hgl_handle* h, const double* lambdas_host, hipStream_t st);
 enum ProfKind { kProfEdge = 0, kProfVertex = 1, kProfUpdate = 2, kProfDirection = 3,
                 kProfReduce = 4, kProfResidEdge = 5, kProfResidVertex = 6, kProfStart = 7,
                 kProfPrecond = 8, kProfGemm = 9, kProfQr = 10, kProfEig = 11, kProfExtract = 12,
-                kProfGrad = 13, kProfFinish = 14 };
+                kProfGrad = 13, kProfFinish = 14, kProfLeaf = 15 };
 void prof_begin(hgl_handle* h, int kind, hipStream_t s);
 void prof_end(hgl_handle* h, hipStream_t s);
 hipEvent_t prof_event(hgl_handle* h);
@@ -274,10 +277,14 @@ inline void launch(const hgl_handle* hc, int kind, F kernel, dim3 grid, dim3 blo
 
 // Preconditioner for the CG driver: Z = P^-1 R (k columns), with partial
 // inner products <R_j, Z_j> per row tile written to part (nullable).
+// `key` holds what its launches bake in besides R, Z and part (buffer
+// addresses, grid sizes, scalar arguments): a recorded CG graph is replayed
+// only while the key is unchanged.
 struct Precond {
   void* ctx = nullptr;
   int (*apply_f32)(void*, const float*, int64_t, float*, int64_t, double*, int, Gate, hipStream_t) = nullptr;
   int (*apply_f64)(void*, const double*, int64_t, double*, int64_t, double*, int, Gate, hipStream_t) = nullptr;
+  std::array<uint64_t, 8> key{};
 };
 
 // The CG / preconditioned CG driver behind hgl_cg_solve (cg.hip).

@@ -1348,6 +1348,11 @@ extern "C" int hgl_block_rsvd_invert(hgl_handle* h, double lambda, int32_t n_blo
   pc.ctx = &bp;
   pc.apply_f32 = &prec_apply<float>;
   pc.apply_f64 = &prec_apply<double>;
+  uint64_t lam_bits;
+  std::memcpy(&lam_bits, &lambda, sizeof(lam_bits));
+  auto u = [](const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); };
+  pc.key = {u(R.meta.p), u(R.U.p), u(R.dT.p), u(R.Tpart.p), u(R.sig.p), lam_bits, uint64_t(R.nb),
+            uint64_t(R.kk) | uint64_t(R.item_b.size()) << 32};
   hgl_cg_opts co{};
   co.mode = HGL_CG_F32_F64DOT_RR;
   co.tol = o->refine_tol;

@@ -306,6 +306,68 @@ def block_rsvd_invert(h: Handle, lam: float, offsets, Y: torch.Tensor, k: int, p
     return F, iters, rel, sig, st
 
 
+def block_schur_plan(offsets, min_block: int) -> dict:
+    """The execution plan of the Schur-complement block inverse (host only):
+    numpy arrays tasks [n x 13], leaves [n x 5], phases [n x 5], tiles
+    [n x 2], moff [n_blocks] and the counts (see hgl_block_schur_plan)."""
+    off = _offsets(offsets)
+    nb = off.size - 1
+    cnt = np.zeros(7, dtype=np.int64)
+    i64 = lambda a: a.ctypes.data_as(_lib.I64P)
+    check(lib().hgl_block_schur_plan(nb, off.ctypes.data_as(_lib.I32P), int(min_block), i64(cnt), None, None,
+                                      None, None, None), "hgl_block_schur_plan")
+    tasks = np.zeros((int(cnt[0]), 13), dtype=np.int64)
+    leaves = np.zeros((int(cnt[1]), 5), dtype=np.int64)
+    phases = np.zeros((int(cnt[2]), 5), dtype=np.int32)
+    tiles = np.zeros((int(cnt[5]), 2), dtype=np.int64)
+    moff = np.zeros(nb, dtype=np.int64)
+    check(lib().hgl_block_schur_plan(nb, off.ctypes.data_as(_lib.I32P), int(min_block), i64(cnt), i64(tasks),
+                                      i64(leaves), phases.ctypes.data_as(_lib.I32P), i64(tiles), i64(moff)),
+          "hgl_block_schur_plan")
+    return {"tasks": tasks, "leaves": leaves, "phases": phases, "tiles": tiles, "moff": moff,
+            "arena_elems": int(cnt[3]), "inv_elems": int(cnt[4]), "flops": int(cnt[6])}
+
+
+def block_schur_inverse(h: Handle, lam: float, offsets, min_block: int = 50):
+    """Inverses of the diagonal blocks (eqs. 12-15): a list of n_b x n_b FP32
+    device tensors (views of one packed buffer) and the products' flops."""
+    off = _offsets(offsets)
+    nb = off.size - 1
+    sizes = np.diff(off).astype(np.int64)
+    buf = torch.empty(int((sizes * sizes).sum()), dtype=torch.float32, device=h.device)
+    flops = C.c_double(0.0)
+    with torch.cuda.device(h.device):
+        st = lib().hgl_block_schur_inverse(h.ptr, float(lam), nb, off.ctypes.data_as(_lib.I32P), int(min_block),
+                                           _ptr(buf), C.byref(flops), _stream(h.device))
+    check(st, "hgl_block_schur_inverse")
+    out, at = [], 0
+    for n in sizes.tolist():
+        out.append(buf[at:at + n * n].view(n, n))
+        at += n * n
+    return out, flops.value
+
+
+def block_schur_invert(h: Handle, lam: float, offsets, Y: torch.Tensor, min_block: int = 50,
+                       refine_tol: float = 5e-7, max_refine: int = 500, chunk: int = 0):
+    """Block-inverse start + preconditioned CG with the Schur-complement block
+    inverse.  Returns (F, iters, relres, status)."""
+    off = _offsets(offsets)
+    nb = off.size - 1
+    _need(Y, torch.float32, "Y", h.device)
+    ldy = _rows(Y, "Y")
+    nrhs = Y.shape[1]
+    F = torch.empty((h.N, nrhs), dtype=torch.float32, device=h.device)
+    iters = np.zeros(nrhs, dtype=np.int32)
+    rel = np.zeros(nrhs, dtype=np.float64)
+    with torch.cuda.device(h.device):
+        st = lib().hgl_block_schur_invert(h.ptr, float(lam), nb, off.ctypes.data_as(_lib.I32P), int(min_block),
+                                          float(refine_tol), int(max_refine), int(chunk), _ptr(Y), ldy, _ptr(F),
+                                          F.stride(0), nrhs, iters.ctypes.data_as(_lib.I32P),
+                                          rel.ctypes.data_as(_lib.DP), _stream(h.device))
+    check(st, "hgl_block_schur_invert")
+    return F, iters, rel, st
+
+
 def measure_peaks(device, copy_bytes: int = 1 << 30, reps: int = 10) -> dict:
     """Achievable HBM GB/s (a copy of copy_bytes between two buffers, each
     larger than the last-level cache; 2 * copy_bytes moved per copy) and
@@ -391,8 +453,8 @@ def project_simplex(v: torch.Tensor, out: torch.Tensor | None = None) -> torch.T
 
 PROFILE_KINDS = {0: "edge_gather", 1: "vertex_gather", 2: "cg_update", 3: "cg_direction",
                  4: "reduce", 5: "resid_edge_gather", 6: "resid_vertex_gather", 7: "start",
-                 8: "precond", 9: "rsvd_gemm", 10: "cholqr", 11: "jacobi", 12: "extract", 13: "grad",
-                 14: "hub_row_finish"}
+                 8: "precond", 9: "dense_gemm", 10: "cholqr", 11: "jacobi", 12: "extract", 13: "grad",
+                 14: "hub_row_finish", 15: "schur_leaf"}
 
 
 def profile(h: Handle, enable: bool, kinds=None, every: int = 1) -> None:

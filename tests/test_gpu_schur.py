@@ -1,0 +1,157 @@
+"""GPU parity: the Schur-complement block inverse under nested tessellation
+(eqs. 12-15) against the FP64 oracle, and the solve it preconditions.
+
+Bar of the inverse: every entry within 1e-4 of the oracle's.  The products
+run in FP32 (unit roundoff u = 6e-8) over sums of up to n_b / 2 terms, and
+every level feeds its rounding into the next through products with inverses
+of norm at most 1 (the eigenvalues of M lie in [1, 1 + 1/lambda]); a random-
+walk estimate sqrt(n_b) u (1 + 1/lambda) per level over up to 8 levels stays
+below 1e-4 for n_b <= 4096 and lambda >= 0.5.  The solve is held to the
+refinement's relres, like the other solvers."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import laplacian as lap
+from oracle import schur, solve
+from tests.helpers import build, colrelerr, device, hgl, say
+
+pytestmark = pytest.mark.gpu
+
+INV_BAR = 1e-4
+
+
+def _problem(sizes, seed, lam=0.5, k_rhs=6):
+    off = synth.block_offsets(np.array(sizes))
+    N = int(off[-1])
+    ep, ev = synth.uniform_hyperedges(N, int(0.75 * N), 2, 20, seed)
+    E = len(ep) - 1
+    return synth.Problem(N, E, ep, ev, synth.dirichlet_weights(E, seed + 1), lam,
+                         synth.binary_rhs(N, k_rhs, 0.05, seed + 2), blocks=off)
+
+
+def _oracle_blocks(p, blocks):
+    Hs = lap.incidence_sparse(p.N, p.E, p.edge_ptr, p.edge_vtx)
+    return {b: schur.system_block(Hs, p.w, p.lam, p.blocks[b], p.blocks[b + 1]) for b in blocks}
+
+
+@pytest.mark.parametrize("sizes,min_block", [([300, 257, 130, 64, 17], 16), ([700, 99, 100, 101], 50),
+                                             ([513, 64, 128], 64)])
+def test_inverse_against_oracle(sizes, min_block):
+    dev = device()
+    p = _problem(sizes, 300 + min_block)
+    say("schur inverse", sizes, min_block)
+    h = build(p, dev)
+    inv, flops = hgl().block_schur_inverse(h, p.lam, p.blocks, min_block)
+    Ms = _oracle_blocks(p, range(len(sizes)))
+    for b, Mb in Ms.items():
+        want = schur.schur_inverse(Mb, min_block)
+        got = inv[b].cpu().double().numpy()
+        assert np.abs(got - want).max() <= INV_BAR, b
+        assert np.abs(Mb @ got - np.eye(Mb.shape[0])).max() <= 4 * INV_BAR
+    assert flops == hgl().block_schur_plan(p.blocks, min_block)["flops"]
+
+
+def test_repeat_and_replan():
+    """Same blocks again: the kept plan gives the same bits; other blocks on
+    the same handle plan again and stay right."""
+    dev = device()
+    p = _problem([260, 190], 310)
+    h = build(p, dev)
+    a, _ = hgl().block_schur_inverse(h, p.lam, p.blocks, 32)
+    b, _ = hgl().block_schur_inverse(h, p.lam, p.blocks, 32)
+    for x, y in zip(a, b):
+        assert bool((x == y).all())
+    c, _ = hgl().block_schur_inverse(h, p.lam, [0, 100, 450], 40)
+    Ms = _oracle_blocks(synth.Problem(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam, p.Y,
+                                      blocks=np.array([0, 100, 450])), [0, 1])
+    for i, Mb in Ms.items():
+        assert np.abs(c[i].cpu().double().numpy() - schur.schur_inverse(Mb, 40)).max() <= INV_BAR
+
+
+def _block_local(sizes, edges_per_block, seed):
+    rng = synth.rng_for(seed)
+    off = synth.block_offsets(np.array(sizes))
+    edges = []
+    for b, nb in enumerate(sizes):
+        for _ in range(edges_per_block):
+            sz = int(rng.integers(2, 9))
+            edges.append(sorted(rng.choice(nb, size=sz, replace=False) + off[b]))
+    ep, ev = synth.explicit_hyperedges(edges)
+    N, E = int(off[-1]), len(ep) - 1
+    return synth.Problem(N, E, ep, ev, synth.dirichlet_weights(E, seed + 1), 0.6,
+                         synth.binary_rhs(N, 5, 0.1, seed + 2), blocks=off)
+
+
+def test_block_local_hyperedges_solve_at_the_start():
+    """Hyperedges inside blocks: the block inverse is M^-1, so F0 = M^-1 Y
+    already meets the tolerance (no CG iteration beyond the first check)."""
+    import torch
+    dev = device()
+    p = _block_local([240, 130, 301], 120, 320)
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    F, it, rel, st = hgl().block_schur_invert(h, p.lam, p.blocks, Y, min_block=32, refine_tol=1e-5)
+    assert st == 0 and np.all(rel <= 1e-5) and it.max() <= 1
+    M = lap.system_matrix(lap.incidence_dense(p.N, p.E, p.edge_ptr, p.edge_vtx), p.w, p.lam)
+    assert colrelerr(F.cpu().numpy(), solve.solve_dense(M, p.Y)).max() <= 1e-5
+
+
+def test_refined_solve_against_dense_oracle():
+    import torch
+    dev = device()
+    p = synth.tessellated(n_blocks=6, lo=150, hi=300, k_rhs=12)
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    tol = 1e-6 / (1 + 1 / p.lam)
+    F, it, rel, st = hgl().block_schur_invert(h, p.lam, p.blocks, Y, min_block=50, refine_tol=tol)
+    assert st == 0 and np.all(rel <= tol)
+    M = lap.system_matrix(lap.incidence_dense(p.N, p.E, p.edge_ptr, p.edge_vtx), p.w, p.lam)
+    assert colrelerr(F.cpu().numpy(), solve.solve_dense(M, p.Y)).max() <= 1e-6
+    # the exact block inverse needs no more iterations than the rank-k one
+    _, it_r, _, _, _ = hgl().block_rsvd_invert(h, p.lam, p.blocks, Y, 24, 8, 2, refine_tol=tol)
+    assert it.max() <= it_r.max()
+
+
+def test_full_size_tessellation():
+    """The tessellated workload at full size (50 blocks of 500-1500 rows,
+    minimum block 50): sampled blocks' inverses against the oracle, the
+    refined solve against the FP64 Tier-2 oracle on sampled columns."""
+    import torch
+    dev = device()
+    p = synth.tessellated()
+    say("schur full size", p.N)
+    h = build(p, dev)
+    inv, _ = hgl().block_schur_inverse(h, p.lam, p.blocks, 50)
+    for b, Mb in _oracle_blocks(p, (0, 17, 49)).items():
+        got = inv[b].cpu().double().numpy()
+        assert np.abs(got - schur.schur_inverse(Mb, 50)).max() <= INV_BAR, b
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    tol = 1e-6 / (1 + 1 / p.lam)
+    F, it, rel, st = hgl().block_schur_invert(h, p.lam, p.blocks, Y, min_block=50, refine_tol=tol)
+    assert st == 0 and np.all(rel <= tol)
+    op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
+    cols = np.arange(0, p.Y.shape[1], 7)
+    fo, _, _ = solve.cg_ranking(op, p.w, p.lam, p.Y[:, cols], tol=1e-13)
+    assert colrelerr(F.cpu().numpy()[:, cols], fo).max() <= 1e-6
+
+
+def test_argument_errors():
+    import torch
+    from paper_1908_08281_amd._lib import HglError
+    dev = device()
+    p = _problem([200, 100], 330)
+    h = build(p, dev)
+    for mb in (15, 65):
+        with pytest.raises(HglError):
+            hgl().block_schur_inverse(h, p.lam, p.blocks, mb)
+    with pytest.raises(HglError):
+        hgl().block_schur_inverse(h, p.lam, [0, 100, 299], 32)   # does not cover [0, N)
+    with pytest.raises(HglError):
+        hgl().block_schur_inverse(h, -1.0, p.blocks, 32)
+    Y = torch.zeros((p.N, 3), dtype=torch.float32, device=dev)
+    with pytest.raises(HglError):
+        hgl().block_schur_invert(h, p.lam, p.blocks, Y, min_block=32, refine_tol=0.0)
+    # a zero right-hand side solves to zero at once
+    F, it, rel, st = hgl().block_schur_invert(h, p.lam, p.blocks, Y, min_block=32)
+    assert st == 0 and float(F.abs().max()) == 0.0
