@@ -415,7 +415,7 @@ def bench_schur(a, min_block=50):
     torch.cuda.synchronize()
     t_rsvd = time.perf_counter() - t0
     cfg = {"workload": "block_schur", "N": p.N, "blocks": nb, "block_rows": "U[500,1500]", "min_block": min_block,
-           "products": "fp32 MFMA 16x16x4, fp32 accumulation", "leaves": "fp64 Gauss-Jordan in LDS"}
+           "products": "fp32 MFMA 16x16x4, fp32 accumulation", "leaves": "fp32 Gauss-Jordan in registers"}
     extra = {"kernel_ms": breakdown, "flops_per_batch": flops,
              "refined_solve": {"nrhs": Y.shape[1], "pcg_iters": int(it.max()), "seconds": round(t_inv, 4),
                                "converged": st == 0 and bool(np.all(rel <= tol)),

@@ -352,9 +352,10 @@ int hgl_sketch_gaussian(int64_t rows, int32_t l, uint64_t seed, uint16_t* out_bf
  * Z1 = X11 - X12 X22^-1 X21 (eq. 13), Z2 = X22 - X21 X11^-1 X12 (eq. 14),
  * and the four inverses X11^-1, X22^-1, Z1^-1, Z2^-1 are the same
  * construction one level down.  The smallest submatrices (min_block to
- * 2 min_block - 1 rows) are inverted exactly (FP64 Gauss-Jordan: eq. 15
- * with all singular values gives the same matrix); the products run in
- * FP32 on MFMA.  So the result is M_bb^-1 up to FP32 rounding.
+ * 2 min_block - 1 rows) are inverted by Gauss-Jordan elimination (eq. 15
+ * with all singular values gives the same matrix), in FP32 like the
+ * products, which run on MFMA.  So the result is M_bb^-1 up to FP32
+ * rounding.
  *
  * Limits: single-graph handle; 16 <= min_block <= 64; every block 1 to 4096
  * rows, offsets covering [0, N).  Errors: HGL_EINVAL (arguments),

@@ -11,11 +11,12 @@
 //   Z1^-1, Z2^-1                             (child nodes, into the output)
 //   top right = -T3 Z2^-1, bottom left = -Z2^-1 T2 (eq. 12)
 // The smallest submatrices (min_block .. 2 min_block - 1 rows) are inverted
-// exactly in FP64 by Gauss-Jordan elimination in LDS: eq. 15 with all of a
+// by Gauss-Jordan elimination in FP32 registers: eq. 15 with all of a
 // submatrix's singular values is its exact inverse, and any exact method
-// gives the same matrix.  No pivoting: every matrix inverted here is a
-// diagonal block of a symmetric positive definite matrix or a Schur
-// complement of one, so it is symmetric positive definite too.
+// gives the same matrix up to rounding.  No pivoting: every matrix inverted
+// here is a diagonal block of a symmetric positive definite matrix or a
+// Schur complement of one, so it is symmetric positive definite too, with
+// its eigenvalues in [1, 1 + 1/lambda] like those of M.
 //
 // Nodes run in phases: a node's two first children run in one phase range,
 // its first products after them, and so on; one phase's products and
@@ -32,11 +33,13 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kLeafMax = 127;   // rows of the largest leaf: its FP64 matrix fits in LDS
+constexpr int kLeafMax = 127;   // rows of the largest leaf: one thread column per leaf column
 constexpr int kMinBlockLo = 16, kMinBlockHi = 64;
 constexpr int kMaxBlock = 4096;  // rows of a diagonal block (the extraction stages 4 FP64 rows)
 constexpr int kGT = 64;          // product tile: 64 x 64 outputs per workgroup
 constexpr int kGK = 16;          // k-depth of one LDS stage
+constexpr int kAPT = kGT * kGK / kBlock;  // elements of A (and of B) a thread stages
+static_assert(kGK % kAPT == 0 && kGT % kAPT == 0 && kBlock == (kGK / kAPT) * kGT, "stage mapping");
 
 // D = alpha A B + beta C over FP32 row-major views of the arena (element
 // offsets).  In the preconditioner's products b and d are first rows of
@@ -131,19 +134,20 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
     ldd = t.ldd;
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ar = tid >> 2, ak = (tid & 3) * 4;   // A stage: row, first k
-  const int bk = tid >> 4, bc = (tid & 15) * 4;  // B stage: k, first column
-  float ra[4], rb[4];
+  constexpr int kAT = kGK / kAPT, kBT = kGT / kAPT;  // threads per row of the A and B stages
+  const int ar = tid / kAT, ak = (tid % kAT) * kAPT;  // A stage: row, first k
+  const int bk = tid / kBT, bc = (tid % kBT) * kAPT;  // B stage: k, first column
+  float ra[kAPT], rb[kAPT];
   auto load = [&](int k0) {
     const int gr = m0 + ar;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kAPT; ++j) {
       const int gk = k0 + ak + j;
       ra[j] = (gr < t.m && gk < t.k) ? A[int64_t(gr) * t.lda + gk] : 0.f;
     }
     const int gk = k0 + bk;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kAPT; ++j) {
       const int gc = n0 + bc + j;
       rb[j] = (gk < t.k && gc < t.n) ? B[int64_t(gk) * ldb + gc] : 0.f;
     }
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
   load(0);
   for (int k0 = 0; k0 < t.k; k0 += kGK) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kAPT; ++j) {
       As[ak + j][ar] = ra[j];
       Bs[bk][bc + j] = rb[j];
     }
@@ -194,40 +198,70 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
     }
 }
 
-// In-place Gauss-Jordan inverse of one leaf in LDS (FP64): at step k the
-// pivot row is scaled by 1/p (its pivot entry becomes 1/p), and every other
-// row i loses X[i][k] times it (its entry in column k becomes -X[i][k]/p).
-// Thread (c, r0) owns column c of rows r0, r0 + 2, ...
-__global__ __launch_bounds__(kBlock) void k_schur_leaf(const LeafTask* __restrict__ tasks, float* __restrict__ arena) {
-  extern __shared__ double L[];
+// Gauss-Jordan inverse of one leaf (FP32), in place in registers: thread
+// (c, g) holds column c of rows g, g + 4, g + 8, ... of the leaf padded to
+// 128 x 128 with the identity (the padding stays the identity, so it needs
+// no bounds checks).  At step k the pivot row is scaled by 1/p (its pivot
+// entry becomes 1/p) and every other row i loses X[i][k] times it (its
+// entry in column k becomes -X[i][k]/p).  With row k and column k zeroed
+// first and -1 stored as row k's entry of the column, every entry takes the
+// same update x -= col[r] * row[c] (row[k] = 1/p, row[c] = X[k][c]/p).  Row
+// k and column k go through LDS, double-buffered by step parity, so one
+// barrier per step suffices: a buffer is written again two steps later,
+// after every thread has passed the barrier that follows its last read.
+constexpr int kLeafThreads = 1024;
+constexpr int kLeafGroups = kLeafThreads / 128;      // row groups
+constexpr int kLeafSlots = 128 / kLeafGroups;        // rows held per thread
+static_assert(kLeafMax < 128, "a leaf fits the padded 128 x 128 layout");
+__global__ __launch_bounds__(kLeafThreads) void k_schur_leaf(const LeafTask* __restrict__ tasks,
+                                                             float* __restrict__ arena) {
+  __shared__ float rowb[2][128];
+  __shared__ float colb[2][128];
   const LeafTask t = tasks[blockIdx.x];
   const int n = t.n;
-  double* X = L;
-  double* rowk = L + n * n;
-  double* colk = rowk + n;
-  const int c = threadIdx.x & 127, r0 = threadIdx.x >> 7;
-  if (c < n)
-    for (int r = r0; r < n; r += 2) X[r * n + c] = double(arena[t.in + int64_t(r) * t.ldi + c]);
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double inv = 1.0 / X[k * n + k];
-    if (threadIdx.x < n) {
-      const int j = threadIdx.x;
-      rowk[j] = j == k ? inv : X[k * n + j] * inv;
-      colk[j] = j == k ? 0.0 : X[j * n + k];
-    }
-    __syncthreads();
-    if (c < n) {
-      const double rk = rowk[c];
-      for (int r = r0; r < n; r += 2) {
-        const double x = c == k ? 0.0 : X[r * n + c];
-        X[r * n + c] = r == k ? rk : x - colk[r] * rk;
-      }
-    }
-    __syncthreads();
+  const int c = threadIdx.x & 127, g = threadIdx.x >> 7;
+  float x[kLeafSlots];
+#pragma unroll
+  for (int j = 0; j < kLeafSlots; ++j) {
+    const int r = g + kLeafGroups * j;
+    x[j] = (c < n && r < n) ? arena[t.in + int64_t(r) * t.ldi + c] : (r == c ? 1.0f : 0.0f);
   }
-  if (c < n)
-    for (int r = r0; r < n; r += 2) arena[t.out + int64_t(r) * t.ldo + c] = float(X[r * n + c]);
+  for (int k = 0; k < n; ++k) {
+    float* rowk = rowb[k & 1];
+    float* colk = colb[k & 1];
+    const bool owner = g == (k & (kLeafGroups - 1));  // holds row k, in slot jk
+    const int jk = k / kLeafGroups;
+    if (c == k) {
+#pragma unroll
+      for (int j = 0; j < kLeafSlots; ++j) colk[g + kLeafGroups * j] = (owner && j == jk) ? -1.0f : x[j];
+    }
+    if (owner) {
+#pragma unroll
+      for (int j = 0; j < kLeafSlots; ++j)
+        if (j == jk) rowk[c] = x[j];
+    }
+    if (c == k) {
+#pragma unroll
+      for (int j = 0; j < kLeafSlots; ++j) x[j] = 0.0f;
+    }
+    if (owner) {
+#pragma unroll
+      for (int j = 0; j < kLeafSlots; ++j)
+        if (j == jk) x[j] = 0.0f;
+    }
+    __syncthreads();
+    const float inv = 1.0f / rowk[k];
+    const float rk = (c == k ? 1.0f : rowk[c]) * inv;
+#pragma unroll
+    for (int j = 0; j < kLeafSlots; ++j) x[j] = fma(-colk[g + kLeafGroups * j], rk, x[j]);
+  }
+  if (c < n) {
+#pragma unroll
+    for (int j = 0; j < kLeafSlots; ++j) {
+      const int r = g + kLeafGroups * j;
+      if (r < n) arena[t.out + int64_t(r) * t.ldo + c] = x[j];
+    }
+  }
 }
 
 // Partial <R_j, Z_j> per CG row tile (FP64), long-row slots zeroed.
@@ -505,22 +539,18 @@ int allow_lds(K kernel, size_t bytes) {
   return HGL_OK;
 }
 
-size_t leaf_lds(int n) { return sizeof(double) * (size_t(n) * n + 2 * size_t(n)); }
-
 // Extract every M_bb and invert it through the phases.
 int schur_run(hgl_handle* h, Schur& S, double lambda, hipStream_t s) {
   const double a = 1.0 + 1.0 / lambda, b = 1.0 / lambda;
   float* arena = S.arena.as<float>();
   const size_t ex_lds = sizeof(double) * 4 * size_t(S.max_n);
   HGL_TRY(allow_lds(k_schur_extract, ex_lds));
-  HGL_TRY(allow_lds(k_schur_leaf, leaf_lds(S.max_leaf)));
   launch(h, kProfExtract, k_schur_extract, dim3((S.max_n + 3) / 4, S.nb), dim3(kBlock), uint32_t(ex_lds), s, S.d_boff,
          S.d_moff, h->vtx_ptr, h->vtx_edge, h->edge_ptr, h->edge_vtx, h->s64, h->c64, a, b, arena, S.max_n);
   HGL_HIP(hipGetLastError());
   for (const Phase& ph : S.phases) {
     if (ph.leaves > 0) {
-      launch(h, kProfLeaf, k_schur_leaf, dim3(ph.leaves), dim3(kBlock), uint32_t(leaf_lds(ph.leaf_n)), s,
-             S.d_leaves + ph.leaf0, arena);
+      launch(h, kProfLeaf, k_schur_leaf, dim3(ph.leaves), dim3(kLeafThreads), 0, s, S.d_leaves + ph.leaf0, arena);
       HGL_HIP(hipGetLastError());
     }
     if (ph.tiles > 0) {
