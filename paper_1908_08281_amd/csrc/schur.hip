@@ -99,8 +99,8 @@ __global__ __launch_bounds__(kBlock) void k_schur_extract(const int32_t* __restr
   }
 }
 
-// One 64 x 64 output tile per workgroup; four waves of 32 x 32, each as
-// 2 x 2 MFMA 16x16x4 tiles.  A is staged k-major and B row-major in LDS, 16
+// One kGT x kGT output tile per workgroup; four waves of kGT/2 x kGT/2,
+// each as kGT/32 x kGT/32 MFMA 16x16x4 tiles.  A is staged k-major and B row-major in LDS, 16
 // deep; the next stage's loads are issued before this stage's MFMAs.
 // MFMA 16x16x4 f32 lane layout: lane l holds A[l%16][l/16], B[l/16][l%16]
 // and D[4(l/16)+v][l%16], v < 4.
@@ -152,12 +152,13 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
       rb[j] = (gk < t.k && gc < t.n) ? B[int64_t(gk) * ldb + gc] : 0.f;
     }
   };
-  floatx4 acc[2][2];
+  constexpr int kWT = kGT / 2, kFT = kWT / 16;  // wave tile, MFMA fragments along each side
+  floatx4 acc[kFT][kFT];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < kFT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    for (int j = 0; j < kFT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int wr = (wave >> 1) * kWT, wc = (wave & 1) * kWT;
   const int r = lane & 15, q = lane >> 4;
   load(0);
   for (int k0 = 0; k0 < t.k; k0 += kGK) {
@@ -170,19 +171,23 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
     if (k0 + kGK < t.k) load(k0 + kGK);
 #pragma unroll
     for (int kk = 0; kk < kGK; kk += 4) {
-      const float a0 = As[kk + q][wr + r], a1 = As[kk + q][wr + 16 + r];
-      const float b0 = Bs[kk + q][wc + r], b1 = Bs[kk + q][wc + 16 + r];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      float a[kFT], b[kFT];
+#pragma unroll
+      for (int i = 0; i < kFT; ++i) {
+        a[i] = As[kk + q][wr + 16 * i + r];
+        b[i] = Bs[kk + q][wc + 16 * i + r];
+      }
+#pragma unroll
+      for (int i = 0; i < kFT; ++i)
+#pragma unroll
+        for (int j = 0; j < kFT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < kFT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < kFT; ++j) {
       const int col = n0 + wc + j * 16 + r;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
