@@ -6,6 +6,10 @@ multipliers (eq. 5); the projected-gradient form w+ = Proj(w - eta g) uses the
 same constraints.  The projection is max(v - tau, 0) with tau chosen so the
 result sums to one (Held, Wolfe and Crowder 1974; Duchi et al. 2008); found
 here by sorting.
+
+The paper's own rule is also here (active_set_direction, active_set_step):
+steepest descent on the Lagrangian of eq. 5 with the active constraints'
+multipliers, and a step shortened to stay feasible.
 """
 from __future__ import annotations
 
@@ -39,3 +43,52 @@ def project_bruteforce(v) -> np.ndarray:
             if d < best_d:
                 best, best_d = np.maximum(w, 0.0), d
     return best
+
+
+def active_set_direction(w, g):
+    """Steepest descent on the Lagrangian of eq. 5: S = P + c_1 (1'w - 1) +
+    sum over the active bounds of c_j w_i.  The multipliers make -grad S the
+    steepest direction that keeps every active constraint: the projection of
+    -g onto {d : sum(d) = 0, d_i >= 0 where w_i = 0}, i.e.
+        d_i = nu - g_i            where w_i > 0,
+        d_i = max(nu - g_i, 0)    where w_i = 0,
+    with nu (= -c_1) the root of sum(d) = 0.  A bound stays active (d_i = 0,
+    multiplier c_j = g_i - nu >= 0) where g_i >= nu and is released where
+    g_i < nu.  The sum is increasing in nu, with slope at least the number of
+    positive weights, so the root is unique; it is found here by walking the
+    sorted breakpoints g_i of the zero weights.
+    Returns (d, nu)."""
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    free = w > 0
+    if not free.any():
+        raise ValueError("w has no positive entry (it is not on the simplex)")
+    bps = np.sort(g[~free])
+    s, c = g[free].sum(), int(free.sum())
+    nu = s / c
+    for b in bps:            # release breakpoints below the current root
+        if b >= nu:
+            break
+        s += b
+        c += 1
+        nu = s / c
+    d = np.where(free, nu - g, np.maximum(nu - g, 0.0))
+    return d, nu
+
+
+def active_set_step(w, g, mu: float):
+    """w_new = w - mu_eff grad S = w + mu_eff d, with mu_eff the largest step
+    up to mu that keeps w >= 0 (ratio test over the entries with d_i < 0);
+    the entries that reach 0 with it are set to exactly 0 and join the active
+    set.  Returns (w_new, d, nu, mu_eff)."""
+    w = np.asarray(w, dtype=np.float64)
+    d, nu = active_set_direction(w, g)
+    neg = d < 0
+    mu_eff = float(mu)
+    ratios = np.full(w.size, np.inf)
+    ratios[neg] = w[neg] / -d[neg]
+    if neg.any():
+        mu_eff = min(mu_eff, float(ratios.min()))
+    w_new = w + mu_eff * d
+    w_new[neg & (ratios <= mu_eff)] = 0.0
+    return w_new, d, nu, mu_eff
