@@ -663,9 +663,24 @@ def bench_learn(a):
            "eta": eta, "cg": "f32 vectors, fp64 inner products, residual replacement at convergence checks; "
                              "forward solve, adjoint solve, FP64 gradient contractions, simplex projection per step",
            "cg_iters_last": recs[-1]["cg_iters"], "adjoint_iters_last": recs[-1]["adjoint_iters"]}
+    extra = {"kernel_ms": _breakdown(h, lambda: learn_weights(h, Y, p.lam, mu, 1, wl, eta=eta, tol=tol), 1)}
+    # the paper's active-set rule of eq. 5 in the same loop, after the timed
+    # steps, and the two step kernels alone on one gradient
+    t0 = time.perf_counter()
+    wa, ra = learn_weights(h, Y, p.lam, mu, a.steps, wl.clone(), eta=eta, tol=tol, history=True, rule="active_set")
+    torch.cuda.synchronize()
+    dta = time.perf_counter() - t0
+    hgl.set_weights(h, wl)
+    F, _, _, _ = hgl.cg_solve(h, p.lam, Y, tol=tol)
+    g, _, _, _ = hgl.weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=tol)
+    d_proj, _ = _timed(lambda: hgl.project_simplex(wl - eta * g), 20, 2)
+    d_act, _ = _timed(lambda: hgl.active_set_step(wl, g, eta), 20, 2)
+    extra["active_set_rule"] = {"steps_per_s": round(a.steps / dta, 3), "mu_eff_last": ra[-1]["mu_eff"],
+                                "released_last": ra[-1]["released"], "active_last": ra[-1]["active"],
+                                "step_us": round(1e6 * d_act / 20, 2),
+                                "projection_step_us": round(1e6 * d_proj / 20, 2)}
     return _line("projected-gradient steps/s", a.steps / dt, "steps/s", a.steps, a.warmup, 1e3 * dt / a.steps,
-                 "f32", cfg, roof, {"kernel_ms": _breakdown(
-                     h, lambda: learn_weights(h, Y, p.lam, mu, 1, wl, eta=eta, tol=tol), 1)})
+                 "f32", cfg, roof, extra)
 
 
 def main():

@@ -441,6 +441,25 @@ int hgl_weight_grad(hgl_handle* h, double lambda, double mu, const void* F, int6
 int hgl_project_simplex(const double* v, double* w, int32_t E, hipStream_t stream);
 
 /*
+ * One steepest-descent step on the Lagrangian of eq. 5 (the paper's active-
+ * set rule): w_out = w - mu_eff grad S.  The multipliers of the active
+ * constraints (1'w = 1, and w_i = 0 for the zero weights that stay at the
+ * bound) make d = -grad S the projection of -g onto {sum d = 0, d_i >= 0
+ * where w_i = 0}: d_i = nu - g_i where w_i > 0, max(nu - g_i, 0) where
+ * w_i = 0, nu the unique root of sum d = 0 (a zero weight with g_i >= nu
+ * stays active with multiplier g_i - nu; one with g_i < nu is released).
+ * mu_eff = min(mu, min over d_i < 0 of w_i / -d_i): the step stops where a
+ * positive weight reaches 0, which is then set to exactly 0.
+ * w (on the simplex), g: device FP64 [E]; w_out (may alias w), d_out
+ * (nullable): device FP64 [E].  info_dev: device FP64 [4] = {nu, mu_eff,
+ * released zero weights, active zero weights}, nu = NaN when w has no
+ * positive entry.  info_host (nullable): copied there after a stream
+ * synchronisation; the call then returns HGL_EINVAL for such a w.  mu > 0.
+ */
+int hgl_active_set_step(const double* w, const double* g, double mu, int32_t E, double* w_out, double* d_out,
+                        double* info_dev, double* info_host, hipStream_t stream);
+
+/*
  * Kernel timing (diagnostics).  hgl_profile(h, enable) resets the counters;
  * with enable = 1 every later solver call on h launches its kernels with
  * start/stop events that the runtime stamps at each kernel's own start and

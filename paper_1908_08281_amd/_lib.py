@@ -80,6 +80,7 @@ SIGNATURES = {
     "hgl_block_schur_plan": (C.c_int, [I32, I32P, I32, I64P, I64P, I64P, I32P, I64P, I64P]),
     "hgl_weight_grad": (C.c_int, [P, D, D, P, I64, P, I64, P, I64, I32, C.POINTER(CgOpts), P, P, I64, I32P, DP, P]),
     "hgl_project_simplex": (C.c_int, [P, P, I32, P]),
+    "hgl_active_set_step": (C.c_int, [P, P, D, I32, P, P, P, DP, P]),
     "hgl_profile": (C.c_int, [P, I32]),
     "hgl_profile_read": (C.c_int, [P, I32, C.POINTER(C.c_int64), DP]),
 }

@@ -212,6 +212,122 @@ __global__ __launch_bounds__(kProj) void k_project_simplex(int32_t E, const doub
   for (int i = threadIdx.x; i < E; i += kProj) w[i] = fmax(v[i] - tau, 0.0);
 }
 
+// ------------------------------------------------ active-set step (eq. 5) --
+
+// Minimum over the workgroup, returned to every thread (fixed order).
+__device__ double block_min(double x, double* lds /* [kProjWaves * kSect] */) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = fmin(x, __shfl_xor(x, off, kWave));
+  if (threadIdx.x % kWave == 0) lds[(threadIdx.x / kWave) * kSect] = x;
+  __syncthreads();
+  double m = INFINITY;
+  for (int w = 0; w < kProjWaves; ++w) m = fmin(m, lds[w * kSect]);
+  __syncthreads();
+  return m;
+}
+
+// Steepest descent on the Lagrangian of eq. 5 in one workgroup of kProj
+// threads.  The direction is the projection of -g onto the constraints that
+// stay active: d_i = nu - g_i where w_i > 0, max(nu - g_i, 0) where w_i = 0,
+// with nu the root of phi(nu) = sum d_i = 0 (phi increases, with slope at
+// least the number of positive weights, so the root is unique and lies in
+// [min g, max g]).  Sectioning passes narrow the bracket as in the
+// projection; then, from the upper end (phi >= 0), nu <- the mean of g over
+// the positive weights and the zero weights with g_i < nu decreases to the
+// root and stops once that set is stable.  The step mu_eff = min(mu, min
+// over d_i < 0 of w_i / -d_i) keeps w >= 0; the entries at the bound get
+// exactly 0.  info = {nu, mu_eff, released zero weights, active zero
+// weights}; nu = NaN when w has no positive entry (then w_out = w).
+__global__ __launch_bounds__(kProj) void k_active_set_step(int32_t E, const double* __restrict__ w,
+                                                           const double* __restrict__ g, double mu,
+                                                           double* w_out, double* __restrict__ d_out,
+                                                           double* __restrict__ info) {
+  __shared__ double lds[kProjWaves * kSect];
+  double mn = INFINITY, mx = -INFINITY, np_[1] = {0.0};
+  for (int i = threadIdx.x; i < E; i += kProj) {
+    mn = fmin(mn, g[i]);
+    mx = fmax(mx, g[i]);
+    if (w[i] > 0.0) np_[0] += 1.0;
+  }
+  mn = block_min(mn, lds);
+  mx = -block_min(-mx, lds);
+  block_sums<1>(np_, lds);
+  if (np_[0] == 0.0) {
+    for (int i = threadIdx.x; i < E; i += kProj) {
+      w_out[i] = w[i];
+      if (d_out) d_out[i] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+      info[0] = NAN;
+      info[1] = 0.0;
+      info[2] = 0.0;
+      info[3] = double(E);
+    }
+    return;
+  }
+  double lo = mn, hi = mx;
+  for (int pass = 0; pass < 7 && hi > lo; ++pass) {
+    double t[kSect], f[kSect];
+#pragma unroll
+    for (int m = 0; m < kSect; ++m) {
+      t[m] = lo + (hi - lo) * double(m + 1) / double(kSect + 1);
+      f[m] = 0.0;
+    }
+    for (int i = threadIdx.x; i < E; i += kProj) {
+      const double gi = g[i];
+      const bool pos = w[i] > 0.0;
+#pragma unroll
+      for (int m = 0; m < kSect; ++m) f[m] += pos ? t[m] - gi : fmax(t[m] - gi, 0.0);
+    }
+    block_sums<kSect>(f, lds);
+    // phi increases: the root lies after the last point with phi < 0
+    double nlo = lo, nhi = hi;
+#pragma unroll
+    for (int m = 0; m < kSect; ++m) {
+      if (f[m] < 0.0) nlo = t[m];
+      else if (nhi == hi) nhi = t[m];
+    }
+    lo = nlo;
+    hi = nhi;
+  }
+  double nu = hi;
+  for (int round = 0; round < 64; ++round) {
+    double sc[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < E; i += kProj)
+      if (w[i] > 0.0 || g[i] < nu) {
+        sc[0] += g[i];
+        sc[1] += 1.0;
+      }
+    block_sums<2>(sc, lds);
+    const double n2 = sc[0] / sc[1];
+    if (!(n2 < nu)) break;
+    nu = n2;
+  }
+  double rmin = INFINITY, cnt[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < E; i += kProj) {
+    const double wi = w[i], gi = g[i];
+    const double di = wi > 0.0 ? nu - gi : fmax(nu - gi, 0.0);
+    if (di < 0.0) rmin = fmin(rmin, wi / -di);
+    if (!(wi > 0.0)) cnt[di > 0.0 ? 0 : 1] += 1.0;
+  }
+  rmin = block_min(rmin, lds);
+  block_sums<2>(cnt, lds);
+  const double me = fmin(mu, rmin);
+  for (int i = threadIdx.x; i < E; i += kProj) {
+    const double wi = w[i], gi = g[i];
+    const double di = wi > 0.0 ? nu - gi : fmax(nu - gi, 0.0);
+    const bool hit = di < 0.0 && wi / -di <= me;
+    w_out[i] = hit ? 0.0 : wi + me * di;
+    if (d_out) d_out[i] = di;
+  }
+  if (threadIdx.x == 0) {
+    info[0] = nu;
+    info[1] = me;
+    info[2] = cnt[0];
+    info[3] = cnt[1];
+  }
+}
+
 // ------------------------------------------------------------------ driver --
 
 template <class T>
@@ -347,5 +463,20 @@ extern "C" int hgl_project_simplex(const double* v, double* w, int32_t E, hipStr
   HGL_CHECK_ARG(E >= 1 && v && w, "need E >= 1 and v, w");
   hipLaunchKernelGGL(k_project_simplex, dim3(1), dim3(kProj), 0, s, E, v, w);
   HGL_HIP(hipGetLastError());
+  return HGL_OK;
+}
+
+extern "C" int hgl_active_set_step(const double* w, const double* g, double mu, int32_t E, double* w_out,
+                                   double* d_out, double* info_dev, double* info_host, hipStream_t s) {
+  clear_error();
+  HGL_CHECK_ARG(E >= 1 && w && g && w_out && info_dev, "need E >= 1 and w, g, w_out, info_dev");
+  HGL_CHECK_ARG(mu > 0.0 && std::isfinite(mu), "mu must be > 0 and finite");
+  hipLaunchKernelGGL(k_active_set_step, dim3(1), dim3(kProj), 0, s, E, w, g, mu, w_out, d_out, info_dev);
+  HGL_HIP(hipGetLastError());
+  if (info_host) {
+    HGL_HIP(hipMemcpyAsync(info_host, info_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HGL_HIP(hipStreamSynchronize(s));
+    HGL_CHECK_ARG(!std::isnan(info_host[0]), "w has no positive entry (it is not on the simplex)");
+  }
   return HGL_OK;
 }

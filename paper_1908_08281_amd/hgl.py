@@ -451,6 +451,26 @@ def project_simplex(v: torch.Tensor, out: torch.Tensor | None = None) -> torch.T
     return w
 
 
+def active_set_step(w: torch.Tensor, g: torch.Tensor, mu: float, out: torch.Tensor | None = None,
+                    direction: bool = False):
+    """One steepest-descent step on the Lagrangian of eq. 5 (active-set
+    rule, ratio-test step).  Returns (w_new, info dict, d or None)."""
+    _need(w, torch.float64, "w")
+    _need(g, torch.float64, "g", w.device)
+    if w.numel() != g.numel():
+        raise ValueError("w and g differ in length")
+    w_new = torch.empty_like(w) if out is None else out
+    d = torch.empty_like(w) if direction else None
+    info_dev = torch.empty(4, dtype=torch.float64, device=w.device)
+    info = np.zeros(4, dtype=np.float64)
+    with torch.cuda.device(w.device):
+        check(lib().hgl_active_set_step(_ptr(w), _ptr(g), float(mu), w.numel(), _ptr(w_new),
+                                        _ptr(d) if d is not None else None, _ptr(info_dev),
+                                        info.ctypes.data_as(_lib.DP), _stream(w.device)), "hgl_active_set_step")
+    return w_new, {"nu": float(info[0]), "mu_eff": float(info[1]), "released": int(info[2]),
+                   "active": int(info[3])}, d
+
+
 PROFILE_KINDS = {0: "edge_gather", 1: "vertex_gather", 2: "cg_update", 3: "cg_direction",
                  4: "reduce", 5: "resid_edge_gather", 6: "resid_vertex_gather", 7: "start",
                  8: "precond", 9: "dense_gemm", 10: "cholqr", 11: "jacobi", 12: "extract", 13: "grad",

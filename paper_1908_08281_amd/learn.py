@@ -43,9 +43,11 @@ class HypergraphSolve(torch.autograd.Function):
 
 def learn_weights(handle, Y: torch.Tensor, lam: float, mu: float, steps: int, w0: torch.Tensor,
                   eta: float | None = None, tol: float = 1e-6, mode: str = "f32", history: bool = False,
-                  rr_period: int = 0):
-    """Projected-gradient descent on the simplex for the adaptive-weight
-    objective.  eta None: fixed step 0.5 ||w0||_inf / ||g0 - mean(g0)||_inf
+                  rr_period: int = 0, rule: str = "projection"):
+    """Descent on the simplex for the adaptive-weight objective.  rule
+    "projection": w <- Proj(w - eta g); "active_set": the steepest-descent
+    step on the Lagrangian of eq. 5 with its active constraints
+    (hgl.active_set_step, the step shortened to stay feasible).  eta None: fixed step 0.5 ||w0||_inf / ||g0 - mean(g0)||_inf
     chosen at step 0.  rr_period: periodic residual replacement of the
     forward solves (0: only at the claim checks, which verify every column's
     FP64 residual anyway).  Returns (w, per-step records)."""
@@ -58,9 +60,18 @@ def learn_weights(handle, Y: torch.Tensor, lam: float, mu: float, steps: int, w0
         if eta is None:
             gc = g - g.mean()
             eta = float(0.5 * w.abs().max() / gc.abs().max().clamp_min(1e-300))
-        w = hgl.project_simplex(w - eta * g)
+        info = None
+        if rule == "projection":
+            w = hgl.project_simplex(w - eta * g)
+        elif rule == "active_set":
+            w, info, _ = hgl.active_set_step(w, g, eta)
+        else:
+            raise ValueError(f"unknown rule {rule!r}")
         if history:
-            recs.append({"step": t, "cg_iters": int(iters.max()), "adjoint_iters": int(ait.max()),
-                         "grad_norm": float(g.norm()), "eta": eta})
+            rec = {"step": t, "cg_iters": int(iters.max()), "adjoint_iters": int(ait.max()),
+                   "grad_norm": float(g.norm()), "eta": eta}
+            if info is not None:
+                rec.update(info)
+            recs.append(rec)
     hgl.set_weights(handle, w)
     return w, recs
