@@ -322,6 +322,12 @@ struct Schur {
   const GemmTask* p_tasks = nullptr;
   const int32_t* p_tile_task = nullptr;
   const int32_t* p_tile_mn = nullptr;
+  // the inverse's launches recorded as a HIP graph, replayed while the key
+  // (buffers, plan, lambda) is unchanged
+  uint64_t plan_gen = 0;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph = nullptr;
+  std::vector<uint64_t> graph_key;
 };
 
 void schur_delete(void* p) {
@@ -329,6 +335,8 @@ void schur_delete(void* p) {
   S->arena.release();
   S->meta.release();
   S->pmeta.release();
+  if (S->graph) hipGraphExecDestroy(S->graph);
+  if (S->cap) hipStreamDestroy(S->cap);
   delete S;
 }
 
@@ -529,6 +537,7 @@ int schur_plan(Schur& S, int n_blocks, const int32_t* offs, int min_block, hipSt
   S.min_block = min_block;
   S.p_nrhs = -1;
   S.nb = n_blocks;
+  ++S.plan_gen;
   return HGL_OK;
 }
 
@@ -544,27 +553,63 @@ int allow_lds(K kernel, size_t bytes) {
   return HGL_OK;
 }
 
-// Extract every M_bb and invert it through the phases.
-int schur_run(hgl_handle* h, Schur& S, double lambda, hipStream_t s) {
+// Extract every M_bb and invert it through the phases: every launch on st.
+int schur_launches(hgl_handle* h, Schur& S, double lambda, hipStream_t st) {
   const double a = 1.0 + 1.0 / lambda, b = 1.0 / lambda;
   float* arena = S.arena.as<float>();
   const size_t ex_lds = sizeof(double) * 4 * size_t(S.max_n);
-  HGL_TRY(allow_lds(k_schur_extract, ex_lds));
-  launch(h, kProfExtract, k_schur_extract, dim3((S.max_n + 3) / 4, S.nb), dim3(kBlock), uint32_t(ex_lds), s, S.d_boff,
-         S.d_moff, h->vtx_ptr, h->vtx_edge, h->edge_ptr, h->edge_vtx, h->s64, h->c64, a, b, arena, S.max_n);
+  launch(h, kProfExtract, k_schur_extract, dim3((S.max_n + 3) / 4, S.nb), dim3(kBlock), uint32_t(ex_lds), st,
+         S.d_boff, S.d_moff, h->vtx_ptr, h->vtx_edge, h->edge_ptr, h->edge_vtx, h->s64, h->c64, a, b, arena,
+         S.max_n);
   HGL_HIP(hipGetLastError());
   for (const Phase& ph : S.phases) {
     if (ph.leaves > 0) {
-      launch(h, kProfLeaf, k_schur_leaf, dim3(ph.leaves), dim3(kLeafThreads), 0, s, S.d_leaves + ph.leaf0, arena);
+      launch(h, kProfLeaf, k_schur_leaf, dim3(ph.leaves), dim3(kLeafThreads), 0, st, S.d_leaves + ph.leaf0, arena);
       HGL_HIP(hipGetLastError());
     }
     if (ph.tiles > 0) {
-      launch(h, kProfGemm, k_schur_gemm<false>, dim3(ph.tiles), dim3(kBlock), 0, s, S.d_tasks, S.d_tile_task + ph.tile0,
-             S.d_tile_mn + ph.tile0, static_cast<const float*>(arena), static_cast<const float*>(arena),
-             static_cast<const float*>(arena), arena, int64_t(0), int64_t(0), Gate{});
+      launch(h, kProfGemm, k_schur_gemm<false>, dim3(ph.tiles), dim3(kBlock), 0, st, S.d_tasks,
+             S.d_tile_task + ph.tile0, S.d_tile_mn + ph.tile0, static_cast<const float*>(arena),
+             static_cast<const float*>(arena), static_cast<const float*>(arena), arena, int64_t(0), int64_t(0), Gate{});
       HGL_HIP(hipGetLastError());
     }
   }
+  return HGL_OK;
+}
+
+// The launches of schur_launches, recorded once as a HIP graph on a
+// capture stream and replayed on s while every value they bake in (buffer
+// addresses, the plan, lambda) is unchanged; direct launches while kernel
+// timing is on.  The graph holds kernels only (no memory set or copy nodes).
+int schur_run(hgl_handle* h, Schur& S, double lambda, hipStream_t s) {
+  HGL_TRY(allow_lds(k_schur_extract, sizeof(double) * 4 * size_t(S.max_n)));
+  if (h->prof_on) return schur_launches(h, S, lambda, s);
+  uint64_t lam_bits;
+  std::memcpy(&lam_bits, &lambda, sizeof(lam_bits));
+  auto u = [](const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); };
+  const std::vector<uint64_t> key = {u(S.arena.p), u(S.meta.p), S.plan_gen, lam_bits, u(h->vtx_ptr),
+                                     u(h->vtx_edge), u(h->edge_ptr), u(h->edge_vtx), u(h->s64), u(h->c64)};
+  if (!S.graph || key != S.graph_key) {
+    if (S.graph) {
+      HGL_HIP(hipGraphExecDestroy(S.graph));
+      S.graph = nullptr;
+    }
+    if (!S.cap) HGL_HIP(hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HGL_HIP(hipStreamBeginCapture(S.cap, hipStreamCaptureModeThreadLocal));
+    const int rc = schur_launches(h, S, lambda, S.cap);
+    const hipError_t e = hipStreamEndCapture(S.cap, &g);
+    if (rc != HGL_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    HGL_HIP(e);
+    const hipError_t e2 = hipGraphInstantiate(&S.graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HGL_HIP(e2);
+    S.graph_key = key;
+  }
+  HGL_HIP(hipGraphLaunch(S.graph, s));
   return HGL_OK;
 }
 
