@@ -120,7 +120,7 @@ __global__ void k_scale(int64_t rows, int k, T* __restrict__ X, int64_t ldx, dou
 // the exact tau of the support found, (sum_{v_i > tau} v_i - 1)/|support|,
 // is recomputed until the support is stable.  Per-thread sums in a fixed
 // stride order and fixed-order block reductions: deterministic.
-constexpr int kProj = 1024, kProjWaves = kProj / kWave, kSect = 8;
+constexpr int kProj = 512, kProjWaves = kProj / kWave, kSect = 8;
 
 // Sums over the workgroup of x[0 .. n-1] (n <= kSect), returned to every thread.
 template <int n>
