@@ -16,7 +16,7 @@ library computes, written from the paper (Karantaidis, Sarridis, Kotropoulos,
 * ``grad``       -- derivative of the weight objective P(w) (eq. 4) and of
   losses through the solve, plus finite differences.
 * ``simplex``    -- Euclidean projection onto {w >= 0, 1'w = 1} (constraints of
-  eq. 4).
+  eq. 4), and the active-set steepest-descent step on the Lagrangian of eq. 5.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the HIP library
