@@ -100,8 +100,11 @@ __global__ __launch_bounds__(kBlock) void k_schur_extract(const int32_t* __restr
 }
 
 // One kGT x kGT output tile per workgroup; four waves of kGT/2 x kGT/2,
-// each as kGT/32 x kGT/32 MFMA 16x16x4 tiles.  A is staged k-major and B row-major in LDS, 16
-// deep; the next stage's loads are issued before this stage's MFMAs.
+// each as kGT/32 x kGT/32 MFMA 16x16x4 tiles.  A is staged k-major and B
+// row-major in LDS, 16 deep, in two buffers: the next stage's loads are
+// issued before this stage's MFMAs and stored into the other buffer after
+// them, so one barrier per stage suffices (a buffer is rewritten only after
+// the barrier that follows its last read).
 // MFMA 16x16x4 f32 lane layout: lane l holds A[l%16][l/16], B[l/16][l%16]
 // and D[4(l/16)+v][l%16], v < 4.
 template <bool PREC>
@@ -113,8 +116,8 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
                                                        const float* __restrict__ Cbase, float* __restrict__ Dbase,
                                                        int64_t ldb_rows, int64_t ldd_rows, Gate gate) {
   if (gate.skip()) return;
-  __shared__ float As[kGK][kGT + 4];
-  __shared__ float Bs[kGK][kGT + 4];
+  __shared__ float As[2][kGK][kGT + 4];
+  __shared__ float Bs[2][kGK][kGT + 4];
   const GemmTask t = tasks[tile_task[blockIdx.x]];
   const int mn = tile_mn[blockIdx.x];
   const int m0 = (mn >> 16) * kGT, n0 = (mn & 0xffff) * kGT;
@@ -160,29 +163,36 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
     for (int j = 0; j < kFT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int wr = (wave >> 1) * kWT, wc = (wave & 1) * kWT;
   const int r = lane & 15, q = lane >> 4;
-  load(0);
-  for (int k0 = 0; k0 < t.k; k0 += kGK) {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < kAPT; ++j) {
-      As[ak + j][ar] = ra[j];
-      Bs[bk][bc + j] = rb[j];
+      As[buf][ak + j][ar] = ra[j];
+      Bs[buf][bk][bc + j] = rb[j];
     }
-    __syncthreads();
-    if (k0 + kGK < t.k) load(k0 + kGK);
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = 0; k0 < t.k; k0 += kGK) {
+    const bool more = k0 + kGK < t.k;
+    if (more) load(k0 + kGK);
 #pragma unroll
     for (int kk = 0; kk < kGK; kk += 4) {
       float a[kFT], b[kFT];
 #pragma unroll
       for (int i = 0; i < kFT; ++i) {
-        a[i] = As[kk + q][wr + 16 * i + r];
-        b[i] = Bs[kk + q][wc + 16 * i + r];
+        a[i] = As[cur][kk + q][wr + 16 * i + r];
+        b[i] = Bs[cur][kk + q][wc + 16 * i + r];
       }
 #pragma unroll
       for (int i = 0; i < kFT; ++i)
 #pragma unroll
         for (int j = 0; j < kFT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) store(cur ^ 1);
     __syncthreads();
+    cur ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < kFT; ++i)
