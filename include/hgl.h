@@ -187,7 +187,13 @@ int hgl_apply(hgl_handle* h, double lambda, int32_t dt, const void* P, int64_t l
  * sum_e c_e |(H' S p)_e|^2, eq. 1, so that the update runs inside the
  * operator product).  A column whose recursive residual reaches the claim
  * level stops until an FP64 residual check: it finishes if the recomputed
- * residual meets tol, and otherwise restarts its search direction from it.  Y, F: N x k of type double (PLAIN_F64) or float
+ * residual meets tol, and otherwise restarts its search direction from it.
+ * A column still iterating when its residual is recomputed (at a check, or
+ * every rr_period iterations) goes on from the recomputed residual; it keeps
+ * its search direction while that residual's norm is at most 1.1 times the
+ * recursive one's, and restarts the direction from it otherwise (a direction
+ * scaled to a drifted recursive residual makes the step overshoot).
+ * Y, F: N x k of type double (PLAIN_F64) or float
  * (F32_F64DOT_RR).  iters_host [G*k] (nullable) receives the iteration count
  * of each (graph, column), relres_host [G*k] (nullable) the FP64-recomputed
  * ||y - M f|| / ||y|| of the returned F (0 for a zero column, whose solution

@@ -8,9 +8,11 @@
 //   -> [preconditioner] -> reduce: beta, convergence
 //   -> direction update (P = R + beta P, or Z + beta P with a preconditioner).
 // Residual replacement (R = Y - M F with FP64 accumulation) runs at host
-// checks and optionally every rr_period iterations.  After a periodic one the
-// recursion continues from the recomputed residual with the same search
-// direction; a column that a check sends back to iterate restarts (P = R).
+// checks and optionally every rr_period iterations.  The recursion continues
+// from the recomputed residual with the same search direction only while the
+// two residuals still agree (true norm at most kKeepDir times the recursive
+// one); otherwise, and for a claimed column that a check sends back to
+// iterate, the direction restarts from the recomputed residual (P = R).
 // Inner products are accumulated in FP64 per workgroup and reduced in a fixed
 // order (deterministic).  Converged columns get alpha = 0; once every column
 // has converged the remaining launches of an enqueued chunk return at once.
@@ -29,6 +31,16 @@ namespace hgl {
 // alpha step makes it active).  A check that finds a column still active
 // replaces its residual and leaves its direction.
 enum : int32_t { kActive = 0, kDone = 1, kBreakdown = 2, kClaimed = 3, kRestart = 4 };
+
+// A replaced residual keeps the column's search direction only if its norm is
+// at most kKeepDir times the recursive residual's.  Near FP32's attainable
+// accuracy the recursive residual drifts far below the true one; alpha =
+// r'r / p'Mp with the true r'r then overshoots along a direction scaled to
+// the recursive residual, and the iteration diverges.  With rounding errors
+// uncorrelated with r, |r_true|^2 ~ |r_rec|^2 + |r_true - r_rec|^2, so the
+// bound keeps the direction while the deviation is below about 0.46 |r_rec|.
+constexpr double kKeepDir = 1.1;
+constexpr double kKeepDir2 = kKeepDir * kKeepDir;
 
 struct CgState {
   double* yy;      // [G*k] ||y||^2
@@ -304,6 +316,7 @@ struct RedArgs {
   const double* part;   // r'r (Init, Beta, Check) or p'Mp (Alpha, not split)
   const double* part2;  // y'y (Init)
   const double* part3;  // r'z (Init, Beta, Check) when preconditioned
+  const double* prec_rr;  // Beta after a periodic replacement: the recursive r'r
   // Alpha with p'Mp split as a p'p - b sum_e c_e |(H' S p)_e|^2 (eq. 1):
   // tile partials of p'p and edge-slot partials of the hyperedge sum
   const double* pp;     // null: p'Mp from part
@@ -351,12 +364,13 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
   int gate = 1;
   if constexpr (OP == RedOp::Alpha || OP == RedOp::Beta) gate = *wd.cnt(it - 1);
   int32_t st0 = 0, it0 = 0;
-  double rz0 = 0.0, yy0 = 0.0;
+  double rz0 = 0.0, yy0 = 0.0, rr0 = 0.0;
   if (lead && OP != RedOp::Init) {
     st0 = st.state[id];
     rz0 = st.rz[id];
     if constexpr (OP == RedOp::Beta || OP == RedOp::Check) yy0 = st.yy[id];
     if constexpr (OP == RedOp::Beta) it0 = st.iters[id];
+    if constexpr (OP == RedOp::Check) rr0 = st.rr[id];
   }
   const bool split = OP == RedOp::Alpha && ra.pp != nullptr;
   double ag = 0.0, bg = 0.0;
@@ -411,6 +425,16 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
       double o[1];
       slot_sums<1>(src, ra.k, col, o, lds);
       sum = o[0];
+    }
+    if (OP == RedOp::Beta && ra.periodic) {
+      // the recursive r'r of this iteration, set aside before the
+      // replacement overwrote part
+      SlotSrc src[1] = {all};
+      src[0].p = ra.prec_rr;
+      double o[1];
+      __syncthreads();
+      slot_sums<1>(src, ra.k, col, o, lds);
+      rr0 = o[0];
     }
   }
   if (OP == RedOp::Init && ra.has_prec) {
@@ -482,7 +506,10 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
           add_err = 1;
           break;
         }
-        st.beta[id] = rz / rz0;
+        // after a periodic replacement the direction is kept only while the
+        // true residual agrees with the recursive one (kKeepDir); else it
+        // restarts in place (beta = 0: P = R, or the preconditioned R)
+        st.beta[id] = (ran && sum > kKeepDir2 * rr0) ? 0.0 : rz / rz0;
         st.rr[id] = sum;
         st.rz[id] = rz;
         if (rel <= ra.claim * ra.tol) {  // stop for a check
@@ -501,12 +528,12 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
         st.rz[id] = rz;
         if (rel <= ra.tol) {
           st.state[id] = kDone;
-        } else if (st0 == kActive) {
-          add_chk = 1;  // still iterating: keeps its direction
+        } else if (st0 == kActive && sum <= kKeepDir2 * rr0) {
+          add_chk = 1;  // still iterating, residuals agree: keeps its direction
         } else {
           // restart: the direction is rebuilt from the recomputed residual
           // (P = R, beta = 0), since the old one was scaled to a recursive
-          // residual that may have drifted far from the true one
+          // residual that has drifted from the true one
           st.state[id] = kRestart;
           st.beta[id] = 0.0;
           add_chk = 1;
@@ -642,8 +669,10 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   // claim < 1 in FP32 leaves room for the drift of the FP32 recursion from
   // the true residual
   const double claim = fp32 ? 0.5 : 1.0;
-  RedArgs ra{G,           k,     nsl,    {0, 0, 0, 0}, {0, 0, 0, 0}, h->seg_slots, b.part, b.part2,
-             b.part3,     b.pp,  b.epart, h->seg_eslots, a_seg, o->tol, claim, 0, 0, has_prec ? 1 : 0};
+  // prec_rr: after a periodic replacement, the recursive r'r partials of the
+  // iteration were written to part2 (free after the start)
+  RedArgs ra{G,       k,      nsl,     {0, 0, 0, 0}, {0, 0, 0, 0}, h->seg_slots, b.part, b.part2,
+             b.part3, b.part2, b.pp, b.epart, h->seg_eslots, a_seg, o->tol, claim, 0, 0, has_prec ? 1 : 0};
   if (G == 1)
     for (int i = 0; i < 4; ++i) {
       ra.slots1[i] = h->seg_slots_host[i];
@@ -698,6 +727,10 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     Gate g_prev{wd.cnt(it - 1), nullptr, 1};
     RedArgs r = ra;
     r.iter = it;
+    const int periodic = (o->rr_period > 0 && (it + 1) % o->rr_period == 0) ? 1 : 0;
+    // partial r'r of the recursive residual: set aside in part2 when the
+    // periodic replacement below overwrites part
+    double* part_rr = periodic ? b.part2 : b.part;
     if (fused) {
       // edge gather + hyperedge half of p'Mp -> alpha -> vertex gather with
       // the update (partial r'r of the new R)
@@ -710,7 +743,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       prof_end(h, s);
       prof_begin(h, kProfVertex, s);
       HGL_TRY(launch_spmm_vertex<T, T>(h, VMode::Step, b.P, ld, b.Z, ld, nullptr, 0, nullptr, 0, a_seg, b_seg,
-                                       b.part, k, csv, g_prev, s, UpdArgs<T>{F, ldf, b.R, ld, b.st.alpha}));
+                                       part_rr, k, csv, g_prev, s, UpdArgs<T>{F, ldf, b.R, ld, b.st.alpha}));
       prof_end(h, s);
     } else {
       prof_begin(h, kProfEdge, s);
@@ -729,14 +762,13 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
         dim3 grid(h->n_tiles, cs.slabs);
         launch(h, -1, k_cg_update<T, GL, V>, grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
                            h->tile_r1, h->tile_seg, nsl, h->n_long, F, ldf, b.R, b.P, b.Q, ld,
-                           b.st.alpha, b.part, k, g_prev);
+                           b.st.alpha, part_rr, k, g_prev);
         HGL_HIP(hipGetLastError());
         return HGL_OK;
       });
       HGL_TRY(rc2);
       prof_end(h, s);
     }
-    const int periodic = (o->rr_period > 0 && (it + 1) % o->rr_period == 0) ? 1 : 0;
     if (periodic) HGL_TRY(resid(g_prev));
     if (has_prec) HGL_TRY(precond(b.R, ld, b.Zp, ld, b.part3, g_prev));
     r.periodic = periodic;
