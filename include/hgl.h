@@ -181,6 +181,24 @@ int hgl_apply(hgl_handle* h, double lambda, int32_t dt, const void* P, int64_t l
               int64_t ldq, int32_t k, hipStream_t stream);
 
 /*
+ * hgl_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, operator and kernels as hgl_apply, and the same Q.  Every
+ * intermediate buffer (Z = C H' S P, E x k; the hub rows' chunk partials; the
+ * per-graph factors) lives in one fixed device array of the library, 64 MiB
+ * per GPU, held until the process ends; a call whose intermediates exceed it
+ * (about E * k * sizeof(element) plus the hub partials) returns
+ * HGL_EUNSUPPORTED and launches nothing.  The call allocates nothing: no
+ * hipMalloc, no pinned staging, no timing events (kernel timing is skipped
+ * for it).  The array is shared by every call on a GPU and keeps the last
+ * call's contents, so calls that overlap on one GPU (other streams, other
+ * threads) race and must be ordered by the caller.  The current device must
+ * be the handle's (HGL_EINVAL otherwise).
+ */
+int hgl_apply_noalloc(hgl_handle* h, double lambda, int32_t dt, const void* P, int64_t ldp, void* Q,
+                      int64_t ldq, int32_t k, hipStream_t stream);
+
+/*
  * Solve (I + L/lambda) F = Y column by column by conjugate gradient, in the
  * recurrences of the paper's section 3 (eqs. 16-20), each column with its own
  * alpha and beta (p'Mp obtained as (1 + 1/lambda) p'p - (1/lambda)

@@ -65,6 +65,7 @@ SIGNATURES = {
     "hgl_get_cg_stats": (C.c_int, [P, I32P]),
     "hgl_get_operator": (C.c_int, [P, P, P, P, P, P, P]),
     "hgl_apply": (C.c_int, [P, D, I32, P, I64, P, I64, I32, P]),
+    "hgl_apply_noalloc": (C.c_int, [P, D, I32, P, I64, P, I64, I32, P]),
     "hgl_cg_solve": (C.c_int, [P, D, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),
     "hgl_cg_solve_batched": (C.c_int, [P, DP, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),
     "hgl_cg_solve_wg": (C.c_int, [P, D, C.POINTER(CgOpts), P, I64, P, I64, I32, I32P, DP, P]),

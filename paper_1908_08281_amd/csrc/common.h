@@ -310,11 +310,14 @@ inline int n_eslots(const hgl_handle* h) { return h->n_etiles + h->n_long_edge; 
 // and partial <X, Out> per column.  Resid: Out = Y - (a X - b s H Z) with FP64
 // accumulation and partial <Out, Out>.  Step (T = TZ, X = P): with Q = a P -
 // b s H Z kept in registers, u.F += alpha P, u.R -= alpha Q and partial
-// <R, R> of the new R.  a, b per segment (device, [G]).
+// <R, R> of the new R.  a, b per segment (device, [G]).  chunk_buf
+// (nullable): the hub rows' chunk partials (n_chunks x k of TZ) in the
+// caller's memory instead of the handle's workspace.
 template <class T, class TZ>
 int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx, const TZ* Z,
                        int64_t ldz, const T* Y, int64_t ldy, T* Out, int64_t ldo,
                        const double* a_seg, const double* b_seg, double* part, int k,
-                       const ColShape& cs, Gate gate, hipStream_t s, UpdArgs<T> u = {});
+                       const ColShape& cs, Gate gate, hipStream_t s, UpdArgs<T> u = {},
+                       TZ* chunk_buf = nullptr);
 
 }  // namespace hgl

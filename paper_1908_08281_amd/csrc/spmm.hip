@@ -408,9 +408,9 @@ template <class T, class TZ>
 int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx, const TZ* Z,
                        int64_t ldz, const T* Y, int64_t ldy, T* Out, int64_t ldo,
                        const double* a_seg, const double* b_seg, double* part, int k,
-                       const ColShape& cs, Gate gate, hipStream_t st, UpdArgs<T> u) {
+                       const ColShape& cs, Gate gate, hipStream_t st, UpdArgs<T> u, TZ* chunk_buf) {
   hgl_handle* hm = const_cast<hgl_handle*>(h);
-  if (h->n_chunks > 0 && hm->ws_chunk.bytes < sizeof(TZ) * size_t(h->n_chunks) * k) {
+  if (!chunk_buf && h->n_chunks > 0 && hm->ws_chunk.bytes < sizeof(TZ) * size_t(h->n_chunks) * k) {
     // growing a buffer frees the old one: wait for queued work that may use it
     HGL_HIP(hipStreamSynchronize(st));
     HGL_TRY(hm->ws_chunk.reserve(sizeof(TZ) * size_t(h->n_chunks) * k));
@@ -420,7 +420,7 @@ int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx,
                 h->long_seg, h->long_chunk0, n_slots(h),  a_seg,       b_seg};
   const TZ* s;
   if constexpr (sizeof(TZ) == 8) s = h->s64; else s = h->s32;
-  TZ* cp = hm->ws_chunk.as<TZ>();
+  TZ* cp = chunk_buf ? chunk_buf : hm->ws_chunk.as<TZ>();
   dim3 grid(h->n_tiles + h->n_chunks, cs.slabs);
   dim3 grid_fin(h->n_long, cs.slabs);
   if (mode == VMode::Resid && sizeof(TZ) != 8) {
@@ -551,16 +551,16 @@ template int launch_spmm_edge<double, double>(const hgl_handle*, const double*, 
 template int launch_spmm_vertex<float, float>(const hgl_handle*, VMode, const float*, int64_t,
                                               const float*, int64_t, const float*, int64_t, float*,
                                               int64_t, const double*, const double*, double*, int,
-                                              const ColShape&, Gate, hipStream_t, UpdArgs<float>);
+                                              const ColShape&, Gate, hipStream_t, UpdArgs<float>, float*);
 template int launch_spmm_vertex<float, double>(const hgl_handle*, VMode, const float*, int64_t,
                                                const double*, int64_t, const float*, int64_t, float*,
                                                int64_t, const double*, const double*, double*, int,
-                                               const ColShape&, Gate, hipStream_t, UpdArgs<float>);
+                                               const ColShape&, Gate, hipStream_t, UpdArgs<float>, double*);
 template int launch_spmm_vertex<double, double>(const hgl_handle*, VMode, const double*, int64_t,
                                                 const double*, int64_t, const double*, int64_t,
                                                 double*, int64_t, const double*, const double*,
                                                 double*, int, const ColShape&, Gate,
-                                                hipStream_t, UpdArgs<double>);
+                                                hipStream_t, UpdArgs<double>, double*);
 
 // Per-graph (a, b) = (1 + 1/lambda_g, 1/lambda_g) in a device array [2G].
 int upload_ab(hgl_handle* h, const double* lambdas_host, hipStream_t st) {

@@ -151,7 +151,11 @@ def get_operator(h: Handle) -> dict:
     return {"dv": dv, "s": s, "c": c[:h.E], "vtx_ptr": vp, "vtx_edge": ve[:h.nnz]}
 
 
-def apply(h: Handle, lam: float, P: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+def apply(h: Handle, lam: float, P: torch.Tensor, out: torch.Tensor | None = None,
+          noalloc: bool = False) -> torch.Tensor:
+    """Q = (I + L/lam) P.  noalloc: through hgl_apply_noalloc (the library's fixed
+    scratch instead of the handle's workspaces; `out` must then be given by callers
+    that cannot allocate)."""
     if P.dtype not in (torch.float32, torch.float64):
         raise TypeError("P must be float32 or float64")
     _need(P, P.dtype, "P", h.device)
@@ -161,9 +165,10 @@ def apply(h: Handle, lam: float, P: torch.Tensor, out: torch.Tensor | None = Non
     Q = torch.empty_like(P, memory_format=torch.contiguous_format) if out is None else out
     ldq = _rows(Q, "out")
     dt = _lib.HGL_F64 if P.dtype == torch.float64 else _lib.HGL_F32
+    fn = "hgl_apply_noalloc" if noalloc else "hgl_apply"
     with torch.cuda.device(h.device):
-        check(lib().hgl_apply(h.ptr, float(lam), dt, _ptr(P), ldp, _ptr(Q), ldq, P.shape[1],
-                              _stream(h.device)), "hgl_apply")
+        check(getattr(lib(), fn)(h.ptr, float(lam), dt, _ptr(P), ldp, _ptr(Q), ldq, P.shape[1],
+                                 _stream(h.device)), fn)
     return Q
 
 
