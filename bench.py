@@ -675,7 +675,7 @@ def bench_learn(a):
     dta = time.perf_counter() - t0
     hgl.set_weights(h, wl)
     F, _, _, _ = hgl.cg_solve(h, p.lam, Y, tol=tol)
-    g, _, _, _ = hgl.weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=tol)
+    g, _, _, _, _ = hgl.weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=tol)
     d_proj, _ = _timed(lambda: hgl.project_simplex(wl - eta * g), 20, 2)
     d_act, _ = _timed(lambda: hgl.active_set_step(wl, g, eta), 20, 2)
     extra["active_set_rule"] = {"steps_per_s": round(a.steps / dta, 3), "mu_eff_last": ra[-1]["mu_eff"],

@@ -24,8 +24,13 @@
  *  - the return value is a status: 0 = HGL_OK, positive = informational,
  *    negative = error; hgl_last_error() gives a message for the last failing
  *    call on the calling thread; no C++ exception crosses this boundary;
- *  - a handle owns its device buffers (allocated with hipMalloc) and frees
- *    them in hgl_destroy; a handle must not be used from two threads at once.
+ *  - a handle owns its device buffers and frees them in hgl_destroy; it
+ *    takes every one of them (structure, scales, workspaces and the
+ *    temporaries of its own build) from the allocator given at build
+ *    (hgl_allocator, e.g. the caller's framework's caching allocator), or
+ *    from hipMalloc when none is given; a handle must not be used from two
+ *    threads at once.  The one exception is hgl_apply_noalloc, which
+ *    allocates nothing.
  */
 #ifndef HGL_H
 #define HGL_H
@@ -38,6 +43,24 @@ extern "C" {
 #endif
 
 typedef struct hgl_handle hgl_handle;
+
+/*
+ * Caller-supplied device memory for a handle.  alloc returns `bytes` of
+ * device memory on the current device, usable by work on `stream` (the
+ * stream of the library call that asks), or NULL on failure (the call then
+ * returns HGL_ENOMEM).  free returns a pointer that alloc gave; `stream` is
+ * the stream of the call that frees it (for hgl_destroy, that of the
+ * handle's last call; work queued before it may still read the memory, so
+ * a stream-ordered allocator must not hand it out to other streams before
+ * that work ends).  ctx is passed through and must stay valid until
+ * hgl_destroy returns.  A handle's calls should use one stream, or the
+ * caller orders them across streams.
+ */
+typedef struct hgl_allocator {
+  void* (*alloc)(size_t bytes, void* ctx, hipStream_t stream);
+  void (*free)(void* ptr, void* ctx, hipStream_t stream);
+  void* ctx;
+} hgl_allocator;
 
 enum hgl_status {
   HGL_OK = 0,
@@ -101,27 +124,35 @@ const char* hgl_last_error(void);
  * Computes delta(v) = sum_e w(e) H(v,e), delta(e) = |e|, the scales
  * s_v = delta(v)^-1/2 (0 when delta(v) = 0, i.e. the pseudo-inverse) and
  * c_e = w_e / delta(e), and the vertex-major transpose of H.  The inputs are
- * copied; the caller may free them afterwards.  Invalid structure or weights
- * -> HGL_EINVAL (validation runs on the device; this call synchronises).
+ * copied; the caller may free them afterwards.  al (nullable): where the
+ * handle takes its device memory from (copied; NULL: hipMalloc / hipFree).
+ * Invalid structure or weights -> HGL_EINVAL (validation runs on the device;
+ * this call synchronises); a failed allocation -> HGL_ENOMEM.
  */
 int hgl_build_laplacian(int32_t N, int32_t E, int64_t nnz, const int32_t* edge_ptr,
-                        const int32_t* edge_vtx, const double* w, hgl_handle** out,
-                        hipStream_t stream);
+                        const int32_t* edge_vtx, const double* w, const hgl_allocator* al,
+                        hgl_handle** out, hipStream_t stream);
 
 /*
  * Build one operator for G independent hypergraphs stored as their disjoint
- * union (vertex ids global).  vtx_offsets_host[G+1] and edge_offsets_host[G+1]
+ * union (vertex ids global): section 2's operator of each graph, with the
+ * paper's per-query independence (section 4, one solve per test image) kept
+ * per (graph, column).  vtx_offsets_host[G+1] and edge_offsets_host[G+1]
  * give each graph's vertex and hyperedge ranges; every hyperedge of graph g
  * must lie inside graph g's vertex range.  Solves on such a handle run one
- * CG recurrence per (graph, column) and may use one lambda per graph.
+ * CG recurrence per (graph, column) and may use one lambda per graph.  al:
+ * as for hgl_build_laplacian.
  */
 int hgl_build_laplacian_batched(int32_t G, const int32_t* vtx_offsets_host,
                                 const int32_t* edge_offsets_host, int64_t nnz,
                                 const int32_t* edge_ptr, const int32_t* edge_vtx,
-                                const double* w, hgl_handle** out, hipStream_t stream);
+                                const double* w, const hgl_allocator* al, hgl_handle** out,
+                                hipStream_t stream);
 
 /* Replace the weights w [E] (same rules as at build) and recompute delta(v),
- * s and c; the structure is reused.  -> HGL_EINVAL on a negative or
+ * s and c of eq. 1; the structure is reused.  This is the re-weighting step
+ * of the paper's alternating scheme (section 2: w is updated with F fixed,
+ * then F is solved again with the new w).  -> HGL_EINVAL on a negative or
  * non-finite weight (synchronises). */
 int hgl_set_weights(hgl_handle* h, const double* w, hipStream_t stream);
 
@@ -224,9 +255,11 @@ int hgl_cg_solve(hgl_handle* h, double lambda, const hgl_cg_opts* opts, const vo
                  int64_t ldy, void* F, int64_t ldf, int32_t k, int32_t* iters_host,
                  double* relres_host, hipStream_t stream);
 
-/* As hgl_cg_solve with one lambda per graph of a batched handle
- * (lambdas_host [G]).  All graphs share k; Y and F are the row
- * concatenations of the graphs' blocks (sum N_g x k). */
+/* As hgl_cg_solve (section 3, eqs. 16-20) with one lambda per graph of a
+ * batched handle (lambdas_host [G]): each (graph, column) pair is its own
+ * recurrence, the paper's independent per-query solves (section 4) run
+ * together.  All graphs share k; Y and F are the row concatenations of the
+ * graphs' blocks (sum N_g x k). */
 int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg_opts* opts,
                          const void* Y, int64_t ldy, void* F, int64_t ldf, int32_t k,
                          int32_t* iters_host, double* relres_host, hipStream_t stream);
@@ -449,7 +482,9 @@ int hgl_block_schur_plan(int32_t n_blocks, const int32_t* block_offsets_host, in
  * F, G, Y, Z_out: N x k, FP32 when adj->mode is F32_F64DOT_RR, FP64 when
  * PLAIN_F64; leading dimensions ldf, ldg, ldy, ldz.  The adjoint solve uses
  * hgl_cg_solve with adj; Z_out (nullable) receives Z (= dl/dY in the G case);
- * iters_host/relres_host (nullable, [k]) report the adjoint solve.
+ * iters_host/relres_host (nullable, [k]) report the adjoint solve.  Returns
+ * HGL_NOT_CONVERGED (1) when the adjoint solve reached max_iter before every
+ * column met adj->tol (grad_w is then computed from that inexact Z).
  * Single-graph handles only.  Synchronises the stream.
  */
 int hgl_weight_grad(hgl_handle* h, double lambda, double mu, const void* F, int64_t ldf, const void* G,
@@ -463,6 +498,22 @@ int hgl_weight_grad(hgl_handle* h, double lambda, double mu, const void* F, int6
  * device FP64 arrays of length E (may alias).  Asynchronous.
  */
 int hgl_project_simplex(const double* v, double* w, int32_t E, hipStream_t stream);
+
+/*
+ * One projected-gradient step of the weight update (paper, section 2: w on
+ * the simplex of eq. 4, descended along the gradient of P(w)):
+ *   w_out = argmin ||x - (w - eta g)||_2 over {x >= 0, sum(x) = 1}.
+ * w, g: device FP64 [E] (the weights and dP/dw); w_out: device FP64 [E], not
+ * aliasing w or g.  eta > 0: that fixed step; eta_dev (nullable, device
+ * FP64 [1]) receives it.  eta <= 0: the step is set from this gradient,
+ * eta = 0.5 max|w| / max|g - mean(g)| (0 for a constant g), computed on the
+ * device and written to eta_dev (then required), so a loop can reuse it as
+ * its fixed step.  The difference w - eta g is formed without contraction.
+ * HGL_EINVAL for E < 1, a NULL array, a non-finite eta, aliasing, or
+ * eta <= 0 without eta_dev.  Asynchronous.
+ */
+int hgl_projected_gradient_step(const double* w, const double* g, double eta, int32_t E, double* w_out,
+                                double* eta_dev, hipStream_t stream);
 
 /*
  * One steepest-descent step on the Lagrangian of eq. 5 (the paper's active-

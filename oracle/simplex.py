@@ -27,6 +27,19 @@ def project(v) -> np.ndarray:
     return np.maximum(v - tau, 0.0)
 
 
+def initial_step(w, g) -> float:
+    """The fixed step of the projected-gradient weight update, set once from
+    the first gradient (the paper leaves the adaptation step unspecified):
+    eta = 0.5 max|w| / max|g - mean(g)|, so the first step moves no weight
+    by more than half the largest weight before the projection; 0 when g is
+    constant (then the projection leaves w unchanged anyway)."""
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    gc = g - g.mean()
+    d = np.abs(gc).max()
+    return float(0.5 * np.abs(w).max() / d) if d > 0 else 0.0
+
+
 def project_bruteforce(v) -> np.ndarray:
     """Enumerate supports: for each nonempty support S, the minimiser of
     ||w - v||^2 on {w_S sums to 1, w outside S = 0} is v_S - (sum v_S - 1)/|S|;

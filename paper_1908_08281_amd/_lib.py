@@ -37,6 +37,15 @@ class RsvdOpts(C.Structure):
                 ("chunk", C.c_int32), ("scheme", C.c_int32)]
 
 
+# hgl_allocator: device memory of a handle from the caller (torch's caching allocator)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
 HGL_SKETCH_BF16 = 0
 HGL_SKETCH_F64 = 1
 HGL_RSVD_SUBSPACE = 0
@@ -55,8 +64,9 @@ I64P = C.POINTER(C.c_int64)
 SIGNATURES = {
     "hgl_version": (C.c_int, []),
     "hgl_last_error": (C.c_char_p, []),
-    "hgl_build_laplacian": (C.c_int, [I32, I32, I64, P, P, P, C.POINTER(P), P]),
-    "hgl_build_laplacian_batched": (C.c_int, [I32, I32P, I32P, I64, P, P, P, C.POINTER(P), P]),
+    "hgl_build_laplacian": (C.c_int, [I32, I32, I64, P, P, P, C.POINTER(Allocator), C.POINTER(P), P]),
+    "hgl_build_laplacian_batched": (C.c_int, [I32, I32P, I32P, I64, P, P, P, C.POINTER(Allocator), C.POINTER(P),
+                                              P]),
     "hgl_set_weights": (C.c_int, [P, P, P]),
     "hgl_destroy": (None, [P]),
     "hgl_get_sizes": (C.c_int, [P, I32P, I32P, C.POINTER(C.c_int64), I32P]),
@@ -81,6 +91,7 @@ SIGNATURES = {
     "hgl_block_schur_plan": (C.c_int, [I32, I32P, I32, I64P, I64P, I64P, I32P, I64P, I64P]),
     "hgl_weight_grad": (C.c_int, [P, D, D, P, I64, P, I64, P, I64, I32, C.POINTER(CgOpts), P, P, I64, I32P, DP, P]),
     "hgl_project_simplex": (C.c_int, [P, P, I32, P]),
+    "hgl_projected_gradient_step": (C.c_int, [P, P, D, I32, P, P, P]),
     "hgl_active_set_step": (C.c_int, [P, P, D, I32, P, P, P, DP, P]),
     "hgl_profile": (C.c_int, [P, I32]),
     "hgl_profile_read": (C.c_int, [P, I32, C.POINTER(C.c_int64), DP]),

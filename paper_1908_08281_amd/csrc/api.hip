@@ -1,8 +1,7 @@
 // Handle lifecycle, hypergraph build (section 2 of the paper: incidence,
 // degrees, scales) and validation.
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -21,39 +20,73 @@ void set_error(const char* fmt, ...) {
 }
 void clear_error() { g_err[0] = 0; }
 
-int DevBuf::reserve(size_t n) {
-  if (n <= bytes) return HGL_OK;
-  if (p) hipFree(p);
-  p = nullptr;
-  bytes = 0;
-  size_t want = std::max<size_t>(n, 256);
-  hipError_t e = hipMalloc(&p, want);
-  if (e != hipSuccess) {
-    p = nullptr;
-    set_error("hipMalloc(%zu bytes) failed: %s", want, hipGetErrorString(e));
-    return HGL_ENOMEM;
-  }
-  bytes = want;
-  return HGL_OK;
-}
-
-void DevBuf::release() {
-  if (p) hipFree(p);
-  p = nullptr;
-  bytes = 0;
-}
-
-template <class T>
-static int dev_alloc(T** p, size_t count) {
+int Mem::alloc(void** p, size_t bytes) {
   *p = nullptr;
-  size_t bytes = std::max<size_t>(count * sizeof(T), 4);
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  bytes = std::max<size_t>(bytes, 256);
+  if (al.alloc) {
+    *p = al.alloc(bytes, al.ctx, stream);
+    if (!*p) {
+      set_error("the caller's allocator returned NULL for %zu bytes", bytes);
+      return HGL_ENOMEM;
+    }
+    return HGL_OK;
+  }
+  hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
     set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     return HGL_ENOMEM;
   }
   return HGL_OK;
+}
+
+void Mem::release(void* p) {
+  if (!p) return;
+  if (al.alloc) {
+    if (al.free) al.free(p, al.ctx, stream);
+  } else {
+    hipFree(p);
+  }
+}
+
+static int raw_alloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    return HGL_ENOMEM;
+  }
+  return HGL_OK;
+}
+
+int DevBuf::reserve(size_t n) {
+  if (n <= bytes) return HGL_OK;
+  release();
+  size_t want = std::max<size_t>(n, 256);
+  int rc = mem ? mem->alloc(&p, want) : raw_alloc(&p, want);
+  if (rc < 0) {
+    p = nullptr;
+    return rc;
+  }
+  bytes = want;
+  return HGL_OK;
+}
+
+void DevBuf::release() {
+  if (p) {
+    if (mem) mem->release(p);
+    else hipFree(p);
+  }
+  p = nullptr;
+  bytes = 0;
+}
+
+template <class T>
+static int dev_alloc(hgl_handle* h, T** p, size_t count) {
+  void* q = nullptr;
+  const int rc = h->mem.alloc(&q, std::max<size_t>(count * sizeof(T), 4));
+  *p = static_cast<T*>(q);
+  return rc;
 }
 
 int ensure_pinned(hgl_handle* h, size_t n) {
@@ -181,19 +214,162 @@ __global__ void k_validate_w(int32_t E, const double* __restrict__ w, int32_t* _
   }
 }
 
-// nnz-long arrays: vertex id (sort key) and edge id (sort value) of each entry
-__global__ void k_expand(int32_t E, const int32_t* __restrict__ edge_ptr,
-                         const int32_t* __restrict__ edge_vtx, uint32_t* __restrict__ key,
-                         int32_t* __restrict__ val, int32_t* __restrict__ deg) {
-  int e = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
-  int lane = threadIdx.x % 16;
+// ------------------------------------------------------ exclusive scans --
+// out[i] = sum_{j < i} in[i] for int32 arrays (in place allowed): each
+// workgroup scans a tile of kScanTile entries (kScanItems consecutive
+// entries per thread, then a wave prefix and a prefix over the waves) and
+// writes its total; one workgroup scans the tile totals; a last pass adds
+// each tile's offset.  Integer sums: exact, so the result does not depend
+// on the order.
+constexpr int kScanThreads = 256, kScanItems = 8, kScanTile = kScanThreads * kScanItems;
+
+// Exclusive prefix of v over the workgroup's threads; the workgroup total in
+// *total.  Every thread must call it.
+__device__ __forceinline__ int32_t block_exclusive(int32_t v, int32_t* lds /* [kScanThreads / kWave] */,
+                                                   int32_t* total) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  int32_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  if (lane == kWave - 1) lds[wave] = x;
+  __syncthreads();
+  int32_t before = 0, tot = 0;
+  for (int w = 0; w < kScanThreads / kWave; ++w) {
+    const int32_t t = lds[w];
+    if (w < wave) before += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int32_t* in, int32_t* out, int64_t n,
+                                                             int32_t* __restrict__ tile_sums) {
+  __shared__ int32_t lds[kScanThreads / kWave];
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  int32_t x[kScanItems];
+  int32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    x[i] = base + i < n ? in[base + i] : 0;
+    sum += x[i];
+  }
+  int32_t total = 0;
+  int32_t run = block_exclusive(sum, lds, &total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += x[i];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the tile totals in place, tile by tile
+// with a carry.
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int32_t* __restrict__ sums, int64_t nt) {
+  __shared__ int32_t lds[kScanThreads / kWave];
+  int32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nt; b0 += kScanTile) {
+    const int64_t base = b0 + int64_t(threadIdx.x) * kScanItems;
+    int32_t x[kScanItems];
+    int32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      x[i] = base + i < nt ? sums[base + i] : 0;
+      sum += x[i];
+    }
+    int32_t total = 0;
+    int32_t run = carry + block_exclusive(sum, lds, &total);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      if (base + i < nt) sums[base + i] = run;
+      run += x[i];
+    }
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* __restrict__ out, int64_t n,
+                                                           const int32_t* __restrict__ tile_off) {
+  const int32_t add = tile_off[blockIdx.x];
+  const int64_t base = int64_t(blockIdx.x) * kScanTile;
+  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads)
+    if (base + i < n) out[base + i] += add;
+}
+
+// ------------------------------------------------ vertex-major transpose --
+
+// deg[v] += 1 for every incidence (v, e).
+__global__ void k_degree_count(int32_t E, const int32_t* __restrict__ edge_ptr,
+                               const int32_t* __restrict__ edge_vtx, int32_t* __restrict__ deg) {
+  const int e = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
+  const int lane = threadIdx.x % 16;
+  if (e >= E) return;
+  for (int j = edge_ptr[e] + lane; j < edge_ptr[e + 1]; j += 16) atomicAdd(&deg[edge_vtx[j]], 1);
+}
+
+// Every incidence (v, e) goes to a free place of vertex v's segment
+// [vtx_ptr[v], vtx_ptr[v+1]) of tmp; the order inside a segment is whatever
+// the atomics give (the ranking pass below fixes it).
+__global__ void k_scatter_edges(int32_t E, const int32_t* __restrict__ edge_ptr,
+                                const int32_t* __restrict__ edge_vtx, const int32_t* __restrict__ vtx_ptr,
+                                int32_t* __restrict__ cursor, int32_t* __restrict__ tmp) {
+  const int e = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
+  const int lane = threadIdx.x % 16;
   if (e >= E) return;
   for (int j = edge_ptr[e] + lane; j < edge_ptr[e + 1]; j += 16) {
-    int32_t v = edge_vtx[j];
-    key[j] = uint32_t(v);
-    val[j] = e;
-    atomicAdd(&deg[v], 1);
+    const int32_t v = edge_vtx[j];
+    tmp[vtx_ptr[v] + atomicAdd(&cursor[v], 1)] = e;
   }
+}
+
+// The hyperedges of a vertex are distinct, so an entry's place in the sorted
+// segment is the number of smaller entries in it.  Rows of at most kLongRow
+// hyperedges: one wave per vertex, one entry per lane, the segment read
+// through lane exchanges.
+__global__ __launch_bounds__(256) void k_rank_short(int32_t N, const int32_t* __restrict__ vtx_ptr,
+                                                    const int32_t* __restrict__ tmp,
+                                                    int32_t* __restrict__ vtx_edge) {
+  const int v = blockIdx.x * 4 + threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (v >= N) return;  // uniform per wave
+  const int b = vtx_ptr[v], d = vtx_ptr[v + 1] - b;
+  if (d > kLongRow) return;  // ranked by k_rank_long
+  const int32_t x = lane < d ? tmp[b + lane] : INT_MAX;
+  int r = 0;
+  for (int j = 0; j < d; ++j) r += __shfl(x, j, kWave) < x ? 1 : 0;
+  if (lane < d) vtx_edge[b + r] = x;
+}
+
+// Longer rows: one workgroup per chunk of the row (kChunk entries, one per
+// thread), counting against the whole segment staged through LDS.
+constexpr int kRankStage = 1024;
+__global__ __launch_bounds__(kChunk) void k_rank_long(const int32_t* __restrict__ vtx_ptr,
+                                                      const int32_t* __restrict__ long_row,
+                                                      const int32_t* __restrict__ chunk_slot,
+                                                      const int32_t* __restrict__ chunk_begin,
+                                                      const int32_t* __restrict__ chunk_end,
+                                                      const int32_t* __restrict__ tmp,
+                                                      int32_t* __restrict__ vtx_edge) {
+  __shared__ int32_t seg[kRankStage];
+  const int c = blockIdx.x;
+  const int v = long_row[chunk_slot[c]];
+  const int b = vtx_ptr[v], en = vtx_ptr[v + 1];
+  const int i = chunk_begin[c] + threadIdx.x;
+  const bool mine = i < chunk_end[c];
+  const int32_t x = mine ? tmp[i] : INT_MAX;
+  int r = 0;
+  for (int t0 = b; t0 < en; t0 += kRankStage) {
+    const int m = min(kRankStage, en - t0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += kChunk) seg[j] = tmp[t0 + j];
+    __syncthreads();
+    for (int j = 0; j < m; ++j) r += seg[j] < x ? 1 : 0;
+  }
+  if (mine) vtx_edge[b + r] = x;
 }
 
 // dv[v] = sum of w_e over the hyperedges of v (the vertex degree of eq. 1),
@@ -307,8 +483,7 @@ static void free_handle(hgl_handle* h) {
                   h->s32, h->c32, h->tile_r0, h->tile_r1, h->tile_seg, h->long_row,
                   h->chunk_slot, h->chunk_begin, h->chunk_end, h->long_chunk0,
                   h->seg_slots, h->long_seg, h->long_edge, h->etile_e0, h->etile_e1, h->seg_eslots};
-  for (void* p : ptrs)
-    if (p) hipFree(p);
+  for (void* p : ptrs) h->mem.release(p);
   DevBuf* bufs[] = {&h->ws_z, &h->ws_z64, &h->ws_chunk, &h->ws_part, &h->ws_part2,
                     &h->ws_vec, &h->ws_state, &h->ws_misc};
   for (DevBuf* b : bufs) b->release();
@@ -329,8 +504,47 @@ static void free_handle(hgl_handle* h) {
   delete h;
 }
 
+// Temporaries of one build, taken from the handle's memory source and
+// returned in one place (before the handle itself on failure).
+struct Temps {
+  hgl_handle* h;
+  std::vector<void*> ps;
+  template <class T>
+  int get(T** p, size_t count) {
+    void* q = nullptr;
+    const int rc = h->mem.alloc(&q, std::max<size_t>(count * sizeof(T), 4));
+    *p = static_cast<T*>(q);
+    if (rc == HGL_OK) ps.push_back(q);
+    return rc;
+  }
+  void release() {
+    for (void* q : ps) h->mem.release(q);
+    ps.clear();
+  }
+};
+
+// out[0 .. n-1] = exclusive prefix sums of in[0 .. n-1] (in place allowed).
+static int scan_exclusive(Temps& tmp, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return HGL_OK;
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  int32_t* sums = nullptr;
+  HGL_TRY(tmp.get(&sums, size_t(nt)));
+  hipLaunchKernelGGL(k_scan_tiles, dim3(unsigned(nt)), dim3(kScanThreads), 0, s, in, out, n, sums);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, sums, nt);
+  hipLaunchKernelGGL(k_scan_add, dim3(unsigned(nt)), dim3(kScanThreads), 0, s, out, n,
+                     static_cast<const int32_t*>(sums));
+  HGL_HIP(hipGetLastError());
+  return HGL_OK;
+}
+
+static void attach_all(hgl_handle* h) {
+  attach(h, h->ws_z, h->ws_z64, h->ws_chunk, h->ws_part, h->ws_part2, h->ws_vec, h->ws_state, h->ws_misc,
+         h->ws_ab, h->wg_tab);
+  for (auto& b : h->ws_extra) b.mem = &h->mem;
+}
+
 static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off_host, int64_t nnz,
-                 const int32_t* edge_ptr, const int32_t* edge_vtx, const double* w,
+                 const int32_t* edge_ptr, const int32_t* edge_vtx, const double* w, const hgl_allocator* al,
                  hgl_handle** out, hipStream_t s) {
   HGL_CHECK_ARG(out != nullptr, "out must not be NULL");
   *out = nullptr;
@@ -346,8 +560,12 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
   HGL_CHECK_ARG(E >= 0 && nnz >= 0 && nnz < (int64_t(1) << 31), "E, nnz out of range");
   HGL_CHECK_ARG(E == 0 || (edge_ptr && edge_vtx && w), "edge_ptr, edge_vtx, w must not be NULL");
   HGL_CHECK_ARG(nnz >= E, "nnz (%lld) < E (%d): some hyperedge would be empty", (long long)nnz, E);
+  HGL_CHECK_ARG(!al || al->alloc, "an allocator must have an alloc function");
 
   hgl_handle* h = new hgl_handle();
+  if (al) h->mem.al = *al;
+  h->mem.stream = s;
+  attach_all(h);
   h->N = N;
   h->E = E;
   h->G = G;
@@ -355,8 +573,11 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
   hipGetDevice(&h->device);
   h->vtx_off.assign(vtx_off_host, vtx_off_host + G + 1);
   h->edge_off.assign(edge_off_host, edge_off_host + G + 1);
+  Temps tmp{h, {}};
 
   auto fail = [&](int code) {
+    hipStreamSynchronize(s);  // queued work may still use the temporaries
+    tmp.release();
     free_handle(h);
     return code;
   };
@@ -374,16 +595,16 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
     }                                                                                 \
   } while (0)
 
-  B_TRY(dev_alloc(&h->edge_ptr, E + 1));
-  B_TRY(dev_alloc(&h->edge_vtx, nnz));
-  B_TRY(dev_alloc(&h->vtx_ptr, N + 1));
-  B_TRY(dev_alloc(&h->vtx_edge, nnz));
-  B_TRY(dev_alloc(&h->w, E));
-  B_TRY(dev_alloc(&h->dv, N));
-  B_TRY(dev_alloc(&h->s64, N));
-  B_TRY(dev_alloc(&h->c64, E));
-  B_TRY(dev_alloc(&h->s32, N));
-  B_TRY(dev_alloc(&h->c32, E));
+  B_TRY(dev_alloc(h, &h->edge_ptr, E + 1));
+  B_TRY(dev_alloc(h, &h->edge_vtx, nnz));
+  B_TRY(dev_alloc(h, &h->vtx_ptr, N + 1));
+  B_TRY(dev_alloc(h, &h->vtx_edge, nnz));
+  B_TRY(dev_alloc(h, &h->w, E));
+  B_TRY(dev_alloc(h, &h->dv, N));
+  B_TRY(dev_alloc(h, &h->s64, N));
+  B_TRY(dev_alloc(h, &h->c64, E));
+  B_TRY(dev_alloc(h, &h->s32, N));
+  B_TRY(dev_alloc(h, &h->c32, E));
   B_TRY(ensure_pinned(h, 64));
 
   if (E > 0) {
@@ -396,55 +617,110 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
   }
 
   // ---- validation (device), before any use of the indices
-  int32_t *d_off = nullptr, *d_err = nullptr;
-  B_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_off), sizeof(int32_t) * (2 * G + 2 + 2), s));
-  d_err = d_off + 2 * G + 2;
-  B_HIP(hipMemcpyAsync(d_off, vtx_off_host, sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
-  B_HIP(hipMemcpyAsync(d_off + G + 1, edge_off_host, sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
-  int32_t err_init[2] = {0, 0x7fffffff};
-  B_HIP(hipMemcpyAsync(d_err, err_init, sizeof(err_init), hipMemcpyHostToDevice, s));
-  if (E > 0)
-    hipLaunchKernelGGL(k_validate, dim3(blocks_for(E, 256)), dim3(256), 0, s, E, nnz, h->edge_ptr,
-                       h->edge_vtx, h->w, d_off, d_off + G + 1, G, d_err);
-  B_HIP(hipGetLastError());
-  B_HIP(hipMemcpyAsync(h->pinned_i, d_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  B_HIP(hipFreeAsync(d_off, s));
-  B_HIP(hipStreamSynchronize(s));
   {
+    int32_t* d_off = nullptr;
+    B_TRY(tmp.get(&d_off, 2 * size_t(G) + 4));
+    int32_t* d_err = d_off + 2 * G + 2;
+    // offsets and the error words' start values, staged in one host vector
+    // (the stream is synchronised before it goes out of scope)
+    std::vector<int32_t> hv(2 * size_t(G) + 4);
+    std::copy(vtx_off_host, vtx_off_host + G + 1, hv.begin());
+    std::copy(edge_off_host, edge_off_host + G + 1, hv.begin() + G + 1);
+    hv[2 * G + 2] = 0;
+    hv[2 * G + 3] = 0x7fffffff;
+    B_HIP(hipMemcpyAsync(d_off, hv.data(), sizeof(int32_t) * hv.size(), hipMemcpyHostToDevice, s));
+    if (E > 0)
+      hipLaunchKernelGGL(k_validate, dim3(blocks_for(E, 256)), dim3(256), 0, s, E, nnz, h->edge_ptr,
+                         h->edge_vtx, h->w, d_off, d_off + G + 1, G, d_err);
+    B_HIP(hipGetLastError());
+    B_HIP(hipMemcpyAsync(h->pinned_i, d_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    B_HIP(hipStreamSynchronize(s));  // hv goes out of scope; the error words are read
     int st = check_error_words(h->pinned_i);
     if (st < 0) return fail(st);
   }
 
-  // ---- vertex-major transpose: stable radix sort of (vertex, edge) pairs
+  // ---- vertex-major transpose: degree counts -> offsets (scan) -> each
+  // incidence scattered into its vertex's segment -> each segment put in
+  // increasing hyperedge order by ranking (hub rows by chunks)
+  int32_t* deg = nullptr;    // [N+1] degree, then the scatter cursor
+  int32_t* etmp = nullptr;   // [nnz] scattered hyperedge ids
+  B_TRY(tmp.get(&deg, size_t(N) + 1));
+  B_TRY(tmp.get(&etmp, size_t(std::max<int64_t>(nnz, 1))));
+  B_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (size_t(N) + 1), s));
+  if (E > 0)
+    hipLaunchKernelGGL(k_degree_count, dim3(blocks_for(E, 16)), dim3(256), 0, s, E, h->edge_ptr, h->edge_vtx, deg);
+  B_HIP(hipGetLastError());
+  B_TRY(scan_exclusive(tmp, deg, h->vtx_ptr, int64_t(N) + 1, s));
+
+  // ---- long vertex rows -> chunks (from the offsets alone)
   {
-    uint32_t* keys = nullptr;
-    int32_t* vals = nullptr;
-    int32_t* deg = nullptr;
-    uint32_t* keys_out = nullptr;
-    size_t n2 = std::max<int64_t>(nnz, 1);
-    B_HIP(hipMallocAsync(reinterpret_cast<void**>(&keys), n2 * 4 * 3 + sizeof(int32_t) * (N + 1), s));
-    keys_out = keys + n2;
-    vals = reinterpret_cast<int32_t*>(keys + 2 * n2);
-    deg = reinterpret_cast<int32_t*>(keys + 3 * n2);
-    B_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (N + 1), s));
-    if (E > 0)
-      hipLaunchKernelGGL(k_expand, dim3(blocks_for(E, 16)), dim3(256), 0, s, E, h->edge_ptr,
-                         h->edge_vtx, keys, vals, deg);
+    int32_t* tmpi = nullptr;
+    B_TRY(tmp.get(&tmpi, 4 * (size_t(N) + 1)));
+    int32_t* is_long = tmpi;
+    int32_t* nch = tmpi + (N + 1);
+    int32_t* slot_of = tmpi + 2 * (N + 1);
+    int32_t* chunk_of = tmpi + 3 * (N + 1);
+    B_HIP(hipMemsetAsync(tmpi, 0, sizeof(int32_t) * 4 * (size_t(N) + 1), s));
+    hipLaunchKernelGGL(k_long_flags, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, h->vtx_ptr,
+                       is_long, nch);
     B_HIP(hipGetLastError());
-    int end_bit = 1;
-    while ((int64_t(1) << end_bit) < N) ++end_bit;
-    size_t tmp_bytes = 0, scan_bytes = 0;
-    B_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys, keys_out, vals, h->vtx_edge,
-                                             int(nnz), 0, end_bit, s));
-    B_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, deg, h->vtx_ptr, N + 1, s));
-    void* tmp = nullptr;
-    B_HIP(hipMallocAsync(&tmp, std::max(tmp_bytes, scan_bytes) + 16, s));
-    if (nnz > 0)
-      B_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys, keys_out, vals, h->vtx_edge,
-                                               int(nnz), 0, end_bit, s));
-    B_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, scan_bytes, deg, h->vtx_ptr, N + 1, s));
-    B_HIP(hipFreeAsync(tmp, s));
-    B_HIP(hipFreeAsync(keys, s));
+    B_TRY(scan_exclusive(tmp, is_long, slot_of, int64_t(N) + 1, s));
+    B_TRY(scan_exclusive(tmp, nch, chunk_of, int64_t(N) + 1, s));
+    B_HIP(hipMemcpyAsync(h->pinned_i, slot_of + N, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    B_HIP(hipMemcpyAsync(h->pinned_i + 1, chunk_of + N, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    B_HIP(hipStreamSynchronize(s));
+    h->n_long = h->pinned_i[0];
+    h->n_chunks = h->pinned_i[1];
+    B_TRY(dev_alloc(h, &h->long_row, h->n_long));
+    B_TRY(dev_alloc(h, &h->long_chunk0, h->n_long + 1));
+    B_TRY(dev_alloc(h, &h->chunk_slot, h->n_chunks));
+    B_TRY(dev_alloc(h, &h->chunk_begin, h->n_chunks));
+    B_TRY(dev_alloc(h, &h->chunk_end, h->n_chunks));
+    hipLaunchKernelGGL(k_long_fill, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, h->vtx_ptr,
+                       is_long, slot_of, chunk_of, h->long_row, h->long_chunk0, h->chunk_slot,
+                       h->chunk_begin, h->chunk_end);
+    B_HIP(hipGetLastError());
+    h->pinned_i[2] = h->n_chunks;
+    B_HIP(hipMemcpyAsync(h->long_chunk0 + h->n_long, h->pinned_i + 2, sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
+    // per-graph slot ranges: long rows are listed in increasing vertex id, so
+    // each graph's long rows are contiguous
+    std::vector<int32_t> lr(h->n_long);
+    if (h->n_long)
+      B_HIP(hipMemcpyAsync(lr.data(), h->long_row, 4 * size_t(h->n_long), hipMemcpyDeviceToHost, s));
+    B_HIP(hipStreamSynchronize(s));
+    h->seg_slots_host.assign(4 * G, 0);
+    int t = 0, l = 0;
+    std::vector<int32_t> lseg(h->n_long);
+    for (int g = 0; g < G; ++g) {
+      // tiles are generated graph by graph, so graph g owns a contiguous range
+      int t0 = t;
+      t += (vtx_off_host[g + 1] - vtx_off_host[g] + kTileRows - 1) / kTileRows;
+      int l0 = l;
+      while (l < h->n_long && lr[l] < vtx_off_host[g + 1]) lseg[l++] = g;
+      h->seg_slots_host[4 * g + 0] = t0;
+      h->seg_slots_host[4 * g + 1] = t;
+      h->seg_slots_host[4 * g + 2] = l0;
+      h->seg_slots_host[4 * g + 3] = l;
+    }
+    B_TRY(dev_alloc(h, &h->long_seg, h->n_long));
+    if (h->n_long)
+      B_HIP(hipMemcpyAsync(h->long_seg, lseg.data(), 4 * size_t(h->n_long), hipMemcpyHostToDevice, s));
+    B_HIP(hipStreamSynchronize(s));
+  }
+
+  // ---- scatter and rank
+  if (nnz > 0) {
+    B_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (size_t(N) + 1), s));
+    hipLaunchKernelGGL(k_scatter_edges, dim3(blocks_for(E, 16)), dim3(256), 0, s, E, h->edge_ptr, h->edge_vtx,
+                       h->vtx_ptr, deg, etmp);
+    hipLaunchKernelGGL(k_rank_short, dim3(blocks_for(N, 4)), dim3(256), 0, s, N, h->vtx_ptr,
+                       static_cast<const int32_t*>(etmp), h->vtx_edge);
+    if (h->n_chunks > 0)
+      hipLaunchKernelGGL(k_rank_long, dim3(h->n_chunks), dim3(kChunk), 0, s, h->vtx_ptr, h->long_row,
+                         h->chunk_slot, h->chunk_begin, h->chunk_end, static_cast<const int32_t*>(etmp),
+                         h->vtx_edge);
+    B_HIP(hipGetLastError());
   }
   B_TRY(compute_scales(h, s));
 
@@ -458,102 +734,38 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
         sg.push_back(g);
       }
     h->n_tiles = int32_t(r0.size());
-    B_TRY(dev_alloc(&h->tile_r0, r0.size()));
-    B_TRY(dev_alloc(&h->tile_r1, r0.size()));
-    B_TRY(dev_alloc(&h->tile_seg, r0.size()));
+    for (int g = 0; g < G; ++g) {
+      h->seg_slots_host[4 * g + 2] += h->n_tiles;
+      h->seg_slots_host[4 * g + 3] += h->n_tiles;
+    }
+    B_TRY(dev_alloc(h, &h->tile_r0, r0.size()));
+    B_TRY(dev_alloc(h, &h->tile_r1, r0.size()));
+    B_TRY(dev_alloc(h, &h->tile_seg, r0.size()));
+    B_TRY(dev_alloc(h, &h->seg_slots, 4 * G));
     B_HIP(hipMemcpyAsync(h->tile_r0, r0.data(), 4 * r0.size(), hipMemcpyHostToDevice, s));
     B_HIP(hipMemcpyAsync(h->tile_r1, r1.data(), 4 * r1.size(), hipMemcpyHostToDevice, s));
     B_HIP(hipMemcpyAsync(h->tile_seg, sg.data(), 4 * sg.size(), hipMemcpyHostToDevice, s));
+    B_HIP(hipMemcpyAsync(h->seg_slots, h->seg_slots_host.data(), 16 * size_t(G), hipMemcpyHostToDevice, s));
     B_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
   }
 
-  // ---- long vertex rows -> chunks
-  {
-    int32_t* tmpi = nullptr;
-    B_HIP(hipMallocAsync(reinterpret_cast<void**>(&tmpi), sizeof(int32_t) * 4 * (size_t(N) + 1), s));
-    int32_t* is_long = tmpi;
-    int32_t* nch = tmpi + (N + 1);
-    int32_t* slot_of = tmpi + 2 * (N + 1);
-    int32_t* chunk_of = tmpi + 3 * (N + 1);
-    B_HIP(hipMemsetAsync(tmpi, 0, sizeof(int32_t) * 4 * (size_t(N) + 1), s));
-    hipLaunchKernelGGL(k_long_flags, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, h->vtx_ptr,
-                       is_long, nch);
-    B_HIP(hipGetLastError());
-    size_t b1 = 0, b2 = 0;
-    B_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b1, is_long, slot_of, N + 1, s));
-    B_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b2, nch, chunk_of, N + 1, s));
-    void* tmp = nullptr;
-    B_HIP(hipMallocAsync(&tmp, std::max(b1, b2) + 16, s));
-    B_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, b1, is_long, slot_of, N + 1, s));
-    B_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, b2, nch, chunk_of, N + 1, s));
-    B_HIP(hipFreeAsync(tmp, s));
-    B_HIP(hipMemcpyAsync(h->pinned_i, slot_of + N, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    B_HIP(hipMemcpyAsync(h->pinned_i + 1, chunk_of + N, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    B_HIP(hipStreamSynchronize(s));
-    h->n_long = h->pinned_i[0];
-    h->n_chunks = h->pinned_i[1];
-    B_TRY(dev_alloc(&h->long_row, h->n_long));
-    B_TRY(dev_alloc(&h->long_chunk0, h->n_long + 1));
-    B_TRY(dev_alloc(&h->chunk_slot, h->n_chunks));
-    B_TRY(dev_alloc(&h->chunk_begin, h->n_chunks));
-    B_TRY(dev_alloc(&h->chunk_end, h->n_chunks));
-    hipLaunchKernelGGL(k_long_fill, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, h->vtx_ptr,
-                       is_long, slot_of, chunk_of, h->long_row, h->long_chunk0, h->chunk_slot,
-                       h->chunk_begin, h->chunk_end);
-    B_HIP(hipGetLastError());
-    B_HIP(hipMemcpyAsync(h->long_chunk0 + h->n_long, &h->n_chunks, sizeof(int32_t),
-                         hipMemcpyHostToDevice, s));
-    B_HIP(hipFreeAsync(tmpi, s));
-    // per-graph slot ranges: long rows are listed in increasing vertex id, so
-    // each graph's long rows are contiguous
-    std::vector<int32_t> lr(h->n_long);
-    if (h->n_long)
-      B_HIP(hipMemcpyAsync(lr.data(), h->long_row, 4 * size_t(h->n_long), hipMemcpyDeviceToHost, s));
-    B_HIP(hipStreamSynchronize(s));
-    h->seg_slots_host.assign(4 * G, 0);
-    int t = 0, l = 0;
-    std::vector<int32_t> lseg(h->n_long);
-    for (int g = 0; g < G; ++g) {
-      // tiles were generated graph by graph, so graph g owns a contiguous range
-      int t0 = t;
-      t += (vtx_off_host[g + 1] - vtx_off_host[g] + kTileRows - 1) / kTileRows;
-      int l0 = l;
-      while (l < h->n_long && lr[l] < vtx_off_host[g + 1]) lseg[l++] = g;
-      h->seg_slots_host[4 * g + 0] = t0;
-      h->seg_slots_host[4 * g + 1] = t;
-      h->seg_slots_host[4 * g + 2] = h->n_tiles + l0;
-      h->seg_slots_host[4 * g + 3] = h->n_tiles + l;
-    }
-    B_TRY(dev_alloc(&h->long_seg, h->n_long));
-    if (h->n_long)
-      B_HIP(hipMemcpyAsync(h->long_seg, lseg.data(), 4 * size_t(h->n_long), hipMemcpyHostToDevice, s));
-    B_TRY(dev_alloc(&h->seg_slots, 4 * G));
-    B_HIP(hipMemcpyAsync(h->seg_slots, h->seg_slots_host.data(), 16 * size_t(G), hipMemcpyHostToDevice, s));
-    B_HIP(hipStreamSynchronize(s));
-  }
   // ---- long hyperedges (one workgroup each in the edge gather)
   if (E > 0) {
     int32_t* tmpi = nullptr;
-    B_HIP(hipMallocAsync(reinterpret_cast<void**>(&tmpi), sizeof(int32_t) * 2 * (size_t(E) + 1), s));
+    B_TRY(tmp.get(&tmpi, 2 * (size_t(E) + 1)));
     int32_t* is_long = tmpi;
     int32_t* slot_of = tmpi + (E + 1);
     B_HIP(hipMemsetAsync(tmpi, 0, sizeof(int32_t) * 2 * (size_t(E) + 1), s));
     hipLaunchKernelGGL(k_long_edge_flags, dim3(blocks_for(E, 256)), dim3(256), 0, s, E, h->edge_ptr, is_long);
     B_HIP(hipGetLastError());
-    size_t b1 = 0;
-    B_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b1, is_long, slot_of, E + 1, s));
-    void* tmp = nullptr;
-    B_HIP(hipMallocAsync(&tmp, b1 + 16, s));
-    B_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, b1, is_long, slot_of, E + 1, s));
-    B_HIP(hipFreeAsync(tmp, s));
+    B_TRY(scan_exclusive(tmp, is_long, slot_of, int64_t(E) + 1, s));
     B_HIP(hipMemcpyAsync(h->pinned_i, slot_of + E, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     B_HIP(hipStreamSynchronize(s));
     h->n_long_edge = h->pinned_i[0];
-    B_TRY(dev_alloc(&h->long_edge, h->n_long_edge));
+    B_TRY(dev_alloc(h, &h->long_edge, h->n_long_edge));
     hipLaunchKernelGGL(k_long_edge_fill, dim3(blocks_for(E, 256)), dim3(256), 0, s, E, is_long, slot_of,
                        h->long_edge);
     B_HIP(hipGetLastError());
-    B_HIP(hipFreeAsync(tmpi, s));
   }
   // ---- edge tiles (graph-aligned) of the edge gather, and per graph the
   // slot ranges of its partial sums: tiles, then long hyperedges (listed in
@@ -566,8 +778,8 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
         e1.push_back(std::min(e + kEdgeTile, edge_off_host[g + 1]));
       }
     h->n_etiles = int32_t(e0.size());
-    B_TRY(dev_alloc(&h->etile_e0, e0.size()));
-    B_TRY(dev_alloc(&h->etile_e1, e1.size()));
+    B_TRY(dev_alloc(h, &h->etile_e0, e0.size()));
+    B_TRY(dev_alloc(h, &h->etile_e1, e1.size()));
     if (!e0.empty()) {
       B_HIP(hipMemcpyAsync(h->etile_e0, e0.data(), 4 * e0.size(), hipMemcpyHostToDevice, s));
       B_HIP(hipMemcpyAsync(h->etile_e1, e1.data(), 4 * e1.size(), hipMemcpyHostToDevice, s));
@@ -587,10 +799,11 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
       h->seg_eslots_host[4 * g + 2] = h->n_etiles + l0;
       h->seg_eslots_host[4 * g + 3] = h->n_etiles + l;
     }
-    B_TRY(dev_alloc(&h->seg_eslots, 4 * G));
+    B_TRY(dev_alloc(h, &h->seg_eslots, 4 * G));
     B_HIP(hipMemcpyAsync(h->seg_eslots, h->seg_eslots_host.data(), 16 * size_t(G), hipMemcpyHostToDevice, s));
   }
   B_HIP(hipStreamSynchronize(s));
+  tmp.release();
 #undef B_TRY
 #undef B_HIP
   *out = h;
@@ -606,37 +819,40 @@ extern "C" int hgl_version(void) { return 100; }
 extern "C" const char* hgl_last_error(void) { return g_err; }
 
 extern "C" int hgl_build_laplacian(int32_t N, int32_t E, int64_t nnz, const int32_t* edge_ptr,
-                                   const int32_t* edge_vtx, const double* w, hgl_handle** out,
-                                   hipStream_t stream) {
+                                   const int32_t* edge_vtx, const double* w, const hgl_allocator* al,
+                                   hgl_handle** out, hipStream_t stream) {
   clear_error();
   int32_t vo[2] = {0, N}, eo[2] = {0, E};
   HGL_CHECK_ARG(N >= 1 && E >= 0, "need N >= 1 and E >= 0 (got N=%d, E=%d)", N, E);
-  return build(1, vo, eo, nnz, edge_ptr, edge_vtx, w, out, stream);
+  return build(1, vo, eo, nnz, edge_ptr, edge_vtx, w, al, out, stream);
 }
 
 extern "C" int hgl_build_laplacian_batched(int32_t G, const int32_t* vtx_offsets_host,
                                            const int32_t* edge_offsets_host, int64_t nnz,
                                            const int32_t* edge_ptr, const int32_t* edge_vtx,
-                                           const double* w, hgl_handle** out, hipStream_t stream) {
+                                           const double* w, const hgl_allocator* al, hgl_handle** out,
+                                           hipStream_t stream) {
   clear_error();
-  return build(G, vtx_offsets_host, edge_offsets_host, nnz, edge_ptr, edge_vtx, w, out, stream);
+  return build(G, vtx_offsets_host, edge_offsets_host, nnz, edge_ptr, edge_vtx, w, al, out, stream);
 }
 
 extern "C" int hgl_set_weights(hgl_handle* h, const double* w, hipStream_t s) {
   clear_error();
   HGL_CHECK_ARG(h != nullptr, "handle is NULL");
   HGL_CHECK_ARG(h->E == 0 || w != nullptr, "w is NULL");
+  enter(h, s);
   if (h->E == 0) return HGL_OK;
-  int32_t* d_err = nullptr;
-  HGL_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_err), 2 * sizeof(int32_t), s));
-  int32_t err_init[2] = {0, 0x7fffffff};
-  HGL_HIP(hipMemcpyAsync(d_err, err_init, sizeof(err_init), hipMemcpyHostToDevice, s));
+  // the error words live in the handle's small workspace
+  HGL_TRY(h->ws_misc.reserve(64));
+  int32_t* d_err = h->ws_misc.as<int32_t>();
+  h->pinned_i[0] = 0;
+  h->pinned_i[1] = 0x7fffffff;
+  HGL_HIP(hipMemcpyAsync(d_err, h->pinned_i, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_validate_w, dim3(blocks_for(h->E, 256)), dim3(256), 0, s, h->E, w, d_err);
   HGL_HIP(hipGetLastError());
-  HGL_HIP(hipMemcpyAsync(h->pinned_i, d_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HGL_HIP(hipFreeAsync(d_err, s));
+  HGL_HIP(hipMemcpyAsync(h->pinned_i + 2, d_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HGL_HIP(hipStreamSynchronize(s));
-  HGL_TRY(check_error_words(h->pinned_i));
+  HGL_TRY(check_error_words(h->pinned_i + 2));
   HGL_HIP(hipMemcpyAsync(h->w, w, sizeof(double) * h->E, hipMemcpyDeviceToDevice, s));
   return compute_scales(h, s);
 }

@@ -993,6 +993,7 @@ extern "C" int hgl_cg_solve(hgl_handle* h, double lambda, const hgl_cg_opts* opt
                             int64_t ldy, void* F, int64_t ldf, int32_t k, int32_t* iters_host,
                             double* relres_host, hipStream_t stream) {
   clear_error();
+  enter(h, stream);
   HGL_CHECK_ARG(h != nullptr, "handle is NULL");
   std::vector<double> lams(h->G, lambda);
   return cg_run(h, lams.data(), opts, Y, ldy, F, ldf, k, iters_host, relres_host, nullptr, stream);
@@ -1002,5 +1003,6 @@ extern "C" int hgl_cg_solve_batched(hgl_handle* h, const double* lambdas_host, c
                                     const void* Y, int64_t ldy, void* F, int64_t ldf, int32_t k,
                                     int32_t* iters_host, double* relres_host, hipStream_t stream) {
   clear_error();
+  enter(h, stream);
   return cg_run(h, lambdas_host, opts, Y, ldy, F, ldf, k, iters_host, relres_host, nullptr, stream);
 }

@@ -601,6 +601,7 @@ extern "C" int hgl_cg_solve_wg(hgl_handle* h, double lambda, const hgl_cg_opts* 
                                float* F, int64_t ldf, int32_t k, int32_t* iters_host, double* relres_host,
                                hipStream_t s) {
   clear_error();
+  enter(h, s);
   HGL_CHECK_ARG(h != nullptr, "handle is NULL");
   std::vector<double> lams(h->G, lambda);
   return run_wg(h, lams.data(), o, Y, ldy, F, ldf, k, iters_host, relres_host, s);
@@ -610,5 +611,6 @@ extern "C" int hgl_cg_solve_wg_batched(hgl_handle* h, const double* lambdas_host
                                        const float* Y, int64_t ldy, float* F, int64_t ldf, int32_t k,
                                        int32_t* iters_host, double* relres_host, hipStream_t s) {
   clear_error();
+  enter(h, s);
   return run_wg(h, lambdas_host, o, Y, ldy, F, ldf, k, iters_host, relres_host, s);
 }

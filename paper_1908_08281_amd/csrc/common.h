@@ -66,10 +66,21 @@ constexpr int kProfKinds = 16;     // kernel kinds of the timing counters
 
 // ------------------------------------------------------ device buffers --
 
-// Grow-only device buffer.
+// Device memory source of a handle: the caller's allocator (hgl_allocator),
+// or hipMalloc / hipFree when none was given.  `stream` is the stream of the
+// call in progress: allocations are made for it and frees are ordered on it.
+struct Mem {
+  hgl_allocator al{};
+  hipStream_t stream = nullptr;
+  int alloc(void** p, size_t bytes);
+  void release(void* p);
+};
+
+// Grow-only device buffer; its memory comes from `mem` (hipMalloc if null).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Mem* mem = nullptr;
   int reserve(size_t n);
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
@@ -83,6 +94,7 @@ struct hgl_handle {
   int32_t N = 0, E = 0, G = 1;
   int64_t nnz = 0;
   int device = 0;
+  hgl::Mem mem;  // every device allocation of the handle goes through it
 
   // structure (device)
   int32_t* edge_ptr = nullptr;   // [E+1]
@@ -180,6 +192,18 @@ struct hgl_handle {
 };
 
 namespace hgl {
+
+// The stream of the API call in progress (allocations through the handle's
+// allocator are made for it).
+inline void enter(hgl_handle* h, hipStream_t s) {
+  if (h) h->mem.stream = s;
+}
+
+// Point a workspace's buffers at the handle's memory source.
+template <class... B>
+inline void attach(hgl_handle* h, B&... bufs) {
+  ((bufs.mem = &h->mem), ...);
+}
 
 // Partial-slot count of the reductions: one per tile, one per long row.
 inline int n_slots(const hgl_handle* h) { return h->n_tiles + h->n_long; }

@@ -142,16 +142,34 @@ __device__ void block_sums(double (&x)[n], double* lds /* [kProjWaves * kSect] *
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kProj) void k_project_simplex(int32_t E, const double* __restrict__ v,
-                                                           double* __restrict__ w) {
+// The point projected: v_i, or (g given) the gradient step w_i - eta g_i,
+// with eta read from *eta_in when it is given; *eta_out (nullable) receives
+// the eta used.  The step is evaluated without contraction, so every pass
+// sees the same value.
+struct StepPoint {
+  const double* v;
+  const double* g;
+  const double* eta_in;
+  double* eta_out;
+  double eta;
+  __device__ __forceinline__ double operator()(int i) const {
+#pragma clang fp contract(off)
+    return g ? v[i] - eta * g[i] : v[i];
+  }
+};
+
+__global__ __launch_bounds__(kProj) void k_project_simplex(int32_t E, StepPoint pt, double* __restrict__ w) {
   __shared__ double lds[kProjWaves * kSect];
+  if (pt.g && pt.eta_in) pt.eta = *pt.eta_in;
+  if (pt.eta_out && threadIdx.x == 0) *pt.eta_out = pt.eta;
+  const StepPoint& v = pt;
   // max v and sum v: tau lies in [max(vmax - 1, (sum v - 1)/E), vmax] (the
   // largest entry alone gives at most 1; tau = (sum v - 1)/E would give
   // every entry, so f there is >= 1)
   double mx = -INFINITY, sm[1] = {0.0};
   for (int i = threadIdx.x; i < E; i += kProj) {
-    mx = fmax(mx, v[i]);
-    sm[0] += v[i];
+    mx = fmax(mx, v(i));
+    sm[0] += v(i);
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
@@ -176,7 +194,7 @@ __global__ __launch_bounds__(kProj) void k_project_simplex(int32_t E, const doub
     for (int i0 = threadIdx.x; i0 < E; i0 += 8 * kProj) {
       double vi[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) vi[u] = i0 + u * kProj < E ? v[i0 + u * kProj] : -INFINITY;
+      for (int u = 0; u < 8; ++u) vi[u] = i0 + u * kProj < E ? v(i0 + u * kProj) : -INFINITY;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
 #pragma unroll
@@ -200,8 +218,8 @@ __global__ __launch_bounds__(kProj) void k_project_simplex(int32_t E, const doub
   for (int round = 0; round < 64; ++round) {
     double sc[2] = {0.0, 0.0};  // sum and count of the support
     for (int i = threadIdx.x; i < E; i += kProj)
-      if (v[i] > tau) {
-        sc[0] += v[i];
+      if (v(i) > tau) {
+        sc[0] += v(i);
         sc[1] += 1.0;
       }
     block_sums<2>(sc, lds);
@@ -209,7 +227,44 @@ __global__ __launch_bounds__(kProj) void k_project_simplex(int32_t E, const doub
     if (!(t2 > tau)) break;
     tau = t2;
   }
-  for (int i = threadIdx.x; i < E; i += kProj) w[i] = fmax(v[i] - tau, 0.0);
+  for (int i = threadIdx.x; i < E; i += kProj) w[i] = fmax(v(i) - tau, 0.0);
+}
+
+// The fixed step of the weight update, set from the first gradient:
+// eta = 0.5 max|w| / max|g - mean(g)| (0 when g is constant), written to
+// *eta_out.  One workgroup, fixed-order sums: deterministic.
+__global__ __launch_bounds__(kProj) void k_step_size(int32_t E, const double* __restrict__ w,
+                                                     const double* __restrict__ g, double* __restrict__ eta_out) {
+  __shared__ double lds[kProjWaves * kSect];
+  double sm[2] = {0.0, 0.0};  // sum g, max |w| (as a sum slot after the max reduction)
+  double wmax = 0.0;
+  for (int i = threadIdx.x; i < E; i += kProj) {
+    sm[0] += g[i];
+    wmax = fmax(wmax, fabs(w[i]));
+  }
+  double sg[1] = {sm[0]};
+  block_sums<1>(sg, lds);
+  const double mean = sg[0] / double(E);
+  double dmax = 0.0;
+  for (int i = threadIdx.x; i < E; i += kProj) dmax = fmax(dmax, fabs(g[i] - mean));
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    wmax = fmax(wmax, __shfl_xor(wmax, off, kWave));
+    dmax = fmax(dmax, __shfl_xor(dmax, off, kWave));
+  }
+  if (threadIdx.x % kWave == 0) {
+    lds[(threadIdx.x / kWave) * kSect] = wmax;
+    lds[(threadIdx.x / kWave) * kSect + 1] = dmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int wv = 0; wv < kProjWaves; ++wv) {
+      a = fmax(a, lds[wv * kSect]);
+      b = fmax(b, lds[wv * kSect + 1]);
+    }
+    *eta_out = b > 0.0 ? 0.5 * a / b : 0.0;
+  }
 }
 
 // ------------------------------------------------ active-set step (eq. 5) --
@@ -439,6 +494,7 @@ extern "C" int hgl_weight_grad(hgl_handle* h, double lambda, double mu, const vo
                                double* grad_w, void* Z_out, int64_t ldz, int32_t* iters_host,
                                double* relres_host, hipStream_t s) {
   clear_error();
+  enter(h, s);
   HGL_CHECK_ARG(h != nullptr && adj != nullptr, "handle and adjoint options must not be NULL");
   HGL_CHECK_ARG(h->G == 1, "the weight gradient needs a single-graph handle");
   HGL_CHECK_ARG(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0");
@@ -461,7 +517,28 @@ extern "C" int hgl_weight_grad(hgl_handle* h, double lambda, double mu, const vo
 extern "C" int hgl_project_simplex(const double* v, double* w, int32_t E, hipStream_t s) {
   clear_error();
   HGL_CHECK_ARG(E >= 1 && v && w, "need E >= 1 and v, w");
-  hipLaunchKernelGGL(k_project_simplex, dim3(1), dim3(kProj), 0, s, E, v, w);
+  hipLaunchKernelGGL(k_project_simplex, dim3(1), dim3(kProj), 0, s, E, StepPoint{v, nullptr, nullptr, nullptr, 0.0},
+                     w);
+  HGL_HIP(hipGetLastError());
+  return HGL_OK;
+}
+
+extern "C" int hgl_projected_gradient_step(const double* w, const double* g, double eta, int32_t E, double* w_out,
+                                           double* eta_dev, hipStream_t s) {
+  clear_error();
+  HGL_CHECK_ARG(E >= 1 && w && g && w_out, "need E >= 1 and w, g, w_out");
+  HGL_CHECK_ARG(std::isfinite(eta), "eta must be finite");
+  HGL_CHECK_ARG(eta > 0.0 || eta_dev, "eta <= 0 asks for the step from the gradient: eta_dev must be given");
+  HGL_CHECK_ARG(w_out != w && w_out != g, "w_out must not alias w or g");
+  if (eta > 0.0) {
+    hipLaunchKernelGGL(k_project_simplex, dim3(1), dim3(kProj), 0, s, E, StepPoint{w, g, nullptr, eta_dev, eta},
+                       w_out);
+  } else {
+    hipLaunchKernelGGL(k_step_size, dim3(1), dim3(kProj), 0, s, E, w, g, eta_dev);
+    HGL_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_project_simplex, dim3(1), dim3(kProj), 0, s, E, StepPoint{w, g, eta_dev, nullptr, 0.0},
+                       w_out);
+  }
   HGL_HIP(hipGetLastError());
   return HGL_OK;
 }

@@ -958,7 +958,10 @@ static void rsvd_delete(void* p) {
 
 static Rsvd& rsvd_of(hgl_handle* h) {
   if (!h->rsvd_ws) {
-    h->rsvd_ws = new Rsvd();
+    Rsvd* R = new Rsvd();
+    attach(h, R->meta, R->A, R->Y, R->S, R->ST, R->Gpart, R->Li, R->Ut, R->sig, R->fail, R->omega, R->U, R->dT,
+           R->Tpart);
+    h->rsvd_ws = R;
     h->rsvd_free = &rsvd_delete;
   }
   return *static_cast<Rsvd*>(h->rsvd_ws);
@@ -1317,6 +1320,7 @@ extern "C" int hgl_block_rsvd(hgl_handle* h, int32_t n_blocks, const int32_t* bl
                               const hgl_rsvd_opts* o, const uint16_t* omega_bf16, float* U_out,
                               double* sigma_out, hipStream_t s) {
   clear_error();
+  enter(h, s);
   HGL_TRY(check_opts(h, n_blocks, block_offsets_host, o));
   HGL_CHECK_ARG(U_out != nullptr, "U_out must not be NULL");
   Rsvd& R = rsvd_of(h);
@@ -1331,6 +1335,7 @@ extern "C" int hgl_block_rsvd_invert(hgl_handle* h, double lambda, int32_t n_blo
                                      int64_t ldf, int32_t nrhs, double* sigma_out, int32_t* iters_host,
                                      double* relres_host, hipStream_t s) {
   clear_error();
+  enter(h, s);
   HGL_TRY(check_opts(h, n_blocks, block_offsets_host, o));
   HGL_CHECK_ARG(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0");
   HGL_CHECK_ARG(Y && F && nrhs >= 1 && ldy >= nrhs && ldf >= nrhs, "bad Y/F/nrhs/leading dimensions");

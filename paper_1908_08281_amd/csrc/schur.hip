@@ -352,7 +352,9 @@ void schur_delete(void* p) {
 
 Schur& schur_of(hgl_handle* h) {
   if (!h->schur_ws) {
-    h->schur_ws = new Schur();
+    Schur* S = new Schur();
+    attach(h, S->arena, S->meta, S->pmeta);
+    h->schur_ws = S;
     h->schur_free = &schur_delete;
   }
   return *static_cast<Schur*>(h->schur_ws);
@@ -728,6 +730,7 @@ extern "C" int hgl_block_schur_inverse(hgl_handle* h, double lambda, int32_t n_b
                                        const int32_t* block_offsets_host, int32_t min_block, float* inv_out,
                                        double* flops_out, hipStream_t s) {
   clear_error();
+  enter(h, s);
   HGL_TRY(check_blocks(h, n_blocks, block_offsets_host, min_block));
   HGL_CHECK_ARG(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0");
   Schur& S = schur_of(h);
@@ -746,6 +749,7 @@ extern "C" int hgl_block_schur_invert(hgl_handle* h, double lambda, int32_t n_bl
                                       int64_t ldf, int32_t nrhs, int32_t* iters_host, double* relres_host,
                                       hipStream_t s) {
   clear_error();
+  enter(h, s);
   HGL_TRY(check_blocks(h, n_blocks, block_offsets_host, min_block));
   HGL_CHECK_ARG(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0");
   HGL_CHECK_ARG(Y && F && nrhs >= 1 && ldy >= nrhs && ldf >= nrhs, "bad Y/F/nrhs/leading dimensions");

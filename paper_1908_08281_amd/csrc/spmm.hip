@@ -590,6 +590,7 @@ using namespace hgl;
 extern "C" int hgl_apply(hgl_handle* h, double lambda, int32_t dt, const void* P, int64_t ldp,
                          void* Q, int64_t ldq, int32_t k, hipStream_t st) {
   clear_error();
+  enter(h, st);
   HGL_CHECK_ARG(h != nullptr, "handle is NULL");
   HGL_CHECK_ARG(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0 (got %g)", lambda);
   HGL_CHECK_ARG(k >= 1, "k must be >= 1");

@@ -7,7 +7,9 @@ tensors on a ROCm device; names follow the C entry points without the
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 import torch
@@ -46,12 +48,58 @@ def _rows(t: torch.Tensor, name: str) -> int:
     return t.stride(0)
 
 
+class TorchAllocator:
+    """torch's caching allocator behind hgl_allocator, so that torch owns every
+    device buffer of a handle (its allocations are made for the stream of the
+    library call that asks, and go back to torch's cache when freed)."""
+
+    def __init__(self, device: torch.device):
+        index = device.index if device.index is not None else torch.cuda.current_device()
+
+        def alloc(nbytes, ctx, stream):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), index, int(stream or 0))
+            except Exception:  # the library reports HGL_ENOMEM
+                return None
+
+        def free(ptr, ctx, stream):
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:
+                pass
+
+        self._alloc = _lib.ALLOC_FN(alloc)
+        self._free = _lib.FREE_FN(free)
+        self.struct = _lib.Allocator(self._alloc, self._free, None)
+
+
+_live_handles = weakref.WeakSet()
+
+
+@atexit.register
+def _destroy_live_handles():
+    # before the interpreter tears torch down: the handles' buffers go back
+    # to torch's allocator while it still exists
+    for h in list(_live_handles):
+        h.destroy()
+
+
+def _allocator(device: torch.device, allocator):
+    if allocator == "torch":
+        return TorchAllocator(device)
+    if allocator is None or allocator == "hip":
+        return None
+    raise ValueError(f"allocator must be 'torch' or 'hip', got {allocator!r}")
+
+
 class Handle:
     """Owns an hgl_handle (the built operator of one or more hypergraphs)."""
 
-    def __init__(self, ptr: C.c_void_p, device: torch.device):
+    def __init__(self, ptr: C.c_void_p, device: torch.device, allocator: TorchAllocator | None = None):
         self._ptr = ptr
         self.device = device
+        self._allocator = allocator  # kept alive as long as the handle
+        _live_handles.add(self)
         N, E, G = C.c_int32(), C.c_int32(), C.c_int32()
         nnz = C.c_int64()
         check(lib().hgl_get_sizes(ptr, C.byref(N), C.byref(E), C.byref(nnz), C.byref(G)),
@@ -99,21 +147,26 @@ class Handle:
             pass
 
 
-def build_laplacian(edge_ptr: torch.Tensor, edge_vtx: torch.Tensor, w: torch.Tensor, N: int) -> Handle:
+def build_laplacian(edge_ptr: torch.Tensor, edge_vtx: torch.Tensor, w: torch.Tensor, N: int,
+                    allocator: str | None = "torch") -> Handle:
+    """allocator "torch" (default): the handle's device memory comes from torch's
+    caching allocator; "hip" or None: the library's hipMalloc."""
     dev = w.device
     _need(edge_ptr, torch.int32, "edge_ptr", dev)
     _need(edge_vtx, torch.int32, "edge_vtx", dev)
     _need(w, torch.float64, "w", dev)
     E = edge_ptr.numel() - 1
     out = C.c_void_p()
+    al = _allocator(dev, allocator)
     with torch.cuda.device(dev):
         check(lib().hgl_build_laplacian(N, E, edge_vtx.numel(), _ptr(edge_ptr), _ptr(edge_vtx), _ptr(w),
-                                        C.byref(out), _stream(dev)), "hgl_build_laplacian")
-    return Handle(out, dev)
+                                        C.byref(al.struct) if al else None, C.byref(out), _stream(dev)),
+              "hgl_build_laplacian")
+    return Handle(out, dev, al)
 
 
 def build_laplacian_batched(vtx_offsets, edge_offsets, edge_ptr: torch.Tensor, edge_vtx: torch.Tensor,
-                            w: torch.Tensor) -> Handle:
+                            w: torch.Tensor, allocator: str | None = "torch") -> Handle:
     dev = w.device
     _need(edge_ptr, torch.int32, "edge_ptr", dev)
     _need(edge_vtx, torch.int32, "edge_vtx", dev)
@@ -122,12 +175,14 @@ def build_laplacian_batched(vtx_offsets, edge_offsets, edge_ptr: torch.Tensor, e
     eo = np.ascontiguousarray(np.asarray(edge_offsets, dtype=np.int32))
     G = vo.size - 1
     out = C.c_void_p()
+    al = _allocator(dev, allocator)
     with torch.cuda.device(dev):
         check(lib().hgl_build_laplacian_batched(
             G, vo.ctypes.data_as(_lib.I32P), eo.ctypes.data_as(_lib.I32P), edge_vtx.numel(),
-            _ptr(edge_ptr), _ptr(edge_vtx), _ptr(w), C.byref(out), _stream(dev)),
+            _ptr(edge_ptr), _ptr(edge_vtx), _ptr(w), C.byref(al.struct) if al else None, C.byref(out),
+            _stream(dev)),
             "hgl_build_laplacian_batched")
-    return Handle(out, dev)
+    return Handle(out, dev, al)
 
 
 def set_weights(h: Handle, w: torch.Tensor) -> None:
@@ -421,7 +476,8 @@ def weight_grad(h: Handle, lam: float, F: torch.Tensor, G: torch.Tensor | None =
                 max_iter: int = 1000, want_z: bool = False):
     """d/dw of a loss through the solve (G given: upstream dl/dF) or of the
     objective tr(F'LF) + lam||F-Y||^2 + mu||w||^2 (G None).
-    Returns (grad_w [E] float64, Z or None, adjoint iters, adjoint relres)."""
+    Returns (grad_w [E] float64, Z or None, adjoint iters, adjoint relres,
+    adjoint status: 0, or 1 when the adjoint solve stopped at max_iter)."""
     m = MODES[mode]
     dtype = torch.float64 if m == _lib.HGL_CG_PLAIN_F64 else torch.float32
     _need(F, dtype, "F", h.device)
@@ -445,7 +501,7 @@ def weight_grad(h: Handle, lam: float, F: torch.Tensor, G: torch.Tensor | None =
                                    iters.ctypes.data_as(_lib.I32P), rel.ctypes.data_as(_lib.DP),
                                    _stream(h.device))
     check(st, "hgl_weight_grad")
-    return grad, Z, iters, rel
+    return grad, Z, iters, rel, st
 
 
 def project_simplex(v: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -454,6 +510,24 @@ def project_simplex(v: torch.Tensor, out: torch.Tensor | None = None) -> torch.T
     with torch.cuda.device(v.device):
         check(lib().hgl_project_simplex(_ptr(v), _ptr(w), v.numel(), _stream(v.device)), "hgl_project_simplex")
     return w
+
+
+def projected_gradient_step(w: torch.Tensor, g: torch.Tensor, eta: float | None = None,
+                            out: torch.Tensor | None = None, eta_out: torch.Tensor | None = None):
+    """w_out = Proj_simplex(w - eta g) (hgl_projected_gradient_step).  eta None: the
+    library sets the step from this gradient (0.5 max|w| / max|g - mean g|).  Returns
+    (w_out, eta as a device FP64 tensor of one element)."""
+    _need(w, torch.float64, "w")
+    _need(g, torch.float64, "g", w.device)
+    if g.numel() != w.numel():
+        raise ValueError("w and g must have the same length")
+    wo = torch.empty_like(w) if out is None else out
+    ed = torch.empty(1, dtype=torch.float64, device=w.device) if eta_out is None else eta_out
+    with torch.cuda.device(w.device):
+        check(lib().hgl_projected_gradient_step(_ptr(w), _ptr(g), 0.0 if eta is None else float(eta), w.numel(),
+                                                _ptr(wo), _ptr(ed), _stream(w.device)),
+              "hgl_projected_gradient_step")
+    return wo, ed
 
 
 def active_set_step(w: torch.Tensor, g: torch.Tensor, mu: float, out: torch.Tensor | None = None,

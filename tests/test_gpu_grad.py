@@ -32,8 +32,9 @@ def test_vjp_matches_oracle(mode):
     tol = 1e-12 if mode == "f64" else 3e-7
     F = torch.from_numpy(np.ascontiguousarray(F_o)).to(dev, dt)
     say("vjp", mode)
-    g, Z, it, rel = hgl().weight_grad(h, p.lam, F, G=torch.from_numpy(G).to(dev, dt), mode=mode, tol=tol,
-                                      want_z=True)
+    g, Z, it, rel, ast = hgl().weight_grad(h, p.lam, F, G=torch.from_numpy(G).to(dev, dt), mode=mode, tol=tol,
+                                           want_z=True)
+    assert ast == 0
     bound = 1e-10 if mode == "f64" else 1e-5
     assert relerr(g.cpu().numpy(), g_o) <= bound
     assert relerr(Z.cpu().double().numpy(), Z_o) <= (1e-10 if mode == "f64" else 1e-6)
@@ -48,7 +49,8 @@ def test_objective_gradient_matches_oracle_and_homogeneity():
     h = build(p, dev)
     Y = torch.from_numpy(p.Y).to(dev, torch.float32)
     F, _, _, st = hgl().cg_solve(h, p.lam, Y, tol=3e-7)
-    g, _, _, _ = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=3e-7)
+    g, _, _, _, ast = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=3e-7)
+    assert ast == 0
     g = g.cpu().numpy()
     g_o = ograd.objective_grad(H, p.w, p.lam, mu, p.Y, F.cpu().double().numpy())
     assert relerr(g, g_o) <= 1e-5
@@ -56,7 +58,7 @@ def test_objective_gradient_matches_oracle_and_homogeneity():
     lhs = float(p.w @ g)
     assert abs(lhs - 2 * mu * p.w @ p.w) <= 1e-6 * float(np.abs(p.w * g).sum())
     # the adjoint handed back: Z = M^-1 (2 lambda (M F - Y)), same gradient
-    g2, Z, _, _ = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=3e-7, want_z=True)
+    g2, Z, _, _, _ = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=3e-7, want_z=True)
     assert np.array_equal(g2.cpu().numpy(), g)
     Fd = F.cpu().double().numpy()
     M = lap.system_matrix(H, p.w, p.lam)
@@ -76,7 +78,8 @@ def test_objective_gradient_matches_richardson_fd():
     h = build(p, dev)
     Y = torch.from_numpy(p.Y).to(dev)
     F, _, _, _ = hgl().cg_solve(h, p.lam, Y, mode="f64", tol=1e-13)
-    g, _, _, _ = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, mode="f64", tol=1e-13)
+    g, _, _, _, ast = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, mode="f64", tol=1e-13)
+    assert ast == 0
     g = g.cpu().numpy()
     edges = synth.rng_for(9).choice(np.nonzero(p.w > 2e-6)[0], size=64, replace=False)
     J = lambda w: ograd.objective(H, w, p.lam, mu, p.Y)  # noqa: E731
@@ -95,6 +98,33 @@ def test_simplex_projection_matches_oracle():
         assert np.all(w >= 0) and abs(w.sum() - 1) < 1e-12
     w0 = synth.dirichlet_weights(500, 4)
     assert np.allclose(hgl().project_simplex(torch.from_numpy(w0).to(dev)).cpu().numpy(), w0, atol=1e-15)
+
+
+def test_projected_gradient_step_matches_oracle():
+    """hgl_projected_gradient_step against the oracle's step rule and
+    projection: a given eta, and eta set from the gradient (reported on the
+    device); sizes from one entry to the learning workload's E."""
+    import torch
+    dev = device()
+    for seed, E in [(0, 1), (1, 7), (2, 1000), (3, 80_000)]:
+        say("pg step", E)
+        w = synth.dirichlet_weights(E, seed)
+        g = synth.rng_for(seed + 10).normal(0.0, 1.0, size=E)
+        wd, gd = torch.from_numpy(w).to(dev), torch.from_numpy(g).to(dev)
+        eta_o = simplex.initial_step(w, g)
+        w1, e1 = hgl().projected_gradient_step(wd, gd, None)
+        eta1 = float(e1.item())
+        assert abs(eta1 - eta_o) <= 1e-14 * abs(eta_o)
+        ref = simplex.project(w - eta1 * g)
+        assert np.allclose(w1.cpu().numpy(), ref, rtol=0, atol=1e-15 + 1e-13 * ref.max())
+        w2, e2 = hgl().projected_gradient_step(wd, gd, 0.37 / E)
+        assert float(e2.item()) == 0.37 / E
+        ref2 = simplex.project(w - (0.37 / E) * g)
+        assert np.allclose(w2.cpu().numpy(), ref2, rtol=0, atol=1e-15 + 1e-13 * ref2.max())
+        assert abs(float(w2.sum()) - 1.0) < 1e-12 and bool((w2 >= 0).all())
+    from paper_1908_08281_amd import _lib
+    with pytest.raises(_lib.HglError):
+        hgl().projected_gradient_step(wd, gd, float("nan"))
 
 
 def test_autograd_function():
@@ -133,8 +163,11 @@ def test_learning_loop_teacher_forced():
     for t in range(4):
         w_t = w.cpu().numpy()
         w, recs = learn_weights(h, Y, p.lam, mu, 1, w, eta=eta, tol=3e-7, history=True)
-        eta = recs[0]["eta"]
+        assert recs[0]["cg_status"] == 0 and recs[0]["adjoint_status"] == 0
         g_o = ograd.objective_grad(H, w_t, p.lam, mu, p.Y)
+        if eta is None:  # the library's step from the first gradient
+            assert abs(recs[0]["eta"] - simplex.initial_step(w_t, g_o)) <= 1e-4 * recs[0]["eta"]
+        eta = recs[0]["eta"]
         w_next_o = simplex.project(w_t - eta * g_o)
         assert relerr(w.cpu().numpy(), w_next_o) <= 1e-5
     J4 = ograd.objective(H, w.cpu().numpy(), p.lam, mu, p.Y)
@@ -154,7 +187,8 @@ def test_full_size_gradient_against_sparse_oracle():
     Y = torch.from_numpy(p.Y).to(dev, torch.float32)
     say("grad full size")
     F, _, _, st = hgl().cg_solve(h, p.lam, Y, tol=5e-7)
-    g, _, _, _ = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=5e-7)
+    g, _, _, _, ast = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=5e-7)
+    assert ast == 0
     g = g.cpu().numpy()
     op = lap.SparseOperator(p.N, p.E, p.edge_ptr, p.edge_vtx, p.w, p.lam)
     g_o = ograd.objective_grad_sparse(op, p.w, p.lam, mu, p.Y, F.cpu().double().numpy())
@@ -182,12 +216,13 @@ def test_full_size_gradient_k500_homogeneity_and_additivity():
     say("grad full size k=500")
     F, _, rel, st = hgl().cg_solve(h, p.lam, Y, tol=tol)
     assert st == 0 and np.all(rel <= tol)
-    g, _, _, _ = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=tol)
+    g, _, _, _, ast = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=tol)
+    assert ast == 0
     g = g.cpu().numpy()
     assert abs(p.w @ g - 2 * mu * p.w @ p.w) <= 1e-6 * float(np.abs(p.w * g).sum())
     halves = []
     for c0, c1 in ((0, 250), (250, 500)):
-        gh, _, _, _ = hgl().weight_grad(h, p.lam, F[:, c0:c1].contiguous(), Y=Y[:, c0:c1].contiguous(), mu=mu,
+        gh, _, _, _, _ = hgl().weight_grad(h, p.lam, F[:, c0:c1].contiguous(), Y=Y[:, c0:c1].contiguous(), mu=mu,
                                         tol=tol)
         halves.append(gh.cpu().numpy() - 2 * mu * p.w)
     assert relerr(g - 2 * mu * p.w, halves[0] + halves[1]) <= 1e-6

@@ -108,3 +108,23 @@ def test_simplex_projection_fixed_point_and_kkt():
     tau = (v - w)[sup]
     assert np.allclose(tau, tau[0], atol=1e-14)        # w = v - tau on the support
     assert np.all(v[~sup] <= tau[0] + 1e-14)           # v <= tau off the support
+
+
+def test_initial_step_rule():
+    """The fixed step of the weight update: a hand-worked value, the constant
+    gradient (no move), and the invariances it must have. Adding a constant
+    to g leaves the projected step unchanged (the projection absorbs it into
+    tau), so eta must not change. Scaling g by c scales eta by 1/c, so the
+    first step eta * g stays the same."""
+    # w = (0.5, 0.3, 0.2), g = (1, 2, 6): mean 3, max|g - 3| = 3, max|w| = 0.5
+    assert abs(simplex.initial_step([0.5, 0.3, 0.2], [1.0, 2.0, 6.0]) - 1.0 / 12.0) < 1e-16
+    assert simplex.initial_step([0.5, 0.5], [3.0, 3.0]) == 0.0
+    w = synth.dirichlet_weights(40, 5)
+    g = synth.rng_for(6).normal(0, 1, 40)
+    eta = simplex.initial_step(w, g)
+    assert abs(simplex.initial_step(w, g + 7.5) - eta) <= 1e-14 * eta
+    assert abs(simplex.initial_step(w, 4.0 * g) - eta / 4.0) <= 1e-14 * eta
+    # the first step moves no weight by more than half the largest one
+    # (before the projection, relative to the mean shift)
+    step = eta * (g - g.mean())
+    assert np.abs(step).max() <= 0.5 * w.max() * (1 + 1e-14)

@@ -59,10 +59,12 @@ def test_noalloc_takes_no_device_memory_and_refuses_oversize():
     hgl().apply(h, p.lam, P[:, :8].contiguous(), out=Q[:, :8].contiguous(), noalloc=True)
     torch.cuda.synchronize()
     free0, _ = torch.cuda.mem_get_info(dev)
+    held0 = torch.cuda.memory_allocated(dev)  # the handle's buffers come from torch's allocator
     hgl().apply(h, p.lam, P, out=Q, noalloc=True)
     torch.cuda.synchronize()
     free1, _ = torch.cuda.mem_get_info(dev)
     assert free0 - free1 < 4 << 20, (free0, free1)
+    assert torch.cuda.memory_allocated(dev) == held0
     Q_ref = hgl().apply(h, p.lam, P)
     assert torch.equal(Q, Q_ref)
     # E x k x 8 = 51 MB of FP64 Z, plus the hub partials: over 64 MiB at k = 300
