@@ -300,9 +300,10 @@ int hgl_cg_solve_wg(hgl_handle* h, double lambda, const hgl_cg_opts* opts, const
                     float* F, int64_t ldf, int32_t k, int32_t* iters_host, double* relres_host,
                     hipStream_t stream);
 
-/* As hgl_cg_solve_wg with one lambda per graph of a batched handle
- * (lambdas_host [G]); Y and F are the row concatenations of the graphs'
- * blocks (sum N_g x k), as for hgl_cg_solve_batched. */
+/* As hgl_cg_solve_wg (section 3, eqs. 16-20, one solve per query as in
+ * section 4) with one lambda per graph of a batched handle (lambdas_host
+ * [G]); Y and F are the row concatenations of the graphs' blocks
+ * (sum N_g x k), as for hgl_cg_solve_batched. */
 int hgl_cg_solve_wg_batched(hgl_handle* h, const double* lambdas_host, const hgl_cg_opts* opts,
                             const float* Y, int64_t ldy, float* F, int64_t ldf, int32_t k,
                             int32_t* iters_host, double* relres_host, hipStream_t stream);
@@ -376,7 +377,9 @@ int hgl_block_rsvd(hgl_handle* h, int32_t n_blocks, const int32_t* block_offsets
 
 /*
  * Solve (I + L/lambda) F = Y (Y, F: N x nrhs FP32) with the block inverse
- * built from hgl_block_rsvd: F0 = blockdiag(M_bb^-1) Y, refined by
+ * built from hgl_block_rsvd (eq. 15 in its identity-plus-low-rank form,
+ * M_bb^-1 ~ lambda/(1+lambda) [I + U diag(sigma/(1+lambda-sigma)) U'], on the
+ * tessellation of eq. 11): F0 = blockdiag(M_bb^-1) Y, refined by
  * preconditioned CG (FP32 vectors, FP64 inner products, residual
  * replacement) until the FP64-recomputed relres of every column is at most
  * opts->refine_tol.  iters_host [nrhs], relres_host [nrhs], sigma_out
@@ -420,7 +423,8 @@ int hgl_sketch_gaussian(int64_t rows, int32_t l, uint64_t seed, uint16_t* out_bf
  * ------------------------------------------------------------------------ */
 
 /*
- * The inverse of every diagonal block.  inv_out (device, nullable): the
+ * The inverse of every diagonal block by eqs. 12-14 under nested
+ * tessellation (as above).  inv_out (device, nullable): the
  * blocks' inverses packed in block order, block b as n_b x n_b FP32
  * row-major at element offset sum_{c<b} n_c^2.  flops_out (host, nullable):
  * the algorithmic flops of the products (2 m n k each).  The workspace
@@ -433,7 +437,8 @@ int hgl_block_schur_inverse(hgl_handle* h, double lambda, int32_t n_blocks, cons
 
 /*
  * Solve (I + L/lambda) F = Y (Y, F: N x nrhs FP32, device, row-major) with
- * the block inverse as the preconditioner: F0 = blockdiag(M_bb^-1) Y, then
+ * the block inverse of eqs. 12-14 as the preconditioner: F0 =
+ * blockdiag(M_bb^-1) Y, then
  * preconditioned CG (FP32 vectors, FP64 inner products, residual
  * replacement) until every column's FP64-recomputed relres is at most
  * refine_tol or max_refine iterations ran.  chunk as hgl_cg_opts.chunk.
@@ -445,7 +450,8 @@ int hgl_block_schur_invert(hgl_handle* h, double lambda, int32_t n_blocks, const
                            double* relres_host, hipStream_t stream);
 
 /*
- * The execution plan of hgl_block_schur_inverse, host only (no device call),
+ * The execution plan of hgl_block_schur_inverse (the products and leaves of
+ * eqs. 12-14, phase by phase), host only (no device call),
  * for inspection.  counts7: {products, leaves, phases, workspace elements,
  * inverse elements, product tiles, flops}.  Optional outputs (host, sized
  * from counts7 by a first call with NULLs):
@@ -471,6 +477,7 @@ int hgl_block_schur_plan(int32_t n_blocks, const int32_t* block_offsets_host, in
  * ------------------------------------------------------------------------ */
 
 /*
+ * The gradient of eq. 4's P(w) through the solve of eq. 3 (section 2).
  * grad_w [E] (device, FP64) = derivative with respect to w of:
  *  - G != NULL: a loss l(F) of F = (I + L/lambda)^-1 Y with upstream
  *    G = dl/dF:  grad_w[e] = Gamma_e(Z, F)/lambda, Z = M^-1 G;
