@@ -61,7 +61,7 @@ BF16_PEAK_TFLOPS = 2500.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
-def gather_bytes(N, E, nnz, k, elem=4, covered=None, hubs=0):
+def gather_bytes(N, E, nnz, k, elem=4, covered=None, hubs=0, decoupled=0):
     """Algorithmic HBM bytes of one launch of each operator-gather kernel, and
     of one CG iteration.
 
@@ -72,17 +72,32 @@ def gather_bytes(N, E, nnz, k, elem=4, covered=None, hubs=0):
     rows, more hyperedges than the hub threshold, are finished by a separate
     launch); vtx_ptr, vtx_edge, s.
     vertex_step (k_spmm_vertex as the fused CG step): read every Z row once,
-    read P, F, R and write F, R for the N - hubs rows it finishes itself;
-    vtx_ptr, vtx_edge, s.
+    read P, F, R and write F, R for the rows it finishes itself: N less the
+    hub rows and the `decoupled` rows (s_v = 0, solved at the start of the
+    solve and skipped); vtx_ptr, vtx_edge, s of every row.
+    direction (k_cg_direction): read R and P, write P, for the rows that
+    iterate (N - decoupled).
     cg_iteration: a lower bound, F, R, P read and written once, the E x k
-    intermediate written and read once, both CSR index arrays read once."""
+    intermediate written and read once, both CSR index arrays read once, over
+    all N rows (the definition the iteration's bandwidth fraction uses).
+    cg_iteration_as_run: the same over the N - decoupled rows that iterate."""
     covered = N if covered is None else covered
     idx = 4 * (N + 1 + nnz + (N - hubs))
     vertex = elem * k * (E + 2 * (N - hubs)) + idx
-    step = elem * k * (E + 5 * (N - hubs)) + idx
+    step = elem * k * (E + 5 * (N - hubs - decoupled)) + 4 * (N + 1 + nnz + N)
     edge = elem * k * (covered + E) + 4 * (2 * E + 1 + nnz + covered)
     per_iter = elem * k * (6 * N + 2 * E) + 4 * (2 * nnz + 2 * N + 2 * E)
-    return {"vertex_gather": vertex, "vertex_step": step, "edge_gather": edge, "cg_iteration": per_iter}
+    as_run = elem * k * (6 * (N - decoupled) + 2 * E) + 4 * (2 * nnz + 2 * N + 2 * E)
+    return {"vertex_gather": vertex, "vertex_step": step, "edge_gather": edge, "cg_iteration": per_iter,
+            "direction": 3 * elem * k * (N - decoupled), "cg_iteration_as_run": as_run}
+
+
+def decoupled_rows(p):
+    """Rows with delta(v) = 0 (no hyperedge of positive weight): s_v = 0, so
+    the fused solve fixes them at the start and skips them."""
+    per_entry = np.repeat(np.asarray(p.w, dtype=np.float64), np.diff(p.edge_ptr))
+    dv = np.bincount(p.edge_vtx, weights=per_entry, minlength=p.N)
+    return int(np.count_nonzero(dv == 0))
 
 
 # ------------------------------------------------------- profile summaries
@@ -443,7 +458,8 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
     elem = 4 if mode == "f32" else 8
     part = h.partition()
     covered = int(np.unique(p.edge_vtx).size)
-    ab = gather_bytes(p.N, p.E, p.nnz, k, elem, covered, part["hub_rows"])
+    dec = decoupled_rows(p)
+    ab = gather_bytes(p.N, p.E, p.nnz, k, elem, covered, part["hub_rows"], dec)
     nv, mv = prof["vertex_gather"]
     ne, me = prof["edge_gather"]
     # template instances the solves ran (the column shape may be autotuned)
@@ -466,7 +482,10 @@ def bench_cg(a, name, p, mode, tol, rr_period=0, with_cpu=True):
                  + (f" and every {rr_period}" if rr_period else ""),
            "iterations": it_mean, "all_columns_converged": state["ok"], "partition": part}
     it_gbs = ab["cg_iteration"] * it_mean / (ms * 1e-3) / 1e9
+    run_gbs = ab["cg_iteration_as_run"] * it_mean / (ms * 1e-3) / 1e9
     extra = {"cg_iteration_gbs": round(it_gbs, 1), "cg_iteration_frac": round(it_gbs / HBM_PEAK_GBS, 4),
+             "cg_iteration_as_run": {"decoupled_rows": dec, "bytes": int(ab["cg_iteration_as_run"]),
+                                     "gbs": round(run_gbs, 1), "frac": round(run_gbs / HBM_PEAK_GBS, 4)},
              "ms_per_step_median": round(float(np.median(state["ms"][:a.steps])), 4),
              "kernel_ms": breakdown}
     if batched and not a.no_extra:
@@ -847,7 +866,7 @@ def bench_learn(a):
     prof = hgl.profile_read(h)
     hgl.profile(h, False)
     part = h.partition()
-    ab = gather_bytes(p.N, p.E, p.nnz, k, 4, int(np.unique(p.edge_vtx).size), part["hub_rows"])
+    ab = gather_bytes(p.N, p.E, p.nnz, k, 4, int(np.unique(p.edge_vtx).size), part["hub_rows"], decoupled_rows(p))
     nv, mv = prof["vertex_gather"]
     roof = _roof("k_spmm_vertex", nv, mv, ab["vertex_step"])
     shp = h.gather_shape()

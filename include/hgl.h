@@ -242,6 +242,9 @@ int hgl_apply_noalloc(hgl_handle* h, double lambda, int32_t dt, const void* P, i
  * its search direction while that residual's norm is at most 1.1 times the
  * recursive one's, and restarts the direction from it otherwise (a direction
  * scaled to a drifted recursive residual makes the step overshoot).
+ * Rows with delta(v) = 0 (no hyperedge of positive weight) are decoupled:
+ * their equation is F_v = Y_v lambda/(1 + lambda), set at the start, and
+ * the iteration skips them (a given start is overwritten there).
  * Y, F: N x k of type double (PLAIN_F64) or float
  * (F32_F64DOT_RR).  iters_host [G*k] (nullable) receives the iteration count
  * of each (graph, column), relres_host [G*k] (nullable) the FP64-recomputed

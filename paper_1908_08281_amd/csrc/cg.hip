@@ -67,9 +67,12 @@ __device__ __forceinline__ void zero_long_slots(double* part, int n_tiles, int n
 }
 
 // Start: (x0 not given) F = 0, R = Y; then P = R, or P = Zp when a
-// preconditioned residual Zp is given.  Partials of r'r (only when x0 is not
-// given; otherwise the residual pass produced them), of y'y, and (part_pp
-// not null) of p'p over the tiles.
+// preconditioned residual Zp is given.  Partials of r'r (when x0 is not
+// given or rows are decoupled; otherwise the residual pass produced them),
+// of y'y, and (part_pp not null) of p'p over the tiles.
+// Decoupled rows (sdec not null, s_v = 0: no hyperedge of positive weight,
+// so row v of A is zero and M_vv = a, reading R2): their equation is solved
+// here, F_v = Y_v / a, and R_v = P_v = 0 keeps them out of the iteration.
 template <class T, int GL, int V>
 __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t n_tiles, const int32_t* __restrict__ tile_r0,
                                                     const int32_t* __restrict__ tile_r1, int n_slots,
@@ -77,7 +80,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t n_tiles, const int32
                                                     T* __restrict__ F, int64_t ldf, T* __restrict__ R,
                                                     T* __restrict__ P, int64_t ld, double* __restrict__ part_rr,
                                                     double* __restrict__ part_yy, int k, int x0_given,
-                                                    const T* __restrict__ Zp, double* __restrict__ part_pp) {
+                                                    const T* __restrict__ Zp, double* __restrict__ part_pp,
+                                                    const T* __restrict__ sdec, const int32_t* __restrict__ tile_seg,
+                                                    const double* __restrict__ a_seg) {
   constexpr int GPB = kBlock / GL, W = GL * V;
   __shared__ double lds[4 * W];
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
@@ -87,9 +92,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t n_tiles, const int32
 #pragma unroll
   for (int i = 0; i < V; ++i) rr[i] = yy[i] = pp[i] = 0.0;
   if (col < k) {
+    const double inv_a = sdec ? 1.0 / a_seg[tile_seg[t]] : 0.0;
     for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
       T y[V], rv[V];
       load_row<V>(Y + int64_t(r) * ldy + col, y);
+      if (sdec && sdec[r] == T(0)) {
+        T f[V], z[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          f[i] = T(double(y[i]) * inv_a);
+          z[i] = T(0);
+          yy[i] += double(y[i]) * double(y[i]);
+        }
+        store_row<V>(F + int64_t(r) * ldf + col, f);
+        store_row<V>(R + int64_t(r) * ld + col, z);
+        store_row<V>(P + int64_t(r) * ld + col, z);
+        continue;
+      }
       if (!x0_given) {
         T z[V];
 #pragma unroll
@@ -122,14 +141,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t n_tiles, const int32
   double srr = block_colsum<GL, V>(rr, lds);
   double spp = part_pp ? block_colsum<GL, V>(pp, lds) : 0.0;
   const int c = blockIdx.y * W + threadIdx.x;
+  // with decoupled rows the r'r of the residual pass (x0 given) included
+  // their old residual: r'r is taken here over the rows that iterate
+  const bool own_rr = !x0_given || sdec;
   if (threadIdx.x < W && c < k) {
     part_yy[int64_t(t) * k + c] = syy;
-    if (!x0_given) part_rr[int64_t(t) * k + c] = srr;
+    if (own_rr) part_rr[int64_t(t) * k + c] = srr;
     if (part_pp) part_pp[int64_t(t) * k + c] = spp;
   }
   if (blockIdx.y == 0) {
+    // the tile sums above cover every row, hub rows included
     zero_long_slots(part_yy, n_tiles, n_slots, n_long, k);
-    if (!x0_given) zero_long_slots(part_rr, n_tiles, n_slots, n_long, k);
+    if (own_rr) zero_long_slots(part_rr, n_tiles, n_slots, n_long, k);
   }
 }
 
@@ -181,12 +204,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
 // every other column keeps P.
 // part_pp (nullable): tile partials of p'p of the new P (the vertex half of
 // the next p'Mp).
+// sdec (nullable): rows with s_v = 0 are decoupled (solved at the start) and
+// skipped.
 template <class T, int GL, int V>
 __global__ __launch_bounds__(kBlock) void k_cg_direction(
     const int32_t* __restrict__ tile_r0, const int32_t* __restrict__ tile_r1,
     const int32_t* __restrict__ tile_seg, const T* __restrict__ R, T* __restrict__ P, int64_t ld,
     const double* __restrict__ beta, const int32_t* __restrict__ state, int k, Gate gate,
-    double* __restrict__ part_pp, int restart_only) {
+    double* __restrict__ part_pp, int restart_only, const T* __restrict__ sdec) {
   if (gate.skip()) return;
   constexpr int GPB = kBlock / GL, W = GL * V;
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
@@ -206,6 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(
       keep[i] = restart_only ? sc != kRestart : sc == kClaimed;
     }
     for (int r = tile_r0[t] + grp; r < tile_r1[t]; r += GPB) {
+      if (sdec && sdec[r] == T(0)) continue;
       T rv[V], p[V];
       load_row<V>(R + int64_t(r) * ld + col, rv);
       load_row<V>(P + int64_t(r) * ld + col, p);
@@ -599,6 +625,14 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   // with Q kept in registers (no Q round trip, no separate update pass).
   const bool fused = !has_prec;
   const int N = h->N, E = h->E, G = h->G;
+  // Decoupled rows (s_v = 0) are solved at the start and skipped by the
+  // iteration's row streams (fused step only; the preconditioned path keeps
+  // every row).
+  const T* sdec = nullptr;
+  if (fused) {
+    if constexpr (sizeof(T) == 4) sdec = h->s32;
+    else sdec = h->s64;
+  }
   const int64_t ld = k;  // internal vectors
   const int nsl = n_slots(h);
   // ---------------------------------------------------------- workspace
@@ -712,7 +746,8 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     dim3 grid(h->n_tiles, cs.slabs);
     launch(h, -1, k_cg_init<T, GL, V>, grid, dim3(kBlock), 0, s, h->n_tiles, h->tile_r0,
                        h->tile_r1, nsl, h->n_long, Y, ldy, F, ldf, b.R, b.P, ld, b.part, b.part2, k,
-                       x0 ? 1 : 0, has_prec ? static_cast<const T*>(b.Zp) : nullptr, b.pp);
+                       x0 ? 1 : 0, has_prec ? static_cast<const T*>(b.Zp) : nullptr, b.pp, sdec, h->tile_seg,
+                       a_seg);
     HGL_HIP(hipGetLastError());
     return HGL_OK;
   });
@@ -783,7 +818,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       dim3 grid(h->n_tiles, cs.slabs);
       launch(h, -1, k_cg_direction<T, GL, V>, grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
                          h->tile_seg, dir_src, b.P, ld, b.st.beta, static_cast<const int32_t*>(b.st.state), k,
-                         g_now, b.pp, 0);
+                         g_now, b.pp, 0, sdec);
       HGL_HIP(hipGetLastError());
       return HGL_OK;
     });
@@ -813,7 +848,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       dim3 grid(h->n_tiles, cs.slabs);
       launch(h, -1, k_cg_direction<T, GL, V>, grid, dim3(kBlock), 0, s, h->tile_r0, h->tile_r1,
                          h->tile_seg, dir_src, b.P, ld, b.st.beta, static_cast<const int32_t*>(b.st.state), k,
-                         Gate{}, b.pp, 1);
+                         Gate{}, b.pp, 1, sdec);
       HGL_HIP(hipGetLastError());
       return HGL_OK;
     });

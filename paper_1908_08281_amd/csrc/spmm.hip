@@ -188,6 +188,8 @@ struct VertexArgs {
 // MODE 2: Out = Y - (a X - b s H Z), partial <Out, Out>, all in TZ (FP64).
 // MODE 3 (CG step with X = P): Q = a P - b s H Z stays in registers;
 // F += alpha P, R -= alpha Q (u.F, u.R), partial <R, R> of the new R.
+// Decoupled rows (s_v = 0, solved at the start of the solve) are skipped:
+// no loads, no stores.
 // At least 5 waves per SIMD: the fused step (MODE 3) with its row prefetch
 // then fits in 96 VGPRs without spilling; the other modes use fewer anyway.
 template <class T, class TZ, int GL, int V, int MODE>
@@ -220,6 +222,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_spmm_vertex(
     // keep their registers (and so their occupancy) and load a row when they
     // reach it.  MODE 0 may have no X (a = 0).
     constexpr bool kAhead = MODE == 3;
+    __shared__ uint8_t s_live[kTileRows];  // MODE 3: the row iterates (s_v != 0, not a hub row)
     T x[V] = {}, fv[V] = {}, rv[V] = {};
     auto fetch = [&](int r, T (&xx)[V], T (&ff)[V], T (&rr)[V]) {
       if (MODE != 0 || X) {
@@ -233,14 +236,30 @@ __global__ __launch_bounds__(kBlock, 5) void k_spmm_vertex(
         load_row<V>(u.R + int64_t(r) * u.ldr + col, rr);
       }
     };
-    if (kAhead && r0 + grp < r1 && colok) fetch(r0 + grp, x, fv, rv);
+    int rcur = r0 + grp;
+    if (kAhead && rcur < r1 && colok) fetch(rcur, x, fv, rv);
     const int nr = r1 - r0;
     for (int i = threadIdx.x; i <= nr; i += kBlock) s_ptr[i] = va.vtx_ptr[r0 + i];
+    TZ sv_own = TZ(0);
+    if (MODE == 3 && threadIdx.x < nr) sv_own = s[r0 + threadIdx.x];
     __syncthreads();
+    if (MODE == 3 && threadIdx.x < nr)
+      s_live[threadIdx.x] = sv_own != TZ(0) && s_ptr[threadIdx.x + 1] - s_ptr[threadIdx.x] <= kLongRow;
     const int base = s_ptr[0];
     const int staged = min(s_ptr[nr] - base, kStageIdx);
     for (int i = threadIdx.x; i < staged; i += kBlock) s_idx[i] = va.vtx_edge[base + i];
     __syncthreads();
+    // the group's next row to process at or after r (MODE 3: rows that iterate)
+    auto next_row = [&](int r) {
+      if constexpr (MODE == 3)
+        while (r < r1 && !s_live[r - r0]) r += GPB;
+      return r;
+    };
+    if constexpr (MODE == 3) {
+      const int first = next_row(rcur);
+      if (first != rcur && first < r1 && colok) fetch(first, x, fv, rv);  // the prefetched row does not iterate
+      rcur = first;
+    }
     double dot[V];
     T al[V];
 #pragma unroll
@@ -248,11 +267,12 @@ __global__ __launch_bounds__(kBlock, 5) void k_spmm_vertex(
       dot[i] = 0.0;
       if constexpr (MODE == 3) al[i] = colok ? T(u.alpha[int64_t(g) * k + col + i]) : T(0);
     }
-    for (int r = r0 + grp; r < r1 && colok; r += GPB) {
+    for (int r = rcur; r < r1 && colok;) {
       const int eb = s_ptr[r - r0], ee = s_ptr[r - r0 + 1];
+      const int rnext = next_row(r + GPB);
       T xn[V] = {}, fn[V] = {}, rn[V] = {};
       if constexpr (kAhead) {
-        if (r + GPB < r1) fetch(r + GPB, xn, fn, rn);
+        if (rnext < r1) fetch(rnext, xn, fn, rn);
       } else {
         fetch(r, x, fv, rv);
       }
@@ -303,6 +323,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_spmm_vertex(
           rv[i] = rn[i];
         }
       }
+      r = rnext;
     }
     if constexpr (MODE != 0) {
       double tot = block_colsum<GL, V>(dot, lds_d);
@@ -386,6 +407,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm_vertex_finish(
     Out[int64_t(r) * ldo + c] = T(ri);
     d = double(ri) * double(ri);
   } else if constexpr (MODE == 3) {
+    if (sr == TZ(0)) {  // decoupled (every hyperedge of weight 0): solved at the start
+      part[int64_t(va.n_tiles + slot) * k + c] = 0.0;
+      return;
+    }
     const T o = T(a * x - bb * sr * sum);
     const T xv = X[int64_t(r) * ldx + c];
     const T al = T(u.alpha[int64_t(g) * k + c]);

@@ -6,6 +6,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 import bench
@@ -19,7 +20,8 @@ def test_gather_bytes_structure():
     b8 = bench.gather_bytes(N, E, nnz, k, 8, covered=900, hubs=hubs)
     # the fused step streams F and R in and out and P in, where the apply
     # streams P in and Q out: three more row streams of the rows it finishes
-    assert b4["vertex_step"] - b4["vertex_gather"] == 4 * k * 3 * (N - hubs)
+    # (and it reads s of the hub rows too, to find the rows that iterate)
+    assert b4["vertex_step"] - b4["vertex_gather"] == 4 * k * 3 * (N - hubs) + 4 * hubs
     # the value bytes scale with the element size, the index bytes do not
     for key in ("vertex_gather", "vertex_step", "edge_gather", "cg_iteration"):
         idx = 2 * b4[key] - b8[key]
@@ -27,6 +29,21 @@ def test_gather_bytes_structure():
     # each covered vertex adds its row of P and its entry of the covered list
     full = bench.gather_bytes(N, E, nnz, k, 4, covered=N, hubs=hubs)
     assert full["edge_gather"] - b4["edge_gather"] == (4 * k + 4) * (N - 900)
+    # decoupled rows drop out of the fused step's and the direction's row
+    # streams (five and three per row), not out of the iteration's definition
+    d = bench.gather_bytes(N, E, nnz, k, 4, covered=900, hubs=hubs, decoupled=100)
+    assert b4["vertex_step"] - d["vertex_step"] == 4 * k * 5 * 100
+    assert b4["direction"] - d["direction"] == 4 * k * 3 * 100
+    assert d["cg_iteration"] == b4["cg_iteration"]
+    assert b4["cg_iteration_as_run"] - d["cg_iteration_as_run"] == 4 * k * 6 * 100
+
+
+def test_decoupled_rows_count():
+    import synth
+    ep, ev = synth.explicit_hyperedges([[0, 1], [1, 2], [4, 5]])
+    p = synth.Problem(7, 3, ep, ev, np.array([0.5, 0.5, 0.0]), 1.0, np.zeros((7, 1)))
+    # vertex 3 and 6 are isolated, 4 and 5 only in a hyperedge of weight 0
+    assert bench.decoupled_rows(p) == 4
 
 
 def _write(path, rows, fields):

@@ -74,6 +74,53 @@ def test_zero_column_x0_and_limits():
     assert np.allclose(rel3[0], ro, rtol=1e-4, atol=1e-12)
 
 
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+def test_decoupled_rows_solved_at_the_start(mode):
+    """Rows with s_v = 0 (isolated vertices, and vertices whose every
+    hyperedge has weight 0) are decoupled: M_vv = 1 + 1/lambda and row v of
+    A is zero (reading R2).  The fused solver sets F_v = Y_v / (1 + 1/lambda)
+    at the start and leaves them out of the iteration.  The whole solution
+    still matches dense Cholesky, those rows hold Y_v lambda/(1+lambda) to
+    rounding, a start x0 with garbage on them is corrected, and the reported
+    relres of an unconverged solve is still the true one."""
+    import torch
+    dev = device()
+    p = synth.multi_rhs(N=2500, E=2000, k=9, smax=80)
+    w = p.w.copy()
+    w[synth.rng_for(5).choice(p.E, size=p.E // 4, replace=False)] = 0.0  # zero-weight hyperedges
+    p.w = w
+    H = lap.incidence_dense(p.N, p.E, p.edge_ptr, p.edge_vtx)
+    dv = H @ w
+    dec = dv == 0
+    member = H.sum(axis=1) > 0
+    assert dec.sum() > 100 and (dec & member).sum() > 10  # both kinds present
+    M = lap.system_matrix(H, w, p.lam)
+    Fo = solve.solve_dense(M, p.Y)
+    h = build(p, dev)
+    dt = torch.float32 if mode == "f32" else torch.float64
+    tol = 1e-6 / (1 + 1 / p.lam) if mode == "f32" else 1e-10
+    bar = 1e-6 if mode == "f32" else 2e-10
+    Y = torch.from_numpy(p.Y).to(dev, dt)
+    say("decoupled", mode)
+    F, it, rel, st = hgl().cg_solve(h, p.lam, Y, mode=mode, tol=tol, max_iter=500)
+    assert st == 0 and np.all(rel <= tol)
+    Fn = F.cpu().double().numpy()
+    assert colrelerr(Fn, Fo).max() <= bar
+    exact = p.Y[dec] * (p.lam / (1 + p.lam))
+    eps = np.finfo(np.float32 if mode == "f32" else np.float64).eps
+    assert np.all(np.abs(Fn[dec] - exact) <= eps * np.abs(exact))
+    # a start with garbage everywhere, decoupled rows included
+    x0 = torch.from_numpy(synth.rng_for(6).standard_normal(p.Y.shape)).to(dev, dt)
+    F2, it2, rel2, st2 = hgl().cg_solve(h, p.lam, Y, mode=mode, tol=tol, max_iter=500, x0=x0)
+    assert st2 == 0 and colrelerr(F2.cpu().double().numpy(), Fo).max() <= bar
+    assert np.all(np.abs(F2.cpu().double().numpy()[dec] - exact) <= eps * np.abs(exact))
+    # one iteration from that start: the reported relres is the true one
+    F3, _, rel3, st3 = hgl().cg_solve(h, p.lam, Y, mode=mode, tol=1e-12, max_iter=1, x0=x0)
+    assert st3 == 1
+    ro = np.linalg.norm(p.Y - M @ F3.cpu().double().numpy(), axis=0) / np.linalg.norm(p.Y, axis=0)
+    assert np.allclose(rel3[0], ro, rtol=1e-6, atol=1e-14)
+
+
 @pytest.mark.parametrize("max_iter", [1, 2, 3, 4, 5])
 def test_iteration_limits_of_every_parity(max_iter):
     """Regression: the FP64 flag words must stay 8-byte aligned for any max_iter."""
