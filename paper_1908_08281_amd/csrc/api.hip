@@ -313,63 +313,38 @@ __global__ void k_degree_count(int32_t E, const int32_t* __restrict__ edge_ptr,
 }
 
 // Every incidence (v, e) goes to a free place of vertex v's segment
-// [vtx_ptr[v], vtx_ptr[v+1]) of tmp; the order inside a segment is whatever
-// the atomics give (the ranking pass below fixes it).
+// [vtx_ptr[v], vtx_ptr[v+1]) of tmp (row[] records v there); the order
+// inside a segment is whatever the atomics give (the ranking pass below
+// fixes it).
 __global__ void k_scatter_edges(int32_t E, const int32_t* __restrict__ edge_ptr,
                                 const int32_t* __restrict__ edge_vtx, const int32_t* __restrict__ vtx_ptr,
-                                int32_t* __restrict__ cursor, int32_t* __restrict__ tmp) {
+                                int32_t* __restrict__ cursor, int32_t* __restrict__ tmp, int32_t* __restrict__ row) {
   const int e = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
   const int lane = threadIdx.x % 16;
   if (e >= E) return;
   for (int j = edge_ptr[e] + lane; j < edge_ptr[e + 1]; j += 16) {
     const int32_t v = edge_vtx[j];
-    tmp[vtx_ptr[v] + atomicAdd(&cursor[v], 1)] = e;
+    const int32_t pos = vtx_ptr[v] + atomicAdd(&cursor[v], 1);
+    tmp[pos] = e;
+    row[pos] = v;
   }
 }
 
 // The hyperedges of a vertex are distinct, so an entry's place in the sorted
-// segment is the number of smaller entries in it.  Rows of at most kLongRow
-// hyperedges: one wave per vertex, one entry per lane, the segment read
-// through lane exchanges.
-__global__ __launch_bounds__(256) void k_rank_short(int32_t N, const int32_t* __restrict__ vtx_ptr,
-                                                    const int32_t* __restrict__ tmp,
-                                                    int32_t* __restrict__ vtx_edge) {
-  const int v = blockIdx.x * 4 + threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  if (v >= N) return;  // uniform per wave
-  const int b = vtx_ptr[v], d = vtx_ptr[v + 1] - b;
-  if (d > kLongRow) return;  // ranked by k_rank_long
-  const int32_t x = lane < d ? tmp[b + lane] : INT_MAX;
-  int r = 0;
-  for (int j = 0; j < d; ++j) r += __shfl(x, j, kWave) < x ? 1 : 0;
-  if (lane < d) vtx_edge[b + r] = x;
-}
-
-// Longer rows: one workgroup per chunk of the row (kChunk entries, one per
-// thread), counting against the whole segment staged through LDS.
-constexpr int kRankStage = 1024;
-__global__ __launch_bounds__(kChunk) void k_rank_long(const int32_t* __restrict__ vtx_ptr,
-                                                      const int32_t* __restrict__ long_row,
-                                                      const int32_t* __restrict__ chunk_slot,
-                                                      const int32_t* __restrict__ chunk_begin,
-                                                      const int32_t* __restrict__ chunk_end,
-                                                      const int32_t* __restrict__ tmp,
-                                                      int32_t* __restrict__ vtx_edge) {
-  __shared__ int32_t seg[kRankStage];
-  const int c = blockIdx.x;
-  const int v = long_row[chunk_slot[c]];
-  const int b = vtx_ptr[v], en = vtx_ptr[v + 1];
-  const int i = chunk_begin[c] + threadIdx.x;
-  const bool mine = i < chunk_end[c];
-  const int32_t x = mine ? tmp[i] : INT_MAX;
-  int r = 0;
-  for (int t0 = b; t0 < en; t0 += kRankStage) {
-    const int m = min(kRankStage, en - t0);
-    __syncthreads();
-    for (int j = threadIdx.x; j < m; j += kChunk) seg[j] = tmp[t0 + j];
-    __syncthreads();
-    for (int j = 0; j < m; ++j) r += seg[j] < x ? 1 : 0;
-  }
-  if (mine) vtx_edge[b + r] = x;
+// segment is the number of smaller entries in it: one thread per entry
+// counts over its row's segment (the lanes of a wave mostly share a row, so
+// their reads of the segment coincide).
+__global__ __launch_bounds__(256) void k_rank(int64_t nnz, const int32_t* __restrict__ vtx_ptr,
+                                              const int32_t* __restrict__ tmp, const int32_t* __restrict__ row,
+                                              int32_t* __restrict__ vtx_edge) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nnz) return;
+  const int32_t v = row[i];
+  const int32_t b = vtx_ptr[v], en = vtx_ptr[v + 1];
+  const int32_t x = tmp[i];
+  int32_t r = 0;
+  for (int32_t j = b; j < en; ++j) r += tmp[j] < x ? 1 : 0;
+  vtx_edge[b + r] = x;
 }
 
 // dv[v] = sum of w_e over the hyperedges of v (the vertex degree of eq. 1),
@@ -410,33 +385,75 @@ __global__ void k_edge_scales(int32_t E, const int32_t* __restrict__ edge_ptr,
   c32[e] = float(c);
 }
 
-__global__ void k_long_flags(int32_t N, const int32_t* __restrict__ vtx_ptr,
-                             int32_t* __restrict__ is_long, int32_t* __restrict__ nch) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= N) return;
-  int d = vtx_ptr[v + 1] - vtx_ptr[v];
-  bool L = d > kLongRow;
-  is_long[v] = L ? 1 : 0;
-  nch[v] = L ? (d + kChunk - 1) / kChunk : 0;
+// Hub rows (more than kLongRow hyperedges) are split into chunks of at most
+// kChunk.  A row of at least kBucketRow hyperedges is first cut where its
+// (increasing) hyperedge ids cross into the next eighth of [0, E): every
+// chunk then reads Z rows of one eighth only, and the chunk's workgroup is
+// placed on the matching XCD (chunk_order), whose L2 so serves one eighth of
+// Z.  Eighth x of [0, E) starts at ceil(x E / 8).
+__device__ __forceinline__ int32_t eighth_start(int x, int32_t E) {
+  return int32_t((int64_t(x) * E + kXcd - 1) / kXcd);
 }
 
-__global__ void k_long_fill(int32_t N, const int32_t* __restrict__ vtx_ptr,
-                            const int32_t* __restrict__ is_long, const int32_t* __restrict__ slot_of,
-                            const int32_t* __restrict__ chunk_of, int32_t* __restrict__ long_row,
-                            int32_t* __restrict__ long_chunk0, int32_t* __restrict__ chunk_slot,
-                            int32_t* __restrict__ chunk_begin, int32_t* __restrict__ chunk_end) {
+// First position in [b, en) whose hyperedge id is >= e (ids increase).
+__device__ __forceinline__ int32_t lower_pos(const int32_t* __restrict__ ids, int32_t b, int32_t en, int32_t e) {
+  while (b < en) {
+    const int32_t m = b + (en - b) / 2;
+    if (ids[m] < e) b = m + 1;
+    else en = m;
+  }
+  return b;
+}
+
+__global__ void k_long_flags(int32_t N, int32_t E, const int32_t* __restrict__ vtx_ptr,
+                             const int32_t* __restrict__ vtx_edge, int32_t* __restrict__ is_long,
+                             int32_t* __restrict__ nch) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int32_t b = vtx_ptr[v], en = vtx_ptr[v + 1], d = en - b;
+  const bool L = d > kLongRow;
+  is_long[v] = L ? 1 : 0;
+  int n = 0;
+  if (L && d >= kBucketRow) {
+    int32_t p0 = b;
+    for (int x = 0; x < kXcd; ++x) {
+      const int32_t p1 = x + 1 < kXcd ? lower_pos(vtx_edge, p0, en, eighth_start(x + 1, E)) : en;
+      n += (p1 - p0 + kChunk - 1) / kChunk;
+      p0 = p1;
+    }
+  } else if (L) {
+    n = (d + kChunk - 1) / kChunk;
+  }
+  nch[v] = n;
+}
+
+// chunk_eighth[c]: the eighth of [0, E) whose Z rows chunk c reads, or -1
+// (a row below kBucketRow: any XCD).
+__global__ void k_long_fill(int32_t N, int32_t E, const int32_t* __restrict__ vtx_ptr,
+                            const int32_t* __restrict__ vtx_edge, const int32_t* __restrict__ is_long,
+                            const int32_t* __restrict__ slot_of, const int32_t* __restrict__ chunk_of,
+                            int32_t* __restrict__ long_row, int32_t* __restrict__ long_chunk0,
+                            int32_t* __restrict__ chunk_slot, int32_t* __restrict__ chunk_begin,
+                            int32_t* __restrict__ chunk_end, int32_t* __restrict__ chunk_eighth) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N || !is_long[v]) return;
   int slot = slot_of[v];
-  int c0 = chunk_of[v];
+  int c = chunk_of[v];
   long_row[slot] = v;
-  long_chunk0[slot] = c0;
-  int b = vtx_ptr[v], en = vtx_ptr[v + 1];
-  int c = c0;
-  for (int j = b; j < en; j += kChunk, ++c) {
-    chunk_slot[c] = slot;
-    chunk_begin[c] = j;
-    chunk_end[c] = min(j + kChunk, en);
+  long_chunk0[slot] = c;
+  const int32_t b = vtx_ptr[v], en = vtx_ptr[v + 1];
+  const bool bucketed = en - b >= kBucketRow;
+  int32_t p0 = b;
+  for (int x = 0; x < (bucketed ? kXcd : 1); ++x) {
+    const int32_t p1 =
+        bucketed && x + 1 < kXcd ? lower_pos(vtx_edge, p0, en, eighth_start(x + 1, E)) : en;
+    for (int32_t j = p0; j < p1; j += kChunk, ++c) {
+      chunk_slot[c] = slot;
+      chunk_begin[c] = j;
+      chunk_end[c] = min(j + kChunk, p1);
+      chunk_eighth[c] = bucketed ? x : -1;
+    }
+    p0 = p1;
   }
 }
 
@@ -482,7 +499,8 @@ static void free_handle(hgl_handle* h) {
   void* ptrs[] = {h->edge_ptr, h->edge_vtx, h->vtx_ptr, h->vtx_edge, h->w, h->dv, h->s64, h->c64,
                   h->s32, h->c32, h->tile_r0, h->tile_r1, h->tile_seg, h->long_row,
                   h->chunk_slot, h->chunk_begin, h->chunk_end, h->long_chunk0,
-                  h->seg_slots, h->long_seg, h->long_edge, h->etile_e0, h->etile_e1, h->seg_eslots};
+                  h->seg_slots, h->long_seg, h->long_edge, h->etile_e0, h->etile_e1, h->seg_eslots,
+                  h->chunk_order};
   for (void* p : ptrs) h->mem.release(p);
   DevBuf* bufs[] = {&h->ws_z, &h->ws_z64, &h->ws_chunk, &h->ws_part, &h->ws_part2,
                     &h->ws_vec, &h->ws_state, &h->ws_misc};
@@ -641,18 +659,32 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
 
   // ---- vertex-major transpose: degree counts -> offsets (scan) -> each
   // incidence scattered into its vertex's segment -> each segment put in
-  // increasing hyperedge order by ranking (hub rows by chunks)
-  int32_t* deg = nullptr;    // [N+1] degree, then the scatter cursor
-  int32_t* etmp = nullptr;   // [nnz] scattered hyperedge ids
-  B_TRY(tmp.get(&deg, size_t(N) + 1));
-  B_TRY(tmp.get(&etmp, size_t(std::max<int64_t>(nnz, 1))));
-  B_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (size_t(N) + 1), s));
-  if (E > 0)
-    hipLaunchKernelGGL(k_degree_count, dim3(blocks_for(E, 16)), dim3(256), 0, s, E, h->edge_ptr, h->edge_vtx, deg);
-  B_HIP(hipGetLastError());
-  B_TRY(scan_exclusive(tmp, deg, h->vtx_ptr, int64_t(N) + 1, s));
+  // increasing hyperedge order by ranking
+  std::vector<int32_t> chunk_eighth_host;
+  {
+    int32_t* deg = nullptr;    // [N+1] degree, then the scatter cursor
+    int32_t* etmp = nullptr;   // [nnz] scattered hyperedge ids
+    int32_t* erow = nullptr;   // [nnz] their vertex
+    B_TRY(tmp.get(&deg, size_t(N) + 1));
+    B_TRY(tmp.get(&etmp, size_t(std::max<int64_t>(nnz, 1))));
+    B_TRY(tmp.get(&erow, size_t(std::max<int64_t>(nnz, 1))));
+    B_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (size_t(N) + 1), s));
+    if (E > 0)
+      hipLaunchKernelGGL(k_degree_count, dim3(blocks_for(E, 16)), dim3(256), 0, s, E, h->edge_ptr, h->edge_vtx,
+                         deg);
+    B_HIP(hipGetLastError());
+    B_TRY(scan_exclusive(tmp, deg, h->vtx_ptr, int64_t(N) + 1, s));
+    if (nnz > 0) {
+      B_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (size_t(N) + 1), s));
+      hipLaunchKernelGGL(k_scatter_edges, dim3(blocks_for(E, 16)), dim3(256), 0, s, E, h->edge_ptr, h->edge_vtx,
+                         h->vtx_ptr, deg, etmp, erow);
+      hipLaunchKernelGGL(k_rank, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, nnz, h->vtx_ptr,
+                         static_cast<const int32_t*>(etmp), static_cast<const int32_t*>(erow), h->vtx_edge);
+      B_HIP(hipGetLastError());
+    }
+  }
 
-  // ---- long vertex rows -> chunks (from the offsets alone)
+  // ---- hub rows -> chunks (the large ones cut by eighth of [0, E))
   {
     int32_t* tmpi = nullptr;
     B_TRY(tmp.get(&tmpi, 4 * (size_t(N) + 1)));
@@ -661,7 +693,7 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
     int32_t* slot_of = tmpi + 2 * (N + 1);
     int32_t* chunk_of = tmpi + 3 * (N + 1);
     B_HIP(hipMemsetAsync(tmpi, 0, sizeof(int32_t) * 4 * (size_t(N) + 1), s));
-    hipLaunchKernelGGL(k_long_flags, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, h->vtx_ptr,
+    hipLaunchKernelGGL(k_long_flags, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, E, h->vtx_ptr, h->vtx_edge,
                        is_long, nch);
     B_HIP(hipGetLastError());
     B_TRY(scan_exclusive(tmp, is_long, slot_of, int64_t(N) + 1, s));
@@ -671,14 +703,16 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
     B_HIP(hipStreamSynchronize(s));
     h->n_long = h->pinned_i[0];
     h->n_chunks = h->pinned_i[1];
+    int32_t* chunk_eighth = nullptr;
+    B_TRY(tmp.get(&chunk_eighth, size_t(h->n_chunks) + 1));
     B_TRY(dev_alloc(h, &h->long_row, h->n_long));
     B_TRY(dev_alloc(h, &h->long_chunk0, h->n_long + 1));
     B_TRY(dev_alloc(h, &h->chunk_slot, h->n_chunks));
     B_TRY(dev_alloc(h, &h->chunk_begin, h->n_chunks));
     B_TRY(dev_alloc(h, &h->chunk_end, h->n_chunks));
-    hipLaunchKernelGGL(k_long_fill, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, h->vtx_ptr,
-                       is_long, slot_of, chunk_of, h->long_row, h->long_chunk0, h->chunk_slot,
-                       h->chunk_begin, h->chunk_end);
+    hipLaunchKernelGGL(k_long_fill, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, E, h->vtx_ptr, h->vtx_edge,
+                       is_long, slot_of, chunk_of, h->long_row, h->long_chunk0, h->chunk_slot, h->chunk_begin,
+                       h->chunk_end, chunk_eighth);
     B_HIP(hipGetLastError());
     h->pinned_i[2] = h->n_chunks;
     B_HIP(hipMemcpyAsync(h->long_chunk0 + h->n_long, h->pinned_i + 2, sizeof(int32_t),
@@ -686,8 +720,12 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
     // per-graph slot ranges: long rows are listed in increasing vertex id, so
     // each graph's long rows are contiguous
     std::vector<int32_t> lr(h->n_long);
+    chunk_eighth_host.assign(h->n_chunks, -1);
     if (h->n_long)
       B_HIP(hipMemcpyAsync(lr.data(), h->long_row, 4 * size_t(h->n_long), hipMemcpyDeviceToHost, s));
+    if (h->n_chunks)
+      B_HIP(hipMemcpyAsync(chunk_eighth_host.data(), chunk_eighth, 4 * size_t(h->n_chunks),
+                           hipMemcpyDeviceToHost, s));
     B_HIP(hipStreamSynchronize(s));
     h->seg_slots_host.assign(4 * G, 0);
     int t = 0, l = 0;
@@ -707,20 +745,6 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
     if (h->n_long)
       B_HIP(hipMemcpyAsync(h->long_seg, lseg.data(), 4 * size_t(h->n_long), hipMemcpyHostToDevice, s));
     B_HIP(hipStreamSynchronize(s));
-  }
-
-  // ---- scatter and rank
-  if (nnz > 0) {
-    B_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (size_t(N) + 1), s));
-    hipLaunchKernelGGL(k_scatter_edges, dim3(blocks_for(E, 16)), dim3(256), 0, s, E, h->edge_ptr, h->edge_vtx,
-                       h->vtx_ptr, deg, etmp);
-    hipLaunchKernelGGL(k_rank_short, dim3(blocks_for(N, 4)), dim3(256), 0, s, N, h->vtx_ptr,
-                       static_cast<const int32_t*>(etmp), h->vtx_edge);
-    if (h->n_chunks > 0)
-      hipLaunchKernelGGL(k_rank_long, dim3(h->n_chunks), dim3(kChunk), 0, s, h->vtx_ptr, h->long_row,
-                         h->chunk_slot, h->chunk_begin, h->chunk_end, static_cast<const int32_t*>(etmp),
-                         h->vtx_edge);
-    B_HIP(hipGetLastError());
   }
   B_TRY(compute_scales(h, s));
 
@@ -747,6 +771,44 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
     B_HIP(hipMemcpyAsync(h->tile_seg, sg.data(), 4 * sg.size(), hipMemcpyHostToDevice, s));
     B_HIP(hipMemcpyAsync(h->seg_slots, h->seg_slots_host.data(), 16 * size_t(G), hipMemcpyHostToDevice, s));
     B_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+  }
+
+  // ---- dispatch order of the chunk workgroups: workgroup n_tiles + j runs
+  // on XCD (n_tiles + j) mod kXcd; a chunk that reads one eighth of Z goes to
+  // that eighth's XCD while such chunks remain, the rest fill in where their
+  // own list is empty.  Padding to a multiple of kXcd keeps the placement for
+  // every column slab of the grid.
+  {
+    std::vector<std::vector<int32_t>> lists(kXcd + 1);
+    for (int32_t c = 0; c < h->n_chunks; ++c) {
+      const int x = chunk_eighth_host[c];
+      lists[x >= 0 ? x : kXcd].push_back(c);
+    }
+    std::vector<size_t> at(kXcd + 1, 0);
+    std::vector<int32_t> order;
+    order.reserve(h->n_chunks + 2 * kXcd);
+    auto left = [&](int x) { return lists[x].size() - at[x]; };
+    int32_t placed = 0;
+    while (placed < h->n_chunks) {
+      const int xcd = int((int64_t(h->n_tiles) + int64_t(order.size())) % kXcd);
+      int from = -1;
+      if (left(xcd) > 0) {
+        from = xcd;
+      } else if (left(kXcd) > 0) {
+        from = kXcd;  // a chunk with no eighth of its own
+      } else {
+        for (int x = 0; x < kXcd; ++x)
+          if (left(x) > 0 && (from < 0 || left(x) > left(from))) from = x;
+      }
+      order.push_back(lists[from][at[from]++]);
+      ++placed;
+    }
+    while ((int64_t(h->n_tiles) + int64_t(order.size())) % kXcd != 0) order.push_back(-1);
+    h->n_dispatch = int32_t(order.size());
+    B_TRY(dev_alloc(h, &h->chunk_order, order.size()));
+    if (!order.empty())
+      B_HIP(hipMemcpyAsync(h->chunk_order, order.data(), 4 * order.size(), hipMemcpyHostToDevice, s));
+    B_HIP(hipStreamSynchronize(s));
   }
 
   // ---- long hyperedges (one workgroup each in the edge gather)

@@ -57,6 +57,8 @@ constexpr int kWave = 64;
 constexpr int kTileRows = 32;      // rows per tile of the row-streaming kernels
 constexpr int kLongRow = 32;       // vertex rows with more hyperedges are split
 constexpr int kChunk = 128;        // hyperedges per chunk of a split vertex row
+constexpr int kBucketRow = 256;    // hub rows with this many hyperedges are split by eighth of [0, E)
+constexpr int kXcd = 8;            // XCDs of the device; workgroup w runs on XCD w mod 8
 constexpr int kStageIdx = 2048;    // hyperedge ids of a tile staged in LDS
 constexpr int kGather = 8;         // gathered rows in flight per lane group
 constexpr int kLongEdge = 32;      // hyperedges with more members get a whole workgroup
@@ -128,6 +130,12 @@ struct hgl_handle {
   int32_t* chunk_begin = nullptr;    // [n_chunks] position in vtx_edge
   int32_t* chunk_end = nullptr;      // [n_chunks]
   int32_t* long_chunk0 = nullptr;    // [n_long+1] first chunk of each long row
+  // dispatch order of the chunk workgroups of a vertex gather: workgroup
+  // n_tiles + j takes chunk chunk_order[j] (-1: none), so that a chunk that
+  // reads one eighth of Z runs on that eighth's XCD; n_dispatch >= n_chunks
+  // makes n_tiles + n_dispatch a multiple of kXcd
+  int32_t n_dispatch = 0;
+  int32_t* chunk_order = nullptr;    // [n_dispatch]
 
   // hyperedges with more than kLongEdge members, increasing id (device)
   int32_t n_long_edge = 0;

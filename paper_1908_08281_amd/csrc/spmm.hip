@@ -181,6 +181,7 @@ struct VertexArgs {
   int32_t n_slots;
   const double* a_seg;
   const double* b_seg;
+  const int32_t* chunk_order;  // chunk of workgroup n_tiles + j (-1: none)
 };
 
 // MODE 0: Out = a X - b s H Z (X may be null when a = 0: Out = -b s H Z).
@@ -334,7 +335,10 @@ __global__ __launch_bounds__(kBlock, 5) void k_spmm_vertex(
   }
 
   // ------------------------------------------------ one chunk of a long row
-  const int ch = blockIdx.x - va.n_tiles;
+  // (workgroups are ordered so that a chunk reading one eighth of Z runs on
+  // the XCD whose L2 serves that eighth)
+  const int ch = va.chunk_order[blockIdx.x - va.n_tiles];
+  if (ch < 0) return;  // padding (uniform over the workgroup)
   const int slot = va.chunk_slot[ch];
   const int eb = va.chunk_begin[ch], ee = va.chunk_end[ch];
   TZ acc[V];
@@ -442,11 +446,12 @@ int launch_spmm_vertex(const hgl_handle* h, VMode mode, const T* X, int64_t ldx,
   }
   VertexArgs va{h->n_tiles,  h->tile_r0,     h->tile_r1,   h->tile_seg, h->vtx_ptr,
                 h->vtx_edge, h->chunk_slot,  h->chunk_begin, h->chunk_end, h->long_row,
-                h->long_seg, h->long_chunk0, n_slots(h),  a_seg,       b_seg};
+                h->long_seg, h->long_chunk0, n_slots(h),  a_seg,       b_seg,
+                h->chunk_order};
   const TZ* s;
   if constexpr (sizeof(TZ) == 8) s = h->s64; else s = h->s32;
   TZ* cp = chunk_buf ? chunk_buf : hm->ws_chunk.as<TZ>();
-  dim3 grid(h->n_tiles + h->n_chunks, cs.slabs);
+  dim3 grid(h->n_tiles + h->n_dispatch, cs.slabs);
   dim3 grid_fin(h->n_long, cs.slabs);
   if (mode == VMode::Resid && sizeof(TZ) != 8) {
     set_error("residual mode needs FP64 accumulation");
