@@ -404,6 +404,15 @@ int hgl_block_rsvd_invert(hgl_handle* h, double lambda, int32_t n_blocks,
  */
 int hgl_sketch_gaussian(int64_t rows, int32_t l, uint64_t seed, uint16_t* out_bf16, hipStream_t stream);
 
+/*
+ * The generator under hgl_sketch_gaussian (Algorithm 1 step 1 draws the
+ * Gaussian test matrix from it): Philox4x32-10 (Salmon et al., SC'11) on
+ * caller counters, for bit-exact checks of its integer words.  ctr, out:
+ * device uint32 arrays [n][4]; key = (key low 32 bits, key high 32 bits);
+ * out[i] = the four output words of counter ctr[i].  Asynchronous.
+ */
+int hgl_philox4x32_10(int64_t n, const uint32_t* ctr, uint64_t key, uint32_t* out, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Block inverse through Schur complements (paper, section 3, eqs. 12-14)
  * under nested tessellation, eq. 15 at the smallest submatrices.

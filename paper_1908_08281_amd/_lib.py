@@ -86,6 +86,7 @@ SIGNATURES = {
     "hgl_block_rsvd_invert": (C.c_int, [P, D, I32, I32P, C.POINTER(RsvdOpts), P, P, I64, P, I64, I32, P,
                                         I32P, DP, P]),
     "hgl_sketch_gaussian": (C.c_int, [I64, I32, C.c_uint64, P, P]),
+    "hgl_philox4x32_10": (C.c_int, [I64, P, C.c_uint64, P, P]),
     "hgl_block_schur_inverse": (C.c_int, [P, D, I32, I32P, I32, P, DP, P]),
     "hgl_block_schur_invert": (C.c_int, [P, D, I32, I32P, I32, D, I32, I32, P, I64, P, I64, I32, I32P, DP, P]),
     "hgl_block_schur_plan": (C.c_int, [I32, I32P, I32, I64P, I64P, I64P, I32P, I64P, I64P]),

@@ -917,6 +917,11 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
 
   int it = 0;
   int n_chunks = 0, n_checks = 0, n_resumed = 0;
+  // per-column results (relres [gk] FP64, then state and iteration counts
+  // [2 gk] int32) in pinned memory after the first 8 words, which hold the
+  // readback of the loop
+  double* res_d = h->pinned_d + 8;
+  bool results_read = false;
   bool all_done = false;
   double r_ref = -1.0;
   int it_ref = 0;
@@ -938,7 +943,13 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
     if (speculate) HGL_TRY(check(it));
     HGL_HIP(hipMemcpyAsync(h->pinned_i, wd.cnt(it - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HGL_HIP(hipMemcpyAsync(h->pinned_d, wd.rmax(it - 1), sizeof(double), hipMemcpyDeviceToHost, s));
-    if (speculate) HGL_HIP(hipMemcpyAsync(h->pinned_i + 1, wd.chk(it), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (speculate) {
+      HGL_HIP(hipMemcpyAsync(h->pinned_i + 1, wd.chk(it), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      // the per-column results too: when this check finishes every column,
+      // the solve ends on this one synchronisation
+      HGL_HIP(hipMemcpyAsync(res_d, b.st.relres, sizeof(double) * gk, hipMemcpyDeviceToHost, s));
+      HGL_HIP(hipMemcpyAsync(res_d + gk, b.st.state, sizeof(int32_t) * 2 * gk, hipMemcpyDeviceToHost, s));
+    }
     HGL_HIP(hipStreamSynchronize(s));
     const int iterating = h->pinned_i[0];
     if (iterating == 0 && !speculate) {  // every column claimed, finished or broken down
@@ -950,6 +961,7 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       checked_at = it;
       ++n_checks;
       all_done = h->pinned_i[1] == 0;
+      results_read = all_done && speculate;
       if (!all_done) {
         ++n_resumed;
         HGL_TRY(restart());  // P = R for the restarted columns only
@@ -976,10 +988,12 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
   h->last_cg[2] = n_checks;
   h->last_cg[3] = n_resumed;
   // ---------------------------------------------------------- results
-  double* pd = h->pinned_d;
-  HGL_HIP(hipMemcpyAsync(pd, b.st.relres, sizeof(double) * gk, hipMemcpyDeviceToHost, s));
-  HGL_HIP(hipMemcpyAsync(pd + gk, b.st.state, sizeof(int32_t) * 2 * gk, hipMemcpyDeviceToHost, s));
-  HGL_HIP(hipStreamSynchronize(s));
+  double* pd = res_d;
+  if (!results_read) {
+    HGL_HIP(hipMemcpyAsync(pd, b.st.relres, sizeof(double) * gk, hipMemcpyDeviceToHost, s));
+    HGL_HIP(hipMemcpyAsync(pd + gk, b.st.state, sizeof(int32_t) * 2 * gk, hipMemcpyDeviceToHost, s));
+    HGL_HIP(hipStreamSynchronize(s));
+  }
   const int32_t* state_h = reinterpret_cast<const int32_t*>(pd + gk);
   const int32_t* iters_h = state_h + gk;
   bool breakdown = false, unconverged = false;

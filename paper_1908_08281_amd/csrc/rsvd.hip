@@ -146,6 +146,17 @@ __global__ void k_philox_sketch(int64_t rows, int l, uint64_t seed, uint16_t* __
   if (2 * idx + 1 < total) out[2 * idx + 1] = f32_to_bf16_rne(float(z1));
 }
 
+// out[4i .. 4i+3] = Philox4x32-10 of counter ctr[4i .. 4i+3] under key.
+__global__ void k_philox_words(int64_t n, const uint32_t* __restrict__ ctr, uint64_t key,
+                               uint32_t* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c[4] = {ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
+  philox4x32_10(c, uint32_t(key), uint32_t(key >> 32));
+#pragma unroll
+  for (int j = 0; j < 4; ++j) out[4 * i + j] = c[j];
+}
+
 // ST_b[j][r] = Omega[o_b + r][j] for j < l, r < n_b; zero elsewhere.
 template <class TS>
 __global__ void k_sketch_to_st(BlockMeta bm, const uint16_t* __restrict__ omega, TS* __restrict__ ST,
@@ -1376,6 +1387,14 @@ extern "C" int hgl_sketch_gaussian(int64_t rows, int32_t l, uint64_t seed, uint1
   HGL_CHECK_ARG(rows >= 1 && l >= 1 && out_bf16 != nullptr, "bad sketch arguments");
   const int64_t pairs = (rows * l + 1) / 2;
   hipLaunchKernelGGL(k_philox_sketch, dim3(int((pairs + 255) / 256)), dim3(256), 0, s, rows, l, seed, out_bf16);
+  HGL_HIP(hipGetLastError());
+  return HGL_OK;
+}
+
+extern "C" int hgl_philox4x32_10(int64_t n, const uint32_t* ctr, uint64_t key, uint32_t* out, hipStream_t s) {
+  clear_error();
+  HGL_CHECK_ARG(n >= 1 && ctr != nullptr && out != nullptr, "need n >= 1 and ctr, out");
+  hipLaunchKernelGGL(k_philox_words, dim3(int((n + 255) / 256)), dim3(256), 0, s, n, ctr, key, out);
   HGL_HIP(hipGetLastError());
   return HGL_OK;
 }

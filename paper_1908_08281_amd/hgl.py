@@ -327,6 +327,19 @@ def _omega_ptr(h: Handle, omega, l: int):
     return _ptr(omega)
 
 
+def philox4x32_10(ctr: torch.Tensor, key: int) -> torch.Tensor:
+    """Raw Philox4x32-10 words of counters ctr [n, 4] (int32 tensor holding the uint32
+    bit patterns) under a 64-bit key; returns [n, 4] int32 bit patterns."""
+    _need(ctr, torch.int32, "ctr")
+    if ctr.dim() != 2 or ctr.shape[1] != 4 or not ctr.is_contiguous():
+        raise ValueError("ctr must be a contiguous (n, 4) int32 tensor")
+    out = torch.empty_like(ctr)
+    with torch.cuda.device(ctr.device):
+        check(lib().hgl_philox4x32_10(ctr.shape[0], _ptr(ctr), C.c_uint64(key), _ptr(out), _stream(ctr.device)),
+              "hgl_philox4x32_10")
+    return out
+
+
 def block_rsvd(h: Handle, offsets, k: int, p: int, q: int, sketch: str = "bf16", omega=None, seed: int = 0,
                scheme: str = "subspace"):
     """Algorithm 1 on every diagonal block ("power": with the sketch of eq. 10 in place of its

@@ -197,6 +197,33 @@ def test_full_size_gradient_against_sparse_oracle():
 
 
 @pytest.mark.slow
+def test_full_size_gradient_against_richardson_fd():
+    """The differentiation workload's graph at full size (N = 100,000,
+    E = 80,000, w = 1/E, lambda = 1, mu = 0.01) on two tag columns: the
+    adjoint gradient of the FP32 solve on 64 random edges with w_e > 2h
+    against central differences of the FP64 objective at h = 1e-6 with
+    Richardson extrapolation (reading R14: plain h = 1e-6 differences carry
+    an O((h/delta_v)^2) error at this weight scale), computed on every host
+    core by the sparse oracle."""
+    import torch
+    from tests import fd_pool
+    dev = device()
+    p = synth.weight_learning(k=2)
+    mu, h_fd = 0.01, 1e-6
+    h = build(p, dev)
+    Y = torch.from_numpy(p.Y).to(dev, torch.float32)
+    say("grad full size vs fd")
+    F, _, rel, st = hgl().cg_solve(h, p.lam, Y, tol=1e-7)
+    assert st == 0
+    g, _, _, _, ast = hgl().weight_grad(h, p.lam, F, Y=Y, mu=mu, tol=1e-7)
+    assert ast == 0
+    g = g.cpu().numpy()
+    edges = synth.rng_for(19).choice(np.nonzero(p.w > 2 * h_fd)[0], size=64, replace=False)
+    fd = fd_pool.richardson_gradient(p, mu, edges, h_fd)
+    assert np.linalg.norm(g[edges] - fd) / np.linalg.norm(fd) <= 1e-5
+
+
+@pytest.mark.slow
 def test_full_size_gradient_k500_homogeneity_and_additivity():
     """The differentiation workload as the bench runs it (N=100,000,
     E=80,000, all 500 tag columns; FP32 solve and adjoint to relres 5e-7).

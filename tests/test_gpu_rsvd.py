@@ -152,6 +152,37 @@ def test_philox_sketch_matches_published_generator():
     assert diff.max() <= 1   # at most one BF16 ulp (last-bit rounding of log/cos)
 
 
+def test_philox_words_bit_exact():
+    """The device generator's integer words, bit for bit: the published
+    known-answer vectors and a sweep of counters and keys, against the
+    oracle's independently written Philox4x32-10 (itself pinned by the same
+    known answers on the CPU)."""
+    import torch
+    dev = device()
+    kat = [((0, 0, 0, 0), 0, (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+           ((0xFFFFFFFF,) * 4, 0xFFFFFFFF_FFFFFFFF, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+           ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0x299F31D0 << 32) | 0xA4093822,
+            (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for ctr, key, out in kat:
+        c = torch.from_numpy(np.array([ctr], dtype=np.uint32).view(np.int32)).to(dev)
+        got = hgl().philox4x32_10(c, key).cpu().numpy().view(np.uint32)[0]
+        assert tuple(int(x) for x in got) == out
+    rng = synth.rng_for(77)
+    for key in (0, 0x1234_5678_9ABC, int(rng.integers(0, 2**63))):
+        say("philox words key", hex(key))
+        n = 100_003
+        c = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64)
+        c[:1000, 2:] = 0  # the sketch's counters: (index low, index high, 0, 0)
+        c[:1000, 0] = np.arange(1000)
+        c[:1000, 1] = 0
+        got = hgl().philox4x32_10(torch.from_numpy(c.astype(np.uint32).view(np.int32)).to(dev), key)
+        got = got.cpu().numpy().view(np.uint32)
+        ref = philox.philox4x32_10([c[:, i] for i in range(4)], [np.uint64(key & 0xFFFFFFFF),
+                                                                   np.uint64(key >> 32)])
+        for i in range(4):
+            assert np.array_equal(got[:, i].astype(np.uint64), ref[i]), (key, i)
+
+
 def test_errors():
     import torch
     dev = device()
