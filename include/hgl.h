@@ -424,14 +424,16 @@ int hgl_philox4x32_10(int64_t n, const uint32_t* ctr, uint64_t key, uint32_t* ou
  * Z1 = X11 - X12 X22^-1 X21 (eq. 13), Z2 = X22 - X21 X11^-1 X12 (eq. 14),
  * and the four inverses X11^-1, X22^-1, Z1^-1, Z2^-1 are the same
  * construction one level down.  The smallest submatrices (min_block to
- * 2 min_block - 1 rows) are inverted by Gauss-Jordan elimination (eq. 15
- * with all singular values gives the same matrix), in FP32 like the
- * products, which run on MFMA.  So the result is M_bb^-1 up to FP32
- * rounding.
+ * 2 min_block - 1 rows; the paper takes 50, and 500 on the second update)
+ * are inverted exactly (eq. 15 with all singular values gives the same
+ * matrix): those of at most 127 rows by Gauss-Jordan elimination, larger
+ * ones by the same 2 x 2 construction carried on down to such pieces, in
+ * FP32 like the products, which run on MFMA.  So the result is M_bb^-1 up
+ * to FP32 rounding for every min_block.
  *
- * Limits: single-graph handle; 16 <= min_block <= 64; every block 1 to 4096
- * rows, offsets covering [0, N).  Errors: HGL_EINVAL (arguments),
- * HGL_EUNSUPPORTED (a leaf over 127 rows), HGL_EDEVICE.
+ * Limits: single-graph handle; 16 <= min_block <= 4096; every block 1 to
+ * 4096 rows, offsets covering [0, N).  Errors: HGL_EINVAL (arguments),
+ * HGL_EDEVICE.
  * ------------------------------------------------------------------------ */
 
 /*

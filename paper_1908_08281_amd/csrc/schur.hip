@@ -11,9 +11,12 @@
 //   Z1^-1, Z2^-1                             (child nodes, into the output)
 //   top right = -T3 Z2^-1, bottom left = -Z2^-1 T2 (eq. 12)
 // The smallest submatrices (min_block .. 2 min_block - 1 rows) are inverted
-// by Gauss-Jordan elimination in FP32 registers: eq. 15 with all of a
-// submatrix's singular values is its exact inverse, and any exact method
-// gives the same matrix up to rounding.  No pivoting: every matrix inverted
+// exactly: eq. 15 with all of a submatrix's singular values is its exact
+// inverse, and any exact method gives the same matrix up to rounding.  A
+// smallest submatrix of at most kLeafMax rows is inverted by Gauss-Jordan
+// elimination in FP32 registers; a larger one (min_block above 64, e.g. the
+// paper's 500) by the same 2x2 construction carried on below it down to
+// such pieces.  No pivoting: every matrix inverted
 // here is a diagonal block of a symmetric positive definite matrix or a
 // Schur complement of one, so it is symmetric positive definite too, with
 // its eigenvalues in [1, 1 + 1/lambda] like those of M.
@@ -34,7 +37,7 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLeafMax = 127;   // rows of the largest leaf: one thread column per leaf column
-constexpr int kMinBlockLo = 16, kMinBlockHi = 64;
+constexpr int kMinBlockLo = 16;
 constexpr int kMaxBlock = 4096;  // rows of a diagonal block (the extraction stages 4 FP64 rows)
 constexpr int kGT = 64;          // product tile: 64 x 64 outputs per workgroup
 constexpr int kGK = 16;          // k-depth of one LDS stage
@@ -381,7 +384,10 @@ struct Planner {
   // Inverse of the n x n view (in, ldi) into the view (out, ldo), starting
   // at phase p0; returns the first phase after it.
   int node(int64_t in, int ldi, int64_t out, int ldo, int n, int p0) {
-    if (n < 2 * min_block) {
+    // a smallest submatrix of the tessellation (n < 2 min_block) is a leaf
+    // when its registers allow; a larger one is inverted exactly by going on
+    // with the construction below it
+    if (n < 2 * min_block && n <= kLeafMax) {
       if (int(l.size()) <= p0) l.resize(p0 + 1);
       l[p0].push_back(LeafTask{in, out, ldi, ldo, n, 0});
       return p0 + 1;
@@ -425,8 +431,8 @@ size_t put(std::vector<char>& host, const std::vector<T>& v) {
 int check_offsets(int n_blocks, const int32_t* offs, int min_block) {
   HGL_CHECK_ARG(n_blocks >= 1 && offs != nullptr, "need at least one block");
   HGL_CHECK_ARG(offs[0] == 0, "block offsets must start at 0");
-  HGL_CHECK_ARG(min_block >= kMinBlockLo && min_block <= kMinBlockHi, "min_block must be in [%d, %d]", kMinBlockLo,
-                kMinBlockHi);
+  HGL_CHECK_ARG(min_block >= kMinBlockLo && min_block <= kMaxBlock, "min_block must be in [%d, %d]", kMinBlockLo,
+                kMaxBlock);
   for (int b = 0; b < n_blocks; ++b) {
     const int n = offs[b + 1] - offs[b];
     HGL_CHECK_ARG(n >= 1, "block %d is empty or offsets decrease", b);

@@ -36,7 +36,7 @@ def _oracle_blocks(p, blocks):
 
 
 @pytest.mark.parametrize("sizes,min_block", [([300, 257, 130, 64, 17], 16), ([700, 99, 100, 101], 50),
-                                             ([513, 64, 128], 64)])
+                                             ([513, 64, 128], 64), ([1300, 600, 1010], 500)])
 def test_inverse_against_oracle(sizes, min_block):
     dev = device()
     p = _problem(sizes, 300 + min_block)
@@ -123,9 +123,16 @@ def test_full_size_tessellation():
     say("schur full size", p.N)
     h = build(p, dev)
     inv, _ = hgl().block_schur_inverse(h, p.lam, p.blocks, 50)
-    for b, Mb in _oracle_blocks(p, (0, 17, 49)).items():
+    Ms = _oracle_blocks(p, (0, 17, 49))
+    for b, Mb in Ms.items():
         got = inv[b].cpu().double().numpy()
         assert np.abs(got - schur.schur_inverse(Mb, 50)).max() <= INV_BAR, b
+    # the paper's minimum of 500 on the second update: the same exact inverse
+    say("schur full size, min_block 500")
+    inv5, _ = hgl().block_schur_inverse(h, p.lam, p.blocks, 500)
+    for b, Mb in Ms.items():
+        got = inv5[b].cpu().double().numpy()
+        assert np.abs(got - schur.schur_inverse(Mb, 500)).max() <= INV_BAR, b
     Y = torch.from_numpy(p.Y).to(dev, torch.float32)
     tol = 1e-6 / (1 + 1 / p.lam)
     F, it, rel, st = hgl().block_schur_invert(h, p.lam, p.blocks, Y, min_block=50, refine_tol=tol)
@@ -142,7 +149,7 @@ def test_argument_errors():
     dev = device()
     p = _problem([200, 100], 330)
     h = build(p, dev)
-    for mb in (15, 65):
+    for mb in (15, 4097):
         with pytest.raises(HglError):
             hgl().block_schur_inverse(h, p.lam, p.blocks, mb)
     with pytest.raises(HglError):

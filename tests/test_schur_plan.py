@@ -96,7 +96,7 @@ def _blocks(sizes, seed, lam=0.5):
 
 
 @pytest.mark.parametrize("sizes,min_block", [([300, 257, 130, 64, 17], 16), ([700, 99, 100, 101], 50),
-                                             ([513, 64, 128], 64), ([31], 16)])
+                                             ([513, 64, 128], 64), ([31], 16), ([1300, 600, 131], 500)])
 def test_plan_executes_to_the_oracle_inverse(sizes, min_block):
     _lib_or_skip()
     off, Ms = _blocks(sizes, 91 + min_block)
@@ -124,6 +124,11 @@ def test_plan_phase_count_and_argument_checks():
     for bad in ([0, 5000], [0, 0, 10]):
         with pytest.raises(HglError):
             hgl.block_schur_plan(bad, 50)
-    for mb in (15, 65):
+    for mb in (15, 4097):
         with pytest.raises(HglError):
             hgl.block_schur_plan([0, 500], mb)
+    # the paper's minimum of 500: smallest submatrices of 500-999 rows, each
+    # inverted exactly by the construction carried on to pieces of <= 127 rows
+    plan = hgl.block_schur_plan([0, 1500], 500)
+    assert (plan["leaves"][:, 4] <= 127).all()
+    assert [m for _, m in schur.nested_tessellation(1500, 500)] == [750, 750]
