@@ -383,13 +383,13 @@ __global__ __launch_bounds__(kBlock) void k_gram_tiles(BlockMeta bm, const TY* _
 constexpr int kDense = 1024;
 
 // A (l x l in LDS, row-major) <- G_b: the block's tile partials summed in tile
-// order (deterministic), upper triangle mirrored.
-template <class TA>
+// order (deterministic), upper triangle mirrored.  NT threads.
+template <int NT, class TA>
 __device__ __forceinline__ void stage_gram(const BlockMeta& bm, const int32_t* __restrict__ item0,
                                            const double* __restrict__ part, int b, TA* A) {
   const int l = bm.l, npairs = l * (l + 1) / 2;
   const int i0 = item0[b], i1 = item0[b + 1];
-  for (int p = threadIdx.x; p < npairs; p += kDense) {
+  for (int p = threadIdx.x; p < npairs; p += NT) {
     double sacc = 0.0;
 #pragma unroll 8
     for (int it = i0; it < i1; ++it) sacc += part[int64_t(it) * npairs + p];
@@ -400,46 +400,86 @@ __device__ __forceinline__ void stage_gram(const BlockMeta& bm, const int32_t* _
   }
 }
 
+// Calls f(std::integral_constant<int, I>{}) for I = 0 .. N-1 in order.
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
 // L^-1 of the Cholesky factor of G_b = Y_b' Y_b (summed from the Gram tile
 // partials), written to Li (LP x LP, lower, zero padded).
 // One elimination on [G | I] with unscaled pivots: step j subtracts
-// A[i][j] A[m][j] / A[j][j] from the trailing triangle of G (m > j) and
+// A[i][j] A[m][j] / A[j][j] from the trailing triangle of G (j < m <= i) and
 // A[i][j] B[j][c] / A[j][j] from the rows i > j of B (c <= j).  Afterwards
 // L[i][j] = A[i][j] / sqrt(A[j][j]) and L^-1[i][c] = B[i][c] / sqrt(A[i][i]).
-// Every thread owns fixed entries of both lower triangles and keeps them in
-// registers; step j reads only column j of A, row j of B and the pivot, which
-// it does not write, so each step is one barrier.
+// 256 threads; thread (ti, tm) = (tid % 16, tid / 16) keeps the entries
+// (ti + 16x, tm + 16y), x, y < NX = LP/16, of both matrices in registers (a
+// 2-D cyclic layout: the shrinking trailing triangle stays spread over all
+// threads).  The steps run in chunks of 16, one unrolled body per chunk, so
+// that a body holds only the row and column groups still live in it (rows
+// and A columns x, y >= chunk, A lower blocks y <= x, B columns y <= chunk).
+// Step j reads column j of A, the pivot's reciprocal and row j of B, which
+// their owners publish at the end of step j-1 into one of two alternating
+// LDS slots; each step is one barrier.
 // A non-positive or non-finite pivot triggers one retry with the shift
 // 11 (n l + l (l+1)) u trace(G) (shifted CholQR, Fukaya et al. 2020); a
 // second failure sets fail[b].
-constexpr int kOwn = (kMaxLP * (kMaxLP + 1) / 2 + kDense - 1) / kDense;  // entries per thread
-__global__ __launch_bounds__(kDense) void k_chol_inv(BlockMeta bm, const int32_t* __restrict__ item0,
+constexpr int kCholT = 256;
+template <int NX>
+__global__ __launch_bounds__(kCholT) void k_chol_inv(BlockMeta bm, const int32_t* __restrict__ item0,
                                                      const double* __restrict__ part, double* __restrict__ Li,
                                                      int32_t* __restrict__ fail) {
-  extern __shared__ double sm[];
+  extern __shared__ double G[];   // l x l, row-major
+  __shared__ double colA[2][kMaxLP], rowB[2][kMaxLP], rinv[2], dg[kMaxLP];
+  __shared__ double s_tr;
   const int b = blockIdx.x, tid = threadIdx.x;
+  const int ti = tid & 15, tm = tid >> 4;
   const int l = bm.l, LP = bm.LP;
   const int n = bm.off[b + 1] - bm.off[b];
-  const int ntri = l * (l + 1) / 2;
-  double* A = sm;             // l x l, row-major
-  double* B = sm + l * l;     // l x l, row-major (lower triangle used)
-  __shared__ double s_tr;
-  int oi[kOwn], om[kOwn];     // owned (row, column), column <= row
+  stage_gram<kCholT>(bm, item0, part, b, G);
+  __syncthreads();
+  double a[NX][NX], bx[NX][NX];
+  // The owners of column s of A and of row s of B write them to slot s & 1
+  // (whole register groups, no per-entry tests: the entries above the
+  // diagonal of B and the padding rows are exact zeros, and whatever lands
+  // in rows < s of the column is masked by its readers); the pivot's owner
+  // adds its reciprocal.  s lies in group X0 or X0 + 1.
+  auto publish = [&](int s, auto x0c) {
+    constexpr int X0 = decltype(x0c)::value;
+    const int slot = s & 1, rs = s & 15;
+    const bool up = (s >> 4) > X0;
+    if (tm == rs) {
 #pragma unroll
-  for (int u = 0; u < kOwn; ++u) {
-    const int t = tid + u * kDense;
-    if (t < ntri) tri_of(t, oi[u], om[u]);
-    else oi[u] = om[u] = -1;
-  }
-  double a[kOwn], bx[kOwn];
+      for (int x = X0; x < NX; ++x) {
+        double v = a[x][X0];
+        if constexpr (X0 + 1 < NX) {
+          if (X0 + 1 <= x) v = up ? a[x][X0 + 1] : v;
+        }
+        colA[slot][ti + 16 * x] = v;
+        if (ti + 16 * x == s) {
+          dg[s] = v;
+          rinv[slot] = 1.0 / v;
+        }
+      }
+    }
+    if (ti == rs) {
+#pragma unroll
+      for (int y = 0; y < NX; ++y) {
+        double v = bx[X0][y];
+        if constexpr (X0 + 1 < NX) v = up ? bx[X0 + 1][y] : v;
+        rowB[slot][tm + 16 * y] = v;
+      }
+    }
+  };
   for (int attempt = 0;; ++attempt) {
-    stage_gram(bm, item0, part, b, A);
-    __syncthreads();
     double shift = 0.0;
     if (attempt > 0) {
       if (tid < kWave) {
         double t = 0.0;
-        for (int i = tid; i < l; i += kWave) t += A[i * l + i];
+        for (int i = tid; i < l; i += kWave) t += G[i * l + i];
         for (int o2 = 32; o2 >= 1; o2 >>= 1) t += __shfl_xor(t, o2, kWave);
         if (tid == 0) s_tr = t;
       }
@@ -447,54 +487,54 @@ __global__ __launch_bounds__(kDense) void k_chol_inv(BlockMeta bm, const int32_t
       shift = 11.0 * (double(n) * l + double(l) * (l + 1)) * 1.1102230246251565e-16 * s_tr;
     }
 #pragma unroll
-    for (int u = 0; u < kOwn; ++u) {
-      a[u] = bx[u] = 0.0;
-      if (oi[u] >= 0) {
-        a[u] = A[oi[u] * l + om[u]] + (oi[u] == om[u] ? shift : 0.0);
-        bx[u] = oi[u] == om[u] ? 1.0 : 0.0;
-      }
-    }
-    __syncthreads();
+    for (int x = 0; x < NX; ++x)
 #pragma unroll
-    for (int u = 0; u < kOwn; ++u)
-      if (oi[u] >= 0) {
-        A[oi[u] * l + om[u]] = a[u];
-        B[oi[u] * l + om[u]] = bx[u];
+      for (int y = 0; y < NX; ++y) {
+        const int i = ti + 16 * x, m = tm + 16 * y;
+        a[x][y] = (i < l && m <= i) ? G[i * l + m] + (i == m ? shift : 0.0) : 0.0;
+        bx[x][y] = (i < l && m == i) ? 1.0 : 0.0;
       }
+    publish(0, std::integral_constant<int, 0>{});
     __syncthreads();
     bool ok = true;
-    for (int j = 0; j < l; ++j) {
-      // every thread reads the same pivot, so the exit is uniform
-      const double piv = A[j * l + j];
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        ok = false;
-        break;
-      }
-      const double inv = 1.0 / piv;
-      double ca[kOwn], cm[kOwn], rb[kOwn];
-#pragma unroll
-      for (int u = 0; u < kOwn; ++u) {
-        const int i = oi[u], m = om[u];
-        const bool live = i > j;   // rows below the pivot only
-        ca[u] = live ? A[i * l + j] : 0.0;
-        cm[u] = (live && m > j) ? A[m * l + j] : 0.0;
-        rb[u] = (live && m <= j) ? B[j * l + m] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < kOwn; ++u) {
-        const int i = oi[u], m = om[u];
-        if (i > j) {
-          if (m > j) {
-            a[u] -= ca[u] * cm[u] * inv;
-            A[i * l + m] = a[u];
-          } else {
-            bx[u] -= ca[u] * rb[u] * inv;
-            B[i * l + m] = bx[u];
-          }
+    static_for<0, NX>([&](auto jbc) {
+      constexpr int JB = decltype(jbc)::value;
+      if (!ok) return;
+      const int j1 = min(l, 16 * JB + 16);
+      for (int j = 16 * JB; j < j1; ++j) {
+        const int slot = j & 1;
+        // every thread reads the same pivot, so the exit is uniform
+        const double piv = colA[slot][j];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+          ok = false;
+          break;
         }
+        const double inv = rinv[slot];
+        // ci = 0 for rows <= j (their B rows are final).  Not masked: cm in
+        // columns <= j (those A entries were published and are not read
+        // again), rb in columns > j (zeros above B's diagonal), and the
+        // padding rows (zero in G, so zero throughout).  Entries above the
+        // diagonal of A are never read.
+        double ci[NX], cm[NX], rb[NX];
+#pragma unroll
+        for (int x = JB; x < NX; ++x) {
+          const int i = ti + 16 * x;
+          ci[x] = i > j ? colA[slot][i] * inv : 0.0;
+          cm[x] = colA[slot][tm + 16 * x];
+        }
+#pragma unroll
+        for (int y = 0; y <= JB; ++y) rb[y] = rowB[slot][tm + 16 * y];
+#pragma unroll
+        for (int x = JB; x < NX; ++x) {
+#pragma unroll
+          for (int y = JB; y <= x; ++y) a[x][y] -= ci[x] * cm[y];
+#pragma unroll
+          for (int y = 0; y <= JB; ++y) bx[x][y] -= ci[x] * rb[y];
+        }
+        if (j + 1 < l) publish(j + 1, jbc);
+        __syncthreads();
       }
-      __syncthreads();
-    }
+    });
     if (ok) break;
     if (attempt == 1) {
       if (tid == 0) fail[b] = 1;
@@ -503,10 +543,13 @@ __global__ __launch_bounds__(kDense) void k_chol_inv(BlockMeta bm, const int32_t
     __syncthreads();
   }
   double* Lb = Li + int64_t(b) * LP * LP;
-  for (int q = tid; q < LP * LP; q += kDense) {
-    const int i = q / LP, c = q - i * LP;
-    Lb[q] = (i < l && c <= i) ? B[i * l + c] / sqrt(A[i * l + i]) : 0.0;
-  }
+#pragma unroll
+  for (int x = 0; x < NX; ++x)
+#pragma unroll
+    for (int y = 0; y < NX; ++y) {
+      const int i = ti + 16 * x, c = tm + 16 * y;
+      Lb[i * LP + c] = (i < l && c <= i) ? bx[x][y] / sqrt(dg[i]) : 0.0;
+    }
 }
 
 // Li <- identity on each block's l x l corner (zero elsewhere in LP x LP):
@@ -591,11 +634,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_rinv(BlockMeta bm, const TY* _
 // sweep; each pair's rotation is the one of Golub & Van Loan, sym.schur2.
 // With J the product of a round's disjoint rotations, J'AJ restricted to the
 // pair blocks (a, b) is J_a' A_ab J_b, so a round is one pass over independent
-// 2 x 2 blocks, done in place (upper blocks a <= b, mirrored), plus V <- V J
-// on the same blocks of V.  Writes the k largest eigenvalues' square roots
-// (singular values of B, decreasing) and the matching eigenvectors (columns
-// of Ut, l x k).
-// kJT = 2 x 2 blocks per thread and round: 3 covers l <= 80, 4 covers l <= 96.
+// 2 x 2 blocks (upper blocks a <= b, mirrored), plus V <- V J on the same
+// blocks of V.  Every wave computes the round's rotations itself (lane a
+// for pair a) and hands them to its threads' blocks by lane shuffles, so a
+// round is a single barrier when A is double-buffered.  Writes the k largest
+// eigenvalues' square roots (singular values of B, decreasing) and the
+// matching eigenvectors (columns of Ut, l x k).
+// NT threads; kJT = 2 x 2 blocks per thread and round (at 512 threads, 5
+// covers l <= 80 and 7 covers l <= 96).
 // TJ = arithmetic of the sweeps: FP64, or FP32 where the matrix comes from a
 // BF16 sketch (its entries carry errors far above FP32 rounding); the sweeps
 // stop when the off-diagonal Frobenius norm is below 1e-13 (FP64) or 1e-4
@@ -603,13 +649,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_rinv(BlockMeta bm, const TY* _
 // order 1e-4 over the relative gap, both below the BF16 sketch's 4e-3) of
 // the diagonal's.
 template <class TJ>
-struct Rot {
-  TJ c, s;
+struct JacPair {
+  TJ c, s;     // the pair's rotation this round
+  int p, q;    // p | (p l) << 8 and q | (q l) << 8: index and row offset
 };
-template <int kJT, class TJ>
-__global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* __restrict__ item0,
-                                                   const double* __restrict__ part, double* __restrict__ sig,
-                                                   double* __restrict__ Ut, int max_sweeps) {
+template <int NT, int kJT, class TJ, bool DB>
+__global__ __launch_bounds__(NT) void k_jacobi(BlockMeta bm, const int32_t* __restrict__ item0,
+                                               const double* __restrict__ part, double* __restrict__ sig,
+                                               double* __restrict__ Ut, int max_sweeps) {
   extern __shared__ double sm[];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int l = bm.l, LP = bm.LP, kk = bm.kk;
@@ -617,46 +664,62 @@ __global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* 
   const int half = ne / 2;
   constexpr double kStop = sizeof(TJ) == 8 ? 1e-26 : 1e-8;   // squared relative off-diagonal norm
   constexpr TJ kTiny = sizeof(TJ) == 8 ? TJ(1e-300) : TJ(1e-30);
-  TJ* A = reinterpret_cast<TJ*>(sm);                       // l x l
-  TJ* V = A + l * l;                                       // l x l
-  Rot<TJ>* rot = reinterpret_cast<Rot<TJ>*>(V + l * l);   // [half] (c, s)
-  int2* pq = reinterpret_cast<int2*>(rot + half);          // [half] (p, q), p < q
-  int* rank = reinterpret_cast<int*>(pq + half);           // [l]
-  constexpr int NW = kDense / kWave;
+  constexpr int NW = NT / kWave;
+  // LDS: A (twice when double-buffered, DB: a round reads one copy and
+  // writes the other, so one barrier per round; otherwise in place with a
+  // barrier between reading the rotations' entries and writing the blocks),
+  // V, the ranks, and one pair table per wave.  Offsets from one base keep
+  // every access an LDS instruction.
+  TJ* const M = reinterpret_cast<TJ*>(sm);
+  const int ll = l * l;
+  const int oV = (DB ? 2 : 1) * ll;
+  int* rank = reinterpret_cast<int*>(M + oV + ll);                       // [l]
+  JacPair<TJ>* tab = reinterpret_cast<JacPair<TJ>*>(sm + (((DB ? 3 : 2) * ll * sizeof(TJ) + 4 * l + 15) / 16) * 2);
   __shared__ double s_off[NW], s_dg[NW];
-  stage_gram(bm, item0, part, b, A);
-  for (int q = tid; q < l * l; q += kDense) V[q] = (q / l == q % l) ? TJ(1) : TJ(0);
+  stage_gram<NT>(bm, item0, part, b, M);
+  for (int q = tid; q < ll; q += NT) M[oV + q] = (q / l == q % l) ? TJ(1) : TJ(0);
   __syncthreads();
-  const int nA = half * (half + 1) / 2, nT = nA + half * half;
-  // this thread's blocks t = tid + u * kDense: A blocks (a <= b) first, then
-  // V blocks (row pair a, column pair b); tk_a = -1 for none
-  int tk_a[kJT], tk_b[kJT];
-  bool tk_isA[kJT];
+  // this thread's tasks t = tid + u * NT, in wave-uniform ranges: the
+  // diagonal A blocks (pair a), the blocks above them (pairs a < b, stored
+  // and mirrored), and V <- V J on row pair (2r, 2r+1) and column pair b
+  const int nOff = half * (half - 1) / 2, nVr = (l + 1) / 2;
+  const int n1 = half, n2 = n1 + nOff, n3 = n2 + nVr * half;
+  int tk_k[kJT], tk_a[kJT], tk_b[kJT];   // kind 0 none, 1 diagonal, 2 above, 3 V
 #pragma unroll
   for (int u = 0; u < kJT; ++u) {
-    const int t = tid + u * kDense;
-    tk_a[u] = tk_b[u] = -1;
-    tk_isA[u] = false;
-    if (t < nA) {
-      tri_of(t, tk_b[u], tk_a[u]);
-      tk_isA[u] = true;
-    } else if (t < nT) {
-      tk_a[u] = (t - nA) / half;
-      tk_b[u] = (t - nA) - tk_a[u] * half;
+    const int t = tid + u * NT;
+    tk_k[u] = 0;
+    tk_a[u] = tk_b[u] = 0;
+    if (t < n1) {
+      tk_k[u] = 1;
+      tk_a[u] = tk_b[u] = t;
+    } else if (t < n2) {
+      int bb, aa;
+      tri_of(t - n1, bb, aa);
+      tk_k[u] = 2;
+      tk_a[u] = aa;
+      tk_b[u] = bb + 1;
+    } else if (t < n3) {
+      tk_k[u] = 3;
+      tk_a[u] = (t - n2) / half;   // row pair
+      tk_b[u] = (t - n2) - tk_a[u] * half;
     }
   }
+  const int lane = tid % kWave;
+  JacPair<TJ>* wtab = tab + (tid / kWave) * half;
+  int oc = 0;   // offset of the current A
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // convergence: off-diagonal mass against the diagonal (fixed-order sums)
     double off = 0.0, dg = 0.0;
-    for (int q = tid; q < l * l; q += kDense) {
-      const double v = double(A[q]) * double(A[q]);
+    for (int q = tid; q < ll; q += NT) {
+      const double v = double(M[oc + q]) * double(M[oc + q]);
       if (q / l != q % l) off += v; else dg += v;
     }
     for (int o2 = 32; o2 >= 1; o2 >>= 1) {
       off += __shfl_xor(off, o2, kWave);
       dg += __shfl_xor(dg, o2, kWave);
     }
-    if (tid % kWave == 0) {
+    if (lane == 0) {
       s_off[tid / kWave] = off;
       s_dg[tid / kWave] = dg;
     }
@@ -671,102 +734,138 @@ __global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* 
     // CholQR noise, or the BF16 sketch's
     if (off_t <= kStop * dg_t) break;
     for (int round = 0; round < ne - 1; ++round) {
-      if (tid < half) {
-        // circle method: slot 0 fixed, the others rotate
+      const int on = DB ? ll - oc : oc;   // offset the round writes A to
+      // lane a of every wave computes pair a (circle method: slot 0 fixed,
+      // the others rotate; pair a is the slots (a, ne-1-a), ordered p < q)
+      // and its rotation into the wave's own table (the same values in
+      // every wave; a wave's LDS accesses complete in order)
+      if (lane < half) {
         auto at = [&](int slot) {
           if (slot == 0) return 0;
           int v = slot - 1 + round;
           if (v >= ne - 1) v -= ne - 1;
           return 1 + v;
         };
-        int p = at(tid), q = at(ne - 1 - tid);
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        TJ c = TJ(1), s = TJ(0);
+        const int x0 = at(lane), y0 = at(ne - 1 - lane);
+        const int p = min(x0, y0), q = max(x0, y0);
+        TJ rc = TJ(1), rs = TJ(0);
         if (q < l) {
-          const TJ apq = A[p * l + q];
+          const TJ apq = M[oc + p * l + q];
           if (fabs(apq) > kTiny) {
-            const TJ tau = (A[q * l + q] - A[p * l + p]) / (TJ(2) * apq);
+            const TJ tau = (M[oc + q * l + q] - M[oc + p * l + p]) / (TJ(2) * apq);
             const TJ tt = (tau >= TJ(0) ? TJ(1) : TJ(-1)) / (fabs(tau) + sqrt(TJ(1) + tau * tau));
-            c = TJ(1) / sqrt(TJ(1) + tt * tt);
-            s = tt * c;
+            rc = TJ(1) / sqrt(TJ(1) + tt * tt);
+            rs = tt * rc;
           }
         }
-        rot[tid] = Rot<TJ>{c, s};
-        pq[tid] = make_int2(p, q);
+        wtab[lane] = JacPair<TJ>{rc, rs, p | (p * l) << 8, q | (q * l) << 8};
       }
-      __syncthreads();
-      // phase 2: this thread's blocks, all loads before any store (the
-      // blocks are disjoint; the compiler cannot see that)
-      int2 PA[kJT], PB[kJT];
-      Rot<TJ> RA[kJT], RB[kJT];
+      if constexpr (DB) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else {
+        __syncthreads();   // every rotation read before any block is written
+      }
+      // this thread's tasks, all loads before any store (the tasks are
+      // disjoint; the compiler cannot see that)
+      JacPair<TJ> ea[kJT], eb[kJT];
       TJ x[kJT][4];
 #pragma unroll
       for (int u = 0; u < kJT; ++u) {
-        PA[u] = tk_a[u] >= 0 ? pq[tk_a[u]] : make_int2(0, l);
-        PB[u] = tk_a[u] >= 0 ? pq[tk_b[u]] : make_int2(0, l);
-        RA[u] = (tk_a[u] >= 0 && tk_isA[u]) ? rot[tk_a[u]] : Rot<TJ>{TJ(1), TJ(0)};
-        RB[u] = tk_a[u] >= 0 ? rot[tk_b[u]] : Rot<TJ>{TJ(1), TJ(0)};
-      }
-#pragma unroll
-      for (int u = 0; u < kJT; ++u) {
-        const TJ* M = tk_isA[u] ? A : V;
-        const bool q0 = PA[u].y < l, q1 = PB[u].y < l, live = tk_a[u] >= 0;
-        x[u][0] = live ? M[PA[u].x * l + PB[u].x] : TJ(0);
-        x[u][1] = (live && q1) ? M[PA[u].x * l + PB[u].y] : TJ(0);
-        x[u][2] = (live && q0) ? M[PA[u].y * l + PB[u].x] : TJ(0);
-        x[u][3] = (live && q0 && q1) ? M[PA[u].y * l + PB[u].y] : TJ(0);
-      }
-#pragma unroll
-      for (int u = 0; u < kJT; ++u) {
-        if (tk_a[u] < 0) continue;
-        // rows by J_a' (p' = c p - s q, q' = s p + c q; identity for V), then
-        // columns by J_b
-        const TJ ca = RA[u].c, sa = RA[u].s, cb = RB[u].c, sb = RB[u].s;
-        const TJ r00 = ca * x[u][0] - sa * x[u][2], r01 = ca * x[u][1] - sa * x[u][3];
-        const TJ r10 = sa * x[u][0] + ca * x[u][2], r11 = sa * x[u][1] + ca * x[u][3];
-        const TJ y00 = cb * r00 - sb * r01, y01 = sb * r00 + cb * r01;
-        const TJ y10 = cb * r10 - sb * r11, y11 = sb * r10 + cb * r11;
-        const int pa = PA[u].x, qa = PA[u].y, pb = PB[u].x, qb = PB[u].y;
-        const bool q0 = qa < l, q1 = qb < l;
-        if (!tk_isA[u]) {
-          V[pa * l + pb] = y00;
-          if (q1) V[pa * l + qb] = y01;
-          if (q0) V[qa * l + pb] = y10;
-          if (q0 && q1) V[qa * l + qb] = y11;
-        } else if (tk_a[u] == tk_b[u]) {
-          // the pair's own 2 x 2 block: diagonalised; kept exactly symmetric
-          A[pa * l + pa] = y00;
-          if (q0) {
-            A[qa * l + qa] = y11;
-            A[pa * l + qa] = y01;
-            A[qa * l + pa] = y01;
+        const int k = tk_k[u];
+        if (k == 0) continue;
+        eb[u] = wtab[tk_b[u]];
+        if (k == 1) {
+          const int p = eb[u].p & 255, pl = eb[u].p >> 8, q = eb[u].q & 255, ql = eb[u].q >> 8;
+          x[u][0] = M[oc + pl + p];
+          if (q < l) {
+            x[u][1] = M[oc + pl + q];
+            x[u][3] = M[oc + ql + q];
           }
+        } else if (k == 2) {
+          ea[u] = wtab[tk_a[u]];
+          const int pa = ea[u].p & 255, pal = ea[u].p >> 8, qa = ea[u].q & 255, qal = ea[u].q >> 8;
+          const int pb = eb[u].p & 255, qb = eb[u].q & 255;
+          x[u][0] = M[oc + pal + pb];
+          x[u][1] = qb < l ? M[oc + pal + qb] : TJ(0);
+          x[u][2] = qa < l ? M[oc + qal + pb] : TJ(0);
+          x[u][3] = (qa < l && qb < l) ? M[oc + qal + qb] : TJ(0);
         } else {
-          A[pa * l + pb] = y00;
-          A[pb * l + pa] = y00;
+          const int r0 = 2 * tk_a[u], pb = eb[u].p & 255, qb = eb[u].q & 255;
+          const bool r1 = r0 + 1 < l, q1 = qb < l;
+          x[u][0] = M[oV + r0 * l + pb];
+          x[u][1] = q1 ? M[oV + r0 * l + qb] : TJ(0);
+          x[u][2] = r1 ? M[oV + (r0 + 1) * l + pb] : TJ(0);
+          x[u][3] = (r1 && q1) ? M[oV + (r0 + 1) * l + qb] : TJ(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kJT; ++u) {
+        const int k = tk_k[u];
+        if (k == 0) continue;
+        const TJ cb = eb[u].c, sb = eb[u].s;
+        if (k == 1) {
+          // the pair's own 2 x 2 block J' X J: diagonalised, kept exactly
+          // symmetric
+          const int p = eb[u].p & 255, pl = eb[u].p >> 8, q = eb[u].q & 255, ql = eb[u].q >> 8;
+          if (q < l) {
+            const TJ x00 = x[u][0], x01 = x[u][1], x11 = x[u][3];
+            const TJ r00 = cb * x00 - sb * x01, r01 = cb * x01 - sb * x11;
+            const TJ r10 = sb * x00 + cb * x01, r11 = sb * x01 + cb * x11;
+            const TJ y00 = cb * r00 - sb * r01, y01 = sb * r00 + cb * r01;
+            const TJ y11 = sb * r10 + cb * r11;
+            M[on + pl + p] = y00;
+            M[on + ql + q] = y11;
+            M[on + pl + q] = y01;
+            M[on + ql + p] = y01;
+          } else {
+            M[on + pl + p] = x[u][0];
+          }
+        } else if (k == 2) {
+          // rows by J_a' (p' = c p - s q, q' = s p + c q), then columns by J_b
+          const TJ ca = ea[u].c, sa = ea[u].s;
+          const TJ r00 = ca * x[u][0] - sa * x[u][2], r01 = ca * x[u][1] - sa * x[u][3];
+          const TJ r10 = sa * x[u][0] + ca * x[u][2], r11 = sa * x[u][1] + ca * x[u][3];
+          const TJ y00 = cb * r00 - sb * r01, y01 = sb * r00 + cb * r01;
+          const TJ y10 = cb * r10 - sb * r11, y11 = sb * r10 + cb * r11;
+          const int pa = ea[u].p & 255, pal = ea[u].p >> 8, qa = ea[u].q & 255, qal = ea[u].q >> 8;
+          const int pb = eb[u].p & 255, pbl = eb[u].p >> 8, qb = eb[u].q & 255, qbl = eb[u].q >> 8;
+          const bool q0 = qa < l, q1 = qb < l;
+          M[on + pal + pb] = y00;
+          M[on + pbl + pa] = y00;
           if (q1) {
-            A[pa * l + qb] = y01;
-            A[qb * l + pa] = y01;
+            M[on + pal + qb] = y01;
+            M[on + qbl + pa] = y01;
           }
           if (q0) {
-            A[qa * l + pb] = y10;
-            A[pb * l + qa] = y10;
+            M[on + qal + pb] = y10;
+            M[on + pbl + qa] = y10;
           }
           if (q0 && q1) {
-            A[qa * l + qb] = y11;
-            A[qb * l + qa] = y11;
+            M[on + qal + qb] = y11;
+            M[on + qbl + qa] = y11;
+          }
+        } else {
+          // V <- V J_b on two rows
+          const int r0 = 2 * tk_a[u], pb = eb[u].p & 255, qb = eb[u].q & 255;
+          const bool r1 = r0 + 1 < l, q1 = qb < l;
+          M[oV + r0 * l + pb] = cb * x[u][0] - sb * x[u][1];
+          if (q1) M[oV + r0 * l + qb] = sb * x[u][0] + cb * x[u][1];
+          if (r1) {
+            M[oV + (r0 + 1) * l + pb] = cb * x[u][2] - sb * x[u][3];
+            if (q1) M[oV + (r0 + 1) * l + qb] = sb * x[u][2] + cb * x[u][3];
           }
         }
       }
       __syncthreads();
+      oc = on;
     }
   }
+  const TJ* A = M + oc;
+  const TJ* V = M + oV;
   // rank by decreasing eigenvalue (ties by index): output the leading kk
-  for (int i = tid; i < l; i += kDense) {
+  for (int i = tid; i < l; i += NT) {
     const double li = A[i * l + i];
     int r = 0;
     for (int j = 0; j < l; ++j) {
@@ -777,9 +876,414 @@ __global__ __launch_bounds__(kDense) void k_jacobi(BlockMeta bm, const int32_t* 
     if (r < kk) sig[int64_t(b) * kk + r] = sqrt(fmax(li, 0.0));
   }
   __syncthreads();
-  for (int q = tid; q < l * l; q += kDense) {
+  for (int q = tid; q < l * l; q += NT) {
     const int r = q / l, i = q - r * l;
     if (rank[i] < kk) Ut[int64_t(b) * LP * kk + int64_t(r) * kk + rank[i]] = double(V[q]);
+  }
+}
+
+// ------------------------------------------- tridiagonal eigensolver --
+
+// Top-kk eigenpairs of the symmetric l x l matrix G_b (= B B', summed from
+// the Gram tile partials) in FP32, for a BF16 sketch, as four phases in one
+// workgroup per block (1024 threads):
+//  1. Householder tridiagonalisation Q' G Q = T (Golub & Van Loan, alg.
+//     8.3.1): step k has p = tau A22 v (16 lanes per row), then
+//     A22 -= v w' + w v' with w = p - (tau/2)(p'v) v.  Wave 0 updates the
+//     first column of A22 alone and forms the next reflector from it while
+//     the other waves update the rest, so a step is two barriers; v_k is
+//     kept in column k of A.
+//  2. The kk largest eigenvalues of T by multisection on Sturm counts
+//     (Golub & Van Loan, sec. 8.4.1): 4 lanes per eigenvalue split its
+//     bracket into 5 parts per pass, 12 passes (5^12 > 2^27).
+//  3. Eigenvectors of T by inverse iteration, one lane per eigenvalue
+//     (Golub & Van Loan, sec. 8.2.2): Gaussian elimination with partial
+//     pivoting of T - lam I once, two solves from a fixed start vector, each
+//     followed by modified Gram-Schmidt against the earlier vectors of the
+//     same cluster (eigenvalues closer than 1e-3 |T|, the threshold of
+//     LAPACK's stein), one wave per vector.
+//  4. Back-transformation U = Q Z: each eigenvector's column held by 16
+//     lanes in registers through the l-2 reflectors (no barriers).
+// Writes sqrt of the eigenvalues (singular values of B, decreasing) to sig
+// and the eigenvectors to Ut (l x kk), as the Jacobi kernel does.
+// cw = eigenvectors per inverse-iteration pass (64, or 32 where the
+// factors of 64 would not fit in LDS).
+constexpr int kEigT = 1024;
+constexpr int kEigG = 4;     // lanes per eigenvalue in the multisection
+constexpr int kEigPass = 12;
+constexpr int kEigSolves = 2;
+constexpr int kZ = kMaxLP / 16;   // entries of a column per lane of a 16-lane group
+
+__device__ __forceinline__ float wave_sum_f(float x) {
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+// Reflector of x (two entries per lane of wave 0: x_lane, x_{lane+64};
+// n entries): H x = beta e_1, H = I - t v v', v_0 = 1.  Writes v to vbuf
+// and to column col of A from row r0, and tau, e at index k.
+__device__ __forceinline__ void eig_reflector(float x0, float x1, int n, int k, int r0, int col, int l,
+                                              float* __restrict__ A, float* __restrict__ vbuf,
+                                              float* __restrict__ tau, float* __restrict__ ee) {
+  const int lane = threadIdx.x % kWave;
+  const float alpha = __shfl(x0, 0, kWave);
+  const float s2 = wave_sum_f((lane >= 1 && lane < n ? x0 * x0 : 0.f) + (lane + 64 < n ? x1 * x1 : 0.f));
+  float t = 0.f, beta = alpha, scale = 0.f;
+  if (s2 > 0.f) {
+    const float nrm = sqrtf(alpha * alpha + s2);
+    beta = alpha >= 0.f ? -nrm : nrm;
+    t = (beta - alpha) / beta;
+    scale = 1.f / (alpha - beta);
+  }
+  if (lane < n) {
+    const float v = lane == 0 ? 1.f : x0 * scale;
+    vbuf[lane] = v;
+    A[(r0 + lane) * l + col] = v;
+  }
+  if (lane + 64 < n) {
+    const float v = x1 * scale;
+    vbuf[lane + 64] = v;
+    A[(r0 + lane + 64) * l + col] = v;
+  }
+  if (lane == 0) {
+    tau[k] = t;
+    ee[k] = beta;
+  }
+}
+
+__global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32_t* __restrict__ item0,
+                                                       const double* __restrict__ part, double* __restrict__ sig,
+                                                       double* __restrict__ Ut, int cw) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int l = bm.l, LP = bm.LP, kk = bm.kk;
+  float* const A = reinterpret_cast<float*>(sm);     // l x l, row-major
+  float* const Z = A + l * l;                        // l x kk, Z[i * kk + j]
+  float* const FA = Z + l * kk;                      // l x cw each: the factors of T - lam I:
+  float* const FB = FA + l * cw;                     //   1 / pivot, first and second superdiagonal,
+  float* const FC = FB + l * cw;                     //   multiplier, row swap (1) or not (0)
+  float* const FM = FC + l * cw;
+  float* const FS = FM + l * cw;
+  __shared__ float vb[2][kMaxLP], pb[kMaxLP], ee[kMaxLP], tau[kMaxLP], lam[kMaxLP];
+  __shared__ __align__(16) float dd[kMaxLP + 4], e2s[kMaxLP + 4];
+  __shared__ int cst[kMaxLP];
+  __shared__ float s_lo, s_hi, s_piv, s_nrm;
+  stage_gram<kEigT>(bm, item0, part, b, A);
+  __syncthreads();
+  // 1. tridiagonalisation
+  if (l >= 3) {
+    if (wave == 0) {
+      if (lane == 0) dd[0] = A[0];
+      const float x0 = lane < l - 1 ? A[(1 + lane) * l] : 0.f;
+      const float x1 = lane + 64 < l - 1 ? A[(65 + lane) * l] : 0.f;
+      eig_reflector(x0, x1, l - 1, 0, 1, 0, l, A, vb[0], tau, ee);
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k + 2 < l; ++k) {
+    const int m = l - k - 1;   // order of A22 = A[k+1:, k+1:]
+    const float* v = vb[k & 1];
+    const float t = tau[k];
+    float* const A22 = A + (k + 1) * l + (k + 1);
+    if (t != 0.f) {   // uniform
+      // p = t A22 v, 16 lanes per row
+      const int g = tid >> 4, c16 = tid & 15;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int i = g + 64 * r;
+        if (i < m) {
+          const float* row = A22 + i * l;
+          float acc = 0.f;
+#pragma unroll
+          for (int u = 0; u < kZ; ++u) {
+            const int j = c16 + 16 * u;
+            if (j < m) acc += row[j] * v[j];
+          }
+          for (int o = 8; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+          if (c16 == 0) pb[i] = t * acc;
+        }
+      }
+    }
+    __syncthreads();
+    // K = t/2 p'v (every wave forms the same sum)
+    float K = 0.f;
+    if (t != 0.f) {
+      float kp = 0.f;
+      if (lane < m) kp += pb[lane] * v[lane];
+      if (lane + 64 < m) kp += pb[lane + 64] * v[lane + 64];
+      K = 0.5f * t * wave_sum_f(kp);
+    }
+    if (wave == 0) {
+      // first column of A22 (rows 1..m-1 in the lanes, row 0 uniform), then
+      // the next reflector from it, or the last entries of T
+      const float w0 = t != 0.f ? pb[0] - K : 0.f;
+      float x0 = 0.f, x1 = 0.f;
+      if (lane + 1 < m) {
+        const int i = lane + 1;
+        const float vi = v[i], wi = t != 0.f ? pb[i] - K * vi : 0.f;
+        x0 = A22[i * l] - (vi * w0 + wi);
+      }
+      if (lane + 65 < m) {
+        const int i = lane + 65;
+        const float vi = v[i], wi = t != 0.f ? pb[i] - K * vi : 0.f;
+        x1 = A22[i * l] - (vi * w0 + wi);
+      }
+      if (lane == 0) dd[k + 1] = A22[0] - (w0 + w0);
+      if (m >= 3) {
+        eig_reflector(x0, x1, m - 1, k + 1, k + 2, k + 1, l, A, vb[(k + 1) & 1], tau, ee);
+      } else if (lane == 0) {
+        ee[k + 1] = x0;
+      }
+    } else if (t != 0.f) {
+      // the rest of A22 (rows and columns >= 1; row 0 is not read again)
+      const int u0 = tid - kWave, g = u0 >> 4, c16 = u0 & 15;
+      constexpr int NG = (kEigT - kWave) / 16;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int i = 1 + g + NG * r;
+        if (i < m) {
+          const float vi = v[i], wi = pb[i] - K * vi;
+          float* row = A22 + i * l;
+#pragma unroll
+          for (int u = 0; u < kZ; ++u) {
+            const int j = 1 + c16 + 16 * u;
+            if (j < m) {
+              const float vj = v[j], wj = pb[j] - K * vj;
+              row[j] -= vi * wj + wi * vj;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (l <= 2) {
+      dd[0] = A[0];
+      if (l == 2) ee[0] = A[l];
+    }
+    dd[l - 1] = A[(l - 1) * l + (l - 1)];
+  }
+  __syncthreads();
+  // Gershgorin bracket, the Sturm pivot floor and |T| (one wave); e2s[i] =
+  // e_{i-1}^2 lines up with dd[i]
+  if (wave == 0) {
+    float lo = 3.4e38f, hi = -3.4e38f, emax = 0.f, tn = 0.f;
+    for (int i = lane; i < l; i += kWave) {
+      const float r = (i > 0 ? fabsf(ee[i - 1]) : 0.f) + (i + 1 < l ? fabsf(ee[i]) : 0.f);
+      lo = fminf(lo, dd[i] - r);
+      hi = fmaxf(hi, dd[i] + r);
+      tn = fmaxf(tn, fabsf(dd[i]) + r);
+      const float e2 = i > 0 ? ee[i - 1] * ee[i - 1] : 0.f;
+      e2s[i] = e2;
+      emax = fmaxf(emax, e2);
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, o, kWave));
+      hi = fmaxf(hi, __shfl_xor(hi, o, kWave));
+      emax = fmaxf(emax, __shfl_xor(emax, o, kWave));
+      tn = fmaxf(tn, __shfl_xor(tn, o, kWave));
+    }
+    if (lane == 0) {
+      const float span = fmaxf(hi - lo, 1e-30f);
+      s_lo = lo - 1e-6f * span;
+      s_hi = hi + 1e-6f * span;
+      s_piv = 1.1754944e-38f * fmaxf(1.f, emax);
+      s_nrm = fmaxf(tn, 1e-30f);
+    }
+  }
+  __syncthreads();
+  // 2. multisection: the r-th largest eigenvalue lies where the count of
+  // eigenvalues below x passes l - 1 - r
+  {
+    const int g = tid / kEigG, gl = tid % kEigG;
+    const float piv = s_piv;
+    for (int r = g; r < kk; r += kEigT / kEigG) {
+      const int target = l - 1 - r;
+      float lo = s_lo, hi = s_hi;
+      for (int it = 0; it < kEigPass; ++it) {
+        const float x = lo + (hi - lo) * float(gl + 1) / float(kEigG + 1);
+        float q = dd[0] - x;
+        int c = q < 0.f;
+        for (int i0 = 0; i0 < l; i0 += 4) {
+          const float4 D = *reinterpret_cast<const float4*>(dd + i0);
+          const float4 E = *reinterpret_cast<const float4*>(e2s + i0);
+          const float dv[4] = {D.x, D.y, D.z, D.w}, ev[4] = {E.x, E.y, E.z, E.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u;
+            if (i >= 1 && i < l) {
+              if (fabsf(q) < piv) q = -piv;
+              q = (dv[u] - x) - ev[u] * __builtin_amdgcn_rcpf(q);
+              c += q < 0.f;
+            }
+          }
+        }
+        // the group's flags (count <= target) are a prefix; its length picks
+        // the sub-bracket, and every lane recomputes its ends the way the
+        // lanes computed their points
+        const uint64_t bal = __ballot(c <= target);
+        const uint32_t mine = uint32_t(bal >> ((lane / kEigG) * kEigG)) & ((1u << kEigG) - 1);
+        const int qn = __builtin_ctz(~mine);
+        const float xl = lo + (hi - lo) * float(qn) / float(kEigG + 1);
+        const float xh = lo + (hi - lo) * float(qn + 1) / float(kEigG + 1);
+        lo = qn > 0 ? xl : lo;
+        hi = qn < kEigG ? xh : hi;
+      }
+      if (gl == 0) lam[r] = 0.5f * (lo + hi);
+    }
+  }
+  __syncthreads();
+  // clusters: j continues the cluster of j-1 when their gap is below
+  // 1e-3 |T|
+  if (tid == 0) {
+    const float ortol = 1e-3f * s_nrm;
+    cst[0] = 0;
+    for (int j = 1; j < kk; ++j) cst[j] = (lam[j - 1] - lam[j] < ortol) ? cst[j - 1] : j;
+  }
+  __syncthreads();
+  int cmax = 1;
+  for (int jj = 1; jj < kk; ++jj) cmax = max(cmax, jj - cst[jj] + 1);
+  // 3. inverse iteration, cw eigenvalues per pass
+  const float eps3 = 1.1920929e-7f * s_nrm;   // pivot floor and separation of equal eigenvalues
+  for (int j0 = 0; j0 < kk; j0 += cw) {
+    const int jc = tid, j = j0 + jc;
+    const bool mine = jc < cw && j < kk;
+    if (mine) {
+      float lj = lam[j];
+      // equal eigenvalues get distinct shifts (LAPACK's stein does the same)
+      if (j > cst[j]) lj = fminf(lj, lam[j - 1] - 10.f * eps3 * float(j - cst[j]));
+      // Gaussian elimination with partial pivoting of T - lj I; the rows
+      // kept in registers are the current pivot row (ca, cb)
+      float ca = dd[0] - lj, cb = l > 1 ? ee[0] : 0.f;
+#pragma unroll 4
+      for (int i = 0; i + 1 < l; ++i) {
+        const float cl = ee[i], na = dd[i + 1] - lj, nb = i + 2 < l ? ee[i + 1] : 0.f;
+        const bool sw = fabsf(ca) < fabsf(cl);
+        const float pv = sw ? cl : (fabsf(ca) >= eps3 ? ca : (ca >= 0.f ? eps3 : -eps3));
+        const float rp = __builtin_amdgcn_rcpf(pv);
+        const float mlt = (sw ? ca : cl) * rp;
+        FA[i * cw + jc] = rp;
+        FB[i * cw + jc] = sw ? na : cb;
+        FC[i * cw + jc] = sw ? nb : 0.f;
+        FM[i * cw + jc] = mlt;
+        FS[i * cw + jc] = sw ? 1.f : 0.f;
+        const float nca = sw ? cb - mlt * na : na - mlt * cb;
+        cb = sw ? -mlt * nb : nb;
+        ca = nca;
+      }
+      if (fabsf(ca) < eps3) ca = ca >= 0.f ? eps3 : -eps3;
+      FA[(l - 1) * cw + jc] = __builtin_amdgcn_rcpf(ca);
+      // start vector: a fixed pseudo-random vector
+      for (int i = 0; i < l; ++i) {
+        uint32_t hsh = uint32_t(i) * 2654435761u ^ uint32_t(j + 1) * 2246822519u;
+        hsh ^= hsh >> 15;
+        hsh *= 2654435761u;
+        hsh ^= hsh >> 13;
+        Z[i * kk + j] = 1.f + 0.5f * (float(hsh & 0xffffu) / 65535.f - 0.5f);
+      }
+    }
+    for (int it = 0; it < kEigSolves; ++it) {
+      if (mine) {
+        // row operations of the elimination on the right side, then back
+        // substitution and the 2-norm
+        float cur = Z[j];
+#pragma unroll 4
+        for (int i = 0; i + 1 < l; ++i) {
+          const float nx = Z[(i + 1) * kk + j];
+          const float mlt = FM[i * cw + jc];
+          const bool sw = FS[i * cw + jc] != 0.f;
+          Z[i * kk + j] = sw ? nx : cur;
+          cur = sw ? cur - mlt * nx : nx - mlt * cur;
+        }
+        float z2 = cur * FA[(l - 1) * cw + jc], z1 = 0.f;
+        Z[(l - 1) * kk + j] = z2;
+        float nrm2 = z2 * z2;
+#pragma unroll 4
+        for (int i = l - 2; i >= 0; --i) {
+          const float zi = (Z[i * kk + j] - FB[i * cw + jc] * z2 - FC[i * cw + jc] * z1) * FA[i * cw + jc];
+          Z[i * kk + j] = zi;
+          nrm2 += zi * zi;
+          z1 = z2;
+          z2 = zi;
+        }
+        const float inv = 1.f / sqrtf(nrm2);
+        for (int i = 0; i < l; ++i) Z[i * kk + j] *= inv;
+      }
+      // modified Gram-Schmidt in clusters, by position in the cluster; one
+      // wave per vector, entries i = lane, lane + 64 in registers
+      for (int pos = 1; pos < cmax; ++pos) {
+        __syncthreads();
+        for (int jv = j0 + wave; jv < min(kk, j0 + cw); jv += kEigT / kWave) {
+          if (jv - cst[jv] != pos) continue;   // uniform in the wave
+          float z0 = lane < l ? Z[lane * kk + jv] : 0.f;
+          float z1 = lane + 64 < l ? Z[(lane + 64) * kk + jv] : 0.f;
+          for (int c = cst[jv]; c < jv; ++c) {
+            const float q0 = lane < l ? Z[lane * kk + c] : 0.f;
+            const float q1 = lane + 64 < l ? Z[(lane + 64) * kk + c] : 0.f;
+            const float dot = wave_sum_f(z0 * q0 + z1 * q1);
+            z0 -= dot * q0;
+            z1 -= dot * q1;
+          }
+          const float inv = 1.f / sqrtf(wave_sum_f(z0 * z0 + z1 * z1));
+          if (lane < l) Z[lane * kk + jv] = z0 * inv;
+          if (lane + 64 < l) Z[(lane + 64) * kk + jv] = z1 * inv;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // 4. back-transformation: column c of Z by the 16 lanes of group c,
+  // rows sl + 16u in registers; the next reflector's entries are loaded
+  // while the current one is applied
+  {
+    const int sl = tid & 15;
+    for (int c = tid >> 4; c < kk; c += kEigT / 16) {
+      float z[kZ], vn[kZ];
+#pragma unroll
+      for (int u = 0; u < kZ; ++u) {
+        const int i = sl + 16 * u;
+        z[u] = i < l ? Z[i * kk + c] : 0.f;
+      }
+      float tn = 0.f;
+      if (l >= 3) {
+        const int k = l - 3;
+        tn = tau[k];
+#pragma unroll
+        for (int u = 0; u < kZ; ++u) {
+          const int i = sl + 16 * u;
+          vn[u] = (i > k && i < l) ? A[i * l + k] : 0.f;
+        }
+      }
+      for (int k = l - 3; k >= 0; --k) {
+        float v[kZ];
+#pragma unroll
+        for (int u = 0; u < kZ; ++u) v[u] = vn[u];
+        const float t = tn;
+        if (k > 0) {
+          tn = tau[k - 1];
+#pragma unroll
+          for (int u = 0; u < kZ; ++u) {
+            const int i = sl + 16 * u;
+            vn[u] = (i > k - 1 && i < l) ? A[i * l + (k - 1)] : 0.f;
+          }
+        }
+        float sdot = 0.f;
+#pragma unroll
+        for (int u = 0; u < kZ; ++u) sdot += v[u] * z[u];
+        for (int o = 8; o >= 1; o >>= 1) sdot += __shfl_xor(sdot, o, kWave);
+        const float f = t * sdot;
+#pragma unroll
+        for (int u = 0; u < kZ; ++u) z[u] -= f * v[u];
+      }
+      double* Ub = Ut + int64_t(b) * LP * kk;
+#pragma unroll
+      for (int u = 0; u < kZ; ++u) {
+        const int i = sl + 16 * u;
+        if (i < l) Ub[int64_t(i) * kk + c] = double(z[u]);
+      }
+      if (sl == 0) sig[int64_t(b) * kk + c] = sqrt(fmax(double(lam[c]), 0.0));
+    }
   }
 }
 
@@ -1113,15 +1617,19 @@ static int launch_gram(hgl_handle* h, Rsvd& R, const DevBuf& Yb, hipStream_t s) 
 template <class TY, class TST>
 static int cholqr(hgl_handle* h, Rsvd& R, hipStream_t s, int passes) {
   const int n_items = int(R.item_b.size());
-  const size_t lds_chol = sizeof(double) * 2 * R.l * R.l;
-  HGL_TRY(allow_lds(k_chol_inv, lds_chol));
+  const size_t lds_chol = sizeof(double) * R.l * R.l;
   prof_begin(h, kProfQr, s);
   for (int pass = 0; pass < passes; ++pass) {
     DevBuf& in = pass == 0 ? R.Y : R.S;
     DevBuf& out = pass == 0 ? R.S : R.Y;
     HGL_TRY(launch_gram<TY>(h, R, in, s));
-    launch(h, -1, k_chol_inv, dim3(R.nb), dim3(kDense), lds_chol, s, R.bm, R.item0_d, R.Gpart.as<double>(),
-                       R.Li.as<double>(), R.fail.as<int32_t>());
+    HGL_TRY(with_lp(R.LP, [&](auto c) -> int {
+      constexpr int NX = decltype(c)::value / 16;
+      HGL_TRY(allow_lds(k_chol_inv<NX>, lds_chol));
+      launch(h, -1, k_chol_inv<NX>, dim3(R.nb), dim3(kCholT), lds_chol, s, R.bm, R.item0_d, R.Gpart.as<double>(),
+             R.Li.as<double>(), R.fail.as<int32_t>());
+      return HGL_OK;
+    }));
     HGL_TRY(with_lp(R.LP, [&](auto c) {
       constexpr int LP = decltype(c)::value;
       launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, in.as<TY>(),
@@ -1221,15 +1729,34 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
   prof_begin(h, kProfEig, s);
   HGL_TRY(launch_gram<TY>(h, R, R.Y, s));
   const int half = (R.l + (R.l & 1)) / 2;
-  // FP32 sweeps for a BF16 sketch, FP64 otherwise
-  const size_t tj = R.f64 ? sizeof(double) : sizeof(float);
-  const size_t lds_j = tj * (2 * R.l * R.l + 2 * half) + sizeof(int) * (2 * half + R.l);
-  const bool wide = half * (half + 1) / 2 + half * half > 3 * kDense;
-  auto jac = R.f64 ? (wide ? &k_jacobi<4, double> : &k_jacobi<3, double>)
-                   : (wide ? &k_jacobi<4, float> : &k_jacobi<3, float>);
-  HGL_TRY(allow_lds(jac, lds_j));
-  launch(h, -1, jac, dim3(R.nb), dim3(kDense), lds_j, s, R.bm, R.item0_d, R.Gpart.as<double>(), R.sig.as<double>(),
-                     R.Ut.as<double>(), 30);
+  if (!R.f64) {
+    // BF16 sketch: FP32 tridiagonal eigensolver
+    auto lds_eig = [&](int cw) {
+      return sizeof(float) * (size_t(R.l) * R.l + size_t(R.l) * R.kk + 5 * size_t(R.l) * cw);
+    };
+    const int cw = lds_eig(64) <= 150 * 1024 ? 64 : 32;
+    HGL_TRY(allow_lds(k_eig_tridiag, lds_eig(cw)));
+    launch(h, -1, k_eig_tridiag, dim3(R.nb), dim3(kEigT), lds_eig(cw), s, R.bm, R.item0_d, R.Gpart.as<double>(),
+           R.sig.as<double>(), R.Ut.as<double>(), cw);
+  } else {
+    // FP64 sketch: FP64 cyclic Jacobi, A double-buffered where it fits in
+    // LDS; 1024 threads while three tasks per thread cover a round (l <= 90),
+    // 512 beyond (more tasks per thread without register spills)
+    const int ntask = half + half * (half - 1) / 2 + (R.l + 1) / 2 * half;
+    const int nt = ntask <= 3 * 1024 ? 1024 : 512;
+    auto lds_jac = [&](int copies) {
+      const size_t mats = (sizeof(double) * copies * R.l * R.l + 4 * R.l + 15) / 16 * 16;
+      return mats + (nt / kWave) * half * sizeof(JacPair<double>);
+    };
+    const bool db = lds_jac(3) <= 160 * 1024;
+    const size_t lds_j = lds_jac(db ? 3 : 2);
+    using JacFn = void (*)(BlockMeta, const int32_t*, const double*, double*, double*, int);
+    JacFn jac = nt == 1024 ? (db ? &k_jacobi<1024, 3, double, true> : &k_jacobi<1024, 3, double, false>)
+                           : (db ? &k_jacobi<512, 7, double, true> : &k_jacobi<512, 7, double, false>);
+    HGL_TRY(allow_lds(jac, lds_j));
+    launch(h, -1, jac, dim3(R.nb), dim3(nt), lds_j, s, R.bm, R.item0_d, R.Gpart.as<double>(), R.sig.as<double>(),
+           R.Ut.as<double>(), 30);
+  }
   HGL_HIP(hipGetLastError());
   prof_end(h, s);
   return HGL_OK;
