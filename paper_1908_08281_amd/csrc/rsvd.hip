@@ -303,16 +303,6 @@ __device__ __forceinline__ void stage_rows(double* lds, int lds_ld, const TS* __
   }
 }
 
-__device__ __forceinline__ void pair_of(int p, int l, int& i, int& j) {
-  int ii = 0, rem = p;
-  while (rem >= l - ii) {
-    rem -= l - ii;
-    ++ii;
-  }
-  i = ii;
-  j = ii + rem;
-}
-
 // t -> (i, m) with m <= i, row-major over a lower triangle.
 __device__ __forceinline__ void tri_of(int t, int& i, int& m) {
   int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
@@ -382,160 +372,236 @@ __global__ __launch_bounds__(kBlock) void k_gram_tiles(BlockMeta bm, const TY* _
 // single pass of independent updates between two barriers.
 constexpr int kDense = 1024;
 
-// A (l x l in LDS, row-major) <- G_b: the block's tile partials summed in tile
-// order (deterministic), upper triangle mirrored.  NT threads.
+// Pair index p of the packed upper triangle (row-major, row m holds
+// columns m .. l-1) -> (m, j): m is the largest row with
+// m l - m(m-1)/2 <= p, from the quadratic's root, then corrected.
+__device__ __forceinline__ void pair_rc(int p, int l, int& m, int& j) {
+  const float bq = float(2 * l + 1);
+  int r = int((bq - sqrtf(bq * bq - 8.0f * float(p))) * 0.5f);
+  r = max(0, min(r, l - 1));
+  while (r > 0 && r * l - r * (r - 1) / 2 > p) --r;
+  while (r + 1 < l && (r + 1) * l - (r + 1) * r / 2 <= p) ++r;
+  m = r;
+  j = r + (p - (r * l - r * (r - 1) / 2));
+}
+
+// G_b = the sum of the block's tile partials in tile order (deterministic),
+// written over the block's first partial; one thread per (pair, block)
+// across the chip, so the dense per-block kernels read one packed triangle.
+__global__ __launch_bounds__(256) void k_gram_reduce(BlockMeta bm, const int32_t* __restrict__ item0,
+                                                     double* __restrict__ part) {
+  const int l = bm.l, npairs = l * (l + 1) / 2;
+  const int p = blockIdx.x * 256 + threadIdx.x, b = blockIdx.y;
+  if (p >= npairs) return;
+  const int i0 = item0[b], i1 = item0[b + 1];
+  double sacc = 0.0;
+#pragma unroll 8
+  for (int it = i0; it < i1; ++it) sacc += part[int64_t(it) * npairs + p];
+  part[int64_t(i0) * npairs + p] = sacc;
+}
+
+// A (l x l in LDS, row-major, leading dimension ld) <- G_b, reduced by
+// k_gram_reduce, mirrored.  NT threads.
 template <int NT, class TA>
 __device__ __forceinline__ void stage_gram(const BlockMeta& bm, const int32_t* __restrict__ item0,
-                                           const double* __restrict__ part, int b, TA* A) {
+                                           const double* __restrict__ part, int b, TA* A, int ld = -1) {
   const int l = bm.l, npairs = l * (l + 1) / 2;
-  const int i0 = item0[b], i1 = item0[b + 1];
+  if (ld < 0) ld = l;
+  const double* Gb = part + int64_t(item0[b]) * npairs;
   for (int p = threadIdx.x; p < npairs; p += NT) {
-    double sacc = 0.0;
-#pragma unroll 8
-    for (int it = i0; it < i1; ++it) sacc += part[int64_t(it) * npairs + p];
-    int i, j;
-    pair_of(p, l, i, j);
-    A[i * l + j] = TA(sacc);
-    A[j * l + i] = TA(sacc);
+    const double g = Gb[p];
+    int m, j;
+    pair_rc(p, l, m, j);
+    A[m * ld + j] = TA(g);
+    A[j * ld + m] = TA(g);
   }
 }
 
-// Calls f(std::integral_constant<int, I>{}) for I = 0 .. N-1 in order.
-template <int I, int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
+// Lane src's value of v (src uniform), both halves by v_readlane.
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const uint64_t u = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), src);
+  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), src);
+  return __longlong_as_double((int64_t(hi) << 32) | lo);
+}
+
+// 16 x 16 block products on LDS by one wave: lane (r, c4) = (lane / 4,
+// lane % 4) accumulates C[r][4 c4 + t], t < 4, of
+// sum_k A[r][k] * (TB ? B[4 c4 + t][k] : B[k][4 c4 + t]).
+template <bool TB>
+__device__ __forceinline__ void blk_mm(double (&acc)[4], const double* __restrict__ Ab,
+                                       const double* __restrict__ Bb, int ld, int r, int c0) {
+#pragma unroll
+  for (int kc = 0; kc < 16; kc += 4) {
+    double av[4], bv[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) av[u] = Ab[r * ld + kc + u];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bv[t][u] = TB ? Bb[(c0 + t) * ld + kc + u] : Bb[(kc + u) * ld + c0 + t];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[t] += av[u] * bv[t][u];
   }
+}
+
+// A wave's LDS accesses complete in issue order; this keeps the compiler
+// from moving them across the point either.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // L^-1 of the Cholesky factor of G_b = Y_b' Y_b (summed from the Gram tile
-// partials), written to Li (LP x LP, lower, zero padded).
-// One elimination on [G | I] with unscaled pivots: step j subtracts
-// A[i][j] A[m][j] / A[j][j] from the trailing triangle of G (j < m <= i) and
-// A[i][j] B[j][c] / A[j][j] from the rows i > j of B (c <= j).  Afterwards
-// L[i][j] = A[i][j] / sqrt(A[j][j]) and L^-1[i][c] = B[i][c] / sqrt(A[i][i]).
-// 256 threads; thread (ti, tm) = (tid % 16, tid / 16) keeps the entries
-// (ti + 16x, tm + 16y), x, y < NX = LP/16, of both matrices in registers (a
-// 2-D cyclic layout: the shrinking trailing triangle stays spread over all
-// threads).  The steps run in chunks of 16, one unrolled body per chunk, so
-// that a body holds only the row and column groups still live in it (rows
-// and A columns x, y >= chunk, A lower blocks y <= x, B columns y <= chunk).
-// Step j reads column j of A, the pivot's reciprocal and row j of B, which
-// their owners publish at the end of step j-1 into one of two alternating
-// LDS slots; each step is one barrier.
+// partials), written to Li (LP x LP, lower, zero padded).  G_b is padded to
+// N = 16 NX = LP with the identity and factored by 16 x 16 blocks
+// (right-looking, Golub & Van Loan, alg. 4.2.2 by blocks), 1024 threads:
+//   for each block column k: one wave factors A_kk = L_kk L_kk' and forms
+//   X_kk = L_kk^-1 in registers (an elimination on [A_kk | I] with unscaled
+//   pivots, one row per lane, then L[r][c] = A[r][c] / sqrt(piv_c),
+//   L^-1[r][c] = B[r][c] / sqrt(piv_r));
+//   one wave per block row below forms L_ik = A_ik L_kk^-T, and one wave
+//   per block left of the diagonal finishes X_kj = -X_kk W_kj; then one wave
+//   per lower block pair updates A_ij -= L_ik L_jk', and one per block
+//   X_ij (i > k >= j) accumulates W_ij += L_ik X_kj, so that
+//   X_ij = -L_ii^-1 sum_{k=j}^{i-1} L_ik X_kj (the blocks of L^-1) are done
+//   with the factorisation.  Three barriers per block column.
 // A non-positive or non-finite pivot triggers one retry with the shift
 // 11 (n l + l (l+1)) u trace(G) (shifted CholQR, Fukaya et al. 2020); a
 // second failure sets fail[b].
-constexpr int kCholT = 256;
+constexpr int kCholT = 1024;
 template <int NX>
 __global__ __launch_bounds__(kCholT) void k_chol_inv(BlockMeta bm, const int32_t* __restrict__ item0,
                                                      const double* __restrict__ part, double* __restrict__ Li,
                                                      int32_t* __restrict__ fail) {
-  extern __shared__ double G[];   // l x l, row-major
-  __shared__ double colA[2][kMaxLP], rowB[2][kMaxLP], rinv[2], dg[kMaxLP];
+  constexpr int N = 16 * NX;
+  constexpr int LD = N + 1;        // odd row stride: the 16 rows of a block fall in distinct banks
+  extern __shared__ double sm[];
+  double* const A = sm;            // N x N (stride LD): G, then L in the lower blocks
+  double* const X = sm + N * LD;   // N x N (stride LD): L^-1 in the lower blocks
   __shared__ double s_tr;
-  const int b = blockIdx.x, tid = threadIdx.x;
-  const int ti = tid & 15, tm = tid >> 4;
+  __shared__ int s_bad;
+  const int b = blockIdx.x, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int r = lane >> 2, c0 = (lane & 3) * 4;
   const int l = bm.l, LP = bm.LP;
   const int n = bm.off[b + 1] - bm.off[b];
-  stage_gram<kCholT>(bm, item0, part, b, G);
-  __syncthreads();
-  double a[NX][NX], bx[NX][NX];
-  // The owners of column s of A and of row s of B write them to slot s & 1
-  // (whole register groups, no per-entry tests: the entries above the
-  // diagonal of B and the padding rows are exact zeros, and whatever lands
-  // in rows < s of the column is masked by its readers); the pivot's owner
-  // adds its reciprocal.  s lies in group X0 or X0 + 1.
-  auto publish = [&](int s, auto x0c) {
-    constexpr int X0 = decltype(x0c)::value;
-    const int slot = s & 1, rs = s & 15;
-    const bool up = (s >> 4) > X0;
-    if (tm == rs) {
-#pragma unroll
-      for (int x = X0; x < NX; ++x) {
-        double v = a[x][X0];
-        if constexpr (X0 + 1 < NX) {
-          if (X0 + 1 <= x) v = up ? a[x][X0 + 1] : v;
-        }
-        colA[slot][ti + 16 * x] = v;
-        if (ti + 16 * x == s) {
-          dg[s] = v;
-          rinv[slot] = 1.0 / v;
-        }
-      }
-    }
-    if (ti == rs) {
-#pragma unroll
-      for (int y = 0; y < NX; ++y) {
-        double v = bx[X0][y];
-        if constexpr (X0 + 1 < NX) v = up ? bx[X0 + 1][y] : v;
-        rowB[slot][tm + 16 * y] = v;
-      }
-    }
-  };
   for (int attempt = 0;; ++attempt) {
-    double shift = 0.0;
+    // G, the identity on the padding; X (the W sums) zero
+    for (int q = tid; q < N * N; q += kCholT) {
+      const int i = q / N, j = q % N;
+      if (i >= l || j >= l) A[i * LD + j] = i == j ? 1.0 : 0.0;
+      X[i * LD + j] = 0.0;
+    }
+    stage_gram<kCholT>(bm, item0, part, b, A, LD);
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
     if (attempt > 0) {
+      // the retry's shift on the diagonal of G
       if (tid < kWave) {
         double t = 0.0;
-        for (int i = tid; i < l; i += kWave) t += G[i * l + i];
+        for (int i = tid; i < l; i += kWave) t += A[i * LD + i];
         for (int o2 = 32; o2 >= 1; o2 >>= 1) t += __shfl_xor(t, o2, kWave);
         if (tid == 0) s_tr = t;
       }
       __syncthreads();
-      shift = 11.0 * (double(n) * l + double(l) * (l + 1)) * 1.1102230246251565e-16 * s_tr;
+      const double shift = 11.0 * (double(n) * l + double(l) * (l + 1)) * 1.1102230246251565e-16 * s_tr;
+      if (tid < l) A[tid * LD + tid] += shift;
+      __syncthreads();
     }
+    for (int kb = 0; kb < NX; ++kb) {
+      double* const Akk = A + kb * 16 * LD + kb * 16;
+      if (wave == 0) {
+        // diagonal block, one row per lane (rows r = lane % 16; the four
+        // copies of a row compute alike): the trailing block stays
+        // symmetric, so column j is row j, read from lane j; likewise row j
+        // of B
+        const int rr = lane & 15;
+        double a[16], x[16];
 #pragma unroll
-    for (int x = 0; x < NX; ++x)
+        for (int c = 0; c < 16; ++c) {
+          a[c] = Akk[rr * LD + c];
+          x[c] = rr == c ? 1.0 : 0.0;
+        }
+        double rs_r = 0.0;
+        bool ok = true;
 #pragma unroll
-      for (int y = 0; y < NX; ++y) {
-        const int i = ti + 16 * x, m = tm + 16 * y;
-        a[x][y] = (i < l && m <= i) ? G[i * l + m] + (i == m ? shift : 0.0) : 0.0;
-        bx[x][y] = (i < l && m == i) ? 1.0 : 0.0;
+        for (int j = 0; j < 16; ++j) {
+          // (no early exit, so the loop unrolls and the rows stay in
+          // registers; a failed pivot makes the result unused)
+          const double piv = lane_read(a[j], j);
+          ok = ok && piv > 0.0 && isfinite(piv);
+          // 1/piv: hardware reciprocal and two Newton steps
+          double inv = __builtin_amdgcn_rcp(piv);
+          inv = fma(inv, fma(-piv, inv, 1.0), inv);
+          inv = fma(inv, fma(-piv, inv, 1.0), inv);
+          const double rsj = 1.0 / sqrt(piv);
+          if (rr == j) rs_r = rsj;
+          // column j of L is final: store it (frees a[j])
+          if (lane < 16) Akk[rr * LD + j] = j <= rr ? a[j] * rsj : 0.0;
+          const double cr = rr > j ? a[j] * inv : 0.0;
+#pragma unroll
+          for (int c = j + 1; c < 16; ++c) a[c] = fma(-cr, lane_read(a[c], j), a[c]);
+#pragma unroll
+          for (int c = 0; c <= j; ++c) x[c] = fma(-cr, lane_read(x[c], j), x[c]);
+        }
+        if (!ok) {
+          if (lane == 0) s_bad = 1;
+        } else if (lane < 16) {
+          double* const Xkk = X + kb * 16 * LD + kb * 16;
+#pragma unroll
+          for (int c = 0; c < 16; ++c) Xkk[rr * LD + c] = x[c] * rs_r;
+        }
       }
-    publish(0, std::integral_constant<int, 0>{});
-    __syncthreads();
-    bool ok = true;
-    static_for<0, NX>([&](auto jbc) {
-      constexpr int JB = decltype(jbc)::value;
-      if (!ok) return;
-      const int j1 = min(l, 16 * JB + 16);
-      for (int j = 16 * JB; j < j1; ++j) {
-        const int slot = j & 1;
-        // every thread reads the same pivot, so the exit is uniform
-        const double piv = colA[slot][j];
-        if (!(piv > 0.0) || !isfinite(piv)) {
-          ok = false;
-          break;
-        }
-        const double inv = rinv[slot];
-        // ci = 0 for rows <= j (their B rows are final).  Not masked: cm in
-        // columns <= j (those A entries were published and are not read
-        // again), rb in columns > j (zeros above B's diagonal), and the
-        // padding rows (zero in G, so zero throughout).  Entries above the
-        // diagonal of A are never read.
-        double ci[NX], cm[NX], rb[NX];
+      __syncthreads();
+      if (s_bad) break;   // uniform
+      const int nr = NX - kb - 1;
+      const double* const Xkk = X + kb * 16 * LD + kb * 16;
+      if (wave < nr) {
+        // panel: L_ik = A_ik L_kk^-T, one wave per block row below
+        const int ib = kb + 1 + wave;
+        double* const Aik = A + ib * 16 * LD + kb * 16;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        blk_mm<true>(acc, Aik, Xkk, LD, r, c0);
 #pragma unroll
-        for (int x = JB; x < NX; ++x) {
-          const int i = ti + 16 * x;
-          ci[x] = i > j ? colA[slot][i] * inv : 0.0;
-          cm[x] = colA[slot][tm + 16 * x];
-        }
+        for (int t = 0; t < 4; ++t) Aik[r * LD + c0 + t] = acc[t];
+      } else if (wave < nr + kb) {
+        // X_kj = -X_kk W_kj, one wave per block left of the diagonal
+        double* const Xkj = X + kb * 16 * LD + (wave - nr) * 16;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        blk_mm<false>(acc, Xkk, Xkj, LD, r, c0);
 #pragma unroll
-        for (int y = 0; y <= JB; ++y) rb[y] = rowB[slot][tm + 16 * y];
-#pragma unroll
-        for (int x = JB; x < NX; ++x) {
-#pragma unroll
-          for (int y = JB; y <= x; ++y) a[x][y] -= ci[x] * cm[y];
-#pragma unroll
-          for (int y = 0; y <= JB; ++y) bx[x][y] -= ci[x] * rb[y];
-        }
-        if (j + 1 < l) publish(j + 1, jbc);
-        __syncthreads();
+        for (int t = 0; t < 4; ++t) Xkj[r * LD + c0 + t] = -acc[t];
       }
-    });
-    if (ok) break;
+      __syncthreads();
+      // trailing update of the lower blocks (one wave per block pair), and
+      // W_ij += L_ik X_kj for the blocks of L^-1 below row k
+      {
+        const int npair = nr * (nr + 1) / 2, nw = nr * (kb + 1);
+        for (int pw = wave; pw < npair + nw; pw += kCholT / kWave) {
+          double acc[4] = {0.0, 0.0, 0.0, 0.0};
+          if (pw < npair) {
+            int ii, jj;
+            tri_of(pw, ii, jj);
+            const int ib = kb + 1 + ii, jb = kb + 1 + jj;
+            double* const Aij = A + ib * 16 * LD + jb * 16;
+            blk_mm<true>(acc, A + ib * 16 * LD + kb * 16, A + jb * 16 * LD + kb * 16, LD, r, c0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) Aij[r * LD + c0 + t] -= acc[t];
+          } else {
+            const int q = pw - npair, ib = kb + 1 + q / (kb + 1), jb = q % (kb + 1);
+            double* const Wij = X + ib * 16 * LD + jb * 16;
+            blk_mm<false>(acc, A + ib * 16 * LD + kb * 16, X + kb * 16 * LD + jb * 16, LD, r, c0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) Wij[r * LD + c0 + t] += acc[t];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (!s_bad) break;
     if (attempt == 1) {
       if (tid == 0) fail[b] = 1;
       return;
@@ -543,13 +609,10 @@ __global__ __launch_bounds__(kCholT) void k_chol_inv(BlockMeta bm, const int32_t
     __syncthreads();
   }
   double* Lb = Li + int64_t(b) * LP * LP;
-#pragma unroll
-  for (int x = 0; x < NX; ++x)
-#pragma unroll
-    for (int y = 0; y < NX; ++y) {
-      const int i = ti + 16 * x, c = tm + 16 * y;
-      Lb[i * LP + c] = (i < l && c <= i) ? bx[x][y] / sqrt(dg[i]) : 0.0;
-    }
+  for (int q = tid; q < LP * LP; q += kCholT) {
+    const int i = q / LP, c = q % LP;
+    Lb[q] = (i < l && c <= i) ? X[i * LD + c] : 0.0;
+  }
 }
 
 // Li <- identity on each block's l x l corner (zero elsewhere in LP x LP):
@@ -1604,11 +1667,14 @@ static int launch_gemm(hgl_handle* h, Rsvd& R, hipStream_t s) {
   return HGL_OK;
 }
 
-// Gram tile partials of Yb (summed by the consuming kernel).
+// Gram tile partials of Yb, then each block's sum over its first partial.
 template <class TY>
 static int launch_gram(hgl_handle* h, Rsvd& R, const DevBuf& Yb, hipStream_t s) {
   const int n_items = int(R.item_b.size());
   launch(h, -1, k_gram_tiles<TY>, dim3(n_items), dim3(kBlock), 0, s, R.bm, Yb.as<TY>(), R.Gpart.as<double>());
+  const int npairs = R.l * (R.l + 1) / 2;
+  launch(h, -1, k_gram_reduce, dim3((npairs + 255) / 256, R.nb), dim3(256), 0, s, R.bm, R.item0_d,
+         R.Gpart.as<double>());
   HGL_HIP(hipGetLastError());
   return HGL_OK;
 }
@@ -1617,7 +1683,7 @@ static int launch_gram(hgl_handle* h, Rsvd& R, const DevBuf& Yb, hipStream_t s) 
 template <class TY, class TST>
 static int cholqr(hgl_handle* h, Rsvd& R, hipStream_t s, int passes) {
   const int n_items = int(R.item_b.size());
-  const size_t lds_chol = sizeof(double) * R.l * R.l;
+  const size_t lds_chol = sizeof(double) * 2 * size_t(R.LP) * (R.LP + 1);
   prof_begin(h, kProfQr, s);
   for (int pass = 0; pass < passes; ++pass) {
     DevBuf& in = pass == 0 ? R.Y : R.S;
