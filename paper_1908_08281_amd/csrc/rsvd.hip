@@ -51,50 +51,108 @@ struct BlockMeta {
   const int64_t* yoff;   // [nb] offset of Y/S/ST (elements)
   const int32_t* item_b; // [n_items] block of a 64-row tile
   const int32_t* item_t; // [n_items] tile index within the block
+  const int32_t* pair_b; // [n_pairs] block of a 128-row item (two tiles, or the block's last one)
+  const int32_t* pair_t; // [n_pairs] its first tile index
 };
+
+// Lane src's value of v (src uniform), both halves by v_readlane.
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const uint64_t u = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), src);
+  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), src);
+  return __longlong_as_double((int64_t(hi) << 32) | lo);
+}
+
+// A wave's LDS accesses complete in issue order; this keeps the compiler
+// from moving them across the point either.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // ------------------------------------------------------------ extraction --
 
 // A_bb[u][v] = s_u s_v sum_{e containing u and v} c_e for u, v in block b.
-// One wave per row u: the row is accumulated in LDS, hyperedges of u in
-// increasing id order, members of one hyperedge on distinct lanes (a vertex
-// set has no repeats), so no two lanes update one entry at once.
+// One wave per row u, 8 rows per workgroup; the row is accumulated in LDS
+// (FP32 for a BF16 block, FP64 otherwise).  Lane i loads the metadata of
+// u's i-th hyperedge of a 64-hyperedge chunk (id, c_e, member range); the
+// member loads of four hyperedges at a time are issued together; the row
+// updates are LDS atomic adds issued in hyperedge order, which a wave's LDS
+// applies in issue order, so the sums are deterministic (members of one
+// hyperedge are distinct, so no two lanes of one add touch one entry).
+constexpr int kExW = 8;
 template <class TA>
-__global__ __launch_bounds__(kBlock) void k_extract_blocks(BlockMeta bm, const int32_t* __restrict__ vtx_ptr,
-                                                           const int32_t* __restrict__ vtx_edge,
-                                                           const int32_t* __restrict__ edge_ptr,
-                                                           const int32_t* __restrict__ edge_vtx,
-                                                           const double* __restrict__ s,
-                                                           const double* __restrict__ c, TA* __restrict__ A,
-                                                           int max_nbp) {
-  extern __shared__ double srow[];  // [4][max_nbp]
+__global__ __launch_bounds__(kExW * kWave) void k_extract_blocks(BlockMeta bm, const int32_t* __restrict__ vtx_ptr,
+                                                                 const int32_t* __restrict__ vtx_edge,
+                                                                 const int32_t* __restrict__ edge_ptr,
+                                                                 const int32_t* __restrict__ edge_vtx,
+                                                                 const double* __restrict__ s,
+                                                                 const double* __restrict__ c, TA* __restrict__ A,
+                                                                 int max_nbp) {
+  using TC = std::conditional_t<sizeof(TA) == 2, float, double>;
+  extern __shared__ double srow_raw[];
+  TC* const srow = reinterpret_cast<TC*>(srow_raw);   // [kExW][max_nbp]
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int b = blockIdx.y;
   const int o = bm.off[b], n = bm.off[b + 1] - o, nbp = bm.nbp[b];
-  const int ur = blockIdx.x * 4 + wave;  // row within the padded block
-  if (blockIdx.x * 4 >= nbp) return;
-  double* row = srow + int64_t(wave) * max_nbp;
-  for (int j = lane; j < nbp; j += kWave) row[j] = 0.0;
-  __syncthreads();
+  const int ur = blockIdx.x * kExW + wave;  // row within the padded block
+  if (blockIdx.x * kExW >= nbp) return;
+  TC* row = srow + int64_t(wave) * max_nbp;
+  for (int j = lane; j < nbp; j += kWave) row[j] = TC(0);
+  wave_sync();
   if (ur < n) {
     const int u = o + ur;
-    for (int q = vtx_ptr[u]; q < vtx_ptr[u + 1]; ++q) {
-      const int e = vtx_edge[q];
-      const double ce = c[e];
-      for (int m = edge_ptr[e] + lane; m < edge_ptr[e + 1]; m += kWave) {
-        const int v = edge_vtx[m];
-        if (v >= o && v < o + n) row[v - o] += ce * s[v];
+    const int q0 = vtx_ptr[u], q1 = vtx_ptr[u + 1];
+    for (int qb = q0; qb < q1; qb += kWave) {
+      int eb = 0, en = 0;
+      TC ce = TC(0);
+      if (qb + lane < q1) {
+        const int e = vtx_edge[qb + lane];
+        ce = TC(c[e]);
+        eb = edge_ptr[e];
+        en = edge_ptr[e + 1];
       }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      const int cnt = min(kWave, q1 - qb);
+      for (int i0 = 0; i0 < cnt; i0 += 4) {
+        int vv[4], beg[4], end[4];
+        TC cc[4], sv[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int i = min(i0 + g, cnt - 1);
+          const bool ok = i0 + g < cnt;
+          beg[g] = ok ? __builtin_amdgcn_readlane(eb, i) : 0;
+          end[g] = ok ? __builtin_amdgcn_readlane(en, i) : 0;
+          if constexpr (sizeof(TC) == 4) {
+            cc[g] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ce), i));
+          } else {
+            cc[g] = lane_read(ce, i);
+          }
+          const int m = beg[g] + lane;
+          vv[g] = m < min(end[g], beg[g] + kWave) ? edge_vtx[m] : -1;
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) sv[g] = (vv[g] >= o && vv[g] < o + n) ? TC(s[vv[g]]) : TC(0);
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          if (vv[g] >= o && vv[g] < o + n) atomicAdd(&row[vv[g] - o], cc[g] * sv[g]);
+        // members past the first 64 (large hyperedges), in hyperedge order
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          for (int m = beg[g] + kWave + lane; m < end[g]; m += kWave) {
+            const int v = edge_vtx[m];
+            if (v >= o && v < o + n) atomicAdd(&row[v - o], cc[g] * TC(s[v]));
+          }
+        }
+      }
     }
   }
-  __syncthreads();
+  wave_sync();
   if (ur < nbp) {
     const double su = ur < n ? s[o + ur] : 0.0;
     TA* dst = A + bm.aoff[b] + int64_t(ur) * nbp;
     for (int j = lane; j < nbp; j += kWave) {
-      const double v = su * row[j];
+      const double v = su * double(row[j]);
       if constexpr (sizeof(TA) == 2) dst[j] = f32_to_bf16_rne(float(v));
       else dst[j] = v;
     }
@@ -186,19 +244,23 @@ __global__ void k_sketch_to_st(BlockMeta bm, const uint16_t* __restrict__ omega,
 // S is carried as a pair of BF16 matrices S = S_hi + S_lo (S_lo = the BF16
 // rounding of S - S_hi), so each loaded A fragment feeds two MFMAs and the
 // product keeps about 16 significant bits of S while A_bb stays in BF16.
+constexpr int kGemmT = 512;   // 8 waves: one 128-row item
 template <int LP>
-__global__ __launch_bounds__(kBlock) void k_gemm_bf16(BlockMeta bm, const uint16_t* __restrict__ A,
+__global__ __launch_bounds__(kGemmT) void k_gemm_bf16(BlockMeta bm, const uint16_t* __restrict__ A,
                                                       const uint16_t* __restrict__ ST, int64_t lo_off,
                                                       float* __restrict__ Y) {
   constexpr int NT = LP / 16;
-  const int b = bm.item_b[blockIdx.x], t = bm.item_t[blockIdx.x];
+  const int b = bm.pair_b[blockIdx.x], t = bm.pair_t[blockIdx.x];
   const int nbp = bm.nbp[b];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int r0 = t * 64 + wave * 16;
+  // a block's last tile may be alone in its item: the waves past it only
+  // help stage S'
+  const bool live = r0 < nbp;
   const int li = lane % 16, kq = lane / 16;
-  const uint16_t* Ab = A + bm.aoff[b] + int64_t(r0 + li) * nbp + kq * 8;
-  // S' (hi and lo) is shared by the four waves: stage 128-wide K chunks of it
-  // in LDS (rows padded by 8 elements against bank conflicts)
+  const uint16_t* Ab = A + bm.aoff[b] + int64_t(live ? r0 + li : 0) * nbp + kq * 8;
+  // S' (hi and lo) is shared by the eight waves: stage 128-wide K chunks of
+  // it in LDS (rows padded by 8 elements against bank conflicts)
   constexpr int KC = 128, KP = KC + 8;
   __shared__ uint16_t sst[2 * LP * KP];
   const uint16_t* STb = ST + bm.yoff[b];
@@ -207,19 +269,19 @@ __global__ __launch_bounds__(kBlock) void k_gemm_bf16(BlockMeta bm, const uint16
   for (int n = 0; n < NT; ++n) acc[n] = floatx4{0.f, 0.f, 0.f, 0.f};
   // software pipeline over 128-wide K chunks: the next chunk's A fragments
   // and S' segments are loaded into registers while this chunk's MFMAs run
-  // (compile-time counts: 2 LP KC/8 segments over kBlock threads, segments
-  // past the chunk's width skipped)
-  constexpr int SEGS = KC / 8, NQ = 2 * LP * SEGS / kBlock;
-  static_assert(2 * LP * SEGS % kBlock == 0, "copy loop");
+  // (compile-time counts: 2 LP KC/8 segments over the workgroup's threads,
+  // segments past the chunk's width skipped)
+  constexpr int SEGS = KC / 8, NQ = 2 * LP * SEGS / kGemmT;
+  static_assert(2 * LP * SEGS % kGemmT == 0, "copy loop");
   bf16x8 a[KC / 32], v[NQ];
   auto fetch = [&](int k0) {
     const int kc = min(KC, nbp - k0);   // 64 or 128 (nbp is a multiple of 64)
 #pragma unroll
     for (int ks = 0; ks < KC / 32; ++ks)
-      if (ks < kc / 32) a[ks] = *reinterpret_cast<const bf16x8*>(Ab + k0 + ks * 32);
+      if (live && ks < kc / 32) a[ks] = *reinterpret_cast<const bf16x8*>(Ab + k0 + ks * 32);
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
-      const int q = threadIdx.x + u * kBlock;
+      const int q = threadIdx.x + u * kGemmT;
       const int half = q / (LP * SEGS), rem = q - half * (LP * SEGS);
       const int j = rem / SEGS, sg = rem - j * SEGS;
       if (sg < kc / 8) v[u] = *reinterpret_cast<const bf16x8*>(STb + half * lo_off + int64_t(j) * nbp + k0 + sg * 8);
@@ -232,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm_bf16(BlockMeta bm, const uint16
     __syncthreads();  // the previous chunk's MFMAs are done with sst
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
-      const int q = threadIdx.x + u * kBlock;
+      const int q = threadIdx.x + u * kGemmT;
       const int half = q / (LP * SEGS), rem = q - half * (LP * SEGS);
       const int j = rem / SEGS, sg = rem - j * SEGS;
       if (sg < kc / 8) *reinterpret_cast<bf16x8*>(&sst[(half * LP + j) * KP + sg * 8]) = v[u];
@@ -244,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm_bf16(BlockMeta bm, const uint16
     if (k0 + KC < nbp) fetch(k0 + KC);
 #pragma unroll
     for (int ks = 0; ks < KC / 32; ++ks) {
-      if (ks < nsteps) {
+      if (live && ks < nsteps) {
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
           const uint16_t* sp = &sst[(n * 16 + li) * KP + ks * 32 + kq * 8];
@@ -256,6 +318,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm_bf16(BlockMeta bm, const uint16
       }
     }
   }
+  if (!live) return;
   float* Yb = Y + bm.yoff[b];
 #pragma unroll
   for (int n = 0; n < NT; ++n)
@@ -312,64 +375,98 @@ __device__ __forceinline__ void tri_of(int t, int& i, int& m) {
   m = t - r * (r + 1) / 2;
 }
 
-// One 64-row tile: each thread owns a 4 x 4 block (I <= J) of the Gram matrix
-// and accumulates it over the tile's rows from LDS (8 loads per 16 FMAs).
-template <class TY>
-__global__ __launch_bounds__(kBlock) void k_gram_tiles(BlockMeta bm, const TY* __restrict__ Y,
-                                                       double* __restrict__ part) {
-  __shared__ __align__(16) double tile[64 * kMaxLP];
-  const int b = bm.item_b[blockIdx.x], t = bm.item_t[blockIdx.x];
-  const int n = bm.off[b + 1] - bm.off[b];
-  const int l = bm.l, LP = bm.LP;
-  const int l4 = (l + 3) & ~3;
-  const int npairs = l * (l + 1) / 2;
-  const int r0 = t * 64;
-  const int rows = max(0, min(64, n - r0));
-  const TY* Yb = Y + bm.yoff[b] + int64_t(r0) * LP;
-  // columns [l, l4) read as zero
-  for (int q = threadIdx.x; q < rows * l4; q += kBlock) {
-    const int r = q / l4, c = q - r * l4;
-    tile[r * kMaxLP + c] = c < l ? double(Yb[int64_t(r) * LP + c]) : 0.0;
+// dst[r * LD + c] = src[r * LP + c] for the rows x LP row-major block src
+// (16-byte aligned, rows <= ROWS), as TD, columns >= lmax and rows >= rows
+// as zero: every thread issues all its 16-byte loads before its first LDS
+// store, so a tile costs one round trip to memory rather than one per
+// element.  NT threads.
+template <int ROWS, int LP, int LD, int NT, class TS, class TD>
+__device__ __forceinline__ void stage_block(TD* __restrict__ dst, const TS* __restrict__ src, int lmax,
+                                            int rows = ROWS) {
+  constexpr int PER = 16 / sizeof(TS);            // elements per 16-byte load
+  constexpr int NV = ROWS * LP / PER;
+  constexpr int IT = (NV + NT - 1) / NT;
+  static_assert(LP % PER == 0, "rows of whole 16-byte vectors");
+  const int nv = rows * LP / PER;
+  uint4 buf[IT];
+#pragma unroll
+  for (int u = 0; u < IT; ++u) {
+    const int q = threadIdx.x + u * NT;
+    if (q < nv) buf[u] = reinterpret_cast<const uint4*>(src)[q];
   }
+#pragma unroll
+  for (int u = 0; u < IT; ++u) {
+    const int q = threadIdx.x + u * NT;
+    if (q < NV) {
+      const int e = q * PER, r = e / LP, c = e - r * LP;
+      const TS* v = reinterpret_cast<const TS*>(&buf[u]);
+#pragma unroll
+      for (int x = 0; x < PER; ++x) dst[r * LD + c + x] = (q < nv && c + x < lmax) ? TD(v[x]) : TD(0);
+    }
+  }
+}
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 on one wave: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; its four outputs are C[l / 16 + 4 i][l % 16].
+__device__ __forceinline__ doublex4 mfma_f64(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// One 128-row item of Y (two 64-row tiles, or a block's last one): the
+// upper 16 x 16 blocks (I <= J) of its Gram matrix Y' Y on FP64 MFMA (the
+// FP32 entries are exact in FP64), three blocks per wave at a time over 8
+// waves, written as the item's packed upper-triangle partial.  Block (I, J)
+// needs A[m][k] = Y[k][16I + m] and B[k][n] = Y[k][16J + n]: both are row k
+// of the staged tile.
+constexpr int kGramT = 512;
+template <class TY, int LP>
+__global__ __launch_bounds__(kGramT) void k_gram_tiles(BlockMeta bm, const TY* __restrict__ Y,
+                                                       double* __restrict__ part) {
+  constexpr int NT = LP / 16, NB = NT * (NT + 1) / 2, LDT = LP + 1, NW = kGramT / kWave;
+  __shared__ TY tile[128 * LDT];
+  const int b = bm.pair_b[blockIdx.x], t = bm.pair_t[blockIdx.x];
+  const int l = bm.l;
+  const int npairs = l * (l + 1) / 2;
+  const int rows = min(128, bm.nbp[b] - t * 64);
+  // columns past l read as zero; rows past the block are zero in Y (zero
+  // rows of the padded A_bb)
+  stage_block<128, LP, LDT, kGramT>(tile, Y + bm.yoff[b] + int64_t(t) * 64 * LP, l, rows);
   __syncthreads();
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int lm = lane % 16, lk = lane / 16;
   double* out = part + int64_t(blockIdx.x) * npairs;
-  const int nb4 = l4 / 4, nblk = nb4 * (nb4 + 1) / 2;
-  for (int q = threadIdx.x; q < nblk; q += kBlock) {
-    int J, I;
-    tri_of(q, J, I);
-    double acc[4][4];
+  for (int q0 = wave; q0 < NB; q0 += 3 * NW) {
+    int bi[3], bj[3];
+    doublex4 acc[3];
+    const int nu = min(3, (NB - 1 - q0) / NW + 1);   // this wave's blocks in the round (uniform)
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int u = 0; u < 3; ++u) {
+      const int q = min(q0 + NW * u, NB - 1);
+      tri_of(q, bj[u], bi[u]);   // bi <= bj
+      acc[u] = doublex4{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int k0 = 0; k0 < rows; k0 += 4) {
+      const TY* row = tile + (k0 + lk) * LDT + lm;
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-    for (int rr = 0; rr < rows; ++rr) {
-      const double* row = tile + rr * kMaxLP;
-      double a[4], c[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        a[x] = row[4 * I + x];
-        c[x] = row[4 * J + x];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * c[y];
+      for (int u = 0; u < 3; ++u)
+        if (u < nu) acc[u] = mfma_f64(double(row[16 * bi[u]]), double(row[16 * bj[u]]), acc[u]);
     }
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int i = 4 * I + x;
+    for (int u = 0; u < 3; ++u) {
+      if (q0 + NW * u >= NB) break;
 #pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const int j = 4 * J + y;
-        if (i <= j && j < l) out[i * l - i * (i - 1) / 2 + (j - i)] = acc[x][y];
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * bi[u] + lk + 4 * v, j = 16 * bj[u] + lm;
+        if (i <= j && j < l) out[i * l - i * (i - 1) / 2 + (j - i)] = acc[u][v];
       }
     }
   }
 }
 
-// Threads of the dense per-block kernels (Cholesky, Jacobi): one workgroup per
-// diagonal block, 16 waves, so that one step of their l-step loops is a
-// single pass of independent updates between two barriers.
+// Threads of the dense per-block kernels (Jacobi, eigensolver): one
+// workgroup per diagonal block, 16 waves.
 constexpr int kDense = 1024;
 
 // Pair index p of the packed upper triangle (row-major, row m holds
@@ -417,14 +514,6 @@ __device__ __forceinline__ void stage_gram(const BlockMeta& bm, const int32_t* _
   }
 }
 
-// Lane src's value of v (src uniform), both halves by v_readlane.
-__device__ __forceinline__ double lane_read(double v, int src) {
-  const uint64_t u = __double_as_longlong(v);
-  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), src);
-  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), src);
-  return __longlong_as_double((int64_t(hi) << 32) | lo);
-}
-
 // 16 x 16 block products on LDS by one wave: lane (r, c4) = (lane / 4,
 // lane % 4) accumulates C[r][4 c4 + t], t < 4, of
 // sum_k A[r][k] * (TB ? B[4 c4 + t][k] : B[k][4 c4 + t]).
@@ -445,14 +534,6 @@ __device__ __forceinline__ void blk_mm(double (&acc)[4], const double* __restric
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[t] += av[u] * bv[t][u];
   }
-}
-
-// A wave's LDS accesses complete in issue order; this keeps the compiler
-// from moving them across the point either.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // L^-1 of the Cholesky factor of G_b = Y_b' Y_b (summed from the Gram tile
@@ -627,64 +708,90 @@ __global__ __launch_bounds__(256) void k_identity_factor(int64_t n, int LP, int 
   }
 }
 
-// S = Y L^-T on a 64-row tile: S[r][j] = sum_{i<=j} Y[r][i] Linv[j][i] (j < l),
-// zero for j >= l and rows >= n_b.  Writes S (row-major) and ST (transposed,
-// the next GEMM operand: BF16 hi/lo pair in the BF16 mode).  Thread (g, h)
-// owns rows g + 16x (x < 4) and columns h*CP + c (c < CP = LP/16); Y rows
-// sit in LDS at an odd stride so the 16 rows a wave reads hit distinct banks.
+// S = Y L^-T on a 128-row item: S[r][j] = sum_{i<=j} Y[r][i] Linv[j][i]
+// (j < l), zero for j >= l and rows >= n_b (zero rows of Y, zero rows of
+// Linv), on FP64 MFMA: wave w computes the 16 rows 16w.. for all column
+// blocks J, skipping the k-steps above Linv's triangle; A[m][k] =
+// Y[16w + m][k], B[k][n] = Linv[16J + n][k], Linv kept as its packed lower
+// triangle.  Writes S (row-major) and, through LDS, ST (transposed, the next
+// GEMM operand: BF16 hi/lo pair in the BF16 mode).
+constexpr int kApplyT = 512;
 template <class TY, class TST, int LP>
-__global__ __launch_bounds__(kBlock) void k_apply_rinv(BlockMeta bm, const TY* __restrict__ Y,
-                                                       const double* __restrict__ Li, TY* __restrict__ S,
-                                                       TST* __restrict__ ST, int64_t lo_off) {
-  constexpr int CP = LP / 16, LDY = LP + 1;
-  __shared__ double Lt[LP * LP];       // Linv, row-major, zero above the diagonal and beyond l
-  __shared__ double Yt[64 * LDY];
-  const int b = bm.item_b[blockIdx.x], t = bm.item_t[blockIdx.x];
-  const int n = bm.off[b + 1] - bm.off[b], nbp = bm.nbp[b];
-  const int l = bm.l;
-  stage_rows(Lt, LP, Li + int64_t(b) * LP * LP, LP, LP, LP);
-  // rows beyond n_b are zero in Y (zero rows of the padded A_bb)
-  stage_rows(Yt, LDY, Y + bm.yoff[b] + int64_t(t) * 64 * LP, LP, 64, LP);
-  __syncthreads();
-  const int g = threadIdx.x % 16, h = threadIdx.x / 16;
-  const int j0 = h * CP;
-  double acc[4][CP];
+__global__ __launch_bounds__(kApplyT) void k_apply_rinv(BlockMeta bm, const TY* __restrict__ Y,
+                                                        const double* __restrict__ Li, TY* __restrict__ S,
+                                                        TST* __restrict__ ST, int64_t lo_off) {
+  constexpr int NT = LP / 16, LD = LP + 1, NPK = LP * (LP + 1) / 2;
+  __shared__ double Lp[NPK];       // Linv[r][c], c <= r, at r(r+1)/2 + c
+  __shared__ TY Yt[128 * LD];      // the Y item, then the S item
+  const int b = bm.pair_b[blockIdx.x], t = bm.pair_t[blockIdx.x];
+  const int nbp = bm.nbp[b];
+  const int rows = min(128, nbp - t * 64);
+  {
+    const double* Lb = Li + int64_t(b) * LP * LP;
+    constexpr int IT = (NPK + kApplyT - 1) / kApplyT;
+    double v[IT];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+    for (int u = 0; u < IT; ++u) {
+      const int q = threadIdx.x + u * kApplyT;
+      int r = 0, c = 0;
+      if (q < NPK) tri_of(q, r, c);
+      v[u] = q < NPK ? Lb[r * LP + c] : 0.0;
+    }
 #pragma unroll
-    for (int c = 0; c < CP; ++c) acc[x][c] = 0.0;
-  const int iend = min(l, j0 + CP);   // Linv[j][i] = 0 for i > j
-  for (int i = 0; i < iend; ++i) {
-    double y[4], lv[CP];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) y[x] = Yt[(g + 16 * x) * LDY + i];
-#pragma unroll
-    for (int c = 0; c < CP; ++c) lv[c] = Lt[(j0 + c) * LP + i];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int c = 0; c < CP; ++c) acc[x][c] += y[x] * lv[c];
+    for (int u = 0; u < IT; ++u) {
+      const int q = threadIdx.x + u * kApplyT;
+      if (q < NPK) Lp[q] = v[u];
+    }
   }
-  TY* Sb = S + bm.yoff[b];
-  TST* STb = ST + bm.yoff[b];
+  stage_block<128, LP, LD, kApplyT>(Yt, Y + bm.yoff[b] + int64_t(t) * 64 * LP, LP, rows);
+  __syncthreads();
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int lm = lane % 16, lk = lane / 16;
+  const bool live = 16 * wave < rows;
+  doublex4 acc[NT];
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int r = t * 64 + g + 16 * x;
-    const bool live = r < n;
+  for (int J = 0; J < NT; ++J) acc[J] = doublex4{0.0, 0.0, 0.0, 0.0};
+  if (live) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < LP; k0 += 4) {
+      const double a = double(Yt[(16 * wave + lm) * LD + k0 + lk]);
+      const int c = k0 + lk;
 #pragma unroll
-    for (int c = 0; c < CP; ++c) {
-      const int j = j0 + c;
-      const double v = (live && j < l) ? acc[x][c] : 0.0;
-      Sb[int64_t(r) * LP + j] = TY(v);
-      if constexpr (sizeof(TST) == 2) {
-        // hi + lo BF16 pair (the lo half lives lo_off elements further on)
-        const float f = float(v);
-        const uint16_t hi = f32_to_bf16_rne(f);
-        STb[int64_t(j) * nbp + r] = hi;
-        STb[lo_off + int64_t(j) * nbp + r] = f32_to_bf16_rne(f - bf16_to_f32(hi));
-      } else {
-        STb[int64_t(j) * nbp + r] = v;
+      for (int J = 0; J < NT; ++J) {
+        if (k0 <= 16 * J + 15) {
+          const int r = 16 * J + lm;
+          acc[J] = mfma_f64(a, c <= r ? Lp[r * (r + 1) / 2 + c] : 0.0, acc[J]);
+        }
       }
+    }
+  }
+  TY* Sb = S + bm.yoff[b] + int64_t(t) * 64 * LP;
+  __syncthreads();   // every wave is done with the Y item
+  if (live) {
+#pragma unroll
+    for (int J = 0; J < NT; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * wave + lk + 4 * v, j = 16 * J + lm;
+        const TY sv = TY(acc[J][v]);
+        Sb[int64_t(r) * LP + j] = sv;
+        Yt[r * LD + j] = sv;
+      }
+  }
+  __syncthreads();
+  TST* STb = ST + bm.yoff[b];
+  for (int q = threadIdx.x; q < LP * 128; q += kApplyT) {
+    const int j = q / 128, r = q % 128;
+    if (r >= rows) continue;
+    const int64_t at = int64_t(j) * nbp + t * 64 + r;
+    if constexpr (sizeof(TST) == 2) {
+      // hi + lo BF16 pair (the lo half lives lo_off elements further on)
+      const float f = float(Yt[r * LD + j]);
+      const uint16_t hi = f32_to_bf16_rne(f);
+      STb[at] = hi;
+      STb[lo_off + at] = f32_to_bf16_rne(f - bf16_to_f32(hi));
+    } else {
+      STb[at] = Yt[r * LD + j];
     }
   }
 }
@@ -1516,13 +1623,14 @@ __global__ __launch_bounds__(kBlock) void k_prec_z(BlockMeta bm, int32_t n_tiles
 struct Rsvd {
   int nb = 0, l = 0, LP = 0, kk = 0;
   bool f64 = false;
-  std::vector<int32_t> off, nbp, item_b, item_t, item0;
+  std::vector<int32_t> off, nbp, item_b, item_t, item0, pair_b, pair_t, pair0;
   std::vector<int64_t> aoff, yoff;
   int64_t a_elems = 0, y_elems = 0;
   int max_nbp = 0;
   // device
   DevBuf meta, A, Y, S, ST, Gpart, Li, Ut, sig, fail, omega, U, dT, Tpart;
   const int32_t* item0_d = nullptr;
+  const int32_t* pair0_d = nullptr;   // [nb+1] first 128-row item of each block
   BlockMeta bm{};
 };
 
@@ -1559,6 +1667,9 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
   R.item_b.clear();
   R.item_t.clear();
   R.item0.assign(n_blocks + 1, 0);
+  R.pair_b.clear();
+  R.pair_t.clear();
+  R.pair0.assign(n_blocks + 1, 0);
   R.max_nbp = 0;
   int64_t a = 0, y = 0;
   for (int b = 0; b < n_blocks; ++b) {
@@ -1575,12 +1686,19 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
       R.item_b.push_back(b);
       R.item_t.push_back(t);
     }
+    R.pair0[b] = int32_t(R.pair_b.size());
+    for (int t = 0; t < p / 64; t += 2) {
+      R.pair_b.push_back(b);
+      R.pair_t.push_back(t);
+    }
   }
   R.item0[n_blocks] = int32_t(R.item_b.size());
+  R.pair0[n_blocks] = int32_t(R.pair_b.size());
   R.a_elems = a;
   R.y_elems = y;
-  const size_t nI = R.item_b.size();
-  const size_t meta_bytes = 4 * (n_blocks + 1) + 4 * n_blocks + 8 * 2 * n_blocks + 4 * 2 * nI + 4 * (n_blocks + 1) + 64;
+  const size_t nI = R.item_b.size(), nP = R.pair_b.size();
+  const size_t meta_bytes = 4 * (n_blocks + 1) + 4 * n_blocks + 8 * 2 * n_blocks + 4 * 2 * nI + 4 * (n_blocks + 1) +
+                            4 * 2 * nP + 4 * (n_blocks + 1) + 64;
   HGL_TRY(R.meta.reserve(meta_bytes));
   std::vector<char> host(meta_bytes, 0);
   size_t pos = 0;
@@ -1598,6 +1716,9 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
   const size_t p_ib = put(R.item_b.data(), 4 * nI, 4);
   const size_t p_it = put(R.item_t.data(), 4 * nI, 4);
   const size_t p_i0 = put(R.item0.data(), 4 * (n_blocks + 1), 4);
+  const size_t p_pb = put(R.pair_b.data(), 4 * nP, 4);
+  const size_t p_pt = put(R.pair_t.data(), 4 * nP, 4);
+  const size_t p_p0 = put(R.pair0.data(), 4 * (n_blocks + 1), 4);
   HGL_TRY(ensure_pinned(h, (pos + 7) / 8 + 8));
   std::memcpy(h->pinned_d, host.data(), pos);
   HGL_HIP(hipMemcpyAsync(R.meta.p, h->pinned_d, pos, hipMemcpyHostToDevice, s));
@@ -1606,9 +1727,11 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
   R.bm = BlockMeta{n_blocks, R.l, R.LP, R.kk,
                    reinterpret_cast<const int32_t*>(base + p_off), reinterpret_cast<const int32_t*>(base + p_nbp),
                    reinterpret_cast<const int64_t*>(base + p_aoff), reinterpret_cast<const int64_t*>(base + p_yoff),
-                   reinterpret_cast<const int32_t*>(base + p_ib), reinterpret_cast<const int32_t*>(base + p_it)};
+                   reinterpret_cast<const int32_t*>(base + p_ib), reinterpret_cast<const int32_t*>(base + p_it),
+                   reinterpret_cast<const int32_t*>(base + p_pb), reinterpret_cast<const int32_t*>(base + p_pt)};
   R.item0_d = reinterpret_cast<const int32_t*>(base + p_i0);
-  HGL_TRY(R.Gpart.reserve(8 * nI * size_t(R.l) * (R.l + 1) / 2));
+  R.pair0_d = reinterpret_cast<const int32_t*>(base + p_p0);
+  HGL_TRY(R.Gpart.reserve(8 * nP * size_t(R.l) * (R.l + 1) / 2));
   const size_t ea = R.f64 ? 8 : 2, ey = R.f64 ? 8 : 4;
   HGL_TRY(R.A.reserve(ea * R.a_elems));
   HGL_TRY(R.Y.reserve(ey * R.y_elems));
@@ -1658,7 +1781,7 @@ static int launch_gemm(hgl_handle* h, Rsvd& R, hipStream_t s) {
   } else {
     HGL_TRY(with_lp(R.LP, [&](auto c) {
       constexpr int LP = decltype(c)::value;
-      launch(h, -1, k_gemm_bf16<LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.A.as<uint16_t>(),
+      launch(h, -1, k_gemm_bf16<LP>, dim3(int(R.pair_b.size())), dim3(kGemmT), 0, s, R.bm, R.A.as<uint16_t>(),
                          R.ST.as<uint16_t>(), R.y_elems, R.Y.as<float>());
       return HGL_OK;
     }));
@@ -1671,9 +1794,14 @@ static int launch_gemm(hgl_handle* h, Rsvd& R, hipStream_t s) {
 template <class TY>
 static int launch_gram(hgl_handle* h, Rsvd& R, const DevBuf& Yb, hipStream_t s) {
   const int n_items = int(R.item_b.size());
-  launch(h, -1, k_gram_tiles<TY>, dim3(n_items), dim3(kBlock), 0, s, R.bm, Yb.as<TY>(), R.Gpart.as<double>());
+  HGL_TRY(with_lp(R.LP, [&](auto c) {
+    constexpr int LP = decltype(c)::value;
+    launch(h, -1, k_gram_tiles<TY, LP>, dim3(int(R.pair_b.size())), dim3(kGramT), 0, s, R.bm, Yb.as<TY>(),
+           R.Gpart.as<double>());
+    return HGL_OK;
+  }));
   const int npairs = R.l * (R.l + 1) / 2;
-  launch(h, -1, k_gram_reduce, dim3((npairs + 255) / 256, R.nb), dim3(256), 0, s, R.bm, R.item0_d,
+  launch(h, -1, k_gram_reduce, dim3((npairs + 255) / 256, R.nb), dim3(256), 0, s, R.bm, R.pair0_d,
          R.Gpart.as<double>());
   HGL_HIP(hipGetLastError());
   return HGL_OK;
@@ -1692,13 +1820,13 @@ static int cholqr(hgl_handle* h, Rsvd& R, hipStream_t s, int passes) {
     HGL_TRY(with_lp(R.LP, [&](auto c) -> int {
       constexpr int NX = decltype(c)::value / 16;
       HGL_TRY(allow_lds(k_chol_inv<NX>, lds_chol));
-      launch(h, -1, k_chol_inv<NX>, dim3(R.nb), dim3(kCholT), lds_chol, s, R.bm, R.item0_d, R.Gpart.as<double>(),
+      launch(h, -1, k_chol_inv<NX>, dim3(R.nb), dim3(kCholT), lds_chol, s, R.bm, R.pair0_d, R.Gpart.as<double>(),
              R.Li.as<double>(), R.fail.as<int32_t>());
       return HGL_OK;
     }));
     HGL_TRY(with_lp(R.LP, [&](auto c) {
       constexpr int LP = decltype(c)::value;
-      launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, in.as<TY>(),
+      launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(int(R.pair_b.size())), dim3(kApplyT), 0, s, R.bm, in.as<TY>(),
                          R.Li.as<double>(), out.as<TY>(), R.ST.as<TST>(), R.y_elems);
       return HGL_OK;
     }));
@@ -1713,21 +1841,21 @@ static int cholqr(hgl_handle* h, Rsvd& R, hipStream_t s, int passes) {
 template <class TY, class TST>
 static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16_t* omega, hipStream_t s) {
   // 1. dense diagonal blocks A_bb
-  const size_t lds_ex = sizeof(double) * 4 * R.max_nbp;
+  const size_t lds_ex = (R.f64 ? sizeof(double) : sizeof(float)) * kExW * R.max_nbp;
   if (lds_ex > 160 * 1024) {
     set_error("diagonal block too large for LDS staging (%d rows)", R.max_nbp);
     return HGL_EUNSUPPORTED;
   }
   {
-    dim3 grid((R.max_nbp + 3) / 4, R.nb);
+    dim3 grid((R.max_nbp + kExW - 1) / kExW, R.nb);
     prof_begin(h, kProfExtract, s);
     if (R.f64) {
       HGL_TRY(allow_lds(k_extract_blocks<double>, lds_ex));
-      launch(h, -1, k_extract_blocks<double>, grid, dim3(kBlock), lds_ex, s, R.bm, h->vtx_ptr, h->vtx_edge,
+      launch(h, -1, k_extract_blocks<double>, grid, dim3(kExW * kWave), lds_ex, s, R.bm, h->vtx_ptr, h->vtx_edge,
                          h->edge_ptr, h->edge_vtx, h->s64, h->c64, R.A.as<double>(), R.max_nbp);
     } else {
       HGL_TRY(allow_lds(k_extract_blocks<uint16_t>, lds_ex));
-      launch(h, -1, k_extract_blocks<uint16_t>, grid, dim3(kBlock), lds_ex, s, R.bm, h->vtx_ptr, h->vtx_edge,
+      launch(h, -1, k_extract_blocks<uint16_t>, grid, dim3(kExW * kWave), lds_ex, s, R.bm, h->vtx_ptr, h->vtx_edge,
                          h->edge_ptr, h->edge_vtx, h->s64, h->c64, R.A.as<uint16_t>(), R.max_nbp);
     }
     HGL_HIP(hipGetLastError());
@@ -1774,7 +1902,7 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
       prof_begin(h, kProfQr, s);
       HGL_TRY(with_lp(R.LP, [&](auto c) {
         constexpr int LP = decltype(c)::value;
-        launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.Y.as<TY>(),
+        launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(int(R.pair_b.size())), dim3(kApplyT), 0, s, R.bm, R.Y.as<TY>(),
                R.Li.as<double>(), R.S.as<TY>(), R.ST.as<TST>(), R.y_elems);
         return HGL_OK;
       }));
@@ -1802,7 +1930,7 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
     };
     const int cw = lds_eig(64) <= 150 * 1024 ? 64 : 32;
     HGL_TRY(allow_lds(k_eig_tridiag, lds_eig(cw)));
-    launch(h, -1, k_eig_tridiag, dim3(R.nb), dim3(kEigT), lds_eig(cw), s, R.bm, R.item0_d, R.Gpart.as<double>(),
+    launch(h, -1, k_eig_tridiag, dim3(R.nb), dim3(kEigT), lds_eig(cw), s, R.bm, R.pair0_d, R.Gpart.as<double>(),
            R.sig.as<double>(), R.Ut.as<double>(), cw);
   } else {
     // FP64 sketch: FP64 cyclic Jacobi, A double-buffered where it fits in
@@ -1820,7 +1948,7 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
     JacFn jac = nt == 1024 ? (db ? &k_jacobi<1024, 3, double, true> : &k_jacobi<1024, 3, double, false>)
                            : (db ? &k_jacobi<512, 7, double, true> : &k_jacobi<512, 7, double, false>);
     HGL_TRY(allow_lds(jac, lds_j));
-    launch(h, -1, jac, dim3(R.nb), dim3(nt), lds_j, s, R.bm, R.item0_d, R.Gpart.as<double>(), R.sig.as<double>(),
+    launch(h, -1, jac, dim3(R.nb), dim3(nt), lds_j, s, R.bm, R.pair0_d, R.Gpart.as<double>(), R.sig.as<double>(),
            R.Ut.as<double>(), 30);
   }
   HGL_HIP(hipGetLastError());
