@@ -53,6 +53,8 @@ struct BlockMeta {
   const int32_t* item_t; // [n_items] tile index within the block
   const int32_t* pair_b; // [n_pairs] block of a 128-row item (two tiles, or the block's last one)
   const int32_t* pair_t; // [n_pairs] its first tile index
+  const int32_t* gemm_b; // [n_gemm] the 128-row items in XCD order (block -1: none)
+  const int32_t* gemm_t;
 };
 
 // Lane src's value of v (src uniform), both halves by v_readlane.
@@ -244,41 +246,48 @@ __global__ void k_sketch_to_st(BlockMeta bm, const uint16_t* __restrict__ omega,
 // S is carried as a pair of BF16 matrices S = S_hi + S_lo (S_lo = the BF16
 // rounding of S - S_hi), so each loaded A fragment feeds two MFMAs and the
 // product keeps about 16 significant bits of S while A_bb stays in BF16.
-constexpr int kGemmT = 512;   // 8 waves: one 128-row item
+constexpr int kGemmT = 256;   // 4 waves of 32 rows: one 128-row item
 template <int LP>
 __global__ __launch_bounds__(kGemmT) void k_gemm_bf16(BlockMeta bm, const uint16_t* __restrict__ A,
                                                       const uint16_t* __restrict__ ST, int64_t lo_off,
                                                       float* __restrict__ Y) {
   constexpr int NT = LP / 16;
-  const int b = bm.pair_b[blockIdx.x], t = bm.pair_t[blockIdx.x];
+  const int b = bm.gemm_b[blockIdx.x], t = bm.gemm_t[blockIdx.x];
+  if (b < 0) return;   // padding of the XCD order
   const int nbp = bm.nbp[b];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int r0 = t * 64 + wave * 16;
+  const int r0 = t * 64 + wave * 32;
   // a block's last tile may be alone in its item: the waves past it only
   // help stage S'
   const bool live = r0 < nbp;
   const int li = lane % 16, kq = lane / 16;
   const uint16_t* Ab = A + bm.aoff[b] + int64_t(live ? r0 + li : 0) * nbp + kq * 8;
-  // S' (hi and lo) is shared by the eight waves: stage 128-wide K chunks of
-  // it in LDS (rows padded by 8 elements against bank conflicts)
+  // S' (hi and lo) is shared by the four waves: stage 128-wide K chunks of
+  // it in LDS (rows padded by 8 elements against bank conflicts); each wave
+  // uses every S' fragment it reads for its two 16-row MFMA blocks
   constexpr int KC = 128, KP = KC + 8;
   __shared__ uint16_t sst[2 * LP * KP];
   const uint16_t* STb = ST + bm.yoff[b];
-  floatx4 acc[NT];
+  floatx4 acc[2][NT];
 #pragma unroll
-  for (int n = 0; n < NT; ++n) acc[n] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[h][n] = floatx4{0.f, 0.f, 0.f, 0.f};
   // software pipeline over 128-wide K chunks: the next chunk's A fragments
   // and S' segments are loaded into registers while this chunk's MFMAs run
   // (compile-time counts: 2 LP KC/8 segments over the workgroup's threads,
   // segments past the chunk's width skipped)
   constexpr int SEGS = KC / 8, NQ = 2 * LP * SEGS / kGemmT;
   static_assert(2 * LP * SEGS % kGemmT == 0, "copy loop");
-  bf16x8 a[KC / 32], v[NQ];
+  bf16x8 a[2][KC / 32], v[NQ];
   auto fetch = [&](int k0) {
     const int kc = min(KC, nbp - k0);   // 64 or 128 (nbp is a multiple of 64)
 #pragma unroll
-    for (int ks = 0; ks < KC / 32; ++ks)
-      if (live && ks < kc / 32) a[ks] = *reinterpret_cast<const bf16x8*>(Ab + k0 + ks * 32);
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int ks = 0; ks < KC / 32; ++ks)
+        if (live && ks < kc / 32)
+          a[h][ks] = *reinterpret_cast<const bf16x8*>(Ab + int64_t(16 * h) * nbp + k0 + ks * 32);
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
       const int q = threadIdx.x + u * kGemmT;
@@ -299,9 +308,11 @@ __global__ __launch_bounds__(kGemmT) void k_gemm_bf16(BlockMeta bm, const uint16
       const int j = rem / SEGS, sg = rem - j * SEGS;
       if (sg < kc / 8) *reinterpret_cast<bf16x8*>(&sst[(half * LP + j) * KP + sg * 8]) = v[u];
     }
-    bf16x8 ac[KC / 32];
+    bf16x8 ac[2][KC / 32];
 #pragma unroll
-    for (int ks = 0; ks < KC / 32; ++ks) ac[ks] = a[ks];
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int ks = 0; ks < KC / 32; ++ks) ac[h][ks] = a[h][ks];
     __syncthreads();
     if (k0 + KC < nbp) fetch(k0 + KC);
 #pragma unroll
@@ -312,8 +323,11 @@ __global__ __launch_bounds__(kGemmT) void k_gemm_bf16(BlockMeta bm, const uint16
           const uint16_t* sp = &sst[(n * 16 + li) * KP + ks * 32 + kq * 8];
           const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(sp);
           const bf16x8 blo = *reinterpret_cast<const bf16x8*>(sp + LP * KP);
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[ks], bhi, acc[n], 0, 0, 0);
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[ks], blo, acc[n], 0, 0, 0);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            acc[h][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[h][ks], bhi, acc[h][n], 0, 0, 0);
+            acc[h][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[h][ks], blo, acc[h][n], 0, 0, 0);
+          }
         }
       }
     }
@@ -321,9 +335,11 @@ __global__ __launch_bounds__(kGemmT) void k_gemm_bf16(BlockMeta bm, const uint16
   if (!live) return;
   float* Yb = Y + bm.yoff[b];
 #pragma unroll
-  for (int n = 0; n < NT; ++n)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) Yb[int64_t(r0 + kq * 4 + i) * LP + n * 16 + li] = acc[n][i];
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Yb[int64_t(r0 + 16 * h + kq * 4 + i) * LP + n * 16 + li] = acc[h][n][i];
 }
 
 // FP64 reference-precision variant: Y_b = A_bb S_b, plain FMA, one thread per
@@ -1623,7 +1639,7 @@ __global__ __launch_bounds__(kBlock) void k_prec_z(BlockMeta bm, int32_t n_tiles
 struct Rsvd {
   int nb = 0, l = 0, LP = 0, kk = 0;
   bool f64 = false;
-  std::vector<int32_t> off, nbp, item_b, item_t, item0, pair_b, pair_t, pair0;
+  std::vector<int32_t> off, nbp, item_b, item_t, item0, pair_b, pair_t, pair0, gemm_b, gemm_t;
   std::vector<int64_t> aoff, yoff;
   int64_t a_elems = 0, y_elems = 0;
   int max_nbp = 0;
@@ -1694,11 +1710,37 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
   }
   R.item0[n_blocks] = int32_t(R.item_b.size());
   R.pair0[n_blocks] = int32_t(R.pair_b.size());
+  // GEMM items in XCD order: the dispatcher deals workgroup w to XCD w % 8,
+  // so the blocks are dealt to the XCDs (largest first, each to the least
+  // loaded, load = items x rows) and the launch interleaves the XCDs'
+  // lists: every item of a block then runs on one XCD, whose L2 keeps the
+  // block's S' for all of them.
+  {
+    std::vector<int> order(n_blocks);
+    for (int b = 0; b < n_blocks; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return R.nbp[x] > R.nbp[y]; });
+    std::vector<std::vector<int>> lists(kXcd);
+    std::vector<int64_t> load(kXcd, 0);
+    for (int b : order) {
+      const int x = int(std::min_element(load.begin(), load.end()) - load.begin());
+      for (int q = R.pair0[b]; q < R.pair0[b + 1]; ++q) lists[x].push_back(q);
+      load[x] += int64_t(R.pair0[b + 1] - R.pair0[b]) * R.nbp[b];
+    }
+    size_t len = 0;
+    for (const auto& v : lists) len = std::max(len, v.size());
+    R.gemm_b.assign(len * kXcd, -1);
+    R.gemm_t.assign(len * kXcd, 0);
+    for (int x = 0; x < kXcd; ++x)
+      for (size_t j = 0; j < lists[x].size(); ++j) {
+        R.gemm_b[j * kXcd + x] = R.pair_b[lists[x][j]];
+        R.gemm_t[j * kXcd + x] = R.pair_t[lists[x][j]];
+      }
+  }
   R.a_elems = a;
   R.y_elems = y;
-  const size_t nI = R.item_b.size(), nP = R.pair_b.size();
+  const size_t nI = R.item_b.size(), nP = R.pair_b.size(), nG = R.gemm_b.size();
   const size_t meta_bytes = 4 * (n_blocks + 1) + 4 * n_blocks + 8 * 2 * n_blocks + 4 * 2 * nI + 4 * (n_blocks + 1) +
-                            4 * 2 * nP + 4 * (n_blocks + 1) + 64;
+                            4 * 2 * nP + 4 * (n_blocks + 1) + 4 * 2 * nG + 64;
   HGL_TRY(R.meta.reserve(meta_bytes));
   std::vector<char> host(meta_bytes, 0);
   size_t pos = 0;
@@ -1719,6 +1761,8 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
   const size_t p_pb = put(R.pair_b.data(), 4 * nP, 4);
   const size_t p_pt = put(R.pair_t.data(), 4 * nP, 4);
   const size_t p_p0 = put(R.pair0.data(), 4 * (n_blocks + 1), 4);
+  const size_t p_gb = put(R.gemm_b.data(), 4 * nG, 4);
+  const size_t p_gt = put(R.gemm_t.data(), 4 * nG, 4);
   HGL_TRY(ensure_pinned(h, (pos + 7) / 8 + 8));
   std::memcpy(h->pinned_d, host.data(), pos);
   HGL_HIP(hipMemcpyAsync(R.meta.p, h->pinned_d, pos, hipMemcpyHostToDevice, s));
@@ -1728,7 +1772,8 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
                    reinterpret_cast<const int32_t*>(base + p_off), reinterpret_cast<const int32_t*>(base + p_nbp),
                    reinterpret_cast<const int64_t*>(base + p_aoff), reinterpret_cast<const int64_t*>(base + p_yoff),
                    reinterpret_cast<const int32_t*>(base + p_ib), reinterpret_cast<const int32_t*>(base + p_it),
-                   reinterpret_cast<const int32_t*>(base + p_pb), reinterpret_cast<const int32_t*>(base + p_pt)};
+                   reinterpret_cast<const int32_t*>(base + p_pb), reinterpret_cast<const int32_t*>(base + p_pt),
+                   reinterpret_cast<const int32_t*>(base + p_gb), reinterpret_cast<const int32_t*>(base + p_gt)};
   R.item0_d = reinterpret_cast<const int32_t*>(base + p_i0);
   R.pair0_d = reinterpret_cast<const int32_t*>(base + p_p0);
   HGL_TRY(R.Gpart.reserve(8 * nP * size_t(R.l) * (R.l + 1) / 2));
@@ -1781,7 +1826,7 @@ static int launch_gemm(hgl_handle* h, Rsvd& R, hipStream_t s) {
   } else {
     HGL_TRY(with_lp(R.LP, [&](auto c) {
       constexpr int LP = decltype(c)::value;
-      launch(h, -1, k_gemm_bf16<LP>, dim3(int(R.pair_b.size())), dim3(kGemmT), 0, s, R.bm, R.A.as<uint16_t>(),
+      launch(h, -1, k_gemm_bf16<LP>, dim3(int(R.gemm_b.size())), dim3(kGemmT), 0, s, R.bm, R.A.as<uint16_t>(),
                          R.ST.as<uint16_t>(), R.y_elems, R.Y.as<float>());
       return HGL_OK;
     }));
