@@ -686,7 +686,7 @@ def bench_rsvd(a, scheme="subspace"):
     t_cg = time.perf_counter() - t0
     cfg = {"workload": "block_rsvd" if scheme == "subspace" else "block_rsvd_power", "N": p.N, "blocks": nb,
            "block_rows": "U[500,1500]", "k": k, "p": pp, "q": q,
-           "sketch": "bf16 A_bb, split-bf16 basis, fp32 accumulation, fp64 CholQR2 and Jacobi",
+           "sketch": "bf16 A_bb, split-bf16 basis, fp32 accumulation, fp64 CholQR2, fp32 tridiagonal eigensolver",
            "scheme": "Algorithm 1 (orthonormalised after every product)" if scheme == "subspace" else
                      "power scheme of eq. 10 (2q+1 products, one CholQR2)"}
     extra = {"roofline_hbm": hbm, "kernel_ms": breakdown,

@@ -324,7 +324,10 @@ int hgl_cg_solve_wg_batched(hgl_handle* h, const double* lambdas_host, const hgl
  * (Gram matrices and their Cholesky factors in FP64): two passes for the
  * basis of the last step and throughout an FP64 sketch, one pass between the
  * products of a BF16 sketch.  The small symmetric eigenproblem of B B' is
- * solved by parallel cyclic Jacobi, in FP32 sweeps for a BF16 sketch.  The diagonal blocks of
+ * solved in FP32 for a BF16 sketch (Householder tridiagonalisation,
+ * multisection on Sturm counts, inverse iteration with Gram-Schmidt within
+ * clusters of close eigenvalues) and by FP64 parallel cyclic Jacobi for an
+ * FP64 sketch.  The diagonal blocks of
  * X = I - A/(1+theta) are full rank, so the low-rank object decomposed is
  * A_bb; eq. (15) is applied as the identity-plus-low-rank inverse
  *   (I + L_bb/lambda)^-1 ~ lambda/(1+lambda) [I + U diag(s/(1+lambda-s)) U'].
@@ -569,7 +572,7 @@ int hgl_active_set_step(const double* w, const double* g, double mu, int32_t E, 
  * (M P, rows up to the hub threshold and hub-row chunks), 2 CG update (F, R),
  * 3 CG direction (P), 4 reductions, 5 residual edge gather (FP64),
  * 6 residual vertex gather (FP64), 7 start-up, 8 preconditioner, 9 rSVD
- * products, 10 CholQR, 11 Jacobi, 12 block extraction, 13 weight gradient,
+ * products, 10 CholQR, 11 the small eigenproblem, 12 block extraction, 13 weight gradient,
  * 14 hub-row finish of every vertex gather.  Kinds 0..15; others ->
  * HGL_EINVAL.
  */

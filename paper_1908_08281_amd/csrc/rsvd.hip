@@ -1080,12 +1080,13 @@ __global__ __launch_bounds__(NT) void k_jacobi(BlockMeta bm, const int32_t* __re
 //     the other waves update the rest, so a step is two barriers; v_k is
 //     kept in column k of A.
 //  2. The kk largest eigenvalues of T by multisection on Sturm counts
-//     (Golub & Van Loan, sec. 8.4.1): 4 lanes per eigenvalue split its
-//     bracket into 5 parts per pass, 12 passes (5^12 > 2^27).
+//     (Golub & Van Loan, sec. 8.4.1): a coarse pass counts at 1024 points
+//     of the Gershgorin bracket, then 16 lanes per eigenvalue (8 when kk >
+//     64) split its bracket into 17 (9) parts per pass, 5 (6) passes.
 //  3. Eigenvectors of T by inverse iteration, one lane per eigenvalue
 //     (Golub & Van Loan, sec. 8.2.2): Gaussian elimination with partial
-//     pivoting of T - lam I once, two solves from a fixed start vector, each
-//     followed by modified Gram-Schmidt against the earlier vectors of the
+//     pivoting of T - lam I once, two solves from a fixed start vector, then
+//     Gram-Schmidt (classical, twice) against the earlier vectors of the
 //     same cluster (eigenvalues closer than 1e-3 |T|, the threshold of
 //     LAPACK's stein), one wave per vector.
 //  4. Back-transformation U = Q Z: each eigenvector's column held by 16
@@ -1095,8 +1096,6 @@ __global__ __launch_bounds__(NT) void k_jacobi(BlockMeta bm, const int32_t* __re
 // cw = eigenvectors per inverse-iteration pass (64, or 32 where the
 // factors of 64 would not fit in LDS).
 constexpr int kEigT = 1024;
-constexpr int kEigG = 4;     // lanes per eigenvalue in the multisection
-constexpr int kEigPass = 12;
 constexpr int kEigSolves = 2;
 constexpr int kZ = kMaxLP / 16;   // entries of a column per lane of a 16-lane group
 
@@ -1150,8 +1149,9 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
   float* const FC = FB + l * cw;                     //   multiplier, row swap (1) or not (0)
   float* const FM = FC + l * cw;
   float* const FS = FM + l * cw;
-  __shared__ float vb[2][kMaxLP], pb[kMaxLP], ee[kMaxLP], tau[kMaxLP], lam[kMaxLP];
-  __shared__ __align__(16) float dd[kMaxLP + 4], e2s[kMaxLP + 4];
+  __shared__ float vb[2][kMaxLP], pb[kMaxLP], ee[kMaxLP + 8], tau[kMaxLP], lam[kMaxLP];
+  __shared__ __align__(16) float dd[kMaxLP + 8], e2s[kMaxLP + 8];
+  __shared__ int s_cnt[kEigT];
   __shared__ int cst[kMaxLP];
   __shared__ float s_lo, s_hi, s_piv, s_nrm;
   stage_gram<kEigT>(bm, item0, part, b, A);
@@ -1280,41 +1280,66 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
   }
   __syncthreads();
   // 2. multisection: the r-th largest eigenvalue lies where the count of
-  // eigenvalues below x passes l - 1 - r
-  {
-    const int g = tid / kEigG, gl = tid % kEigG;
-    const float piv = s_piv;
-    for (int r = g; r < kk; r += kEigT / kEigG) {
-      const int target = l - 1 - r;
-      float lo = s_lo, hi = s_hi;
-      for (int it = 0; it < kEigPass; ++it) {
-        const float x = lo + (hi - lo) * float(gl + 1) / float(kEigG + 1);
-        float q = dd[0] - x;
-        int c = q < 0.f;
-        for (int i0 = 0; i0 < l; i0 += 4) {
-          const float4 D = *reinterpret_cast<const float4*>(dd + i0);
-          const float4 E = *reinterpret_cast<const float4*>(e2s + i0);
-          const float dv[4] = {D.x, D.y, D.z, D.w}, ev[4] = {E.x, E.y, E.z, E.w};
+  // eigenvalues below x passes l - 1 - r.  A coarse pass counts at kEigT
+  // points across the Gershgorin bracket (one per thread) and gives every
+  // eigenvalue a bracket of one step; groups of g lanes then split it into
+  // g + 1 parts per pass.
+  const float piv = s_piv;
+  // count of eigenvalues of T below x (Sturm sequence of the LDL' pivots
+  // of T - x I); the next four entries are loaded while four are processed
+  auto sturm = [&](float x) {
+    float q = dd[0] - x;
+    int c = q < 0.f;
+    float4 D = *reinterpret_cast<const float4*>(dd), E = *reinterpret_cast<const float4*>(e2s);
+    for (int i0 = 0; i0 < l; i0 += 4) {
+      const float4 Dn = *reinterpret_cast<const float4*>(dd + i0 + 4);
+      const float4 En = *reinterpret_cast<const float4*>(e2s + i0 + 4);
+      const float dv[4] = {D.x, D.y, D.z, D.w}, ev[4] = {E.x, E.y, E.z, E.w};
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u;
-            if (i >= 1 && i < l) {
-              if (fabsf(q) < piv) q = -piv;
-              q = (dv[u] - x) - ev[u] * __builtin_amdgcn_rcpf(q);
-              c += q < 0.f;
-            }
-          }
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u;
+        if (i >= 1 && i < l) {
+          if (fabsf(q) < piv) q = -piv;
+          q = (dv[u] - x) - ev[u] * __builtin_amdgcn_rcpf(q);
+          c += q < 0.f;
         }
+      }
+      D = Dn;
+      E = En;
+    }
+    return c;
+  };
+  {
+    const float lo0 = s_lo, span = s_hi - s_lo;
+    s_cnt[tid] = sturm(lo0 + span * float(tid + 1) / float(kEigT + 1));
+    __syncthreads();
+    const int G = kk <= kEigT / 16 ? 16 : 8;
+    const int g = tid / G, gl = tid % G;
+    const int npass = G == 16 ? 5 : 6;   // 17^5, 9^6 > 2^17: with the coarse 2^10, past FP32 resolution
+    for (int r = g; r < kk; r += kEigT / G) {
+      const int target = l - 1 - r;
+      // the last coarse point whose count is <= target (counts rise with x)
+      int lo_i = -1, hi_i = kEigT;
+      while (hi_i - lo_i > 1) {
+        const int mid = (lo_i + hi_i) >> 1;
+        if (s_cnt[mid] <= target) lo_i = mid;
+        else hi_i = mid;
+      }
+      float lo = lo_i < 0 ? lo0 : lo0 + span * float(lo_i + 1) / float(kEigT + 1);
+      float hi = hi_i >= kEigT ? s_hi : lo0 + span * float(hi_i + 1) / float(kEigT + 1);
+      for (int it = 0; it < npass; ++it) {
+        const float x = lo + (hi - lo) * float(gl + 1) / float(G + 1);
+        const int c = sturm(x);
         // the group's flags (count <= target) are a prefix; its length picks
         // the sub-bracket, and every lane recomputes its ends the way the
         // lanes computed their points
         const uint64_t bal = __ballot(c <= target);
-        const uint32_t mine = uint32_t(bal >> ((lane / kEigG) * kEigG)) & ((1u << kEigG) - 1);
+        const uint32_t mine = uint32_t(bal >> ((lane / G) * G)) & ((1u << G) - 1);
         const int qn = __builtin_ctz(~mine);
-        const float xl = lo + (hi - lo) * float(qn) / float(kEigG + 1);
-        const float xh = lo + (hi - lo) * float(qn + 1) / float(kEigG + 1);
+        const float xl = lo + (hi - lo) * float(qn) / float(G + 1);
+        const float xh = lo + (hi - lo) * float(qn + 1) / float(G + 1);
         lo = qn > 0 ? xl : lo;
-        hi = qn < kEigG ? xh : hi;
+        hi = qn < G ? xh : hi;
       }
       if (gl == 0) lam[r] = 0.5f * (lo + hi);
     }
@@ -1330,7 +1355,8 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
   __syncthreads();
   int cmax = 1;
   for (int jj = 1; jj < kk; ++jj) cmax = max(cmax, jj - cst[jj] + 1);
-  // 3. inverse iteration, cw eigenvalues per pass
+  // 3. inverse iteration, cw eigenvalues per pass.  The per-lane loops run
+  // along T, each step's LDS operands loaded one step ahead.
   const float eps3 = 1.1920929e-7f * s_nrm;   // pivot floor and separation of equal eigenvalues
   for (int j0 = 0; j0 < kk; j0 += cw) {
     const int jc = tid, j = j0 + jc;
@@ -1342,13 +1368,17 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
       // Gaussian elimination with partial pivoting of T - lj I; the rows
       // kept in registers are the current pivot row (ca, cb)
       float ca = dd[0] - lj, cb = l > 1 ? ee[0] : 0.f;
-#pragma unroll 4
+      float cl = ee[0], dn = l > 1 ? dd[1] : 0.f, en = l > 2 ? ee[1] : 0.f;
       for (int i = 0; i + 1 < l; ++i) {
-        const float cl = ee[i], na = dd[i + 1] - lj, nb = i + 2 < l ? ee[i + 1] : 0.f;
-        const bool sw = fabsf(ca) < fabsf(cl);
-        const float pv = sw ? cl : (fabsf(ca) >= eps3 ? ca : (ca >= 0.f ? eps3 : -eps3));
+        const float na = dn - lj, nb = i + 2 < l ? en : 0.f, cli = cl;
+        // next step's operands
+        cl = ee[i + 1];
+        dn = dd[i + 2];
+        en = ee[i + 2];
+        const bool sw = fabsf(ca) < fabsf(cli);
+        const float pv = sw ? cli : (fabsf(ca) >= eps3 ? ca : (ca >= 0.f ? eps3 : -eps3));
         const float rp = __builtin_amdgcn_rcpf(pv);
-        const float mlt = (sw ? ca : cl) * rp;
+        const float mlt = (sw ? ca : cli) * rp;
         FA[i * cw + jc] = rp;
         FB[i * cw + jc] = sw ? na : cb;
         FC[i * cw + jc] = sw ? nb : 0.f;
@@ -1374,42 +1404,76 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
         // row operations of the elimination on the right side, then back
         // substitution and the 2-norm
         float cur = Z[j];
-#pragma unroll 4
+        float nx = l > 1 ? Z[kk + j] : 0.f, mlt = FM[jc], swf = FS[jc];
         for (int i = 0; i + 1 < l; ++i) {
-          const float nx = Z[(i + 1) * kk + j];
-          const float mlt = FM[i * cw + jc];
-          const bool sw = FS[i * cw + jc] != 0.f;
-          Z[i * kk + j] = sw ? nx : cur;
-          cur = sw ? cur - mlt * nx : nx - mlt * cur;
+          const float nxi = nx, mi = mlt;
+          const bool sw = swf != 0.f;
+          if (i + 2 < l) {
+            nx = Z[(i + 2) * kk + j];
+            mlt = FM[(i + 1) * cw + jc];
+            swf = FS[(i + 1) * cw + jc];
+          }
+          Z[i * kk + j] = sw ? nxi : cur;
+          cur = sw ? cur - mi * nxi : nxi - mi * cur;
         }
         float z2 = cur * FA[(l - 1) * cw + jc], z1 = 0.f;
         Z[(l - 1) * kk + j] = z2;
         float nrm2 = z2 * z2;
-#pragma unroll 4
-        for (int i = l - 2; i >= 0; --i) {
-          const float zi = (Z[i * kk + j] - FB[i * cw + jc] * z2 - FC[i * cw + jc] * z1) * FA[i * cw + jc];
+        int i = l - 2;
+        float zb = i >= 0 ? Z[i * kk + j] : 0.f, fb = i >= 0 ? FB[i * cw + jc] : 0.f;
+        float fc = i >= 0 ? FC[i * cw + jc] : 0.f, fa = i >= 0 ? FA[i * cw + jc] : 0.f;
+        for (; i >= 0; --i) {
+          const float zbi = zb, fbi = fb, fci = fc, fai = fa;
+          if (i >= 1) {
+            zb = Z[(i - 1) * kk + j];
+            fb = FB[(i - 1) * cw + jc];
+            fc = FC[(i - 1) * cw + jc];
+            fa = FA[(i - 1) * cw + jc];
+          }
+          const float zi = (zbi - fbi * z2 - fci * z1) * fai;
           Z[i * kk + j] = zi;
           nrm2 += zi * zi;
           z1 = z2;
           z2 = zi;
         }
         const float inv = 1.f / sqrtf(nrm2);
-        for (int i = 0; i < l; ++i) Z[i * kk + j] *= inv;
+        for (int q = 0; q < l; ++q) Z[q * kk + j] *= inv;
       }
-      // modified Gram-Schmidt in clusters, by position in the cluster; one
-      // wave per vector, entries i = lane, lane + 64 in registers
-      for (int pos = 1; pos < cmax; ++pos) {
+      // after the last solve: Gram-Schmidt in clusters, by position in the
+      // cluster; one wave per vector (entries lane, lane + 64 in
+      // registers), classical twice (the earlier members' projections from
+      // one set of inner products, then once more), four inner products
+      // reduced at a time.  The solves of nearly equal eigenvalues already
+      // use separated shifts.
+      for (int pos = 1; it + 1 == kEigSolves && pos < cmax; ++pos) {
         __syncthreads();
         for (int jv = j0 + wave; jv < min(kk, j0 + cw); jv += kEigT / kWave) {
           if (jv - cst[jv] != pos) continue;   // uniform in the wave
           float z0 = lane < l ? Z[lane * kk + jv] : 0.f;
           float z1 = lane + 64 < l ? Z[(lane + 64) * kk + jv] : 0.f;
-          for (int c = cst[jv]; c < jv; ++c) {
-            const float q0 = lane < l ? Z[lane * kk + c] : 0.f;
-            const float q1 = lane + 64 < l ? Z[(lane + 64) * kk + c] : 0.f;
-            const float dot = wave_sum_f(z0 * q0 + z1 * q1);
-            z0 -= dot * q0;
-            z1 -= dot * q1;
+          for (int rep = 0; rep < 2; ++rep) {
+            float y0 = 0.f, y1 = 0.f;   // sum of the projections
+            for (int c0 = cst[jv]; c0 < jv; c0 += 4) {
+              float q0[4], q1[4], d[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u;
+                q0[u] = (c < jv && lane < l) ? Z[lane * kk + c] : 0.f;
+                q1[u] = (c < jv && lane + 64 < l) ? Z[(lane + 64) * kk + c] : 0.f;
+                d[u] = z0 * q0[u] + z1 * q1[u];
+              }
+#pragma unroll
+              for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) d[u] += __shfl_xor(d[u], o, kWave);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                y0 += d[u] * q0[u];
+                y1 += d[u] * q1[u];
+              }
+            }
+            z0 -= y0;
+            z1 -= y1;
           }
           const float inv = 1.f / sqrtf(wave_sum_f(z0 * z0 + z1 * z1));
           if (lane < l) Z[lane * kk + jv] = z0 * inv;
@@ -1473,51 +1537,51 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
   }
 }
 
-// U[o_b + r][c] = sum_{i<l} S_b[r][i] Ut_b[i][c], c < kk (global N x kk, FP32).
-// Thread (g, h) owns rows g + 16x (x < 4) and columns h*CP + c (c < CP).
+// U[o_b + r][c] = sum_{i<l} S_b[r][i] Ut_b[i][c], c < kk (global N x kk, FP32)
+// on a 128-row item, FP64 MFMA: wave w computes the 16 rows 16w.. for all
+// column blocks; A[m][k] = S[16w + m][k], B[k][n] = Ut[k][16J + n] (Ut
+// staged in FP32, the precision U is stored in).
+constexpr int kBasisT = 512;
 template <class TY, int LP>
-__global__ __launch_bounds__(kBlock) void k_basis(BlockMeta bm, const TY* __restrict__ S,
-                                                  const double* __restrict__ Ut, float* __restrict__ U) {
-  constexpr int CP = LP / 16, LDS_ = LP + 1;
-  __shared__ double Ub[LP * LP];     // Ut_b, rows < l, columns < kk (zero beyond)
-  __shared__ double St[64 * LDS_];
-  const int b = bm.item_b[blockIdx.x], t = bm.item_t[blockIdx.x];
-  const int o = bm.off[b], n = bm.off[b + 1] - o;
+__global__ __launch_bounds__(kBasisT) void k_basis(BlockMeta bm, const TY* __restrict__ S,
+                                                   const double* __restrict__ Ut, float* __restrict__ U) {
+  constexpr int LD = LP + 1, KS = kMaxLP + 1, NCM = kMaxLP / 16;
+  __shared__ float Ub[LP * KS];    // Ut_b, rows < l (zero beyond), odd row stride
+  __shared__ TY St[128 * LD];
+  const int b = bm.pair_b[blockIdx.x], t = bm.pair_t[blockIdx.x];
+  const int o = bm.off[b], n = bm.off[b + 1] - o, nbp = bm.nbp[b];
   const int l = bm.l, kk = bm.kk;
+  const int rows = min(128, nbp - t * 64);
   const double* Utb = Ut + int64_t(b) * LP * kk;
-  for (int q = threadIdx.x; q < l * LP; q += kBlock) {
-    const int i = q / LP, c = q - i * LP;
-    Ub[q] = c < kk ? Utb[int64_t(i) * kk + c] : 0.0;
+  for (int q = threadIdx.x; q < LP * kk; q += kBasisT) {
+    const int i = q / kk, c = q - i * kk;
+    Ub[i * KS + c] = i < l ? float(Utb[q]) : 0.f;
   }
-  stage_rows(St, LDS_, S + bm.yoff[b] + int64_t(t) * 64 * LP, LP, 64, l);
+  stage_block<128, LP, LD, kBasisT>(St, S + bm.yoff[b] + int64_t(t) * 64 * LP, l, rows);
   __syncthreads();
-  const int g = threadIdx.x % 16, h = threadIdx.x / 16;
-  const int c0 = h * CP;
-  if (c0 >= kk) return;
-  double acc[4][CP];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int lm = lane % 16, lk = lane / 16;
+  const int vrows = min(rows, n - t * 64);   // rows of the block (the padding has no U)
+  if (16 * wave >= vrows) return;
+  const int nc = (kk + 15) / 16;
+  doublex4 acc[NCM];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int J = 0; J < NCM; ++J) acc[J] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < LP; k0 += 4) {
+    const double a = double(St[(16 * wave + lm) * LD + k0 + lk]);
 #pragma unroll
-    for (int c = 0; c < CP; ++c) acc[x][c] = 0.0;
-  for (int i = 0; i < l; ++i) {
-    double sv[4], uv[CP];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) sv[x] = St[(g + 16 * x) * LDS_ + i];
-#pragma unroll
-    for (int c = 0; c < CP; ++c) uv[c] = Ub[i * LP + c0 + c];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int c = 0; c < CP; ++c) acc[x][c] += sv[x] * uv[c];
+    for (int J = 0; J < NCM; ++J)
+      if (J < nc) acc[J] = mfma_f64(a, double(Ub[(k0 + lk) * KS + 16 * J + lm]), acc[J]);
   }
+  // columns past kk of Ub are not staged: their outputs are not written
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int r = t * 64 + g + 16 * x;
-    if (r >= n) continue;
+  for (int J = 0; J < NCM; ++J)
 #pragma unroll
-    for (int c = 0; c < CP; ++c)
-      if (c0 + c < kk) U[int64_t(o + r) * kk + c0 + c] = float(acc[x][c]);
-  }
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * wave + lk + 4 * v, c = 16 * J + lm;
+      if (J < nc && r < vrows && c < kk) U[int64_t(o + t * 64 + r) * kk + c] = float(acc[J][v]);
+    }
 }
 
 // ------------------------------------------------ block preconditioner --
@@ -2023,10 +2087,10 @@ static int finish_rsvd(hgl_handle* h, Rsvd& R, float* U_out, double* sigma_out, 
   HGL_TRY(with_lp(R.LP, [&](auto c) {
     constexpr int LP = decltype(c)::value;
     if (R.f64)
-      launch(h, -1, k_basis<double, LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.S.as<double>(),
+      launch(h, -1, k_basis<double, LP>, dim3(int(R.pair_b.size())), dim3(kBasisT), 0, s, R.bm, R.S.as<double>(),
                          R.Ut.as<double>(), U_out);
     else
-      launch(h, -1, k_basis<float, LP>, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.S.as<float>(),
+      launch(h, -1, k_basis<float, LP>, dim3(int(R.pair_b.size())), dim3(kBasisT), 0, s, R.bm, R.S.as<float>(),
                          R.Ut.as<double>(), U_out);
     return HGL_OK;
   }));

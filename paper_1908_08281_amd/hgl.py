@@ -565,7 +565,7 @@ def active_set_step(w: torch.Tensor, g: torch.Tensor, mu: float, out: torch.Tens
 
 PROFILE_KINDS = {0: "edge_gather", 1: "vertex_gather", 2: "cg_update", 3: "cg_direction",
                  4: "reduce", 5: "resid_edge_gather", 6: "resid_vertex_gather", 7: "start",
-                 8: "precond", 9: "dense_gemm", 10: "cholqr", 11: "jacobi", 12: "extract", 13: "grad",
+                 8: "precond", 9: "dense_gemm", 10: "cholqr", 11: "eig", 12: "extract", 13: "grad",
                  14: "hub_row_finish", 15: "schur_leaf"}
 
 
