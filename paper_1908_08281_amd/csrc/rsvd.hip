@@ -514,19 +514,36 @@ __global__ __launch_bounds__(256) void k_gram_reduce(BlockMeta bm, const int32_t
 }
 
 // A (l x l in LDS, row-major, leading dimension ld) <- G_b, reduced by
-// k_gram_reduce, mirrored.  NT threads.
-template <int NT, class TA>
+// k_gram_reduce, mirrored.  NT threads.  fill() runs while the loads are in
+// flight (it must not write the l x l corner of A).
+struct NoFill {
+  __device__ void operator()() const {}
+};
+template <int NT, class TA, class Fill = NoFill>
 __device__ __forceinline__ void stage_gram(const BlockMeta& bm, const int32_t* __restrict__ item0,
-                                           const double* __restrict__ part, int b, TA* A, int ld = -1) {
+                                           const double* __restrict__ part, int b, TA* A, int ld = -1,
+                                           Fill fill = {}) {
   const int l = bm.l, npairs = l * (l + 1) / 2;
   if (ld < 0) ld = l;
   const double* Gb = part + int64_t(item0[b]) * npairs;
-  for (int p = threadIdx.x; p < npairs; p += NT) {
-    const double g = Gb[p];
-    int m, j;
-    pair_rc(p, l, m, j);
-    A[m * ld + j] = TA(g);
-    A[j * ld + m] = TA(g);
+  // every round's load issued before the first store: one memory round trip
+  constexpr int R = (kMaxLP * (kMaxLP + 1) / 2 + NT - 1) / NT;
+  double g[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int p = threadIdx.x + u * NT;
+    g[u] = p < npairs ? Gb[p] : 0.0;
+  }
+  fill();
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int p = threadIdx.x + u * NT;
+    if (p < npairs) {
+      int m, j;
+      pair_rc(p, l, m, j);
+      A[m * ld + j] = TA(g[u]);
+      A[j * ld + m] = TA(g[u]);
+    }
   }
 }
 
@@ -555,21 +572,23 @@ __device__ __forceinline__ void blk_mm(double (&acc)[4], const double* __restric
 // L^-1 of the Cholesky factor of G_b = Y_b' Y_b (summed from the Gram tile
 // partials), written to Li (LP x LP, lower, zero padded).  G_b is padded to
 // N = 16 NX = LP with the identity and factored by 16 x 16 blocks
-// (right-looking, Golub & Van Loan, alg. 4.2.2 by blocks), 1024 threads:
+// (right-looking, Golub & Van Loan, alg. 4.2.2 by blocks), 512 threads:
 //   for each block column k: one wave factors A_kk = L_kk L_kk' and forms
 //   X_kk = L_kk^-1 in registers (an elimination on [A_kk | I] with unscaled
 //   pivots, one row per lane, then L[r][c] = A[r][c] / sqrt(piv_c),
 //   L^-1[r][c] = B[r][c] / sqrt(piv_r));
 //   one wave per block row below forms L_ik = A_ik L_kk^-T, and one wave
-//   per block left of the diagonal finishes X_kj = -X_kk W_kj; then one wave
-//   per lower block pair updates A_ij -= L_ik L_jk', and one per block
-//   X_ij (i > k >= j) accumulates W_ij += L_ik X_kj, so that
+//   per block left of the diagonal finishes X_kj = -X_kk W_kj; then the
+//   lower block pairs are updated, A_ij -= L_ik L_jk', and the blocks X_ij
+//   (i > k >= j) accumulate W_ij += L_ik X_kj, so that
 //   X_ij = -L_ii^-1 sum_{k=j}^{i-1} L_ik X_kj (the blocks of L^-1) are done
-//   with the factorisation.  Three barriers per block column.
+//   with the factorisation.  One block of lookahead: wave 0 updates
+//   A_{k+1,k+1} first and factors it (the next diagonal step) while the
+//   other waves do the remaining updates.  Two barriers per block column.
 // A non-positive or non-finite pivot triggers one retry with the shift
 // 11 (n l + l (l+1)) u trace(G) (shifted CholQR, Fukaya et al. 2020); a
 // second failure sets fail[b].
-constexpr int kCholT = 1024;
+constexpr int kCholT = 512;   // 8 waves: 256 VGPRs each, so the diagonal step never spills
 template <int NX>
 __global__ __launch_bounds__(kCholT) void k_chol_inv(BlockMeta bm, const int32_t* __restrict__ item0,
                                                      const double* __restrict__ part, double* __restrict__ Li,
@@ -579,20 +598,67 @@ __global__ __launch_bounds__(kCholT) void k_chol_inv(BlockMeta bm, const int32_t
   extern __shared__ double sm[];
   double* const A = sm;            // N x N (stride LD): G, then L in the lower blocks
   double* const X = sm + N * LD;   // N x N (stride LD): L^-1 in the lower blocks
-  __shared__ double s_tr;
+  __shared__ double s_tr, s_rs[16];
   __shared__ int s_bad;
   const int b = blockIdx.x, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int r = lane >> 2, c0 = (lane & 3) * 4;
   const int l = bm.l, LP = bm.LP;
   const int n = bm.off[b + 1] - bm.off[b];
+  // the diagonal step of block column kb, by wave 0: one row per lane (rows
+  // r = lane % 16; the four copies of a row, one per row of 16 lanes,
+  // compute alike); the trailing block stays symmetric, so column j is row
+  // j, read from lane j of the lane's own row of 16; likewise row j of B.  No early exit, so the steps unroll and the rows stay in
+  // registers; a failed pivot makes the result unused.  Column j of L
+  // leaves unscaled: L[r][j] = a_j / sqrt(piv_j) once all pivots are known.
+  auto diag = [&](int kb) {
+    double* const Akk = A + kb * 16 * LD + kb * 16;
+    const int rr = lane & 15;
+    double a[16], x[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      a[c] = Akk[rr * LD + c];
+      x[c] = rr == c ? 1.0 : 0.0;
+    }
+    double pr = 1.0;   // the lane's own row's pivot
+    bool ok = true;
+    static_for<0, 16>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      const double piv = row_bcast_d<j>(a[j]);
+      ok = ok && piv > 0.0 && isfinite(piv);
+      if (rr == j) pr = piv;
+      // 1/piv: hardware reciprocal and two Newton steps
+      double inv = __builtin_amdgcn_rcp(piv);
+      inv = fma(inv, fma(-piv, inv, 1.0), inv);
+      inv = fma(inv, fma(-piv, inv, 1.0), inv);
+      if (lane < 16 && j <= rr) Akk[rr * LD + j] = a[j];
+      const double cr = rr > j ? a[j] * inv : 0.0;
+#pragma unroll
+      for (int c = j + 1; c < 16; ++c) a[c] = fma(-cr, row_bcast_d<j>(a[c]), a[c]);
+#pragma unroll
+      for (int c = 0; c <= j; ++c) x[c] = fma(-cr, row_bcast_d<j>(x[c]), x[c]);
+    });
+    const double rs_r = 1.0 / sqrt(pr);
+    if (!ok) {
+      if (lane == 0) s_bad = 1;
+    } else if (lane < 16) {
+      double* const Xkk = X + kb * 16 * LD + kb * 16;
+      s_rs[rr] = rs_r;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) Xkk[rr * LD + c] = x[c] * rs_r;
+      wave_sync();
+#pragma unroll
+      for (int c = 0; c < 16; ++c) Akk[rr * LD + c] = c <= rr ? Akk[rr * LD + c] * s_rs[c] : 0.0;
+    }
+  };
   for (int attempt = 0;; ++attempt) {
     // G, the identity on the padding; X (the W sums) zero
-    for (int q = tid; q < N * N; q += kCholT) {
-      const int i = q / N, j = q % N;
-      if (i >= l || j >= l) A[i * LD + j] = i == j ? 1.0 : 0.0;
-      X[i * LD + j] = 0.0;
-    }
-    stage_gram<kCholT>(bm, item0, part, b, A, LD);
+    stage_gram<kCholT>(bm, item0, part, b, A, LD, [&]() {
+      for (int q = tid; q < N * N; q += kCholT) {
+        const int i = q / N, j = q % N;
+        if (i >= l || j >= l) A[i * LD + j] = i == j ? 1.0 : 0.0;
+        X[i * LD + j] = 0.0;
+      }
+    });
     if (tid == 0) s_bad = 0;
     __syncthreads();
     if (attempt > 0) {
@@ -608,53 +674,15 @@ __global__ __launch_bounds__(kCholT) void k_chol_inv(BlockMeta bm, const int32_t
       if (tid < l) A[tid * LD + tid] += shift;
       __syncthreads();
     }
-    for (int kb = 0; kb < NX; ++kb) {
-      double* const Akk = A + kb * 16 * LD + kb * 16;
-      if (wave == 0) {
-        // diagonal block, one row per lane (rows r = lane % 16; the four
-        // copies of a row compute alike): the trailing block stays
-        // symmetric, so column j is row j, read from lane j; likewise row j
-        // of B
-        const int rr = lane & 15;
-        double a[16], x[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          a[c] = Akk[rr * LD + c];
-          x[c] = rr == c ? 1.0 : 0.0;
-        }
-        double rs_r = 0.0;
-        bool ok = true;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          // (no early exit, so the loop unrolls and the rows stay in
-          // registers; a failed pivot makes the result unused)
-          const double piv = lane_read(a[j], j);
-          ok = ok && piv > 0.0 && isfinite(piv);
-          // 1/piv: hardware reciprocal and two Newton steps
-          double inv = __builtin_amdgcn_rcp(piv);
-          inv = fma(inv, fma(-piv, inv, 1.0), inv);
-          inv = fma(inv, fma(-piv, inv, 1.0), inv);
-          const double rsj = 1.0 / sqrt(piv);
-          if (rr == j) rs_r = rsj;
-          // column j of L is final: store it (frees a[j])
-          if (lane < 16) Akk[rr * LD + j] = j <= rr ? a[j] * rsj : 0.0;
-          const double cr = rr > j ? a[j] * inv : 0.0;
-#pragma unroll
-          for (int c = j + 1; c < 16; ++c) a[c] = fma(-cr, lane_read(a[c], j), a[c]);
-#pragma unroll
-          for (int c = 0; c <= j; ++c) x[c] = fma(-cr, lane_read(x[c], j), x[c]);
-        }
-        if (!ok) {
-          if (lane == 0) s_bad = 1;
-        } else if (lane < 16) {
-          double* const Xkk = X + kb * 16 * LD + kb * 16;
-#pragma unroll
-          for (int c = 0; c < 16; ++c) Xkk[rr * LD + c] = x[c] * rs_r;
-        }
-      }
-      __syncthreads();
-      if (s_bad) break;   // uniform
+    // kb = -1 only runs the first diagonal step (one call site of diag)
+    for (int kb = -1; kb < NX; ++kb) {
       const int nr = NX - kb - 1;
+      if (kb < 0) {
+        if (wave == 0) diag(0);
+        __syncthreads();
+        continue;
+      }
+      if (s_bad) break;   // uniform: the diagonal step of kb ran before the last barrier
       const double* const Xkk = X + kb * 16 * LD + kb * 16;
       if (wave < nr) {
         // panel: L_ik = A_ik L_kk^-T, one wave per block row below
@@ -674,26 +702,36 @@ __global__ __launch_bounds__(kCholT) void k_chol_inv(BlockMeta bm, const int32_t
       }
       __syncthreads();
       // trailing update of the lower blocks (one wave per block pair), and
-      // W_ij += L_ik X_kj for the blocks of L^-1 below row k
-      {
-        const int npair = nr * (nr + 1) / 2, nw = nr * (kb + 1);
-        for (int pw = wave; pw < npair + nw; pw += kCholT / kWave) {
-          double acc[4] = {0.0, 0.0, 0.0, 0.0};
-          if (pw < npair) {
-            int ii, jj;
-            tri_of(pw, ii, jj);
-            const int ib = kb + 1 + ii, jb = kb + 1 + jj;
-            double* const Aij = A + ib * 16 * LD + jb * 16;
-            blk_mm<true>(acc, A + ib * 16 * LD + kb * 16, A + jb * 16 * LD + kb * 16, LD, r, c0);
+      // W_ij += L_ik X_kj for the blocks of L^-1 below row k.  Wave 0 takes
+      // the next diagonal block (pair 0) and goes straight on to its
+      // diagonal step while the other waves finish the rest: no other
+      // update reads or writes that block or X_{k+1,k+1}.
+      const int npair = nr * (nr + 1) / 2, nw = nr * (kb + 1);
+      auto update = [&](int pw) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (pw < npair) {
+          int ii, jj;
+          tri_of(pw, ii, jj);
+          const int ib = kb + 1 + ii, jb = kb + 1 + jj;
+          double* const Aij = A + ib * 16 * LD + jb * 16;
+          blk_mm<true>(acc, A + ib * 16 * LD + kb * 16, A + jb * 16 * LD + kb * 16, LD, r, c0);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) Aij[r * LD + c0 + t] -= acc[t];
-          } else {
-            const int q = pw - npair, ib = kb + 1 + q / (kb + 1), jb = q % (kb + 1);
-            double* const Wij = X + ib * 16 * LD + jb * 16;
-            blk_mm<false>(acc, A + ib * 16 * LD + kb * 16, X + kb * 16 * LD + jb * 16, LD, r, c0);
+          for (int t = 0; t < 4; ++t) Aij[r * LD + c0 + t] -= acc[t];
+        } else {
+          const int q = pw - npair, ib = kb + 1 + q / (kb + 1), jb = q % (kb + 1);
+          double* const Wij = X + ib * 16 * LD + jb * 16;
+          blk_mm<false>(acc, A + ib * 16 * LD + kb * 16, X + kb * 16 * LD + jb * 16, LD, r, c0);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) Wij[r * LD + c0 + t] += acc[t];
-          }
+          for (int t = 0; t < 4; ++t) Wij[r * LD + c0 + t] += acc[t];
+        }
+      };
+      if (nr > 0) {
+        if (wave == 0) {
+          update(0);
+          wave_sync();
+          diag(kb + 1);
+        } else {
+          for (int pw = wave; pw < npair + nw; pw += kCholT / kWave - 1) update(pw);
         }
       }
       __syncthreads();
@@ -1099,10 +1137,7 @@ constexpr int kEigT = 1024;
 constexpr int kEigSolves = 2;
 constexpr int kZ = kMaxLP / 16;   // entries of a column per lane of a 16-lane group
 
-__device__ __forceinline__ float wave_sum_f(float x) {
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
-}
+__device__ __forceinline__ float wave_sum_f(float x) { return wave_sum_dpp(x); }
 
 // Reflector of x (two entries per lane of wave 0: x_lane, x_{lane+64};
 // n entries): H x = beta e_1, H = I - t v v', v_0 = 1.  Writes v to vbuf
@@ -1111,7 +1146,7 @@ __device__ __forceinline__ void eig_reflector(float x0, float x1, int n, int k, 
                                               float* __restrict__ A, float* __restrict__ vbuf,
                                               float* __restrict__ tau, float* __restrict__ ee) {
   const int lane = threadIdx.x % kWave;
-  const float alpha = __shfl(x0, 0, kWave);
+  const float alpha = readlane_f(x0, 0);
   const float s2 = wave_sum_f((lane >= 1 && lane < n ? x0 * x0 : 0.f) + (lane + 64 < n ? x1 * x1 : 0.f));
   float t = 0.f, beta = alpha, scale = 0.f;
   if (s2 > 0.f) {
@@ -1185,7 +1220,7 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
             const int j = c16 + 16 * u;
             if (j < m) acc += row[j] * v[j];
           }
-          for (int o = 8; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+          acc = row16_sum(acc);
           if (c16 == 0) pb[i] = t * acc;
         }
       }
@@ -1264,12 +1299,10 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
       e2s[i] = e2;
       emax = fmaxf(emax, e2);
     }
-    for (int o = 32; o >= 1; o >>= 1) {
-      lo = fminf(lo, __shfl_xor(lo, o, kWave));
-      hi = fmaxf(hi, __shfl_xor(hi, o, kWave));
-      emax = fmaxf(emax, __shfl_xor(emax, o, kWave));
-      tn = fmaxf(tn, __shfl_xor(tn, o, kWave));
-    }
+    lo = wave_reduce(lo, OpMin{});
+    hi = wave_reduce(hi, OpMax{});
+    emax = wave_reduce(emax, OpMax{});
+    tn = wave_reduce(tn, OpMax{});
     if (lane == 0) {
       const float span = fmaxf(hi - lo, 1e-30f);
       s_lo = lo - 1e-6f * span;
@@ -1463,9 +1496,7 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
                 d[u] = z0 * q0[u] + z1 * q1[u];
               }
 #pragma unroll
-              for (int o = 32; o >= 1; o >>= 1)
-#pragma unroll
-                for (int u = 0; u < 4; ++u) d[u] += __shfl_xor(d[u], o, kWave);
+              for (int u = 0; u < 4; ++u) d[u] = wave_sum_dpp(d[u]);
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
                 y0 += d[u] * q0[u];
@@ -1521,8 +1552,7 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
         float sdot = 0.f;
 #pragma unroll
         for (int u = 0; u < kZ; ++u) sdot += v[u] * z[u];
-        for (int o = 8; o >= 1; o >>= 1) sdot += __shfl_xor(sdot, o, kWave);
-        const float f = t * sdot;
+        const float f = t * row16_sum(sdot);
 #pragma unroll
         for (int u = 0; u < kZ; ++u) z[u] -= f * v[u];
       }
