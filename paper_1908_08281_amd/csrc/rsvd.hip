@@ -1904,12 +1904,20 @@ __global__ void k_zero_i32(int32_t* __restrict__ p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// Bytes of LDS the kernel declares statically (0 if the query fails).
+template <class K>
+static size_t static_lds(K kernel) {
+  hipFuncAttributes attr{};
+  if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(kernel)) != hipSuccess) return 0;
+  return attr.sharedSizeBytes;
+}
+
 // Kernels whose dynamic LDS exceeds the default 64 KiB must opt in (gfx950
-// has 160 KiB of LDS per CU).
+// has 160 KiB of LDS per CU, static and dynamic together).
 template <class K>
 static int allow_lds(K kernel, size_t bytes) {
-  if (bytes > 160 * 1024) {
-    set_error("kernel needs %zu bytes of LDS", bytes);
+  if (bytes + static_lds(kernel) > 160 * 1024) {
+    set_error("kernel needs %zu bytes of LDS", bytes + static_lds(kernel));
     return HGL_EUNSUPPORTED;
   }
   if (bytes > 64 * 1024)
@@ -2088,7 +2096,7 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
     auto lds_eig = [&](int cw) {
       return sizeof(float) * (size_t(R.l) * R.l + size_t(R.l) * R.kk + 5 * size_t(R.l) * cw);
     };
-    const int cw = lds_eig(64) <= 150 * 1024 ? 64 : 32;
+    const int cw = lds_eig(64) + static_lds(k_eig_tridiag) <= 160 * 1024 ? 64 : 32;
     HGL_TRY(allow_lds(k_eig_tridiag, lds_eig(cw)));
     launch(h, -1, k_eig_tridiag, dim3(R.nb), dim3(kEigT), lds_eig(cw), s, R.bm, R.pair0_d, R.Gpart.as<double>(),
            R.sig.as<double>(), R.Ut.as<double>(), cw);
