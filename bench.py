@@ -665,12 +665,16 @@ def bench_rsvd(a, scheme="subspace"):
     hgl.profile(h, False)
     breakdown = _breakdown(h, run, max(2, a.steps // 5))
     sizes = np.diff(p.blocks).astype(np.float64)
-    gemm_flops = float(np.sum(2.0 * sizes * sizes * l))           # one product A_bb S per block
+    gemm_flops = float(np.sum(2.0 * sizes * sizes * l))           # one product A_bb S, every block
     n_g, ms_g = prof["dense_gemm"]
-    roof = _roof("rsvd_gemm", n_g, ms_g, gemm_flops, bound="mfma")
+    # 2q + 2 products per call; the library splits the blocks into groups
+    # with a launch each, so a launch covers the products' share n_prod / n_g
+    n_prod = (2 * q + 2) * a.steps
+    per_launch = n_prod / max(n_g, 1)
+    roof = _roof("rsvd_gemm", n_g, ms_g, gemm_flops * per_launch, bound="mfma")
     nbp = np.ceil(sizes / 64) * 64
     gemm_bytes = float(np.sum(2 * nbp * nbp + 2 * 2 * nbp * 80 + 4 * nbp * 80))
-    hbm = _roof("rsvd_gemm", n_g, ms_g, gemm_bytes)
+    hbm = _roof("rsvd_gemm", n_g, ms_g, gemm_bytes * per_launch)
     ms = 1e3 * dt / a.steps
     # refined solve beside it
     Y = torch.from_numpy(p.Y).to(dev, torch.float32)

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <type_traits>
 
 #include "kernels.h"
@@ -34,6 +35,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxLP = 96;
+constexpr int kGroups = 2;   // concurrent chains of blocks (see Grp)
 
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
@@ -55,6 +57,10 @@ struct BlockMeta {
   const int32_t* pair_t; // [n_pairs] its first tile index
   const int32_t* gemm_b; // [n_gemm] the 128-row items in XCD order (block -1: none)
   const int32_t* gemm_t;
+  // a launch over a group of blocks adds these to its workgroup index: the
+  // first block (per-block kernels), 128-row item (per-item kernels), 64-row
+  // item and GEMM-list entry of the group
+  int32_t b0 = 0, p0 = 0, i0 = 0, g0 = 0;
 };
 
 // Lane src's value of v (src uniform), both halves by v_readlane.
@@ -96,7 +102,7 @@ __global__ __launch_bounds__(kExW * kWave) void k_extract_blocks(BlockMeta bm, c
   extern __shared__ double srow_raw[];
   TC* const srow = reinterpret_cast<TC*>(srow_raw);   // [kExW][max_nbp]
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int b = blockIdx.y;
+  const int b = bm.b0 + blockIdx.y;
   const int o = bm.off[b], n = bm.off[b + 1] - o, nbp = bm.nbp[b];
   const int ur = blockIdx.x * kExW + wave;  // row within the padded block
   if (blockIdx.x * kExW >= nbp) return;
@@ -221,7 +227,7 @@ __global__ void k_philox_words(int64_t n, const uint32_t* __restrict__ ctr, uint
 template <class TS>
 __global__ void k_sketch_to_st(BlockMeta bm, const uint16_t* __restrict__ omega, TS* __restrict__ ST,
                                int64_t lo_off) {
-  const int b = blockIdx.y;
+  const int b = bm.b0 + blockIdx.y;
   const int o = bm.off[b], n = bm.off[b + 1] - o, nbp = bm.nbp[b];
   const int64_t total = int64_t(bm.LP) * nbp;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(kGemmT) void k_gemm_bf16(BlockMeta bm, const uint16
                                                       const uint16_t* __restrict__ ST, int64_t lo_off,
                                                       float* __restrict__ Y) {
   constexpr int NT = LP / 16;
-  const int b = bm.gemm_b[blockIdx.x], t = bm.gemm_t[blockIdx.x];
+  const int b = bm.gemm_b[bm.g0 + blockIdx.x], t = bm.gemm_t[bm.g0 + blockIdx.x];
   if (b < 0) return;   // padding of the XCD order
   const int nbp = bm.nbp[b];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -273,48 +279,50 @@ __global__ __launch_bounds__(kGemmT) void k_gemm_bf16(BlockMeta bm, const uint16
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[h][n] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // software pipeline over 128-wide K chunks: the next chunk's A fragments
-  // and S' segments are loaded into registers while this chunk's MFMAs run
-  // (compile-time counts: 2 LP KC/8 segments over the workgroup's threads,
-  // segments past the chunk's width skipped)
+  // software pipeline over 128-wide K chunks, two deep: while a chunk's
+  // MFMAs run, the A fragments and S' segments of the next two chunks are
+  // in flight in registers (compile-time counts: 2 LP KC/8 segments over the
+  // workgroup's threads, segments past the chunk's width skipped)
   constexpr int SEGS = KC / 8, NQ = 2 * LP * SEGS / kGemmT;
   static_assert(2 * LP * SEGS % kGemmT == 0, "copy loop");
-  bf16x8 a[2][KC / 32], v[NQ];
-  auto fetch = [&](int k0) {
-    const int kc = min(KC, nbp - k0);   // 64 or 128 (nbp is a multiple of 64)
+  bf16x8 a[2][2][KC / 32], v[2][NQ];
+  // (no branches around the loads: past a chunk's width the column is
+  // clamped into the row, and the values land in LDS or registers that the
+  // MFMA steps do not read; branches would make the compiler wait for every
+  // load in flight before each store)
+  auto fetch = [&](int k0, auto bufc) {
+    constexpr int buf = decltype(bufc)::value;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int ks = 0; ks < KC / 32; ++ks)
-        if (live && ks < kc / 32)
-          a[h][ks] = *reinterpret_cast<const bf16x8*>(Ab + int64_t(16 * h) * nbp + k0 + ks * 32);
+        a[buf][h][ks] = *reinterpret_cast<const bf16x8*>(Ab + int64_t(16 * h) * nbp + min(k0 + ks * 32, nbp - 32));
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
       const int q = threadIdx.x + u * kGemmT;
       const int half = q / (LP * SEGS), rem = q - half * (LP * SEGS);
       const int j = rem / SEGS, sg = rem - j * SEGS;
-      if (sg < kc / 8) v[u] = *reinterpret_cast<const bf16x8*>(STb + half * lo_off + int64_t(j) * nbp + k0 + sg * 8);
+      v[buf][u] = *reinterpret_cast<const bf16x8*>(STb + half * lo_off + int64_t(j) * nbp + min(k0 + sg * 8, nbp - 8));
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < nbp; k0 += KC) {
-    const int kc = min(KC, nbp - k0);
-    const int nsteps = kc / 32;
+  auto step = [&](int k0, auto bufc) {
+    constexpr int buf = decltype(bufc)::value;
+    const int nsteps = min(KC, nbp - k0) / 32;   // <= 0 past the end
     __syncthreads();  // the previous chunk's MFMAs are done with sst
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
       const int q = threadIdx.x + u * kGemmT;
       const int half = q / (LP * SEGS), rem = q - half * (LP * SEGS);
       const int j = rem / SEGS, sg = rem - j * SEGS;
-      if (sg < kc / 8) *reinterpret_cast<bf16x8*>(&sst[(half * LP + j) * KP + sg * 8]) = v[u];
+      *reinterpret_cast<bf16x8*>(&sst[(half * LP + j) * KP + sg * 8]) = v[buf][u];
     }
     bf16x8 ac[2][KC / 32];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int ks = 0; ks < KC / 32; ++ks) ac[h][ks] = a[h][ks];
+      for (int ks = 0; ks < KC / 32; ++ks) ac[h][ks] = a[buf][h][ks];
     __syncthreads();
-    if (k0 + KC < nbp) fetch(k0 + KC);
+    fetch(k0 + 2 * KC, bufc);   // past the end: clamped, unused
 #pragma unroll
     for (int ks = 0; ks < KC / 32; ++ks) {
       if (live && ks < nsteps) {
@@ -331,6 +339,17 @@ __global__ __launch_bounds__(kGemmT) void k_gemm_bf16(BlockMeta bm, const uint16
         }
       }
     }
+  };
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
+  // chunks in pairs, every load unconditional, so the compiler counts the
+  // loads in flight exactly and waits only for the chunk it stores (a chunk
+  // past the end does no MFMA step)
+  fetch(0, B0{});
+  fetch(KC, B1{});
+  for (int k0 = 0; k0 < nbp; k0 += 2 * KC) {
+    step(k0, B0{});
+    step(k0 + KC, B1{});
   }
   if (!live) return;
   float* Yb = Y + bm.yoff[b];
@@ -346,7 +365,7 @@ __global__ __launch_bounds__(kGemmT) void k_gemm_bf16(BlockMeta bm, const uint16
 // (row, 4 columns) of a 64-row tile.
 __global__ __launch_bounds__(kBlock) void k_gemm_f64(BlockMeta bm, const double* __restrict__ A,
                                                      const double* __restrict__ ST, double* __restrict__ Y) {
-  const int b = bm.item_b[blockIdx.x], t = bm.item_t[blockIdx.x];
+  const int b = bm.item_b[bm.i0 + blockIdx.x], t = bm.item_t[bm.i0 + blockIdx.x];
   const int nbp = bm.nbp[b], LP = bm.LP;
   const double* Ab = A + bm.aoff[b];
   const double* Sb = ST + bm.yoff[b];
@@ -442,7 +461,7 @@ __global__ __launch_bounds__(kGramT) void k_gram_tiles(BlockMeta bm, const TY* _
                                                        double* __restrict__ part) {
   constexpr int NT = LP / 16, NB = NT * (NT + 1) / 2, LDT = LP + 1, NW = kGramT / kWave;
   __shared__ TY tile[128 * LDT];
-  const int b = bm.pair_b[blockIdx.x], t = bm.pair_t[blockIdx.x];
+  const int b = bm.pair_b[bm.p0 + blockIdx.x], t = bm.pair_t[bm.p0 + blockIdx.x];
   const int l = bm.l;
   const int npairs = l * (l + 1) / 2;
   const int rows = min(128, bm.nbp[b] - t * 64);
@@ -452,7 +471,7 @@ __global__ __launch_bounds__(kGramT) void k_gram_tiles(BlockMeta bm, const TY* _
   __syncthreads();
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int lm = lane % 16, lk = lane / 16;
-  double* out = part + int64_t(blockIdx.x) * npairs;
+  double* out = part + int64_t(bm.p0 + blockIdx.x) * npairs;
   for (int q0 = wave; q0 < NB; q0 += 3 * NW) {
     int bi[3], bj[3];
     doublex4 acc[3];
@@ -504,7 +523,7 @@ __device__ __forceinline__ void pair_rc(int p, int l, int& m, int& j) {
 __global__ __launch_bounds__(256) void k_gram_reduce(BlockMeta bm, const int32_t* __restrict__ item0,
                                                      double* __restrict__ part) {
   const int l = bm.l, npairs = l * (l + 1) / 2;
-  const int p = blockIdx.x * 256 + threadIdx.x, b = blockIdx.y;
+  const int p = blockIdx.x * 256 + threadIdx.x, b = bm.b0 + blockIdx.y;
   if (p >= npairs) return;
   const int i0 = item0[b], i1 = item0[b + 1];
   double sacc = 0.0;
@@ -600,7 +619,7 @@ __global__ __launch_bounds__(kCholT) void k_chol_inv(BlockMeta bm, const int32_t
   double* const X = sm + N * LD;   // N x N (stride LD): L^-1 in the lower blocks
   __shared__ double s_tr, s_rs[16];
   __shared__ int s_bad;
-  const int b = blockIdx.x, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int b = bm.b0 + blockIdx.x, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int r = lane >> 2, c0 = (lane & 3) * 4;
   const int l = bm.l, LP = bm.LP;
   const int n = bm.off[b + 1] - bm.off[b];
@@ -777,7 +796,7 @@ __global__ __launch_bounds__(kApplyT) void k_apply_rinv(BlockMeta bm, const TY* 
   constexpr int NT = LP / 16, LD = LP + 1, NPK = LP * (LP + 1) / 2;
   __shared__ double Lp[NPK];       // Linv[r][c], c <= r, at r(r+1)/2 + c
   __shared__ TY Yt[128 * LD];      // the Y item, then the S item
-  const int b = bm.pair_b[blockIdx.x], t = bm.pair_t[blockIdx.x];
+  const int b = bm.pair_b[bm.p0 + blockIdx.x], t = bm.pair_t[bm.p0 + blockIdx.x];
   const int nbp = bm.nbp[b];
   const int rows = min(128, nbp - t * 64);
   {
@@ -882,7 +901,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(BlockMeta bm, const int32_t* __re
                                                const double* __restrict__ part, double* __restrict__ sig,
                                                double* __restrict__ Ut, int max_sweeps) {
   extern __shared__ double sm[];
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int b = bm.b0 + blockIdx.x, tid = threadIdx.x;
   const int l = bm.l, LP = bm.LP, kk = bm.kk;
   const int ne = l + (l & 1);  // even count (a dummy index l pairs with the odd one out)
   const int half = ne / 2;
@@ -1175,7 +1194,7 @@ __global__ __launch_bounds__(kEigT) void k_eig_tridiag(BlockMeta bm, const int32
                                                        const double* __restrict__ part, double* __restrict__ sig,
                                                        double* __restrict__ Ut, int cw) {
   extern __shared__ double sm[];
-  const int b = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int b = bm.b0 + blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const int l = bm.l, LP = bm.LP, kk = bm.kk;
   float* const A = reinterpret_cast<float*>(sm);     // l x l, row-major
   float* const Z = A + l * l;                        // l x kk, Z[i * kk + j]
@@ -1578,7 +1597,7 @@ __global__ __launch_bounds__(kBasisT) void k_basis(BlockMeta bm, const TY* __res
   constexpr int LD = LP + 1, KS = kMaxLP + 1, NCM = kMaxLP / 16;
   __shared__ float Ub[LP * KS];    // Ut_b, rows < l (zero beyond), odd row stride
   __shared__ TY St[128 * LD];
-  const int b = bm.pair_b[blockIdx.x], t = bm.pair_t[blockIdx.x];
+  const int b = bm.pair_b[bm.p0 + blockIdx.x], t = bm.pair_t[bm.p0 + blockIdx.x];
   const int o = bm.off[b], n = bm.off[b + 1] - o, nbp = bm.nbp[b];
   const int l = bm.l, kk = bm.kk;
   const int rows = min(128, nbp - t * 64);
@@ -1745,11 +1764,15 @@ struct Rsvd {
   // the block layout the metadata was built for, and its generation
   std::vector<int32_t> layout_key;
   uint64_t layout_gen = 0;
+  // groups of consecutive blocks: first blocks [ngroups+1], and the start
+  // and length of each group's GEMM list ([0]: all blocks as one group)
+  std::vector<int> grp_b0, grp_g0, grp_ng;
   // the rSVD's launches recorded as a HIP graph, replayed while the values
-  // they bake in are unchanged
+  // they bake in are unchanged; a capture stream and an event per group
   hipGraphExec_t graph = nullptr;
   std::vector<uint64_t> graph_key;
-  hipStream_t cap = nullptr;
+  hipStream_t cap[kGroups] = {};
+  hipEvent_t ev[kGroups] = {};
 };
 
 static void rsvd_delete(void* p) {
@@ -1757,8 +1780,11 @@ static void rsvd_delete(void* p) {
   DevBuf* bufs[] = {&R->meta, &R->A, &R->Y, &R->S, &R->ST, &R->Gpart, &R->Li,
                     &R->Ut, &R->sig, &R->fail, &R->omega, &R->U, &R->dT, &R->Tpart};
   for (DevBuf* b : bufs) b->release();
-  if (R->graph) hipGraphExecDestroy(R->graph);
-  if (R->cap) hipStreamDestroy(R->cap);
+  if (R->graph) (void)hipGraphExecDestroy(R->graph);
+  for (hipStream_t c : R->cap)
+    if (c) (void)hipStreamDestroy(c);
+  for (hipEvent_t e : R->ev)
+    if (e) (void)hipEventDestroy(e);
   delete R;
 }
 
@@ -1823,9 +1849,15 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
   // loaded, load = items x rows) and the launch interleaves the XCDs'
   // lists: every item of a block then runs on one XCD, whose L2 keeps the
   // block's S' for all of them.
-  {
-    std::vector<int> order(n_blocks);
-    for (int b = 0; b < n_blocks; ++b) order[b] = b;
+  // One list for all blocks, then one per group (each a multiple of kXcd
+  // long, so a group's launch keeps the dealing).
+  R.gemm_b.clear();
+  R.gemm_t.clear();
+  R.grp_g0.clear();
+  R.grp_ng.clear();
+  auto deal = [&](int b_lo, int b_hi) {
+    std::vector<int> order;
+    for (int b = b_lo; b < b_hi; ++b) order.push_back(b);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return R.nbp[x] > R.nbp[y]; });
     std::vector<std::vector<int>> lists(kXcd);
     std::vector<int64_t> load(kXcd, 0);
@@ -1836,13 +1868,23 @@ static int rsvd_setup(hgl_handle* h, Rsvd& R, int n_blocks, const int32_t* offs,
     }
     size_t len = 0;
     for (const auto& v : lists) len = std::max(len, v.size());
-    R.gemm_b.assign(len * kXcd, -1);
-    R.gemm_t.assign(len * kXcd, 0);
+    const size_t g0 = R.gemm_b.size();
+    R.gemm_b.resize(g0 + len * kXcd, -1);
+    R.gemm_t.resize(g0 + len * kXcd, 0);
     for (int x = 0; x < kXcd; ++x)
       for (size_t j = 0; j < lists[x].size(); ++j) {
-        R.gemm_b[j * kXcd + x] = R.pair_b[lists[x][j]];
-        R.gemm_t[j * kXcd + x] = R.pair_t[lists[x][j]];
+        R.gemm_b[g0 + j * kXcd + x] = R.pair_b[lists[x][j]];
+        R.gemm_t[g0 + j * kXcd + x] = R.pair_t[lists[x][j]];
       }
+    R.grp_g0.push_back(int(g0));
+    R.grp_ng.push_back(int(len * kXcd));
+  };
+  deal(0, n_blocks);
+  const int ngrp = std::min(kGroups, n_blocks);
+  R.grp_b0.assign(1, 0);
+  for (int g = 0; g < ngrp; ++g) {
+    R.grp_b0.push_back(int(int64_t(n_blocks) * (g + 1) / ngrp));
+    deal(R.grp_b0[g], R.grp_b0[g + 1]);
   }
   R.a_elems = a;
   R.y_elems = y;
@@ -1940,18 +1982,47 @@ static int with_lp(int LP, F&& f) {
   }
 }
 
-static int launch_gemm(hgl_handle* h, Rsvd& R, hipStream_t s) {
-  const int n_items = int(R.item_b.size());
-  if (R.f64) {
-    launch(h, -1, k_gemm_f64, dim3(n_items), dim3(kBlock), 0, s, R.bm, R.A.as<double>(),
-                       R.ST.as<double>(), R.Y.as<double>());
-  } else {
-    HGL_TRY(with_lp(R.LP, [&](auto c) {
-      constexpr int LP = decltype(c)::value;
-      launch(h, -1, k_gemm_bf16<LP>, dim3(int(R.gemm_b.size())), dim3(kGemmT), 0, s, R.bm, R.A.as<uint16_t>(),
-                         R.ST.as<uint16_t>(), R.y_elems, R.Y.as<float>());
-      return HGL_OK;
-    }));
+// Consecutive blocks whose chain of launches runs on one stream: the blocks
+// are independent, so while one group's single-CU steps (Cholesky, the
+// small eigenproblem) hold a few CUs, another group's products fill the rest.
+struct Grp {
+  BlockMeta bm;   // the handle's, with the group's first block and items
+  hipStream_t s;
+  int nb, npair, nitem, ngemm;
+};
+
+// All blocks as one group on s, or the layout's groups on st[0..].
+static std::vector<Grp> groups_of(const Rsvd& R, bool split, hipStream_t s, const hipStream_t* st) {
+  std::vector<Grp> G;
+  if (!split || R.grp_b0.size() < 3) {
+    G.push_back({R.bm, s, R.nb, int(R.pair_b.size()), int(R.item_b.size()), R.grp_ng[0]});
+    return G;
+  }
+  for (size_t g = 0; g + 1 < R.grp_b0.size(); ++g) {
+    const int b0 = R.grp_b0[g], b1 = R.grp_b0[g + 1];
+    Grp x{R.bm, st[g], b1 - b0, R.pair0[b1] - R.pair0[b0], R.item0[b1] - R.item0[b0], R.grp_ng[g + 1]};
+    x.bm.b0 = b0;
+    x.bm.p0 = R.pair0[b0];
+    x.bm.i0 = R.item0[b0];
+    x.bm.g0 = R.grp_g0[g + 1];
+    G.push_back(x);
+  }
+  return G;
+}
+
+static int launch_gemm(hgl_handle* h, Rsvd& R, const std::vector<Grp>& G) {
+  for (const Grp& g : G) {
+    if (R.f64) {
+      launch(h, -1, k_gemm_f64, dim3(g.nitem), dim3(kBlock), 0, g.s, g.bm, R.A.as<double>(), R.ST.as<double>(),
+             R.Y.as<double>());
+    } else {
+      HGL_TRY(with_lp(R.LP, [&](auto c) {
+        constexpr int LP = decltype(c)::value;
+        launch(h, -1, k_gemm_bf16<LP>, dim3(g.ngemm), dim3(kGemmT), 0, g.s, g.bm, R.A.as<uint16_t>(),
+               R.ST.as<uint16_t>(), R.y_elems, R.Y.as<float>());
+        return HGL_OK;
+      }));
+    }
   }
   HGL_HIP(hipGetLastError());
   return HGL_OK;
@@ -1959,93 +2030,109 @@ static int launch_gemm(hgl_handle* h, Rsvd& R, hipStream_t s) {
 
 // Gram tile partials of Yb, then each block's sum over its first partial.
 template <class TY>
-static int launch_gram(hgl_handle* h, Rsvd& R, const DevBuf& Yb, hipStream_t s) {
-  const int n_items = int(R.item_b.size());
-  HGL_TRY(with_lp(R.LP, [&](auto c) {
-    constexpr int LP = decltype(c)::value;
-    launch(h, -1, k_gram_tiles<TY, LP>, dim3(int(R.pair_b.size())), dim3(kGramT), 0, s, R.bm, Yb.as<TY>(),
-           R.Gpart.as<double>());
-    return HGL_OK;
-  }));
+static int launch_gram(hgl_handle* h, Rsvd& R, const DevBuf& Yb, const std::vector<Grp>& G) {
   const int npairs = R.l * (R.l + 1) / 2;
-  launch(h, -1, k_gram_reduce, dim3((npairs + 255) / 256, R.nb), dim3(256), 0, s, R.bm, R.pair0_d,
-         R.Gpart.as<double>());
+  for (const Grp& g : G) {
+    HGL_TRY(with_lp(R.LP, [&](auto c) {
+      constexpr int LP = decltype(c)::value;
+      launch(h, -1, k_gram_tiles<TY, LP>, dim3(g.npair), dim3(kGramT), 0, g.s, g.bm, Yb.as<TY>(),
+             R.Gpart.as<double>());
+      return HGL_OK;
+    }));
+    launch(h, -1, k_gram_reduce, dim3((npairs + 255) / 256, g.nb), dim3(256), 0, g.s, g.bm, R.pair0_d,
+           R.Gpart.as<double>());
+  }
   HGL_HIP(hipGetLastError());
   return HGL_OK;
 }
 
 // S, ST <- orth(Y) by CholQR2 (Y is overwritten by the first pass).
 template <class TY, class TST>
-static int cholqr(hgl_handle* h, Rsvd& R, hipStream_t s, int passes) {
-  const int n_items = int(R.item_b.size());
+static int cholqr(hgl_handle* h, Rsvd& R, const std::vector<Grp>& G, int passes) {
   const size_t lds_chol = sizeof(double) * 2 * size_t(R.LP) * (R.LP + 1);
-  prof_begin(h, kProfQr, s);
+  prof_begin(h, kProfQr, G[0].s);
   for (int pass = 0; pass < passes; ++pass) {
     DevBuf& in = pass == 0 ? R.Y : R.S;
     DevBuf& out = pass == 0 ? R.S : R.Y;
-    HGL_TRY(launch_gram<TY>(h, R, in, s));
-    HGL_TRY(with_lp(R.LP, [&](auto c) -> int {
-      constexpr int NX = decltype(c)::value / 16;
-      HGL_TRY(allow_lds(k_chol_inv<NX>, lds_chol));
-      launch(h, -1, k_chol_inv<NX>, dim3(R.nb), dim3(kCholT), lds_chol, s, R.bm, R.pair0_d, R.Gpart.as<double>(),
-             R.Li.as<double>(), R.fail.as<int32_t>());
-      return HGL_OK;
-    }));
-    HGL_TRY(with_lp(R.LP, [&](auto c) {
-      constexpr int LP = decltype(c)::value;
-      launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(int(R.pair_b.size())), dim3(kApplyT), 0, s, R.bm, in.as<TY>(),
-                         R.Li.as<double>(), out.as<TY>(), R.ST.as<TST>(), R.y_elems);
-      return HGL_OK;
-    }));
+    HGL_TRY(launch_gram<TY>(h, R, in, G));
+    for (const Grp& g : G) {
+      HGL_TRY(with_lp(R.LP, [&](auto c) -> int {
+        constexpr int NX = decltype(c)::value / 16;
+        HGL_TRY(allow_lds(k_chol_inv<NX>, lds_chol));
+        launch(h, -1, k_chol_inv<NX>, dim3(g.nb), dim3(kCholT), lds_chol, g.s, g.bm, R.pair0_d,
+               R.Gpart.as<double>(), R.Li.as<double>(), R.fail.as<int32_t>());
+        return HGL_OK;
+      }));
+      HGL_TRY(with_lp(R.LP, [&](auto c) {
+        constexpr int LP = decltype(c)::value;
+        launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(g.npair), dim3(kApplyT), 0, g.s, g.bm, in.as<TY>(),
+               R.Li.as<double>(), out.as<TY>(), R.ST.as<TST>(), R.y_elems);
+        return HGL_OK;
+      }));
+    }
     HGL_HIP(hipGetLastError());
   }
-  prof_end(h, s);
+  prof_end(h, G[0].s);
   // after two passes the basis is in R.Y; keep it in R.S
   if (passes == 2) std::swap(R.Y, R.S);
   return HGL_OK;
 }
 
+// The launches of Algorithm 1 before the basis product: the ones over all
+// blocks on s0, then each group's chain on its stream (the groups' streams
+// already wait for s0).
 template <class TY, class TST>
-static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16_t* omega, hipStream_t s) {
-  launch(h, -1, k_zero_i32, dim3((R.nb + 255) / 256), dim3(256), 0, s, R.fail.as<int32_t>(), R.nb);
-  // 1. dense diagonal blocks A_bb
+static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16_t* omega, hipStream_t s0,
+                    const std::vector<Grp>& G, const std::function<int()>& fork) {
+  launch(h, -1, k_zero_i32, dim3((R.nb + 255) / 256), dim3(256), 0, s0, R.fail.as<int32_t>(), R.nb);
   const size_t lds_ex = (R.f64 ? sizeof(double) : sizeof(float)) * kExW * R.max_nbp;
   if (lds_ex > 160 * 1024) {
     set_error("diagonal block too large for LDS staging (%d rows)", R.max_nbp);
     return HGL_EUNSUPPORTED;
   }
-  {
-    dim3 grid((R.max_nbp + kExW - 1) / kExW, R.nb);
-    prof_begin(h, kProfExtract, s);
-    if (R.f64) {
-      HGL_TRY(allow_lds(k_extract_blocks<double>, lds_ex));
-      launch(h, -1, k_extract_blocks<double>, grid, dim3(kExW * kWave), lds_ex, s, R.bm, h->vtx_ptr, h->vtx_edge,
-                         h->edge_ptr, h->edge_vtx, h->s64, h->c64, R.A.as<double>(), R.max_nbp);
-    } else {
-      HGL_TRY(allow_lds(k_extract_blocks<uint16_t>, lds_ex));
-      launch(h, -1, k_extract_blocks<uint16_t>, grid, dim3(kExW * kWave), lds_ex, s, R.bm, h->vtx_ptr, h->vtx_edge,
-                         h->edge_ptr, h->edge_vtx, h->s64, h->c64, R.A.as<uint16_t>(), R.max_nbp);
-    }
-    HGL_HIP(hipGetLastError());
-    prof_end(h, s);
-  }
-  // 2. sketch Omega (caller's, or Philox from the seed: its buffer was
-  // reserved by the caller) into ST
+  // the sketch Omega (caller's, or Philox from the seed: its buffer was
+  // reserved by the caller)
   const uint16_t* om = omega;
   if (!om) {
     const int64_t pairs = (int64_t(h->N) * R.l + 1) / 2;
-    launch(h, -1, k_philox_sketch, dim3(int((pairs + 255) / 256)), dim3(256), 0, s, int64_t(h->N), R.l,
-                       o->seed, R.omega.as<uint16_t>());
+    launch(h, -1, k_philox_sketch, dim3(int((pairs + 255) / 256)), dim3(256), 0, s0, int64_t(h->N), R.l, o->seed,
+           R.omega.as<uint16_t>());
     om = R.omega.as<uint16_t>();
   }
-  launch(h, -1, k_sketch_to_st<TST>, dim3(64, R.nb), dim3(256), 0, s, R.bm, om, R.ST.as<TST>(),
-                     R.y_elems);
+  const bool power = o->scheme == HGL_RSVD_POWER;
+  if (power && o->q > 0) {
+    // the power scheme lays each product out unchanged as the next operand:
+    // identity factors (no orthonormalisation before the last product)
+    const int64_t n = int64_t(R.nb) * R.LP * R.LP;
+    launch(h, -1, k_identity_factor, dim3(int(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, s0, n,
+           R.LP, R.l, R.Li.as<double>());
+  }
   HGL_HIP(hipGetLastError());
-  // 3. Y = A Omega, S = orth(Y); q subspace iterations (or the power scheme)
+  HGL_TRY(fork());
+  // 1. dense diagonal blocks A_bb, and Omega's rows of each block into ST
+  prof_begin(h, kProfExtract, G[0].s);
+  for (const Grp& g : G) {
+    dim3 grid((R.max_nbp + kExW - 1) / kExW, g.nb);
+    if (R.f64) {
+      HGL_TRY(allow_lds(k_extract_blocks<double>, lds_ex));
+      launch(h, -1, k_extract_blocks<double>, grid, dim3(kExW * kWave), lds_ex, g.s, g.bm, h->vtx_ptr, h->vtx_edge,
+             h->edge_ptr, h->edge_vtx, h->s64, h->c64, R.A.as<double>(), R.max_nbp);
+    } else {
+      HGL_TRY(allow_lds(k_extract_blocks<uint16_t>, lds_ex));
+      launch(h, -1, k_extract_blocks<uint16_t>, grid, dim3(kExW * kWave), lds_ex, g.s, g.bm, h->vtx_ptr,
+             h->vtx_edge, h->edge_ptr, h->edge_vtx, h->s64, h->c64, R.A.as<uint16_t>(), R.max_nbp);
+    }
+  }
+  HGL_HIP(hipGetLastError());
+  prof_end(h, G[0].s);
+  for (const Grp& g : G)
+    launch(h, -1, k_sketch_to_st<TST>, dim3(64, g.nb), dim3(256), 0, g.s, g.bm, om, R.ST.as<TST>(), R.y_elems);
+  HGL_HIP(hipGetLastError());
+  // 2. Y = A Omega, S = orth(Y); q subspace iterations (or the power scheme)
   auto gemm = [&]() -> int {
-    prof_begin(h, kProfGemm, s);
-    const int st = launch_gemm(h, R, s);
-    prof_end(h, s);
+    prof_begin(h, kProfGemm, G[0].s);
+    const int st = launch_gemm(h, R, G);
+    prof_end(h, G[0].s);
     return st;
   };
   // Orthonormalisation by CholQR2 (two passes) where the basis must be
@@ -2053,29 +2140,23 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
   // and every one of an FP64 sketch.  Between the products of a BF16 sketch
   // one pass suffices: it only has to keep the basis well conditioned, and
   // the next product and the final CholQR2 act on the subspace it spans.
-  auto orth = [&](bool last) { return cholqr<TY, TST>(h, R, s, (last || R.f64) ? 2 : 1); };
+  auto orth = [&](bool last) { return cholqr<TY, TST>(h, R, G, (last || R.f64) ? 2 : 1); };
   HGL_TRY(gemm());
-  if (o->scheme == HGL_RSVD_POWER) {
+  if (power) {
     // eq. 10: Y = (A A')^q A Omega (A_bb is symmetric: 2q + 1 products with
     // A), each product's result laid out unchanged as the next operand, and
     // one two-pass CholQR of the last Y
-    if (o->q > 0) {
-      const int64_t n = int64_t(R.nb) * R.LP * R.LP;
-      launch(h, -1, k_identity_factor, dim3(int(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, s, n,
-             R.LP, R.l, R.Li.as<double>());
-      HGL_HIP(hipGetLastError());
-    }
-    const int n_items = int(R.item_b.size());
     for (int i = 0; i < 2 * o->q; ++i) {
-      prof_begin(h, kProfQr, s);
-      HGL_TRY(with_lp(R.LP, [&](auto c) {
-        constexpr int LP = decltype(c)::value;
-        launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(int(R.pair_b.size())), dim3(kApplyT), 0, s, R.bm, R.Y.as<TY>(),
-               R.Li.as<double>(), R.S.as<TY>(), R.ST.as<TST>(), R.y_elems);
-        return HGL_OK;
-      }));
+      prof_begin(h, kProfQr, G[0].s);
+      for (const Grp& g : G)
+        HGL_TRY(with_lp(R.LP, [&](auto c) {
+          constexpr int LP = decltype(c)::value;
+          launch(h, -1, k_apply_rinv<TY, TST, LP>, dim3(g.npair), dim3(kApplyT), 0, g.s, g.bm, R.Y.as<TY>(),
+                 R.Li.as<double>(), R.S.as<TY>(), R.ST.as<TST>(), R.y_elems);
+          return HGL_OK;
+        }));
       HGL_HIP(hipGetLastError());
-      prof_end(h, s);
+      prof_end(h, G[0].s);
       HGL_TRY(gemm());
     }
     HGL_TRY(orth(true));
@@ -2086,10 +2167,10 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
       HGL_TRY(orth(i == 2 * o->q - 1));
     }
   }
-  // 4. W = A S; B B' = W'W; Jacobi; U = S U~
+  // 3. W = A S; B B' = W'W; its top eigenpairs
   HGL_TRY(gemm());  // W in R.Y, basis S in R.S
-  prof_begin(h, kProfEig, s);
-  HGL_TRY(launch_gram<TY>(h, R, R.Y, s));
+  prof_begin(h, kProfEig, G[0].s);
+  HGL_TRY(launch_gram<TY>(h, R, R.Y, G));
   const int half = (R.l + (R.l & 1)) / 2;
   if (!R.f64) {
     // BF16 sketch: FP32 tridiagonal eigensolver
@@ -2098,8 +2179,9 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
     };
     const int cw = lds_eig(64) + static_lds(k_eig_tridiag) <= 160 * 1024 ? 64 : 32;
     HGL_TRY(allow_lds(k_eig_tridiag, lds_eig(cw)));
-    launch(h, -1, k_eig_tridiag, dim3(R.nb), dim3(kEigT), lds_eig(cw), s, R.bm, R.pair0_d, R.Gpart.as<double>(),
-           R.sig.as<double>(), R.Ut.as<double>(), cw);
+    for (const Grp& g : G)
+      launch(h, -1, k_eig_tridiag, dim3(g.nb), dim3(kEigT), lds_eig(cw), g.s, g.bm, R.pair0_d, R.Gpart.as<double>(),
+             R.sig.as<double>(), R.Ut.as<double>(), cw);
   } else {
     // FP64 sketch: FP64 cyclic Jacobi, A double-buffered where it fits in
     // LDS; 1024 threads while three tasks per thread cover a round (l <= 90),
@@ -2116,11 +2198,12 @@ static int run_rsvd(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
     JacFn jac = nt == 1024 ? (db ? &k_jacobi<1024, 3, double, true> : &k_jacobi<1024, 3, double, false>)
                            : (db ? &k_jacobi<512, 7, double, true> : &k_jacobi<512, 7, double, false>);
     HGL_TRY(allow_lds(jac, lds_j));
-    launch(h, -1, jac, dim3(R.nb), dim3(nt), lds_j, s, R.bm, R.pair0_d, R.Gpart.as<double>(), R.sig.as<double>(),
-           R.Ut.as<double>(), 30);
+    for (const Grp& g : G)
+      launch(h, -1, jac, dim3(g.nb), dim3(nt), lds_j, g.s, g.bm, R.pair0_d, R.Gpart.as<double>(),
+             R.sig.as<double>(), R.Ut.as<double>(), 30);
   }
   HGL_HIP(hipGetLastError());
-  prof_end(h, s);
+  prof_end(h, G[0].s);
   return HGL_OK;
 }
 
@@ -2142,15 +2225,15 @@ static int check_opts(hgl_handle* h, int n_blocks, const int32_t* offs, const hg
 }
 
 static int finish_rsvd(hgl_handle* h, Rsvd& R, float* U_out, double* sigma_out, hipStream_t s) {
-  const int n_items = int(R.item_b.size());
+  const std::vector<Grp> G = groups_of(R, false, s, nullptr);
   HGL_TRY(with_lp(R.LP, [&](auto c) {
     constexpr int LP = decltype(c)::value;
     if (R.f64)
-      launch(h, -1, k_basis<double, LP>, dim3(int(R.pair_b.size())), dim3(kBasisT), 0, s, R.bm, R.S.as<double>(),
-                         R.Ut.as<double>(), U_out);
+      launch(h, -1, k_basis<double, LP>, dim3(G[0].npair), dim3(kBasisT), 0, s, R.bm, R.S.as<double>(),
+             R.Ut.as<double>(), U_out);
     else
-      launch(h, -1, k_basis<float, LP>, dim3(int(R.pair_b.size())), dim3(kBasisT), 0, s, R.bm, R.S.as<float>(),
-                         R.Ut.as<double>(), U_out);
+      launch(h, -1, k_basis<float, LP>, dim3(G[0].npair), dim3(kBasisT), 0, s, R.bm, R.S.as<float>(),
+             R.Ut.as<double>(), U_out);
     return HGL_OK;
   }));
   HGL_HIP(hipGetLastError());
@@ -2176,14 +2259,46 @@ static int finish_rsvd(hgl_handle* h, Rsvd& R, float* U_out, double* sigma_out, 
 
 // The rSVD's launches, recorded once as a HIP graph on a capture stream and
 // replayed on s while every value they bake in (buffer addresses, the
-// layout, the options, the sketch) is unchanged; direct launches while
-// kernel timing is on.  The graph holds kernels only.
+// layout, the options, the sketch) is unchanged: the launches over all
+// blocks, then a fork into the groups' chains (one capture stream each)
+// and a join.  Direct launches, the first group on s and the others on
+// spare streams, while kernel timing is on.  The graph holds kernels only.
 static int rsvd_any(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16_t* omega, hipStream_t s) {
   if (!omega) HGL_TRY(R.omega.reserve(sizeof(uint16_t) * size_t(h->N) * R.l + 16));
-  auto run = [&](hipStream_t st) {
-    return R.f64 ? run_rsvd<double, double>(h, R, o, omega, st) : run_rsvd<float, uint16_t>(h, R, o, omega, st);
+  auto run = [&](hipStream_t s0, const std::vector<Grp>& G, const std::function<int()>& fork) {
+    return R.f64 ? run_rsvd<double, double>(h, R, o, omega, s0, G, fork)
+                 : run_rsvd<float, uint16_t>(h, R, o, omega, s0, G, fork);
   };
-  if (h->prof_on) return run(s);
+  for (int g = 1; g < kGroups; ++g)
+    if (!R.cap[g]) HGL_HIP(hipStreamCreateWithFlags(&R.cap[g], hipStreamNonBlocking));
+  if (!R.ev[0])
+    for (auto& e : R.ev) HGL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  // fork: the other groups' streams wait for what is queued on st[0] so far
+  auto forker = [&](const std::vector<Grp>& G, const hipStream_t* st) {
+    return [&G, st, &R]() -> int {
+      if (G.size() > 1) {
+        HGL_HIP(hipEventRecord(R.ev[0], st[0]));
+        for (size_t g = 1; g < G.size(); ++g) HGL_HIP(hipStreamWaitEvent(st[g], R.ev[0], 0));
+      }
+      return HGL_OK;
+    };
+  };
+  auto join = [&](const std::vector<Grp>& G, const hipStream_t* st) -> int {
+    for (size_t g = 1; g < G.size(); ++g) {
+      HGL_HIP(hipEventRecord(R.ev[g], st[g]));
+      HGL_HIP(hipStreamWaitEvent(st[0], R.ev[g], 0));
+    }
+    return HGL_OK;
+  };
+  if (h->prof_on) {
+    // direct launches: the groups on s and the spare streams
+    hipStream_t st[kGroups];
+    st[0] = s;
+    for (int g = 1; g < kGroups; ++g) st[g] = R.cap[g];
+    const std::vector<Grp> G = groups_of(R, true, s, st);
+    HGL_TRY(run(s, G, forker(G, st)));
+    return join(G, st);
+  }
   auto u = [](const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); };
   const std::vector<uint64_t> key = {R.layout_gen, u(R.meta.p), u(R.A.p), u(R.Y.p), u(R.S.p), u(R.ST.p),
                                      u(R.Gpart.p), u(R.Li.p), u(R.Ut.p), u(R.sig.p), u(R.fail.p), u(R.omega.p),
@@ -2195,18 +2310,22 @@ static int rsvd_any(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
       HGL_HIP(hipGraphExecDestroy(R.graph));
       R.graph = nullptr;
     }
-    if (!R.cap) HGL_HIP(hipStreamCreateWithFlags(&R.cap, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    HGL_HIP(hipStreamBeginCapture(R.cap, hipStreamCaptureModeThreadLocal));
-    const int rc = run(R.cap);
-    const hipError_t e = hipStreamEndCapture(R.cap, &g);
+    if (!R.cap[0]) HGL_HIP(hipStreamCreateWithFlags(&R.cap[0], hipStreamNonBlocking));
+    // the groups' streams join the capture after the launches over all
+    // blocks, and the capture stream waits for them at the end
+    const std::vector<Grp> G = groups_of(R, true, R.cap[0], R.cap);
+    hipGraph_t gr = nullptr;
+    HGL_HIP(hipStreamBeginCapture(R.cap[0], hipStreamCaptureModeThreadLocal));
+    int rc = run(R.cap[0], G, forker(G, R.cap));
+    if (rc == HGL_OK) rc = join(G, R.cap);
+    const hipError_t e = hipStreamEndCapture(R.cap[0], &gr);
     if (rc != HGL_OK) {
-      if (g) hipGraphDestroy(g);
+      if (gr) (void)hipGraphDestroy(gr);
       return rc;
     }
     HGL_HIP(e);
-    const hipError_t e2 = hipGraphInstantiate(&R.graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    const hipError_t e2 = hipGraphInstantiate(&R.graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
     HGL_HIP(e2);
     R.graph_key = key;
   }
