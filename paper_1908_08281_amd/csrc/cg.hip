@@ -404,7 +404,9 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
     ag = ra.ab[g];
     bg = ra.ab[ra.G + g];
   }
-  if (gate == 0) return;  // uniform: no column iterates
+  // (the gate is tested after the sums: its load and the slot loads are in
+  // flight together, and a gated-off launch, which reads valid slots it
+  // then ignores, only happens after the last iteration)
   int sl[4], esl[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -474,6 +476,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_reduce(RedArgs ra, CgState s
   } else if (!ra.has_prec) {
     rz = sum;  // r'z = r'r without a preconditioner
   }
+  if (gate == 0) return;  // uniform: no column iterates
   if (threadIdx.x >= kRedCols) return;
   // the per-column step: the counters it raises are added up over the
   // workgroup's columns first, so each flag word takes one atomic per
