@@ -2300,12 +2300,16 @@ static int rsvd_any(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
     return join(G, st);
   }
   auto u = [](const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); };
-  const std::vector<uint64_t> key = {R.layout_gen, u(R.meta.p), u(R.A.p), u(R.Y.p), u(R.S.p), u(R.ST.p),
-                                     u(R.Gpart.p), u(R.Li.p), u(R.Ut.p), u(R.sig.p), u(R.fail.p), u(R.omega.p),
-                                     u(omega), u(h->vtx_ptr), u(h->vtx_edge), u(h->edge_ptr), u(h->edge_vtx),
-                                     u(h->s64), u(h->c64), uint64_t(o->k), uint64_t(o->p), uint64_t(o->q),
-                                     uint64_t(o->scheme), uint64_t(o->sketch), o->seed};
-  if (!R.graph || key != R.graph_key) {
+  // (the host swaps the roles of R.Y and R.S while it records; a replay
+  // does not, so the key a replay must match is the one after recording)
+  auto key_now = [&]() {
+    return std::vector<uint64_t>{R.layout_gen, u(R.meta.p), u(R.A.p), u(R.Y.p), u(R.S.p), u(R.ST.p),
+                                 u(R.Gpart.p), u(R.Li.p), u(R.Ut.p), u(R.sig.p), u(R.fail.p), u(R.omega.p),
+                                 u(omega), u(h->vtx_ptr), u(h->vtx_edge), u(h->edge_ptr), u(h->edge_vtx),
+                                 u(h->s64), u(h->c64), uint64_t(o->k), uint64_t(o->p), uint64_t(o->q),
+                                 uint64_t(o->scheme), uint64_t(o->sketch), o->seed};
+  };
+  if (!R.graph || key_now() != R.graph_key) {
     if (R.graph) {
       HGL_HIP(hipGraphExecDestroy(R.graph));
       R.graph = nullptr;
@@ -2327,7 +2331,7 @@ static int rsvd_any(hgl_handle* h, Rsvd& R, const hgl_rsvd_opts* o, const uint16
     const hipError_t e2 = hipGraphInstantiate(&R.graph, gr, nullptr, nullptr, 0);
     (void)hipGraphDestroy(gr);
     HGL_HIP(e2);
-    R.graph_key = key;
+    R.graph_key = key_now();
   }
   HGL_HIP(hipGraphLaunch(R.graph, s));
   return HGL_OK;

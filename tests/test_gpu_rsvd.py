@@ -237,3 +237,29 @@ def test_full_size_tessellation():
     cols = np.arange(0, p.Y.shape[1], 7)
     fo, _, relo = solve.cg_ranking(op, p.w, p.lam, p.Y[:, cols], tol=1e-13)
     assert colrelerr(F.cpu().numpy()[:, cols], fo).max() <= 1e-6
+
+
+def test_recorded_graph_replays_match_direct_launches():
+    """The rSVD's launches are recorded once and replayed (the host swaps
+    the roles of two buffers while recording): replays, a new recording
+    after direct launches, and the direct launches themselves give the same
+    U and sigma bit for bit."""
+    import torch
+    dev = device()
+    p = _tess_problem()
+    k, pp, q = 24, 8, 2
+    bits, _ = _omega(p, k + pp, 9)
+    say("rsvd graph replays vs direct launches")
+    h = build(p, dev)
+    om = _to_dev_bits(bits, dev)
+    runs = []
+    for mode in ("graph", "graph", "graph", "direct", "graph", "graph"):
+        if mode == "direct":
+            hgl().profile(h, True)
+        U, sig = hgl().block_rsvd(h, p.blocks, k, pp, q, sketch="bf16", omega=om)
+        torch.cuda.synchronize()
+        if mode == "direct":
+            hgl().profile(h, False)
+        runs.append((U.cpu().numpy(), sig.cpu().numpy()))
+    for U, sig in runs[1:]:
+        assert np.array_equal(U, runs[0][0]) and np.array_equal(sig, runs[0][1])
