@@ -477,6 +477,7 @@ int hgl_block_schur_invert(hgl_handle* h, double lambda, int32_t n_blocks, const
  *   leaves [leaves x 5]: in, out, ldi, ldo, n (out = inverse of in);
  *   phases [phases x 5]: first tile, tiles, first leaf, leaves, largest leaf;
  *   tiles  [tiles x 2]: product, (tile row << 16) | tile column (64 x 64);
+ *                       in XCD order, product -1 for an empty slot;
  *   moff   [n_blocks]: workspace offset of M_bb (n_b x n_b row-major).
  * Block b's inverse sits at offset sum_{c<b} n_c^2 (ld n_b).  Within a
  * phase the leaves and products are independent; phases run in order.

@@ -121,7 +121,9 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
   if (gate.skip()) return;
   __shared__ float As[2][kGK][kGT + 4];
   __shared__ float Bs[2][kGK][kGT + 4];
-  const GemmTask t = tasks[tile_task[blockIdx.x]];
+  const int32_t task = tile_task[blockIdx.x];
+  if (task < 0) return;   // padding of the XCD order
+  const GemmTask t = tasks[task];
   const int mn = tile_mn[blockIdx.x];
   const int m0 = (mn >> 16) * kGT, n0 = (mn & 0xffff) * kGT;
   const float* A = Abase + t.a;
@@ -144,18 +146,27 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
   const int ar = tid / kAT, ak = (tid % kAT) * kAPT;  // A stage: row, first k
   const int bk = tid / kBT, bc = (tid % kBT) * kAPT;  // B stage: k, first column
   float ra[kAPT], rb[kAPT];
+  // (no branches around the loads: an element outside the operand reads
+  // the operand's first element, and the store replaces it by zero, so the
+  // loads stay in flight through the MFMAs)
+  uint32_t okA = 0, okB = 0;
   auto load = [&](int k0) {
     const int gr = m0 + ar;
+    okA = okB = 0;
 #pragma unroll
     for (int j = 0; j < kAPT; ++j) {
       const int gk = k0 + ak + j;
-      ra[j] = (gr < t.m && gk < t.k) ? A[int64_t(gr) * t.lda + gk] : 0.f;
+      const bool ok = gr < t.m && gk < t.k;
+      ra[j] = A[ok ? int64_t(gr) * t.lda + gk : 0];
+      okA |= uint32_t(ok) << j;
     }
     const int gk = k0 + bk;
 #pragma unroll
     for (int j = 0; j < kAPT; ++j) {
       const int gc = n0 + bc + j;
-      rb[j] = (gk < t.k && gc < t.n) ? B[int64_t(gk) * ldb + gc] : 0.f;
+      const bool ok = gk < t.k && gc < t.n;
+      rb[j] = B[ok ? int64_t(gk) * ldb + gc : 0];
+      okB |= uint32_t(ok) << j;
     }
   };
   constexpr int kWT = kGT / 2, kFT = kWT / 16;  // wave tile, MFMA fragments along each side
@@ -169,8 +180,8 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
   auto store = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < kAPT; ++j) {
-      As[buf][ak + j][ar] = ra[j];
-      Bs[buf][bk][bc + j] = rb[j];
+      As[buf][ak + j][ar] = (okA >> j) & 1u ? ra[j] : 0.f;
+      Bs[buf][bk][bc + j] = (okB >> j) & 1u ? rb[j] : 0.f;
     }
   };
   load(0);
@@ -197,6 +208,25 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
     __syncthreads();
     cur ^= 1;
   }
+  // C's elements loaded all at once (an element outside the tile reads C's
+  // first one, unused), then the outputs
+  float cv[kFT][kFT][4] = {};
+  if constexpr (!PREC) {
+    if (t.beta != 0.f) {   // uniform
+#pragma unroll
+      for (int i = 0; i < kFT; ++i)
+#pragma unroll
+        for (int j = 0; j < kFT; ++j) {
+          const int col = n0 + wc + j * 16 + r;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = m0 + wr + i * 16 + q * 4 + v;
+            const bool ok = row < t.m && col < t.n;
+            cv[i][j][v] = Cbase[t.c + (ok ? int64_t(row) * t.ldc + col : 0)];
+          }
+        }
+    }
+  }
 #pragma unroll
   for (int i = 0; i < kFT; ++i)
 #pragma unroll
@@ -208,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_schur_gemm(const GemmTask* __restric
         if (row < t.m && col < t.n) {
           float val = t.alpha * acc[i][j][v];
           if constexpr (!PREC) {
-            if (t.beta != 0.f) val += t.beta * Cbase[t.c + int64_t(row) * t.ldc + col];
+            if (t.beta != 0.f) val += t.beta * cv[i][j][v];
           }
           D[int64_t(row) * ldd + col] = val;
         }
@@ -494,10 +524,32 @@ int make_plan(int n_blocks, const int32_t* offs, int min_block, Plan& out) {
   for (int p = 0; p < n_phases; ++p) {
     Phase& ph = out.phases[p];
     ph.tile0 = int32_t(out.tt.size());
-    for (const GemmTask& t : P.g[p]) {
-      add_tiles(t, int32_t(out.tasks.size()), out.tt, out.tmn);
-      out.tasks.push_back(t);
+    // Tiles in XCD order: the dispatcher deals workgroup w to XCD w mod 8,
+    // so the phase's products are dealt to the XCDs (most tiles first, each
+    // to the least loaded) and the launch interleaves the XCDs' lists: all
+    // tiles of a product then run on one XCD, whose L2 keeps its operands'
+    // panels.  Short lists are padded with empty tiles (product -1).
+    std::vector<std::vector<int32_t>> xt(kXcd), xmn(kXcd);
+    std::vector<int64_t> load(kXcd, 0);
+    std::vector<int32_t> order(P.g[p].size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = int32_t(i);
+    auto ntile = [&](const GemmTask& t) { return int64_t((t.m + kGT - 1) / kGT) * ((t.n + kGT - 1) / kGT); };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return ntile(P.g[p][x]) > ntile(P.g[p][y]); });
+    const int32_t task0 = int32_t(out.tasks.size());
+    for (int32_t i : order) {
+      const int x = int(std::min_element(load.begin(), load.end()) - load.begin());
+      add_tiles(P.g[p][i], task0 + i, xt[x], xmn[x]);
+      load[x] += ntile(P.g[p][i]) * P.g[p][i].k;
     }
+    for (const GemmTask& t : P.g[p]) out.tasks.push_back(t);
+    size_t len = 0;
+    for (const auto& v : xt) len = std::max(len, v.size());
+    for (size_t j = 0; j < len; ++j)
+      for (int x = 0; x < kXcd; ++x) {
+        out.tt.push_back(j < xt[x].size() ? xt[x][j] : -1);
+        out.tmn.push_back(j < xmn[x].size() ? xmn[x][j] : 0);
+      }
     ph.tiles = int32_t(out.tt.size()) - ph.tile0;
     ph.leaf0 = int32_t(out.leaves.size());
     for (const LeafTask& t : P.l[p]) {

@@ -49,7 +49,12 @@ def run_plan(plan, M_blocks):
             writes.append(dst)
             results.append(np.linalg.inv(X))
         ph_tiles = tiles[tile0:tile0 + ntiles]
+        # empty slots (product -1) pad the XCD order: the tiles of a product
+        # all sit at positions of one residue modulo 8
         for t in dict.fromkeys(ph_tiles[:, 0].tolist()):
+            if t < 0:
+                continue
+            assert len(set((np.nonzero(ph_tiles[:, 0] == t)[0] % 8).tolist())) == 1
             a, b, c, d, lda, ldb, ldc, ldd, m, n, k, alpha, beta = tasks[t].tolist()
             mine = ph_tiles[ph_tiles[:, 0] == t, 1]
             want = {(i << 16) | j for i in range(-(-m // 64)) for j in range(-(-n // 64))}
