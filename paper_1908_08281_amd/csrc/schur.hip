@@ -263,8 +263,10 @@ constexpr int kLeafSlots = 128 / kLeafGroups;        // rows held per thread
 static_assert(kLeafMax < 128, "a leaf fits the padded 128 x 128 layout");
 __global__ __launch_bounds__(kLeafThreads) void k_schur_leaf(const LeafTask* __restrict__ tasks,
                                                              float* __restrict__ arena) {
+  // column k by row group: rows g + 8 j at g * 16 + j, so that a thread
+  // reads its 16 entries as four 16-byte loads
   __shared__ float rowb[2][128];
-  __shared__ float colb[2][128];
+  __shared__ __align__(16) float colb[2][128];
   const LeafTask t = tasks[blockIdx.x];
   const int n = t.n;
   const int c = threadIdx.x & 127, g = threadIdx.x >> 7;
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_schur_leaf(const LeafTask* __r
     const int jk = k / kLeafGroups;
     if (c == k) {
 #pragma unroll
-      for (int j = 0; j < kLeafSlots; ++j) colk[g + kLeafGroups * j] = (owner && j == jk) ? -1.0f : x[j];
+      for (int j = 0; j < kLeafSlots; ++j) colk[g * kLeafSlots + j] = (owner && j == jk) ? -1.0f : x[j];
     }
     if (owner) {
 #pragma unroll
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_schur_leaf(const LeafTask* __r
     const float inv = 1.0f / rowk[k];
     const float rk = (c == k ? 1.0f : rowk[c]) * inv;
 #pragma unroll
-    for (int j = 0; j < kLeafSlots; ++j) x[j] = fma(-colk[g + kLeafGroups * j], rk, x[j]);
+    for (int j = 0; j < kLeafSlots; ++j) x[j] = fma(-colk[g * kLeafSlots + j], rk, x[j]);
   }
   if (c < n) {
 #pragma unroll
