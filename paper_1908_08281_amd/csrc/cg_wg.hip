@@ -42,7 +42,7 @@
 #include <type_traits>
 #include <vector>
 
-#include "common.h"
+#include "kernels.h"
 
 namespace hgl {
 namespace {
@@ -100,42 +100,31 @@ __device__ __forceinline__ void load_share(const uint32_t* tab, Share& sh) {
   sh.mask = tab[(kSlotW + 2) * kWg + t];
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
-  return x;
-}
-
 // Workgroup sums of x and y, identical in every thread, in a fixed order:
-// a lane butterfly per wave, then wave 0's first kWgWaves lanes add the
-// waves' sums by a butterfly of their own and broadcast the two totals.
-// red: 2 * kWgWaves + 2 doubles.
-__device__ __forceinline__ void wg_sum2(double& x, double& y, double* red) {
+// each wave's sum by DPP row sums and four lane reads, then every thread
+// adds the waves' sums in wave order.  red: 4 * kWgWaves doubles, two
+// halves used by alternate calls (par), so the one barrier both publishes
+// this call's sums and orders the last-but-one call's reads of the half
+// before this call's writes.  To the caller the call is one barrier.
+__device__ __forceinline__ void wg_sum2(double& x, double& y, double* red, int& par) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  x = wave_sum(x);
-  y = wave_sum(y);
+  x = wave_sum_dpp(x);
+  y = wave_sum_dpp(y);
+  double* const half = red + par * 2 * kWgWaves;
+  par ^= 1;
   if (lane == 0) {
-    red[wave] = x;
-    red[kWgWaves + wave] = y;
+    half[wave] = x;
+    half[kWgWaves + wave] = y;
   }
   __syncthreads();
-  if (wave == 0) {
-    double sx = lane < kWgWaves ? red[lane] : 0.0;
-    double sy = lane < kWgWaves ? red[kWgWaves + lane] : 0.0;
+  double sx = 0.0, sy = 0.0;
 #pragma unroll
-    for (int m = kWgWaves / 2; m >= 1; m >>= 1) {
-      sx += __shfl_xor(sx, m);
-      sy += __shfl_xor(sy, m);
-    }
-    if (lane == 0) {
-      red[2 * kWgWaves] = sx;
-      red[2 * kWgWaves + 1] = sy;
-    }
+  for (int w = 0; w < kWgWaves; ++w) {
+    sx += half[w];
+    sy += half[kWgWaves + w];
   }
-  __syncthreads();
-  x = red[2 * kWgWaves];
-  y = red[2 * kWgWaves + 1];
-  __syncthreads();  // red is reused by the next call
+  x = sx;
+  y = sy;
 }
 
 // Row sums of val over one CSR: out[q] = sum of val[idx] over row q's
@@ -192,7 +181,8 @@ __device__ __attribute__((noinline)) void share_gather(const uint32_t* tab, cons
 
 __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
   extern __shared__ __align__(16) double wg_lds[];
-  __shared__ double red[2 * kWgWaves + 2];
+  __shared__ double red[4 * kWgWaves];
+  int par = 0;   // the half of red the next wg_sum2 writes
   const int tid = threadIdx.x, col = blockIdx.x, g = blockIdx.y;
   const int32_t* dg = A.desc + kDesc * g;
   const int N = dg[0], E = dg[1], nq = dg[2], voff = dg[3], eoff = dg[4];
@@ -240,7 +230,7 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
       yy += double(y) * double(y);
     }
   }
-  wg_sum2(yy, unused, red);
+  wg_sum2(yy, unused, red, par);
   if (yy == 0.0) {  // zero column: f = 0 exactly
 #pragma unroll
     for (int i = 0; i < kRowsPT; ++i) {
@@ -303,7 +293,7 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
       r2 += rt * rt;
       p2 += double(p[i]) * double(p[i]);
     });
-    wg_sum2(r2, p2, red);  // its barriers publish Ps
+    wg_sum2(r2, p2, red, par);  // its barrier publishes Ps
     rr = r2;
     pp = p2;
   };
@@ -329,7 +319,7 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
       }
     }
     double r2 = p2;
-    wg_sum2(r2, p2, red);
+    wg_sum2(r2, p2, red, par);
     rr = r2;
     pp = p2;
   }
@@ -356,7 +346,7 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
     // p'Mp = a p'p - b sum_e c_e u_e^2
     double ep = edge_phase(Psf, Uf);
     double unused2 = 0.0;
-    wg_sum2(ep, unused2, red);  // its barriers complete Z
+    wg_sum2(ep, unused2, red, par);  // its barrier completes Z
     const double pmp = a * pp - bb * ep;
     if (!(pmp > 0.0) || !std::isfinite(pmp)) {
       st = -4;
@@ -372,7 +362,7 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
       r2 += double(r[i]) * double(r[i]);
     });
     double unused3 = 0.0;
-    wg_sum2(r2, unused3, red);
+    wg_sum2(r2, unused3, red, par);
     ++it;
     const double beta = r2 / rr;
     rr = r2;
@@ -389,7 +379,7 @@ __global__ __launch_bounds__(kWg) void k_cg_wg(WgArgs A) {
       }
     }
     double unused4 = 0.0;
-    wg_sum2(p2, unused4, red);  // its barriers publish Ps to the edge gather
+    wg_sum2(p2, unused4, red, par);  // its barrier publishes Ps to the edge gather
     pp = p2;
   }
 
