@@ -45,7 +45,7 @@ void Mem::release(void* p) {
   if (al.alloc) {
     if (al.free) al.free(p, al.ctx, stream);
   } else {
-    hipFree(p);
+    (void)hipFree(p);
   }
 }
 
@@ -75,7 +75,7 @@ int DevBuf::reserve(size_t n) {
 void DevBuf::release() {
   if (p) {
     if (mem) mem->release(p);
-    else hipFree(p);
+    else (void)hipFree(p);
   }
   p = nullptr;
   bytes = 0;
@@ -92,7 +92,7 @@ static int dev_alloc(hgl_handle* h, T** p, size_t count) {
 int ensure_pinned(hgl_handle* h, size_t n) {
   if (!h->pinned_i) HGL_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->pinned_i), 64 * sizeof(int32_t)));
   if (n > h->pinned_d_len) {
-    if (h->pinned_d) hipHostFree(h->pinned_d);
+    if (h->pinned_d) (void)hipHostFree(h->pinned_d);
     h->pinned_d = nullptr;
     h->pinned_d_len = 0;
     HGL_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->pinned_d), n * sizeof(double)));
@@ -122,7 +122,7 @@ void prof_end(hgl_handle* h, hipStream_t) { h->prof_kind = -1; }
 
 static void prof_collect(hgl_handle* h) {
   if (h->prof_pending.empty()) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   for (auto& p : h->prof_pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
@@ -510,15 +510,15 @@ static void free_handle(hgl_handle* h) {
   h->wg_tab.release();
   if (h->rsvd_free) h->rsvd_free(h->rsvd_ws);
   if (h->schur_free) h->schur_free(h->schur_ws);
-  if (h->cg_graph) hipGraphExecDestroy(h->cg_graph);
-  if (h->capture_stream) hipStreamDestroy(h->capture_stream);
-  if (h->pinned_i) hipHostFree(h->pinned_i);
-  if (h->pinned_d) hipHostFree(h->pinned_d);
+  if (h->cg_graph) (void)hipGraphExecDestroy(h->cg_graph);
+  if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+  if (h->pinned_i) (void)hipHostFree(h->pinned_i);
+  if (h->pinned_d) (void)hipHostFree(h->pinned_d);
   for (auto& p : h->prof_pending) {
-    hipEventDestroy(p.second.first);
-    hipEventDestroy(p.second.second);
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
   }
-  for (hipEvent_t e : h->prof_pool) hipEventDestroy(e);
+  for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -588,13 +588,13 @@ static int build(int32_t G, const int32_t* vtx_off_host, const int32_t* edge_off
   h->E = E;
   h->G = G;
   h->nnz = nnz;
-  hipGetDevice(&h->device);
+  (void)hipGetDevice(&h->device);
   h->vtx_off.assign(vtx_off_host, vtx_off_host + G + 1);
   h->edge_off.assign(edge_off_host, edge_off_host + G + 1);
   Temps tmp{h, {}};
 
   auto fail = [&](int code) {
-    hipStreamSynchronize(s);  // queued work may still use the temporaries
+    (void)hipStreamSynchronize(s);  // queued work may still use the temporaries
     tmp.release();
     free_handle(h);
     return code;
@@ -921,7 +921,7 @@ extern "C" int hgl_set_weights(hgl_handle* h, const double* w, hipStream_t s) {
 
 extern "C" void hgl_destroy(hgl_handle* h) {
   if (!h) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   free_handle(h);
 }
 

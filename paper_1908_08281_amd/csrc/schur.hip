@@ -380,8 +380,8 @@ void schur_delete(void* p) {
   S->arena.release();
   S->meta.release();
   S->pmeta.release();
-  if (S->graph) hipGraphExecDestroy(S->graph);
-  if (S->cap) hipStreamDestroy(S->cap);
+  if (S->graph) (void)hipGraphExecDestroy(S->graph);
+  if (S->cap) (void)hipStreamDestroy(S->cap);
   delete S;
 }
 
@@ -672,12 +672,12 @@ int schur_run(hgl_handle* h, Schur& S, double lambda, hipStream_t s) {
     const int rc = schur_launches(h, S, lambda, S.cap);
     const hipError_t e = hipStreamEndCapture(S.cap, &g);
     if (rc != HGL_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return rc;
     }
     HGL_HIP(e);
     const hipError_t e2 = hipGraphInstantiate(&S.graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     HGL_HIP(e2);
     S.graph_key = key;
   }
