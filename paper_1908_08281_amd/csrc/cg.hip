@@ -905,12 +905,12 @@ static int run_cg(hgl_handle* h, const double* lambdas, const hgl_cg_opts* o, co
       const hipError_t e = hipStreamEndCapture(s, &graph);
       s = s_user;
       if (rc != HGL_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
+        if (graph) hipGraphDestroy(graph);
         return rc;
       }
       HGL_HIP(e);
       const hipError_t e2 = hipGraphInstantiate(&h->cg_graph, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
+      hipGraphDestroy(graph);
       HGL_HIP(e2);
       h->cg_graph_key = key;
     }

@@ -303,7 +303,7 @@ inline void launch(const hgl_handle* hc, int kind, F kernel, dim3 grid, dim3 blo
     auto formal = validateArgsCountType(kernel, actual);
     void* kargs[sizeof...(Args) > 0 ? sizeof...(Args) : 1];
     pArgs<0>(formal, kargs);
-    (void)hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, kargs, shm, s);  // errors: hipGetLastError
+    hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, kargs, shm, s);
   }
 }
 

@@ -518,7 +518,7 @@ GatherShapes tune_shapes(hgl_handle* h, int k, const ColShape& base, const T* X,
   for (auto& e : ev)
     if (hipEventCreate(&e) != hipSuccess) {
       for (auto& e2 : ev)
-        if (e2) (void)hipEventDestroy(e2);
+        if (e2) hipEventDestroy(e2);
       return best;
     }
   float best_e = 1e30f, best_v = 1e30f, base_e = -1.f, base_v = -1.f;
@@ -532,12 +532,12 @@ GatherShapes tune_shapes(hgl_handle* h, int k, const ColShape& base, const T* X,
                                       cs, Gate{}, s, u) == HGL_OK;
     };
     if (!edge() || !vertex()) continue;  // warm-up (and shape check)
-    (void)hipEventRecord(ev[0], s);
+    hipEventRecord(ev[0], s);
     bool ok = true;
     for (int rep = 0; rep < 3 && ok; ++rep) ok = edge();
-    (void)hipEventRecord(ev[1], s);
+    hipEventRecord(ev[1], s);
     for (int rep = 0; rep < 3 && ok; ++rep) ok = vertex();
-    (void)hipEventRecord(ev[2], s);
+    hipEventRecord(ev[2], s);
     float me = 0.f, mv = 0.f;
     if (!ok || hipEventSynchronize(ev[2]) != hipSuccess || hipEventElapsedTime(&me, ev[0], ev[1]) != hipSuccess ||
         hipEventElapsedTime(&mv, ev[1], ev[2]) != hipSuccess)
@@ -555,7 +555,7 @@ GatherShapes tune_shapes(hgl_handle* h, int k, const ColShape& base, const T* X,
       best.vertex = cs;
     }
   }
-  for (auto& e : ev) (void)hipEventDestroy(e);
+  for (auto& e : ev) hipEventDestroy(e);
   clear_error();
   // keep the default unless another shape is clearly faster (timing noise
   // must not flip the choice from one process to the next)
