@@ -59,18 +59,20 @@ def _tess_problem(n_blocks=6, lo=150, hi=300):
     return synth.tessellated(n_blocks=n_blocks, lo=lo, hi=hi, k_rhs=12)
 
 
-@pytest.mark.parametrize("k,pp", [(24, 8), (1, 1), (2, 1), (3, 2), (80, 16)])
-def test_bf16_sigma_and_approximation_match_oracle(k, pp):
+@pytest.mark.parametrize("k,pp,n_blocks", [(24, 8, 6), (1, 1, 6), (2, 1, 6), (3, 2, 6), (80, 16, 6), (24, 8, 1),
+                                            (24, 8, 3)])
+def test_bf16_sigma_and_approximation_match_oracle(k, pp, n_blocks):
     """Same Omega: top-k sigma and the approximation error agree with the
     oracle's Algorithm 1 run on the BF16-rounded blocks (kernel correctness);
     the error against the FP64 blocks is reported as the true error.  Sketch
     widths l = k + p from 2 (no Householder step) and 3 (one) to 96, the
-    widest supported."""
+    widest supported; one block (a single group of blocks) and three (groups
+    of one and two)."""
     dev = device()
-    p = _tess_problem()
+    p = _tess_problem(n_blocks=n_blocks)
     q = 2
     bits, vals = _omega(p, k + pp, 9)
-    say(f"rsvd bf16 vs oracle k={k} p={pp}")
+    say(f"rsvd bf16 vs oracle k={k} p={pp} blocks={n_blocks}")
     h = build(p, dev)
     U, sig = hgl().block_rsvd(h, p.blocks, k, pp, q, sketch="bf16", omega=_to_dev_bits(bits, dev))
     U, sig = U.cpu().double().numpy(), sig.cpu().numpy()
